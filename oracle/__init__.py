@@ -1,0 +1,288 @@
+"""CPU FP64 oracle of the differentiable tile rasterizer.
+
+TEST INFRASTRUCTURE ONLY: the test-suite, the smoke check and the benchmark's
+CPU-baseline leg are the only callers.  It shares no code with the GPU
+library, and the GPU library never calls it.
+
+This module marshals numpy arrays into ``liboracle.so`` (plain C, FP64; see
+``gsoracle.c`` for the passages of the paper each function follows).  All
+parameters are widened exactly from FP32 to FP64 before the call.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+from . import build as _build
+
+_LIB = None
+
+# Thresholds the rasterizer uses, as FP32 values widened to FP64.
+ALPHA_MIN = float(np.float32(1.0) / np.float32(255.0))
+T_MIN = float(np.float32(1e-4))
+ALPHA_MAX = float(np.float32(0.99))
+REC_FIELDS = ("px", "py", "A", "B", "C", "opacity", "depth", "radius")
+
+_d = C.POINTER(C.c_double)
+_i32 = C.POINTER(C.c_int32)
+_u32 = C.POINTER(C.c_uint32)
+_u64 = C.POINTER(C.c_uint64)
+_u8 = C.POINTER(C.c_uint8)
+_i64 = C.POINTER(C.c_int64)
+
+
+def lib():
+    global _LIB
+    if _LIB is None:
+        if not os.path.exists(_build.LIB) or (
+                os.path.getmtime(_build.LIB) < os.path.getmtime(_build.SRC)):
+            _build.build()
+        L = C.CDLL(os.environ.get("ORACLE_LIB_OVERRIDE", _build.LIB))
+        L.or_project.restype = C.c_int
+        L.or_project.argtypes = [C.c_int, _d, _d, _d, _d, _d, C.c_int, C.c_int,
+                                 _d, _d, _i32, _i32, C.c_int]
+        L.or_bin_sort.restype = C.c_int64
+        L.or_bin_sort.argtypes = [C.c_int, C.c_int, _i32, _i32, _d, C.c_int,
+                                  C.c_int, C.c_int, _u64, _u32, _u64, _u32,
+                                  C.c_int64, _u32]
+        L.or_forward.restype = C.c_int
+        L.or_forward.argtypes = [C.c_int, C.c_int, C.c_int, C.c_int, C.c_int,
+                                 _d, _i32, _d, _u32, _u32, _d, C.c_double,
+                                 C.c_double, C.c_double, _d, _d, _i32, _u8, _d,
+                                 _i64, _u8, C.c_int, C.c_int, C.c_int]
+        L.or_backward.restype = C.c_int
+        L.or_backward.argtypes = [C.c_int, C.c_int, C.c_int, C.c_int, C.c_int,
+                                  _d, _i32, _d, _u32, _u32, _d, C.c_double,
+                                  C.c_double, C.c_double, _d, _u8, C.c_int,
+                                  C.c_int, _d, _d, _d, C.c_int]
+        L.or_project_bwd.restype = C.c_int
+        L.or_project_bwd.argtypes = [C.c_int, C.c_int, _d, _d, _d, _d, _d, _d,
+                                     _d, _d, _d, _d, _d, _d, _d, C.c_int]
+        L.or_l1.restype = C.c_double
+        L.or_l1.argtypes = [C.c_int, C.c_int, C.c_int, _d, _d, C.c_double, _d]
+        L.or_planar_reg.restype = C.c_double
+        L.or_planar_reg.argtypes = [C.c_int, _d, C.c_double, C.c_double, _d]
+        L.or_adam.restype = None
+        L.or_adam.argtypes = [C.c_int64, _d, _d, _d, _d, C.c_double,
+                              C.c_double, C.c_double, C.c_double, C.c_int]
+        L.or_insert.restype = C.c_int
+        L.or_insert.argtypes = [_d, _d, _d, _d, C.c_int, C.c_double, C.c_int,
+                                C.c_int, _d, _d, _d, _d, _d, _i32]
+        _LIB = L
+    return _LIB
+
+
+def _p(a, t):
+    return a.ctypes.data_as(t) if a is not None else None
+
+
+def _f64(a):
+    return np.ascontiguousarray(np.asarray(a, dtype=np.float32), dtype=np.float64)
+
+
+def cam_array(cam) -> np.ndarray:
+    """Camera as 19 doubles (R[9], t[3], fx, fy, cx, cy, near, W, H); every
+    real value is the FP32 value the GPU sees, widened exactly."""
+    f = lambda x: float(np.float32(x))
+    return np.array(list(np.asarray(cam.R, np.float32).astype(np.float64).ravel())
+                    + list(np.asarray(cam.t, np.float32).astype(np.float64))
+                    + [f(cam.fx), f(cam.fy), f(cam.cx), f(cam.cy), f(cam.near),
+                       float(cam.width), float(cam.height)], dtype=np.float64)
+
+
+def params64(g):
+    """FP64 copies of a Gaussians set's planar arrays."""
+    return dict(mean=_f64(g.mean), log_scale=_f64(g.log_scale),
+                quat=_f64(g.quat), opacity_logit=_f64(g.opacity_logit),
+                rgb=_f64(g.rgb))
+
+
+def project(p, cams, tile=16, publish=True, nthreads=1):
+    """Projects every Gaussian into every camera (Eq. 1-2).
+
+    ``p`` is a dict from :func:`params64` (or any dict of FP64 planar arrays).
+    Returns rec [V][n][8], cov [V][n][3], box [V][n][4] int32, tiles [V][n].
+    """
+    L = lib()
+    n = p["mean"].shape[1]
+    V = len(cams)
+    rec = np.zeros((V, n, 8))
+    cov = np.zeros((V, n, 3))
+    box = np.zeros((V, n, 4), np.int32)
+    tiles = np.zeros((V, n), np.int32)
+    for k, cam in enumerate(cams):
+        ca = cam_array(cam)
+        L.or_project(n, _p(p["mean"], _d), _p(p["log_scale"], _d),
+                     _p(p["quat"], _d), _p(p["opacity_logit"], _d), _p(ca, _d),
+                     tile, 1 if publish else 0, _p(rec[k], _d), _p(cov[k], _d),
+                     _p(box[k], _i32), _p(tiles[k], _i32), nthreads)
+    return dict(rec=rec, cov=cov, box=box, tiles=tiles)
+
+
+def bin_sort(proj, tile, W, H, cap=None, emit=True):
+    """Duplicated (tile, depth) keys, stable sort and tile ranges."""
+    L = lib()
+    V, n = proj["tiles"].shape
+    total = int(proj["tiles"].astype(np.int64).sum())
+    cap = total if cap is None else cap
+    Tx, Ty = (W + tile - 1) // tile, (H + tile - 1) // tile
+    keys_emit = np.zeros(max(total, 1), np.uint64) if emit else None
+    vals_emit = np.zeros(max(total, 1), np.uint32) if emit else None
+    keys = np.zeros(max(total, 1), np.uint64)
+    vals = np.zeros(max(total, 1), np.uint32)
+    ranges = np.zeros((V * Tx * Ty, 2), np.uint32)
+    nk = L.or_bin_sort(V, n, _p(proj["box"], _i32), _p(proj["tiles"], _i32),
+                       _p(proj["rec"], _d), tile, W, H, _p(keys_emit, _u64),
+                       _p(vals_emit, _u32), _p(keys, _u64), _p(vals, _u32),
+                       cap, _p(ranges, _u32))
+    if nk < 0:
+        raise OverflowError("key capacity exceeded")
+    out = dict(keys=keys[:nk], vals=vals[:nk], ranges=ranges, n_keys=int(nk),
+               Tx=Tx, Ty=Ty, tile=tile)
+    if emit:
+        out["keys_emit"] = keys_emit[:nk]
+        out["vals_emit"] = vals_emit[:nk]
+    return out
+
+
+def forward(proj, bins, rgb, W, H, bg=(0.0, 0.0, 0.0), alpha_min=ALPHA_MIN,
+            T_min=T_MIN, alpha_max=ALPHA_MAX, dec=None, dec_mode=0,
+            nthreads=1):
+    """Front-to-back compositing (Eq. 3) over each tile's sorted list."""
+    L = lib()
+    V, n = proj["tiles"].shape
+    img = np.zeros((V, 3, H, W))
+    T = np.zeros((V, H, W))
+    nlast = np.zeros((V, H, W), np.int32)
+    flags = np.zeros((V, H, W), np.uint8)
+    errb = np.zeros((V, H, W))
+    cnt = np.zeros(3, np.int64)
+    bgv = np.asarray(bg, np.float64)
+    Ld = 0 if dec is None else dec.shape[-1]
+    rgb = np.ascontiguousarray(rgb, np.float64)
+    vals = bins["vals"] if bins["n_keys"] else np.zeros(1, np.uint32)
+    rc = L.or_forward(V, W, H, bins["tile"], n, _p(proj["rec"], _d),
+                      _p(proj["box"], _i32), _p(rgb, _d), _p(vals, _u32),
+                      _p(bins["ranges"], _u32), _p(bgv, _d), alpha_min, T_min,
+                      alpha_max, _p(img, _d), _p(T, _d), _p(nlast, _i32),
+                      _p(flags, _u8), _p(errb, _d), _p(cnt, _i64),
+                      _p(dec, _u8), Ld, dec_mode, nthreads)
+    if rc != 0:
+        raise ValueError("decision buffer too short")
+    return dict(img=img, T=T, nlast=nlast, flags=flags, errb=errb,
+                counters=dict(examined=int(cnt[0]), inbox=int(cnt[1]),
+                              contributing=int(cnt[2])))
+
+
+def decision_buffer(bins, V, W, H):
+    r = bins["ranges"].astype(np.int64)
+    L = max(1, int((r[:, 1] - r[:, 0]).max()))
+    return np.zeros((V, H, W, L), np.uint8)
+
+
+def backward(proj, bins, rgb, W, H, dimg, bg=(0.0, 0.0, 0.0),
+             alpha_min=ALPHA_MIN, T_min=T_MIN, alpha_max=ALPHA_MAX, dec=None,
+             dec_mode=0, nthreads=1):
+    """Exact derivative of the compositing with the decision set fixed.
+    Returns g2d [V][n][5] (px, py, A, B, C), gop [n], grgb [3][n]."""
+    L = lib()
+    V, n = proj["tiles"].shape
+    g2d = np.zeros((V, n, 5))
+    gop = np.zeros(n)
+    grgb = np.zeros((3, n))
+    bgv = np.asarray(bg, np.float64)
+    dimg = np.ascontiguousarray(dimg, np.float64)
+    rgb = np.ascontiguousarray(rgb, np.float64)
+    Ld = 0 if dec is None else dec.shape[-1]
+    vals = bins["vals"] if bins["n_keys"] else np.zeros(1, np.uint32)
+    rc = L.or_backward(V, W, H, bins["tile"], n, _p(proj["rec"], _d),
+                       _p(proj["box"], _i32), _p(rgb, _d), _p(vals, _u32),
+                       _p(bins["ranges"], _u32), _p(bgv, _d), alpha_min, T_min,
+                       alpha_max, _p(dimg, _d), _p(dec, _u8), Ld, dec_mode,
+                       _p(g2d, _d), _p(gop, _d), _p(grgb, _d), nthreads)
+    if rc != 0:
+        raise ValueError("decision buffer too short")
+    return dict(g2d=g2d, gop=gop, grgb=grgb)
+
+
+def project_bwd(p, cams, bwd, nthreads=1):
+    """Chain rule from the screen-space gradients to the 14 parameter rows."""
+    L = lib()
+    n = p["mean"].shape[1]
+    camd = np.stack([cam_array(c) for c in cams])
+    out = dict(mean=np.zeros((3, n)), log_scale=np.zeros((3, n)),
+               quat=np.zeros((4, n)), opacity_logit=np.zeros(n),
+               rgb=np.zeros((3, n)))
+    L.or_project_bwd(len(cams), n, _p(p["mean"], _d), _p(p["log_scale"], _d),
+                     _p(p["quat"], _d), _p(p["opacity_logit"], _d),
+                     _p(camd, _d), _p(bwd["g2d"], _d), _p(bwd["gop"], _d),
+                     _p(bwd["grgb"], _d), _p(out["mean"], _d),
+                     _p(out["log_scale"], _d), _p(out["quat"], _d),
+                     _p(out["opacity_logit"], _d), _p(out["rgb"], _d), nthreads)
+    return out
+
+
+def l1(img, target, lam=1.0):
+    """Sum over views of lam * mean |img - target| and its gradient."""
+    L = lib()
+    img = np.ascontiguousarray(img, np.float64)
+    tgt = _f64(target)
+    V, _, H, W = img.shape
+    dimg = np.zeros_like(img)
+    loss = L.or_l1(V, H, W, _p(img, _d), _p(tgt, _d), lam, _p(dimg, _d))
+    return loss, dimg
+
+
+def planar_reg(log_scale, lam=1.0, floor=0.01):
+    """lam * mean_g max(floor, min_j exp(l_gj)) and its gradient."""
+    L = lib()
+    ls = np.ascontiguousarray(log_scale, np.float64)
+    g = np.zeros_like(ls)
+    v = L.or_planar_reg(ls.shape[1], _p(ls, _d), lam, floor, _p(g, _d))
+    return v, g
+
+
+def adam(p, g, m, v, lr, step, b1=0.9, b2=0.999, eps=1e-15):
+    L = lib()
+    p = np.ascontiguousarray(p, np.float64).copy()
+    m = np.ascontiguousarray(m, np.float64).copy()
+    v = np.ascontiguousarray(v, np.float64).copy()
+    g = np.ascontiguousarray(g, np.float64)
+    L.or_adam(p.size, _p(p, _d), _p(g, _d), _p(m, _d), _p(v, _d), lr, b1, b2,
+              eps, step)
+    return p, m, v
+
+
+def insert(cam, kf_rgb, kf_T, pts_uvd, alpha_skip=0.9, centre_only=False,
+           cap=None):
+    """Back-projected, masked insertion of patch pixels (Eq. 6)."""
+    L = lib()
+    K = pts_uvd.shape[0]
+    cap = 9 * K if cap is None else cap
+    ca = cam_array(cam)
+    rgb = _f64(kf_rgb)
+    T = np.ascontiguousarray(kf_T, np.float64)
+    pts = _f64(pts_uvd)
+    out = dict(mean=np.zeros((3, cap)), log_scale=np.zeros((3, cap)),
+               quat=np.zeros((4, cap)), opacity_logit=np.zeros(cap),
+               rgb=np.zeros((3, cap)))
+    src = np.zeros(cap, np.int32)
+    cnt = L.or_insert(_p(ca, _d), _p(rgb, _d), _p(T, _d), _p(pts, _d), K,
+                      alpha_skip, 1 if centre_only else 0, cap,
+                      _p(out["mean"], _d), _p(out["log_scale"], _d),
+                      _p(out["quat"], _d), _p(out["opacity_logit"], _d),
+                      _p(out["rgb"], _d), _p(src, _i32))
+    m = min(cnt, cap)
+    return dict(count=int(cnt), src=src[:m],
+                **{k: v[..., :m] for k, v in out.items()})
+
+
+def render(p, cams, tile=16, bg=(0.0, 0.0, 0.0), publish=True, nthreads=1):
+    """Projection, binning and forward compositing in one call."""
+    W, H = cams[0].width, cams[0].height
+    proj = project(p, cams, tile, publish, nthreads)
+    bins = bin_sort(proj, tile, W, H, emit=False)
+    fwd = forward(proj, bins, p["rgb"], W, H, bg, nthreads=nthreads)
+    return proj, bins, fwd

@@ -1,0 +1,57 @@
+"""Brute-force per-pixel compositing in NumPy (test infrastructure only).
+
+For every pixel it gathers every Gaussian whose integer pixel box contains the
+pixel, orders them by (FP32 depth, index) with ``numpy.lexsort`` and blends
+front to back with the rule of Eq. 3 plus the cut-offs.  It uses no tiles, no
+keys and no ranges, so it checks the oracle's binning, sort and tile walk
+independently.  Only for tiny scenes: pure Python loops over pixels.
+"""
+from __future__ import annotations
+
+import math
+
+import numpy as np
+
+
+def composite(rec, box, rgb, W, H, bg=(0.0, 0.0, 0.0), alpha_min=None,
+              T_min=None, alpha_max=None):
+    from . import ALPHA_MAX, ALPHA_MIN, T_MIN
+    alpha_min = ALPHA_MIN if alpha_min is None else alpha_min
+    T_min = T_MIN if T_min is None else T_min
+    alpha_max = ALPHA_MAX if alpha_max is None else alpha_max
+    V, n, _ = rec.shape
+    img = np.zeros((V, 3, H, W))
+    Tf = np.ones((V, H, W))
+    ncontrib = np.zeros((V, H, W), np.int64)
+    for k in range(V):
+        depth_bits = rec[k, :, 6].astype(np.float32).view(np.uint32)
+        for v in range(H):
+            for u in range(W):
+                inb = ((box[k, :, 0] <= u) & (u <= box[k, :, 1]) &
+                       (box[k, :, 2] <= v) & (v <= box[k, :, 3]))
+                cand = np.nonzero(inb)[0]
+                order = cand[np.lexsort((cand, depth_bits[cand]))]
+                T = 1.0
+                C = [0.0, 0.0, 0.0]
+                cnt = 0
+                for g in order:
+                    px, py, A, B, Cc, o = rec[k, g, :6]
+                    dx, dy = px - u, py - v
+                    pw = -0.5 * (A * dx * dx + Cc * dy * dy) - B * dx * dy
+                    if pw > 0:
+                        continue
+                    a = min(alpha_max, o * math.exp(pw))
+                    if a < alpha_min:
+                        continue
+                    Tn = T * (1.0 - a)
+                    if Tn < T_min:
+                        break
+                    for ch in range(3):
+                        C[ch] += rgb[ch, g] * a * T
+                    T = Tn
+                    cnt += 1
+                for ch in range(3):
+                    img[k, ch, v, u] = C[ch] + T * bg[ch]
+                Tf[k, v, u] = T
+                ncontrib[k, v, u] = cnt
+    return img, Tf, ncontrib

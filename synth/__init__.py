@@ -1,0 +1,10 @@
+"""Seeded synthetic workloads (random numbers and array layout only)."""
+from .scenes import (Camera, Gaussians, KeyframePoints, Workload, config0,
+                     config1, config2, config3_crop, frustum_gaussians,
+                     identity_camera, insertion_stream, random_walk_poses,
+                     room_camera, room_gaussians, tiny_scene, uniform_targets)
+
+__all__ = ["Camera", "Gaussians", "KeyframePoints", "Workload", "config0",
+           "config1", "config2", "config3_crop", "frustum_gaussians",
+           "identity_camera", "insertion_stream", "random_walk_poses",
+           "room_camera", "room_gaussians", "tiny_scene", "uniform_targets"]

