@@ -1,0 +1,270 @@
+/*
+ * gsmap: differentiable tile-based 3D Gaussian splatting rasterizer for
+ * MI355X (gfx950), the data-parallel hot path of a Gaussian-splatting
+ * mapping back end (MonoGS++, arXiv 2504.02437, Methodology: Scene
+ * Representation and Map Optimization).
+ *
+ * C ABI.  Every pointer documented as "device" is a HIP device pointer the
+ * caller owns; the library allocates no device memory.  Every call that takes
+ * a stream only enqueues work on it (no host synchronisation) unless stated,
+ * so a sequence of calls can be captured into a HIP graph.  Streams are
+ * passed as void* (a hipStream_t; NULL is the null stream).
+ *
+ * Return codes: GS_OK, or
+ *   GS_E_INVALID   a host-side argument check failed; nothing was launched;
+ *   GS_E_CAPACITY  a host-known size is too small; nothing was launched;
+ *   GS_E_OVERFLOW  (gs_read_status only) a device-side capacity was exceeded;
+ *   GS_E_HIP       a HIP runtime call failed; gs_last_error() has the text.
+ * No call aborts or throws across the ABI.
+ *
+ * Conventions (shared with the rest of the method): pinhole camera with
+ * OpenCV axes (x right, y down, z forward); a world point X maps to camera
+ * space as R X + t; pixel (u, v) is sampled at integer coordinates;
+ * quaternions are (w, x, y, z) and normalised inside the projection; scale is
+ * exp(log_scale); opacity is sigmoid(opacity_logit); colour is raw RGB.
+ */
+#ifndef GSMAP_H
+#define GSMAP_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define GS_API __attribute__((visibility("default")))
+
+#define GS_OK 0
+#define GS_E_INVALID 1
+#define GS_E_CAPACITY 2
+#define GS_E_OVERFLOW 3
+#define GS_E_HIP 4
+
+/* Device status word bits (gs_read_status). */
+#define GS_STATUS_KEY_OVERFLOW 1      /* more (view, Gaussian, tile) keys than key_capacity */
+#define GS_STATUS_GAUSSIAN_OVERFLOW 2 /* insertion wanted more than capacity */
+
+/* gs_settings.flags bits. */
+#define GS_FLAG_EMIT_KEYS 1 /* sort_tile_keys also writes the sorted 64-bit keys */
+
+/* Gaussian parameters (Eq. 1: mean, rotation quaternion, scale, opacity,
+ * colour), planar structure of arrays, FP32, all device pointers.  Each row
+ * holds `capacity` floats; entries [0, *n_dev) are live.
+ *   mean          [3][capacity]  x, y, z (world)
+ *   log_scale     [3][capacity]  log of the per-axis standard deviation
+ *   quat          [4][capacity]  w, x, y, z (any non-zero norm)
+ *   opacity_logit [capacity]
+ *   rgb           [3][capacity]
+ * n_dev is a device int32 holding the live count, so a captured graph stays
+ * valid while insertion grows the map.  The same struct describes gradient
+ * and optimiser-moment arrays of the same layout (their n_dev may be NULL). */
+typedef struct gs_params {
+  float* mean;
+  float* log_scale;
+  float* quat;
+  float* opacity_logit;
+  float* rgb;
+  int32_t* n_dev;
+  int32_t capacity;
+  int32_t pad_;
+} gs_params;
+
+/* One view: world-to-camera rotation R (row-major) and translation t,
+ * intrinsics in pixels, near-plane depth and image size.  80 bytes.  Arrays of
+ * cameras passed to the library live in device memory. */
+typedef struct gs_camera {
+  float R[9];
+  float t[3];
+  float fx, fy, cx, cy;
+  float near_z;
+  int32_t width, height;
+  int32_t pad_;
+} gs_camera;
+
+/* Rasterizer settings, passed by host pointer and copied at each call.
+ *   tile        screen tile edge in pixels: 8, 16 or 32
+ *   lds_batch   Gaussians staged in LDS per batch: 128, 256 or 512
+ *   bg          background colour added with weight T_final
+ *   alpha_min   entries with alpha below this are skipped (1/255)
+ *   T_min       a pixel stops before the entry that would take its
+ *               transmittance below this (1e-4)
+ *   alpha_max   alpha clamp (0.99)
+ *   flags       GS_FLAG_* bits */
+typedef struct gs_settings {
+  int32_t tile;
+  int32_t lds_batch;
+  float bg[3];
+  float alpha_min;
+  float T_min;
+  float alpha_max;
+  int32_t flags;
+  int32_t pad_;
+} gs_settings;
+
+/* Fixed sizes of one rasterization problem; all views share width, height
+ * and tile. */
+typedef struct gs_geometry {
+  int32_t n_views;
+  int32_t width;
+  int32_t height;
+  int32_t tile;
+  int32_t capacity;      /* Gaussian capacity (matches gs_params.capacity) */
+  int32_t pad_;
+  int64_t key_capacity;  /* max number of (view, Gaussian, tile) keys */
+} gs_geometry;
+
+/* Opaque host-side handle over a caller-provided device buffer. */
+typedef struct gs_workspace gs_workspace;
+
+/* Device pointers inside a workspace (for inspection and tests).
+ *   records        [n_views][capacity] 48-byte records, three float4:
+ *                  (px, py, A, B), (C, opacity, r, g),
+ *                  (b, depth, u_lo | u_hi << 16, v_lo | v_hi << 16)
+ *                  where (A, B, C) is the conic (inverse screen covariance)
+ *                  and the last two words are integer bit patterns
+ *   tiles_touched  [n_views][capacity] int32 (0 = culled)
+ *   ranges         [n_views * tiles_y * tiles_x][2] uint32 [start, end)
+ *   vals_sorted    [key_capacity] uint32 Gaussian index per sorted key
+ *   keys_sorted    [key_capacity] uint64 (tile << 32 | depth bits), written
+ *                  only with GS_FLAG_EMIT_KEYS
+ *   grad2d         [n_views][5][capacity] dL/d(px, py, A, B, C)
+ *   n_keys         device int64 key count of the last project_and_bin
+ *   status         device int32 GS_STATUS_* bits (sticky until cleared) */
+typedef struct gs_workspace_view {
+  void* records;
+  int32_t* tiles_touched;
+  uint32_t* ranges;
+  uint32_t* vals_sorted;
+  uint64_t* keys_sorted;
+  float* grad2d;
+  int64_t* n_keys;
+  int32_t* status;
+  int32_t tiles_x;
+  int32_t tiles_y;
+} gs_workspace_view;
+
+/* Host only.  Bytes of device memory a workspace for `geo` needs. */
+GS_API int gs_workspace_size(const gs_geometry* geo, size_t* bytes);
+
+/* Host only.  Creates a handle over `device_buffer` (at least
+ * gs_workspace_size bytes, 256-byte aligned, owned by the caller and kept
+ * alive while the handle is used).  The handle itself is host memory freed by
+ * gs_workspace_destroy.  Clears the status word on `stream`. */
+GS_API int gs_workspace_create(const gs_geometry* geo, void* device_buffer,
+                        size_t bytes, void* stream, gs_workspace** out);
+GS_API int gs_workspace_destroy(gs_workspace* ws);
+GS_API int gs_workspace_get_view(const gs_workspace* ws, gs_workspace_view* out);
+
+/* Projection and tile binning (Eq. 1-2).  For every view k and live
+ * Gaussian g: transform the mean to camera space, cull when not in front of
+ * the near plane or non-finite, form Sigma = R S S^T R^T, the EWA screen
+ * covariance J W Sigma W^T J^T plus a 0.3 px^2 dilation, its conic, a radius
+ * of ceil(3 sqrt(lambda_max)), the integer pixel box clipped to the image,
+ * and the number of screen tiles the box touches.  This front end runs in
+ * FP64 and publishes FP32 records.  Then counts the keys per tile, derives
+ * the ranges by an exclusive scan (n_keys stays on the device; more keys than
+ * key_capacity set GS_STATUS_KEY_OVERFLOW and no key is written past the
+ * capacity), and scatters every Gaussian index into each of its tiles'
+ * segments (order within a segment unspecified until sort_tile_keys).
+ *   cams  device gs_camera[n_views] */
+GS_API int gs_project_and_bin(gs_workspace* ws, const gs_params* params,
+                       const gs_camera* cams, const gs_settings* s,
+                       void* stream);
+
+/* Sorts every tile's segment by (depth, Gaussian index) ascending, so each
+ * tile's list is front to back with ties in index order; with
+ * GS_FLAG_EMIT_KEYS also writes keys_sorted.  The result equals a stable sort
+ * of the keys (tile << 32 | depth bits) emitted in (view, Gaussian, tile row,
+ * tile column) order. */
+GS_API int gs_sort_tile_keys(gs_workspace* ws, const gs_settings* s, void* stream);
+
+/* Forward render (Eq. 3): per pixel, front to back over its tile's list,
+ * evaluate only entries whose pixel box contains the pixel, alpha =
+ * min(alpha_max, opacity * exp(-1/2 d^T conic d)) with d = mean2D - pixel,
+ * skip alpha < alpha_min, stop before an entry that would take T below T_min,
+ * C += colour * alpha * T.  Outputs (device, caller-owned):
+ *   out_rgb   [n_views][3][H][W]  C + T_final * bg
+ *   out_T     [n_views][H][W]     final transmittance
+ *   out_nlast [n_views][H][W]     index in the tile list of the last
+ *                                 contributing entry plus one (0 if none) */
+GS_API int gs_render_fwd(gs_workspace* ws, const gs_params* params,
+                  const gs_settings* s, float* out_rgb, float* out_T,
+                  int32_t* out_nlast, void* stream);
+
+/* Backward of render + projection: given dL/d(out_rgb) [n_views][3][H][W]
+ * and the forward's out_T / out_nlast, walks each tile's list back to front
+ * recomputing the transmittance, and ACCUMULATES (+=) dL/d(parameters) into
+ * `grad` (same layout as gs_params; the caller zeroes it).  The chain through
+ * the projection runs in FP64.  Clamped alphas pass no gradient to opacity
+ * or shape.  cams as in gs_project_and_bin. */
+GS_API int gs_render_bwd(gs_workspace* ws, const gs_params* params,
+                  const gs_camera* cams, const gs_settings* s,
+                  const float* dL_drgb, const float* T_final,
+                  const int32_t* n_last, gs_params* grad, void* stream);
+
+/* Photometric term of the map-optimisation loss (Eq. 10-11, L1 part):
+ * per view lambda * mean over 3HW of |rgb - target|; writes dL/drgb =
+ * lambda * sign(rgb - target) / (3HW) (sign(0) = 0) and ADDS the loss summed
+ * over views to *loss_dev (device double) and the per-view squared error sum
+ * to sqerr_dev[n_views] (device double, may be NULL) for PSNR. */
+GS_API int gs_loss_l1(const float* rgb, const float* target, int32_t n_views,
+               int32_t height, int32_t width, float lambda, float* dL_drgb,
+               double* loss_dev, double* sqerr_dev, void* stream);
+
+/* Planar regulariser of Eq. 10-11: lambda * mean over live Gaussians of
+ * max(floor, min_j exp(log_scale_j)).  ADDS its gradient into
+ * grad->log_scale (smallest axis only, lowest index on ties, only where the
+ * smallest scale exceeds the floor) and the term to *loss_dev. */
+GS_API int gs_planar_reg(const gs_params* params, float lambda, float floor_,
+                  gs_params* grad, double* loss_dev, void* stream);
+
+/* Adam step (the optimiser is not fixed by the paper) over the live entries
+ * of the 14 parameter rows.  lr[5] = learning rates of mean, log_scale,
+ * quat, opacity_logit, rgb.  m and v are moment arrays of the params layout.
+ * step >= 1 is the bias-correction step count. */
+GS_API int gs_adam(gs_params* params, const gs_params* grad, gs_params* m,
+            gs_params* v, const float* lr, float beta1, float beta2,
+            float eps, int32_t step, void* stream);
+
+/* Keyframe insertion (Eq. 6 with an accumulated-alpha mask).  Candidates are
+ * the 3x3 pixel patch around each of the n_pts centres pts_uvd [n][3] =
+ * (u, v, inverse depth) (device), visited patch by patch, pixels row-major
+ * (or only the centre pixel when centre_only != 0).  A candidate inside the
+ * image is kept when 1 - kf_T_final(u, v) <= alpha_skip.  Kept candidates,
+ * in visiting order, are appended at the live count: mean = R^T(K^-1 [u v 1]^T
+ * / d - t), colour = kf_rgb [3][H][W] at the pixel, opacity logit 0, identity
+ * rotation and log-scale log(z / fx) on every axis, or - when mlp_out is not
+ * NULL - log-scale, opacity logit and colour from mlp_out [n_pts][7]
+ * (per patch).  Zeroes the Adam moments of the new entries (m, v may be
+ * NULL), updates *params->n_dev, and sets GS_STATUS_GAUSSIAN_OVERFLOW when
+ * capacity would be exceeded (nothing past capacity is written).  At most 9
+ * * n_pts <= 65536 candidates.  status_dev: a device int32 receiving the
+ * status bits (may be NULL).  n_inserted_dev: device int32 receiving the
+ * number kept before the capacity check (may be NULL).
+ *   cam  device gs_camera (the keyframe's) */
+GS_API int gs_insert_gaussians(gs_params* params, gs_params* adam_m, gs_params* adam_v,
+                        const gs_camera* cam, int32_t width, int32_t height,
+                        const float* kf_rgb, const float* kf_T_final,
+                        const float* pts_uvd, int32_t n_pts, float alpha_skip,
+                        int32_t centre_only, const float* mlp_out,
+                        int32_t* n_inserted_dev, int32_t* status_dev,
+                        void* stream);
+
+/* Synchronises `stream`, then reads the workspace's status bits and key
+ * count (either output may be NULL).  Returns GS_E_OVERFLOW when any status
+ * bit is set, GS_OK otherwise.  clear != 0 resets the status word. */
+GS_API int gs_read_status(gs_workspace* ws, void* stream, int32_t* flags,
+                   int64_t* n_keys, int32_t clear);
+
+/* Text of the last error on the calling host thread ("" if none). */
+GS_API const char* gs_last_error(void);
+
+/* Library version string. */
+GS_API const char* gs_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* GSMAP_H */

@@ -1,0 +1,94 @@
+// Internal declarations shared by the HIP translation units of libgsmap.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "../../include/gsmap.h"
+
+namespace gs {
+
+// One projected (view, Gaussian) record, 48 bytes = three float4:
+//   q0 = (px, py, A, B), q1 = (C, opacity, r, g),
+//   q2 = (b, depth, u_lo | u_hi << 16, v_lo | v_hi << 16)
+// (A, B, C) is the conic: the inverse of the dilated screen covariance.
+struct __align__(16) Record {
+  float4 q0, q1, q2;
+};
+
+// Workspace layout: every region is carved from the caller's device buffer.
+struct Layout {
+  size_t records, tiles_touched, diff, ranges, cursor, vals_unsorted,
+      vals_sorted, keys_sorted, sort_tmp, grad2d, gop, counters, total;
+};
+
+// Device-side counters block.
+struct Counters {
+  long long n_keys;
+  int status;
+  int pad;
+};
+
+}  // namespace gs
+
+struct gs_workspace {
+  gs_geometry geo;
+  int tiles_x, tiles_y;
+  char* base;
+  size_t bytes;
+  gs::Layout L;
+  gs::Record* records;
+  int32_t* tiles_touched;
+  int32_t* diff;         // [V][Ty + 1][Tx + 1] tile-coverage difference grid
+  uint32_t* ranges;      // [V * Ty * Tx][2]
+  uint32_t* cursor;      // [V * Ty * Tx] scatter cursors
+  uint32_t* vals_unsorted;
+  uint32_t* vals_sorted;
+  unsigned long long* keys_sorted;
+  unsigned long long* sort_tmp;
+  float* grad2d;         // [V][5][capacity]
+  float* gop;            // [capacity] dL/d opacity summed over views
+  gs::Counters* counters;
+};
+
+namespace gs {
+
+void set_error(const char* fmt, ...);
+int check_hip(hipError_t e, const char* what);
+int validate_settings(const gs_settings* s);
+int validate_params(const gs_params* p, const char* what);
+
+// Launchers implemented by the kernel translation units.  They return a
+// hipError_t from the launch (hipGetLastError).
+hipError_t launch_project(gs_workspace* ws, const gs_params* p,
+                          const gs_camera* cams, hipStream_t st);
+hipError_t launch_project_bwd(gs_workspace* ws, const gs_params* p,
+                              const gs_camera* cams, gs_params* grad,
+                              hipStream_t st);
+hipError_t launch_bin(gs_workspace* ws, const gs_params* p, hipStream_t st);
+hipError_t launch_sort(gs_workspace* ws, const gs_settings* s, hipStream_t st);
+hipError_t launch_render_fwd(gs_workspace* ws, const gs_settings* s,
+                             float* rgb, float* T, int32_t* nlast,
+                             hipStream_t st);
+hipError_t launch_render_bwd(gs_workspace* ws, const gs_settings* s,
+                             const float* dL, const float* T,
+                             const int32_t* nlast, float* grad_rgb,
+                             hipStream_t st);
+hipError_t launch_fill_u32(void* ptr, uint32_t value, size_t count,
+                           hipStream_t st);
+hipError_t launch_loss_l1(const float* rgb, const float* target, int V, int H,
+                          int W, float lambda, float* dL, double* loss,
+                          double* sqerr, hipStream_t st);
+hipError_t launch_planar_reg(const gs_params* p, float lambda, float floor_,
+                             gs_params* grad, double* loss, hipStream_t st);
+hipError_t launch_adam(gs_params* p, const gs_params* g, gs_params* m,
+                       gs_params* v, const float* lr, float b1, float b2,
+                       float eps, int step, hipStream_t st);
+hipError_t launch_insert(gs_params* p, gs_params* m, gs_params* v,
+                         const gs_camera* cam, int W, int H,
+                         const float* kf_rgb, const float* kf_T,
+                         const float* pts, int n_pts, float alpha_skip,
+                         int centre_only, const float* mlp_out,
+                         int32_t* n_inserted, int32_t* status, hipStream_t st);
+
+}  // namespace gs

@@ -1,0 +1,293 @@
+// Loss terms of the map optimisation (Eq. 10-11), the Adam step and keyframe
+// insertion (Eq. 6), plus a fill kernel used instead of memset so every call
+// stays safe to capture in a HIP graph.
+
+#include <math.h>
+
+#include "gs_internal.h"
+
+namespace gs {
+namespace {
+
+__global__ void k_fill_u32(uint32_t* p, uint32_t v, size_t n) {
+  for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n;
+       i += (size_t)gridDim.x * blockDim.x)
+    p[i] = v;
+}
+
+template <typename T>
+__device__ inline T block_sum(T x, T* sh) {
+  // 256 threads, wave64.
+  for (int off = 32; off > 0; off >>= 1) x += __shfl_down(x, off, 64);
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  if (lane == 0) sh[wv] = x;
+  __syncthreads();
+  T r = 0;
+  if (threadIdx.x == 0)
+    for (int i = 0; i < 4; ++i) r += sh[i];
+  __syncthreads();
+  return r;
+}
+
+// L1 photometric term: per view lambda * mean |rgb - target| over 3HW.
+__global__ __launch_bounds__(256) void k_loss_l1(const float* rgb,
+                                                 const float* tgt, size_t per,
+                                                 float scale, float* dL,
+                                                 double* loss, double* sqerr,
+                                                 double lam_inv) {
+  __shared__ double sh[4];
+  const int k = blockIdx.y;
+  const float* x = rgb + (size_t)k * per;
+  const float* y = tgt + (size_t)k * per;
+  float* d = dL + (size_t)k * per;
+  double sa = 0.0, sq = 0.0;
+  for (size_t i = blockIdx.x * 256 + threadIdx.x; i < per;
+       i += (size_t)gridDim.x * 256) {
+    const float r = x[i] - y[i];
+    d[i] = r > 0.f ? scale : (r < 0.f ? -scale : 0.f);
+    sa += fabs((double)x[i] - (double)y[i]);
+    sq += ((double)x[i] - (double)y[i]) * ((double)x[i] - (double)y[i]);
+  }
+  const double ta = block_sum(sa, sh);
+  const double tq = block_sum(sq, sh);
+  if (threadIdx.x == 0) {
+    atomicAdd(loss, ta * lam_inv);
+    if (sqerr) atomicAdd(&sqerr[k], tq);
+  }
+}
+
+// Planar regulariser: lambda * mean_g max(floor, min_j exp(l_gj)).
+__global__ __launch_bounds__(256) void k_planar_reg(const float* lsc,
+                                                    const int32_t* n_dev,
+                                                    int cap, float lam,
+                                                    double floor_, float* dlsc,
+                                                    double* loss) {
+  __shared__ double sh[4];
+  const int g = blockIdx.x * 256 + threadIdx.x;
+  const int n = min(*n_dev, cap);
+  double term = 0.0;
+  if (g < n) {
+    const float l0 = lsc[g], l1 = lsc[cap + g], l2 = lsc[2 * cap + g];
+    int jm = 0;
+    float lm = l0;
+    if (l1 < lm) { lm = l1; jm = 1; }
+    if (l2 < lm) { lm = l2; jm = 2; }
+    const double sm = exp((double)lm);
+    term = sm > floor_ ? sm : floor_;
+    if (sm > floor_) dlsc[jm * cap + g] += (float)((double)lam * sm / (double)n);
+  }
+  const double t = block_sum(term, sh);
+  if (threadIdx.x == 0 && n > 0) atomicAdd(loss, (double)lam * t / (double)n);
+}
+
+struct AdamArgs {
+  float* p[14];
+  const float* g[14];
+  float* m[14];
+  float* v[14];
+  float lr[14];
+  const int32_t* n_dev;
+  int cap;
+  float b1, b2, eps, c1, c2;
+};
+
+__global__ __launch_bounds__(256) void k_adam(AdamArgs a) {
+  const int g = blockIdx.x * 256 + threadIdx.x;
+  const int row = blockIdx.y;
+  const int n = min(*a.n_dev, a.cap);
+  if (g >= n) return;
+  const float gr = a.g[row][g];
+  const float m = a.b1 * a.m[row][g] + (1.f - a.b1) * gr;
+  const float v = a.b2 * a.v[row][g] + (1.f - a.b2) * gr * gr;
+  a.m[row][g] = m;
+  a.v[row][g] = v;
+  a.p[row][g] -= a.lr[row] * (m / a.c1) / (sqrtf(v / a.c2) + a.eps);
+}
+
+struct InsertArgs {
+  float* rows[14];   // mean 0-2, log_scale 3-5, quat 6-9, opacity 10, rgb 11-13
+  float* mrows[14];  // may be null
+  float* vrows[14];
+  int32_t* n_dev;
+  int cap;
+  const gs_camera* cam;
+  int W, H;
+  const float* kf_rgb;
+  const float* kf_T;
+  const float* pts;
+  int n_pts;
+  float alpha_skip;
+  int centre_only;
+  const float* mlp_out;
+  int32_t* n_inserted;
+  int32_t* status;
+};
+
+constexpr int kInsThreads = 1024;
+
+__global__ __launch_bounds__(kInsThreads) void k_insert(InsertArgs a) {
+  __shared__ int scan[kInsThreads];
+  const int tid = threadIdx.x;
+  const int n0 = min(*a.n_dev, a.cap);
+  const gs_camera cam = *a.cam;
+  const int per = a.centre_only ? 1 : 9;
+  const int total = a.n_pts * per;
+  int running = 0;
+  for (int base = 0; base < total; base += kInsThreads) {
+    const int c = base + tid;
+    int keep = 0, u = 0, v = 0, patch = 0;
+    if (c < total) {
+      patch = c / per;
+      const int pix = a.centre_only ? 4 : c - patch * per;
+      u = (int)a.pts[3 * patch] + pix % 3 - 1;
+      v = (int)a.pts[3 * patch + 1] + pix / 3 - 1;
+      const float d = a.pts[3 * patch + 2];
+      if (u >= 0 && u < a.W && v >= 0 && v < a.H && d > 0.f) {
+        const double accum = 1.0 - (double)a.kf_T[(size_t)v * a.W + u];
+        keep = accum <= (double)a.alpha_skip;
+      }
+    }
+    scan[tid] = keep;
+    __syncthreads();
+    for (int off = 1; off < kInsThreads; off <<= 1) {
+      const int x = tid >= off ? scan[tid - off] : 0;
+      __syncthreads();
+      scan[tid] += x;
+      __syncthreads();
+    }
+    const int incl = scan[tid];
+    const int count = scan[kInsThreads - 1];
+    if (keep) {
+      const int dst = n0 + running + incl - 1;
+      if (dst < a.cap) {
+        const double z = 1.0 / (double)a.pts[3 * patch + 2];
+        const double xc[3] = {((double)u - (double)cam.cx) / (double)cam.fx * z,
+                              ((double)v - (double)cam.cy) / (double)cam.fy * z,
+                              z};
+        for (int i = 0; i < 3; ++i) {
+          double sacc = 0.0;
+          for (int j = 0; j < 3; ++j)
+            sacc += (double)cam.R[3 * j + i] * (xc[j] - (double)cam.t[j]);
+          a.rows[i][dst] = (float)sacc;
+        }
+        if (a.mlp_out) {
+          const float* o = a.mlp_out + 7 * (size_t)patch;
+          for (int i = 0; i < 3; ++i) a.rows[3 + i][dst] = o[i];
+          a.rows[10][dst] = o[3];
+          for (int i = 0; i < 3; ++i) a.rows[11 + i][dst] = o[4 + i];
+        } else {
+          const float ls = (float)log(z / (double)cam.fx);
+          for (int i = 0; i < 3; ++i) a.rows[3 + i][dst] = ls;
+          a.rows[10][dst] = 0.f;
+          for (int i = 0; i < 3; ++i)
+            a.rows[11 + i][dst] =
+                a.kf_rgb[((size_t)i * a.H + v) * a.W + u];
+        }
+        a.rows[6][dst] = 1.f;
+        a.rows[7][dst] = 0.f;
+        a.rows[8][dst] = 0.f;
+        a.rows[9][dst] = 0.f;
+        for (int r = 0; r < 14; ++r) {
+          if (a.mrows[r]) a.mrows[r][dst] = 0.f;
+          if (a.vrows[r]) a.vrows[r][dst] = 0.f;
+        }
+      }
+    }
+    running += count;
+    __syncthreads();
+  }
+  if (tid == 0) {
+    if (a.n_inserted) *a.n_inserted = running;
+    const long long want = (long long)n0 + running;
+    *a.n_dev = (int)min(want, (long long)a.cap);
+    if (want > a.cap && a.status) atomicOr(a.status, GS_STATUS_GAUSSIAN_OVERFLOW);
+  }
+}
+
+void rows_of(const gs_params* p, float** rows) {
+  const int cap = p->capacity;
+  for (int i = 0; i < 3; ++i) rows[i] = p->mean ? p->mean + (size_t)i * cap : nullptr;
+  for (int i = 0; i < 3; ++i)
+    rows[3 + i] = p->log_scale ? p->log_scale + (size_t)i * cap : nullptr;
+  for (int i = 0; i < 4; ++i) rows[6 + i] = p->quat ? p->quat + (size_t)i * cap : nullptr;
+  rows[10] = p->opacity_logit;
+  for (int i = 0; i < 3; ++i) rows[11 + i] = p->rgb ? p->rgb + (size_t)i * cap : nullptr;
+}
+
+}  // namespace
+
+hipError_t launch_fill_u32(void* ptr, uint32_t value, size_t count,
+                           hipStream_t st) {
+  if (count == 0) return hipSuccess;
+  size_t blocks = (count + 255) / 256;
+  if (blocks > 8192) blocks = 8192;
+  hipLaunchKernelGGL(k_fill_u32, dim3((unsigned)blocks), dim3(256), 0, st,
+                     (uint32_t*)ptr, value, count);
+  return hipGetLastError();
+}
+
+hipError_t launch_loss_l1(const float* rgb, const float* target, int V, int H,
+                          int W, float lambda, float* dL, double* loss,
+                          double* sqerr, hipStream_t st) {
+  const size_t per = (size_t)3 * H * W;
+  const float scale = (float)((double)lambda / (double)per);
+  size_t bx = (per + 256 * 4 - 1) / (256 * 4);
+  if (bx > 2048) bx = 2048;
+  if (bx < 1) bx = 1;
+  hipLaunchKernelGGL(k_loss_l1, dim3((unsigned)bx, V), dim3(256), 0, st, rgb,
+                     target, per, scale, dL, loss, sqerr,
+                     (double)lambda / (double)per);
+  return hipGetLastError();
+}
+
+hipError_t launch_planar_reg(const gs_params* p, float lambda, float floor_,
+                             gs_params* grad, double* loss, hipStream_t st) {
+  const int blocks = (p->capacity + 255) / 256;
+  if (blocks <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_planar_reg, dim3(blocks), dim3(256), 0, st,
+                     p->log_scale, p->n_dev, p->capacity, lambda,
+                     (double)floor_, grad->log_scale, loss);
+  return hipGetLastError();
+}
+
+hipError_t launch_adam(gs_params* p, const gs_params* g, gs_params* m,
+                       gs_params* v, const float* lr, float b1, float b2,
+                       float eps, int step, hipStream_t st) {
+  AdamArgs a;
+  float* tmp[14];
+  rows_of(p, a.p);
+  rows_of(g, tmp);
+  for (int i = 0; i < 14; ++i) a.g[i] = tmp[i];
+  rows_of(m, a.m);
+  rows_of(v, a.v);
+  const int grp[14] = {0, 0, 0, 1, 1, 1, 2, 2, 2, 2, 3, 4, 4, 4};
+  for (int i = 0; i < 14; ++i) a.lr[i] = lr[grp[i]];
+  a.n_dev = p->n_dev; a.cap = p->capacity;
+  a.b1 = b1; a.b2 = b2; a.eps = eps;
+  a.c1 = (float)(1.0 - pow((double)b1, step));
+  a.c2 = (float)(1.0 - pow((double)b2, step));
+  const int blocks = (p->capacity + 255) / 256;
+  if (blocks <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_adam, dim3(blocks, 14), dim3(256), 0, st, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_insert(gs_params* p, gs_params* m, gs_params* v,
+                         const gs_camera* cam, int W, int H,
+                         const float* kf_rgb, const float* kf_T,
+                         const float* pts, int n_pts, float alpha_skip,
+                         int centre_only, const float* mlp_out,
+                         int32_t* n_inserted, int32_t* status, hipStream_t st) {
+  InsertArgs a;
+  rows_of(p, a.rows);
+  if (m) rows_of(m, a.mrows); else for (int i = 0; i < 14; ++i) a.mrows[i] = nullptr;
+  if (v) rows_of(v, a.vrows); else for (int i = 0; i < 14; ++i) a.vrows[i] = nullptr;
+  a.n_dev = p->n_dev; a.cap = p->capacity; a.cam = cam; a.W = W; a.H = H;
+  a.kf_rgb = kf_rgb; a.kf_T = kf_T; a.pts = pts; a.n_pts = n_pts;
+  a.alpha_skip = alpha_skip; a.centre_only = centre_only; a.mlp_out = mlp_out;
+  a.n_inserted = n_inserted; a.status = status;
+  hipLaunchKernelGGL(k_insert, dim3(1), dim3(kInsThreads), 0, st, a);
+  return hipGetLastError();
+}
+
+}  // namespace gs

@@ -1,0 +1,370 @@
+// Projection front end (Eq. 1-2) and its backward, in FP64 on the GPU.
+//
+// This translation unit is compiled with -ffp-contract=off: every FP64
+// operation below is one IEEE-754 rounding in the order written, so the
+// published FP32 record and the integer pixel box are reproducible bit for
+// bit by any FP64 implementation that follows the same order.
+//
+// Layout: one thread per Gaussian, looping over the views, so the 56 bytes of
+// parameters are read from HBM once per call (coalesced planar rows) and the
+// view-independent part (scale, rotation, 3D covariance) is formed once.
+
+#include <math.h>
+
+#include "gs_internal.h"
+
+namespace gs {
+namespace {
+
+struct ProjArgs {
+  const float* mean;
+  const float* lsc;
+  const float* quat;
+  const float* opl;
+  const float* rgb;
+  const int32_t* n_dev;
+  int cap;
+  const gs_camera* cams;
+  int V, W, H, tile, Tx, Ty;
+  Record* rec;
+  int32_t* tiles;
+  int32_t* diff;
+};
+
+// View-independent part of Eq. 1: s = exp(l), R(q / |q|), M = R diag(s),
+// Sigma = M M^T.
+struct Shape {
+  double s[3];
+  double qn[4];
+  double qnorm;
+  double R[9];
+  double M[9];
+  double Sig[9];
+  bool ok;
+};
+
+__device__ inline void make_shape(const float* lsc, const float* quat, int cap,
+                                  int g, Shape& S) {
+  for (int j = 0; j < 3; ++j) S.s[j] = exp((double)lsc[j * cap + g]);
+  double q[4];
+  for (int j = 0; j < 4; ++j) q[j] = (double)quat[j * cap + g];
+  const double qq = ((q[0] * q[0] + q[1] * q[1]) + q[2] * q[2]) + q[3] * q[3];
+  S.qnorm = sqrt(qq);
+  S.ok = S.qnorm > 0.0 && isfinite(S.qnorm) && isfinite(S.s[0]) &&
+         isfinite(S.s[1]) && isfinite(S.s[2]);
+  for (int j = 0; j < 4; ++j) S.qn[j] = q[j] / S.qnorm;
+  const double w = S.qn[0], x = S.qn[1], y = S.qn[2], z = S.qn[3];
+  double* R = S.R;
+  R[0] = 1.0 - 2.0 * (y * y + z * z);
+  R[1] = 2.0 * (x * y - w * z);
+  R[2] = 2.0 * (x * z + w * y);
+  R[3] = 2.0 * (x * y + w * z);
+  R[4] = 1.0 - 2.0 * (x * x + z * z);
+  R[5] = 2.0 * (y * z - w * x);
+  R[6] = 2.0 * (x * z - w * y);
+  R[7] = 2.0 * (y * z + w * x);
+  R[8] = 1.0 - 2.0 * (x * x + y * y);
+  for (int i = 0; i < 3; ++i)
+    for (int j = 0; j < 3; ++j) S.M[3 * i + j] = R[3 * i + j] * S.s[j];
+  for (int i = 0; i < 3; ++i)
+    for (int j = 0; j < 3; ++j)
+      S.Sig[3 * i + j] = (S.M[3 * i] * S.M[3 * j] + S.M[3 * i + 1] * S.M[3 * j + 1]) +
+                         S.M[3 * i + 2] * S.M[3 * j + 2];
+}
+
+// View-dependent part of Eq. 2 for one camera.
+struct View {
+  double W[9];
+  double fx, fy, cx, cy;
+  double t[3];
+  double limx, limy, xc, yc;
+  int clampx, clampy;
+  double J00, J02, J11, J12;
+  double T[6];
+  double a, b, c, det, A, B, C;
+  double px, py;
+  bool ok;
+};
+
+__device__ inline void make_view(const gs_camera& cam, double mx, double my,
+                                 double mz, const Shape& S, View& P) {
+  for (int i = 0; i < 9; ++i) P.W[i] = (double)cam.R[i];
+  P.fx = (double)cam.fx;
+  P.fy = (double)cam.fy;
+  P.cx = (double)cam.cx;
+  P.cy = (double)cam.cy;
+  const double* W = P.W;
+  P.t[0] = ((W[0] * mx + W[1] * my) + W[2] * mz) + (double)cam.t[0];
+  P.t[1] = ((W[3] * mx + W[4] * my) + W[5] * mz) + (double)cam.t[1];
+  P.t[2] = ((W[6] * mx + W[7] * my) + W[8] * mz) + (double)cam.t[2];
+  const double tx = P.t[0], ty = P.t[1], tz = P.t[2];
+  P.ok = isfinite(tx) && isfinite(ty) && isfinite(tz) &&
+         tz > (double)cam.near_z && S.ok;
+  if (!P.ok) return;
+  P.limx = 1.3 * ((double)cam.width / (2.0 * P.fx));
+  P.limy = 1.3 * ((double)cam.height / (2.0 * P.fy));
+  double rx = tx / tz, ry = ty / tz;
+  P.clampx = 0;
+  P.clampy = 0;
+  if (rx > P.limx) { rx = P.limx; P.clampx = 1; }
+  if (rx < -P.limx) { rx = -P.limx; P.clampx = -1; }
+  if (ry > P.limy) { ry = P.limy; P.clampy = 1; }
+  if (ry < -P.limy) { ry = -P.limy; P.clampy = -1; }
+  P.xc = rx * tz;
+  P.yc = ry * tz;
+  const double tz2 = tz * tz;
+  P.J00 = P.fx / tz;
+  P.J02 = -(P.fx * P.xc) / tz2;
+  P.J11 = P.fy / tz;
+  P.J12 = -(P.fy * P.yc) / tz2;
+  for (int j = 0; j < 3; ++j) {
+    P.T[j] = P.J00 * W[j] + P.J02 * W[6 + j];
+    P.T[3 + j] = P.J11 * W[3 + j] + P.J12 * W[6 + j];
+  }
+  double U[6];
+  for (int i = 0; i < 2; ++i)
+    for (int j = 0; j < 3; ++j)
+      U[3 * i + j] = (P.T[3 * i] * S.Sig[j] + P.T[3 * i + 1] * S.Sig[3 + j]) +
+                     P.T[3 * i + 2] * S.Sig[6 + j];
+  P.a = ((U[0] * P.T[0] + U[1] * P.T[1]) + U[2] * P.T[2]) + 0.3;
+  P.b = (U[0] * P.T[3] + U[1] * P.T[4]) + U[2] * P.T[5];
+  P.c = ((U[3] * P.T[3] + U[4] * P.T[4]) + U[5] * P.T[5]) + 0.3;
+  P.det = P.a * P.c - P.b * P.b;
+  P.ok = P.det > 0.0 && isfinite(P.det);
+  if (!P.ok) return;
+  P.A = P.c / P.det;
+  P.B = -P.b / P.det;
+  P.C = P.a / P.det;
+  P.px = (P.fx * tx) / tz + P.cx;
+  P.py = (P.fy * ty) / tz + P.cy;
+}
+
+__global__ __launch_bounds__(256) void k_project(ProjArgs a) {
+  const int g = blockIdx.x * 256 + threadIdx.x;
+  const int n = min(*a.n_dev, a.cap);
+  if (g >= n) return;
+  const int cap = a.cap;
+  Shape S;
+  make_shape(a.lsc, a.quat, cap, g, S);
+  const double mx = a.mean[g], my = a.mean[cap + g], mz = a.mean[2 * cap + g];
+  const double op = 1.0 / (1.0 + exp(-(double)a.opl[g]));
+  const float r = a.rgb[g], gg = a.rgb[cap + g], bb = a.rgb[2 * cap + g];
+  for (int k = 0; k < a.V; ++k) {
+    const size_t slot = (size_t)k * cap + g;
+    View P;
+    make_view(a.cams[k], mx, my, mz, S, P);
+    bool ok = P.ok;
+    double ulo = 0, uhi = -1, vlo = 0, vhi = -1;
+    if (ok) {
+      const double mid = 0.5 * (P.a + P.c);
+      const double lam = mid + sqrt(fmax(0.1, mid * mid - P.det));
+      const double rad = ceil(3.0 * sqrt(lam));
+      ok = isfinite(P.px) && isfinite(P.py) && isfinite(rad);
+      if (ok) {
+        ulo = fmax(0.0, ceil(P.px - rad));
+        uhi = fmin((double)(a.W - 1), floor(P.px + rad));
+        vlo = fmax(0.0, ceil(P.py - rad));
+        vhi = fmin((double)(a.H - 1), floor(P.py + rad));
+        ok = ulo <= uhi && vlo <= vhi;
+      }
+    }
+    if (!ok) {
+      a.tiles[slot] = 0;
+      continue;
+    }
+    const int iu0 = (int)ulo, iu1 = (int)uhi, iv0 = (int)vlo, iv1 = (int)vhi;
+    Record R;
+    R.q0 = make_float4((float)P.px, (float)P.py, (float)P.A, (float)P.B);
+    R.q1 = make_float4((float)P.C, (float)op, r, gg);
+    R.q2 = make_float4(bb, (float)P.t[2],
+                       __int_as_float(iu0 | (iu1 << 16)),
+                       __int_as_float(iv0 | (iv1 << 16)));
+    a.rec[slot] = R;
+    const int tx0 = iu0 / a.tile, tx1 = iu1 / a.tile;
+    const int ty0 = iv0 / a.tile, ty1 = iv1 / a.tile;
+    a.tiles[slot] = (tx1 - tx0 + 1) * (ty1 - ty0 + 1);
+    // Tile-coverage difference grid: +1/-1 at the four corners of the box of
+    // tiles; a 2D prefix sum then yields the key count of every tile.
+    int32_t* d = a.diff + (size_t)k * (a.Ty + 1) * (a.Tx + 1);
+    const int stride = a.Tx + 1;
+    atomicAdd(&d[ty0 * stride + tx0], 1);
+    atomicAdd(&d[ty0 * stride + tx1 + 1], -1);
+    atomicAdd(&d[(ty1 + 1) * stride + tx0], -1);
+    atomicAdd(&d[(ty1 + 1) * stride + tx1 + 1], 1);
+  }
+}
+
+struct ProjBwdArgs {
+  const float* mean;
+  const float* lsc;
+  const float* quat;
+  const float* opl;
+  const int32_t* n_dev;
+  int cap;
+  const gs_camera* cams;
+  int V;
+  const int32_t* tiles;
+  float* grad2d;  // [V][5][cap], zeroed after reading
+  float* gop;     // [cap], zeroed after reading
+  float* d_mean;
+  float* d_lsc;
+  float* d_quat;
+  float* d_opl;
+};
+
+// Chain rule from dL/d(px, py, A, B, C) of every view back to the mean,
+// log-scale and quaternion, and from dL/d(opacity) to the logit.  Written in
+// matrix form: for the conic Q = Sigma2D^-1 the symmetric gradient is
+// G2 = -Q dQ Q; for Sigma2D = T Sigma T^T, dSigma = T^T G2 T and
+// dT = 2 G2 T Sigma; Sigma = M M^T gives dM = 2 dSigma M (summed over views).
+__global__ __launch_bounds__(256) void k_project_bwd(ProjBwdArgs a) {
+  const int g = blockIdx.x * 256 + threadIdx.x;
+  const int n = min(*a.n_dev, a.cap);
+  if (g >= n) return;
+  const int cap = a.cap;
+  Shape S;
+  make_shape(a.lsc, a.quat, cap, g, S);
+  const double mx = a.mean[g], my = a.mean[cap + g], mz = a.mean[2 * cap + g];
+  double dmu[3] = {0, 0, 0};
+  double dSig[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
+  for (int k = 0; k < a.V; ++k) {
+    const size_t slot = (size_t)k * cap + g;
+    if (a.tiles[slot] == 0) continue;
+    float* gk = a.grad2d + (size_t)k * 5 * cap + g;
+    const double dpx = gk[0], dpy = gk[cap], dA = gk[2 * (size_t)cap],
+                 dB = gk[3 * (size_t)cap], dC = gk[4 * (size_t)cap];
+    gk[0] = 0.f; gk[cap] = 0.f; gk[2 * (size_t)cap] = 0.f;
+    gk[3 * (size_t)cap] = 0.f; gk[4 * (size_t)cap] = 0.f;
+    if (dpx == 0.0 && dpy == 0.0 && dA == 0.0 && dB == 0.0 && dC == 0.0)
+      continue;
+    View P;
+    make_view(a.cams[k], mx, my, mz, S, P);
+    if (!P.ok) continue;
+    // Conic -> dilated screen covariance (symmetric matrix gradient).
+    const double Q[4] = {P.A, P.B, P.B, P.C};
+    const double GQ[4] = {dA, 0.5 * dB, 0.5 * dB, dC};
+    double X[4];  // GQ Q
+    X[0] = GQ[0] * Q[0] + GQ[1] * Q[2];
+    X[1] = GQ[0] * Q[1] + GQ[1] * Q[3];
+    X[2] = GQ[2] * Q[0] + GQ[3] * Q[2];
+    X[3] = GQ[2] * Q[1] + GQ[3] * Q[3];
+    double G2[4];  // -Q X
+    G2[0] = -(Q[0] * X[0] + Q[1] * X[2]);
+    G2[1] = -(Q[0] * X[1] + Q[1] * X[3]);
+    G2[2] = -(Q[2] * X[0] + Q[3] * X[2]);
+    G2[3] = -(Q[2] * X[1] + Q[3] * X[3]);
+    const double* T = P.T;
+    // dSigma += T^T G2 T
+    for (int i = 0; i < 3; ++i)
+      for (int j = 0; j < 3; ++j)
+        dSig[3 * i + j] += T[i] * (G2[0] * T[j] + G2[1] * T[3 + j]) +
+                           T[3 + i] * (G2[2] * T[j] + G2[3] * T[3 + j]);
+    // dT = (G2 + G2^T) T Sigma
+    double TS[6];
+    for (int i = 0; i < 2; ++i)
+      for (int j = 0; j < 3; ++j)
+        TS[3 * i + j] = T[3 * i] * S.Sig[j] + T[3 * i + 1] * S.Sig[3 + j] +
+                        T[3 * i + 2] * S.Sig[6 + j];
+    double dT[6];
+    for (int j = 0; j < 3; ++j) {
+      dT[j] = (2.0 * G2[0]) * TS[j] + (G2[1] + G2[2]) * TS[3 + j];
+      dT[3 + j] = (G2[1] + G2[2]) * TS[j] + (2.0 * G2[3]) * TS[3 + j];
+    }
+    // T = J W with J = [[J00, 0, J02], [0, J11, J12]]
+    const double* W = P.W;
+    double dJ00 = 0, dJ02 = 0, dJ11 = 0, dJ12 = 0;
+    for (int j = 0; j < 3; ++j) {
+      dJ00 += dT[j] * W[j];
+      dJ02 += dT[j] * W[6 + j];
+      dJ11 += dT[3 + j] * W[3 + j];
+      dJ12 += dT[3 + j] * W[6 + j];
+    }
+    const double tx = P.t[0], ty = P.t[1], tz = P.t[2];
+    const double itz = 1.0 / tz, itz2 = itz * itz, itz3 = itz2 * itz;
+    double dt[3];
+    // J02 = -fx xc / tz^2 with xc = tx, or xc = +-limx tz when clamped.
+    const double dJ02_dxc = -P.fx * itz2, dJ12_dyc = -P.fy * itz2;
+    dt[0] = (P.clampx ? 0.0 : dJ02 * dJ02_dxc) + dpx * P.fx * itz;
+    dt[1] = (P.clampy ? 0.0 : dJ12 * dJ12_dyc) + dpy * P.fy * itz;
+    dt[2] = -dJ00 * P.fx * itz2 - dJ11 * P.fy * itz2 +
+            dJ02 * (2.0 * P.fx * P.xc * itz3 +
+                    (P.clampx ? dJ02_dxc * P.clampx * P.limx : 0.0)) +
+            dJ12 * (2.0 * P.fy * P.yc * itz3 +
+                    (P.clampy ? dJ12_dyc * P.clampy * P.limy : 0.0)) -
+            dpx * P.fx * tx * itz2 - dpy * P.fy * ty * itz2;
+    for (int j = 0; j < 3; ++j)
+      dmu[j] += W[j] * dt[0] + W[3 + j] * dt[1] + W[6 + j] * dt[2];
+  }
+  // Shared shape chain: dM = 2 dSigma_sym M, with dSigma symmetrised.
+  double dM[9];
+  for (int i = 0; i < 3; ++i)
+    for (int j = 0; j < 3; ++j) {
+      double acc = 0.0;
+      for (int m = 0; m < 3; ++m)
+        acc += (dSig[3 * i + m] + dSig[3 * m + i]) * S.M[3 * m + j];
+      dM[3 * i + j] = acc;
+    }
+  double dR[9], ds[3] = {0, 0, 0};
+  for (int i = 0; i < 3; ++i)
+    for (int j = 0; j < 3; ++j) {
+      dR[3 * i + j] = dM[3 * i + j] * S.s[j];
+      ds[j] += dM[3 * i + j] * S.R[3 * i + j];
+    }
+  const double w = S.qn[0], x = S.qn[1], y = S.qn[2], z = S.qn[3];
+  // Partial derivatives of R(w, x, y, z) contracted with dR.
+  double dq[4];
+  dq[0] = 2.0 * (z * (dR[3] - dR[1]) + y * (dR[2] - dR[6]) + x * (dR[7] - dR[5]));
+  dq[1] = 2.0 * (y * (dR[1] + dR[3]) + z * (dR[2] + dR[6]) + w * (dR[7] - dR[5])) -
+          4.0 * x * (dR[4] + dR[8]);
+  dq[2] = 2.0 * (x * (dR[1] + dR[3]) + w * (dR[2] - dR[6]) + z * (dR[5] + dR[7])) -
+          4.0 * y * (dR[0] + dR[8]);
+  dq[3] = 2.0 * (w * (dR[3] - dR[1]) + x * (dR[2] + dR[6]) + y * (dR[5] + dR[7])) -
+          4.0 * z * (dR[0] + dR[4]);
+  const double dot = dq[0] * w + dq[1] * x + dq[2] * y + dq[3] * z;
+  const bool any = S.ok;
+  for (int j = 0; j < 3; ++j) {
+    a.d_mean[j * cap + g] += (float)dmu[j];
+    if (any) a.d_lsc[j * cap + g] += (float)(ds[j] * S.s[j]);
+  }
+  if (any)
+    for (int j = 0; j < 4; ++j)
+      a.d_quat[j * cap + g] += (float)((dq[j] - S.qn[j] * dot) / S.qnorm);
+  const double gop = a.gop[g];
+  a.gop[g] = 0.f;
+  const double o = 1.0 / (1.0 + exp(-(double)a.opl[g]));
+  a.d_opl[g] += (float)(gop * o * (1.0 - o));
+}
+
+}  // namespace
+
+hipError_t launch_project(gs_workspace* ws, const gs_params* p,
+                          const gs_camera* cams, hipStream_t st) {
+  ProjArgs a;
+  a.mean = p->mean; a.lsc = p->log_scale; a.quat = p->quat;
+  a.opl = p->opacity_logit; a.rgb = p->rgb; a.n_dev = p->n_dev;
+  a.cap = p->capacity; a.cams = cams; a.V = ws->geo.n_views;
+  a.W = ws->geo.width; a.H = ws->geo.height; a.tile = ws->geo.tile;
+  a.Tx = ws->tiles_x; a.Ty = ws->tiles_y;
+  a.rec = ws->records; a.tiles = ws->tiles_touched; a.diff = ws->diff;
+  const int blocks = (p->capacity + 255) / 256;
+  if (blocks > 0) hipLaunchKernelGGL(k_project, dim3(blocks), dim3(256), 0, st, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_project_bwd(gs_workspace* ws, const gs_params* p,
+                              const gs_camera* cams, gs_params* grad,
+                              hipStream_t st) {
+  ProjBwdArgs a;
+  a.mean = p->mean; a.lsc = p->log_scale; a.quat = p->quat;
+  a.opl = p->opacity_logit; a.n_dev = p->n_dev; a.cap = p->capacity;
+  a.cams = cams; a.V = ws->geo.n_views; a.tiles = ws->tiles_touched;
+  a.grad2d = ws->grad2d; a.gop = ws->gop;
+  a.d_mean = grad->mean; a.d_lsc = grad->log_scale; a.d_quat = grad->quat;
+  a.d_opl = grad->opacity_logit;
+  const int blocks = (p->capacity + 255) / 256;
+  if (blocks > 0)
+    hipLaunchKernelGGL(k_project_bwd, dim3(blocks), dim3(256), 0, st, a);
+  return hipGetLastError();
+}
+
+}  // namespace gs

@@ -1,0 +1,216 @@
+// Backward of the compositing (exact derivative of Eq. 3 with the forward's
+// decisions), per screen tile.
+//
+// One workgroup per (view, tile), the same pixel ownership as the forward.
+// Only per-pixel state is kept from the forward (T_final and n_last); the
+// list is walked back to front from the tile's largest n_last, and each
+// admitted entry's transmittance is recovered as T_i = T_{i+1} / (1 - a_i).
+// The colour accumulated behind entry i, dotted with dL/dC, follows
+// S_{i-1} = a_i (c_i . g) + (1 - a_i) S_i, so
+//   dL/dc_i     = a_i T_i g
+//   dL/da_i     = T_i (c_i . g - S_i) - T_final (bg . g) / (1 - a_i)
+//   dL/dpi_i    = a_i dL/da_i                 (a = o exp(pi), unclamped)
+//   dL/do_i     = G_i dL/da_i
+// and pi's derivatives give the 2D mean and conic gradients.  The nine
+// per-entry sums are reduced across each wave with DPP, merged across waves
+// in LDS, and added to global memory with one atomic per (entry, quantity).
+
+#include "raster_common.h"
+
+namespace gs {
+namespace {
+
+struct BwdArgs {
+  RasterArgs r;
+  const float* dL;
+  const float* Tfin;
+  const int32_t* nlast;
+  float* grad2d;   // [V][5][cap]
+  float* gop;      // [cap]
+  float* grgb;     // [3][cap] (caller's gradient rows, accumulated)
+};
+
+template <int CTRL, int ROW_MASK>
+__device__ __forceinline__ float dpp_step(float x) {
+  const int y = __builtin_amdgcn_update_dpp(0, __float_as_int(x), CTRL,
+                                            ROW_MASK, 0xf, false);
+  return x + __int_as_float(y);
+}
+
+// Sum over the 64 lanes of a wave; the total is valid in lane 63.
+__device__ __forceinline__ float wave_sum(float x) {
+  x = dpp_step<0xb1, 0xf>(x);   // quad_perm [1,0,3,2]
+  x = dpp_step<0x4e, 0xf>(x);   // quad_perm [2,3,0,1]
+  x = dpp_step<0x141, 0xf>(x);  // row_half_mirror
+  x = dpp_step<0x140, 0xf>(x);  // row_mirror
+  x = dpp_step<0x142, 0xa>(x);  // row_bcast:15 into rows 1 and 3
+  x = dpp_step<0x143, 0xc>(x);  // row_bcast:31 into rows 2 and 3
+  return x;
+}
+
+__device__ __forceinline__ float lane63(float x) {
+  return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(x), 63));
+}
+
+template <int TILE, int BATCH>
+__global__ __launch_bounds__(TILE * TILE > 256 ? 256 : TILE * TILE) void
+k_render_bwd(BwdArgs a) {
+  constexpr int NT = TILE * TILE > 256 ? 256 : TILE * TILE;
+  constexpr int PPT = TILE * TILE / NT;
+  __shared__ Entry ent[BATCH];
+  __shared__ float acc[BATCH][9];
+  __shared__ uint32_t gid[BATCH];
+  __shared__ int smax;
+  const RasterArgs& r = a.r;
+  const int t = blockIdx.x;
+  const int tpv = r.Tx * r.Ty;
+  const int k = t / tpv;
+  const int rem = t - k * tpv;
+  const int ty = rem / r.Tx, tx = rem - ty * r.Tx;
+  const int tid = threadIdx.x;
+  const int lane = tid & 63;
+  long long s, e;
+  tile_range(r, t, s, e);
+  const size_t HW = (size_t)r.H * r.W;
+
+  int u[PPT], v[PPT], last[PPT];
+  float T[PPT], g0[PPT], g1[PPT], g2[PPT], Tb[PPT], Sg[PPT];
+  int mylast = 0;
+#pragma unroll
+  for (int p = 0; p < PPT; ++p) {
+    const int l = tid + p * NT;
+    u[p] = tx * TILE + (l % TILE);
+    v[p] = ty * TILE + (l / TILE);
+    last[p] = 0;
+    T[p] = 1.f; g0[p] = g1[p] = g2[p] = 0.f; Tb[p] = 0.f; Sg[p] = 0.f;
+    if (u[p] < r.W && v[p] < r.H) {
+      const size_t pix = (size_t)v[p] * r.W + u[p];
+      T[p] = a.Tfin[(size_t)k * HW + pix];
+      last[p] = a.nlast[(size_t)k * HW + pix];
+      g0[p] = a.dL[((size_t)k * 3 + 0) * HW + pix];
+      g1[p] = a.dL[((size_t)k * 3 + 1) * HW + pix];
+      g2[p] = a.dL[((size_t)k * 3 + 2) * HW + pix];
+      Tb[p] = T[p] * (r.bg0 * g0[p] + r.bg1 * g1[p] + r.bg2 * g2[p]);
+      mylast = max(mylast, last[p]);
+    }
+  }
+  if (tid == 0) smax = 0;
+  __syncthreads();
+  atomicMax(&smax, mylast);
+  __syncthreads();
+  const int maxlast = (int)min((long long)smax, e - s);
+  const Record* rv = r.rec + (size_t)k * r.cap;
+  float* gk = a.grad2d + (size_t)k * 5 * r.cap;
+
+  for (int hi = maxlast; hi > 0; hi -= BATCH) {
+    const int lo = max(0, hi - BATCH);
+    const int cnt = hi - lo;
+    __syncthreads();
+    for (int i = tid; i < cnt; i += NT) {
+      const uint32_t g = r.vals[s + lo + i];
+      gid[i] = g;
+      stage(ent[i], rv[g]);
+    }
+    for (int i = tid; i < cnt * 9; i += NT) (&acc[0][0])[i] = 0.f;
+    __syncthreads();
+    for (int j = cnt - 1; j >= 0; --j) {
+      const int pos = lo + j;
+      const Entry& E = ent[j];
+      float d_px = 0.f, d_py = 0.f, d_A = 0.f, d_B = 0.f, d_C = 0.f;
+      float d_o = 0.f, d_r = 0.f, d_g = 0.f, d_b = 0.f;
+      bool hit = false;
+#pragma unroll
+      for (int p = 0; p < PPT; ++p) {
+        if (pos >= last[p] || !in_box(E.box, u[p], v[p])) continue;
+        float dx, dy, G, e2, oG;
+        const float al = eval_alpha(E, (float)u[p], (float)v[p], r.alpha_max,
+                                    dx, dy, G, e2, oG);
+        if (e2 > 0.f || al < r.alpha_min) continue;
+        hit = true;
+        const float om = 1.f - al;
+        const float rom = __builtin_amdgcn_rcpf(om);
+        T[p] = T[p] * rom;                       // T_i
+        const float w = al * T[p];
+        d_r = fmaf(w, g0[p], d_r);
+        d_g = fmaf(w, g1[p], d_g);
+        d_b = fmaf(w, g2[p], d_b);
+        const float cg = fmaf(E.b.z, g0[p], fmaf(E.b.w, g1[p], E.c.x * g2[p]));
+        const float diff = cg - Sg[p];
+        const float dal = fmaf(T[p], diff, -(Tb[p] * rom));
+        Sg[p] = fmaf(al, diff, Sg[p]);
+        if (oG > r.alpha_max) continue;          // clamped: no shape gradient
+        const float dpw = dal * al;
+        d_o = fmaf(dal, G, d_o);
+        const float A = E.c.y, B = E.c.z, C = E.c.w;
+        d_px = fmaf(-dpw, fmaf(A, dx, B * dy), d_px);
+        d_py = fmaf(-dpw, fmaf(C, dy, B * dx), d_py);
+        d_A = fmaf(-0.5f * dpw, dx * dx, d_A);
+        d_B = fmaf(-dpw, dx * dy, d_B);
+        d_C = fmaf(-0.5f * dpw, dy * dy, d_C);
+      }
+      if (__any(hit)) {
+        const float s0 = lane63(wave_sum(d_px));
+        const float s1 = lane63(wave_sum(d_py));
+        const float s2 = lane63(wave_sum(d_A));
+        const float s3 = lane63(wave_sum(d_B));
+        const float s4 = lane63(wave_sum(d_C));
+        const float s5 = lane63(wave_sum(d_o));
+        const float s6 = lane63(wave_sum(d_r));
+        const float s7 = lane63(wave_sum(d_g));
+        const float s8 = lane63(wave_sum(d_b));
+        if (lane == 0) {
+          float* ac = acc[j];
+          atomicAdd(&ac[0], s0); atomicAdd(&ac[1], s1); atomicAdd(&ac[2], s2);
+          atomicAdd(&ac[3], s3); atomicAdd(&ac[4], s4); atomicAdd(&ac[5], s5);
+          atomicAdd(&ac[6], s6); atomicAdd(&ac[7], s7); atomicAdd(&ac[8], s8);
+        }
+      }
+    }
+    __syncthreads();
+    for (int i = tid; i < cnt * 9; i += NT) {
+      const float val = (&acc[0][0])[i];
+      if (val == 0.f) continue;
+      const int jj = i / 9, q = i - jj * 9;
+      const uint32_t g = gid[jj];
+      if (q < 5) atomicAdd(&gk[(size_t)q * r.cap + g], val);
+      else if (q == 5) atomicAdd(&a.gop[g], val);
+      else atomicAdd(&a.grgb[(size_t)(q - 6) * r.cap + g], val);
+    }
+  }
+}
+
+template <int TILE, int BATCH>
+void launch_t(const BwdArgs& a, int blocks, hipStream_t st) {
+  constexpr int NT = TILE * TILE > 256 ? 256 : TILE * TILE;
+  hipLaunchKernelGGL((k_render_bwd<TILE, BATCH>), dim3(blocks), dim3(NT), 0,
+                     st, a);
+}
+
+template <int TILE>
+void launch_b(const BwdArgs& a, int batch, int blocks, hipStream_t st) {
+  if (batch == 128) launch_t<TILE, 128>(a, blocks, st);
+  else if (batch == 256) launch_t<TILE, 256>(a, blocks, st);
+  else launch_t<TILE, 512>(a, blocks, st);
+}
+
+}  // namespace
+
+hipError_t launch_render_bwd(gs_workspace* ws, const gs_settings* s,
+                             const float* dL, const float* T,
+                             const int32_t* nlast, float* grad_rgb,
+                             hipStream_t st) {
+  BwdArgs a;
+  a.r = make_raster_args(ws, s);
+  a.dL = dL; a.Tfin = T; a.nlast = nlast;
+  a.grad2d = ws->grad2d; a.gop = ws->gop; a.grgb = grad_rgb;
+  const int blocks = ws->geo.n_views * ws->tiles_x * ws->tiles_y;
+  if (blocks <= 0) return hipSuccess;
+  switch (ws->geo.tile) {
+    case 8: launch_b<8>(a, s->lds_batch, blocks, st); break;
+    case 16: launch_b<16>(a, s->lds_batch, blocks, st); break;
+    default: launch_b<32>(a, s->lds_batch, blocks, st); break;
+  }
+  return hipGetLastError();
+}
+
+}  // namespace gs

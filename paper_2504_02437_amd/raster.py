@@ -1,0 +1,364 @@
+"""Python surface of the rasterizer: device buffers, workspaces and the calls
+of the C ABI under the same names, plus a torch.autograd.Function.
+
+PyTorch is used for device memory and streams only.  Every computation runs
+in libgsmap's HIP kernels; this module marshals pointers and sizes.
+"""
+from __future__ import annotations
+
+import ctypes as C
+from dataclasses import dataclass, field
+
+import numpy as np
+import torch
+
+from . import _lib as L
+
+ROWS = {"mean": (0, 3), "log_scale": (3, 6), "quat": (6, 10),
+        "opacity_logit": (10, 11), "rgb": (11, 14)}
+ALPHA_MIN = float(np.float32(1.0) / np.float32(255.0))
+T_MIN = float(np.float32(1e-4))
+ALPHA_MAX = float(np.float32(0.99))
+
+
+def _ptr(t) -> C.c_void_p:
+    return C.c_void_p(0 if t is None else t.data_ptr())
+
+
+def _stream(stream) -> C.c_void_p:
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return C.c_void_p(stream.cuda_stream)
+
+
+def _require_cuda(t, name):
+    if not t.is_cuda:
+        raise ValueError(f"{name} must be a device tensor")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+
+
+class ParamBuffer:
+    """Gaussian parameters (or gradients / optimiser moments of the same
+    layout) as one FP32 device tensor [14][capacity] whose rows are
+    mean 0-2, log_scale 3-5, quat 6-9 (w, x, y, z), opacity_logit 10 and
+    rgb 11-13, plus a device int32 live count."""
+
+    def __init__(self, capacity: int, device="cuda", n: int = 0, data=None,
+                 n_dev=None):
+        self.capacity = int(capacity)
+        self.data = (torch.zeros(14, self.capacity, dtype=torch.float32,
+                                 device=device) if data is None else data)
+        assert self.data.shape == (14, self.capacity)
+        self.n_dev = (torch.tensor([n], dtype=torch.int32, device=device)
+                      if n_dev is None else n_dev)
+
+    @classmethod
+    def from_gaussians(cls, g, capacity=None, device="cuda"):
+        n = g.n
+        cap = n if capacity is None else int(capacity)
+        if cap < n:
+            raise ValueError("capacity below the Gaussian count")
+        host = np.zeros((14, cap), np.float32)
+        host[0:3, :n] = g.mean
+        host[3:6, :n] = g.log_scale
+        host[6:10, :n] = g.quat
+        host[10, :n] = g.opacity_logit
+        host[11:14, :n] = g.rgb
+        return cls(cap, device, n, torch.from_numpy(host).to(device))
+
+    def zeros_like(self, share_count=True):
+        return ParamBuffer(self.capacity, self.data.device,
+                           data=torch.zeros_like(self.data),
+                           n_dev=self.n_dev if share_count else None)
+
+    def row(self, name):
+        a, b = ROWS[name]
+        return self.data[a:b]
+
+    def n(self) -> int:
+        return int(self.n_dev.item())
+
+    def struct(self) -> L.gs_params:
+        base = self.data.data_ptr()
+        stride = self.capacity * 4
+        return L.gs_params(base + 0 * stride, base + 3 * stride,
+                           base + 6 * stride, base + 10 * stride,
+                           base + 11 * stride, self.n_dev.data_ptr(),
+                           self.capacity, 0)
+
+    def to_numpy(self):
+        n = self.n()
+        h = self.data[:, :n].cpu().numpy()
+        return {k: (h[a:b] if b - a > 1 else h[a]) for k, (a, b) in ROWS.items()}
+
+
+def camera_struct(cam) -> L.gs_camera:
+    c = L.gs_camera()
+    c.R[:] = [float(x) for x in np.asarray(cam.R, np.float32).ravel()]
+    c.t[:] = [float(x) for x in np.asarray(cam.t, np.float32).ravel()]
+    c.fx, c.fy, c.cx, c.cy = cam.fx, cam.fy, cam.cx, cam.cy
+    c.near_z = getattr(cam, "near", 0.2)
+    c.width, c.height = int(cam.width), int(cam.height)
+    return c
+
+
+def cameras_to_device(cams, device="cuda") -> torch.Tensor:
+    """gs_camera[V] packed into a device uint8 tensor."""
+    arr = (L.gs_camera * len(cams))(*[camera_struct(c) for c in cams])
+    host = np.frombuffer(bytes(arr), dtype=np.uint8).copy()
+    return torch.from_numpy(host).to(device)
+
+
+@dataclass
+class Settings:
+    tile: int = 16
+    lds_batch: int = 256
+    bg: tuple = (0.0, 0.0, 0.0)
+    alpha_min: float = ALPHA_MIN
+    T_min: float = T_MIN
+    alpha_max: float = ALPHA_MAX
+    emit_keys: bool = False
+
+    def struct(self) -> L.gs_settings:
+        s = L.gs_settings()
+        s.tile, s.lds_batch = self.tile, self.lds_batch
+        s.bg[:] = list(self.bg)
+        s.alpha_min, s.T_min, s.alpha_max = (self.alpha_min, self.T_min,
+                                             self.alpha_max)
+        s.flags = L.GS_FLAG_EMIT_KEYS if self.emit_keys else 0
+        return s
+
+
+class Workspace:
+    """A caller-owned device buffer carved by the library for one geometry."""
+
+    def __init__(self, n_views, width, height, tile, capacity, key_capacity,
+                 device="cuda", stream=None):
+        self.geo = L.gs_geometry(n_views, width, height, tile, capacity, 0,
+                                 int(key_capacity))
+        size = C.c_size_t()
+        L.call("gs_workspace_size", C.byref(self.geo), C.byref(size))
+        self.bytes = size.value
+        self.buf = torch.empty(self.bytes + 256, dtype=torch.uint8, device=device)
+        off = (-self.buf.data_ptr()) % 256
+        self.base = self.buf.data_ptr() + off
+        self.handle = C.c_void_p()
+        L.call("gs_workspace_create", C.byref(self.geo), C.c_void_p(self.base),
+               C.c_size_t(self.bytes), _stream(stream), C.byref(self.handle))
+        v = L.gs_workspace_view()
+        L.call("gs_workspace_get_view", self.handle, C.byref(v))
+        self.view = v
+        self.tiles_x, self.tiles_y = v.tiles_x, v.tiles_y
+        self.generation = 0
+
+    def __del__(self):
+        h = getattr(self, "handle", None)
+        if h is not None and h.value:
+            try:
+                L.lib().gs_workspace_destroy(h)
+            except Exception:
+                pass
+            self.handle = None
+
+    def _slice(self, ptr, dtype, count):
+        start = ptr - self.buf.data_ptr()
+        nbytes = count * torch.tensor([], dtype=dtype).element_size()
+        return self.buf[start:start + nbytes].view(dtype)
+
+    @property
+    def n_tiles(self):
+        return self.geo.n_views * self.tiles_x * self.tiles_y
+
+    def records(self):
+        """[V][capacity][12] float32 view of the projected records."""
+        V, cap = self.geo.n_views, self.geo.capacity
+        return self._slice(self.view.records, torch.float32, V * cap * 12).view(
+            V, cap, 12)
+
+    def tiles_touched(self):
+        V, cap = self.geo.n_views, self.geo.capacity
+        return self._slice(self.view.tiles_touched, torch.int32, V * cap).view(V, cap)
+
+    def ranges(self):
+        return self._slice(self.view.ranges, torch.int32, self.n_tiles * 2).view(
+            self.n_tiles, 2)
+
+    def vals_sorted(self, n):
+        return self._slice(self.view.vals_sorted, torch.int32, n)
+
+    def keys_sorted(self, n):
+        return self._slice(self.view.keys_sorted, torch.int64, n)
+
+    def grad2d(self):
+        V, cap = self.geo.n_views, self.geo.capacity
+        return self._slice(self.view.grad2d, torch.float32, V * 5 * cap).view(
+            V, 5, cap)
+
+
+# ---- The C ABI under its own names ---------------------------------------
+
+def project_and_bin(ws, params, cams_dev, settings, stream=None):
+    L.call("gs_project_and_bin", ws.handle, C.byref(params.struct()),
+           _ptr(cams_dev), C.byref(settings.struct()), _stream(stream))
+    ws.generation += 1
+
+
+def sort_tile_keys(ws, settings, stream=None):
+    L.call("gs_sort_tile_keys", ws.handle, C.byref(settings.struct()),
+           _stream(stream))
+
+
+def render_fwd(ws, params, settings, out_rgb, out_T, out_nlast, stream=None):
+    for t, nm in ((out_rgb, "out_rgb"), (out_T, "out_T"), (out_nlast, "out_nlast")):
+        _require_cuda(t, nm)
+    V, H, W = ws.geo.n_views, ws.geo.height, ws.geo.width
+    if out_rgb.numel() != V * 3 * H * W or out_T.numel() != V * H * W or \
+            out_nlast.numel() != V * H * W:
+        raise ValueError("output sizes do not match the workspace geometry")
+    if out_rgb.dtype != torch.float32 or out_T.dtype != torch.float32 or \
+            out_nlast.dtype != torch.int32:
+        raise ValueError("outputs must be float32, float32, int32")
+    L.call("gs_render_fwd", ws.handle, C.byref(params.struct()),
+           C.byref(settings.struct()), _ptr(out_rgb), _ptr(out_T),
+           _ptr(out_nlast), _stream(stream))
+
+
+def render_bwd(ws, params, cams_dev, settings, dL_drgb, T_final, n_last, grad,
+               stream=None):
+    V, H, W = ws.geo.n_views, ws.geo.height, ws.geo.width
+    for t, nm, cnt in ((dL_drgb, "dL_drgb", V * 3 * H * W),
+                       (T_final, "T_final", V * H * W),
+                       (n_last, "n_last", V * H * W)):
+        _require_cuda(t, nm)
+        if t.numel() != cnt:
+            raise ValueError(f"{nm} size does not match the workspace geometry")
+    L.call("gs_render_bwd", ws.handle, C.byref(params.struct()),
+           _ptr(cams_dev), C.byref(settings.struct()), _ptr(dL_drgb),
+           _ptr(T_final), _ptr(n_last), C.byref(grad.struct()), _stream(stream))
+
+
+def loss_l1(rgb, target, lam, dL_drgb, loss_dev, sqerr_dev=None, stream=None):
+    V, _, H, W = rgb.shape
+    for t, nm in ((rgb, "rgb"), (target, "target"), (dL_drgb, "dL_drgb")):
+        _require_cuda(t, nm)
+        if t.shape != rgb.shape or t.dtype != torch.float32:
+            raise ValueError(f"{nm} must be float32 of shape {tuple(rgb.shape)}")
+    if loss_dev.dtype != torch.float64:
+        raise ValueError("loss_dev must be float64")
+    L.call("gs_loss_l1", _ptr(rgb), _ptr(target), V, H, W, float(lam),
+           _ptr(dL_drgb), _ptr(loss_dev), _ptr(sqerr_dev), _stream(stream))
+
+
+def planar_reg(params, lam, floor, grad, loss_dev, stream=None):
+    L.call("gs_planar_reg", C.byref(params.struct()), float(lam), float(floor),
+           C.byref(grad.struct()), _ptr(loss_dev), _stream(stream))
+
+
+def adam(params, grad, m, v, lr, beta1, beta2, eps, step, stream=None):
+    lr_arr = (C.c_float * 5)(*[float(x) for x in lr])
+    L.call("gs_adam", C.byref(params.struct()), C.byref(grad.struct()),
+           C.byref(m.struct()), C.byref(v.struct()), lr_arr, float(beta1),
+           float(beta2), float(eps), int(step), _stream(stream))
+
+
+def insert_gaussians(params, m, v, cam_dev, width, height, kf_rgb, kf_T, pts,
+                     alpha_skip=0.9, centre_only=False, mlp_out=None,
+                     n_inserted_dev=None, status_dev=None, stream=None):
+    n_pts = 0 if pts is None else pts.shape[0]
+    L.call("gs_insert_gaussians", C.byref(params.struct()),
+           C.byref(m.struct()) if m is not None else None,
+           C.byref(v.struct()) if v is not None else None, _ptr(cam_dev),
+           int(width), int(height), _ptr(kf_rgb), _ptr(kf_T), _ptr(pts), n_pts,
+           float(alpha_skip), 1 if centre_only else 0, _ptr(mlp_out),
+           _ptr(n_inserted_dev), _ptr(status_dev), _stream(stream))
+
+
+def read_status(ws, stream=None, clear=False):
+    flags = C.c_int32()
+    nk = C.c_int64()
+    rc = L.lib().gs_read_status(ws.handle, _stream(stream), C.byref(flags),
+                                C.byref(nk), 1 if clear else 0)
+    if rc not in (L.GS_OK, L.GS_E_OVERFLOW):
+        L.check(rc)
+    return flags.value, nk.value
+
+
+# ---- Convenience: one rasterizer over a fixed set of views ---------------
+
+def default_key_capacity(capacity, n_views):
+    return int(min(2 ** 31 - 1, max(1 << 20, 48 * capacity * n_views)))
+
+
+class Rasterizer:
+    """Project, bin, sort and render a ParamBuffer into a fixed set of views,
+    holding the workspace and the per-pixel outputs of the last forward."""
+
+    def __init__(self, cams, capacity, settings: Settings | None = None,
+                 key_capacity=None, device="cuda"):
+        self.settings = settings or Settings()
+        self.cams = list(cams)
+        self.V = len(self.cams)
+        self.W, self.H = self.cams[0].width, self.cams[0].height
+        for c in self.cams:
+            if (c.width, c.height) != (self.W, self.H):
+                raise ValueError("all views must share the image size")
+        self.capacity = capacity
+        kc = default_key_capacity(capacity, self.V) if key_capacity is None \
+            else key_capacity
+        self.ws = Workspace(self.V, self.W, self.H, self.settings.tile,
+                            capacity, kc, device)
+        self.cams_dev = cameras_to_device(self.cams, device)
+        self.rgb = torch.empty(self.V, 3, self.H, self.W, device=device)
+        self.T = torch.empty(self.V, self.H, self.W, device=device)
+        self.nlast = torch.empty(self.V, self.H, self.W, dtype=torch.int32,
+                                 device=device)
+
+    def set_cameras(self, cams):
+        if len(cams) != self.V:
+            raise ValueError("view count is fixed per rasterizer")
+        self.cams = list(cams)
+        self.cams_dev.copy_(cameras_to_device(cams, self.cams_dev.device))
+
+    def forward(self, params, stream=None):
+        project_and_bin(self.ws, params, self.cams_dev, self.settings, stream)
+        sort_tile_keys(self.ws, self.settings, stream)
+        render_fwd(self.ws, params, self.settings, self.rgb, self.T,
+                   self.nlast, stream)
+        return self.rgb, self.T, self.nlast
+
+    def backward(self, params, dL_drgb, grad, stream=None):
+        render_bwd(self.ws, params, self.cams_dev, self.settings,
+                   dL_drgb.contiguous(), self.T, self.nlast, grad, stream)
+
+    def status(self, clear=False):
+        return read_status(self.ws, None, clear)
+
+
+class Rasterize(torch.autograd.Function):
+    """Differentiable render: forward keeps only per-pixel state (T_final,
+    n_last) and the sorted tile lists; backward recomputes each entry's
+    transmittance inside render_bwd."""
+
+    @staticmethod
+    def forward(ctx, data, rast: Rasterizer, params: ParamBuffer):
+        if data.data_ptr() != params.data.data_ptr():
+            raise ValueError("data must be params.data")
+        rgb, T, nlast = rast.forward(params)
+        ctx.rast = rast
+        ctx.params = params
+        ctx.generation = rast.ws.generation
+        ctx.mark_non_differentiable(T, nlast)
+        return rgb.clone(), T.clone(), nlast.clone()
+
+    @staticmethod
+    def backward(ctx, g_rgb, g_T, g_nlast):
+        rast, params = ctx.rast, ctx.params
+        if rast.ws.generation != ctx.generation:
+            raise RuntimeError("another forward ran on this rasterizer before "
+                               "the backward of this one")
+        grad = params.zeros_like()
+        if g_rgb is None:
+            g_rgb = torch.zeros_like(rast.rgb)
+        rast.backward(params, g_rgb.contiguous(), grad)
+        return grad.data, None, None
