@@ -51,7 +51,7 @@ def lib():
         L.or_forward.argtypes = [C.c_int, C.c_int, C.c_int, C.c_int, C.c_int,
                                  _d, _i32, _d, _u32, _u32, _d, C.c_double,
                                  C.c_double, C.c_double, _d, _d, _i32, _u8, _d,
-                                 _i64, _u8, C.c_int, C.c_int, C.c_int]
+                                 _d, _i64, _u8, C.c_int, C.c_int, C.c_int]
         L.or_backward.restype = C.c_int
         L.or_backward.argtypes = [C.c_int, C.c_int, C.c_int, C.c_int, C.c_int,
                                   _d, _i32, _d, _u32, _u32, _d, C.c_double,
@@ -158,6 +158,7 @@ def forward(proj, bins, rgb, W, H, bg=(0.0, 0.0, 0.0), alpha_min=ALPHA_MIN,
     nlast = np.zeros((V, H, W), np.int32)
     flags = np.zeros((V, H, W), np.uint8)
     errb = np.zeros((V, H, W))
+    terr = np.zeros((V, H, W))
     cnt = np.zeros(3, np.int64)
     bgv = np.asarray(bg, np.float64)
     Ld = 0 if dec is None else dec.shape[-1]
@@ -167,11 +168,11 @@ def forward(proj, bins, rgb, W, H, bg=(0.0, 0.0, 0.0), alpha_min=ALPHA_MIN,
                       _p(proj["box"], _i32), _p(rgb, _d), _p(vals, _u32),
                       _p(bins["ranges"], _u32), _p(bgv, _d), alpha_min, T_min,
                       alpha_max, _p(img, _d), _p(T, _d), _p(nlast, _i32),
-                      _p(flags, _u8), _p(errb, _d), _p(cnt, _i64),
+                      _p(flags, _u8), _p(errb, _d), _p(terr, _d), _p(cnt, _i64),
                       _p(dec, _u8), Ld, dec_mode, nthreads)
     if rc != 0:
         raise ValueError("decision buffer too short")
-    return dict(img=img, T=T, nlast=nlast, flags=flags, errb=errb,
+    return dict(img=img, T=T, nlast=nlast, flags=flags, errb=errb, terr=terr,
                 counters=dict(examined=int(cnt[0]), inbox=int(cnt[1]),
                               contributing=int(cnt[2])))
 

@@ -343,24 +343,31 @@ static int eval_pair(const fwdcfg* F, const double* r, const int32_t* b,
   const double pw = -0.5 * (A * dx * dx + C * dy * dy) - B * dx * dy;
   const double S = fabs(A) * dx * dx + 2.0 * fabs(B) * fabs(dx * dy) +
                    fabs(C) * dy * dy;
-  const double ea = EPS32 * (8.0 * S + 8.0);
+  /* First-order bound on the relative error of alpha evaluated in FP32:
+   * the exponent is a sum of three products (about 2 eps S), its scaling and
+   * exponential add about eps (|pi| + 2) <= eps (S / 2 + 2), and the product
+   * with the opacity one more eps; 4 S + 4 keeps a margin over 2.5 S + 3. */
+  const double ea = EPS32 * (4.0 * S + 4.0);
   if (ea_out) *ea_out = ea;
   *dxo = dx; *dyo = dy;
-  if (amb && pw != 0.0 && fabs(pw) <= 8.0 * EPS32 * S) *amb = 1;
+  if (amb && pw != 0.0 && fabs(pw) <= 8.0 * EPS32 * S) *amb |= 8;
   if (pw > 0.0) return DEC_SKIP;
   const double g = exp(pw);
   const double og = o * g;
   const double a = og < F->alpha_max ? og : F->alpha_max;
   *G = g;
-  const double band = fmax(1e-5, 2.0 * ea);
-  if (amb && fabs(og - F->alpha_max) <= F->alpha_max * band) *amb = 1;
-  if (amb && fabs(a - F->alpha_min) <= F->alpha_min * band) *amb = 1;
+  const double band = fmax(1e-5, ea);
+  if (amb && fabs(og - F->alpha_max) <= F->alpha_max * band) *amb |= 2;
+  if (amb && fabs(a - F->alpha_min) <= F->alpha_min * band) *amb |= 1;
   if (a < F->alpha_min) return DEC_SKIP;
   *alpha = a;
+  /* A clamped alpha is exactly alpha_max in any precision: no alpha error. */
+  if (og > F->alpha_max && ea_out) *ea_out = 0.0;
   const double Tn = T * (1.0 - a);
   if (amb) {
-    const double rTn = rT + ea * a / (1.0 - a) + 2.0 * EPS32;
-    if (fabs(Tn - F->T_min) <= F->T_min * fmax(1e-5, 2.0 * rTn)) *amb = 1;
+    const double rTn = rT + (og > F->alpha_max ? 0.0 : ea * a / (1.0 - a)) +
+                       2.0 * EPS32;
+    if (fabs(Tn - F->T_min) <= F->T_min * fmax(1e-5, rTn)) *amb |= 4;
   }
   if (Tn < F->T_min) return DEC_STOP;
   return og > F->alpha_max ? DEC_CLAMP : DEC_ADMIT;
@@ -369,9 +376,12 @@ static int eval_pair(const fwdcfg* F, const double* r, const int32_t* b,
 /* Per view: rec [V][n][8], box [V][n][4]; rgb [3][n]; sorted values and
  * ranges from or_bin_sort.  Outputs image [V][3][H][W], T_final [V][H][W],
  * n_last [V][H][W] (index in the tile list of the last contributing entry,
- * plus one).  flags (optional) bit 0: a threshold decision is ambiguous at
- * FP32 precision.  errb (optional): bound on the FP32 colour error of the
- * pixel.  counters (optional) [3]: examined, in-box, contributing pairs.
+ * plus one).  flags (optional): non-zero when a threshold decision of the
+ * pixel lies within the error an FP32 evaluation can carry (bit 0: alpha vs
+ * alpha_min, bit 1: the alpha clamp, bit 2: the transmittance stop, bit 3:
+ * the sign of the exponent).  errb (optional): bound on the FP32 colour error of the
+ * pixel; terr (optional): bound on the relative FP32 error of T_final.
+ * counters (optional) [3]: examined, in-box, contributing pairs.
  * dec (optional) [V][H][W][L]: decision codes recorded (dec_mode 1) or
  * replayed (dec_mode 2) per list position. */
 OR_EXPORT int or_forward(int V, int W, int H, int tile, int n,
@@ -380,8 +390,9 @@ OR_EXPORT int or_forward(int V, int W, int H, int tile, int n,
                          const uint32_t* ranges, const double* bg,
                          double alpha_min, double T_min, double alpha_max,
                          double* img, double* Tfin, int32_t* nlast,
-                         uint8_t* flags, double* errb, int64_t* counters,
-                         uint8_t* dec, int L, int dec_mode, int nthreads) {
+                         uint8_t* flags, double* errb, double* terr,
+                         int64_t* counters, uint8_t* dec, int L, int dec_mode,
+                         int nthreads) {
   fwdcfg F = {W, H, tile, (W + tile - 1) / tile, (H + tile - 1) / tile, n,
               alpha_min, T_min, alpha_max, {bg[0], bg[1], bg[2]}};
   const int64_t ntiles = (int64_t)V * F.Tx * F.Ty;
@@ -447,8 +458,9 @@ OR_EXPORT int or_forward(int V, int W, int H, int tile, int n,
         }
         Tfin[pix] = T;
         nlast[pix] = last;
-        if (flags) flags[pix] = (uint8_t)(amb ? 1 : 0);
+        if (flags) flags[pix] = (uint8_t)amb;
         if (errb) errb[pix] = eb;
+        if (terr) terr[pix] = rT;
       }
   }
   if (counters) {

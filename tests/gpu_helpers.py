@@ -8,7 +8,7 @@ from paper_2504_02437_amd import raster as R
 
 IMG_TOL = 1e-5       # absolute, per pixel and channel (FP32 vs FP64)
 GRAD_RTOL = 1e-3     # relative, with a floor of 1e-2 * max |g| per tensor
-MAX_FLAGGED = 2e-3   # fraction of pixels whose decisions are FP32-ambiguous
+MAX_FLAGGED = 1e-3   # fraction of pixels whose decisions are FP32-ambiguous
 
 
 def gpu_forward(w, tile=16, batch=256, bg=(0.0, 0.0, 0.0), emit_keys=True,
