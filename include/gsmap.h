@@ -192,16 +192,42 @@ GS_API int gs_render_fwd(gs_workspace* ws, const gs_params* params,
                   const gs_settings* s, float* out_rgb, float* out_T,
                   int32_t* out_nlast, void* stream);
 
-/* Backward of render + projection: given dL/d(out_rgb) [n_views][3][H][W]
- * and the forward's out_T / out_nlast, walks each tile's list back to front
- * recomputing the transmittance, and ACCUMULATES (+=) dL/d(parameters) into
- * `grad` (same layout as gs_params; the caller zeroes it).  The chain through
- * the projection runs in FP64.  Clamped alphas pass no gradient to opacity
- * or shape.  cams as in gs_project_and_bin. */
+/* Work counters of the forward walk (same decisions as gs_render_fwd, no
+ * image written), for roofline accounting.  ADDS to counts_dev[4] (device
+ * uint64):
+ *   [0] (pixel, entry) pairs examined: from the start of the pixel's tile
+ *       list up to and including the entry at which the pixel stops
+ *   [1] those of them whose pixel lies in the entry's box
+ *   [2] contributing (admitted and blended) pairs
+ *   [3] in-box pairs at positions before the pixel's n_last (the pairs a
+ *       backward pass revisits) */
+GS_API int gs_count_pairs(gs_workspace* ws, const gs_params* params,
+                          const gs_settings* s, uint64_t* counts_dev,
+                          void* stream);
+
+/* Backward of the compositing (exact derivative of Eq. 3 with the forward's
+ * decisions): given dL/d(out_rgb) [n_views][3][H][W] and the forward's out_T
+ * and out_nlast, walks each tile's list back to front recomputing every
+ * entry's transmittance from T_final (no per-entry state is stored), ADDS
+ * dL/d(colour) into grad->rgb and accumulates dL/d(mean2D, conic) per view
+ * and dL/d(opacity) into the workspace, where gs_project_bwd consumes them.
+ * Clamped alphas pass no gradient to opacity or shape.  Call
+ * gs_project_bwd afterwards, on the same stream, to finish the backward. */
 GS_API int gs_render_bwd(gs_workspace* ws, const gs_params* params,
-                  const gs_camera* cams, const gs_settings* s,
-                  const float* dL_drgb, const float* T_final,
-                  const int32_t* n_last, gs_params* grad, void* stream);
+                         const gs_settings* s, const float* dL_drgb,
+                         const float* T_final, const int32_t* n_last,
+                         gs_params* grad, void* stream);
+
+/* Backward of the projection (Eq. 1-2, FP64): chains the screen-space
+ * gradients that gs_render_bwd left in the workspace, summed over the views,
+ * through the conic, the EWA covariance, the Jacobian and the view transform
+ * to the mean, log-scale and quaternion, and the opacity gradient through the
+ * sigmoid; ADDS them into `grad` (same layout as gs_params; the caller
+ * zeroes it) and clears the workspace's screen-space gradients for the next
+ * backward.  cams as in gs_project_and_bin. */
+GS_API int gs_project_bwd(gs_workspace* ws, const gs_params* params,
+                          const gs_camera* cams, gs_params* grad,
+                          void* stream);
 
 /* Photometric term of the map-optimisation loss (Eq. 10-11, L1 part):
  * per view lambda * mean over 3HW of |rgb - target|; writes dL/drgb =

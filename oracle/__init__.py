@@ -159,7 +159,7 @@ def forward(proj, bins, rgb, W, H, bg=(0.0, 0.0, 0.0), alpha_min=ALPHA_MIN,
     flags = np.zeros((V, H, W), np.uint8)
     errb = np.zeros((V, H, W))
     terr = np.zeros((V, H, W))
-    cnt = np.zeros(3, np.int64)
+    cnt = np.zeros(4, np.int64)
     bgv = np.asarray(bg, np.float64)
     Ld = 0 if dec is None else dec.shape[-1]
     rgb = np.ascontiguousarray(rgb, np.float64)
@@ -174,7 +174,7 @@ def forward(proj, bins, rgb, W, H, bg=(0.0, 0.0, 0.0), alpha_min=ALPHA_MIN,
         raise ValueError("decision buffer too short")
     return dict(img=img, T=T, nlast=nlast, flags=flags, errb=errb, terr=terr,
                 counters=dict(examined=int(cnt[0]), inbox=int(cnt[1]),
-                              contributing=int(cnt[2])))
+                              contributing=int(cnt[2]), revisit=int(cnt[3])))
 
 
 def decision_buffer(bins, V, W, H):

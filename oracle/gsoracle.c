@@ -381,7 +381,9 @@ static int eval_pair(const fwdcfg* F, const double* r, const int32_t* b,
  * alpha_min, bit 1: the alpha clamp, bit 2: the transmittance stop, bit 3:
  * the sign of the exponent).  errb (optional): bound on the FP32 colour error of the
  * pixel; terr (optional): bound on the relative FP32 error of T_final.
- * counters (optional) [3]: examined, in-box, contributing pairs.
+ * counters (optional) [4]: examined pairs (up to and including the stop
+ * entry), in-box pairs among them, contributing pairs, and in-box pairs at
+ * positions before n_last (the ones a backward pass revisits).
  * dec (optional) [V][H][W][L]: decision codes recorded (dec_mode 1) or
  * replayed (dec_mode 2) per list position. */
 OR_EXPORT int or_forward(int V, int W, int H, int tile, int n,
@@ -396,12 +398,12 @@ OR_EXPORT int or_forward(int V, int W, int H, int tile, int n,
   fwdcfg F = {W, H, tile, (W + tile - 1) / tile, (H + tile - 1) / tile, n,
               alpha_min, T_min, alpha_max, {bg[0], bg[1], bg[2]}};
   const int64_t ntiles = (int64_t)V * F.Tx * F.Ty;
-  int64_t c_exam = 0, c_inbox = 0, c_contrib = 0;
+  int64_t c_exam = 0, c_inbox = 0, c_contrib = 0, c_revisit = 0;
   int bad = 0;
 #ifdef _OPENMP
   if (nthreads < 1) nthreads = 1;
 #pragma omp parallel for schedule(dynamic, 4) num_threads(nthreads) \
-    reduction(+ : c_exam, c_inbox, c_contrib, bad)
+    reduction(+ : c_exam, c_inbox, c_contrib, c_revisit, bad)
 #endif
   for (int64_t t = 0; t < ntiles; ++t) {
     const int k = (int)(t / ((int64_t)F.Tx * F.Ty));
@@ -413,6 +415,7 @@ OR_EXPORT int or_forward(int V, int W, int H, int tile, int n,
         const size_t pix = ((size_t)k * H + v) * W + u;
         double T = 1.0, Cc[3] = {0, 0, 0}, err[3] = {0, 0, 0}, rT = 0.0;
         int last = 0, amb = 0;
+        int64_t ib = 0, ib_last = 0;
         for (uint32_t i = s; i < e; ++i) {
           const uint32_t g = vals[i];
           const double* r = &rec[((size_t)k * n + g) * REC_STRIDE];
@@ -420,7 +423,10 @@ OR_EXPORT int or_forward(int V, int W, int H, int tile, int n,
           double alpha = 0, G = 0, dx = 0, dy = 0, ea = 0;
           int code;
           c_exam += 1;
-          if (u >= b[0] && u <= b[1] && v >= b[2] && v <= b[3]) c_inbox += 1;
+          if (u >= b[0] && u <= b[1] && v >= b[2] && v <= b[3]) {
+            c_inbox += 1;
+            ib += 1;
+          }
           if (dec_mode == 2) {
             if ((int)(i - s) >= L) { bad = 1; break; }
             code = dec[pix * L + (i - s)];
@@ -449,7 +455,9 @@ OR_EXPORT int or_forward(int V, int W, int H, int tile, int n,
           rT += ea * alpha / (1.0 - alpha) + 2.0 * EPS32;
           T = T * (1.0 - alpha);
           last = (int)(i - s) + 1;
+          ib_last = ib;
         }
+        c_revisit += ib_last;
         double eb = 0.0;
         for (int ch = 0; ch < 3; ++ch) {
           img[(((size_t)k * 3 + ch) * H + v) * W + u] = Cc[ch] + T * F.bg[ch];
@@ -465,6 +473,7 @@ OR_EXPORT int or_forward(int V, int W, int H, int tile, int n,
   }
   if (counters) {
     counters[0] = c_exam; counters[1] = c_inbox; counters[2] = c_contrib;
+    counters[3] = c_revisit;
   }
   return bad ? -1 : 0;
 }

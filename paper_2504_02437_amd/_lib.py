@@ -75,8 +75,12 @@ _SIGS = {
     "gs_sort_tile_keys": (C.c_int, [_vp, _P(gs_settings), _vp]),
     "gs_render_fwd": (C.c_int, [_vp, _P(gs_params), _P(gs_settings), _vp, _vp,
                                 _vp, _vp]),
-    "gs_render_bwd": (C.c_int, [_vp, _P(gs_params), _vp, _P(gs_settings), _vp,
+    "gs_count_pairs": (C.c_int, [_vp, _P(gs_params), _P(gs_settings), _vp,
+                                 _vp]),
+    "gs_render_bwd": (C.c_int, [_vp, _P(gs_params), _P(gs_settings), _vp,
                                 _vp, _vp, _P(gs_params), _vp]),
+    "gs_project_bwd": (C.c_int, [_vp, _P(gs_params), _vp, _P(gs_params),
+                                 _vp]),
     "gs_loss_l1": (C.c_int, [_vp, _vp, C.c_int32, C.c_int32, C.c_int32,
                              C.c_float, _vp, _vp, _vp, _vp]),
     "gs_planar_reg": (C.c_int, [_P(gs_params), C.c_float, C.c_float,

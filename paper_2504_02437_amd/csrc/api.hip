@@ -244,8 +244,20 @@ int gs_render_fwd(gs_workspace* ws, const gs_params* params,
                                   (hipStream_t)stream), "render_fwd");
 }
 
+int gs_count_pairs(gs_workspace* ws, const gs_params* params,
+                   const gs_settings* s, uint64_t* counts_dev, void* stream) {
+  g_err[0] = 0;
+  if (int rc = check_ws(ws)) return rc;
+  if (int rc = validate_params(params, "params")) return rc;
+  if (int rc = validate_settings(s)) return rc;
+  if (s->tile != ws->geo.tile) { set_error("settings.tile differs from the workspace's"); return GS_E_INVALID; }
+  if (!counts_dev) { set_error("counts_dev is NULL"); return GS_E_INVALID; }
+  return finish(launch_count_pairs(ws, s, (unsigned long long*)counts_dev,
+                                   (hipStream_t)stream), "count_pairs");
+}
+
 int gs_render_bwd(gs_workspace* ws, const gs_params* params,
-                  const gs_camera* cams, const gs_settings* s,
+                  const gs_settings* s,
                   const float* dL_drgb, const float* T_final,
                   const int32_t* n_last, gs_params* grad, void* stream) {
   g_err[0] = 0;
@@ -254,7 +266,7 @@ int gs_render_bwd(gs_workspace* ws, const gs_params* params,
   if (int rc = validate_params(grad, "grad")) return rc;
   if (int rc = validate_settings(s)) return rc;
   if (s->tile != ws->geo.tile) { set_error("settings.tile differs from the workspace's"); return GS_E_INVALID; }
-  if (!cams || !dL_drgb || !T_final || !n_last || !params->n_dev) {
+  if (!dL_drgb || !T_final || !n_last) {
     set_error("an input is NULL");
     return GS_E_INVALID;
   }
@@ -262,10 +274,23 @@ int gs_render_bwd(gs_workspace* ws, const gs_params* params,
     set_error("grad / params / workspace capacities differ");
     return GS_E_CAPACITY;
   }
-  hipStream_t st = (hipStream_t)stream;
-  hipError_t e = launch_render_bwd(ws, s, dL_drgb, T_final, n_last, grad->rgb, st);
-  if (e != hipSuccess) return finish(e, "render_bwd");
-  return finish(launch_project_bwd(ws, params, cams, grad, st), "project_bwd");
+  return finish(launch_render_bwd(ws, s, dL_drgb, T_final, n_last, grad->rgb,
+                                  (hipStream_t)stream), "render_bwd");
+}
+
+int gs_project_bwd(gs_workspace* ws, const gs_params* params,
+                   const gs_camera* cams, gs_params* grad, void* stream) {
+  g_err[0] = 0;
+  if (int rc = check_ws(ws)) return rc;
+  if (int rc = validate_params(params, "params")) return rc;
+  if (int rc = validate_params(grad, "grad")) return rc;
+  if (!cams || !params->n_dev) { set_error("an input is NULL"); return GS_E_INVALID; }
+  if (grad->capacity != params->capacity || params->capacity != ws->geo.capacity) {
+    set_error("grad / params / workspace capacities differ");
+    return GS_E_CAPACITY;
+  }
+  return finish(launch_project_bwd(ws, params, cams, grad, (hipStream_t)stream),
+                "project_bwd");
 }
 
 int gs_loss_l1(const float* rgb, const float* target, int32_t n_views,

@@ -70,6 +70,8 @@ hipError_t launch_sort(gs_workspace* ws, const gs_settings* s, hipStream_t st);
 hipError_t launch_render_fwd(gs_workspace* ws, const gs_settings* s,
                              float* rgb, float* T, int32_t* nlast,
                              hipStream_t st);
+hipError_t launch_count_pairs(gs_workspace* ws, const gs_settings* s,
+                              unsigned long long* counts, hipStream_t st);
 hipError_t launch_render_bwd(gs_workspace* ws, const gs_settings* s,
                              const float* dL, const float* T,
                              const int32_t* nlast, float* grad_rgb,

@@ -19,9 +19,13 @@ struct FwdArgs {
   float* rgb;
   float* T;
   int32_t* nlast;
+  unsigned long long* counts;  // counting variant only
 };
 
-template <int TILE, int BATCH>
+// COUNT = true is the work-counting variant: the same walk and decisions,
+// adding up examined / in-box / contributing / revisited pairs instead of
+// writing the image.
+template <int TILE, int BATCH, bool COUNT>
 __global__ __launch_bounds__(TILE * TILE > 256 ? 256 : TILE * TILE) void
 k_render_fwd(FwdArgs a) {
   constexpr int NT = TILE * TILE > 256 ? 256 : TILE * TILE;
@@ -40,6 +44,8 @@ k_render_fwd(FwdArgs a) {
   int u[PPT], v[PPT], last[PPT];
   float T[PPT], C0[PPT], C1[PPT], C2[PPT];
   bool done[PPT];
+  unsigned n_exam = 0, n_inbox = 0, n_contrib = 0;
+  unsigned ib[PPT], ib_last[PPT];
 #pragma unroll
   for (int p = 0; p < PPT; ++p) {
     const int l = tid + p * NT;
@@ -49,6 +55,7 @@ k_render_fwd(FwdArgs a) {
     T[p] = 1.f;
     C0[p] = C1[p] = C2[p] = 0.f;
     last[p] = 0;
+    ib[p] = ib_last[p] = 0;
   }
   const Record* rv = r.rec + (size_t)k * r.cap;
   for (long long b0 = s; b0 < e; b0 += BATCH) {
@@ -68,7 +75,9 @@ k_render_fwd(FwdArgs a) {
       const Entry& E = ent[j];
 #pragma unroll
       for (int p = 0; p < PPT; ++p) {
+        if (COUNT && !done[p]) ++n_exam;
         if (done[p] || !in_box(E.box, u[p], v[p])) continue;
+        if (COUNT) { ++n_inbox; ++ib[p]; }
         float dx, dy, G, e2, oG;
         const float al = eval_alpha(E, (float)u[p], (float)v[p], r.alpha_max,
                                     dx, dy, G, e2, oG);
@@ -84,8 +93,21 @@ k_render_fwd(FwdArgs a) {
         C2[p] = fmaf(E.c.x, w, C2[p]);
         T[p] = Tn;
         last[p] = base + j + 1;
+        if (COUNT) { ++n_contrib; ib_last[p] = ib[p]; }
       }
     }
+  }
+  if (COUNT) {
+    unsigned long long c[4] = {n_exam, n_inbox, n_contrib, 0};
+#pragma unroll
+    for (int p = 0; p < PPT; ++p) c[3] += ib_last[p];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      unsigned long long x = c[q];
+      for (int off = 32; off > 0; off >>= 1) x += __shfl_down(x, off, 64);
+      if ((tid & 63) == 0 && x) atomicAdd(&a.counts[q], x);
+    }
+    return;
   }
   const size_t HW = (size_t)r.H * r.W;
 #pragma unroll
@@ -100,18 +122,28 @@ k_render_fwd(FwdArgs a) {
   }
 }
 
-template <int TILE, int BATCH>
+template <int TILE, int BATCH, bool COUNT>
 void launch_t(const FwdArgs& a, int blocks, hipStream_t st) {
   constexpr int NT = TILE * TILE > 256 ? 256 : TILE * TILE;
-  hipLaunchKernelGGL((k_render_fwd<TILE, BATCH>), dim3(blocks), dim3(NT), 0,
-                     st, a);
+  hipLaunchKernelGGL((k_render_fwd<TILE, BATCH, COUNT>), dim3(blocks), dim3(NT),
+                     0, st, a);
 }
 
-template <int TILE>
+template <int TILE, bool COUNT>
 void launch_b(const FwdArgs& a, int batch, int blocks, hipStream_t st) {
-  if (batch == 128) launch_t<TILE, 128>(a, blocks, st);
-  else if (batch == 256) launch_t<TILE, 256>(a, blocks, st);
-  else launch_t<TILE, 512>(a, blocks, st);
+  if (batch == 128) launch_t<TILE, 128, COUNT>(a, blocks, st);
+  else if (batch == 256) launch_t<TILE, 256, COUNT>(a, blocks, st);
+  else launch_t<TILE, 512, COUNT>(a, blocks, st);
+}
+
+template <bool COUNT>
+void launch_tile(const FwdArgs& a, int tile, int batch, int blocks,
+                 hipStream_t st) {
+  switch (tile) {
+    case 8: launch_b<8, COUNT>(a, batch, blocks, st); break;
+    case 16: launch_b<16, COUNT>(a, batch, blocks, st); break;
+    default: launch_b<32, COUNT>(a, batch, blocks, st); break;
+  }
 }
 
 }  // namespace
@@ -132,14 +164,21 @@ hipError_t launch_render_fwd(gs_workspace* ws, const gs_settings* s,
                              hipStream_t st) {
   FwdArgs a;
   a.r = make_raster_args(ws, s);
-  a.rgb = rgb; a.T = T; a.nlast = nlast;
+  a.rgb = rgb; a.T = T; a.nlast = nlast; a.counts = nullptr;
   const int blocks = ws->geo.n_views * ws->tiles_x * ws->tiles_y;
   if (blocks <= 0) return hipSuccess;
-  switch (ws->geo.tile) {
-    case 8: launch_b<8>(a, s->lds_batch, blocks, st); break;
-    case 16: launch_b<16>(a, s->lds_batch, blocks, st); break;
-    default: launch_b<32>(a, s->lds_batch, blocks, st); break;
-  }
+  launch_tile<false>(a, ws->geo.tile, s->lds_batch, blocks, st);
+  return hipGetLastError();
+}
+
+hipError_t launch_count_pairs(gs_workspace* ws, const gs_settings* s,
+                              unsigned long long* counts, hipStream_t st) {
+  FwdArgs a;
+  a.r = make_raster_args(ws, s);
+  a.rgb = nullptr; a.T = nullptr; a.nlast = nullptr; a.counts = counts;
+  const int blocks = ws->geo.n_views * ws->tiles_x * ws->tiles_y;
+  if (blocks <= 0) return hipSuccess;
+  launch_tile<true>(a, ws->geo.tile, s->lds_batch, blocks, st);
   return hipGetLastError();
 }
 

@@ -224,8 +224,25 @@ def render_fwd(ws, params, settings, out_rgb, out_T, out_nlast, stream=None):
            _ptr(out_nlast), _stream(stream))
 
 
+def count_pairs(ws, params, settings, counts_dev, stream=None):
+    """Adds (examined, in-box, contributing, revisited) pair counts of the
+    forward walk to counts_dev (int64[4] device tensor)."""
+    if counts_dev.dtype != torch.int64 or counts_dev.numel() < 4:
+        raise ValueError("counts_dev must be an int64 tensor of 4 elements")
+    L.call("gs_count_pairs", ws.handle, C.byref(params.struct()),
+           C.byref(settings.struct()), _ptr(counts_dev), _stream(stream))
+
+
 def render_bwd(ws, params, cams_dev, settings, dL_drgb, T_final, n_last, grad,
                stream=None):
+    """The whole backward: gs_render_bwd (pixel pass) then gs_project_bwd."""
+    render_bwd_pixels(ws, params, settings, dL_drgb, T_final, n_last, grad,
+                      stream)
+    project_bwd(ws, params, cams_dev, grad, stream)
+
+
+def render_bwd_pixels(ws, params, settings, dL_drgb, T_final, n_last, grad,
+                      stream=None):
     V, H, W = ws.geo.n_views, ws.geo.height, ws.geo.width
     for t, nm, cnt in ((dL_drgb, "dL_drgb", V * 3 * H * W),
                        (T_final, "T_final", V * H * W),
@@ -234,8 +251,13 @@ def render_bwd(ws, params, cams_dev, settings, dL_drgb, T_final, n_last, grad,
         if t.numel() != cnt:
             raise ValueError(f"{nm} size does not match the workspace geometry")
     L.call("gs_render_bwd", ws.handle, C.byref(params.struct()),
-           _ptr(cams_dev), C.byref(settings.struct()), _ptr(dL_drgb),
-           _ptr(T_final), _ptr(n_last), C.byref(grad.struct()), _stream(stream))
+           C.byref(settings.struct()), _ptr(dL_drgb), _ptr(T_final),
+           _ptr(n_last), C.byref(grad.struct()), _stream(stream))
+
+
+def project_bwd(ws, params, cams_dev, grad, stream=None):
+    L.call("gs_project_bwd", ws.handle, C.byref(params.struct()),
+           _ptr(cams_dev), C.byref(grad.struct()), _stream(stream))
 
 
 def loss_l1(rgb, target, lam, dL_drgb, loss_dev, sqerr_dev=None, stream=None):
@@ -326,6 +348,13 @@ class Rasterizer:
         render_fwd(self.ws, params, self.settings, self.rgb, self.T,
                    self.nlast, stream)
         return self.rgb, self.T, self.nlast
+
+    def count_pairs(self, params, stream=None):
+        """Work counters of the current sorted lists (run forward first)."""
+        c = torch.zeros(4, dtype=torch.int64, device=self.rgb.device)
+        count_pairs(self.ws, params, self.settings, c, stream)
+        h = c.cpu().tolist()
+        return dict(examined=h[0], inbox=h[1], contributing=h[2], revisit=h[3])
 
     def backward(self, params, dL_drgb, grad, stream=None):
         render_bwd(self.ws, params, self.cams_dev, self.settings,

@@ -58,8 +58,13 @@ def test_calls_reject_null_workspace_without_launching():
     assert lib.gs_sort_tile_keys(None, C.byref(s), None) == L.GS_E_INVALID
     assert lib.gs_render_fwd(None, C.byref(p), C.byref(s), None, None, None,
                              None) == L.GS_E_INVALID
-    assert lib.gs_render_bwd(None, C.byref(p), None, C.byref(s), None, None,
-                             None, C.byref(p), None) == L.GS_E_INVALID
+    assert lib.gs_render_bwd(None, C.byref(p), C.byref(s), None, None, None,
+                             C.byref(p), None) == L.GS_E_INVALID
+    assert lib.gs_project_bwd(None, C.byref(p), None, C.byref(p),
+                              None) == L.GS_E_INVALID
+    c = (C.c_uint64 * 4)()
+    assert lib.gs_count_pairs(None, C.byref(p), C.byref(s), c,
+                              None) == L.GS_E_INVALID
     assert lib.gs_read_status(None, None, None, None, 0) == L.GS_E_INVALID
 
 
