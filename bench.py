@@ -1,0 +1,238 @@
+#!/usr/bin/env python3
+"""Mapping-iteration benchmark of the differentiable tile rasterizer.
+
+One step is one mapping iteration over a keyframe window: projection and
+binning, per-tile sort, forward render, L1 photometric + planar-regulariser
+gradients, backward pixel pass, projection backward and the Adam update, for
+all views of the window.  Inputs are synthetic (a room-shaped scene standing
+in for the paper's indoor sequences) and resident in HBM before timing.
+
+Prints one JSON line.  Extra fields: Mpix/s, per-kernel milliseconds, the
+roofline of the dominant kernel (credited FP32 VALU lane-operations from exact
+pair counts, against 256 CUs x 64 lanes x 2.4 GHz), and the CPU oracle timed
+on a bounded sample of the same workload.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+METRIC = ("mapping iters/s (fwd+bwd, 10-KF window, 1200×680, 300k "
+          "Gaussians) + Mpix/s")
+PEAK_LANE_OPS = 256 * 64 * 2.4e9   # non-packed FP32 VALU lane-ops per second
+# Credited FP32 VALU lane-operations per pair (what the method must compute):
+FWD_OPS = dict(examined=2, inbox=12, contributing=7)
+BWD_OPS = dict(revisit=14, contributing=45)
+LR = (1.6e-4, 5e-3, 1e-3, 5e-2, 2.5e-3)   # mean, log_scale, quat, opacity, rgb
+LAMBDA_COLOR, LAMBDA_REG, REG_FLOOR = 1.0, 1.0, 0.01
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def workload(name):
+    import synth
+    if name == "window":
+        return synth.config2(0, 10, "1200x680")
+    if name == "window640":
+        return synth.config2(0, 10, "640x480")
+    if name == "single":
+        return synth.config1()
+    if name == "small":
+        return synth.config0()
+    raise ValueError(name)
+
+
+def cpu_baseline(w, threads):
+    """The CPU oracle, as it stands, on the first four views of the workload
+    (every stage of the iteration for those views), scaled to window
+    iterations/s."""
+    import numpy as np
+    import oracle
+    views = 4
+    cam = list(w.cameras[:views])
+    W, H = cam[0].width, cam[0].height
+    t0 = time.perf_counter()
+    p64 = oracle.params64(w.gaussians)
+    proj = oracle.project(p64, cam, 16, publish=True, nthreads=threads)
+    bins = oracle.bin_sort(proj, 16, W, H, emit=False)
+    fwd = oracle.forward(proj, bins, p64["rgb"], W, H, nthreads=threads)
+    _, dimg = oracle.l1(fwd["img"], w.targets[:views], LAMBDA_COLOR)
+    b = oracle.backward(proj, bins, p64["rgb"], W, H, dimg, nthreads=threads)
+    g = oracle.project_bwd(p64, cam, b, nthreads=threads)
+    _, greg = oracle.planar_reg(p64["log_scale"], LAMBDA_REG, REG_FLOOR)
+    g["log_scale"] = g["log_scale"] + greg
+    for k, lr in zip(("mean", "log_scale", "quat", "opacity_logit", "rgb"), LR):
+        z = np.zeros_like(p64[k])
+        oracle.adam(p64[k], g[k], z, z, lr, 1)
+    dt = time.perf_counter() - t0
+    V = len(w.cameras)
+    return {"value": views / (dt * V), "unit": "iterations/s",
+            "cores": threads, "kind": "oracle",
+            "sample": f"{views} of {V} views, every stage of the iteration, "
+                      f"FP64, {threads} threads, {dt:.2f} s; scaled "
+                      f"x{V / views:g}"}
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--workload", default="window",
+                    choices=["window", "window640", "single", "small"])
+    ap.add_argument("--tile", type=int, default=16)
+    ap.add_argument("--batch", type=int, default=256)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-threads", type=int, default=0)
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py measures one GPU only: this build has no multi-GPU "
+              "path (the window would shard by views with one gradient "
+              "all-reduce; not built). Run with --gpus 1.", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+    from paper_2504_02437_amd import raster as R
+
+    dev = "cuda"
+    log("bench: building workload", args.workload)
+    w = workload(args.workload)
+    V = len(w.cameras)
+    W, H = w.cameras[0].width, w.cameras[0].height
+    N = w.gaussians.n
+    S = R.Settings(tile=args.tile, lds_batch=args.batch)
+    params = R.ParamBuffer.from_gaussians(w.gaussians, device=dev)
+    grad = params.zeros_like()
+    m = params.zeros_like()
+    v = params.zeros_like()
+    rast = R.Rasterizer(w.cameras, params.capacity, S, device=dev)
+    ws, cams_dev = rast.ws, rast.cams_dev
+    rgb, T, nlast = rast.rgb, rast.T, rast.nlast
+    target = torch.from_numpy(w.targets).to(dev)
+    dL = torch.empty_like(rgb)
+    loss = torch.zeros(1, dtype=torch.float64, device=dev)
+    ev = {k: [] for k in ("fwd0", "fwd1", "bwd0", "bwd1", "pb0", "pb1",
+                          "sort0", "sort1", "proj0", "proj1")}
+
+    def mark(name, timed):
+        if timed:
+            e = torch.cuda.Event(enable_timing=True)
+            e.record()
+            ev[name].append(e)
+
+    def step(it, timed):
+        grad.data.zero_()
+        loss.zero_()
+        mark("proj0", timed)
+        R.project_and_bin(ws, params, cams_dev, S)
+        mark("proj1", timed)
+        mark("sort0", timed)
+        R.sort_tile_keys(ws, S)
+        mark("sort1", timed)
+        mark("fwd0", timed)
+        R.render_fwd(ws, params, S, rgb, T, nlast)
+        mark("fwd1", timed)
+        R.loss_l1(rgb, target, LAMBDA_COLOR, dL, loss)
+        R.planar_reg(params, LAMBDA_REG, REG_FLOOR, grad, loss)
+        mark("bwd0", timed)
+        R.render_bwd_pixels(ws, params, S, dL, T, nlast, grad)
+        mark("bwd1", timed)
+        mark("pb0", timed)
+        R.project_bwd(ws, params, cams_dev, grad)
+        mark("pb1", timed)
+        R.adam(params, grad, m, v, LR, 0.9, 0.999, 1e-15, it)
+
+    log("bench: warmup", args.warmup)
+    it = 1
+    for _ in range(args.warmup):
+        step(it, False)
+        it += 1
+    torch.cuda.synchronize()
+    flags, n_keys = rast.status()
+    if flags:
+        raise SystemExit(f"device status {flags}: key capacity exceeded")
+    counts0 = rast.count_pairs(params)
+    log("bench: keys", n_keys, "counts", counts0)
+
+    torch.cuda.synchronize()
+    t_start = torch.cuda.Event(enable_timing=True)
+    t_end = torch.cuda.Event(enable_timing=True)
+    t0 = time.perf_counter()
+    t_start.record()
+    for k in range(args.steps):
+        step(it, True)
+        it += 1
+        if (k + 1) % max(1, args.steps // 4) == 0:
+            log(f"bench: step {k + 1}/{args.steps}")
+    t_end.record()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    ms = t_start.elapsed_time(t_end) / args.steps
+    _, n_keys_end = rast.status()
+    counts1 = rast.count_pairs(params)
+
+    def avg(a, b):
+        return float(np.mean([x.elapsed_time(y) for x, y in zip(ev[a], ev[b])]))
+
+    kern = {"project_and_bin": avg("proj0", "proj1"),
+            "sort_tile_keys": avg("sort0", "sort1"),
+            "render_fwd": avg("fwd0", "fwd1"),
+            "render_bwd": avg("bwd0", "bwd1"),
+            "project_bwd": avg("pb0", "pb1")}
+    cnt = {k: 0.5 * (counts0[k] + counts1[k]) for k in counts0}
+    fwd_ops = sum(FWD_OPS[k] * cnt[k] for k in FWD_OPS)
+    bwd_ops = sum(BWD_OPS[k] * cnt[k] for k in BWD_OPS)
+    if kern["render_bwd"] >= kern["render_fwd"]:
+        dom, ops, t = "render_bwd", bwd_ops, kern["render_bwd"]
+    else:
+        dom, ops, t = "render_fwd", fwd_ops, kern["render_fwd"]
+    achieved = ops / (t * 1e-3) / 1e12
+    peak = PEAK_LANE_OPS / 1e12
+    iters = 1000.0 / ms
+    out = {
+        "metric": METRIC,
+        "value": iters,
+        "unit": "iterations/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": w.name, "views": V, "width": W, "height": H,
+                   "gaussians": N, "tile": S.tile, "lds_batch": S.lds_batch,
+                   "launch": "eager", "adam_in_step": True},
+        "mpix_per_s": V * W * H * iters / 1e6,
+        "keys_per_iter": int(0.5 * (n_keys + n_keys_end)),
+        "kernels_ms": kern,
+        "pairs": cnt,
+        "roofline": {"bound": "alu", "kernel": dom, "achieved": achieved,
+                     "peak": peak, "unit": "Tlane-op/s",
+                     "frac": achieved / peak, "traffic": None,
+                     "ops_per_launch": ops,
+                     "other": {"render_fwd_frac": fwd_ops / (kern["render_fwd"] * 1e-3) / PEAK_LANE_OPS,
+                               "render_bwd_frac": bwd_ops / (kern["render_bwd"] * 1e-3) / PEAK_LANE_OPS}},
+        "wall_s": wall,
+    }
+    if not args.no_cpu_baseline:
+        threads = args.cpu_threads or min(16, os.cpu_count() or 1)
+        log("bench: CPU oracle baseline on", threads, "threads")
+        out["cpu_baseline"] = cpu_baseline(w, threads)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

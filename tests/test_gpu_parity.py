@@ -156,3 +156,21 @@ def test_config1_full_size():
     ref = oracle_backward(w, p64, proj, bins, dL, nthreads=16)
     worst = check_grads(got, ref, w.gaussians.n)
     print("config1 worst grad rel err", worst, flush=True)
+
+
+@pytest.mark.parametrize("tile", [8, 16, 32])
+def test_pair_counters_match_oracle(tile):
+    """gs_count_pairs walks the lists with the forward's decisions: its four
+    counters equal the oracle's exactly wherever no decision flips."""
+    w = synth.config0()
+    print("case counters", tile, flush=True)
+    p64, proj, bins, fwd = oracle_forward(w, tile)
+    params, rast = gpu_forward(w, tile)
+    got = rast.count_pairs(params)
+    ref = fwd["counters"]
+    flips = int((rast.nlast.cpu().numpy() != fwd["nlast"]).sum())
+    longest = int((bins["ranges"][:, 1] - bins["ranges"][:, 0]).max())
+    for k in ("examined", "inbox", "contributing", "revisit"):
+        assert abs(got[k] - ref[k]) <= flips * longest, (k, got[k], ref[k])
+        if flips == 0:
+            assert got[k] == ref[k], k
