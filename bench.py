@@ -89,8 +89,12 @@ def main():
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--workload", default="window",
                     choices=["window", "window640", "single", "small"])
-    ap.add_argument("--tile", type=int, default=16)
+    ap.add_argument("--tile", type=int, default=0,
+                    help="fix the launch shape (default: autotune)")
     ap.add_argument("--batch", type=int, default=256)
+    ap.add_argument("--threads", type=int, default=0)
+    ap.add_argument("--no-graph", action="store_true")
+    ap.add_argument("--no-per-view", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-threads", type=int, default=0)
     args = ap.parse_args()
@@ -102,6 +106,7 @@ def main():
 
     import numpy as np
     import torch
+    from paper_2504_02437_amd import autotune as AT
     from paper_2504_02437_amd import raster as R
 
     dev = "cuda"
@@ -110,8 +115,18 @@ def main():
     V = len(w.cameras)
     W, H = w.cameras[0].width, w.cameras[0].height
     N = w.gaussians.n
-    S = R.Settings(tile=args.tile, lds_batch=args.batch)
     params = R.ParamBuffer.from_gaussians(w.gaussians, device=dev)
+    if args.tile:
+        S = R.Settings(tile=args.tile, lds_batch=args.batch,
+                       block_threads=args.threads)
+        tuned = None
+    else:
+        S, times = AT.autotune(params, w.cameras, reps=2, use_cache=False,
+                               cache_path=None, log=log)
+        tuned = {f"{t}/{b}/{n}": round(ms, 3) for (t, b, n), ms in
+                 sorted(times.items(), key=lambda kv: kv[1])}
+    log("bench: launch shape tile", S.tile, "batch", S.lds_batch, "threads",
+        S.block_threads)
     grad = params.zeros_like()
     m = params.zeros_like()
     v = params.zeros_like()
@@ -121,74 +136,121 @@ def main():
     target = torch.from_numpy(w.targets).to(dev)
     dL = torch.empty_like(rgb)
     loss = torch.zeros(1, dtype=torch.float64, device=dev)
-    ev = {k: [] for k in ("fwd0", "fwd1", "bwd0", "bwd1", "pb0", "pb1",
-                          "sort0", "sort1", "proj0", "proj1")}
+    step_dev = torch.ones(1, dtype=torch.int32, device=dev)
+    names = ("project_and_bin", "sort_tile_keys", "render_fwd", "render_bwd",
+             "project_bwd")
+    ev = {k: [] for k in names}
 
-    def mark(name, timed):
-        if timed:
-            e = torch.cuda.Event(enable_timing=True)
-            e.record()
-            ev[name].append(e)
+    def timed(name, fn, on):
+        if not on:
+            fn()
+            return
+        a, b = (torch.cuda.Event(enable_timing=True) for _ in range(2))
+        a.record()
+        fn()
+        b.record()
+        ev[name].append((a, b))
 
-    def step(it, timed):
+    def step(on=False):
         grad.data.zero_()
         loss.zero_()
-        mark("proj0", timed)
-        R.project_and_bin(ws, params, cams_dev, S)
-        mark("proj1", timed)
-        mark("sort0", timed)
-        R.sort_tile_keys(ws, S)
-        mark("sort1", timed)
-        mark("fwd0", timed)
-        R.render_fwd(ws, params, S, rgb, T, nlast)
-        mark("fwd1", timed)
+        timed("project_and_bin",
+              lambda: R.project_and_bin(ws, params, cams_dev, S), on)
+        timed("sort_tile_keys", lambda: R.sort_tile_keys(ws, S), on)
+        timed("render_fwd",
+              lambda: R.render_fwd(ws, params, S, rgb, T, nlast), on)
         R.loss_l1(rgb, target, LAMBDA_COLOR, dL, loss)
         R.planar_reg(params, LAMBDA_REG, REG_FLOOR, grad, loss)
-        mark("bwd0", timed)
-        R.render_bwd_pixels(ws, params, S, dL, T, nlast, grad)
-        mark("bwd1", timed)
-        mark("pb0", timed)
-        R.project_bwd(ws, params, cams_dev, grad)
-        mark("pb1", timed)
-        R.adam(params, grad, m, v, LR, 0.9, 0.999, 1e-15, it)
+        timed("render_bwd",
+              lambda: R.render_bwd_pixels(ws, params, S, dL, T, nlast, grad), on)
+        timed("project_bwd",
+              lambda: R.project_bwd(ws, params, cams_dev, grad), on)
+        R.adam(params, grad, m, v, LR, 0.9, 0.999, 1e-15, step_dev)
+        step_dev.add_(1)
+
+    def run(k, on):
+        a, b = (torch.cuda.Event(enable_timing=True) for _ in range(2))
+        a.record()
+        for i in range(k):
+            step(on)
+            if k >= 4 and (i + 1) % max(1, k // 4) == 0:
+                log(f"bench: eager step {i + 1}/{k}")
+        b.record()
+        torch.cuda.synchronize()
+        return a.elapsed_time(b) / k
 
     log("bench: warmup", args.warmup)
-    it = 1
-    for _ in range(args.warmup):
-        step(it, False)
-        it += 1
-    torch.cuda.synchronize()
+    run(args.warmup, False)
     flags, n_keys = rast.status()
     if flags:
         raise SystemExit(f"device status {flags}: key capacity exceeded")
     counts0 = rast.count_pairs(params)
     log("bench: keys", n_keys, "counts", counts0)
-
-    torch.cuda.synchronize()
-    t_start = torch.cuda.Event(enable_timing=True)
-    t_end = torch.cuda.Event(enable_timing=True)
     t0 = time.perf_counter()
-    t_start.record()
-    for k in range(args.steps):
-        step(it, True)
-        it += 1
-        if (k + 1) % max(1, args.steps // 4) == 0:
-            log(f"bench: step {k + 1}/{args.steps}")
-    t_end.record()
-    torch.cuda.synchronize()
+    ms_eager = run(args.steps, True)
     wall = time.perf_counter() - t0
-    ms = t_start.elapsed_time(t_end) / args.steps
-    _, n_keys_end = rast.status()
     counts1 = rast.count_pairs(params)
+    kern = {k: float(np.mean([a.elapsed_time(b) for a, b in ev[k]]))
+            for k in names}
 
-    def avg(a, b):
-        return float(np.mean([x.elapsed_time(y) for x, y in zip(ev[a], ev[b])]))
+    ms_graph = None
+    if not args.no_graph:
+        log("bench: capturing one iteration in a HIP graph")
+        g = torch.cuda.CUDAGraph()
+        side = torch.cuda.Stream()
+        side.wait_stream(torch.cuda.current_stream())
+        with torch.cuda.stream(side):
+            step()
+        torch.cuda.current_stream().wait_stream(side)
+        with torch.cuda.graph(g):
+            step()
+        for _ in range(args.warmup):
+            g.replay()
+        torch.cuda.synchronize()
+        a, b = (torch.cuda.Event(enable_timing=True) for _ in range(2))
+        a.record()
+        for i in range(args.steps):
+            g.replay()
+        b.record()
+        torch.cuda.synchronize()
+        ms_graph = a.elapsed_time(b) / args.steps
+        log(f"bench: graph {ms_graph:.3f} ms/iteration, eager {ms_eager:.3f}")
 
-    kern = {"project_and_bin": avg("proj0", "proj1"),
-            "sort_tile_keys": avg("sort0", "sort1"),
-            "render_fwd": avg("fwd0", "fwd1"),
-            "render_bwd": avg("bwd0", "bwd1"),
-            "project_bwd": avg("pb0", "pb1")}
+    per_view = None
+    if not args.no_per_view and V > 1:
+        log("bench: per-keyframe plain path")
+        singles = [R.Rasterizer([c], params.capacity, S, device=dev)
+                   for c in w.cameras]
+        tgt1 = [target[i:i + 1] for i in range(V)]
+        dL1 = torch.empty(1, 3, H, W, device=dev)
+
+        def plain_step():
+            grad.data.zero_()
+            loss.zero_()
+            for i, r1 in enumerate(singles):
+                r1.forward(params)
+                R.loss_l1(r1.rgb, tgt1[i], LAMBDA_COLOR, dL1, loss)
+                r1.backward(params, dL1, grad)
+            R.planar_reg(params, LAMBDA_REG, REG_FLOOR, grad, loss)
+            R.adam(params, grad, m, v, LR, 0.9, 0.999, 1e-15, step_dev)
+            step_dev.add_(1)
+
+        for _ in range(2):
+            plain_step()
+        torch.cuda.synchronize()
+        a, b = (torch.cuda.Event(enable_timing=True) for _ in range(2))
+        k = max(3, args.steps // 2)
+        a.record()
+        for _ in range(k):
+            plain_step()
+        b.record()
+        torch.cuda.synchronize()
+        ms_plain = a.elapsed_time(b) / k
+        per_view = {"iterations_per_s": 1000.0 / ms_plain,
+                    "ms_per_iteration": ms_plain,
+                    "batched_speedup": ms_plain / (ms_graph or ms_eager)}
+        del singles
+
     cnt = {k: 0.5 * (counts0[k] + counts1[k]) for k in counts0}
     fwd_ops = sum(FWD_OPS[k] * cnt[k] for k in FWD_OPS)
     bwd_ops = sum(BWD_OPS[k] * cnt[k] for k in BWD_OPS)
@@ -198,6 +260,7 @@ def main():
         dom, ops, t = "render_fwd", fwd_ops, kern["render_fwd"]
     achieved = ops / (t * 1e-3) / 1e12
     peak = PEAK_LANE_OPS / 1e12
+    ms = ms_graph if ms_graph is not None else ms_eager
     iters = 1000.0 / ms
     out = {
         "metric": METRIC,
@@ -214,17 +277,22 @@ def main():
         "data": "synthetic",
         "config": {"workload": w.name, "views": V, "width": W, "height": H,
                    "gaussians": N, "tile": S.tile, "lds_batch": S.lds_batch,
-                   "launch": "eager", "adam_in_step": True},
+                   "block_threads": S.block_threads or (256 if S.tile == 32 else 64),
+                   "launch": "hip_graph" if ms_graph is not None else "eager",
+                   "adam_in_step": True},
         "mpix_per_s": V * W * H * iters / 1e6,
-        "keys_per_iter": int(0.5 * (n_keys + n_keys_end)),
+        "ms_per_step_eager": ms_eager,
+        "keys_per_iter": int(n_keys),
         "kernels_ms": kern,
         "pairs": cnt,
         "roofline": {"bound": "alu", "kernel": dom, "achieved": achieved,
                      "peak": peak, "unit": "Tlane-op/s",
                      "frac": achieved / peak, "traffic": None,
                      "ops_per_launch": ops,
-                     "other": {"render_fwd_frac": fwd_ops / (kern["render_fwd"] * 1e-3) / PEAK_LANE_OPS,
-                               "render_bwd_frac": bwd_ops / (kern["render_bwd"] * 1e-3) / PEAK_LANE_OPS}},
+                     "render_fwd_frac": fwd_ops / (kern["render_fwd"] * 1e-3) / PEAK_LANE_OPS,
+                     "render_bwd_frac": bwd_ops / (kern["render_bwd"] * 1e-3) / PEAK_LANE_OPS},
+        "per_keyframe_plain": per_view,
+        "autotune_ms": tuned,
         "wall_s": wall,
     }
     if not args.no_cpu_baseline:

@@ -85,6 +85,10 @@ typedef struct gs_camera {
 /* Rasterizer settings, passed by host pointer and copied at each call.
  *   tile        screen tile edge in pixels: 8, 16 or 32
  *   lds_batch   Gaussians staged in LDS per batch: 128, 256 or 512
+ *   block_threads  threads per tile workgroup (0 = default); each thread
+ *               owns a vertical strip of tile*tile/block_threads pixels:
+ *               tile 8: 64; tile 16: 64, 128 or 256 (default 64);
+ *               tile 32: 128 or 256 (default 256)
  *   bg          background colour added with weight T_final
  *   alpha_min   entries with alpha below this are skipped (1/255)
  *   T_min       a pixel stops before the entry that would take its
@@ -99,7 +103,7 @@ typedef struct gs_settings {
   float T_min;
   float alpha_max;
   int32_t flags;
-  int32_t pad_;
+  int32_t block_threads;
 } gs_settings;
 
 /* Fixed sizes of one rasterization problem; all views share width, height
@@ -248,10 +252,13 @@ GS_API int gs_planar_reg(const gs_params* params, float lambda, float floor_,
 /* Adam step (the optimiser is not fixed by the paper) over the live entries
  * of the 14 parameter rows.  lr[5] = learning rates of mean, log_scale,
  * quat, opacity_logit, rgb.  m and v are moment arrays of the params layout.
- * step >= 1 is the bias-correction step count. */
+ * The bias-correction step count is *step_dev (device int32) when step_dev
+ * is not NULL - so a captured graph can advance it on the device - and
+ * `step` otherwise; it must be >= 1. */
 GS_API int gs_adam(gs_params* params, const gs_params* grad, gs_params* m,
-            gs_params* v, const float* lr, float beta1, float beta2,
-            float eps, int32_t step, void* stream);
+                   gs_params* v, const float* lr, float beta1, float beta2,
+                   float eps, int32_t step, const int32_t* step_dev,
+                   void* stream);
 
 /* Keyframe insertion (Eq. 6 with an accumulated-alpha mask).  Candidates are
  * the 3x3 pixel patch around each of the n_pts centres pts_uvd [n][3] =

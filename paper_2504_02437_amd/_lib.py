@@ -44,7 +44,7 @@ class gs_settings(C.Structure):
     _fields_ = [("tile", C.c_int32), ("lds_batch", C.c_int32),
                 ("bg", C.c_float * 3), ("alpha_min", C.c_float),
                 ("T_min", C.c_float), ("alpha_max", C.c_float),
-                ("flags", C.c_int32), ("pad_", C.c_int32)]
+                ("flags", C.c_int32), ("block_threads", C.c_int32)]
 
 
 class gs_geometry(C.Structure):
@@ -87,7 +87,7 @@ _SIGS = {
                                 _P(gs_params), _vp, _vp]),
     "gs_adam": (C.c_int, [_P(gs_params), _P(gs_params), _P(gs_params),
                           _P(gs_params), _vp, C.c_float, C.c_float, C.c_float,
-                          C.c_int32, _vp]),
+                          C.c_int32, _vp, _vp]),
     "gs_insert_gaussians": (C.c_int, [_P(gs_params), _P(gs_params),
                                       _P(gs_params), _vp, C.c_int32, C.c_int32,
                                       _vp, _vp, _vp, C.c_int32, C.c_float,

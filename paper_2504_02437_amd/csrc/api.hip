@@ -35,6 +35,14 @@ int validate_settings(const gs_settings* s) {
     set_error("lds_batch must be 128, 256 or 512 (got %d)", s->lds_batch);
     return GS_E_INVALID;
   }
+  const int bt = s->block_threads;
+  const bool bt_ok = bt == 0 || (s->tile == 8 && bt == 64) ||
+                     (s->tile == 16 && (bt == 64 || bt == 128 || bt == 256)) ||
+                     (s->tile == 32 && (bt == 128 || bt == 256));
+  if (!bt_ok) {
+    set_error("block_threads %d not supported for tile %d", bt, s->tile);
+    return GS_E_INVALID;
+  }
   if (!(s->alpha_min > 0.f) || !(s->alpha_max <= 1.f) ||
       !(s->alpha_min < s->alpha_max) || !(s->T_min > 0.f) ||
       !(s->alpha_max < 1.f)) {
@@ -316,21 +324,21 @@ int gs_planar_reg(const gs_params* params, float lambda, float floor_,
 
 int gs_adam(gs_params* params, const gs_params* grad, gs_params* m,
             gs_params* v, const float* lr, float beta1, float beta2,
-            float eps, int32_t step, void* stream) {
+            float eps, int32_t step, const int32_t* step_dev, void* stream) {
   g_err[0] = 0;
   if (int rc = validate_params(params, "params")) return rc;
   if (int rc = validate_params(grad, "grad")) return rc;
   if (int rc = validate_params(m, "m")) return rc;
   if (int rc = validate_params(v, "v")) return rc;
   if (!lr || !params->n_dev) { set_error("lr or n_dev is NULL"); return GS_E_INVALID; }
-  if (step < 1) { set_error("step must be >= 1"); return GS_E_INVALID; }
+  if (!step_dev && step < 1) { set_error("step must be >= 1"); return GS_E_INVALID; }
   if (grad->capacity != params->capacity || m->capacity != params->capacity ||
       v->capacity != params->capacity) {
     set_error("capacities differ");
     return GS_E_CAPACITY;
   }
   return finish(launch_adam(params, grad, m, v, lr, beta1, beta2, eps, step,
-                            (hipStream_t)stream), "adam");
+                            step_dev, (hipStream_t)stream), "adam");
 }
 
 int gs_insert_gaussians(gs_params* params, gs_params* adam_m, gs_params* adam_v,

@@ -85,7 +85,8 @@ hipError_t launch_planar_reg(const gs_params* p, float lambda, float floor_,
                              gs_params* grad, double* loss, hipStream_t st);
 hipError_t launch_adam(gs_params* p, const gs_params* g, gs_params* m,
                        gs_params* v, const float* lr, float b1, float b2,
-                       float eps, int step, hipStream_t st);
+                       float eps, int step, const int32_t* step_dev,
+                       hipStream_t st);
 hipError_t launch_insert(gs_params* p, gs_params* m, gs_params* v,
                          const gs_camera* cam, int W, int H,
                          const float* kf_rgb, const float* kf_T,

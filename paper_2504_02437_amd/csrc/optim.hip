@@ -30,6 +30,10 @@ __device__ inline T block_sum(T x, T* sh) {
 }
 
 // L1 photometric term: per view lambda * mean |rgb - target| over 3HW.
+// A few hundred blocks per view stream the images with 16-byte loads (the
+// per-view image starts 16-byte aligned when 3HW is a multiple of 4; other
+// sizes take the scalar path), so only a few hundred FP64 atomics land on
+// the loss accumulator.
 __global__ __launch_bounds__(256) void k_loss_l1(const float* rgb,
                                                  const float* tgt, size_t per,
                                                  float scale, float* dL,
@@ -40,15 +44,33 @@ __global__ __launch_bounds__(256) void k_loss_l1(const float* rgb,
   const float* x = rgb + (size_t)k * per;
   const float* y = tgt + (size_t)k * per;
   float* d = dL + (size_t)k * per;
-  double sa = 0.0, sq = 0.0;
-  for (size_t i = blockIdx.x * 256 + threadIdx.x; i < per;
-       i += (size_t)gridDim.x * 256) {
-    const float r = x[i] - y[i];
-    d[i] = r > 0.f ? scale : (r < 0.f ? -scale : 0.f);
-    sa += fabs((double)x[i] - (double)y[i]);
-    sq += ((double)x[i] - (double)y[i]) * ((double)x[i] - (double)y[i]);
+  float sa = 0.f;
+  double sq = 0.0;
+  const size_t stride = (size_t)gridDim.x * 256;
+  const size_t first = blockIdx.x * 256 + threadIdx.x;
+  auto one = [&](float a, float b) -> float {
+    const float r = a - b;
+    sa += fabsf(r);
+    sq += (double)r * (double)r;
+    return r > 0.f ? scale : (r < 0.f ? -scale : 0.f);
+  };
+  if ((per & 3) == 0) {
+    const float4* x4 = reinterpret_cast<const float4*>(x);
+    const float4* y4 = reinterpret_cast<const float4*>(y);
+    float4* d4 = reinterpret_cast<float4*>(d);
+    for (size_t i = first; i < per / 4; i += stride) {
+      const float4 a = x4[i], b = y4[i];
+      float4 o;
+      o.x = one(a.x, b.x);
+      o.y = one(a.y, b.y);
+      o.z = one(a.z, b.z);
+      o.w = one(a.w, b.w);
+      d4[i] = o;
+    }
+  } else {
+    for (size_t i = first; i < per; i += stride) d[i] = one(x[i], y[i]);
   }
-  const double ta = block_sum(sa, sh);
+  const double ta = block_sum((double)sa, sh);
   const double tq = block_sum(sq, sh);
   if (threadIdx.x == 0) {
     atomicAdd(loss, ta * lam_inv);
@@ -87,8 +109,9 @@ struct AdamArgs {
   float* v[14];
   float lr[14];
   const int32_t* n_dev;
-  int cap;
-  float b1, b2, eps, c1, c2;
+  const int32_t* step_dev;
+  int cap, step;
+  float b1, b2, eps;
 };
 
 __global__ __launch_bounds__(256) void k_adam(AdamArgs a) {
@@ -96,12 +119,15 @@ __global__ __launch_bounds__(256) void k_adam(AdamArgs a) {
   const int row = blockIdx.y;
   const int n = min(*a.n_dev, a.cap);
   if (g >= n) return;
+  const int step = a.step_dev ? max(1, *a.step_dev) : a.step;
+  const float c1 = (float)(1.0 - pow((double)a.b1, (double)step));
+  const float c2 = (float)(1.0 - pow((double)a.b2, (double)step));
   const float gr = a.g[row][g];
   const float m = a.b1 * a.m[row][g] + (1.f - a.b1) * gr;
   const float v = a.b2 * a.v[row][g] + (1.f - a.b2) * gr * gr;
   a.m[row][g] = m;
   a.v[row][g] = v;
-  a.p[row][g] -= a.lr[row] * (m / a.c1) / (sqrtf(v / a.c2) + a.eps);
+  a.p[row][g] -= a.lr[row] * (m / c1) / (sqrtf(v / c2) + a.eps);
 }
 
 struct InsertArgs {
@@ -231,8 +257,8 @@ hipError_t launch_loss_l1(const float* rgb, const float* target, int V, int H,
                           double* sqerr, hipStream_t st) {
   const size_t per = (size_t)3 * H * W;
   const float scale = (float)((double)lambda / (double)per);
-  size_t bx = (per + 256 * 4 - 1) / (256 * 4);
-  if (bx > 2048) bx = 2048;
+  size_t bx = (per + 256 * 16 - 1) / (256 * 16);
+  if (bx > 160) bx = 160;
   if (bx < 1) bx = 1;
   hipLaunchKernelGGL(k_loss_l1, dim3((unsigned)bx, V), dim3(256), 0, st, rgb,
                      target, per, scale, dL, loss, sqerr,
@@ -252,7 +278,8 @@ hipError_t launch_planar_reg(const gs_params* p, float lambda, float floor_,
 
 hipError_t launch_adam(gs_params* p, const gs_params* g, gs_params* m,
                        gs_params* v, const float* lr, float b1, float b2,
-                       float eps, int step, hipStream_t st) {
+                       float eps, int step, const int32_t* step_dev,
+                       hipStream_t st) {
   AdamArgs a;
   float* tmp[14];
   rows_of(p, a.p);
@@ -264,8 +291,7 @@ hipError_t launch_adam(gs_params* p, const gs_params* g, gs_params* m,
   for (int i = 0; i < 14; ++i) a.lr[i] = lr[grp[i]];
   a.n_dev = p->n_dev; a.cap = p->capacity;
   a.b1 = b1; a.b2 = b2; a.eps = eps;
-  a.c1 = (float)(1.0 - pow((double)b1, step));
-  a.c2 = (float)(1.0 - pow((double)b2, step));
+  a.step = step; a.step_dev = step_dev;
   const int blocks = (p->capacity + 255) / 256;
   if (blocks <= 0) return hipSuccess;
   hipLaunchKernelGGL(k_adam, dim3(blocks, 14), dim3(256), 0, st, a);

@@ -1,7 +1,15 @@
-// Pieces shared by the forward and backward compositing kernels.  Both
-// kernels stage records into LDS with stage() and evaluate a (pixel, entry)
-// pair with eval_alpha(); compiled without FMA contraction, both therefore
-// take bit-identical admit / clamp / stop decisions.
+// Pieces shared by the forward and backward compositing kernels.
+//
+// Both kernels stage records into LDS with stage() and evaluate (pixel,
+// entry) pairs with lane_prep() + pixel_alpha(); compiled without FMA
+// contraction (FMAs are written explicitly), both therefore take
+// bit-identical admit / clamp / stop decisions.
+//
+// Pixel ownership: a tile of TILE x TILE pixels is served by NT threads laid
+// out as TILE columns x (NT / TILE) row groups; each thread owns a vertical
+// strip of PPT = TILE * TILE / NT consecutive pixels of one column.  The
+// pixels of a strip share their column, so the x-offset terms of the
+// exponent are formed once per (entry, thread).
 #pragma once
 
 #include "gs_internal.h"
@@ -29,19 +37,33 @@ __device__ __forceinline__ void stage(Entry& E, const Record& R) {
   E.box = make_int4(bu & 0xffff, bu >> 16, bv & 0xffff, bv >> 16);
 }
 
-__device__ __forceinline__ bool in_box(const int4& b, int u, int v) {
-  return u >= b.x && u <= b.y && v >= b.z && v <= b.w;
+// Column part of the exponent for one (entry, thread): dx and the terms that
+// depend on dx only.
+struct Lane {
+  float dx, a0, b0;
+  bool in_u;
+};
+
+__device__ __forceinline__ Lane lane_prep(const Entry& E, int u) {
+  Lane L;
+  L.in_u = u >= E.box.x && u <= E.box.y;
+  L.dx = E.a.x - (float)u;
+  L.a0 = (E.a.z * L.dx) * L.dx;   // A2 dx^2
+  L.b0 = E.a.w * L.dx;            // B2 dx
+  return L;
 }
 
-// alpha = min(alpha_max, opacity * exp2(e2)); e2 > 0 only by rounding and
-// the entry is then skipped by the caller.  Returns o * G in oG.
-__device__ __forceinline__ float eval_alpha(const Entry& E, float fu, float fv,
-                                            float alpha_max, float& dx,
-                                            float& dy, float& G, float& e2,
-                                            float& oG) {
-  dx = E.a.x - fu;
-  dy = E.a.y - fv;
-  e2 = fmaf(E.a.z * dx, dx, fmaf(E.b.x * dy, dy, (E.a.w * dx) * dy));
+__device__ __forceinline__ bool in_v(const Entry& E, int v) {
+  return v >= E.box.z && v <= E.box.w;
+}
+
+// alpha = min(alpha_max, opacity * exp2(e2)) for the pixel in row v of the
+// thread's column; e2 > 0 happens only by rounding and the caller skips it.
+__device__ __forceinline__ float pixel_alpha(const Entry& E, const Lane& L,
+                                             int v, float alpha_max, float& dy,
+                                             float& G, float& e2, float& oG) {
+  dy = E.a.y - (float)v;
+  e2 = fmaf(E.b.x * dy, dy, fmaf(L.b0, dy, L.a0));
   G = __builtin_amdgcn_exp2f(e2);
   oG = E.b.y * G;
   return fminf(alpha_max, oG);
@@ -63,6 +85,31 @@ __device__ __forceinline__ void tile_range(const RasterArgs& a, int t,
                                            long long& s, long long& e) {
   s = min((long long)a.ranges[2 * t], a.key_cap);
   e = min((long long)a.ranges[2 * t + 1], a.key_cap);
+}
+
+inline int default_threads(int tile) { return tile == 32 ? 256 : 64; }
+
+// Calls launcher.template go<TILE, BATCH, NT>() for a supported shape.
+template <typename Launcher>
+void dispatch_shape(int tile, int batch, int nt, const Launcher& l) {
+  if (nt == 0) nt = default_threads(tile);
+#define GS_BATCHES(T, N)                                  \
+  do {                                                    \
+    if (batch == 128) l.template go<T, 128, N>();         \
+    else if (batch == 256) l.template go<T, 256, N>();    \
+    else l.template go<T, 512, N>();                      \
+  } while (0)
+  if (tile == 8) {
+    GS_BATCHES(8, 64);
+  } else if (tile == 16) {
+    if (nt == 64) GS_BATCHES(16, 64);
+    else if (nt == 128) GS_BATCHES(16, 128);
+    else GS_BATCHES(16, 256);
+  } else {
+    if (nt == 128) GS_BATCHES(32, 128);
+    else GS_BATCHES(32, 256);
+  }
+#undef GS_BATCHES
 }
 
 }  // namespace gs

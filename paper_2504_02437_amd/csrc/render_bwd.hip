@@ -5,14 +5,16 @@
 // Only per-pixel state is kept from the forward (T_final and n_last); the
 // list is walked back to front from the tile's largest n_last, and each
 // admitted entry's transmittance is recovered as T_i = T_{i+1} / (1 - a_i).
-// The colour accumulated behind entry i, dotted with dL/dC, follows
+// The colour accumulated behind entry i, dotted with g = dL/dC, follows
 // S_{i-1} = a_i (c_i . g) + (1 - a_i) S_i, so
 //   dL/dc_i     = a_i T_i g
 //   dL/da_i     = T_i (c_i . g - S_i) - T_final (bg . g) / (1 - a_i)
 //   dL/dpi_i    = a_i dL/da_i                 (a = o exp(pi), unclamped)
 //   dL/do_i     = G_i dL/da_i
-// and pi's derivatives give the 2D mean and conic gradients.  The nine
-// per-entry sums are reduced across each wave with DPP, merged across waves
+// with pi = -(A dx^2 + C dy^2) / 2 - B dx dy.  A thread's pixels share dx, so
+// it accumulates only sum(dL/dpi), sum(dL/dpi dy) and sum(dL/dpi dy^2) over
+// its strip and forms the mean and conic gradients once per entry.  The nine
+// per-entry sums are reduced across the wave with DPP, merged across waves
 // in LDS, and added to global memory with one atomic per (entry, quantity).
 
 #include "raster_common.h"
@@ -52,11 +54,11 @@ __device__ __forceinline__ float lane63(float x) {
   return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(x), 63));
 }
 
-template <int TILE, int BATCH>
-__global__ __launch_bounds__(TILE * TILE > 256 ? 256 : TILE * TILE) void
-k_render_bwd(BwdArgs a) {
-  constexpr int NT = TILE * TILE > 256 ? 256 : TILE * TILE;
-  constexpr int PPT = TILE * TILE / NT;
+template <int TILE, int BATCH, int NT>
+__global__ __launch_bounds__(NT) void k_render_bwd(BwdArgs a) {
+  constexpr int GROUPS = NT / TILE;
+  constexpr int PPT = TILE / GROUPS;
+  static_assert(GROUPS * PPT == TILE, "thread layout must tile the tile");
   __shared__ Entry ent[BATCH];
   __shared__ float acc[BATCH][9];
   __shared__ uint32_t gid[BATCH];
@@ -73,18 +75,18 @@ k_render_bwd(BwdArgs a) {
   tile_range(r, t, s, e);
   const size_t HW = (size_t)r.H * r.W;
 
-  int u[PPT], v[PPT], last[PPT];
+  const int u = tx * TILE + (tid % TILE);
+  const int v0 = ty * TILE + (tid / TILE) * PPT;
+  int last[PPT];
   float T[PPT], g0[PPT], g1[PPT], g2[PPT], Tb[PPT], Sg[PPT];
   int mylast = 0;
 #pragma unroll
   for (int p = 0; p < PPT; ++p) {
-    const int l = tid + p * NT;
-    u[p] = tx * TILE + (l % TILE);
-    v[p] = ty * TILE + (l / TILE);
+    const int v = v0 + p;
     last[p] = 0;
     T[p] = 1.f; g0[p] = g1[p] = g2[p] = 0.f; Tb[p] = 0.f; Sg[p] = 0.f;
-    if (u[p] < r.W && v[p] < r.H) {
-      const size_t pix = (size_t)v[p] * r.W + u[p];
+    if (u < r.W && v < r.H) {
+      const size_t pix = (size_t)v * r.W + u;
       T[p] = a.Tfin[(size_t)k * HW + pix];
       last[p] = a.nlast[(size_t)k * HW + pix];
       g0[p] = a.dL[((size_t)k * 3 + 0) * HW + pix];
@@ -116,39 +118,47 @@ k_render_bwd(BwdArgs a) {
     for (int j = cnt - 1; j >= 0; --j) {
       const int pos = lo + j;
       const Entry& E = ent[j];
-      float d_px = 0.f, d_py = 0.f, d_A = 0.f, d_B = 0.f, d_C = 0.f;
+      const Lane L = lane_prep(E, u);
       float d_o = 0.f, d_r = 0.f, d_g = 0.f, d_b = 0.f;
+      float S0 = 0.f, S1 = 0.f, S2 = 0.f;
       bool hit = false;
+      if (L.in_u) {
 #pragma unroll
-      for (int p = 0; p < PPT; ++p) {
-        if (pos >= last[p] || !in_box(E.box, u[p], v[p])) continue;
-        float dx, dy, G, e2, oG;
-        const float al = eval_alpha(E, (float)u[p], (float)v[p], r.alpha_max,
-                                    dx, dy, G, e2, oG);
-        if (e2 > 0.f || al < r.alpha_min) continue;
-        hit = true;
-        const float om = 1.f - al;
-        const float rom = __builtin_amdgcn_rcpf(om);
-        T[p] = T[p] * rom;                       // T_i
-        const float w = al * T[p];
-        d_r = fmaf(w, g0[p], d_r);
-        d_g = fmaf(w, g1[p], d_g);
-        d_b = fmaf(w, g2[p], d_b);
-        const float cg = fmaf(E.b.z, g0[p], fmaf(E.b.w, g1[p], E.c.x * g2[p]));
-        const float diff = cg - Sg[p];
-        const float dal = fmaf(T[p], diff, -(Tb[p] * rom));
-        Sg[p] = fmaf(al, diff, Sg[p]);
-        if (oG > r.alpha_max) continue;          // clamped: no shape gradient
-        const float dpw = dal * al;
-        d_o = fmaf(dal, G, d_o);
-        const float A = E.c.y, B = E.c.z, C = E.c.w;
-        d_px = fmaf(-dpw, fmaf(A, dx, B * dy), d_px);
-        d_py = fmaf(-dpw, fmaf(C, dy, B * dx), d_py);
-        d_A = fmaf(-0.5f * dpw, dx * dx, d_A);
-        d_B = fmaf(-dpw, dx * dy, d_B);
-        d_C = fmaf(-0.5f * dpw, dy * dy, d_C);
+        for (int p = 0; p < PPT; ++p) {
+          if (pos >= last[p] || !in_v(E, v0 + p)) continue;
+          float dy, G, e2, oG;
+          const float al =
+              pixel_alpha(E, L, v0 + p, r.alpha_max, dy, G, e2, oG);
+          if (e2 > 0.f || al < r.alpha_min) continue;
+          hit = true;
+          const float rom = __builtin_amdgcn_rcpf(1.f - al);
+          T[p] = T[p] * rom;                       // T_i
+          const float w = al * T[p];
+          d_r = fmaf(w, g0[p], d_r);
+          d_g = fmaf(w, g1[p], d_g);
+          d_b = fmaf(w, g2[p], d_b);
+          const float cg =
+              fmaf(E.b.z, g0[p], fmaf(E.b.w, g1[p], E.c.x * g2[p]));
+          const float diff = cg - Sg[p];
+          const float dal = fmaf(T[p], diff, -(Tb[p] * rom));
+          Sg[p] = fmaf(al, diff, Sg[p]);
+          if (oG > r.alpha_max) continue;          // clamped: no shape gradient
+          const float dpw = dal * al;
+          d_o = fmaf(dal, G, d_o);
+          const float tdy = dpw * dy;
+          S0 += dpw;
+          S1 += tdy;
+          S2 = fmaf(tdy, dy, S2);
+        }
       }
       if (__any(hit)) {
+        const float A = E.c.y, B = E.c.z, C = E.c.w, dx = L.dx;
+        const float dxS0 = dx * S0;
+        const float d_px = -fmaf(A, dxS0, B * S1);
+        const float d_py = -fmaf(C, S1, B * dxS0);
+        const float d_A = -0.5f * dx * dxS0;
+        const float d_B = -dx * S1;
+        const float d_C = -0.5f * S2;
         const float s0 = lane63(wave_sum(d_px));
         const float s1 = lane63(wave_sum(d_py));
         const float s2 = lane63(wave_sum(d_A));
@@ -160,9 +170,14 @@ k_render_bwd(BwdArgs a) {
         const float s8 = lane63(wave_sum(d_b));
         if (lane == 0) {
           float* ac = acc[j];
-          atomicAdd(&ac[0], s0); atomicAdd(&ac[1], s1); atomicAdd(&ac[2], s2);
-          atomicAdd(&ac[3], s3); atomicAdd(&ac[4], s4); atomicAdd(&ac[5], s5);
-          atomicAdd(&ac[6], s6); atomicAdd(&ac[7], s7); atomicAdd(&ac[8], s8);
+          if (NT == 64) {
+            ac[0] = s0; ac[1] = s1; ac[2] = s2; ac[3] = s3; ac[4] = s4;
+            ac[5] = s5; ac[6] = s6; ac[7] = s7; ac[8] = s8;
+          } else {
+            atomicAdd(&ac[0], s0); atomicAdd(&ac[1], s1); atomicAdd(&ac[2], s2);
+            atomicAdd(&ac[3], s3); atomicAdd(&ac[4], s4); atomicAdd(&ac[5], s5);
+            atomicAdd(&ac[6], s6); atomicAdd(&ac[7], s7); atomicAdd(&ac[8], s8);
+          }
         }
       }
     }
@@ -179,19 +194,16 @@ k_render_bwd(BwdArgs a) {
   }
 }
 
-template <int TILE, int BATCH>
-void launch_t(const BwdArgs& a, int blocks, hipStream_t st) {
-  constexpr int NT = TILE * TILE > 256 ? 256 : TILE * TILE;
-  hipLaunchKernelGGL((k_render_bwd<TILE, BATCH>), dim3(blocks), dim3(NT), 0,
-                     st, a);
-}
-
-template <int TILE>
-void launch_b(const BwdArgs& a, int batch, int blocks, hipStream_t st) {
-  if (batch == 128) launch_t<TILE, 128>(a, blocks, st);
-  else if (batch == 256) launch_t<TILE, 256>(a, blocks, st);
-  else launch_t<TILE, 512>(a, blocks, st);
-}
+struct BwdLauncher {
+  const BwdArgs& a;
+  int blocks;
+  hipStream_t st;
+  template <int T, int B, int N>
+  void go() const {
+    hipLaunchKernelGGL((k_render_bwd<T, B, N>), dim3(blocks), dim3(N), 0, st,
+                       a);
+  }
+};
 
 }  // namespace
 
@@ -205,11 +217,8 @@ hipError_t launch_render_bwd(gs_workspace* ws, const gs_settings* s,
   a.grad2d = ws->grad2d; a.gop = ws->gop; a.grgb = grad_rgb;
   const int blocks = ws->geo.n_views * ws->tiles_x * ws->tiles_y;
   if (blocks <= 0) return hipSuccess;
-  switch (ws->geo.tile) {
-    case 8: launch_b<8>(a, s->lds_batch, blocks, st); break;
-    case 16: launch_b<16>(a, s->lds_batch, blocks, st); break;
-    default: launch_b<32>(a, s->lds_batch, blocks, st); break;
-  }
+  dispatch_shape(ws->geo.tile, s->lds_batch, s->block_threads,
+                 BwdLauncher{a, blocks, st});
   return hipGetLastError();
 }
 

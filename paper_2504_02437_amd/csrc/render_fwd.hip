@@ -1,13 +1,13 @@
 // Forward compositing (Eq. 3) over screen tiles.
 //
-// One workgroup per (view, tile).  Threads own pixels (one per thread for
-// 8x8 and 16x16 tiles, four per thread for 32x32).  The tile's sorted list is
-// walked front to back in batches: the workgroup stages a batch of records
-// into LDS (one coalesced gather per thread), then every thread blends its
-// pixels against the batch, reading each entry by an LDS broadcast.  A pixel
-// stops before the entry that would take its transmittance below T_min; a
-// wave leaves the batch once all its pixels stopped, and the workgroup stops
-// fetching batches once every pixel has.
+// One workgroup per (view, tile); each thread owns a vertical strip of the
+// tile's pixels (see raster_common.h).  The tile's sorted list is walked
+// front to back in batches: the workgroup stages a batch of records into LDS
+// (one gather per entry), then every thread blends its pixels against the
+// batch, reading each entry by an LDS broadcast.  A pixel stops before the
+// entry that would take its transmittance below T_min; a wave leaves the
+// batch once all its pixels stopped, and the workgroup stops fetching
+// batches once every pixel has.
 
 #include "raster_common.h"
 
@@ -25,11 +25,11 @@ struct FwdArgs {
 // COUNT = true is the work-counting variant: the same walk and decisions,
 // adding up examined / in-box / contributing / revisited pairs instead of
 // writing the image.
-template <int TILE, int BATCH, bool COUNT>
-__global__ __launch_bounds__(TILE * TILE > 256 ? 256 : TILE * TILE) void
-k_render_fwd(FwdArgs a) {
-  constexpr int NT = TILE * TILE > 256 ? 256 : TILE * TILE;
-  constexpr int PPT = TILE * TILE / NT;
+template <int TILE, int BATCH, int NT, bool COUNT>
+__global__ __launch_bounds__(NT) void k_render_fwd(FwdArgs a) {
+  constexpr int GROUPS = NT / TILE;
+  constexpr int PPT = TILE / GROUPS;
+  static_assert(GROUPS * PPT == TILE, "thread layout must tile the tile");
   __shared__ Entry ent[BATCH];
   const RasterArgs& r = a.r;
   const int t = blockIdx.x;
@@ -41,17 +41,16 @@ k_render_fwd(FwdArgs a) {
   long long s, e;
   tile_range(r, t, s, e);
 
-  int u[PPT], v[PPT], last[PPT];
+  const int u = tx * TILE + (tid % TILE);
+  const int v0 = ty * TILE + (tid / TILE) * PPT;
+  int last[PPT];
   float T[PPT], C0[PPT], C1[PPT], C2[PPT];
   bool done[PPT];
   unsigned n_exam = 0, n_inbox = 0, n_contrib = 0;
   unsigned ib[PPT], ib_last[PPT];
 #pragma unroll
   for (int p = 0; p < PPT; ++p) {
-    const int l = tid + p * NT;
-    u[p] = tx * TILE + (l % TILE);
-    v[p] = ty * TILE + (l / TILE);
-    done[p] = !(u[p] < r.W && v[p] < r.H);
+    done[p] = !(u < r.W && v0 + p < r.H);
     T[p] = 1.f;
     C0[p] = C1[p] = C2[p] = 0.f;
     last[p] = 0;
@@ -73,14 +72,21 @@ k_render_fwd(FwdArgs a) {
       for (int p = 0; p < PPT; ++p) any |= !done[p];
       if (!__any(any)) break;
       const Entry& E = ent[j];
+      const Lane L = lane_prep(E, u);
+      if (COUNT) {
+#pragma unroll
+        for (int p = 0; p < PPT; ++p) {
+          if (done[p]) continue;
+          ++n_exam;
+          if (L.in_u && in_v(E, v0 + p)) { ++n_inbox; ++ib[p]; }
+        }
+      }
+      if (!L.in_u) continue;
 #pragma unroll
       for (int p = 0; p < PPT; ++p) {
-        if (COUNT && !done[p]) ++n_exam;
-        if (done[p] || !in_box(E.box, u[p], v[p])) continue;
-        if (COUNT) { ++n_inbox; ++ib[p]; }
-        float dx, dy, G, e2, oG;
-        const float al = eval_alpha(E, (float)u[p], (float)v[p], r.alpha_max,
-                                    dx, dy, G, e2, oG);
+        if (done[p] || !in_v(E, v0 + p)) continue;
+        float dy, G, e2, oG;
+        const float al = pixel_alpha(E, L, v0 + p, r.alpha_max, dy, G, e2, oG);
         if (e2 > 0.f || al < r.alpha_min) continue;
         const float Tn = T[p] * (1.f - al);
         if (Tn < r.T_min) {
@@ -112,8 +118,9 @@ k_render_fwd(FwdArgs a) {
   const size_t HW = (size_t)r.H * r.W;
 #pragma unroll
   for (int p = 0; p < PPT; ++p) {
-    if (!(u[p] < r.W && v[p] < r.H)) continue;
-    const size_t pix = (size_t)v[p] * r.W + u[p];
+    const int v = v0 + p;
+    if (!(u < r.W && v < r.H)) continue;
+    const size_t pix = (size_t)v * r.W + u;
     a.rgb[((size_t)k * 3 + 0) * HW + pix] = fmaf(T[p], r.bg0, C0[p]);
     a.rgb[((size_t)k * 3 + 1) * HW + pix] = fmaf(T[p], r.bg1, C1[p]);
     a.rgb[((size_t)k * 3 + 2) * HW + pix] = fmaf(T[p], r.bg2, C2[p]);
@@ -122,29 +129,17 @@ k_render_fwd(FwdArgs a) {
   }
 }
 
-template <int TILE, int BATCH, bool COUNT>
-void launch_t(const FwdArgs& a, int blocks, hipStream_t st) {
-  constexpr int NT = TILE * TILE > 256 ? 256 : TILE * TILE;
-  hipLaunchKernelGGL((k_render_fwd<TILE, BATCH, COUNT>), dim3(blocks), dim3(NT),
-                     0, st, a);
-}
-
-template <int TILE, bool COUNT>
-void launch_b(const FwdArgs& a, int batch, int blocks, hipStream_t st) {
-  if (batch == 128) launch_t<TILE, 128, COUNT>(a, blocks, st);
-  else if (batch == 256) launch_t<TILE, 256, COUNT>(a, blocks, st);
-  else launch_t<TILE, 512, COUNT>(a, blocks, st);
-}
-
 template <bool COUNT>
-void launch_tile(const FwdArgs& a, int tile, int batch, int blocks,
-                 hipStream_t st) {
-  switch (tile) {
-    case 8: launch_b<8, COUNT>(a, batch, blocks, st); break;
-    case 16: launch_b<16, COUNT>(a, batch, blocks, st); break;
-    default: launch_b<32, COUNT>(a, batch, blocks, st); break;
+struct FwdLauncher {
+  const FwdArgs& a;
+  int blocks;
+  hipStream_t st;
+  template <int T, int B, int N>
+  void go() const {
+    hipLaunchKernelGGL((k_render_fwd<T, B, N, COUNT>), dim3(blocks), dim3(N),
+                       0, st, a);
   }
-}
+};
 
 }  // namespace
 
@@ -167,7 +162,8 @@ hipError_t launch_render_fwd(gs_workspace* ws, const gs_settings* s,
   a.rgb = rgb; a.T = T; a.nlast = nlast; a.counts = nullptr;
   const int blocks = ws->geo.n_views * ws->tiles_x * ws->tiles_y;
   if (blocks <= 0) return hipSuccess;
-  launch_tile<false>(a, ws->geo.tile, s->lds_batch, blocks, st);
+  dispatch_shape(ws->geo.tile, s->lds_batch, s->block_threads,
+                 FwdLauncher<false>{a, blocks, st});
   return hipGetLastError();
 }
 
@@ -178,7 +174,8 @@ hipError_t launch_count_pairs(gs_workspace* ws, const gs_settings* s,
   a.rgb = nullptr; a.T = nullptr; a.nlast = nullptr; a.counts = counts;
   const int blocks = ws->geo.n_views * ws->tiles_x * ws->tiles_y;
   if (blocks <= 0) return hipSuccess;
-  launch_tile<true>(a, ws->geo.tile, s->lds_batch, blocks, st);
+  dispatch_shape(ws->geo.tile, s->lds_batch, s->block_threads,
+                 FwdLauncher<true>{a, blocks, st});
   return hipGetLastError();
 }
 

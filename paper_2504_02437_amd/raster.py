@@ -119,6 +119,7 @@ class Settings:
     T_min: float = T_MIN
     alpha_max: float = ALPHA_MAX
     emit_keys: bool = False
+    block_threads: int = 0
 
     def struct(self) -> L.gs_settings:
         s = L.gs_settings()
@@ -127,6 +128,7 @@ class Settings:
         s.alpha_min, s.T_min, s.alpha_max = (self.alpha_min, self.T_min,
                                              self.alpha_max)
         s.flags = L.GS_FLAG_EMIT_KEYS if self.emit_keys else 0
+        s.block_threads = self.block_threads
         return s
 
 
@@ -278,10 +280,19 @@ def planar_reg(params, lam, floor, grad, loss_dev, stream=None):
 
 
 def adam(params, grad, m, v, lr, beta1, beta2, eps, step, stream=None):
+    """Adam step; `step` is an int, or an int32 device tensor holding the
+    step count (read on the device, so graph replays see its current
+    value)."""
     lr_arr = (C.c_float * 5)(*[float(x) for x in lr])
+    if isinstance(step, torch.Tensor):
+        if step.dtype != torch.int32 or not step.is_cuda:
+            raise ValueError("a device step count must be an int32 device tensor")
+        s_host, s_dev = 0, _ptr(step)
+    else:
+        s_host, s_dev = int(step), None
     L.call("gs_adam", C.byref(params.struct()), C.byref(grad.struct()),
            C.byref(m.struct()), C.byref(v.struct()), lr_arr, float(beta1),
-           float(beta2), float(eps), int(step), _stream(stream))
+           float(beta2), float(eps), s_host, s_dev, _stream(stream))
 
 
 def insert_gaussians(params, m, v, cam_dev, width, height, kf_rgb, kf_T, pts,

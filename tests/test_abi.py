@@ -91,7 +91,7 @@ def test_insert_and_adam_reject_bad_arguments():
     p = L.gs_params()
     lr = (C.c_float * 5)(1, 1, 1, 1, 1)
     assert lib.gs_adam(C.byref(p), C.byref(p), C.byref(p), C.byref(p), lr, 0.9,
-                       0.999, 1e-15, 1, None) == L.GS_E_INVALID
+                       0.999, 1e-15, 1, None, None) == L.GS_E_INVALID
     assert lib.gs_insert_gaussians(C.byref(p), None, None, None, 10, 10, None,
                                    None, None, 5, 0.9, 0, None, None, None,
                                    None) == L.GS_E_INVALID

@@ -33,14 +33,17 @@ def test_tiny_projection_sort_forward_backward(tile):
     check_grads(got, ref, w.gaussians.n)
 
 
-@pytest.mark.parametrize("tile,batch", [(8, 128), (8, 512), (16, 128),
-                                        (16, 256), (16, 512), (32, 256),
-                                        (32, 512)])
-def test_config0_all_launch_shapes(tile, batch):
+SHAPES = [(8, 128, 64), (8, 512, 64), (16, 128, 64), (16, 256, 64),
+          (16, 512, 64), (16, 128, 128), (16, 256, 128), (16, 512, 256),
+          (16, 256, 256), (32, 256, 128), (32, 128, 256), (32, 512, 256)]
+
+
+@pytest.mark.parametrize("tile,batch,threads", SHAPES)
+def test_config0_all_launch_shapes(tile, batch, threads):
     w = synth.config0()
-    print("case config0", tile, batch, flush=True)
+    print("case config0", tile, batch, threads, flush=True)
     p64, proj, bins, fwd = oracle_forward(w, tile)
-    params, rast = gpu_forward(w, tile, batch)
+    params, rast = gpu_forward(w, tile, batch, threads=threads)
     check_records(rast, proj)
     check_sort(rast, bins)
     mask, _ = check_forward(rast, fwd)
