@@ -131,6 +131,7 @@ def main():
     m = params.zeros_like()
     v = params.zeros_like()
     rast = R.Rasterizer(w.cameras, params.capacity, S, device=dev)
+    rast.fit_key_capacity(params)
     ws, cams_dev = rast.ws, rast.cams_dev
     rgb, T, nlast = rast.rgb, rast.T, rast.nlast
     target = torch.from_numpy(w.targets).to(dev)
@@ -221,6 +222,8 @@ def main():
         log("bench: per-keyframe plain path")
         singles = [R.Rasterizer([c], params.capacity, S, device=dev)
                    for c in w.cameras]
+        for r1 in singles:
+            r1.fit_key_capacity(params)
         tgt1 = [target[i:i + 1] for i in range(V)]
         dL1 = torch.empty(1, 3, H, W, device=dev)
 

@@ -78,6 +78,7 @@ def autotune(params, cams, base: R.Settings | None = None, reps=3,
         rast = R.Rasterizer(cams, params.capacity, s0,
                             key_capacity=key_capacity,
                             device=params.data.device)
+        rast.fit_key_capacity(params)
         for (t, b, n) in shapes((tile,)):
             rast.settings = R.Settings(t, b, base.bg, base.alpha_min,
                                        base.T_min, base.alpha_max, False, n)

@@ -347,6 +347,22 @@ class Rasterizer:
         self.nlast = torch.empty(self.V, self.H, self.W, dtype=torch.int32,
                                  device=device)
 
+    def fit_key_capacity(self, params, margin=1.25, stream=None):
+        """Projects and bins once; if the keys overflowed the workspace,
+        rebuilds it with `margin` times the exact key count.  Returns the key
+        count.  (Synchronises the stream.)"""
+        project_and_bin(self.ws, params, self.cams_dev, self.settings, stream)
+        flags, nk = read_status(self.ws, stream, clear=True)
+        if flags & L.GS_STATUS_KEY_OVERFLOW:
+            cap = int(min(2 ** 31 - 1, max(1024, int(nk * margin))))
+            if nk > cap:
+                raise RuntimeError(f"{nk} keys exceed the 2^31 limit")
+            self.ws = None
+            torch.cuda.empty_cache()
+            self.ws = Workspace(self.V, self.W, self.H, self.settings.tile,
+                                self.capacity, cap, self.rgb.device)
+        return nk
+
     def set_cameras(self, cams):
         if len(cams) != self.V:
             raise ValueError("view count is fixed per rasterizer")

@@ -33,7 +33,9 @@ def test_autograd_function_matches_oracle_gradient():
 
 def test_autograd_function_against_fp32_finite_differences():
     """Central differences of the GPU forward itself (FP32, step 1e-3
-    relative), skipping samples whose decision set changes."""
+    relative), skipping samples whose decision set changes (boxes, sorted
+    lists or stop positions).  FP32 rounding of the image gives the
+    differences an absolute noise of about 5e-4, hence the floor."""
     w = synth.tiny_scene(32, n=60, width=48, height=40, f=45.0,
                          log_scale_mu=-1.6)
     print("case autograd fd", flush=True)
@@ -46,6 +48,14 @@ def test_autograd_function_against_fp32_finite_differences():
     (rgb * wimg).sum().backward()
     g = data.grad.detach().clone()
     nl0 = nl0.clone()
+
+    def decisions():
+        nk = rast.status()[1]
+        return (rast.ws.tiles_touched().clone(), rast.ws.ranges().clone(),
+                rast.ws.vals_sorted(nk).clone())
+
+    rast.forward(params)
+    dec0 = decisions()
     rng = np.random.default_rng(3)
     checked = 0
     with torch.no_grad():
@@ -60,6 +70,9 @@ def test_autograd_function_against_fp32_finite_differences():
                 params.data[row, col] = x0 + sgn * h
                 out, _, nl = rast.forward(params)
                 ok &= bool(torch.equal(nl, nl0))
+                d = decisions()
+                ok &= all(a.shape == b.shape and bool(torch.equal(a, b))
+                          for a, b in zip(d, dec0))
                 vals.append(float((out * wimg).double().sum()))
             params.data[row, col] = x0
             if not ok:
@@ -67,7 +80,7 @@ def test_autograd_function_against_fp32_finite_differences():
             fd = (vals[0] - vals[1]) / (2 * h)
             an = float(g[row, col])
             scale = float(g[row].abs().max())
-            assert abs(fd - an) <= 2e-2 * max(abs(an), 1e-2 * scale) + 1e-4, \
+            assert abs(fd - an) <= 2e-2 * max(abs(an), 1e-2 * scale) + 2e-3, \
                 (row, col, fd, an)
             checked += 1
     assert checked >= 30
@@ -151,8 +164,9 @@ def test_loss_reg_adam_match_oracle():
     grad = params.zeros_like()
     reg = torch.zeros(1, dtype=torch.float64, device="cuda")
     R.planar_reg(params, 2.0, 0.01, grad, reg)
+    # The floor is an FP32 argument of the API: give the oracle the same value.
     ref_v, ref_g = oracle.planar_reg(w.gaussians.log_scale.astype(np.float64),
-                                     2.0, 0.01)
+                                     2.0, float(np.float32(0.01)))
     assert float(reg) == pytest.approx(ref_v, rel=1e-12)
     np.testing.assert_allclose(grad.data[3:6, :500].cpu().numpy(), ref_g,
                                rtol=1e-6, atol=0)
