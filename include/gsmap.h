@@ -177,7 +177,7 @@ GS_API int gs_project_and_bin(gs_workspace* ws, const gs_params* params,
                        void* stream);
 
 /* Sorts every tile's segment by (depth, Gaussian index) ascending, so each
- * tile's list is front to back with ties in index order; with
+ * tile's list is front to back with ties in index order (vals_sorted); with
  * GS_FLAG_EMIT_KEYS also writes keys_sorted.  The result equals a stable sort
  * of the keys (tile << 32 | depth bits) emitted in (view, Gaussian, tile row,
  * tile column) order. */

@@ -91,10 +91,10 @@ static int make_layout(const gs_geometry* g, Layout& L, int& tx, int& ty) {
   L.diff = take(V * (size_t)(ty + 1) * (tx + 1) * 4);
   L.ranges = take(tiles * 8);
   L.cursor = take(tiles * 4);
-  L.vals_unsorted = take(kc * 4);
+  L.view_tot = take(V * 8);
+  L.keys_unsorted = take(kc * 8);
   L.vals_sorted = take(kc * 4);
   L.keys_sorted = take(kc * 8);
-  L.sort_tmp = take(kc * 8);
   L.grad2d = take(V * 5 * cap * 4);
   L.gop = take(cap * 4);
   L.counters = take(sizeof(Counters));
@@ -162,10 +162,10 @@ int gs_workspace_create(const gs_geometry* geo, void* device_buffer,
   ws->diff = (int32_t*)(b + L.diff);
   ws->ranges = (uint32_t*)(b + L.ranges);
   ws->cursor = (uint32_t*)(b + L.cursor);
-  ws->vals_unsorted = (uint32_t*)(b + L.vals_unsorted);
+  ws->view_tot = (long long*)(b + L.view_tot);
+  ws->keys_unsorted = (unsigned long long*)(b + L.keys_unsorted);
   ws->vals_sorted = (uint32_t*)(b + L.vals_sorted);
   ws->keys_sorted = (unsigned long long*)(b + L.keys_sorted);
-  ws->sort_tmp = (unsigned long long*)(b + L.sort_tmp);
   ws->grad2d = (float*)(b + L.grad2d);
   ws->gop = (float*)(b + L.gop);
   ws->counters = (Counters*)(b + L.counters);

@@ -1,14 +1,20 @@
-// Tile binning: per-tile key counts, ranges, and the scatter of Gaussian
-// indices into their tiles' segments.
+// Tile binning: per-tile key counts, ranges, and the scatter of the
+// (depth, index) keys into their tiles' segments.
 //
 // Counts come from the tile-coverage difference grid the projection kernel
-// fills (four corner increments per box of tiles); a 2D prefix sum turns it
-// into the number of boxes covering each tile.  One exclusive scan over all
-// (view, tile) cells then gives every tile's [start, end) range in the key
-// buffer, so n_keys never leaves the device.  The scatter walks each box of
-// tiles with wave-level load balancing (one lane per emitted key) and claims
-// slots with one atomic per key; sort_tile_keys makes the order inside each
-// segment deterministic.
+// fills (four corner increments per box of tiles): one workgroup per view
+// loads its grid into LDS and takes the 2D prefix sum, which is the number of
+// boxes covering each tile.  A second kernel turns the counts into every
+// tile's [start, end) range with one exclusive scan per view plus the totals
+// of the preceding views, so n_keys never leaves the device.
+//
+// The scatter gives each workgroup a chunk of Gaussians of one view.  It
+// walks the chunk's keys twice with wave-level load balancing (one lane per
+// key): first counting keys per tile in LDS, then - after reserving each
+// touched tile's share with a single global atomic - claiming positions with
+// LDS atomics.  Each key is written as (depth bits << 32 | index), so the
+// per-tile sort needs no gather.  Images whose tile grid does not fit in LDS
+// use a per-key global-atomic scatter.
 
 #include "gs_internal.h"
 
@@ -16,79 +22,105 @@ namespace gs {
 namespace {
 
 constexpr int kScanThreads = 1024;
+constexpr int kMaxGridCells = 16384;  // LDS difference grid (64 KB)
 
-struct ScanArgs {
-  int32_t* diff;  // [V][Ty + 1][Tx + 1], consumed and cleared
+struct CountArgs {
+  int32_t* diff;        // [V][Ty + 1][Tx + 1], consumed and cleared
+  uint32_t* counts;     // [V][Ty][Tx] key count per tile (the cursor array)
+  long long* view_tot;  // [V]
+  int Tx, Ty;
+};
+
+// One workgroup per view: counts = 2D inclusive prefix of the difference
+// grid.  Grids larger than kMaxGridCells are scanned in global memory.
+__global__ __launch_bounds__(kScanThreads) void k_tile_count(CountArgs a) {
+  __shared__ int32_t grid[kMaxGridCells];
+  __shared__ long long part[kScanThreads / 64];
+  const int k = blockIdx.x, tid = threadIdx.x;
+  const int stride = a.Tx + 1, rows = a.Ty + 1;
+  const int cells = stride * rows;
+  int32_t* d = a.diff + (size_t)k * cells;
+  const bool in_lds = cells <= kMaxGridCells;
+  int32_t* G = in_lds ? grid : d;
+  if (in_lds)
+    for (int i = tid; i < cells; i += kScanThreads) grid[i] = d[i];
+  __syncthreads();
+  for (int y = tid; y < rows; y += kScanThreads) {
+    int acc = 0;
+    for (int x = 0; x < stride; ++x) { acc += G[y * stride + x]; G[y * stride + x] = acc; }
+  }
+  __syncthreads();
+  for (int x = tid; x < stride; x += kScanThreads) {
+    int acc = 0;
+    for (int y = 0; y < rows; ++y) { acc += G[y * stride + x]; G[y * stride + x] = acc; }
+  }
+  __syncthreads();
+  long long local = 0;
+  const int tiles = a.Tx * a.Ty;
+  uint32_t* c = a.counts + (size_t)k * tiles;
+  for (int t = tid; t < tiles; t += kScanThreads) {
+    const int ty = t / a.Tx, tx = t - ty * a.Tx;
+    const int v = G[ty * stride + tx];
+    c[t] = (uint32_t)v;
+    local += v;
+  }
+  for (int off = 32; off > 0; off >>= 1) local += __shfl_down(local, off, 64);
+  if ((tid & 63) == 0) part[tid >> 6] = local;
+  __syncthreads();
+  if (tid == 0) {
+    long long s = 0;
+    for (int i = 0; i < kScanThreads / 64; ++i) s += part[i];
+    a.view_tot[k] = s;
+  }
+  for (int i = tid; i < cells; i += kScanThreads) d[i] = 0;
+}
+
+struct RangeArgs {
+  uint32_t* counts;   // in: counts; out: cursors (= range starts)
   uint32_t* ranges;
-  uint32_t* cursor;
+  const long long* view_tot;
   Counters* ctr;
   int V, Tx, Ty;
   long long key_cap;
 };
 
-__global__ __launch_bounds__(kScanThreads) void k_tile_scan(ScanArgs a) {
-  const int tid = threadIdx.x;
-  const int stride = a.Tx + 1;
-  const int rows = a.Ty + 1;
-  // 1. Prefix along x of every row of every view.
-  for (int r = tid; r < a.V * rows; r += kScanThreads) {
-    int32_t* row = a.diff + (size_t)r * stride;
-    int acc = 0;
-    for (int x = 0; x < stride; ++x) {
-      acc += row[x];
-      row[x] = acc;
-    }
-  }
-  __syncthreads();
-  // 2. Prefix along y of every column of every view.
-  for (int c = tid; c < a.V * stride; c += kScanThreads) {
-    const int k = c / stride, x = c % stride;
-    int32_t* col = a.diff + (size_t)k * rows * stride + x;
-    int acc = 0;
-    for (int y = 0; y < rows; ++y) {
-      acc += col[(size_t)y * stride];
-      col[(size_t)y * stride] = acc;
-    }
-  }
-  __syncthreads();
-  // 3. Exclusive scan of the counts over (view, ty, tx), chunked per thread.
-  const long long total_tiles = (long long)a.V * a.Ty * a.Tx;
-  const long long per = (total_tiles + kScanThreads - 1) / kScanThreads;
-  const long long t0 = tid * per;
-  const long long t1 = min(total_tiles, t0 + per);
-  auto count_of = [&](long long t) -> long long {
-    const int k = (int)(t / ((long long)a.Tx * a.Ty));
-    const int rem = (int)(t % ((long long)a.Tx * a.Ty));
-    const int ty = rem / a.Tx, tx = rem % a.Tx;
-    return a.diff[((size_t)k * rows + ty) * stride + tx];
-  };
-  long long local = 0;
-  for (long long t = t0; t < t1; ++t) local += count_of(t);
+// One workgroup per view: exclusive scan of the view's tile counts, offset by
+// the totals of the preceding views.
+__global__ __launch_bounds__(kScanThreads) void k_tile_ranges(RangeArgs a) {
   __shared__ long long part[kScanThreads];
+  const int k = blockIdx.x, tid = threadIdx.x;
+  long long base = 0, total = 0;
+  for (int i = 0; i < a.V; ++i) {
+    if (i < k) base += a.view_tot[i];
+    total += a.view_tot[i];
+  }
+  const int tiles = a.Tx * a.Ty;
+  const int per = (tiles + kScanThreads - 1) / kScanThreads;
+  const int t0 = tid * per, t1 = min(tiles, t0 + per);
+  uint32_t* c = a.counts + (size_t)k * tiles;
+  long long local = 0;
+  for (int t = t0; t < t1; ++t) local += c[t];
   part[tid] = local;
   __syncthreads();
   for (int off = 1; off < kScanThreads; off <<= 1) {
-    long long v = tid >= off ? part[tid - off] : 0;
+    const long long v = tid >= off ? part[tid - off] : 0;
     __syncthreads();
     part[tid] += v;
     __syncthreads();
   }
-  long long run = part[tid] - local;
-  for (long long t = t0; t < t1; ++t) {
-    const long long c = count_of(t);
-    a.ranges[2 * t] = (uint32_t)run;
-    a.cursor[t] = (uint32_t)run;
-    run += c;
-    a.ranges[2 * t + 1] = (uint32_t)run;
+  long long run = base + part[tid] - local;
+  uint32_t* r = a.ranges + 2 * (size_t)k * tiles;
+  for (int t = t0; t < t1; ++t) {
+    const uint32_t cnt = c[t];
+    r[2 * t] = (uint32_t)run;
+    c[t] = (uint32_t)run;
+    run += cnt;
+    r[2 * t + 1] = (uint32_t)run;
   }
-  if (tid == kScanThreads - 1) {
-    a.ctr->n_keys = part[tid];
-    if (part[tid] > a.key_cap) atomicOr(&a.ctr->status, GS_STATUS_KEY_OVERFLOW);
+  if (k == 0 && tid == 0) {
+    a.ctr->n_keys = total;
+    if (total > a.key_cap) atomicOr(&a.ctr->status, GS_STATUS_KEY_OVERFLOW);
   }
-  __syncthreads();
-  // 4. Clear the difference grid for the next call.
-  const size_t cells = (size_t)a.V * rows * stride;
-  for (size_t i = tid; i < cells; i += kScanThreads) a.diff[i] = 0;
 }
 
 struct ScatterArgs {
@@ -97,87 +129,161 @@ struct ScatterArgs {
   const int32_t* n_dev;
   int cap, tile, Tx, Ty;
   uint32_t* cursor;
-  uint32_t* vals;
+  unsigned long long* keys;
   long long key_cap;
 };
 
-// One thread per (view, Gaussian); the keys of a wave's 64 Gaussians are
-// emitted 64 at a time, each lane locating its owner by binary search over
-// the wave's inclusive prefix of key counts.
-__global__ __launch_bounds__(256) void k_scatter(ScatterArgs a) {
-  __shared__ int incl[4][64];
-  __shared__ int own_x0[4][64], own_y0[4][64], own_w[4][64];
-  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-  const int k = blockIdx.y;
-  const int g = blockIdx.x * 256 + threadIdx.x;
+// Per-wave key enumeration: lane l owns one Gaussian with cnt keys (its box
+// of tiles, row-major); f(tile_in_view, g, depth_bits) runs once per key,
+// 64 keys per step, each lane locating its key's owner by binary search over
+// the wave's inclusive prefix of counts.
+struct WaveOwners {
+  int incl[64], x0[64], y0[64], w[64];
+  uint32_t g[64], d[64];
+};
+
+__device__ inline void load_owner(const ScatterArgs& a, int k, int g, int& cnt,
+                                  int& x0, int& y0, int& w, uint32_t& dbits) {
+  cnt = 0; x0 = 0; y0 = 0; w = 1; dbits = 0;
   const int n = min(*a.n_dev, a.cap);
-  int cnt = 0, x0 = 0, y0 = 0, w = 1;
-  if (g < n) {
-    const size_t slot = (size_t)k * a.cap + g;
-    cnt = a.tiles[slot];
-    if (cnt > 0) {
-      const float4 q2 = a.rec[slot].q2;
-      const int bu = __float_as_int(q2.z), bv = __float_as_int(q2.w);
-      x0 = (bu & 0xffff) / a.tile;
-      const int x1 = (bu >> 16) / a.tile;
-      y0 = (bv & 0xffff) / a.tile;
-      w = x1 - x0 + 1;
-    }
-  }
-  // Inclusive prefix of counts across the wave.
+  if (g >= n) return;
+  const size_t slot = (size_t)k * a.cap + g;
+  cnt = a.tiles[slot];
+  if (cnt <= 0) { cnt = 0; return; }
+  const float4 q2 = a.rec[slot].q2;
+  const int bu = __float_as_int(q2.z), bv = __float_as_int(q2.w);
+  x0 = (bu & 0xffff) / a.tile;
+  w = (bu >> 16) / a.tile - x0 + 1;
+  y0 = (bv & 0xffff) / a.tile;
+  dbits = __float_as_uint(q2.y);
+}
+
+template <typename F>
+__device__ inline void wave_enumerate(WaveOwners& O, int lane, int cnt, int x0,
+                                      int y0, int w, uint32_t g, uint32_t dbits,
+                                      int Tx, F&& f) {
   int s = cnt;
   for (int off = 1; off < 64; off <<= 1) {
     const int v = __shfl_up(s, off, 64);
     if (lane >= off) s += v;
   }
-  incl[wv][lane] = s;
-  own_x0[wv][lane] = x0;
-  own_y0[wv][lane] = y0;
-  own_w[wv][lane] = w;
+  O.incl[lane] = s; O.x0[lane] = x0; O.y0[lane] = y0; O.w[lane] = w;
+  O.g[lane] = g; O.d[lane] = dbits;
   __syncthreads();
   const int total = __shfl(s, 63, 64);
-  const uint32_t tile_base = (uint32_t)k * a.Tx * a.Ty;
-  for (int base = 0; base < total; base += 64) {
-    const int j = base + lane;
+  for (int b = 0; b < total; b += 64) {
+    const int j = b + lane;
     if (j < total) {
-      // First owner o with incl[o] > j.
       int lo = 0, hi = 63;
       while (lo < hi) {
         const int mid = (lo + hi) >> 1;
-        if (incl[wv][mid] > j) hi = mid; else lo = mid + 1;
+        if (O.incl[mid] > j) hi = mid; else lo = mid + 1;
       }
-      const int o = lo;
-      const int local = j - (o ? incl[wv][o - 1] : 0);
-      const int ww = own_w[wv][o];
-      const int ty = own_y0[wv][o] + local / ww;
-      const int tx = own_x0[wv][o] + local % ww;
-      const uint32_t t = tile_base + (uint32_t)(ty * a.Tx + tx);
-      const uint32_t pos = atomicAdd(&a.cursor[t], 1u);
-      if ((long long)pos < a.key_cap)
-        a.vals[pos] = (uint32_t)(blockIdx.x * 256 + wv * 64 + o);
+      const int local = j - (lo ? O.incl[lo - 1] : 0);
+      const int ww = O.w[lo];
+      const int ty = O.y0[lo] + local / ww;
+      const int tx = O.x0[lo] + local % ww;
+      f(ty * Tx + tx, O.g[lo], O.d[lo]);
     }
   }
+  __syncthreads();
+}
+
+// LDS-privatised scatter: GPT Gaussians per thread, one view per block.
+template <int MAXBINS, int GPT>
+__global__ __launch_bounds__(256) void k_scatter_lds(ScatterArgs a) {
+  __shared__ uint32_t bins[MAXBINS];
+  __shared__ WaveOwners owners[4];
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  const int k = blockIdx.y;
+  const int nb = a.Tx * a.Ty;
+  for (int i = tid; i < nb; i += 256) bins[i] = 0;
+  __syncthreads();
+  const int g0 = blockIdx.x * 256 * GPT;
+  for (int sub = 0; sub < GPT; ++sub) {
+    const int g = g0 + sub * 256 + tid;
+    int cnt, x0, y0, w;
+    uint32_t d;
+    load_owner(a, k, g, cnt, x0, y0, w, d);
+    wave_enumerate(owners[wv], lane, cnt, x0, y0, w, (uint32_t)g, d, a.Tx,
+                   [&](int t, uint32_t, uint32_t) { atomicAdd(&bins[t], 1u); });
+  }
+  __syncthreads();
+  uint32_t* cur = a.cursor + (size_t)k * nb;
+  for (int i = tid; i < nb; i += 256) {
+    const uint32_t c = bins[i];
+    if (c) bins[i] = atomicAdd(&cur[i], c);
+  }
+  __syncthreads();
+  for (int sub = 0; sub < GPT; ++sub) {
+    const int g = g0 + sub * 256 + tid;
+    int cnt, x0, y0, w;
+    uint32_t d;
+    load_owner(a, k, g, cnt, x0, y0, w, d);
+    wave_enumerate(owners[wv], lane, cnt, x0, y0, w, (uint32_t)g, d, a.Tx,
+                   [&](int t, uint32_t gg, uint32_t dd) {
+                     const uint32_t pos = atomicAdd(&bins[t], 1u);
+                     if ((long long)pos < a.key_cap)
+                       a.keys[pos] = ((unsigned long long)dd << 32) | gg;
+                   });
+  }
+}
+
+// Fallback for tile grids larger than the LDS bins: one global atomic per key.
+__global__ __launch_bounds__(256) void k_scatter_global(ScatterArgs a) {
+  __shared__ WaveOwners owners[4];
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  const int k = blockIdx.y;
+  const int g = blockIdx.x * 256 + tid;
+  int cnt, x0, y0, w;
+  uint32_t d;
+  load_owner(a, k, g, cnt, x0, y0, w, d);
+  uint32_t* cur = a.cursor + (size_t)k * a.Tx * a.Ty;
+  wave_enumerate(owners[wv], lane, cnt, x0, y0, w, (uint32_t)g, d, a.Tx,
+                 [&](int t, uint32_t gg, uint32_t dd) {
+                   const uint32_t pos = atomicAdd(&cur[t], 1u);
+                   if ((long long)pos < a.key_cap)
+                     a.keys[pos] = ((unsigned long long)dd << 32) | gg;
+                 });
+}
+
+template <int MAXBINS, int GPT>
+void launch_lds(const ScatterArgs& c, int V, hipStream_t st) {
+  const int bx = (c.cap + 256 * GPT - 1) / (256 * GPT);
+  hipLaunchKernelGGL((k_scatter_lds<MAXBINS, GPT>), dim3(bx, V), dim3(256), 0,
+                     st, c);
 }
 
 }  // namespace
 
 hipError_t launch_bin(gs_workspace* ws, const gs_params* p, hipStream_t st) {
-  ScanArgs s;
-  s.diff = ws->diff; s.ranges = ws->ranges; s.cursor = ws->cursor;
-  s.ctr = ws->counters; s.V = ws->geo.n_views; s.Tx = ws->tiles_x;
-  s.Ty = ws->tiles_y; s.key_cap = ws->geo.key_capacity;
-  hipLaunchKernelGGL(k_tile_scan, dim3(1), dim3(kScanThreads), 0, st, s);
+  const int V = ws->geo.n_views;
+  CountArgs ca;
+  ca.diff = ws->diff; ca.counts = ws->cursor; ca.view_tot = ws->view_tot;
+  ca.Tx = ws->tiles_x; ca.Ty = ws->tiles_y;
+  hipLaunchKernelGGL(k_tile_count, dim3(V), dim3(kScanThreads), 0, st, ca);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
+  RangeArgs ra;
+  ra.counts = ws->cursor; ra.ranges = ws->ranges; ra.view_tot = ws->view_tot;
+  ra.ctr = ws->counters; ra.V = V; ra.Tx = ws->tiles_x; ra.Ty = ws->tiles_y;
+  ra.key_cap = ws->geo.key_capacity;
+  hipLaunchKernelGGL(k_tile_ranges, dim3(V), dim3(kScanThreads), 0, st, ra);
+  e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  if (p->capacity <= 0) return hipSuccess;
   ScatterArgs c;
   c.rec = ws->records; c.tiles = ws->tiles_touched; c.n_dev = p->n_dev;
   c.cap = p->capacity; c.tile = ws->geo.tile; c.Tx = ws->tiles_x;
-  c.Ty = ws->tiles_y; c.cursor = ws->cursor; c.vals = ws->vals_unsorted;
+  c.Ty = ws->tiles_y; c.cursor = ws->cursor; c.keys = ws->keys_unsorted;
   c.key_cap = ws->geo.key_capacity;
-  const int bx = (p->capacity + 255) / 256;
-  if (bx > 0)
-    hipLaunchKernelGGL(k_scatter, dim3(bx, ws->geo.n_views), dim3(256), 0, st,
-                       c);
+  const int nb = ws->tiles_x * ws->tiles_y;
+  if (nb <= 1024) launch_lds<1024, 4>(c, V, st);
+  else if (nb <= 4096) launch_lds<4096, 8>(c, V, st);
+  else if (nb <= 16384) launch_lds<16384, 8>(c, V, st);
+  else
+    hipLaunchKernelGGL(k_scatter_global, dim3((c.cap + 255) / 256, V),
+                       dim3(256), 0, st, c);
   return hipGetLastError();
 }
 

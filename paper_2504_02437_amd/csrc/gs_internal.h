@@ -18,8 +18,8 @@ struct __align__(16) Record {
 
 // Workspace layout: every region is carved from the caller's device buffer.
 struct Layout {
-  size_t records, tiles_touched, diff, ranges, cursor, vals_unsorted,
-      vals_sorted, keys_sorted, sort_tmp, grad2d, gop, counters, total;
+  size_t records, tiles_touched, diff, ranges, cursor, view_tot, keys_unsorted,
+      vals_sorted, keys_sorted, grad2d, gop, counters, total;
 };
 
 // Device-side counters block.
@@ -41,11 +41,11 @@ struct gs_workspace {
   int32_t* tiles_touched;
   int32_t* diff;         // [V][Ty + 1][Tx + 1] tile-coverage difference grid
   uint32_t* ranges;      // [V * Ty * Tx][2]
-  uint32_t* cursor;      // [V * Ty * Tx] scatter cursors
-  uint32_t* vals_unsorted;
+  uint32_t* cursor;      // [V * Ty * Tx] tile counts, then scatter cursors
+  long long* view_tot;   // [V] keys per view
+  unsigned long long* keys_unsorted;  // [key_capacity] depth bits << 32 | g
   uint32_t* vals_sorted;
   unsigned long long* keys_sorted;
-  unsigned long long* sort_tmp;
   float* grad2d;         // [V][5][capacity]
   float* gop;            // [capacity] dL/d opacity summed over views
   gs::Counters* counters;

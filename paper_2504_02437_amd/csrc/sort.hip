@@ -1,20 +1,18 @@
 // Per-tile sort of the binned keys.
 //
-// After the scatter every tile owns a contiguous segment of Gaussian indices
-// in unspecified order.  One workgroup per (view, tile) gathers each entry's
-// FP32 depth from its record, forms the 64-bit key (depth bits << 32 | index)
-// and sorts the segment ascending.  Depths are positive, so their IEEE bit
-// patterns order like the values; the index in the low half makes every key
-// unique and breaks depth ties in index order, which is exactly the order of
-// a stable sort of (tile << 32 | depth bits) keys emitted Gaussian by
-// Gaussian.
+// After the scatter every tile owns a contiguous segment of 64-bit keys
+// (FP32 depth bits << 32 | Gaussian index) in unspecified order.  One
+// workgroup per (view, tile) sorts its segment ascending.  Depths are
+// positive, so their IEEE bit patterns order like the values; the index in
+// the low half makes every key unique and breaks depth ties in index order,
+// which is exactly the order of a stable sort of (tile << 32 | depth bits)
+// keys emitted Gaussian by Gaussian.
 //
 // Sorting network: bitonic, in the form whose first comparator of every
 // merge stage pairs mirrored positions, so every comparator is ascending and
 // positions past the segment end act as +infinity without being stored.
-// Segments up to kCap entries sort in LDS; longer ones sort in place in a
-// global scratch region of the same extent (rare: a tile covered by more
-// than kCap Gaussians).
+// Segments up to kCap keys sort in LDS; longer ones sort in place in the
+// unsorted key buffer (rare: a tile covered by more than kCap Gaussians).
 
 #include "gs_internal.h"
 
@@ -22,14 +20,11 @@ namespace gs {
 namespace {
 
 struct SortArgs {
-  const Record* rec;
   const uint32_t* ranges;
-  const uint32_t* vals_in;
+  unsigned long long* keys_in;   // sorted in place when a segment is long
   uint32_t* vals_out;
   unsigned long long* keys_out;  // may be null
-  unsigned long long* tmp;
   long long key_cap;
-  int cap, tiles_per_view;
 };
 
 template <typename P>
@@ -76,27 +71,18 @@ __global__ __launch_bounds__(256) void k_sort_tiles(SortArgs a) {
   const long long e = min((long long)a.ranges[2 * t + 1], a.key_cap);
   const int L = (int)(e - s);
   if (L <= 0) return;
-  const int k = t / a.tiles_per_view;
-  const Record* rv = a.rec + (size_t)k * a.cap;
-  auto key_of = [&](int i) -> unsigned long long {
-    const uint32_t g = a.vals_in[s + i];
-    const uint32_t d = __float_as_uint(rv[g].q2.y);
-    return ((unsigned long long)d << 32) | g;
-  };
   auto store = [&](int i, unsigned long long v) {
     a.vals_out[s + i] = (uint32_t)v;
     if (a.keys_out)
       a.keys_out[s + i] = ((unsigned long long)(uint32_t)t << 32) | (v >> 32);
   };
   if (L <= kCap) {
-    for (int i = tid; i < L; i += 256) buf[i] = key_of(i);
+    for (int i = tid; i < L; i += 256) buf[i] = a.keys_in[s + i];
     __syncthreads();
     bitonic_sort(buf, L, tid, 256);
     for (int i = tid; i < L; i += 256) store(i, buf[i]);
   } else {
-    unsigned long long* g = a.tmp + s;
-    for (int i = tid; i < L; i += 256) g[i] = key_of(i);
-    __syncthreads();
+    unsigned long long* g = a.keys_in + s;
     bitonic_sort(g, L, tid, 256);
     for (int i = tid; i < L; i += 256) store(i, g[i]);
   }
@@ -106,17 +92,13 @@ __global__ __launch_bounds__(256) void k_sort_tiles(SortArgs a) {
 
 hipError_t launch_sort(gs_workspace* ws, const gs_settings* s, hipStream_t st) {
   SortArgs a;
-  a.rec = ws->records; a.ranges = ws->ranges; a.vals_in = ws->vals_unsorted;
+  a.ranges = ws->ranges; a.keys_in = ws->keys_unsorted;
   a.vals_out = ws->vals_sorted;
   a.keys_out = (s->flags & GS_FLAG_EMIT_KEYS) ? ws->keys_sorted : nullptr;
-  a.tmp = ws->sort_tmp; a.key_cap = ws->geo.key_capacity;
-  a.cap = ws->geo.capacity; a.tiles_per_view = ws->tiles_x * ws->tiles_y;
-  const int blocks = ws->geo.n_views * a.tiles_per_view;
+  a.key_cap = ws->geo.key_capacity;
+  const int blocks = ws->geo.n_views * ws->tiles_x * ws->tiles_y;
   if (blocks <= 0) return hipSuccess;
-  if (ws->geo.tile >= 32)
-    hipLaunchKernelGGL(k_sort_tiles<8192>, dim3(blocks), dim3(256), 0, st, a);
-  else
-    hipLaunchKernelGGL(k_sort_tiles<4096>, dim3(blocks), dim3(256), 0, st, a);
+  hipLaunchKernelGGL(k_sort_tiles<4096>, dim3(blocks), dim3(256), 0, st, a);
   return hipGetLastError();
 }
 

@@ -33,11 +33,11 @@ def _geo(**kw):
 def test_workspace_size_host_only():
     size = C.c_size_t()
     assert L.lib().gs_workspace_size(C.byref(_geo()), C.byref(size)) == L.GS_OK
-    # records 48 B + tiles 4 B per (view, Gaussian); 24 B per key; grad2d.
-    assert size.value >= 2 * 1000 * 52 + 50000 * 24 + 2 * 5 * 1000 * 4
+    # records 48 B + tiles 4 B per (view, Gaussian); 20 B per key; grad2d.
+    assert size.value >= 2 * 1000 * 52 + 50000 * 20 + 2 * 5 * 1000 * 4
     big = C.c_size_t()
     L.lib().gs_workspace_size(C.byref(_geo(key_capacity=100000)), C.byref(big))
-    assert big.value - size.value >= 50000 * 24 - 4 * 256
+    assert big.value - size.value >= 50000 * 20 - 4 * 256
 
 
 @pytest.mark.parametrize("kw", [dict(tile=12), dict(n_views=0), dict(width=0),

@@ -33,14 +33,19 @@ def test_autograd_function_matches_oracle_gradient():
 
 def test_autograd_function_against_fp32_finite_differences():
     """Central differences of the GPU forward itself (FP32, step 1e-3
-    relative), skipping samples whose decision set changes (boxes, sorted
-    lists or stop positions).  FP32 rounding of the image gives the
+    relative).  The alpha and transmittance cut-offs are discontinuities that
+    no output reveals (one pixel crossing alpha_min moves the loss by
+    ~alpha_min), so this check runs with cut-offs of 1e-30 / 1e-35 where
+    every remaining decision (boxes, sorted lists, stop positions) is checked
+    frozen; the cut-off rules are covered by the oracle's frozen-decision
+    differences and the parity tests.  FP32 rounding of the image gives the
     differences an absolute noise of about 5e-4, hence the floor."""
     w = synth.tiny_scene(32, n=60, width=48, height=40, f=45.0,
                          log_scale_mu=-1.6)
     print("case autograd fd", flush=True)
     params = R.ParamBuffer.from_gaussians(w.gaussians)
-    rast = R.Rasterizer(w.cameras, params.capacity, R.Settings(tile=16))
+    rast = R.Rasterizer(w.cameras, params.capacity,
+                        R.Settings(tile=16, alpha_min=1e-30, T_min=1e-35))
     wimg = torch.from_numpy(np.random.default_rng(2).normal(
         size=(1, 3, 40, 48)).astype(np.float32)).cuda()
     data = params.data.requires_grad_(True)
@@ -52,7 +57,8 @@ def test_autograd_function_against_fp32_finite_differences():
     def decisions():
         nk = rast.status()[1]
         return (rast.ws.tiles_touched().clone(), rast.ws.ranges().clone(),
-                rast.ws.vals_sorted(nk).clone())
+                rast.ws.vals_sorted(nk).clone(),
+                rast.ws.records()[..., 10:12].clone())
 
     rast.forward(params)
     dec0 = decisions()
