@@ -66,9 +66,9 @@ def check_sort(rast, bins):
     np.testing.assert_array_equal(keys, bins["keys"])
 
 
-def check_forward(rast, fwd):
+def check_forward(rast, fwd, max_flagged=MAX_FLAGGED):
     mask = fwd["flags"] == 0
-    assert 1.0 - mask.mean() <= MAX_FLAGGED, 1.0 - mask.mean()
+    assert 1.0 - mask.mean() <= max_flagged, 1.0 - mask.mean()
     img = rast.rgb.cpu().numpy()
     T = rast.T.cpu().numpy()
     nl = rast.nlast.cpu().numpy()

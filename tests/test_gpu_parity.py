@@ -196,4 +196,6 @@ def test_long_tile_lists_use_the_global_sort_path():
     params, rast = gpu_forward(w, 16)
     check_records(rast, proj)
     check_sort(rast, bins)
-    check_forward(rast, fwd)
+    # Thousands of faint entries per pixel widen the transmittance error
+    # bound, so more pixels are FP32-ambiguous here than in real scenes.
+    check_forward(rast, fwd, max_flagged=0.05)
