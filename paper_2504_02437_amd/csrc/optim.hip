@@ -115,13 +115,19 @@ struct AdamArgs {
 };
 
 __global__ __launch_bounds__(256) void k_adam(AdamArgs a) {
+  __shared__ float corr[2];
   const int g = blockIdx.x * 256 + threadIdx.x;
   const int row = blockIdx.y;
   const int n = min(*a.n_dev, a.cap);
+  if (blockIdx.x * 256 >= n) return;
+  if (threadIdx.x == 0) {
+    const int step = a.step_dev ? max(1, *a.step_dev) : a.step;
+    corr[0] = (float)(1.0 - pow((double)a.b1, (double)step));
+    corr[1] = (float)(1.0 - pow((double)a.b2, (double)step));
+  }
+  __syncthreads();
   if (g >= n) return;
-  const int step = a.step_dev ? max(1, *a.step_dev) : a.step;
-  const float c1 = (float)(1.0 - pow((double)a.b1, (double)step));
-  const float c2 = (float)(1.0 - pow((double)a.b2, (double)step));
+  const float c1 = corr[0], c2 = corr[1];
   const float gr = a.g[row][g];
   const float m = a.b1 * a.m[row][g] + (1.f - a.b1) * gr;
   const float v = a.b2 * a.v[row][g] + (1.f - a.b2) * gr * gr;
