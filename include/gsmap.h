@@ -263,26 +263,73 @@ GS_API int gs_adam(gs_params* params, const gs_params* grad, gs_params* m,
 /* Keyframe insertion (Eq. 6 with an accumulated-alpha mask).  Candidates are
  * the 3x3 pixel patch around each of the n_pts centres pts_uvd [n][3] =
  * (u, v, inverse depth) (device), visited patch by patch, pixels row-major
- * (or only the centre pixel when centre_only != 0).  A candidate inside the
+ * (or only the centre pixel when centre_only != 0); candidate c is patch
+ * c / 9, pixel c % 9 (c = patch with centre_only).  A candidate inside the
  * image is kept when 1 - kf_T_final(u, v) <= alpha_skip.  Kept candidates,
- * in visiting order, are appended at the live count: mean = R^T(K^-1 [u v 1]^T
- * / d - t), colour = kf_rgb [3][H][W] at the pixel, opacity logit 0, identity
- * rotation and log-scale log(z / fx) on every axis, or - when mlp_out is not
- * NULL - log-scale, opacity logit and colour from mlp_out [n_pts][7]
- * (per patch).  Zeroes the Adam moments of the new entries (m, v may be
- * NULL), updates *params->n_dev, and sets GS_STATUS_GAUSSIAN_OVERFLOW when
- * capacity would be exceeded (nothing past capacity is written).  At most 9
- * * n_pts <= 65536 candidates.  status_dev: a device int32 receiving the
- * status bits (may be NULL).  n_inserted_dev: device int32 receiving the
+ * in visiting order, are appended at the live count: mean = R^T(K^-1
+ * [u v 1]^T / d - t), colour = kf_rgb [3][H][W] at the pixel, opacity logit
+ * 0, identity rotation and log-scale log(z / fx) on every axis - or, when
+ * mlp_out is not NULL, log-scale, opacity logit and colour from row c of
+ * mlp_out [candidates][7] (log-scale 3, opacity logit, RGB 3).  Zeroes the
+ * Adam moments of the new entries (m, v may be NULL), updates
+ * *params->n_dev, and sets GS_STATUS_GAUSSIAN_OVERFLOW in *status_dev when
+ * capacity would be exceeded (nothing past capacity is written).  At most
+ * 9 * n_pts <= 65536 candidates.  n_inserted_dev: device int32 receiving the
  * number kept before the capacity check (may be NULL).
  *   cam  device gs_camera (the keyframe's) */
-GS_API int gs_insert_gaussians(gs_params* params, gs_params* adam_m, gs_params* adam_v,
-                        const gs_camera* cam, int32_t width, int32_t height,
-                        const float* kf_rgb, const float* kf_T_final,
-                        const float* pts_uvd, int32_t n_pts, float alpha_skip,
-                        int32_t centre_only, const float* mlp_out,
-                        int32_t* n_inserted_dev, int32_t* status_dev,
-                        void* stream);
+GS_API int gs_insert_gaussians(gs_params* params, gs_params* adam_m,
+                               gs_params* adam_v, const gs_camera* cam,
+                               int32_t width, int32_t height,
+                               const float* kf_rgb, const float* kf_T_final,
+                               const float* pts_uvd, int32_t n_pts,
+                               float alpha_skip, int32_t centre_only,
+                               const float* mlp_out, int32_t* n_inserted_dev,
+                               int32_t* status_dev, void* stream);
+
+/* Learned initialisation: the parameter vector of the network
+ * (32 -> 64 -> 64 -> 7, GELU) holds GS_MLP_PARAMS FP32 master weights,
+ * W1 [32][64], b1 [64], W2 [64][64], b2 [64], W3 [64][7], b3 [7], each layer
+ * computing z = x W + b.  Weights, inputs and hidden activations are rounded
+ * to BF16 where they enter a product (BF16 MFMA, FP32 accumulate). */
+#define GS_MLP_PARAMS 6727
+#define GS_MLP_IN 32
+#define GS_MLP_OUT 7
+
+/* Features of every insertion candidate (same candidate order as
+ * gs_insert_gaussians), feats [candidates][32] (device FP32): the 3x3 RGB
+ * neighbourhood of the candidate pixel in kf_rgb (27, neighbours row-major,
+ * channels interleaved, 0 outside the image), the inverse depth, the mean
+ * log-distance (m, floor 1e-6) from the back-projected point to its 8
+ * nearest existing Gaussian means (exact search, FP64 distances, ties to the
+ * lower index) and their inverse-distance-weighted mean colour (0 when the
+ * map is empty).  knn_idx / knn_dist [candidates][8] (may be NULL) receive
+ * the neighbours (-1 / 0 past the live count). */
+GS_API int gs_knn_features(const gs_params* params, const gs_camera* cam,
+                           int32_t width, int32_t height, const float* kf_rgb,
+                           const float* pts_uvd, int32_t n_pts,
+                           int32_t centre_only, float* feats, int32_t* knn_idx,
+                           float* knn_dist, void* stream);
+
+/* Forward pass: x [m][32] -> y [m][7].  cache [m][128] (may be NULL)
+ * receives the two hidden pre-activations for gs_mlp_bwd. */
+GS_API int gs_mlp_fwd(const float* weights, const float* x, int32_t m,
+                      float* y, float* cache, void* stream);
+
+/* Mean squared error over the m x 7 outputs: dy = 2 (y - target) / (7 m);
+ * ADDS the loss to *loss_dev (device double, may be NULL). */
+GS_API int gs_mlp_mse(const float* y, const float* target, int32_t m,
+                      float* dy, double* loss_dev, void* stream);
+
+/* Backward pass from dy [m][7]: ACCUMULATES (+=) the gradient of the
+ * parameter vector into dweights [GS_MLP_PARAMS] (caller zeroes it). */
+GS_API int gs_mlp_bwd(const float* weights, const float* x,
+                      const float* cache, const float* dy, int32_t m,
+                      float* dweights, void* stream);
+
+/* Adam step on the parameter vector (step >= 1 for bias correction). */
+GS_API int gs_mlp_adam(float* weights, const float* dweights, float* adam_m,
+                       float* adam_v, float lr, float beta1, float beta2,
+                       float eps, int32_t step, void* stream);
 
 /* Synchronises `stream`, then reads the workspace's status bits and key
  * count (either output may be NULL).  Returns GS_E_OVERFLOW when any status

@@ -92,6 +92,14 @@ _SIGS = {
                                       _P(gs_params), _vp, C.c_int32, C.c_int32,
                                       _vp, _vp, _vp, C.c_int32, C.c_float,
                                       C.c_int32, _vp, _vp, _vp, _vp]),
+    "gs_knn_features": (C.c_int, [_P(gs_params), _vp, C.c_int32, C.c_int32,
+                                  _vp, _vp, C.c_int32, C.c_int32, _vp, _vp,
+                                  _vp, _vp]),
+    "gs_mlp_fwd": (C.c_int, [_vp, _vp, C.c_int32, _vp, _vp, _vp]),
+    "gs_mlp_mse": (C.c_int, [_vp, _vp, C.c_int32, _vp, _vp, _vp]),
+    "gs_mlp_bwd": (C.c_int, [_vp, _vp, _vp, _vp, C.c_int32, _vp, _vp]),
+    "gs_mlp_adam": (C.c_int, [_vp, _vp, _vp, _vp, C.c_float, C.c_float,
+                              C.c_float, C.c_float, C.c_int32, _vp]),
     "gs_read_status": (C.c_int, [_vp, _vp, _P(C.c_int32), _P(C.c_int64),
                                  C.c_int32]),
     "gs_last_error": (C.c_char_p, []),

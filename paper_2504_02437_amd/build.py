@@ -36,6 +36,7 @@ UNITS = [
     ("render_fwd.hip", NO_CONTRACT),
     ("render_bwd.hip", NO_CONTRACT),
     ("optim.hip", []),
+    ("mlp.hip", NO_CONTRACT),
 ]
 
 

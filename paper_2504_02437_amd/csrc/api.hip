@@ -368,6 +368,56 @@ int gs_insert_gaussians(gs_params* params, gs_params* adam_m, gs_params* adam_v,
                               (hipStream_t)stream), "insert_gaussians");
 }
 
+int gs_knn_features(const gs_params* params, const gs_camera* cam,
+                    int32_t width, int32_t height, const float* kf_rgb,
+                    const float* pts_uvd, int32_t n_pts, int32_t centre_only,
+                    float* feats, int32_t* knn_idx, float* knn_dist,
+                    void* stream) {
+  g_err[0] = 0;
+  if (int rc = validate_params(params, "params")) return rc;
+  if (!params->n_dev || !cam || !kf_rgb || !feats) { set_error("an argument is NULL"); return GS_E_INVALID; }
+  if (n_pts < 0 || (long long)n_pts * 9 > 65536) { set_error("need 0 <= n_pts and 9 n_pts <= 65536"); return GS_E_INVALID; }
+  if (n_pts > 0 && !pts_uvd) { set_error("pts_uvd is NULL"); return GS_E_INVALID; }
+  if (width < 1 || height < 1) { set_error("bad image size"); return GS_E_INVALID; }
+  return finish(launch_knn_features(params, cam, width, height, kf_rgb, pts_uvd,
+                                    n_pts, centre_only, feats, knn_idx, knn_dist,
+                                    (hipStream_t)stream), "knn_features");
+}
+
+int gs_mlp_fwd(const float* weights, const float* x, int32_t m, float* y,
+               float* cache, void* stream) {
+  g_err[0] = 0;
+  if (!weights || (m > 0 && (!x || !y))) { set_error("an argument is NULL"); return GS_E_INVALID; }
+  if (m < 0) { set_error("m < 0"); return GS_E_INVALID; }
+  return finish(launch_mlp_fwd(weights, x, m, y, cache, (hipStream_t)stream), "mlp_fwd");
+}
+
+int gs_mlp_mse(const float* y, const float* target, int32_t m, float* dy,
+               double* loss_dev, void* stream) {
+  g_err[0] = 0;
+  if (m > 0 && (!y || !target || !dy)) { set_error("an argument is NULL"); return GS_E_INVALID; }
+  if (m < 0) { set_error("m < 0"); return GS_E_INVALID; }
+  return finish(launch_mlp_mse(y, target, m, dy, loss_dev, (hipStream_t)stream), "mlp_mse");
+}
+
+int gs_mlp_bwd(const float* weights, const float* x, const float* cache,
+               const float* dy, int32_t m, float* dweights, void* stream) {
+  g_err[0] = 0;
+  if (!weights || !dweights || (m > 0 && (!x || !cache || !dy))) { set_error("an argument is NULL"); return GS_E_INVALID; }
+  if (m < 0) { set_error("m < 0"); return GS_E_INVALID; }
+  return finish(launch_mlp_bwd(weights, x, cache, dy, m, dweights, (hipStream_t)stream), "mlp_bwd");
+}
+
+int gs_mlp_adam(float* weights, const float* dweights, float* adam_m,
+                float* adam_v, float lr, float beta1, float beta2, float eps,
+                int32_t step, void* stream) {
+  g_err[0] = 0;
+  if (!weights || !dweights || !adam_m || !adam_v) { set_error("an argument is NULL"); return GS_E_INVALID; }
+  if (step < 1) { set_error("step must be >= 1"); return GS_E_INVALID; }
+  return finish(launch_mlp_adam(weights, dweights, adam_m, adam_v, lr, beta1, beta2,
+                                eps, step, (hipStream_t)stream), "mlp_adam");
+}
+
 int gs_read_status(gs_workspace* ws, void* stream, int32_t* flags,
                    int64_t* n_keys, int32_t clear) {
   g_err[0] = 0;

@@ -29,6 +29,21 @@ struct Counters {
   int pad;
 };
 
+hipError_t launch_knn_features(const gs_params* p, const gs_camera* cam, int W,
+                               int H, const float* kf_rgb, const float* pts,
+                               int n_pts, int centre_only, float* feats,
+                               int32_t* knn_idx, float* knn_dist,
+                               hipStream_t st);
+hipError_t launch_mlp_fwd(const float* w, const float* x, int M, float* y,
+                          float* cache, hipStream_t st);
+hipError_t launch_mlp_bwd(const float* w, const float* x, const float* cache,
+                          const float* dy, int M, float* dw, hipStream_t st);
+hipError_t launch_mlp_mse(const float* y, const float* t, int M, float* dy,
+                          double* loss, hipStream_t st);
+hipError_t launch_mlp_adam(float* w, const float* g, float* m, float* v,
+                           float lr, float b1, float b2, float eps, int step,
+                           hipStream_t st);
+
 }  // namespace gs
 
 struct gs_workspace {
@@ -93,5 +108,20 @@ hipError_t launch_insert(gs_params* p, gs_params* m, gs_params* v,
                          const float* pts, int n_pts, float alpha_skip,
                          int centre_only, const float* mlp_out,
                          int32_t* n_inserted, int32_t* status, hipStream_t st);
+
+hipError_t launch_knn_features(const gs_params* p, const gs_camera* cam, int W,
+                               int H, const float* kf_rgb, const float* pts,
+                               int n_pts, int centre_only, float* feats,
+                               int32_t* knn_idx, float* knn_dist,
+                               hipStream_t st);
+hipError_t launch_mlp_fwd(const float* w, const float* x, int M, float* y,
+                          float* cache, hipStream_t st);
+hipError_t launch_mlp_bwd(const float* w, const float* x, const float* cache,
+                          const float* dy, int M, float* dw, hipStream_t st);
+hipError_t launch_mlp_mse(const float* y, const float* t, int M, float* dy,
+                          double* loss, hipStream_t st);
+hipError_t launch_mlp_adam(float* w, const float* g, float* m, float* v,
+                           float lr, float b1, float b2, float eps, int step,
+                           hipStream_t st);
 
 }  // namespace gs

@@ -203,7 +203,7 @@ __global__ __launch_bounds__(kInsThreads) void k_insert(InsertArgs a) {
           a.rows[i][dst] = (float)sacc;
         }
         if (a.mlp_out) {
-          const float* o = a.mlp_out + 7 * (size_t)patch;
+          const float* o = a.mlp_out + 7 * (size_t)c;
           for (int i = 0; i < 3; ++i) a.rows[3 + i][dst] = o[i];
           a.rows[10][dst] = o[3];
           for (int i = 0; i < 3; ++i) a.rows[11 + i][dst] = o[4 + i];

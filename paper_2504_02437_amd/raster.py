@@ -307,6 +307,37 @@ def insert_gaussians(params, m, v, cam_dev, width, height, kf_rgb, kf_T, pts,
            _ptr(n_inserted_dev), _ptr(status_dev), _stream(stream))
 
 
+def knn_features(params, cam_dev, width, height, kf_rgb, pts, centre_only,
+                 feats, knn_idx=None, knn_dist=None, stream=None):
+    n_pts = 0 if pts is None else pts.shape[0]
+    L.call("gs_knn_features", C.byref(params.struct()), _ptr(cam_dev),
+           int(width), int(height), _ptr(kf_rgb), _ptr(pts), n_pts,
+           1 if centre_only else 0, _ptr(feats), _ptr(knn_idx),
+           _ptr(knn_dist), _stream(stream))
+
+
+def mlp_fwd(weights, x, y, cache=None, stream=None):
+    L.call("gs_mlp_fwd", _ptr(weights), _ptr(x), int(x.shape[0]), _ptr(y),
+           _ptr(cache), _stream(stream))
+
+
+def mlp_mse(y, target, dy, loss_dev=None, stream=None):
+    L.call("gs_mlp_mse", _ptr(y), _ptr(target), int(y.shape[0]), _ptr(dy),
+           _ptr(loss_dev), _stream(stream))
+
+
+def mlp_bwd(weights, x, cache, dy, dweights, stream=None):
+    L.call("gs_mlp_bwd", _ptr(weights), _ptr(x), _ptr(cache), _ptr(dy),
+           int(x.shape[0]), _ptr(dweights), _stream(stream))
+
+
+def mlp_adam(weights, dweights, m, v, lr, beta1, beta2, eps, step,
+             stream=None):
+    L.call("gs_mlp_adam", _ptr(weights), _ptr(dweights), _ptr(m), _ptr(v),
+           float(lr), float(beta1), float(beta2), float(eps), int(step),
+           _stream(stream))
+
+
 def read_status(ws, stream=None, clear=False):
     flags = C.c_int32()
     nk = C.c_int64()
