@@ -111,3 +111,145 @@ def targets_from_params(data_rows):
     descending, opacity logit, RGB."""
     ls = np.sort(data_rows[3:6], axis=0)[::-1]
     return np.concatenate([ls, data_rows[10:11], data_rows[11:14]], 0).T.copy()
+
+
+# ---------------------------------------------------------------------------
+# Training data from the plain mapper, training, and evaluation.
+# ---------------------------------------------------------------------------
+
+def _stream(seed, n_kf, width, height, f, n_gt):
+    import synth
+    return synth.mapping_stream(seed, n_kf, width, height, f, n_gt)
+
+
+def collect_pairs(seed, n_kf=40, width=320, height=240, f=260.0,
+                  n_gt=100_000, iters_per_kf=10, window=10, device="cuda",
+                  log=None):
+    """Runs the plain mapper (heuristic initialisation) over one synthetic
+    keyframe stream and returns (features [N][32], targets [N][7]) of every
+    Gaussian it inserted: the features at insertion time and its parameters
+    at the end of the run (log-scales sorted descending, opacity logit,
+    RGB)."""
+    from .mapper import Mapper, render_images
+    st = _stream(seed, n_kf, width, height, f, n_gt)
+    imgs = render_images(st.gt, st.cameras, device)
+    mp = Mapper(capacity=n_kf * 9 * st.pts[0].shape[0], width=width,
+                height=height, window=window, device=device)
+    feats, ids = [], []
+    for i, cam in enumerate(st.cameras):
+        info = mp.add_keyframe(cam, imgs[i], st.pts[i], features=True)
+        kept = torch.from_numpy(info["kept"]).to(device)
+        k = int(info["kept"].sum())
+        n_ins = info["n_after"] - info["n_before"]
+        if k != n_ins:
+            raise RuntimeError(f"kept mask {k} != inserted {n_ins}")
+        feats.append(info["feats"][kept])
+        ids.append(torch.arange(info["n_before"], info["n_after"], device=device))
+        mp.optimise(iters_per_kf)
+        if log and (i + 1) % 10 == 0:
+            log(f"collect seed {seed}: kf {i + 1}/{n_kf}, map {mp.params.n()}, "
+                f"psnr {mp.psnr():.2f}")
+    ids = torch.cat(ids)
+    rows = mp.params.data[:, ids]
+    ls = torch.sort(rows[3:6], dim=0, descending=True).values
+    t = torch.cat([ls, rows[10:11], rows[11:14]], 0).T.contiguous()
+    return torch.cat(feats).contiguous(), t
+
+
+def run_window(seed, mlp=None, n_kf=10, width=320, height=240, f=260.0,
+               n_gt=100_000, iters_per_kf=5, extra_iters=100, eval_every=5,
+               device="cuda"):
+    """Maps a keyframe window with heuristic (mlp=None) or learned
+    initialisation; returns the window PSNR curve over iterations."""
+    from .mapper import Mapper, render_images
+    st = _stream(seed, n_kf, width, height, f, n_gt)
+    imgs = render_images(st.gt, st.cameras, device)
+    mp = Mapper(capacity=n_kf * 9 * st.pts[0].shape[0], width=width,
+                height=height, window=n_kf, device=device)
+    curve = []
+    for i, cam in enumerate(st.cameras):
+        mp.add_keyframe(cam, imgs[i], st.pts[i], mlp=mlp)
+        mp.optimise(iters_per_kf)
+    cams = st.cameras
+    full = imgs.contiguous()
+    curve.append((mp.iterations, mp.psnr(cams, full)))
+    for _ in range(0, extra_iters, eval_every):
+        mp.optimise(eval_every)
+        curve.append((mp.iterations, mp.psnr(cams, full)))
+    return dict(curve=curve, gaussians=mp.params.n())
+
+
+def iterations_to_reach(curve, target):
+    for it, p in curve:
+        if p >= target:
+            return it
+    return None
+
+
+def experiment(train_seeds=range(16), eval_seeds=(1000, 1001, 1002),
+               n_kf=40, epochs=30, iters_per_kf=10, width=320, height=240,
+               f=260.0, n_gt=100_000, eval_kf=10, device="cuda", log=None):
+    """Collects pairs from the plain mapper on the training seeds, trains the
+    network, and compares heuristic vs learned initialisation on the held-out
+    seeds over an ``eval_kf``-keyframe window.  Returns (results, network)."""
+    X, T = [], []
+    for s in train_seeds:
+        x, t = collect_pairs(s, n_kf=n_kf, width=width, height=height, f=f,
+                             n_gt=n_gt, iters_per_kf=iters_per_kf,
+                             device=device, log=log)
+        X.append(x)
+        T.append(t)
+        if log:
+            log(f"seed {s}: {x.shape[0]} pairs")
+    X = torch.cat(X)
+    T = torch.cat(T)
+    net = InitMLP(device=device)
+    net.fit_normalisation(X, T)
+    hist = net.train(X, T, epochs=epochs, batch=8192, lr=1e-3, log=log)
+    res = dict(pairs=int(X.shape[0]), train_loss=hist, evals=[],
+               setup=dict(width=width, height=height, f=f, n_gt=n_gt,
+                          train_seeds=list(train_seeds), n_kf=n_kf,
+                          iters_per_kf=iters_per_kf, epochs=epochs,
+                          eval_seeds=list(eval_seeds), eval_kf=eval_kf))
+    for s in eval_seeds:
+        h = run_window(s, None, n_kf=eval_kf, width=width, height=height,
+                       f=f, n_gt=n_gt, device=device)
+        m = run_window(s, net, n_kf=eval_kf, width=width, height=height,
+                       f=f, n_gt=n_gt, device=device)
+        ch, cm = h["curve"], m["curve"]
+        ev = dict(seed=s, heuristic=ch, learned=cm)
+        # Iterations the heuristic needs to reach the learned PSNR at each
+        # point of the learned curve.
+        ev["equal_psnr"] = [(it, p, iterations_to_reach(ch, p)) for it, p in cm]
+        res["evals"].append(ev)
+        if log:
+            log(f"eval seed {s}: heuristic {ch[0][1]:.2f} -> {ch[-1][1]:.2f} dB, "
+                f"learned {cm[0][1]:.2f} -> {cm[-1][1]:.2f} dB")
+    return res, net
+
+
+def main(argv=None):
+    import argparse
+    import json
+    import sys
+    ap = argparse.ArgumentParser(description="learned-initialisation experiment")
+    ap.add_argument("--train-seeds", type=int, default=16)
+    ap.add_argument("--n-kf", type=int, default=40)
+    ap.add_argument("--epochs", type=int, default=30)
+    ap.add_argument("--width", type=int, default=320)
+    ap.add_argument("--height", type=int, default=240)
+    ap.add_argument("--f", type=float, default=260.0)
+    ap.add_argument("--n-gt", type=int, default=100_000)
+    ap.add_argument("--save", default="")
+    a = ap.parse_args(argv)
+    lg = lambda *x: print(*x, file=sys.stderr, flush=True)
+    res, net = experiment(train_seeds=range(a.train_seeds), n_kf=a.n_kf,
+                          epochs=a.epochs, width=a.width, height=a.height,
+                          f=a.f, n_gt=a.n_gt, log=lg)
+    if a.save:
+        np.savez(a.save, **net.state())
+    print(json.dumps(res))
+
+
+if __name__ == "__main__":
+    main()

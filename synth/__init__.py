@@ -1,10 +1,12 @@
 """Seeded synthetic workloads (random numbers and array layout only)."""
-from .scenes import (Camera, Gaussians, KeyframePoints, Workload, config0,
+from .scenes import (Camera, Gaussians, KeyframePoints, MappingStream,
+                     Workload, config0, mapping_stream, wall_depth,
                      config1, config2, config3_crop, frustum_gaussians,
                      identity_camera, insertion_stream, random_walk_poses,
                      room_camera, room_gaussians, tiny_scene, uniform_targets)
 
-__all__ = ["Camera", "Gaussians", "KeyframePoints", "Workload", "config0",
+__all__ = ["Camera", "Gaussians", "KeyframePoints", "MappingStream",
+           "Workload", "config0", "mapping_stream", "wall_depth",
            "config1", "config2", "config3_crop", "frustum_gaussians",
            "identity_camera", "insertion_stream", "random_walk_poses",
            "room_camera", "room_gaussians", "tiny_scene", "uniform_targets"]

@@ -296,3 +296,54 @@ def tiny_scene(seed: int, n: int = 40, width: int = 33, height: int = 29,
     g.log_scale[:] = rng.normal(log_scale_mu, 0.4, size=(3, n)).astype(np.float32)
     tgt = uniform_targets(rng, 1, width, height)
     return Workload(f"tiny{width}x{height}-{n}", g, [cam], tgt)
+
+
+# ---------------------------------------------------------------------------
+# Synthetic visual-odometry stand-in for mapping runs.
+# ---------------------------------------------------------------------------
+
+def wall_depth(cam: Camera, u, v):
+    """Camera-space depth z at which the rays through pixels (u, v) leave the
+    room box (the true surface depth of the room's walls)."""
+    R = np.asarray(cam.R, np.float64)
+    t = np.asarray(cam.t, np.float64)
+    centre = -R.T @ t
+    u = np.asarray(u, np.float64)
+    v = np.asarray(v, np.float64)
+    dirs_cam = np.stack([(u - cam.cx) / cam.fx, (v - cam.cy) / cam.fy,
+                         np.ones_like(u)])                      # z = 1
+    dirs = R.T @ dirs_cam                                       # world
+    with np.errstate(divide="ignore", invalid="ignore"):
+        tx = np.where(dirs > 0, (ROOM_HI[:, None] - centre[:, None]) / dirs,
+                      np.where(dirs < 0,
+                               (ROOM_LO[:, None] - centre[:, None]) / dirs,
+                               np.inf))
+    return tx.min(0)                 # ray parameter = camera z (dirs_cam z = 1)
+
+
+@dataclass
+class MappingStream:
+    cameras: list            # keyframe cameras
+    pts: list                # per keyframe float32 [K][3] (u, v, inverse depth)
+    gt: Gaussians            # ground-truth scene the keyframe images show
+
+
+def mapping_stream(seed: int, n_kf: int, width: int = 320, height: int = 240,
+                   f: float = 260.0, n_gt: int = 100_000, n_patches: int = 96,
+                   wall_frac: float = 1.0, config_id: int = 4):
+    """A mapping run: keyframes on the random walk, a ground-truth room scene
+    to render their images from, and per keyframe ``n_patches`` patch centres
+    (integer pixels, the 3x3 patch inside the image) with the true inverse
+    depth of the wall they see."""
+    rng = _rng(config_id, seed)
+    gt = room_gaussians(rng, n_gt, wall_frac=wall_frac)
+    cams, pts = [], []
+    for R, t in random_walk_poses(rng, n_kf):
+        cam = Camera(R, t, f, f, (width - 1) / 2.0, (height - 1) / 2.0,
+                     width, height)
+        u = rng.integers(1, width - 1, size=n_patches)
+        v = rng.integers(1, height - 1, size=n_patches)
+        z = wall_depth(cam, u, v)
+        cams.append(cam)
+        pts.append(np.stack([u, v, 1.0 / z], 1).astype(np.float32))
+    return MappingStream(cams, pts, gt)
