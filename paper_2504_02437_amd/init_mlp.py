@@ -100,6 +100,19 @@ class InitMLP:
                 log(f"init_mlp: epoch {ep + 1}/{epochs} loss {hist[-1]:.4f}")
         return hist
 
+    @classmethod
+    def load(cls, path=None, device="cuda"):
+        """A network saved with np.savez(**state()); by default the one
+        trained on 2M pairs from 1200x680 plain-mapper runs."""
+        import os
+        path = path or os.path.join(os.path.dirname(os.path.abspath(__file__)),
+                                    "data", "init_mlp_1200x680.npz")
+        d = np.load(path)
+        net = cls(weights=d["w"], device=device)
+        for k in ("x_mu", "x_sd", "t_mu", "t_sd"):
+            setattr(net, k, torch.from_numpy(d[k]).to(device))
+        return net
+
     def state(self):
         return dict(w=self.w.cpu().numpy(), x_mu=self.x_mu.cpu().numpy(),
                     x_sd=self.x_sd.cpu().numpy(), t_mu=self.t_mu.cpu().numpy(),

@@ -75,4 +75,4 @@ def test_crop_gradients_against_fp64_finite_differences():
                 assert abs(an - fd) <= tol, (k, r, g_idx, an, fd)
                 checked += 1
     print("checked", checked, "partial derivatives", flush=True)
-    assert checked >= 272 * 14
+    assert checked == 14 * len(chosen) and len(chosen) >= 256
