@@ -1,15 +1,16 @@
 // Pieces shared by the forward and backward compositing kernels.
 //
 // Both kernels stage records into LDS with stage() and evaluate (pixel,
-// entry) pairs with lane_prep() + pixel_alpha(); compiled without FMA
-// contraction (FMAs are written explicitly), both therefore take
-// bit-identical admit / clamp / stop decisions.
+// entry) pairs with column() + exponent2(); compiled without FMA contraction
+// (FMAs are written explicitly), both therefore take bit-identical admit /
+// clamp / stop decisions.
 //
-// Pixel ownership: a tile of TILE x TILE pixels is served by NT threads laid
-// out as TILE columns x (NT / TILE) row groups; each thread owns a vertical
-// strip of PPT = TILE * TILE / NT consecutive pixels of one column.  The
-// pixels of a strip share their column, so the x-offset terms of the
-// exponent are formed once per (entry, thread).
+// Pixel ownership: each of the NT threads of a tile owns a vertical strip of
+// PPT = TILE * TILE / NT consecutive pixels of one column.  The pixels of a
+// strip share their column, so the x-offset terms of the exponent are formed
+// once per (entry, thread).  The 64 lanes of a wave cover a footprint of WC
+// columns x FH rows that is as square as the tile allows (16 x 16 for PPT 4),
+// which keeps a Gaussian's box test coherent across the wave.
 #pragma once
 
 #include "gs_internal.h"
@@ -23,6 +24,28 @@ struct __align__(16) Entry {
   float4 b;   // C2, opacity, r, g
   float4 c;   // b, A, B, C (unscaled conic, for the backward)
   int4 box;   // u_lo, u_hi, v_lo, v_hi
+};
+
+template <int TILE, int NT>
+struct PixLayout {
+  static constexpr int PPT = TILE * TILE / NT;
+  static constexpr int WC = PPT == 1 ? 8 : (TILE < 16 ? TILE : 16);
+  static constexpr int FH = (64 / WC) * PPT;  // footprint rows of one wave
+  static constexpr int WPR = TILE / WC;       // waves side by side
+  static_assert(NT % 64 == 0 && WPR * (TILE / FH) == NT / 64 &&
+                    TILE % FH == 0,
+                "wave footprints must tile the tile");
+  // Column and first row of thread tid's strip, relative to the tile.
+  __device__ static void of(int tid, int& cu, int& cv0) {
+    const int w = tid >> 6, l = tid & 63;
+    cu = (w % WPR) * WC + l % WC;
+    cv0 = (w / WPR) * FH + (l / WC) * PPT;
+  }
+  // Top-left pixel of the footprint of wave w, relative to the tile.
+  __device__ static void wave_origin(int w, int& wu, int& wv) {
+    wu = (w % WPR) * WC;
+    wv = (w / WPR) * FH;
+  }
 };
 
 constexpr float kHalfLog2e = -0.72134752044448170368f;  // -log2(e) / 2
@@ -39,34 +62,25 @@ __device__ __forceinline__ void stage(Entry& E, const Record& R) {
 
 // Column part of the exponent for one (entry, thread): dx and the terms that
 // depend on dx only.
-struct Lane {
+struct Column {
   float dx, a0, b0;
-  bool in_u;
 };
 
-__device__ __forceinline__ Lane lane_prep(const Entry& E, int u) {
-  Lane L;
-  L.in_u = u >= E.box.x && u <= E.box.y;
-  L.dx = E.a.x - (float)u;
-  L.a0 = (E.a.z * L.dx) * L.dx;   // A2 dx^2
-  L.b0 = E.a.w * L.dx;            // B2 dx
-  return L;
+__device__ __forceinline__ Column column(const float4& ea, float uf) {
+  Column c;
+  c.dx = ea.x - uf;
+  c.a0 = (ea.z * c.dx) * c.dx;   // A2 dx^2
+  c.b0 = ea.w * c.dx;            // B2 dx
+  return c;
 }
 
-__device__ __forceinline__ bool in_v(const Entry& E, int v) {
-  return v >= E.box.z && v <= E.box.w;
-}
-
-// alpha = min(alpha_max, opacity * exp2(e2)) for the pixel in row v of the
-// thread's column; e2 > 0 happens only by rounding and the caller skips it.
-__device__ __forceinline__ float pixel_alpha(const Entry& E, const Lane& L,
-                                             int v, float alpha_max, float& dy,
-                                             float& G, float& e2, float& oG) {
-  dy = E.a.y - (float)v;
-  e2 = fmaf(E.b.x * dy, dy, fmaf(L.b0, dy, L.a0));
-  G = __builtin_amdgcn_exp2f(e2);
-  oG = E.b.y * G;
-  return fminf(alpha_max, oG);
+// Base-2 exponent of the Gaussian at the pixel in row vf of the thread's
+// column: e2 = A2 dx^2 + B2 dx dy + C2 dy^2.  e2 > 0 happens only by
+// rounding; the callers skip such pairs.
+__device__ __forceinline__ float exponent2(const Column& c, float py, float C2,
+                                           float vf, float& dy) {
+  dy = py - vf;
+  return fmaf(C2 * dy, dy, fmaf(c.b0, dy, c.a0));
 }
 
 struct RasterArgs {

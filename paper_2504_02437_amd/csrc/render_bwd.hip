@@ -54,11 +54,20 @@ __device__ __forceinline__ float lane63(float x) {
   return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(x), 63));
 }
 
+__device__ __forceinline__ int wave_max(int x) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) x = max(x, __shfl_xor(x, off, 64));
+  return x;
+}
+
+// The per-pixel work is predicated like the forward's: every lane evaluates
+// its pixels for each entry and the admit decision selects what is
+// accumulated.  A wave starts its backward walk at the largest n_last of its
+// own pixels and skips entries whose box misses its footprint.
 template <int TILE, int BATCH, int NT>
 __global__ __launch_bounds__(NT) void k_render_bwd(BwdArgs a) {
-  constexpr int GROUPS = NT / TILE;
-  constexpr int PPT = TILE / GROUPS;
-  static_assert(GROUPS * PPT == TILE, "thread layout must tile the tile");
+  using Lay = PixLayout<TILE, NT>;
+  constexpr int PPT = Lay::PPT;
   __shared__ Entry ent[BATCH];
   __shared__ float acc[BATCH][9];
   __shared__ uint32_t gid[BATCH];
@@ -75,15 +84,23 @@ __global__ __launch_bounds__(NT) void k_render_bwd(BwdArgs a) {
   tile_range(r, t, s, e);
   const size_t HW = (size_t)r.H * r.W;
 
-  const int u = tx * TILE + (tid % TILE);
-  const int v0 = ty * TILE + (tid / TILE) * PPT;
+  int cu, cv0, wu, wv;
+  Lay::of(tid, cu, cv0);
+  Lay::wave_origin(tid >> 6, wu, wv);
+  const int u = tx * TILE + cu;
+  const int v0 = ty * TILE + cv0;
+  const int fu0 = tx * TILE + wu, fu1 = fu0 + Lay::WC - 1;
+  const int fv0 = ty * TILE + wv, fv1 = fv0 + Lay::FH - 1;
+  const float uf = (float)u;
+  const float amax = r.alpha_max, amin = r.alpha_min;
   int last[PPT];
-  float T[PPT], g0[PPT], g1[PPT], g2[PPT], Tb[PPT], Sg[PPT];
+  float T[PPT], g0[PPT], g1[PPT], g2[PPT], Tb[PPT], Sg[PPT], vf[PPT];
   int mylast = 0;
 #pragma unroll
   for (int p = 0; p < PPT; ++p) {
     const int v = v0 + p;
     last[p] = 0;
+    vf[p] = (float)v;
     T[p] = 1.f; g0[p] = g1[p] = g2[p] = 0.f; Tb[p] = 0.f; Sg[p] = 0.f;
     if (u < r.W && v < r.H) {
       const size_t pix = (size_t)v * r.W + u;
@@ -99,6 +116,7 @@ __global__ __launch_bounds__(NT) void k_render_bwd(BwdArgs a) {
   if (tid == 0) smax = 0;
   __syncthreads();
   atomicMax(&smax, mylast);
+  const int wlast = wave_max(mylast);
   __syncthreads();
   const int maxlast = (int)min((long long)smax, e - s);
   const Record* rv = r.rec + (size_t)k * r.cap;
@@ -115,45 +133,52 @@ __global__ __launch_bounds__(NT) void k_render_bwd(BwdArgs a) {
     }
     for (int i = tid; i < cnt * 9; i += NT) (&acc[0][0])[i] = 0.f;
     __syncthreads();
-    for (int j = cnt - 1; j >= 0; --j) {
+    for (int j = min(cnt, wlast - lo) - 1; j >= 0; --j) {
       const int pos = lo + j;
-      const Entry& E = ent[j];
-      const Lane L = lane_prep(E, u);
+      const int4 box = ent[j].box;
+      if (box.y < fu0 || box.x > fu1 || box.w < fv0 || box.z > fv1) continue;
+      const float4 ea = ent[j].a;
+      const float4 eb = ent[j].b;
+      const float4 ec = ent[j].c;
+      const bool in_u = u >= box.x && u <= box.y;
+      const int rlo = box.z - v0, rhi = box.w - v0;
+      const Column col = column(ea, uf);
       float d_o = 0.f, d_r = 0.f, d_g = 0.f, d_b = 0.f;
       float S0 = 0.f, S1 = 0.f, S2 = 0.f;
       bool hit = false;
-      if (L.in_u) {
 #pragma unroll
-        for (int p = 0; p < PPT; ++p) {
-          if (pos >= last[p] || !in_v(E, v0 + p)) continue;
-          float dy, G, e2, oG;
-          const float al =
-              pixel_alpha(E, L, v0 + p, r.alpha_max, dy, G, e2, oG);
-          if (e2 > 0.f || al < r.alpha_min) continue;
-          hit = true;
-          const float rom = __builtin_amdgcn_rcpf(1.f - al);
-          T[p] = T[p] * rom;                       // T_i
-          const float w = al * T[p];
-          d_r = fmaf(w, g0[p], d_r);
-          d_g = fmaf(w, g1[p], d_g);
-          d_b = fmaf(w, g2[p], d_b);
-          const float cg =
-              fmaf(E.b.z, g0[p], fmaf(E.b.w, g1[p], E.c.x * g2[p]));
-          const float diff = cg - Sg[p];
-          const float dal = fmaf(T[p], diff, -(Tb[p] * rom));
-          Sg[p] = fmaf(al, diff, Sg[p]);
-          if (oG > r.alpha_max) continue;          // clamped: no shape gradient
-          const float dpw = dal * al;
-          d_o = fmaf(dal, G, d_o);
-          const float tdy = dpw * dy;
-          S0 += dpw;
-          S1 += tdy;
-          S2 = fmaf(tdy, dy, S2);
-        }
+      for (int p = 0; p < PPT; ++p) {
+        float dy;
+        const float e2 = exponent2(col, ea.y, eb.x, vf[p], dy);
+        const float G = __builtin_amdgcn_exp2f(e2);
+        const float oG = eb.y * G;
+        const float al = fminf(amax, oG);
+        const bool ok = in_u && rlo <= p && p <= rhi && pos < last[p] &&
+                        !(e2 > 0.f) && al >= amin;
+        hit |= ok;
+        const float rom = __builtin_amdgcn_rcpf(1.f - al);
+        const float Ti = T[p] * rom;                 // T_i
+        T[p] = ok ? Ti : T[p];
+        const float w = ok ? al * Ti : 0.f;
+        d_r = fmaf(w, g0[p], d_r);
+        d_g = fmaf(w, g1[p], d_g);
+        d_b = fmaf(w, g2[p], d_b);
+        const float cg = fmaf(eb.z, g0[p], fmaf(eb.w, g1[p], ec.x * g2[p]));
+        const float diff = cg - Sg[p];
+        const float dal = fmaf(Ti, diff, -(Tb[p] * rom));
+        Sg[p] = ok ? fmaf(al, diff, Sg[p]) : Sg[p];
+        // Clamped alpha has no shape or opacity gradient.
+        const float dalm = (ok && !(oG > amax)) ? dal : 0.f;
+        const float dpw = dalm * al;
+        d_o = fmaf(dalm, G, d_o);
+        const float tdy = dpw * dy;
+        S0 += dpw;
+        S1 += tdy;
+        S2 = fmaf(tdy, dy, S2);
       }
       if (__any(hit)) {
-        const float A = E.c.y, B = E.c.z, C = E.c.w, dx = L.dx;
-        const float dxS0 = dx * S0;
+        const float A = ec.y, B = ec.z, C = ec.w;
+        const float dx = col.dx, dxS0 = dx * S0;
         const float d_px = -fmaf(A, dxS0, B * S1);
         const float d_py = -fmaf(C, S1, B * dxS0);
         const float d_A = -0.5f * dx * dxS0;

@@ -25,11 +25,18 @@ struct FwdArgs {
 // COUNT = true is the work-counting variant: the same walk and decisions,
 // adding up examined / in-box / contributing / revisited pairs instead of
 // writing the image.
+//
+// A pixel's transmittance is kept with its sign as the liveness flag: a
+// pixel that stopped holds -T, so "still compositing" is one compare and the
+// output is |T|.  T >= T_min > 0 holds for every accepted step, so a live
+// pixel's T is never zero.  The per-pixel work is predicated rather than
+// branched: every lane evaluates alpha for each of its pixels and the
+// decisions select what is accumulated.  A wave skips an entry outright when
+// the Gaussian's box misses the wave's footprint.
 template <int TILE, int BATCH, int NT, bool COUNT>
 __global__ __launch_bounds__(NT) void k_render_fwd(FwdArgs a) {
-  constexpr int GROUPS = NT / TILE;
-  constexpr int PPT = TILE / GROUPS;
-  static_assert(GROUPS * PPT == TILE, "thread layout must tile the tile");
+  using Lay = PixLayout<TILE, NT>;
+  constexpr int PPT = Lay::PPT;
   __shared__ Entry ent[BATCH];
   const RasterArgs& r = a.r;
   const int t = blockIdx.x;
@@ -41,65 +48,88 @@ __global__ __launch_bounds__(NT) void k_render_fwd(FwdArgs a) {
   long long s, e;
   tile_range(r, t, s, e);
 
-  const int u = tx * TILE + (tid % TILE);
-  const int v0 = ty * TILE + (tid / TILE) * PPT;
+  int cu, cv0, wu, wv;
+  Lay::of(tid, cu, cv0);
+  Lay::wave_origin(tid >> 6, wu, wv);
+  const int u = tx * TILE + cu;
+  const int v0 = ty * TILE + cv0;
+  // The wave's footprint: an entry whose box misses it is skipped by the
+  // whole wave.
+  const int fu0 = tx * TILE + wu, fu1 = fu0 + Lay::WC - 1;
+  const int fv0 = ty * TILE + wv, fv1 = fv0 + Lay::FH - 1;
+  const float uf = (float)u;
+  const float amax = __builtin_canonicalizef(r.alpha_max);
+  const float amin = r.alpha_min, tmin = r.T_min;
   int last[PPT];
-  float T[PPT], C0[PPT], C1[PPT], C2[PPT];
-  bool done[PPT];
+  float T[PPT], C0[PPT], C1[PPT], C2[PPT], vf[PPT];
   unsigned n_exam = 0, n_inbox = 0, n_contrib = 0;
   unsigned ib[PPT], ib_last[PPT];
 #pragma unroll
   for (int p = 0; p < PPT; ++p) {
-    done[p] = !(u < r.W && v0 + p < r.H);
-    T[p] = 1.f;
+    T[p] = (u < r.W && v0 + p < r.H) ? 1.f : -1.f;
     C0[p] = C1[p] = C2[p] = 0.f;
     last[p] = 0;
+    vf[p] = (float)(v0 + p);
     ib[p] = ib_last[p] = 0;
   }
   const Record* rv = r.rec + (size_t)k * r.cap;
   for (long long b0 = s; b0 < e; b0 += BATCH) {
     int alive = 0;
 #pragma unroll
-    for (int p = 0; p < PPT; ++p) alive |= !done[p];
+    for (int p = 0; p < PPT; ++p) alive |= T[p] > 0.f;
     if (__syncthreads_or(alive) == 0) break;
     const int cnt = (int)min((long long)BATCH, e - b0);
     for (int i = tid; i < cnt; i += NT) stage(ent[i], rv[r.vals[b0 + i]]);
     __syncthreads();
     const int base = (int)(b0 - s);
     for (int j = 0; j < cnt; ++j) {
-      bool any = false;
+      if ((j & 7) == 0) {
+        bool any = false;
 #pragma unroll
-      for (int p = 0; p < PPT; ++p) any |= !done[p];
-      if (!__any(any)) break;
-      const Entry& E = ent[j];
-      const Lane L = lane_prep(E, u);
+        for (int p = 0; p < PPT; ++p) any |= T[p] > 0.f;
+        if (!__any(any)) break;
+      }
+      const int4 box = ent[j].box;
       if (COUNT) {
 #pragma unroll
         for (int p = 0; p < PPT; ++p) {
-          if (done[p]) continue;
+          if (!(T[p] > 0.f)) continue;
           ++n_exam;
-          if (L.in_u && in_v(E, v0 + p)) { ++n_inbox; ++ib[p]; }
+          if (u >= box.x && u <= box.y && v0 + p >= box.z && v0 + p <= box.w) {
+            ++n_inbox;
+            ++ib[p];
+          }
         }
       }
-      if (!L.in_u) continue;
+      if (box.y < fu0 || box.x > fu1 || box.w < fv0 || box.z > fv1) continue;
+      const float4 ea = ent[j].a;
+      const float4 eb = ent[j].b;
+      const float ecb = ent[j].c.x;
+      const bool in_u = u >= box.x && u <= box.y;
+      const int lo = box.z - v0, hi = box.w - v0;
+      const Column col = column(ea, uf);
+      const int idx = base + j + 1;
 #pragma unroll
       for (int p = 0; p < PPT; ++p) {
-        if (done[p] || !in_v(E, v0 + p)) continue;
-        float dy, G, e2, oG;
-        const float al = pixel_alpha(E, L, v0 + p, r.alpha_max, dy, G, e2, oG);
-        if (e2 > 0.f || al < r.alpha_min) continue;
+        float dy;
+        const float e2 = exponent2(col, ea.y, eb.x, vf[p], dy);
+        const float G = __builtin_amdgcn_exp2f(e2);
+        const float al = fminf(amax, eb.y * G);
+        const bool ok = in_u && lo <= p && p <= hi && T[p] > 0.f &&
+                        !(e2 > 0.f) && al >= amin;
         const float Tn = T[p] * (1.f - al);
-        if (Tn < r.T_min) {
-          done[p] = true;
-          continue;
+        const bool con = ok && Tn >= tmin;
+        const bool stop = ok && !(Tn >= tmin);
+        const float w = con ? al * T[p] : 0.f;
+        C0[p] = fmaf(eb.z, w, C0[p]);
+        C1[p] = fmaf(eb.w, w, C1[p]);
+        C2[p] = fmaf(ecb, w, C2[p]);
+        T[p] = con ? Tn : (stop ? -T[p] : T[p]);
+        last[p] = con ? idx : last[p];
+        if (COUNT) {
+          n_contrib += con;
+          ib_last[p] = con ? ib[p] : ib_last[p];
         }
-        const float w = al * T[p];
-        C0[p] = fmaf(E.b.z, w, C0[p]);
-        C1[p] = fmaf(E.b.w, w, C1[p]);
-        C2[p] = fmaf(E.c.x, w, C2[p]);
-        T[p] = Tn;
-        last[p] = base + j + 1;
-        if (COUNT) { ++n_contrib; ib_last[p] = ib[p]; }
       }
     }
   }
@@ -120,11 +150,12 @@ __global__ __launch_bounds__(NT) void k_render_fwd(FwdArgs a) {
   for (int p = 0; p < PPT; ++p) {
     const int v = v0 + p;
     if (!(u < r.W && v < r.H)) continue;
+    const float Tf = fabsf(T[p]);
     const size_t pix = (size_t)v * r.W + u;
-    a.rgb[((size_t)k * 3 + 0) * HW + pix] = fmaf(T[p], r.bg0, C0[p]);
-    a.rgb[((size_t)k * 3 + 1) * HW + pix] = fmaf(T[p], r.bg1, C1[p]);
-    a.rgb[((size_t)k * 3 + 2) * HW + pix] = fmaf(T[p], r.bg2, C2[p]);
-    a.T[(size_t)k * HW + pix] = T[p];
+    a.rgb[((size_t)k * 3 + 0) * HW + pix] = fmaf(Tf, r.bg0, C0[p]);
+    a.rgb[((size_t)k * 3 + 1) * HW + pix] = fmaf(Tf, r.bg1, C1[p]);
+    a.rgb[((size_t)k * 3 + 2) * HW + pix] = fmaf(Tf, r.bg2, C2[p]);
+    a.T[(size_t)k * HW + pix] = Tf;
     a.nlast[(size_t)k * HW + pix] = last[p];
   }
 }
