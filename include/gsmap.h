@@ -47,6 +47,14 @@ extern "C" {
 
 /* gs_settings.flags bits. */
 #define GS_FLAG_EMIT_KEYS 1 /* sort_tile_keys also writes the sorted 64-bit keys */
+/* Render every pixel of each Gaussian's integer box.  Without this flag
+ * gs_project_and_bin also narrows each (view, Gaussian) box to a render box:
+ * the box intersected with a conservative bound of the pixels whose alpha
+ * can reach alpha_min (see gs_project_and_bin).  Outside it every pair would
+ * be skipped for alpha < alpha_min, so images, n_last and gradients do not
+ * change; the compositing kernels just examine fewer pairs.  Keys and tile
+ * lists always follow the full box. */
+#define GS_FLAG_FULL_BOX 2
 
 /* Gaussian parameters (Eq. 1: mean, rotation quaternion, scale, opacity,
  * colour), planar structure of arrays, FP32, all device pointers.  Each row
@@ -128,6 +136,9 @@ typedef struct gs_workspace gs_workspace;
  *                  where (A, B, C) is the conic (inverse screen covariance)
  *                  and the last two words are integer bit patterns
  *   tiles_touched  [n_views][capacity] int32 (0 = culled)
+ *   render_box     [n_views][capacity] two int32: (u_lo | u_hi << 16,
+ *                  v_lo | v_hi << 16) of the render box; an empty box has
+ *                  u_lo = v_lo = 0xffff and u_hi = v_hi = 0
  *   ranges         [n_views * tiles_y * tiles_x][2] uint32 [start, end)
  *   vals_sorted    [key_capacity] uint32 Gaussian index per sorted key
  *   keys_sorted    [key_capacity] uint64 (tile << 32 | depth bits), written
@@ -138,6 +149,7 @@ typedef struct gs_workspace gs_workspace;
 typedef struct gs_workspace_view {
   void* records;
   int32_t* tiles_touched;
+  int32_t* render_box;
   uint32_t* ranges;
   uint32_t* vals_sorted;
   uint64_t* keys_sorted;

@@ -18,6 +18,7 @@ GS_OK, GS_E_INVALID, GS_E_CAPACITY, GS_E_OVERFLOW, GS_E_HIP = 0, 1, 2, 3, 4
 GS_STATUS_KEY_OVERFLOW = 1
 GS_STATUS_GAUSSIAN_OVERFLOW = 2
 GS_FLAG_EMIT_KEYS = 1
+GS_FLAG_FULL_BOX = 2
 
 
 class GsError(RuntimeError):
@@ -56,7 +57,7 @@ class gs_geometry(C.Structure):
 
 class gs_workspace_view(C.Structure):
     _fields_ = [("records", C.c_void_p), ("tiles_touched", C.c_void_p),
-                ("ranges", C.c_void_p), ("vals_sorted", C.c_void_p),
+                ("render_box", C.c_void_p), ("ranges", C.c_void_p), ("vals_sorted", C.c_void_p),
                 ("keys_sorted", C.c_void_p), ("grad2d", C.c_void_p),
                 ("n_keys", C.c_void_p), ("status", C.c_void_p),
                 ("tiles_x", C.c_int32), ("tiles_y", C.c_int32)]

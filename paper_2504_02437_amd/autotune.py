@@ -9,6 +9,7 @@ the entry's pixel box), so tuning never changes results.
 """
 from __future__ import annotations
 
+import dataclasses
 import json
 import math
 import os
@@ -63,8 +64,7 @@ def autotune(params, cams, base: R.Settings | None = None, reps=3,
             cache = {}
     if use_cache and key in cache:
         t, b, n = cache[key]["shape"]
-        return (R.Settings(t, b, base.bg, base.alpha_min, base.T_min,
-                           base.alpha_max, base.emit_keys, n),
+        return (dataclasses.replace(base, tile=t, lds_batch=b, block_threads=n),
                 {tuple(cache[key]["shape"]): cache[key]["ms"]})
     grad = params.zeros_like()
     V = len(cams)
@@ -73,15 +73,15 @@ def autotune(params, cams, base: R.Settings | None = None, reps=3,
                     device=params.data.device)
     times = {}
     for tile in tiles:
-        s0 = R.Settings(tile, 256, base.bg, base.alpha_min, base.T_min,
-                        base.alpha_max, False, 0)
+        s0 = dataclasses.replace(base, tile=tile, lds_batch=256,
+                                 emit_keys=False, block_threads=0)
         rast = R.Rasterizer(cams, params.capacity, s0,
                             key_capacity=key_capacity,
                             device=params.data.device)
         rast.fit_key_capacity(params)
         for (t, b, n) in shapes((tile,)):
-            rast.settings = R.Settings(t, b, base.bg, base.alpha_min,
-                                       base.T_min, base.alpha_max, False, n)
+            rast.settings = dataclasses.replace(s0, lds_batch=b,
+                                                block_threads=n)
             ms = _time_iteration(rast, params, grad, dL, reps)
             if rast.status()[0]:
                 raise RuntimeError("key capacity exceeded while autotuning")
@@ -98,5 +98,4 @@ def autotune(params, cams, base: R.Settings | None = None, reps=3,
             json.dump(cache, f, indent=1)
         os.replace(cache_path + ".tmp", cache_path)
     t, b, n = best
-    return (R.Settings(t, b, base.bg, base.alpha_min, base.T_min,
-                       base.alpha_max, base.emit_keys, n), times)
+    return dataclasses.replace(base, tile=t, lds_batch=b, block_threads=n), times

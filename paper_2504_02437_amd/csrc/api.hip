@@ -88,6 +88,7 @@ static int make_layout(const gs_geometry* g, Layout& L, int& tx, int& ty) {
   auto take = [&](size_t bytes) { size_t o = off; off += align256(bytes); return o; };
   L.records = take(V * cap * sizeof(Record));
   L.tiles_touched = take(V * cap * 4);
+  L.rbox = take(V * cap * 8);
   L.diff = take(V * (size_t)(ty + 1) * (tx + 1) * 4);
   L.ranges = take(tiles * 8);
   L.cursor = take(tiles * 4);
@@ -159,6 +160,8 @@ int gs_workspace_create(const gs_geometry* geo, void* device_buffer,
   char* b = ws->base;
   ws->records = (Record*)(b + L.records);
   ws->tiles_touched = (int32_t*)(b + L.tiles_touched);
+  ws->rbox = (int2*)(b + L.rbox);
+  ws->box_alpha_min = 0.f;
   ws->diff = (int32_t*)(b + L.diff);
   ws->ranges = (uint32_t*)(b + L.ranges);
   ws->cursor = (uint32_t*)(b + L.cursor);
@@ -196,6 +199,7 @@ int gs_workspace_get_view(const gs_workspace* ws, gs_workspace_view* out) {
   if (!out) { set_error("out is NULL"); return GS_E_INVALID; }
   out->records = ws->records;
   out->tiles_touched = ws->tiles_touched;
+  out->render_box = (int32_t*)ws->rbox;
   out->ranges = ws->ranges;
   out->vals_sorted = ws->vals_sorted;
   out->keys_sorted = (uint64_t*)ws->keys_sorted;
@@ -227,8 +231,9 @@ int gs_project_and_bin(gs_workspace* ws, const gs_params* params,
     return GS_E_CAPACITY;
   }
   hipStream_t st = (hipStream_t)stream;
-  hipError_t e = launch_project(ws, params, cams, st);
+  hipError_t e = launch_project(ws, params, cams, s, st);
   if (e != hipSuccess) return finish(e, "project");
+  ws->box_alpha_min = (s->flags & GS_FLAG_FULL_BOX) ? 0.f : s->alpha_min;
   return finish(launch_bin(ws, params, st), "bin");
 }
 
@@ -239,6 +244,19 @@ int gs_sort_tile_keys(gs_workspace* ws, const gs_settings* s, void* stream) {
   return finish(launch_sort(ws, s, (hipStream_t)stream), "sort_tile_keys");
 }
 
+// The render boxes of the last projection hold every pixel whose alpha can
+// reach the alpha_min they were formed for; a smaller alpha_min needs larger
+// boxes.
+static int check_box_alpha(const gs_workspace* ws, const gs_settings* s) {
+  if (s->alpha_min < ws->box_alpha_min) {
+    set_error("settings.alpha_min %g is below the %g the render boxes were "
+              "formed for; project again with these settings",
+              (double)s->alpha_min, (double)ws->box_alpha_min);
+    return GS_E_INVALID;
+  }
+  return GS_OK;
+}
+
 int gs_render_fwd(gs_workspace* ws, const gs_params* params,
                   const gs_settings* s, float* out_rgb, float* out_T,
                   int32_t* out_nlast, void* stream) {
@@ -247,6 +265,7 @@ int gs_render_fwd(gs_workspace* ws, const gs_params* params,
   if (int rc = validate_params(params, "params")) return rc;
   if (int rc = validate_settings(s)) return rc;
   if (s->tile != ws->geo.tile) { set_error("settings.tile differs from the workspace's"); return GS_E_INVALID; }
+  if (int rc = check_box_alpha(ws, s)) return rc;
   if (!out_rgb || !out_T || !out_nlast) { set_error("an output is NULL"); return GS_E_INVALID; }
   return finish(launch_render_fwd(ws, s, out_rgb, out_T, out_nlast,
                                   (hipStream_t)stream), "render_fwd");
@@ -259,6 +278,7 @@ int gs_count_pairs(gs_workspace* ws, const gs_params* params,
   if (int rc = validate_params(params, "params")) return rc;
   if (int rc = validate_settings(s)) return rc;
   if (s->tile != ws->geo.tile) { set_error("settings.tile differs from the workspace's"); return GS_E_INVALID; }
+  if (int rc = check_box_alpha(ws, s)) return rc;
   if (!counts_dev) { set_error("counts_dev is NULL"); return GS_E_INVALID; }
   return finish(launch_count_pairs(ws, s, (unsigned long long*)counts_dev,
                                    (hipStream_t)stream), "count_pairs");
@@ -274,6 +294,7 @@ int gs_render_bwd(gs_workspace* ws, const gs_params* params,
   if (int rc = validate_params(grad, "grad")) return rc;
   if (int rc = validate_settings(s)) return rc;
   if (s->tile != ws->geo.tile) { set_error("settings.tile differs from the workspace's"); return GS_E_INVALID; }
+  if (int rc = check_box_alpha(ws, s)) return rc;
   if (!dL_drgb || !T_final || !n_last) {
     set_error("an input is NULL");
     return GS_E_INVALID;

@@ -18,7 +18,7 @@ struct __align__(16) Record {
 
 // Workspace layout: every region is carved from the caller's device buffer.
 struct Layout {
-  size_t records, tiles_touched, diff, ranges, cursor, view_tot, keys_unsorted,
+  size_t records, tiles_touched, rbox, diff, ranges, cursor, view_tot, keys_unsorted,
       vals_sorted, keys_sorted, grad2d, gop, counters, total;
 };
 
@@ -54,6 +54,8 @@ struct gs_workspace {
   gs::Layout L;
   gs::Record* records;
   int32_t* tiles_touched;
+  int2* rbox;            // [V][capacity] render boxes (packed 16-bit pairs)
+  float box_alpha_min;   // alpha_min the render boxes were formed for
   int32_t* diff;         // [V][Ty + 1][Tx + 1] tile-coverage difference grid
   uint32_t* ranges;      // [V * Ty * Tx][2]
   uint32_t* cursor;      // [V * Ty * Tx] tile counts, then scatter cursors
@@ -76,7 +78,8 @@ int validate_params(const gs_params* p, const char* what);
 // Launchers implemented by the kernel translation units.  They return a
 // hipError_t from the launch (hipGetLastError).
 hipError_t launch_project(gs_workspace* ws, const gs_params* p,
-                          const gs_camera* cams, hipStream_t st);
+                          const gs_camera* cams, const gs_settings* s,
+                          hipStream_t st);
 hipError_t launch_project_bwd(gs_workspace* ws, const gs_params* p,
                               const gs_camera* cams, gs_params* grad,
                               hipStream_t st);

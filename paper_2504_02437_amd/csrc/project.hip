@@ -29,7 +29,57 @@ struct ProjArgs {
   Record* rec;
   int32_t* tiles;
   int32_t* diff;
+  int2* rbox;
+  double amin;    // alpha_min the render boxes are formed for
+  int full_box;   // 1: render boxes equal the boxes
 };
+
+constexpr int kEmptyPair = 0xffff;   // u_lo = 0xffff, u_hi = 0
+
+// Render box: the integer box narrowed to the pixels where the compositing
+// kernels can admit the Gaussian.  They admit a pair only when their FP32
+// alpha = min(alpha_max, o * exp2(e2)) reaches alpha_min, with e2 the FP32
+// evaluation of -log2(e)/2 * q(d), q(d) = A dx^2 + 2 B dx dy + C dy^2 over
+// the published record.  Its rounding error is below 8 u S (u = 2^-24, S the
+// sum of the magnitudes of the three terms), and exp2 and the product with o
+// add less than 2^-20 relative.  So an admitted pixel satisfies
+//   q(d) <= 2 ln(o / alpha_min) + 2 ln(2) (16 u S_max + 2^-19) =: L,
+// with S_max bounding S over the box, and lies in the bounding box of the
+// ellipse q(d) <= L: |dx| <= sqrt(L C / det), |dy| <= sqrt(L A / det) with
+// det = A C - B^2 (the inverse conic's diagonal).  Evaluated in FP64 from
+// the FP32 record, with a further relative and absolute slack.
+__device__ inline void render_box(const Record& R, int iu0, int iu1, int iv0,
+                                  int iv1, double amin, int& ru0, int& ru1,
+                                  int& rv0, int& rv1) {
+  ru0 = iu0; ru1 = iu1; rv0 = iv0; rv1 = iv1;
+  const double px = R.q0.x, py = R.q0.y, A = R.q0.z, B = R.q0.w;
+  const double C = R.q1.x, o = R.q1.y;
+  if (!(o >= amin * (1.0 - 0x1p-20))) {   // o * G < alpha_min everywhere
+    ru0 = rv0 = kEmptyPair;
+    ru1 = rv1 = 0;
+    return;
+  }
+  const double det = A * C - B * B;
+  if (!(det > 0.0) || !(A > 0.0) || !(C > 0.0)) return;
+  const double dxm = fmax(fabs(px - (double)iu0), fabs((double)iu1 - px));
+  const double dym = fmax(fabs(py - (double)iv0), fabs((double)iv1 - py));
+  const double smax = 0.72134752044448170 *
+                      ((A * dxm * dxm + 2.0 * fabs(B) * dxm * dym) +
+                       C * dym * dym);
+  const double marg = 16.0 * 0x1p-24 * smax + 0x1p-19;
+  const double L = 2.0 * log(o / amin) + 2.0 * 0.69314718055994531 * marg;
+  const double hx = sqrt(L * C / det) * (1.0 + 1e-9) + 1e-6;
+  const double hy = sqrt(L * A / det) * (1.0 + 1e-9) + 1e-6;
+  if (!isfinite(hx) || !isfinite(hy)) return;
+  ru0 = (int)fmax((double)iu0, ceil(px - hx));
+  ru1 = (int)fmin((double)iu1, floor(px + hx));
+  rv0 = (int)fmax((double)iv0, ceil(py - hy));
+  rv1 = (int)fmin((double)iv1, floor(py + hy));
+  if (ru0 > ru1 || rv0 > rv1) {
+    ru0 = rv0 = kEmptyPair;
+    ru1 = rv1 = 0;
+  }
+}
 
 // View-independent part of Eq. 1: s = exp(l), R(q / |q|), M = R diag(s),
 // Sigma = M M^T.
@@ -180,6 +230,9 @@ __global__ __launch_bounds__(256) void k_project(ProjArgs a) {
                        __int_as_float(iu0 | (iu1 << 16)),
                        __int_as_float(iv0 | (iv1 << 16)));
     a.rec[slot] = R;
+    int ru0 = iu0, ru1 = iu1, rv0 = iv0, rv1 = iv1;
+    if (!a.full_box) render_box(R, iu0, iu1, iv0, iv1, a.amin, ru0, ru1, rv0, rv1);
+    a.rbox[slot] = make_int2(ru0 | (ru1 << 16), rv0 | (rv1 << 16));
     const int tx0 = iu0 / a.tile, tx1 = iu1 / a.tile;
     const int ty0 = iv0 / a.tile, ty1 = iv1 / a.tile;
     a.tiles[slot] = (tx1 - tx0 + 1) * (ty1 - ty0 + 1);
@@ -338,7 +391,8 @@ __global__ __launch_bounds__(256) void k_project_bwd(ProjBwdArgs a) {
 }  // namespace
 
 hipError_t launch_project(gs_workspace* ws, const gs_params* p,
-                          const gs_camera* cams, hipStream_t st) {
+                          const gs_camera* cams, const gs_settings* s,
+                          hipStream_t st) {
   ProjArgs a;
   a.mean = p->mean; a.lsc = p->log_scale; a.quat = p->quat;
   a.opl = p->opacity_logit; a.rgb = p->rgb; a.n_dev = p->n_dev;
@@ -346,6 +400,8 @@ hipError_t launch_project(gs_workspace* ws, const gs_params* p,
   a.W = ws->geo.width; a.H = ws->geo.height; a.tile = ws->geo.tile;
   a.Tx = ws->tiles_x; a.Ty = ws->tiles_y;
   a.rec = ws->records; a.tiles = ws->tiles_touched; a.diff = ws->diff;
+  a.rbox = ws->rbox; a.amin = (double)s->alpha_min;
+  a.full_box = (s->flags & GS_FLAG_FULL_BOX) ? 1 : 0;
   const int blocks = (p->capacity + 255) / 256;
   if (blocks > 0) hipLaunchKernelGGL(k_project, dim3(blocks), dim3(256), 0, st, a);
   return hipGetLastError();

@@ -72,16 +72,43 @@ __global__ __launch_bounds__(NT) void k_render_fwd(FwdArgs a) {
     vf[p] = (float)(v0 + p);
     ib[p] = ib_last[p] = 0;
   }
+  // Staging: the list is read in rounds of RS entries; entries whose render
+  // box misses the tile are dropped (order kept) and the rest fill the LDS
+  // batch with their list position.
+  constexpr int RS = NT < BATCH ? NT : BATCH;
+  __shared__ int eidx[BATCH];
+  __shared__ int wcnt[NT / 64];
   const Record* rv = r.rec + (size_t)k * r.cap;
-  for (long long b0 = s; b0 < e; b0 += BATCH) {
+  const int2* rbv = r.rbox + (size_t)k * r.cap;
+  const int tu0 = tx * TILE, tu1 = tu0 + TILE - 1;
+  const int tv0 = ty * TILE, tv1 = tv0 + TILE - 1;
+  long long pos = s;
+  while (pos < e) {
     int alive = 0;
 #pragma unroll
     for (int p = 0; p < PPT; ++p) alive |= T[p] > 0.f;
     if (__syncthreads_or(alive) == 0) break;
-    const int cnt = (int)min((long long)BATCH, e - b0);
-    for (int i = tid; i < cnt; i += NT) stage(ent[i], rv[r.vals[b0 + i]]);
+    int cnt = 0;
+    while (pos < e && cnt + RS <= BATCH) {
+      const long long i = pos + tid;
+      bool keep = false;
+      uint32_t g = 0;
+      int4 box = make_int4(0, 0, 0, 0);
+      if (tid < RS && i < e) {
+        g = r.vals[i];
+        box = unpack_box(rbv[g]);
+        keep = box_meets(box, tu0, tu1, tv0, tv1);
+      }
+      int tot;
+      const int slot = cnt + compact_rank<NT>(keep, wcnt, tot);
+      if (keep) {
+        stage(ent[slot], rv[g], box);
+        eidx[slot] = (int)(i - s) + 1;
+      }
+      cnt += tot;
+      pos += RS;
+    }
     __syncthreads();
-    const int base = (int)(b0 - s);
     for (int j = 0; j < cnt; ++j) {
       if ((j & 7) == 0) {
         bool any = false;
@@ -108,7 +135,7 @@ __global__ __launch_bounds__(NT) void k_render_fwd(FwdArgs a) {
       const bool in_u = u >= box.x && u <= box.y;
       const int lo = box.z - v0, hi = box.w - v0;
       const Column col = column(ea, uf);
-      const int idx = base + j + 1;
+      const int idx = eidx[j];
 #pragma unroll
       for (int p = 0; p < PPT; ++p) {
         float dy;
@@ -176,7 +203,8 @@ struct FwdLauncher {
 
 RasterArgs make_raster_args(gs_workspace* ws, const gs_settings* s) {
   RasterArgs r;
-  r.rec = ws->records; r.vals = ws->vals_sorted; r.ranges = ws->ranges;
+  r.rec = ws->records; r.rbox = ws->rbox;
+  r.vals = ws->vals_sorted; r.ranges = ws->ranges;
   r.key_cap = ws->geo.key_capacity; r.cap = ws->geo.capacity;
   r.V = ws->geo.n_views; r.W = ws->geo.width; r.H = ws->geo.height;
   r.Tx = ws->tiles_x; r.Ty = ws->tiles_y;

@@ -120,6 +120,7 @@ class Settings:
     alpha_max: float = ALPHA_MAX
     emit_keys: bool = False
     block_threads: int = 0
+    full_box: bool = False   # render whole integer boxes (no render-box cut)
 
     def struct(self) -> L.gs_settings:
         s = L.gs_settings()
@@ -127,7 +128,8 @@ class Settings:
         s.bg[:] = list(self.bg)
         s.alpha_min, s.T_min, s.alpha_max = (self.alpha_min, self.T_min,
                                              self.alpha_max)
-        s.flags = L.GS_FLAG_EMIT_KEYS if self.emit_keys else 0
+        s.flags = ((L.GS_FLAG_EMIT_KEYS if self.emit_keys else 0) |
+                   (L.GS_FLAG_FULL_BOX if self.full_box else 0))
         s.block_threads = self.block_threads
         return s
 
@@ -181,6 +183,12 @@ class Workspace:
     def tiles_touched(self):
         V, cap = self.geo.n_views, self.geo.capacity
         return self._slice(self.view.tiles_touched, torch.int32, V * cap).view(V, cap)
+
+    def render_box(self):
+        """[V][capacity][2] int32 packed render boxes."""
+        V, cap = self.geo.n_views, self.geo.capacity
+        return self._slice(self.view.render_box, torch.int32, V * cap * 2).view(
+            V, cap, 2)
 
     def ranges(self):
         return self._slice(self.view.ranges, torch.int32, self.n_tiles * 2).view(

@@ -12,12 +12,13 @@ MAX_FLAGGED = 1e-3   # fraction of pixels whose decisions are FP32-ambiguous
 
 
 def gpu_forward(w, tile=16, batch=256, bg=(0.0, 0.0, 0.0), emit_keys=True,
-                key_capacity=None, params=None, threads=0):
+                key_capacity=None, params=None, threads=0, full_box=False):
     if params is None:
         params = R.ParamBuffer.from_gaussians(w.gaussians)
     rast = R.Rasterizer(w.cameras, params.capacity,
                         R.Settings(tile=tile, lds_batch=batch, bg=bg,
-                                   emit_keys=emit_keys, block_threads=threads),
+                                   emit_keys=emit_keys, block_threads=threads,
+                                   full_box=full_box),
                         key_capacity=key_capacity)
     rast.forward(params)
     torch.cuda.synchronize()

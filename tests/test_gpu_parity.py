@@ -10,6 +10,7 @@ import synth
 from gpu_helpers import (check_forward, check_grads, check_records,
                          check_sort, gpu_backward, gpu_forward, masked_dL,
                          oracle_backward, oracle_forward)
+from paper_2504_02437_amd import raster as R
 
 pytestmark = pytest.mark.gpu
 
@@ -163,13 +164,20 @@ def test_config1_full_size():
 
 @pytest.mark.parametrize("tile", [8, 16, 32])
 def test_pair_counters_match_oracle(tile):
-    """gs_count_pairs walks the lists with the forward's decisions: its four
-    counters equal the oracle's exactly wherever no decision flips."""
+    """gs_count_pairs walks the lists with the forward's decisions: with
+    whole integer boxes (the oracle's rule) its four counters equal the
+    oracle's exactly wherever no decision flips.  Render boxes examine no
+    more pairs and the same contributing ones."""
     w = synth.config0()
     print("case counters", tile, flush=True)
     p64, proj, bins, fwd = oracle_forward(w, tile)
-    params, rast = gpu_forward(w, tile)
+    params, rast = gpu_forward(w, tile, full_box=True)
     got = rast.count_pairs(params)
+    _, rast_rb = gpu_forward(w, tile, params=params)
+    cut = rast_rb.count_pairs(params)
+    assert cut["contributing"] == got["contributing"]
+    for k in ("examined", "inbox", "revisit"):
+        assert cut[k] <= got[k], (k, cut[k], got[k])
     ref = fwd["counters"]
     flips = int((rast.nlast.cpu().numpy() != fwd["nlast"]).sum())
     longest = int((bins["ranges"][:, 1] - bins["ranges"][:, 0]).max())
@@ -199,3 +207,86 @@ def test_long_tile_lists_use_the_global_sort_path():
     # Thousands of faint entries per pixel widen the transmittance error
     # bound, so more pixels are FP32-ambiguous here than in real scenes.
     check_forward(rast, fwd, max_flagged=0.05)
+
+
+def _unpack(rb):
+    return np.stack([rb[..., 0] & 0xFFFF, rb[..., 0] >> 16,
+                     rb[..., 1] & 0xFFFF, rb[..., 1] >> 16], -1)
+
+
+def _same_render(w, tile, batch, threads, n_check_grads=True, rtol=1e-4):
+    params = R.ParamBuffer.from_gaussians(w.gaussians)
+    _, full = gpu_forward(w, tile, batch, params=params, threads=threads,
+                          full_box=True)
+    _, cut = gpu_forward(w, tile, batch, params=params, threads=threads)
+    for a, b in ((full.rgb, cut.rgb), (full.T, cut.T), (full.nlast, cut.nlast)):
+        assert torch.equal(a, b)
+    # The render box lies inside the integer box; empty ones are encoded as
+    # lo = 0xffff, hi = 0.
+    vis = cut.ws.tiles_touched().cpu().numpy() > 0
+    rb = _unpack(cut.ws.render_box().cpu().numpy())[vis]
+    rec = cut.ws.records().cpu().numpy()
+    box = _unpack(np.stack([rec[..., 10].view(np.int32),
+                            rec[..., 11].view(np.int32)], -1))[vis]
+    empty = rb[:, 0] == 0xFFFF
+    assert np.all(rb[empty] == [0xFFFF, 0, 0xFFFF, 0])
+    ne = ~empty
+    assert np.all(rb[ne, 0] >= box[ne, 0]) and np.all(rb[ne, 1] <= box[ne, 1])
+    assert np.all(rb[ne, 2] >= box[ne, 2]) and np.all(rb[ne, 3] <= box[ne, 3])
+    assert np.all(rb[ne, 0] <= rb[ne, 1]) and np.all(rb[ne, 2] <= rb[ne, 3])
+    area = lambda b: ((b[:, 1] - b[:, 0] + 1) * (b[:, 3] - b[:, 2] + 1)).sum()
+    ratio = area(rb[ne]) / area(box)
+    if n_check_grads:
+        rng = np.random.default_rng(5)
+        V, H, W = cut.T.shape
+        dL = rng.normal(size=(V, 3, H, W)).astype(np.float32)
+        g_full = gpu_backward(full, params, dL)
+        g_cut = gpu_backward(cut, params, dL)
+        n = w.gaussians.n
+        ref = {name: g_full[a:b, :n] for name, (a, b) in R.ROWS.items()}
+        check_grads(g_cut, ref, n, rtol=rtol)
+    return ratio
+
+
+@pytest.mark.parametrize("tile,batch,threads", [
+    (8, 128, 64), (16, 256, 64), (16, 512, 128), (16, 128, 256),
+    (32, 128, 256), (32, 256, 128)])
+def test_render_box_changes_nothing(tile, batch, threads):
+    """Render boxes drop only pairs whose FP32 alpha cannot reach alpha_min:
+    images, T_final and n_last are bit-identical to whole-box rendering and
+    the gradients agree to FP32 summation order."""
+    print("case render box config0", tile, batch, threads, flush=True)
+    ratio = _same_render(synth.config0(), tile, batch, threads)
+    assert ratio < 1.0
+
+
+def test_render_box_changes_nothing_on_the_window():
+    """The same on the 10-view 1200x680 window in the benchmark's launch
+    shape, where the render boxes cover well under the integer boxes."""
+    print("case render box window", flush=True)
+    # Unit-normal pixel gradients over 8 Mpx cancel heavily in the opacity
+    # sums, so summation order alone moves them by ~1e-4: use the parity
+    # tolerance here.
+    ratio = _same_render(synth.config2(), 32, 128, 256, rtol=1e-3)
+    print("render-box / box pixel ratio", ratio, flush=True)
+    assert ratio < 0.8
+
+
+def test_render_needs_the_projection_alpha_min():
+    """Render boxes are formed for the projection's alpha_min: rendering with
+    a smaller one is refused; a larger one, or whole boxes, is accepted."""
+    w = synth.config0()
+    params = R.ParamBuffer.from_gaussians(w.gaussians)
+    base = R.Settings(tile=16)
+    rast = R.Rasterizer(w.cameras, params.capacity, base)
+    rast.forward(params)
+    lower = R.Settings(tile=16, alpha_min=base.alpha_min * 0.5)
+    with pytest.raises(R.L.GsError):
+        R.render_fwd(rast.ws, params, lower, rast.rgb, rast.T, rast.nlast)
+    higher = R.Settings(tile=16, alpha_min=base.alpha_min * 2)
+    R.render_fwd(rast.ws, params, higher, rast.rgb, rast.T, rast.nlast)
+    R.project_and_bin(rast.ws, params, rast.cams_dev,
+                      R.Settings(tile=16, full_box=True))
+    R.sort_tile_keys(rast.ws, base)
+    R.render_fwd(rast.ws, params, lower, rast.rgb, rast.T, rast.nlast)
+    torch.cuda.synchronize()
