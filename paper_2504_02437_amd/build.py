@@ -26,6 +26,10 @@ COMMON = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}",
           "-packed-fp32-ops", "-fvisibility=hidden", "-I", INCLUDE,
           "-Wall", "-Wno-unused-result"]
 NO_CONTRACT = ["-ffp-contract=off"]
+# The backward adds row partial sums into LDS from a few lanes per wave; the
+# compiler's atomic optimizer would turn each such add into a serial
+# cross-lane loop.
+NO_ATOMIC_OPT = ["-mllvm", "-amdgpu-atomic-optimizer-strategy=None"]
 
 # (source, extra flags)
 UNITS = [
@@ -34,7 +38,7 @@ UNITS = [
     ("bin.hip", []),
     ("sort.hip", []),
     ("render_fwd.hip", NO_CONTRACT),
-    ("render_bwd.hip", NO_CONTRACT),
+    ("render_bwd.hip", NO_CONTRACT + NO_ATOMIC_OPT),
     ("optim.hip", []),
     ("mlp.hip", NO_CONTRACT),
 ]

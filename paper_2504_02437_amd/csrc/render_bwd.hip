@@ -14,8 +14,10 @@
 // with pi = -(A dx^2 + C dy^2) / 2 - B dx dy.  A thread's pixels share dx, so
 // it accumulates only sum(dL/dpi), sum(dL/dpi dy) and sum(dL/dpi dy^2) over
 // its strip and forms the mean and conic gradients once per entry.  The nine
-// per-entry sums are reduced across the wave with DPP, merged across waves
-// in LDS, and added to global memory with one atomic per (entry, quantity).
+// per-entry sums are reduced over each 16-lane row with DPP (a transposed
+// reduction that packs four quantities into one register), merged across
+// rows and waves by LDS adds, and added to global memory with one atomic per
+// (entry, quantity).
 
 #include "raster_common.h"
 
@@ -32,26 +34,45 @@ struct BwdArgs {
   float* grgb;     // [3][cap] (caller's gradient rows, accumulated)
 };
 
-template <int CTRL, int ROW_MASK>
-__device__ __forceinline__ float dpp_step(float x) {
-  const int y = __builtin_amdgcn_update_dpp(0, __float_as_int(x), CTRL,
-                                            ROW_MASK, 0xf, false);
-  return x + __int_as_float(y);
+// x plus the DPP-permuted y.  Lanes whose source lies outside their row read
+// 0; the reductions below only keep lanes whose source is inside the row.
+template <int CTRL>
+__device__ __forceinline__ float add_dpp(float x, float y) {
+  const int t = __builtin_amdgcn_update_dpp(0, __float_as_int(y), CTRL, 0xf,
+                                            0xf, true);
+  return x + __int_as_float(t);
 }
 
-// Sum over the 64 lanes of a wave; the total is valid in lane 63.
-__device__ __forceinline__ float wave_sum(float x) {
-  x = dpp_step<0xb1, 0xf>(x);   // quad_perm [1,0,3,2]
-  x = dpp_step<0x4e, 0xf>(x);   // quad_perm [2,3,0,1]
-  x = dpp_step<0x141, 0xf>(x);  // row_half_mirror
-  x = dpp_step<0x140, 0xf>(x);  // row_mirror
-  x = dpp_step<0x142, 0xa>(x);  // row_bcast:15 into rows 1 and 3
-  x = dpp_step<0x143, 0xc>(x);  // row_bcast:31 into rows 2 and 3
+// Transposed row reduction of four per-lane values: returns, in each lane,
+// the sum over the lane's 16-lane row of value number (lane >> 2) & 3.
+// Two bank-masked exchange levels halve the number of registers each time
+// (shift 4: banks 0, 2 keep a / c and banks 1, 3 keep b / d; shift 8: banks
+// 0, 1 keep the first pair), then a quad reduction finishes each bank.
+__device__ __forceinline__ float row_sum4(float a, float b, float c, float d,
+                                          bool bank02, bool bank01) {
+  // The DPP reads of neighbouring lanes run in converged control flow; only
+  // the selects depend on the lane.
+  const float a1 = add_dpp<0x104>(a, a);   // row_shl:4
+  const float b1 = add_dpp<0x114>(b, b);   // row_shr:4
+  const float c1 = add_dpp<0x104>(c, c);
+  const float d1 = add_dpp<0x114>(d, d);
+  const float ab = bank02 ? a1 : b1;
+  const float cd = bank02 ? c1 : d1;
+  const float ab1 = add_dpp<0x108>(ab, ab);  // row_shl:8
+  const float cd1 = add_dpp<0x118>(cd, cd);  // row_shr:8
+  float x = bank01 ? ab1 : cd1;
+  x = add_dpp<0xb1>(x, x);   // quad_perm [1,0,3,2]
+  x = add_dpp<0x4e>(x, x);   // quad_perm [2,3,0,1]
   return x;
 }
 
-__device__ __forceinline__ float lane63(float x) {
-  return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(x), 63));
+// Sum over the lane's 16-lane row, in every lane of the row.
+__device__ __forceinline__ float row_sum(float x) {
+  x = add_dpp<0xb1>(x, x);   // quad_perm [1,0,3,2]
+  x = add_dpp<0x4e>(x, x);   // quad_perm [2,3,0,1]
+  x = add_dpp<0x141>(x, x);  // row_half_mirror
+  x = add_dpp<0x140>(x, x);  // row_mirror
+  return x;
 }
 
 __device__ __forceinline__ int wave_max(int x) {
@@ -80,6 +101,8 @@ __global__ __launch_bounds__(NT) void k_render_bwd(BwdArgs a) {
   const int ty = rem / r.Tx, tx = rem - ty * r.Tx;
   const int tid = threadIdx.x;
   const int lane = tid & 63;
+  const bool bank02 = ((lane >> 2) & 1) == 0;   // lane in bank 0 or 2 of its row
+  const bool bank01 = ((lane >> 3) & 1) == 0;   // lane in bank 0 or 1
   long long s, e;
   tile_range(r, t, s, e);
   const size_t HW = (size_t)r.H * r.W;
@@ -212,25 +235,18 @@ __global__ __launch_bounds__(NT) void k_render_bwd(BwdArgs a) {
         const float d_A = -0.5f * dx * dxS0;
         const float d_B = -dx * S1;
         const float d_C = -0.5f * S2;
-        const float s0 = lane63(wave_sum(d_px));
-        const float s1 = lane63(wave_sum(d_py));
-        const float s2 = lane63(wave_sum(d_A));
-        const float s3 = lane63(wave_sum(d_B));
-        const float s4 = lane63(wave_sum(d_C));
-        const float s5 = lane63(wave_sum(d_o));
-        const float s6 = lane63(wave_sum(d_r));
-        const float s7 = lane63(wave_sum(d_g));
-        const float s8 = lane63(wave_sum(d_b));
-        if (lane == 0) {
-          float* ac = acc[j];
-          if (NT == 64) {
-            ac[0] = s0; ac[1] = s1; ac[2] = s2; ac[3] = s3; ac[4] = s4;
-            ac[5] = s5; ac[6] = s6; ac[7] = s7; ac[8] = s8;
-          } else {
-            atomicAdd(&ac[0], s0); atomicAdd(&ac[1], s1); atomicAdd(&ac[2], s2);
-            atomicAdd(&ac[3], s3); atomicAdd(&ac[4], s4); atomicAdd(&ac[5], s5);
-            atomicAdd(&ac[6], s6); atomicAdd(&ac[7], s7); atomicAdd(&ac[8], s8);
-          }
+        // Row sums of the nine quantities, added into the entry's LDS slot
+        // by lanes 0, 4, 8, 12 of each row (the four rows of the wave and
+        // the other waves of the tile meet in the LDS adds).
+        const float x = row_sum4(d_px, d_py, d_A, d_B, bank02, bank01);
+        const float y = row_sum4(d_C, d_o, d_r, d_g, bank02, bank01);
+        const float z = row_sum(d_b);
+        float* ac = acc[j];
+        if ((lane & 3) == 0) {
+          const int q = (lane >> 2) & 3;
+          atomicAdd(&ac[q], x);
+          atomicAdd(&ac[4 + q], y);
+          if (q == 0) atomicAdd(&ac[8], z);
         }
       }
     }
