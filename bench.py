@@ -96,6 +96,9 @@ def main():
     ap.add_argument("--threads", type=int, default=0)
     ap.add_argument("--full-box", action="store_true",
                     help="render whole integer boxes (no render-box cut)")
+    ap.add_argument("--calib-copy", type=int, default=0, metavar="MIB",
+                    help="first run one plain device copy of MIB MiB (a "
+                         "known-size reference for HBM traffic counters)")
     ap.add_argument("--no-graph", action="store_true")
     ap.add_argument("--no-per-view", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -113,6 +116,15 @@ def main():
     from paper_2504_02437_amd import raster as R
 
     dev = "cuda"
+    if args.calib_copy:
+        n = args.calib_copy << 18                  # float32 elements
+        src = torch.ones(n, device=dev)
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        torch.mul(src, 2.0, out=dst)   # elementwise: reads and writes 4n B
+        torch.cuda.synchronize()
+        log(f"bench: calibration copy of {4 * n} bytes")
+        del src, dst
     log("bench: building workload", args.workload)
     w = workload(args.workload)
     V = len(w.cameras)

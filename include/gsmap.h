@@ -47,13 +47,14 @@ extern "C" {
 
 /* gs_settings.flags bits. */
 #define GS_FLAG_EMIT_KEYS 1 /* sort_tile_keys also writes the sorted 64-bit keys */
-/* Render every pixel of each Gaussian's integer box.  Without this flag
- * gs_project_and_bin also narrows each (view, Gaussian) box to a render box:
- * the box intersected with a conservative bound of the pixels whose alpha
- * can reach alpha_min (see gs_project_and_bin).  Outside it every pair would
- * be skipped for alpha < alpha_min, so images, n_last and gradients do not
- * change; the compositing kernels just examine fewer pairs.  Keys and tile
- * lists always follow the full box. */
+/* Bin and render every pixel of each Gaussian's integer box (the rule of the
+ * method as stated).  Without this flag gs_project_and_bin narrows each
+ * (view, Gaussian) box to a render box: the box intersected with a
+ * conservative bound of the pixels whose alpha can reach alpha_min.  Every
+ * pair outside it would be skipped for alpha < alpha_min, so images, T_final
+ * and gradients do not change; the Gaussian is binned only into the tiles its
+ * render box touches, so tile lists are shorter (and n_last, an index into
+ * them, smaller) but hold the same contributing entries in the same order. */
 #define GS_FLAG_FULL_BOX 2
 
 /* Gaussian parameters (Eq. 1: mean, rotation quaternion, scale, opacity,
@@ -177,8 +178,10 @@ GS_API int gs_workspace_get_view(const gs_workspace* ws, gs_workspace_view* out)
  * the near plane or non-finite, form Sigma = R S S^T R^T, the EWA screen
  * covariance J W Sigma W^T J^T plus a 0.3 px^2 dilation, its conic, a radius
  * of ceil(3 sqrt(lambda_max)), the integer pixel box clipped to the image,
- * and the number of screen tiles the box touches.  This front end runs in
- * FP64 and publishes FP32 records.  Then counts the keys per tile, derives
+ * the render box (see GS_FLAG_FULL_BOX) and the number of screen tiles the
+ * render box touches.  This front end runs in FP64 and publishes FP32
+ * records (the render box bound in FP32 with slack).  Then counts the keys
+ * per tile, derives
  * the ranges by an exclusive scan (n_keys stays on the device; more keys than
  * key_capacity set GS_STATUS_KEY_OVERFLOW and no key is written past the
  * capacity), and scatters every Gaussian index into each of its tiles'
@@ -213,7 +216,8 @@ GS_API int gs_render_fwd(gs_workspace* ws, const gs_params* params,
  * uint64):
  *   [0] (pixel, entry) pairs examined: from the start of the pixel's tile
  *       list up to and including the entry at which the pixel stops
- *   [1] those of them whose pixel lies in the entry's box
+ *   [1] those of them whose pixel lies in the entry's render box (the
+ *       integer box with GS_FLAG_FULL_BOX)
  *   [2] contributing (admitted and blended) pairs
  *   [3] in-box pairs at positions before the pixel's n_last (the pairs a
  *       backward pass revisits) */

@@ -125,6 +125,7 @@ __global__ __launch_bounds__(kScanThreads) void k_tile_ranges(RangeArgs a) {
 
 struct ScatterArgs {
   const Record* rec;
+  const int2* rbox;
   const int32_t* tiles;
   const int32_t* n_dev;
   int cap, tile, Tx, Ty;
@@ -133,8 +134,8 @@ struct ScatterArgs {
   long long key_cap;
 };
 
-// Per-wave key enumeration: lane l owns one Gaussian with cnt keys (its box
-// of tiles, row-major); f(tile_in_view, g, depth_bits) runs once per key,
+// Per-wave key enumeration: lane l owns one Gaussian with cnt keys (the tiles
+// of its render box, row-major); f(tile_in_view, g, depth_bits) runs once per key,
 // 64 keys per step, each lane locating its key's owner by binary search over
 // the wave's inclusive prefix of counts.
 struct WaveOwners {
@@ -150,12 +151,11 @@ __device__ inline void load_owner(const ScatterArgs& a, int k, int g, int& cnt,
   const size_t slot = (size_t)k * a.cap + g;
   cnt = a.tiles[slot];
   if (cnt <= 0) { cnt = 0; return; }
-  const float4 q2 = a.rec[slot].q2;
-  const int bu = __float_as_int(q2.z), bv = __float_as_int(q2.w);
-  x0 = (bu & 0xffff) / a.tile;
-  w = (bu >> 16) / a.tile - x0 + 1;
-  y0 = (bv & 0xffff) / a.tile;
-  dbits = __float_as_uint(q2.y);
+  const int2 rb = a.rbox[slot];
+  x0 = (rb.x & 0xffff) / a.tile;
+  w = (rb.x >> 16) / a.tile - x0 + 1;
+  y0 = (rb.y & 0xffff) / a.tile;
+  dbits = __float_as_uint(a.rec[slot].q2.y);
 }
 
 template <typename F>
@@ -273,7 +273,8 @@ hipError_t launch_bin(gs_workspace* ws, const gs_params* p, hipStream_t st) {
   if (e != hipSuccess) return e;
   if (p->capacity <= 0) return hipSuccess;
   ScatterArgs c;
-  c.rec = ws->records; c.tiles = ws->tiles_touched; c.n_dev = p->n_dev;
+  c.rec = ws->records; c.rbox = ws->rbox; c.tiles = ws->tiles_touched;
+  c.n_dev = p->n_dev;
   c.cap = p->capacity; c.tile = ws->geo.tile; c.Tx = ws->tiles_x;
   c.Ty = ws->tiles_y; c.cursor = ws->cursor; c.keys = ws->keys_unsorted;
   c.key_cap = ws->geo.key_capacity;

@@ -30,7 +30,7 @@ struct ProjArgs {
   int32_t* tiles;
   int32_t* diff;
   int2* rbox;
-  double amin;    // alpha_min the render boxes are formed for
+  float amin;     // alpha_min the render boxes are formed for
   int full_box;   // 1: render boxes equal the boxes
 };
 
@@ -46,35 +46,37 @@ constexpr int kEmptyPair = 0xffff;   // u_lo = 0xffff, u_hi = 0
 //   q(d) <= 2 ln(o / alpha_min) + 2 ln(2) (16 u S_max + 2^-19) =: L,
 // with S_max bounding S over the box, and lies in the bounding box of the
 // ellipse q(d) <= L: |dx| <= sqrt(L C / det), |dy| <= sqrt(L A / det) with
-// det = A C - B^2 (the inverse conic's diagonal).  Evaluated in FP64 from
-// the FP32 record, with a further relative and absolute slack.
+// det = A C - B^2 (the inverse conic's diagonal).  det is formed in FP64
+// (the products of FP32 values are exact there); the rest runs in FP32 with
+// relative and absolute slack well above its rounding, and the final bounds
+// in FP64.
 __device__ inline void render_box(const Record& R, int iu0, int iu1, int iv0,
-                                  int iv1, double amin, int& ru0, int& ru1,
+                                  int iv1, float amin, int& ru0, int& ru1,
                                   int& rv0, int& rv1) {
   ru0 = iu0; ru1 = iu1; rv0 = iv0; rv1 = iv1;
-  const double px = R.q0.x, py = R.q0.y, A = R.q0.z, B = R.q0.w;
-  const double C = R.q1.x, o = R.q1.y;
-  if (!(o >= amin * (1.0 - 0x1p-20))) {   // o * G < alpha_min everywhere
+  const float px = R.q0.x, py = R.q0.y, A = R.q0.z, B = R.q0.w;
+  const float C = R.q1.x, o = R.q1.y;
+  if (!(o >= amin * (1.f - 0x1p-19f))) {   // o * G < alpha_min everywhere
     ru0 = rv0 = kEmptyPair;
     ru1 = rv1 = 0;
     return;
   }
-  const double det = A * C - B * B;
-  if (!(det > 0.0) || !(A > 0.0) || !(C > 0.0)) return;
-  const double dxm = fmax(fabs(px - (double)iu0), fabs((double)iu1 - px));
-  const double dym = fmax(fabs(py - (double)iv0), fabs((double)iv1 - py));
-  const double smax = 0.72134752044448170 *
-                      ((A * dxm * dxm + 2.0 * fabs(B) * dxm * dym) +
-                       C * dym * dym);
-  const double marg = 16.0 * 0x1p-24 * smax + 0x1p-19;
-  const double L = 2.0 * log(o / amin) + 2.0 * 0.69314718055994531 * marg;
-  const double hx = sqrt(L * C / det) * (1.0 + 1e-9) + 1e-6;
-  const double hy = sqrt(L * A / det) * (1.0 + 1e-9) + 1e-6;
+  const double det = (double)A * (double)C - (double)B * (double)B;
+  if (!(det > 0.0) || !(A > 0.f) || !(C > 0.f)) return;
+  const float dxm = fmaxf(fabsf(px - (float)iu0), fabsf((float)iu1 - px)) + 1.f;
+  const float dym = fmaxf(fabsf(py - (float)iv0), fabsf((float)iv1 - py)) + 1.f;
+  const float smax = 0.7213475f * ((A * dxm * dxm + 2.f * fabsf(B) * dxm * dym) +
+                                   C * dym * dym) * 1.0001f;
+  const float marg = 16.f * 0x1p-24f * smax + 0x1p-19f;
+  const float L = 2.f * logf(o / amin) + 1.3862944f * marg + 1e-5f;
+  const float idet = (float)(1.0 / det);
+  const float hx = sqrtf(L * C * idet * 1.0001f) * 1.0001f + 1e-3f;
+  const float hy = sqrtf(L * A * idet * 1.0001f) * 1.0001f + 1e-3f;
   if (!isfinite(hx) || !isfinite(hy)) return;
-  ru0 = (int)fmax((double)iu0, ceil(px - hx));
-  ru1 = (int)fmin((double)iu1, floor(px + hx));
-  rv0 = (int)fmax((double)iv0, ceil(py - hy));
-  rv1 = (int)fmin((double)iv1, floor(py + hy));
+  ru0 = (int)fmax((double)iu0, ceil((double)px - (double)hx));
+  ru1 = (int)fmin((double)iu1, floor((double)px + (double)hx));
+  rv0 = (int)fmax((double)iv0, ceil((double)py - (double)hy));
+  rv1 = (int)fmin((double)iv1, floor((double)py + (double)hy));
   if (ru0 > ru1 || rv0 > rv1) {
     ru0 = rv0 = kEmptyPair;
     ru1 = rv1 = 0;
@@ -136,6 +138,10 @@ struct View {
   bool ok;
 };
 
+__device__ inline double T_dot(const double* Trow, const double* Sig, int j) {
+  return Trow[0] * Sig[j] + Trow[1] * Sig[3 + j] + Trow[2] * Sig[6 + j];
+}
+
 __device__ inline void make_view(const gs_camera& cam, double mx, double my,
                                  double mz, const Shape& S, View& P) {
   for (int i = 0; i < 9; ++i) P.W[i] = (double)cam.R[i];
@@ -189,6 +195,57 @@ __device__ inline void make_view(const gs_camera& cam, double mx, double my,
   P.py = (P.fy * ty) / tz + P.cy;
 }
 
+// The view quantities the backward needs, formed with two reciprocals in
+// place of the forward's correctly rounded divisions: the backward only has
+// to be accurate, not reproducible bit for bit.
+__device__ inline void make_view_grad(const gs_camera& cam, double mx,
+                                      double my, double mz, const Shape& S,
+                                      View& P) {
+  for (int i = 0; i < 9; ++i) P.W[i] = (double)cam.R[i];
+  P.fx = (double)cam.fx;
+  P.fy = (double)cam.fy;
+  const double* W = P.W;
+  P.t[0] = ((W[0] * mx + W[1] * my) + W[2] * mz) + (double)cam.t[0];
+  P.t[1] = ((W[3] * mx + W[4] * my) + W[5] * mz) + (double)cam.t[1];
+  P.t[2] = ((W[6] * mx + W[7] * my) + W[8] * mz) + (double)cam.t[2];
+  const double tx = P.t[0], ty = P.t[1], tz = P.t[2];
+  P.ok = isfinite(tx) && isfinite(ty) && isfinite(tz) &&
+         tz > (double)cam.near_z && S.ok;
+  if (!P.ok) return;
+  const double itz = 1.0 / tz;
+  P.limx = 0.65 * (double)cam.width / P.fx;
+  P.limy = 0.65 * (double)cam.height / P.fy;
+  double rx = tx * itz, ry = ty * itz;
+  P.clampx = rx > P.limx ? 1 : rx < -P.limx ? -1 : 0;
+  P.clampy = ry > P.limy ? 1 : ry < -P.limy ? -1 : 0;
+  if (P.clampx) rx = P.clampx * P.limx;
+  if (P.clampy) ry = P.clampy * P.limy;
+  P.xc = rx * tz;
+  P.yc = ry * tz;
+  P.J00 = P.fx * itz;
+  P.J02 = -P.fx * rx * itz;
+  P.J11 = P.fy * itz;
+  P.J12 = -P.fy * ry * itz;
+  for (int j = 0; j < 3; ++j) {
+    P.T[j] = P.J00 * W[j] + P.J02 * W[6 + j];
+    P.T[3 + j] = P.J11 * W[3 + j] + P.J12 * W[6 + j];
+  }
+  double U[6];
+  for (int i = 0; i < 2; ++i)
+    for (int j = 0; j < 3; ++j)
+      U[3 * i + j] = T_dot(P.T + 3 * i, S.Sig, j);
+  P.a = U[0] * P.T[0] + U[1] * P.T[1] + U[2] * P.T[2] + 0.3;
+  P.b = U[0] * P.T[3] + U[1] * P.T[4] + U[2] * P.T[5];
+  P.c = U[3] * P.T[3] + U[4] * P.T[4] + U[5] * P.T[5] + 0.3;
+  P.det = P.a * P.c - P.b * P.b;
+  P.ok = P.det > 0.0 && isfinite(P.det);
+  if (!P.ok) return;
+  const double idet = 1.0 / P.det;
+  P.A = P.c * idet;
+  P.B = -P.b * idet;
+  P.C = P.a * idet;
+}
+
 __global__ __launch_bounds__(256) void k_project(ProjArgs a) {
   const int g = blockIdx.x * 256 + threadIdx.x;
   const int n = min(*a.n_dev, a.cap);
@@ -233,8 +290,13 @@ __global__ __launch_bounds__(256) void k_project(ProjArgs a) {
     int ru0 = iu0, ru1 = iu1, rv0 = iv0, rv1 = iv1;
     if (!a.full_box) render_box(R, iu0, iu1, iv0, iv1, a.amin, ru0, ru1, rv0, rv1);
     a.rbox[slot] = make_int2(ru0 | (ru1 << 16), rv0 | (rv1 << 16));
-    const int tx0 = iu0 / a.tile, tx1 = iu1 / a.tile;
-    const int ty0 = iv0 / a.tile, ty1 = iv1 / a.tile;
+    if (ru0 > ru1) {   // empty render box: nothing to bin
+      a.tiles[slot] = 0;
+      continue;
+    }
+    // The Gaussian is binned into the tiles its render box touches.
+    const int tx0 = ru0 / a.tile, tx1 = ru1 / a.tile;
+    const int ty0 = rv0 / a.tile, ty1 = rv1 / a.tile;
     a.tiles[slot] = (tx1 - tx0 + 1) * (ty1 - ty0 + 1);
     // Tile-coverage difference grid: +1/-1 at the four corners of the box of
     // tiles; a 2D prefix sum then yields the key count of every tile.
@@ -291,7 +353,7 @@ __global__ __launch_bounds__(256) void k_project_bwd(ProjBwdArgs a) {
     if (dpx == 0.0 && dpy == 0.0 && dA == 0.0 && dB == 0.0 && dC == 0.0)
       continue;
     View P;
-    make_view(a.cams[k], mx, my, mz, S, P);
+    make_view_grad(a.cams[k], mx, my, mz, S, P);
     if (!P.ok) continue;
     // Conic -> dilated screen covariance (symmetric matrix gradient).
     const double Q[4] = {P.A, P.B, P.B, P.C};
@@ -400,7 +462,7 @@ hipError_t launch_project(gs_workspace* ws, const gs_params* p,
   a.W = ws->geo.width; a.H = ws->geo.height; a.tile = ws->geo.tile;
   a.Tx = ws->tiles_x; a.Ty = ws->tiles_y;
   a.rec = ws->records; a.tiles = ws->tiles_touched; a.diff = ws->diff;
-  a.rbox = ws->rbox; a.amin = (double)s->alpha_min;
+  a.rbox = ws->rbox; a.amin = s->alpha_min;
   a.full_box = (s->flags & GS_FLAG_FULL_BOX) ? 1 : 0;
   const int blocks = (p->capacity + 255) / 256;
   if (blocks > 0) hipLaunchKernelGGL(k_project, dim3(blocks), dim3(256), 0, st, a);

@@ -56,13 +56,6 @@ __device__ __forceinline__ int4 unpack_box(int2 b) {
   return make_int4(b.x & 0xffff, b.x >> 16, b.y & 0xffff, b.y >> 16);
 }
 
-// Whether render box b (unpacked) meets the pixel rectangle [u0, u1] x
-// [v0, v1].  Empty boxes (lo = 0xffff, hi = 0) meet nothing.
-__device__ __forceinline__ bool box_meets(const int4& b, int u0, int u1,
-                                          int v0, int v1) {
-  return b.x <= u1 && b.y >= u0 && b.z <= v1 && b.w >= v0;
-}
-
 __device__ __forceinline__ void stage(Entry& E, const Record& R,
                                       const int4& box) {
   const float A = R.q0.z, B = R.q0.w, C = R.q1.x;
@@ -70,30 +63,6 @@ __device__ __forceinline__ void stage(Entry& E, const Record& R,
   E.b = make_float4(C * kHalfLog2e, R.q1.y, R.q1.z, R.q1.w);
   E.c = make_float4(R.q2.x, A, B, C);
   E.box = box;
-}
-
-// Order-preserving compaction across a workgroup of NT threads: returns the
-// rank of this thread's item among the kept items of the round (meaningful
-// when keep) and the round's kept count in total.  wcnt is an LDS array of
-// NT / 64 ints.  Every thread of the workgroup must call it.
-template <int NT>
-__device__ __forceinline__ int compact_rank(bool keep, int* wcnt, int& total) {
-  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-  const unsigned long long m = __ballot(keep);
-  const int below = __builtin_amdgcn_mbcnt_hi(
-      (unsigned)(m >> 32), __builtin_amdgcn_mbcnt_lo((unsigned)m, 0u));
-  if (lane == 0) wcnt[w] = __popcll(m);
-  __syncthreads();
-  int off = 0;
-  total = 0;
-#pragma unroll
-  for (int i = 0; i < NT / 64; ++i) {
-    const int c = wcnt[i];
-    off += i < w ? c : 0;
-    total += c;
-  }
-  __syncthreads();   // wcnt is rewritten by the next round
-  return off + below;
 }
 
 // Column part of the exponent for one (entry, thread): dx and the terms that

@@ -145,47 +145,20 @@ __global__ __launch_bounds__(NT) void k_render_bwd(BwdArgs a) {
   const Record* rv = r.rec + (size_t)k * r.cap;
   const int2* rbv = r.rbox + (size_t)k * r.cap;
   float* gk = a.grad2d + (size_t)k * 5 * r.cap;
-  const int tu0 = tx * TILE, tu1 = tu0 + TILE - 1;
-  const int tv0 = ty * TILE, tv1 = tv0 + TILE - 1;
 
-  // Staging, back to front: the list below position hi is read in rounds of
-  // RS entries; entries whose render box misses the tile are dropped and the
-  // rest fill the LDS batch from its top, so slots ascend with list position.
-  constexpr int RS = NT < BATCH ? NT : BATCH;
-  __shared__ int eidx[BATCH];
-  __shared__ int wcnt[NT / 64];
-  int hi = maxlast;
-  while (hi > 0) {
+  for (int hi = maxlast; hi > 0; hi -= BATCH) {
+    const int lo = max(0, hi - BATCH);
+    const int cnt = hi - lo;
     __syncthreads();   // the previous batch is flushed
-    int cnt = 0;
-    while (hi > 0 && cnt + RS <= BATCH) {
-      const int lo = max(0, hi - RS);
-      const int i = lo + tid;
-      bool keep = false;
-      uint32_t g = 0;
-      int4 box = make_int4(0, 0, 0, 0);
-      if (tid < RS && i < hi) {
-        g = r.vals[s + i];
-        box = unpack_box(rbv[g]);
-        keep = box_meets(box, tu0, tu1, tv0, tv1);
-      }
-      int tot;
-      const int rank = compact_rank<NT>(keep, wcnt, tot);
-      if (keep) {
-        const int slot = BATCH - cnt - tot + rank;
-        gid[slot] = g;
-        eidx[slot] = i;
-        stage(ent[slot], rv[g], box);
-      }
-      cnt += tot;
-      hi = lo;
+    for (int i = tid; i < cnt; i += NT) {
+      const uint32_t g = r.vals[s + lo + i];
+      gid[i] = g;
+      stage(ent[i], rv[g], unpack_box(rbv[g]));
     }
-    const int j0 = BATCH - cnt;
-    for (int q = tid; q < cnt * 9; q += NT) (&acc[j0][0])[q] = 0.f;
+    for (int i = tid; i < cnt * 9; i += NT) (&acc[0][0])[i] = 0.f;
     __syncthreads();
-    for (int j = BATCH - 1; j >= j0; --j) {
-      const int pos = eidx[j];
-      if (pos >= wlast) continue;
+    for (int j = min(cnt, wlast - lo) - 1; j >= 0; --j) {
+      const int pos = lo + j;
       const int4 box = ent[j].box;
       if (box.y < fu0 || box.x > fu1 || box.w < fv0 || box.z > fv1) continue;
       const float4 ea = ent[j].a;
@@ -252,9 +225,9 @@ __global__ __launch_bounds__(NT) void k_render_bwd(BwdArgs a) {
     }
     __syncthreads();
     for (int i = tid; i < cnt * 9; i += NT) {
-      const float val = (&acc[j0][0])[i];
+      const float val = (&acc[0][0])[i];
       if (val == 0.f) continue;
-      const int jj = j0 + i / 9, q = i - (i / 9) * 9;
+      const int jj = i / 9, q = i - jj * 9;
       const uint32_t g = gid[jj];
       if (q < 5) atomicAdd(&gk[(size_t)q * r.cap + g], val);
       else if (q == 5) atomicAdd(&a.gop[g], val);

@@ -32,7 +32,7 @@ struct FwdArgs {
 // pixel's T is never zero.  The per-pixel work is predicated rather than
 // branched: every lane evaluates alpha for each of its pixels and the
 // decisions select what is accumulated.  A wave skips an entry outright when
-// the Gaussian's box misses the wave's footprint.
+// its render box misses the wave's footprint.
 template <int TILE, int BATCH, int NT, bool COUNT>
 __global__ __launch_bounds__(NT) void k_render_fwd(FwdArgs a) {
   using Lay = PixLayout<TILE, NT>;
@@ -72,43 +72,20 @@ __global__ __launch_bounds__(NT) void k_render_fwd(FwdArgs a) {
     vf[p] = (float)(v0 + p);
     ib[p] = ib_last[p] = 0;
   }
-  // Staging: the list is read in rounds of RS entries; entries whose render
-  // box misses the tile are dropped (order kept) and the rest fill the LDS
-  // batch with their list position.
-  constexpr int RS = NT < BATCH ? NT : BATCH;
-  __shared__ int eidx[BATCH];
-  __shared__ int wcnt[NT / 64];
   const Record* rv = r.rec + (size_t)k * r.cap;
   const int2* rbv = r.rbox + (size_t)k * r.cap;
-  const int tu0 = tx * TILE, tu1 = tu0 + TILE - 1;
-  const int tv0 = ty * TILE, tv1 = tv0 + TILE - 1;
-  long long pos = s;
-  while (pos < e) {
+  for (long long b0 = s; b0 < e; b0 += BATCH) {
     int alive = 0;
 #pragma unroll
     for (int p = 0; p < PPT; ++p) alive |= T[p] > 0.f;
     if (__syncthreads_or(alive) == 0) break;
-    int cnt = 0;
-    while (pos < e && cnt + RS <= BATCH) {
-      const long long i = pos + tid;
-      bool keep = false;
-      uint32_t g = 0;
-      int4 box = make_int4(0, 0, 0, 0);
-      if (tid < RS && i < e) {
-        g = r.vals[i];
-        box = unpack_box(rbv[g]);
-        keep = box_meets(box, tu0, tu1, tv0, tv1);
-      }
-      int tot;
-      const int slot = cnt + compact_rank<NT>(keep, wcnt, tot);
-      if (keep) {
-        stage(ent[slot], rv[g], box);
-        eidx[slot] = (int)(i - s) + 1;
-      }
-      cnt += tot;
-      pos += RS;
+    const int cnt = (int)min((long long)BATCH, e - b0);
+    for (int i = tid; i < cnt; i += NT) {
+      const uint32_t g = r.vals[b0 + i];
+      stage(ent[i], rv[g], unpack_box(rbv[g]));
     }
     __syncthreads();
+    const int base = (int)(b0 - s) + 1;
     for (int j = 0; j < cnt; ++j) {
       if ((j & 7) == 0) {
         bool any = false;
@@ -135,7 +112,7 @@ __global__ __launch_bounds__(NT) void k_render_fwd(FwdArgs a) {
       const bool in_u = u >= box.x && u <= box.y;
       const int lo = box.z - v0, hi = box.w - v0;
       const Column col = column(ea, uf);
-      const int idx = eidx[j];
+      const int idx = base + j;
 #pragma unroll
       for (int p = 0; p < PPT; ++p) {
         float dy;

@@ -36,8 +36,8 @@ def test_autograd_function_against_fp32_finite_differences():
     relative).  The alpha and transmittance cut-offs are discontinuities that
     no output reveals (one pixel crossing alpha_min moves the loss by
     ~alpha_min), so this check runs with cut-offs of 1e-30 / 1e-35 where
-    every remaining decision (boxes, sorted lists, stop positions) is checked
-    frozen; the cut-off rules are covered by the oracle's frozen-decision
+    every remaining decision (boxes, render boxes, sorted lists, stop
+    positions) is checked frozen; the cut-off rules are covered by the oracle's frozen-decision
     differences and the parity tests.  FP32 rounding of the image gives the
     differences an absolute noise of about 5e-4, hence the floor."""
     w = synth.tiny_scene(32, n=60, width=48, height=40, f=45.0,
@@ -58,7 +58,8 @@ def test_autograd_function_against_fp32_finite_differences():
         nk = rast.status()[1]
         return (rast.ws.tiles_touched().clone(), rast.ws.ranges().clone(),
                 rast.ws.vals_sorted(nk).clone(),
-                rast.ws.records()[..., 10:12].clone())
+                rast.ws.records()[..., 10:12].clone(),
+                rast.ws.render_box().clone())
 
     rast.forward(params)
     dec0 = decisions()

@@ -7,9 +7,10 @@ import torch
 
 import oracle
 import synth
-from gpu_helpers import (check_forward, check_grads, check_records,
-                         check_sort, gpu_backward, gpu_forward, masked_dL,
-                         oracle_backward, oracle_forward)
+from gpu_helpers import (_unpack, check_forward, check_grads, check_records,
+                         check_sort, gpu_backward, gpu_forward,
+                         last_contributors, masked_dL, oracle_backward,
+                         oracle_forward)
 from paper_2504_02437_amd import raster as R
 
 pytestmark = pytest.mark.gpu
@@ -27,7 +28,7 @@ def test_tiny_projection_sort_forward_backward(tile):
     params, rast = gpu_forward(w, tile)
     check_records(rast, proj)
     check_sort(rast, bins)
-    mask, _ = check_forward(rast, fwd)
+    mask, _ = check_forward(rast, fwd, bins)
     dL = masked_dL(np.random.default_rng(2), mask, (1, 3, 45, 70))
     got = gpu_backward(rast, params, dL)
     ref = oracle_backward(w, p64, proj, bins, dL)
@@ -47,7 +48,7 @@ def test_config0_all_launch_shapes(tile, batch, threads):
     params, rast = gpu_forward(w, tile, batch, threads=threads)
     check_records(rast, proj)
     check_sort(rast, bins)
-    mask, _ = check_forward(rast, fwd)
+    mask, _ = check_forward(rast, fwd, bins)
     dL = masked_dL(np.random.default_rng(3), mask, (1, 3, 120, 160), 1e-3)
     got = gpu_backward(rast, params, dL)
     ref = oracle_backward(w, p64, proj, bins, dL)
@@ -74,7 +75,7 @@ def test_multiview_background_ragged():
     params, rast = gpu_forward(w, 16, 256, bg)
     check_records(rast, proj)
     check_sort(rast, bins)
-    mask, _ = check_forward(rast, fwd)
+    mask, _ = check_forward(rast, fwd, bins)
     dL = masked_dL(np.random.default_rng(5), mask, (3, 3, 53, 77))
     got = gpu_backward(rast, params, dL)
     ref = oracle_backward(w, p64, proj, bins, dL, bg)
@@ -88,7 +89,7 @@ def test_equal_depth_ties():
     p64, proj, bins, fwd = oracle_forward(w, 16)
     params, rast = gpu_forward(w, 16)
     check_sort(rast, bins)
-    check_forward(rast, fwd)
+    check_forward(rast, fwd, bins)
 
 
 def test_empty_and_all_culled():
@@ -124,7 +125,7 @@ def test_key_overflow_sets_status_and_stays_in_bounds():
     p64, proj, bins, fwd = oracle_forward(w, 16)
     cap = bins["n_keys"] // 2
     print("case overflow", cap, flush=True)
-    params, rast = gpu_forward(w, 16, key_capacity=cap)
+    params, rast = gpu_forward(w, 16, key_capacity=cap, full_box=True)
     flags, nk = rast.status(clear=True)
     assert flags & 1
     assert nk == bins["n_keys"]
@@ -152,7 +153,7 @@ def test_config1_full_size():
     params, rast = gpu_forward(w, 16, 256)
     check_records(rast, proj)
     check_sort(rast, bins)
-    mask, err = check_forward(rast, fwd)
+    mask, err = check_forward(rast, fwd, bins)
     print("config1 max image error", err, "flagged", 1 - mask.mean(), flush=True)
     dL = masked_dL(np.random.default_rng(11), mask, (1, 3, 680, 1200),
                    1.0 / (3 * 680 * 1200))
@@ -201,17 +202,12 @@ def test_long_tile_lists_use_the_global_sort_path():
     p64, proj, bins, fwd = oracle_forward(w, 16)
     r = bins["ranges"]
     assert (r[:, 1] - r[:, 0]).max() > 4096
-    params, rast = gpu_forward(w, 16)
+    params, rast = gpu_forward(w, 16, full_box=True)
     check_records(rast, proj)
     check_sort(rast, bins)
     # Thousands of faint entries per pixel widen the transmittance error
     # bound, so more pixels are FP32-ambiguous here than in real scenes.
-    check_forward(rast, fwd, max_flagged=0.05)
-
-
-def _unpack(rb):
-    return np.stack([rb[..., 0] & 0xFFFF, rb[..., 0] >> 16,
-                     rb[..., 1] & 0xFFFF, rb[..., 1] >> 16], -1)
+    check_forward(rast, fwd, bins, max_flagged=0.05)
 
 
 def _same_render(w, tile, batch, threads, n_check_grads=True, rtol=1e-4):
@@ -219,11 +215,24 @@ def _same_render(w, tile, batch, threads, n_check_grads=True, rtol=1e-4):
     _, full = gpu_forward(w, tile, batch, params=params, threads=threads,
                           full_box=True)
     _, cut = gpu_forward(w, tile, batch, params=params, threads=threads)
-    for a, b in ((full.rgb, cut.rgb), (full.T, cut.T), (full.nlast, cut.nlast)):
+    for a, b in ((full.rgb, cut.rgb), (full.T, cut.T)):
         assert torch.equal(a, b)
+    # Shorter lists, same last contributor at every pixel.
+    lasts = []
+    for r in (full, cut):
+        _, nk = r.status()
+        lasts.append(last_contributors(
+            r.nlast.cpu().numpy(), r.ws.ranges().cpu().numpy().view(np.uint32),
+            r.ws.vals_sorted(nk).cpu().numpy().view(np.uint32), tile,
+            r.ws.tiles_x, r.ws.tiles_y))
+    np.testing.assert_array_equal(lasts[0], lasts[1])
+    assert torch.all(cut.nlast <= full.nlast)
+    _, nk_full = full.status()
+    _, nk_cut = cut.status()
+    assert nk_cut <= nk_full
     # The render box lies inside the integer box; empty ones are encoded as
     # lo = 0xffff, hi = 0.
-    vis = cut.ws.tiles_touched().cpu().numpy() > 0
+    vis = full.ws.tiles_touched().cpu().numpy() > 0
     rb = _unpack(cut.ws.render_box().cpu().numpy())[vis]
     rec = cut.ws.records().cpu().numpy()
     box = _unpack(np.stack([rec[..., 10].view(np.int32),
@@ -253,8 +262,9 @@ def _same_render(w, tile, batch, threads, n_check_grads=True, rtol=1e-4):
     (32, 128, 256), (32, 256, 128)])
 def test_render_box_changes_nothing(tile, batch, threads):
     """Render boxes drop only pairs whose FP32 alpha cannot reach alpha_min:
-    images, T_final and n_last are bit-identical to whole-box rendering and
-    the gradients agree to FP32 summation order."""
+    images and T_final are bit-identical to whole-box rendering, every
+    pixel's last contributor is the same Gaussian, and the gradients agree to
+    FP32 summation order."""
     print("case render box config0", tile, batch, threads, flush=True)
     ratio = _same_render(synth.config0(), tile, batch, threads)
     assert ratio < 1.0
