@@ -11,6 +11,7 @@
 
 #include <math.h>
 
+#include "admit.h"
 #include "gs_internal.h"
 
 namespace gs {
@@ -36,39 +37,24 @@ struct ProjArgs {
 
 constexpr int kEmptyPair = 0xffff;   // u_lo = 0xffff, u_hi = 0
 
-// Render box: the integer box narrowed to the pixels where the compositing
-// kernels can admit the Gaussian.  They admit a pair only when their FP32
-// alpha = min(alpha_max, o * exp2(e2)) reaches alpha_min, with e2 the FP32
-// evaluation of -log2(e)/2 * q(d), q(d) = A dx^2 + 2 B dx dy + C dy^2 over
-// the published record.  Its rounding error is below 8 u S (u = 2^-24, S the
-// sum of the magnitudes of the three terms), and exp2 and the product with o
-// add less than 2^-20 relative.  So an admitted pixel satisfies
-//   q(d) <= 2 ln(o / alpha_min) + 2 ln(2) (16 u S_max + 2^-19) =: L,
-// with S_max bounding S over the box, and lies in the bounding box of the
-// ellipse q(d) <= L: |dx| <= sqrt(L C / det), |dy| <= sqrt(L A / det) with
-// det = A C - B^2 (the inverse conic's diagonal).  det is formed in FP64
-// (the products of FP32 values are exact there); the rest runs in FP32 with
-// relative and absolute slack well above its rounding, and the final bounds
-// in FP64.
+// Render box: the integer box narrowed to the bounding box of the ellipse
+// q(d) <= L (admit.h) outside which no pixel is admitted: |dx| <=
+// sqrt(L C / det), |dy| <= sqrt(L A / det) with det = A C - B^2 (the inverse
+// conic's diagonal).  det is formed in FP64 (exact products of FP32 values),
+// the root in FP32 with slack, the final bounds in FP64.
 __device__ inline void render_box(const Record& R, int iu0, int iu1, int iv0,
                                   int iv1, float amin, int& ru0, int& ru1,
                                   int& rv0, int& rv1) {
   ru0 = iu0; ru1 = iu1; rv0 = iv0; rv1 = iv1;
-  const float px = R.q0.x, py = R.q0.y, A = R.q0.z, B = R.q0.w;
-  const float C = R.q1.x, o = R.q1.y;
-  if (!(o >= amin * (1.f - 0x1p-19f))) {   // o * G < alpha_min everywhere
+  const float L = admit_level(R, iu0, iu1, iv0, iv1, amin);
+  if (L == kNoPixel) {
     ru0 = rv0 = kEmptyPair;
     ru1 = rv1 = 0;
     return;
   }
+  if (!(L < INFINITY)) return;
+  const float px = R.q0.x, py = R.q0.y, A = R.q0.z, B = R.q0.w, C = R.q1.x;
   const double det = (double)A * (double)C - (double)B * (double)B;
-  if (!(det > 0.0) || !(A > 0.f) || !(C > 0.f)) return;
-  const float dxm = fmaxf(fabsf(px - (float)iu0), fabsf((float)iu1 - px)) + 1.f;
-  const float dym = fmaxf(fabsf(py - (float)iv0), fabsf((float)iv1 - py)) + 1.f;
-  const float smax = 0.7213475f * ((A * dxm * dxm + 2.f * fabsf(B) * dxm * dym) +
-                                   C * dym * dym) * 1.0001f;
-  const float marg = 16.f * 0x1p-24f * smax + 0x1p-19f;
-  const float L = 2.f * logf(o / amin) + 1.3862944f * marg + 1e-5f;
   const float idet = (float)(1.0 / det);
   const float hx = sqrtf(L * C * idet * 1.0001f) * 1.0001f + 1e-3f;
   const float hy = sqrtf(L * A * idet * 1.0001f) * 1.0001f + 1e-3f;

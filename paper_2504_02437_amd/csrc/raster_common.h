@@ -13,6 +13,7 @@
 // which keeps a Gaussian's box test coherent across the wave.
 #pragma once
 
+#include "admit.h"
 #include "gs_internal.h"
 
 namespace gs {
@@ -65,6 +66,31 @@ __device__ __forceinline__ void stage(Entry& E, const Record& R,
   E.box = box;
 }
 
+// Bit w is set when wave w of a tile whose top-left pixel is (tu0, tv0) has
+// to evaluate the staged entry: its footprint meets the render box rb and,
+// with the ellipse test, the ellipse q(d) <= L outside which no pixel is
+// admitted (admit.h).  Computed once per staged entry.
+template <int TILE, int NT>
+__device__ inline int wave_mask(const Record& R, const int4& rb, int tu0,
+                                int tv0, float amin, bool ellipse) {
+  using Lay = PixLayout<TILE, NT>;
+  float L = INFINITY;
+  if (ellipse) {
+    const int bu = __float_as_int(R.q2.z), bv = __float_as_int(R.q2.w);
+    L = admit_level(R, bu & 0xffff, bu >> 16, bv & 0xffff, bv >> 16, amin);
+  }
+  int m = 0;
+#pragma unroll
+  for (int w = 0; w < NT / 64; ++w) {
+    int wu, wv;
+    Lay::wave_origin(w, wu, wv);
+    const int u0 = max(rb.x, tu0 + wu), u1 = min(rb.y, tu0 + wu + Lay::WC - 1);
+    const int v0 = max(rb.z, tv0 + wv), v1 = min(rb.w, tv0 + wv + Lay::FH - 1);
+    if (ellipse_meets(R, L, u0, u1, v0, v1)) m |= 1 << w;
+  }
+  return m;
+}
+
 // Column part of the exponent for one (entry, thread): dx and the terms that
 // depend on dx only.
 struct Column {
@@ -91,6 +117,7 @@ __device__ __forceinline__ float exponent2(const Column& c, float py, float C2,
 struct RasterArgs {
   const Record* rec;
   const int2* rbox;
+  int ellipse_test;   // 0 with GS_FLAG_FULL_BOX
   const uint32_t* vals;
   const uint32_t* ranges;
   long long key_cap;

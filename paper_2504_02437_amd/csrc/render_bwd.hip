@@ -84,7 +84,7 @@ __device__ __forceinline__ int wave_max(int x) {
 // The per-pixel work is predicated like the forward's: every lane evaluates
 // its pixels for each entry and the admit decision selects what is
 // accumulated.  A wave starts its backward walk at the largest n_last of its
-// own pixels and skips entries whose box misses its footprint.
+// own pixels and skips entries no pixel of its footprint can admit.
 template <int TILE, int BATCH, int NT>
 __global__ __launch_bounds__(NT) void k_render_bwd(BwdArgs a) {
   using Lay = PixLayout<TILE, NT>;
@@ -107,13 +107,12 @@ __global__ __launch_bounds__(NT) void k_render_bwd(BwdArgs a) {
   tile_range(r, t, s, e);
   const size_t HW = (size_t)r.H * r.W;
 
-  int cu, cv0, wu, wv;
+  int cu, cv0;
   Lay::of(tid, cu, cv0);
-  Lay::wave_origin(tid >> 6, wu, wv);
   const int u = tx * TILE + cu;
   const int v0 = ty * TILE + cv0;
-  const int fu0 = tx * TILE + wu, fu1 = fu0 + Lay::WC - 1;
-  const int fv0 = ty * TILE + wv, fv1 = fv0 + Lay::FH - 1;
+  const int wave = tid >> 6;
+  __shared__ int wmask[BATCH];   // per staged entry: waves that evaluate it
   const float uf = (float)u;
   const float amax = r.alpha_max, amin = r.alpha_min;
   int last[PPT];
@@ -153,14 +152,18 @@ __global__ __launch_bounds__(NT) void k_render_bwd(BwdArgs a) {
     for (int i = tid; i < cnt; i += NT) {
       const uint32_t g = r.vals[s + lo + i];
       gid[i] = g;
-      stage(ent[i], rv[g], unpack_box(rbv[g]));
+      const Record R = rv[g];
+      const int4 box = unpack_box(rbv[g]);
+      stage(ent[i], R, box);
+      wmask[i] = wave_mask<TILE, NT>(R, box, tx * TILE, ty * TILE, amin,
+                                     r.ellipse_test);
     }
     for (int i = tid; i < cnt * 9; i += NT) (&acc[0][0])[i] = 0.f;
     __syncthreads();
     for (int j = min(cnt, wlast - lo) - 1; j >= 0; --j) {
       const int pos = lo + j;
+      if (!((wmask[j] >> wave) & 1)) continue;
       const int4 box = ent[j].box;
-      if (box.y < fu0 || box.x > fu1 || box.w < fv0 || box.z > fv1) continue;
       const float4 ea = ent[j].a;
       const float4 eb = ent[j].b;
       const float4 ec = ent[j].c;

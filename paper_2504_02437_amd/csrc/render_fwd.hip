@@ -32,7 +32,7 @@ struct FwdArgs {
 // pixel's T is never zero.  The per-pixel work is predicated rather than
 // branched: every lane evaluates alpha for each of its pixels and the
 // decisions select what is accumulated.  A wave skips an entry outright when
-// its render box misses the wave's footprint.
+// no pixel of its footprint can admit it (wave_mask).
 template <int TILE, int BATCH, int NT, bool COUNT>
 __global__ __launch_bounds__(NT) void k_render_fwd(FwdArgs a) {
   using Lay = PixLayout<TILE, NT>;
@@ -48,15 +48,12 @@ __global__ __launch_bounds__(NT) void k_render_fwd(FwdArgs a) {
   long long s, e;
   tile_range(r, t, s, e);
 
-  int cu, cv0, wu, wv;
+  int cu, cv0;
   Lay::of(tid, cu, cv0);
-  Lay::wave_origin(tid >> 6, wu, wv);
   const int u = tx * TILE + cu;
   const int v0 = ty * TILE + cv0;
-  // The wave's footprint: an entry whose box misses it is skipped by the
-  // whole wave.
-  const int fu0 = tx * TILE + wu, fu1 = fu0 + Lay::WC - 1;
-  const int fv0 = ty * TILE + wv, fv1 = fv0 + Lay::FH - 1;
+  const int wave = tid >> 6;
+  __shared__ int wmask[BATCH];   // per staged entry: waves that evaluate it
   const float uf = (float)u;
   const float amax = __builtin_canonicalizef(r.alpha_max);
   const float amin = r.alpha_min, tmin = r.T_min;
@@ -82,7 +79,11 @@ __global__ __launch_bounds__(NT) void k_render_fwd(FwdArgs a) {
     const int cnt = (int)min((long long)BATCH, e - b0);
     for (int i = tid; i < cnt; i += NT) {
       const uint32_t g = r.vals[b0 + i];
-      stage(ent[i], rv[g], unpack_box(rbv[g]));
+      const Record R = rv[g];
+      const int4 box = unpack_box(rbv[g]);
+      stage(ent[i], R, box);
+      wmask[i] = wave_mask<TILE, NT>(R, box, tx * TILE, ty * TILE, amin,
+                                     r.ellipse_test);
     }
     __syncthreads();
     const int base = (int)(b0 - s) + 1;
@@ -94,18 +95,20 @@ __global__ __launch_bounds__(NT) void k_render_fwd(FwdArgs a) {
         if (!__any(any)) break;
       }
       const int4 box = ent[j].box;
+      const bool evaluate = (wmask[j] >> wave) & 1;
       if (COUNT) {
 #pragma unroll
         for (int p = 0; p < PPT; ++p) {
           if (!(T[p] > 0.f)) continue;
           ++n_exam;
-          if (u >= box.x && u <= box.y && v0 + p >= box.z && v0 + p <= box.w) {
+          if (evaluate && u >= box.x && u <= box.y && v0 + p >= box.z &&
+              v0 + p <= box.w) {
             ++n_inbox;
             ++ib[p];
           }
         }
       }
-      if (box.y < fu0 || box.x > fu1 || box.w < fv0 || box.z > fv1) continue;
+      if (!evaluate) continue;
       const float4 ea = ent[j].a;
       const float4 eb = ent[j].b;
       const float ecb = ent[j].c.x;
@@ -181,6 +184,7 @@ struct FwdLauncher {
 RasterArgs make_raster_args(gs_workspace* ws, const gs_settings* s) {
   RasterArgs r;
   r.rec = ws->records; r.rbox = ws->rbox;
+  r.ellipse_test = (s->flags & GS_FLAG_FULL_BOX) ? 0 : 1;
   r.vals = ws->vals_sorted; r.ranges = ws->ranges;
   r.key_cap = ws->geo.key_capacity; r.cap = ws->geo.capacity;
   r.V = ws->geo.n_views; r.W = ws->geo.width; r.H = ws->geo.height;
