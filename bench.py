@@ -35,6 +35,31 @@ LR = (1.6e-4, 5e-3, 1e-3, 5e-2, 2.5e-3)   # mean, log_scale, quat, opacity, rgb
 LAMBDA_COLOR, LAMBDA_REG, REG_FLOOR = 1.0, 1.0, 0.01
 
 
+TRAFFIC_FILE = os.path.join(ROOT, "profiles",
+                            "render_window10-1200x680-300k_tile32_counters.txt")
+
+
+def measured_traffic(kernel):
+    """HBM bytes per dispatch of `kernel` from the committed rocprofv3
+    counter summary (FETCH_SIZE and WRITE_SIZE scaled by a known-size copy),
+    or None when the summary is for another kernel or the kernel's sources
+    changed since the counters were taken."""
+    import hashlib
+    try:
+        kv = dict(l.split(": ", 1) for l in open(TRAFFIC_FILE).read().splitlines()
+                  if l and not l.startswith("#") and ": " in l)
+        if not kv["traffic_kernel"].startswith(kernel + ">"):
+            return None
+        h = hashlib.sha256()
+        for src in kv["traffic_sources"].split():
+            h.update(open(os.path.join(ROOT, src), "rb").read())
+        if h.hexdigest() != kv["traffic_sources_sha256"].strip():
+            return None
+        return int(kv["traffic_bytes"])
+    except (OSError, KeyError, ValueError):
+        return None
+
+
 def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
@@ -317,7 +342,10 @@ def main():
         "pairs_full_box": cnt_full,
         "roofline": {"bound": "alu", "kernel": dom, "achieved": achieved,
                      "peak": peak, "unit": "Tlane-op/s",
-                     "frac": achieved / peak, "traffic": None,
+                     "frac": achieved / peak,
+                     "traffic": measured_traffic(
+                         f"k_render_{dom[7:]}<{S.tile}, {S.lds_batch}, "
+                         f"{S.block_threads or (256 if S.tile == 32 else 64)}"),
                      "ops_per_launch": ops,
                      "render_fwd_frac": fwd_ops / (kern["render_fwd"] * 1e-3) / PEAK_LANE_OPS,
                      "render_bwd_frac": bwd_ops / (kern["render_bwd"] * 1e-3) / PEAK_LANE_OPS},
