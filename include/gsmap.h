@@ -258,6 +258,21 @@ GS_API int gs_loss_l1(const float* rgb, const float* target, int32_t n_views,
                int32_t height, int32_t width, float lambda, float* dL_drgb,
                double* loss_dev, double* sqerr_dev, void* stream);
 
+/* Structural-similarity term of the colour loss (Eq. 10, the term weighted
+ * by lambda_photo): per view and channel, SSIM over an 11 x 11 Gaussian
+ * window (sigma 1.5, normalised; samples outside the image are 0) with
+ * C1 = 0.01^2, C2 = 0.03^2.  ADDS lambda * sum over views of (1 - mean SSIM
+ * over 3HW) to *loss_dev (device double), ADDS its gradient into dL_drgb
+ * (call after gs_loss_l1, which writes it), and ADDS each view's mean SSIM
+ * into ssim_dev[n_views] (device double, may be NULL).
+ *   rgb, target, dL_drgb  device float [n_views][3][height][width]
+ *   scratch               device float [3][n_views][3][height][width],
+ *                         caller-owned, overwritten */
+GS_API int gs_loss_ssim(const float* rgb, const float* target, int32_t n_views,
+                        int32_t height, int32_t width, float lambda,
+                        float* dL_drgb, double* loss_dev, double* ssim_dev,
+                        float* scratch, void* stream);
+
 /* Planar regulariser of Eq. 10-11: lambda * mean over live Gaussians of
  * max(floor, min_j exp(log_scale_j)).  ADDS its gradient into
  * grad->log_scale (smallest axis only, lowest index on ties, only where the

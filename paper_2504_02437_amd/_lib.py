@@ -84,6 +84,8 @@ _SIGS = {
                                  _vp]),
     "gs_loss_l1": (C.c_int, [_vp, _vp, C.c_int32, C.c_int32, C.c_int32,
                              C.c_float, _vp, _vp, _vp, _vp]),
+    "gs_loss_ssim": (C.c_int, [_vp, _vp, C.c_int32, C.c_int32, C.c_int32,
+                               C.c_float, _vp, _vp, _vp, _vp, _vp]),
     "gs_planar_reg": (C.c_int, [_P(gs_params), C.c_float, C.c_float,
                                 _P(gs_params), _vp, _vp]),
     "gs_adam": (C.c_int, [_P(gs_params), _P(gs_params), _P(gs_params),

@@ -40,6 +40,7 @@ UNITS = [
     ("render_fwd.hip", NO_CONTRACT),
     ("render_bwd.hip", NO_CONTRACT + NO_ATOMIC_OPT),
     ("optim.hip", []),
+    ("ssim.hip", []),
     ("mlp.hip", NO_CONTRACT),
 ]
 

@@ -333,6 +333,19 @@ int gs_loss_l1(const float* rgb, const float* target, int32_t n_views,
                 "loss_l1");
 }
 
+int gs_loss_ssim(const float* rgb, const float* target, int32_t n_views,
+                 int32_t height, int32_t width, float lambda, float* dL_drgb,
+                 double* loss_dev, double* ssim_dev, float* scratch,
+                 void* stream) {
+  g_err[0] = 0;
+  if (!rgb || !target || !dL_drgb || !loss_dev || !scratch) { set_error("an argument is NULL"); return GS_E_INVALID; }
+  if (n_views < 1 || height < 1 || width < 1 || n_views > 21845) { set_error("bad image size"); return GS_E_INVALID; }
+  return finish(launch_loss_ssim(rgb, target, n_views, height, width, lambda,
+                                 dL_drgb, loss_dev, ssim_dev, scratch,
+                                 (hipStream_t)stream),
+                "loss_ssim");
+}
+
 int gs_planar_reg(const gs_params* params, float lambda, float floor_,
                   gs_params* grad, double* loss_dev, void* stream) {
   g_err[0] = 0;

@@ -29,6 +29,9 @@ struct Counters {
   int pad;
 };
 
+hipError_t launch_loss_ssim(const float* rgb, const float* target, int V,
+                            int H, int W, float lam, float* dL, double* loss,
+                            double* ssim, float* scratch, hipStream_t st);
 hipError_t launch_knn_features(const gs_params* p, const gs_camera* cam, int W,
                                int H, const float* kf_rgb, const float* pts,
                                int n_pts, int centre_only, float* feats,

@@ -282,6 +282,32 @@ def loss_l1(rgb, target, lam, dL_drgb, loss_dev, sqerr_dev=None, stream=None):
            _ptr(dL_drgb), _ptr(loss_dev), _ptr(sqerr_dev), _stream(stream))
 
 
+def ssim_scratch(rgb):
+    """Scratch buffer gs_loss_ssim needs for images shaped like `rgb`."""
+    return torch.empty((3,) + tuple(rgb.shape), dtype=torch.float32,
+                       device=rgb.device)
+
+
+def loss_ssim(rgb, target, lam, dL_drgb, loss_dev, ssim_dev=None, scratch=None,
+              stream=None):
+    """ADDS lam * sum_views (1 - mean SSIM) to loss_dev and its gradient to
+    dL_drgb (after loss_l1, which writes dL_drgb)."""
+    V, _, H, W = rgb.shape
+    for t, nm in ((rgb, "rgb"), (target, "target"), (dL_drgb, "dL_drgb")):
+        _require_cuda(t, nm)
+        if t.shape != rgb.shape or t.dtype != torch.float32 or not t.is_contiguous():
+            raise ValueError(f"{nm} must be contiguous float32 of shape {tuple(rgb.shape)}")
+    if loss_dev.dtype != torch.float64:
+        raise ValueError("loss_dev must be float64")
+    if scratch is None:
+        scratch = ssim_scratch(rgb)
+    if scratch.numel() < 3 * rgb.numel() or scratch.dtype != torch.float32:
+        raise ValueError("scratch must hold 3 * rgb.numel() float32")
+    L.call("gs_loss_ssim", _ptr(rgb), _ptr(target), V, H, W, float(lam),
+           _ptr(dL_drgb), _ptr(loss_dev), _ptr(ssim_dev), _ptr(scratch),
+           _stream(stream))
+
+
 def planar_reg(params, lam, floor, grad, loss_dev, stream=None):
     L.call("gs_planar_reg", C.byref(params.struct()), float(lam), float(floor),
            C.byref(grad.struct()), _ptr(loss_dev), _stream(stream))

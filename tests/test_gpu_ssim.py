@@ -1,0 +1,83 @@
+"""GPU structural-similarity term (Eq. 10) against the FP64 oracle: loss and
+per-view mean SSIM within 1e-5 relative, gradient within 1e-3 relative
+(floor 1e-2 of the largest), on ragged multi-view images, degenerate sizes
+and the full 1200x680 view."""
+import numpy as np
+import pytest
+import torch
+
+from oracle import ssim as OS
+from paper_2504_02437_amd import raster as R
+
+pytestmark = pytest.mark.gpu
+
+
+def _pair(seed, shape, noise=0.15):
+    rng = np.random.default_rng(seed)
+    y = rng.uniform(size=shape).astype(np.float32)
+    # Smooth structure plus noise, so windows see both.
+    V, C, H, W = shape
+    yy, xx = np.mgrid[0:H, 0:W]
+    y = (0.5 + 0.4 * np.sin(xx / 7.0 + yy / 11.0))[None, None] * y
+    x = np.clip(y + noise * rng.normal(size=shape), 0, 1).astype(np.float32)
+    return x, y.astype(np.float32)
+
+
+def _gpu(x, y, lam, base=None):
+    xd, yd = torch.from_numpy(x).cuda(), torch.from_numpy(y).cuda()
+    dL = torch.from_numpy(base if base is not None else np.zeros_like(x)).cuda()
+    loss = torch.zeros(1, dtype=torch.float64, device="cuda")
+    ssim = torch.zeros(x.shape[0], dtype=torch.float64, device="cuda")
+    R.loss_ssim(xd, yd, lam, dL, loss, ssim)
+    torch.cuda.synchronize()
+    return float(loss), ssim.cpu().numpy(), dL.cpu().numpy()
+
+
+def _check(x, y, lam=0.2):
+    got_loss, got_ssim, got_g = _gpu(x, y, lam)
+    ref_loss, ref_g = OS.loss_ssim(x.astype(np.float64), y.astype(np.float64), lam)
+    ref_ssim = OS.ssim_map(x, y).reshape(x.shape[0], -1).mean(1)
+    assert abs(got_loss - ref_loss) <= 1e-5 * max(abs(ref_loss), 1e-3), \
+        (got_loss, ref_loss)
+    assert np.abs(got_ssim - ref_ssim).max() <= 1e-5, (got_ssim, ref_ssim)
+    tol = 1e-3 * np.maximum(np.abs(ref_g), 1e-2 * np.abs(ref_g).max()) + 1e-30
+    bad = np.argwhere(np.abs(got_g - ref_g) > tol)
+    assert bad.size == 0, (bad[:5], got_g[tuple(bad[0])], ref_g[tuple(bad[0])])
+    return got_loss
+
+
+def test_ragged_multiview():
+    """Two views of 45 x 70: several 64 x 16 tiles with ragged right and
+    bottom edges."""
+    x, y = _pair(1, (2, 3, 45, 70))
+    print("case ssim ragged", flush=True)
+    _check(x, y, 0.2)
+
+
+def test_gradient_adds_to_what_dL_held():
+    x, y = _pair(2, (2, 3, 45, 70))
+    base = np.random.default_rng(2).normal(size=x.shape).astype(np.float32)
+    _, _, g0 = _gpu(x, y, 0.2)
+    _, _, g1 = _gpu(x, y, 0.2, base)
+    np.testing.assert_array_equal(g1, base + g0)
+
+
+def test_identical_images_give_zero_loss_and_gradient():
+    x, _ = _pair(3, (1, 3, 40, 33))
+    loss, ssim, g = _gpu(x, x, 0.2)
+    assert abs(loss) < 1e-5 and np.all(np.abs(ssim - 1.0) < 1e-5)
+    assert np.abs(g).max() < 1e-6
+
+
+@pytest.mark.parametrize("shape", [(1, 3, 1, 1), (1, 3, 4, 130), (3, 3, 17, 3)])
+def test_images_smaller_than_the_window(shape):
+    x, y = _pair(4, shape)
+    print("case ssim tiny", shape, flush=True)
+    _check(x, y)
+
+
+def test_full_size_view():
+    """The 1200 x 680 view the benchmark renders, every pixel compared."""
+    x, y = _pair(5, (1, 3, 680, 1200))
+    print("case ssim full size", flush=True)
+    _check(x, y)
