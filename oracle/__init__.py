@@ -51,7 +51,8 @@ def lib():
         L.or_forward.argtypes = [C.c_int, C.c_int, C.c_int, C.c_int, C.c_int,
                                  _d, _i32, _d, _u32, _u32, _d, C.c_double,
                                  C.c_double, C.c_double, _d, _d, _i32, _u8, _d,
-                                 _d, _i64, _u8, C.c_int, C.c_int, C.c_int]
+                                 _d, _i64, _u8, C.c_int, C.c_int, _i32, _d, _d,
+                                 _d, C.c_int]
         L.or_backward.restype = C.c_int
         L.or_backward.argtypes = [C.c_int, C.c_int, C.c_int, C.c_int, C.c_int,
                                   _d, _i32, _d, _u32, _u32, _d, C.c_double,
@@ -150,7 +151,10 @@ def bin_sort(proj, tile, W, H, cap=None, emit=True):
 def forward(proj, bins, rgb, W, H, bg=(0.0, 0.0, 0.0), alpha_min=ALPHA_MIN,
             T_min=T_MIN, alpha_max=ALPHA_MAX, dec=None, dec_mode=0,
             nthreads=1):
-    """Front-to-back compositing (Eq. 3) over each tile's sorted list."""
+    """Front-to-back compositing (Eq. 3) over each tile's sorted list; also
+    the dominant Gaussian of every pixel (Eq. 8): "dom" (index, -1 if none),
+    "w1" its blend weight, "w2" the runner-up weight, "werr" a relative FP32
+    error bound of the weights."""
     L = lib()
     V, n = proj["tiles"].shape
     img = np.zeros((V, 3, H, W))
@@ -160,6 +164,10 @@ def forward(proj, bins, rgb, W, H, bg=(0.0, 0.0, 0.0), alpha_min=ALPHA_MIN,
     errb = np.zeros((V, H, W))
     terr = np.zeros((V, H, W))
     cnt = np.zeros(4, np.int64)
+    dom = np.zeros((V, H, W), np.int32)
+    w1 = np.zeros((V, H, W))
+    w2 = np.zeros((V, H, W))
+    werr = np.zeros((V, H, W))
     bgv = np.asarray(bg, np.float64)
     Ld = 0 if dec is None else dec.shape[-1]
     rgb = np.ascontiguousarray(rgb, np.float64)
@@ -169,10 +177,12 @@ def forward(proj, bins, rgb, W, H, bg=(0.0, 0.0, 0.0), alpha_min=ALPHA_MIN,
                       _p(bins["ranges"], _u32), _p(bgv, _d), alpha_min, T_min,
                       alpha_max, _p(img, _d), _p(T, _d), _p(nlast, _i32),
                       _p(flags, _u8), _p(errb, _d), _p(terr, _d), _p(cnt, _i64),
-                      _p(dec, _u8), Ld, dec_mode, nthreads)
+                      _p(dec, _u8), Ld, dec_mode, _p(dom, _i32), _p(w1, _d),
+                      _p(w2, _d), _p(werr, _d), nthreads)
     if rc != 0:
         raise ValueError("decision buffer too short")
     return dict(img=img, T=T, nlast=nlast, flags=flags, errb=errb, terr=terr,
+                dom=dom, w1=w1, w2=w2, werr=werr,
                 counters=dict(examined=int(cnt[0]), inbox=int(cnt[1]),
                               contributing=int(cnt[2]), revisit=int(cnt[3])))
 

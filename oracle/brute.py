@@ -14,7 +14,10 @@ import numpy as np
 
 
 def composite(rec, box, rgb, W, H, bg=(0.0, 0.0, 0.0), alpha_min=None,
-              T_min=None, alpha_max=None):
+              T_min=None, alpha_max=None, with_dominant=False):
+    """Returns (image, T_final, contributor count) and, with_dominant, also
+    the Gaussian of largest blend weight alpha * T per pixel (Eq. 8; first
+    on ties, -1 when none)."""
     from . import ALPHA_MAX, ALPHA_MIN, T_MIN
     alpha_min = ALPHA_MIN if alpha_min is None else alpha_min
     T_min = T_MIN if T_min is None else T_min
@@ -23,6 +26,7 @@ def composite(rec, box, rgb, W, H, bg=(0.0, 0.0, 0.0), alpha_min=None,
     img = np.zeros((V, 3, H, W))
     Tf = np.ones((V, H, W))
     ncontrib = np.zeros((V, H, W), np.int64)
+    dominant = np.full((V, H, W), -1, np.int64)
     for k in range(V):
         depth_bits = rec[k, :, 6].astype(np.float32).view(np.uint32)
         for v in range(H):
@@ -34,6 +38,7 @@ def composite(rec, box, rgb, W, H, bg=(0.0, 0.0, 0.0), alpha_min=None,
                 T = 1.0
                 C = [0.0, 0.0, 0.0]
                 cnt = 0
+                wbest, gbest = 0.0, -1
                 for g in order:
                     px, py, A, B, Cc, o = rec[k, g, :6]
                     dx, dy = px - u, py - v
@@ -48,10 +53,15 @@ def composite(rec, box, rgb, W, H, bg=(0.0, 0.0, 0.0), alpha_min=None,
                         break
                     for ch in range(3):
                         C[ch] += rgb[ch, g] * a * T
+                    if a * T > wbest:
+                        wbest, gbest = a * T, int(g)
                     T = Tn
                     cnt += 1
                 for ch in range(3):
                     img[k, ch, v, u] = C[ch] + T * bg[ch]
                 Tf[k, v, u] = T
                 ncontrib[k, v, u] = cnt
+                dominant[k, v, u] = gbest
+    if with_dominant:
+        return img, Tf, ncontrib, dominant
     return img, Tf, ncontrib

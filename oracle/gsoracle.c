@@ -385,7 +385,12 @@ static int eval_pair(const fwdcfg* F, const double* r, const int32_t* b,
  * entry), in-box pairs among them, contributing pairs, and in-box pairs at
  * positions before n_last (the ones a backward pass revisits).
  * dec (optional) [V][H][W][L]: decision codes recorded (dec_mode 1) or
- * replayed (dec_mode 2) per list position. */
+ * replayed (dec_mode 2) per list position.
+ * Dominant Gaussian (Eq. 8, optional): dom [V][H][W] receives the index of
+ * the Gaussian with the largest blend weight w = alpha T of the pixel (the
+ * first one on exact ties, -1 when nothing contributes), w1 that weight, w2
+ * the largest weight of any other contributing Gaussian (0 if none) and werr
+ * a bound on the relative FP32 error of the weights of the pixel. */
 OR_EXPORT int or_forward(int V, int W, int H, int tile, int n,
                          const double* rec, const int32_t* box,
                          const double* rgb, const uint32_t* vals,
@@ -394,6 +399,7 @@ OR_EXPORT int or_forward(int V, int W, int H, int tile, int n,
                          double* img, double* Tfin, int32_t* nlast,
                          uint8_t* flags, double* errb, double* terr,
                          int64_t* counters, uint8_t* dec, int L, int dec_mode,
+                         int32_t* dom, double* w1, double* w2, double* werr,
                          int nthreads) {
   fwdcfg F = {W, H, tile, (W + tile - 1) / tile, (H + tile - 1) / tile, n,
               alpha_min, T_min, alpha_max, {bg[0], bg[1], bg[2]}};
@@ -414,6 +420,8 @@ OR_EXPORT int or_forward(int V, int W, int H, int tile, int n,
       for (int u = tx * tile; u < (tx + 1) * tile && u < W; ++u) {
         const size_t pix = ((size_t)k * H + v) * W + u;
         double T = 1.0, Cc[3] = {0, 0, 0}, err[3] = {0, 0, 0}, rT = 0.0;
+        double wbest = 0.0, wnext = 0.0, wrel = 0.0;
+        int32_t best = -1;
         int last = 0, amb = 0;
         int64_t ib = 0, ib_last = 0;
         for (uint32_t i = s; i < e; ++i) {
@@ -447,6 +455,18 @@ OR_EXPORT int or_forward(int V, int W, int H, int tile, int n,
             if (code == DEC_SKIP) continue;
           }
           c_contrib += 1;
+          {
+            const double w = alpha * T;
+            if (w > wbest) {
+              wnext = wbest;
+              wbest = w;
+              best = (int32_t)g;
+            } else if (w > wnext) {
+              wnext = w;
+            }
+            const double we = ea + rT + 2.0 * EPS32;
+            if (we > wrel) wrel = we;
+          }
           for (int ch = 0; ch < 3; ++ch) {
             const double cc = rgb[(size_t)ch * n + g];
             Cc[ch] += cc * alpha * T;
@@ -469,6 +489,10 @@ OR_EXPORT int or_forward(int V, int W, int H, int tile, int n,
         if (flags) flags[pix] = (uint8_t)amb;
         if (errb) errb[pix] = eb;
         if (terr) terr[pix] = rT;
+        if (dom) dom[pix] = best;
+        if (w1) w1[pix] = wbest;
+        if (w2) w2[pix] = wnext;
+        if (werr) werr[pix] = wrel;
       }
   }
   if (counters) {
