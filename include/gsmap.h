@@ -211,6 +211,35 @@ GS_API int gs_render_fwd(gs_workspace* ws, const gs_params* params,
                   const gs_settings* s, float* out_rgb, float* out_T,
                   int32_t* out_nlast, void* stream);
 
+/* gs_render_fwd that also writes, per pixel, the dominant Gaussian of
+ * Eq. 8: the Gaussian with the largest blend weight alpha * T among the
+ * contributing ones (the front-most on exact ties), or -1 when nothing
+ * contributes.
+ *   out_dom [n_views][H][W] device int32 */
+GS_API int gs_render_dominant(gs_workspace* ws, const gs_params* params,
+                              const gs_settings* s, float* out_rgb,
+                              float* out_T, int32_t* out_nlast,
+                              int32_t* out_dom, void* stream);
+
+/* Clarity-enhancing densification (Eq. 9): counts the pixels of dom (from
+ * gs_render_dominant) each Gaussian dominates and splits every live
+ * Gaussian that dominates more than sigma of them into two children with
+ * means mu + R(q) (s * xi[g][c]) (s = exp(log_scale), xi [capacity][2][3]
+ * device standard-normal draws supplied by the caller), log-scales reduced
+ * by log(1.6), rotation, opacity and colour copied.  Child 0 takes the
+ * parent's slot; child 1 is appended at the live count, in ascending parent
+ * order.  Parents whose appended child would not fit in the capacity stay
+ * unsplit and GS_STATUS_GAUSSIAN_OVERFLOW is set in *status_dev (may be
+ * NULL).  Zeroes the Adam moments of every child (adam_m, adam_v may be
+ * NULL); updates *params->n_dev; writes the number split to *n_split_dev
+ * (may be NULL).
+ *   dom      device int32 [n_pixels]
+ *   scratch  device int32 [capacity + ceil(capacity / 1024) + 4], caller-owned */
+GS_API int gs_densify(gs_params* params, gs_params* adam_m, gs_params* adam_v,
+                      const int32_t* dom, int64_t n_pixels, int32_t sigma,
+                      const float* xi, int32_t* scratch, int32_t* n_split_dev,
+                      int32_t* status_dev, void* stream);
+
 /* Work counters of the forward walk (same decisions as gs_render_fwd, no
  * image written), for roofline accounting.  ADDS to counts_dev[4] (device
  * uint64):

@@ -41,6 +41,7 @@ UNITS = [
     ("render_bwd.hip", NO_CONTRACT + NO_ATOMIC_OPT),
     ("optim.hip", []),
     ("ssim.hip", []),
+    ("densify.hip", []),
     ("mlp.hip", NO_CONTRACT),
 ]
 

@@ -271,6 +271,47 @@ int gs_render_fwd(gs_workspace* ws, const gs_params* params,
                                   (hipStream_t)stream), "render_fwd");
 }
 
+int gs_render_dominant(gs_workspace* ws, const gs_params* params,
+                       const gs_settings* s, float* out_rgb, float* out_T,
+                       int32_t* out_nlast, int32_t* out_dom, void* stream) {
+  g_err[0] = 0;
+  if (int rc = check_ws(ws)) return rc;
+  if (int rc = validate_params(params, "params")) return rc;
+  if (int rc = validate_settings(s)) return rc;
+  if (s->tile != ws->geo.tile) { set_error("settings.tile differs from the workspace's"); return GS_E_INVALID; }
+  if (int rc = check_box_alpha(ws, s)) return rc;
+  if (!out_rgb || !out_T || !out_nlast || !out_dom) { set_error("an output is NULL"); return GS_E_INVALID; }
+  return finish(launch_render_dominant(ws, s, out_rgb, out_T, out_nlast,
+                                       out_dom, (hipStream_t)stream),
+                "render_dominant");
+}
+
+int gs_densify(gs_params* params, gs_params* adam_m, gs_params* adam_v,
+               const int32_t* dom, int64_t n_pixels, int32_t sigma,
+               const float* xi, int32_t* scratch, int32_t* n_split_dev,
+               int32_t* status_dev, void* stream) {
+  g_err[0] = 0;
+  if (int rc = validate_params(params, "params")) return rc;
+  if (!params->n_dev) { set_error("params.n_dev is NULL"); return GS_E_INVALID; }
+  if (adam_m) {
+    if (int rc = validate_params(adam_m, "adam_m")) return rc;
+  }
+  if (adam_v) {
+    if (int rc = validate_params(adam_v, "adam_v")) return rc;
+  }
+  if ((adam_m && adam_m->capacity != params->capacity) ||
+      (adam_v && adam_v->capacity != params->capacity)) {
+    set_error("Adam moment capacities differ from the parameters'");
+    return GS_E_CAPACITY;
+  }
+  if (!xi || !scratch || (n_pixels > 0 && !dom)) { set_error("an argument is NULL"); return GS_E_INVALID; }
+  if (n_pixels < 0 || sigma < 0) { set_error("need n_pixels >= 0 and sigma >= 0"); return GS_E_INVALID; }
+  return finish(launch_densify(params, adam_m, adam_v, dom, n_pixels, sigma, xi,
+                               scratch, n_split_dev, status_dev,
+                               (hipStream_t)stream),
+                "densify");
+}
+
 int gs_count_pairs(gs_workspace* ws, const gs_params* params,
                    const gs_settings* s, uint64_t* counts_dev, void* stream) {
   g_err[0] = 0;

@@ -91,6 +91,13 @@ hipError_t launch_sort(gs_workspace* ws, const gs_settings* s, hipStream_t st);
 hipError_t launch_render_fwd(gs_workspace* ws, const gs_settings* s,
                              float* rgb, float* T, int32_t* nlast,
                              hipStream_t st);
+hipError_t launch_render_dominant(gs_workspace* ws, const gs_settings* s,
+                                  float* rgb, float* T, int32_t* nlast,
+                                  int32_t* dom, hipStream_t st);
+hipError_t launch_densify(gs_params* p, gs_params* m, gs_params* v,
+                          const int32_t* dom, long long n_pix, int sigma,
+                          const float* xi, int32_t* scratch, int32_t* n_split,
+                          int32_t* status, hipStream_t st);
 hipError_t launch_count_pairs(gs_workspace* ws, const gs_settings* s,
                               unsigned long long* counts, hipStream_t st);
 hipError_t launch_render_bwd(gs_workspace* ws, const gs_settings* s,

@@ -19,12 +19,15 @@ struct FwdArgs {
   float* rgb;
   float* T;
   int32_t* nlast;
+  int32_t* dom;                // dominant variant only
   unsigned long long* counts;  // counting variant only
 };
 
-// COUNT = true is the work-counting variant: the same walk and decisions,
-// adding up examined / in-box / contributing / revisited pairs instead of
-// writing the image.
+// MODE kRender writes the image; kCount is the work-counting variant: the
+// same walk and decisions, adding up examined / in-box / contributing /
+// revisited pairs instead of writing the image; kDominant also writes each
+// pixel's dominant Gaussian (Eq. 8): the one with the largest blend weight
+// alpha T, the first one on exact ties, -1 when nothing contributes.
 //
 // A pixel's transmittance is kept with its sign as the liveness flag: a
 // pixel that stopped holds -T, so "still compositing" is one compare and the
@@ -33,8 +36,12 @@ struct FwdArgs {
 // branched: every lane evaluates alpha for each of its pixels and the
 // decisions select what is accumulated.  A wave skips an entry outright when
 // no pixel of its footprint can admit it (wave_mask).
-template <int TILE, int BATCH, int NT, bool COUNT>
+enum { kRender = 0, kCount = 1, kDominant = 2 };
+
+template <int TILE, int BATCH, int NT, int MODE>
 __global__ __launch_bounds__(NT) void k_render_fwd(FwdArgs a) {
+  constexpr bool COUNT = MODE == kCount;
+  constexpr bool DOM = MODE == kDominant;
   using Lay = PixLayout<TILE, NT>;
   constexpr int PPT = Lay::PPT;
   __shared__ Entry ent[BATCH];
@@ -54,6 +61,7 @@ __global__ __launch_bounds__(NT) void k_render_fwd(FwdArgs a) {
   const int v0 = ty * TILE + cv0;
   const int wave = tid >> 6;
   __shared__ int wmask[BATCH];   // per staged entry: waves that evaluate it
+  __shared__ uint32_t egid[DOM ? BATCH : 1];   // Gaussian index per entry
   const float uf = (float)u;
   const float amax = __builtin_canonicalizef(r.alpha_max);
   const float amin = r.alpha_min, tmin = r.T_min;
@@ -61,8 +69,12 @@ __global__ __launch_bounds__(NT) void k_render_fwd(FwdArgs a) {
   float T[PPT], C0[PPT], C1[PPT], C2[PPT], vf[PPT];
   unsigned n_exam = 0, n_inbox = 0, n_contrib = 0;
   unsigned ib[PPT], ib_last[PPT];
+  float wbest[PPT];
+  int32_t best[PPT];
 #pragma unroll
   for (int p = 0; p < PPT; ++p) {
+    wbest[p] = 0.f;
+    best[p] = -1;
     T[p] = (u < r.W && v0 + p < r.H) ? 1.f : -1.f;
     C0[p] = C1[p] = C2[p] = 0.f;
     last[p] = 0;
@@ -84,6 +96,7 @@ __global__ __launch_bounds__(NT) void k_render_fwd(FwdArgs a) {
       stage(ent[i], R, box);
       wmask[i] = wave_mask<TILE, NT>(R, box, tx * TILE, ty * TILE, amin,
                                      r.ellipse_test);
+      if (DOM) egid[i] = g;
     }
     __syncthreads();
     const int base = (int)(b0 - s) + 1;
@@ -116,6 +129,7 @@ __global__ __launch_bounds__(NT) void k_render_fwd(FwdArgs a) {
       const int lo = box.z - v0, hi = box.w - v0;
       const Column col = column(ea, uf);
       const int idx = base + j;
+      const int32_t gj = DOM ? (int32_t)egid[j] : 0;
 #pragma unroll
       for (int p = 0; p < PPT; ++p) {
         float dy;
@@ -133,6 +147,11 @@ __global__ __launch_bounds__(NT) void k_render_fwd(FwdArgs a) {
         C2[p] = fmaf(ecb, w, C2[p]);
         T[p] = con ? Tn : (stop ? -T[p] : T[p]);
         last[p] = con ? idx : last[p];
+        if (DOM) {
+          const bool better = con && w > wbest[p];
+          wbest[p] = better ? w : wbest[p];
+          best[p] = better ? gj : best[p];
+        }
         if (COUNT) {
           n_contrib += con;
           ib_last[p] = con ? ib[p] : ib_last[p];
@@ -164,17 +183,18 @@ __global__ __launch_bounds__(NT) void k_render_fwd(FwdArgs a) {
     a.rgb[((size_t)k * 3 + 2) * HW + pix] = fmaf(Tf, r.bg2, C2[p]);
     a.T[(size_t)k * HW + pix] = Tf;
     a.nlast[(size_t)k * HW + pix] = last[p];
+    if (DOM) a.dom[(size_t)k * HW + pix] = best[p];
   }
 }
 
-template <bool COUNT>
+template <int MODE>
 struct FwdLauncher {
   const FwdArgs& a;
   int blocks;
   hipStream_t st;
   template <int T, int B, int N>
   void go() const {
-    hipLaunchKernelGGL((k_render_fwd<T, B, N, COUNT>), dim3(blocks), dim3(N),
+    hipLaunchKernelGGL((k_render_fwd<T, B, N, MODE>), dim3(blocks), dim3(N),
                        0, st, a);
   }
 };
@@ -199,11 +219,24 @@ hipError_t launch_render_fwd(gs_workspace* ws, const gs_settings* s,
                              hipStream_t st) {
   FwdArgs a;
   a.r = make_raster_args(ws, s);
-  a.rgb = rgb; a.T = T; a.nlast = nlast; a.counts = nullptr;
+  a.rgb = rgb; a.T = T; a.nlast = nlast; a.dom = nullptr; a.counts = nullptr;
   const int blocks = ws->geo.n_views * ws->tiles_x * ws->tiles_y;
   if (blocks <= 0) return hipSuccess;
   dispatch_shape(ws->geo.tile, s->lds_batch, s->block_threads,
-                 FwdLauncher<false>{a, blocks, st});
+                 FwdLauncher<kRender>{a, blocks, st});
+  return hipGetLastError();
+}
+
+hipError_t launch_render_dominant(gs_workspace* ws, const gs_settings* s,
+                                  float* rgb, float* T, int32_t* nlast,
+                                  int32_t* dom, hipStream_t st) {
+  FwdArgs a;
+  a.r = make_raster_args(ws, s);
+  a.rgb = rgb; a.T = T; a.nlast = nlast; a.dom = dom; a.counts = nullptr;
+  const int blocks = ws->geo.n_views * ws->tiles_x * ws->tiles_y;
+  if (blocks <= 0) return hipSuccess;
+  dispatch_shape(ws->geo.tile, s->lds_batch, s->block_threads,
+                 FwdLauncher<kDominant>{a, blocks, st});
   return hipGetLastError();
 }
 
@@ -211,11 +244,12 @@ hipError_t launch_count_pairs(gs_workspace* ws, const gs_settings* s,
                               unsigned long long* counts, hipStream_t st) {
   FwdArgs a;
   a.r = make_raster_args(ws, s);
-  a.rgb = nullptr; a.T = nullptr; a.nlast = nullptr; a.counts = counts;
+  a.rgb = nullptr; a.T = nullptr; a.nlast = nullptr; a.dom = nullptr;
+  a.counts = counts;
   const int blocks = ws->geo.n_views * ws->tiles_x * ws->tiles_y;
   if (blocks <= 0) return hipSuccess;
   dispatch_shape(ws->geo.tile, s->lds_batch, s->block_threads,
-                 FwdLauncher<true>{a, blocks, st});
+                 FwdLauncher<kCount>{a, blocks, st});
   return hipGetLastError();
 }
 

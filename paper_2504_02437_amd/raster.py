@@ -234,6 +234,46 @@ def render_fwd(ws, params, settings, out_rgb, out_T, out_nlast, stream=None):
            _ptr(out_nlast), _stream(stream))
 
 
+def render_dominant(ws, params, settings, out_rgb, out_T, out_nlast, out_dom,
+                    stream=None):
+    """render_fwd that also writes each pixel's dominant Gaussian (Eq. 8)."""
+    for t, nm in ((out_rgb, "out_rgb"), (out_T, "out_T"),
+                  (out_nlast, "out_nlast"), (out_dom, "out_dom")):
+        _require_cuda(t, nm)
+    V, H, W = ws.geo.n_views, ws.geo.height, ws.geo.width
+    if out_dom.numel() != V * H * W or out_dom.dtype != torch.int32:
+        raise ValueError("out_dom must be int32 [V][H][W]")
+    L.call("gs_render_dominant", ws.handle, C.byref(params.struct()),
+           C.byref(settings.struct()), _ptr(out_rgb), _ptr(out_T),
+           _ptr(out_nlast), _ptr(out_dom), _stream(stream))
+
+
+def densify_scratch(capacity, device="cuda"):
+    return torch.empty(capacity + (capacity + 1023) // 1024 + 4,
+                       dtype=torch.int32, device=device)
+
+
+def densify(params, m, v, dom, sigma, xi, scratch=None, n_split=None,
+            status=None, stream=None):
+    """Splits the Gaussians dominating more than sigma pixels of dom (Eq. 9).
+    xi: [capacity][2][3] float32 standard-normal draws.  Returns the scratch
+    buffer (its first `capacity` entries hold the dominated-pixel counts)."""
+    _require_cuda(dom, "dom")
+    if dom.dtype != torch.int32:
+        raise ValueError("dom must be int32")
+    cap = params.capacity
+    if xi.shape != (cap, 2, 3) or xi.dtype != torch.float32 or not xi.is_contiguous():
+        raise ValueError("xi must be contiguous float32 [capacity][2][3]")
+    if scratch is None:
+        scratch = densify_scratch(cap, params.data.device)
+    L.call("gs_densify", C.byref(params.struct()),
+           C.byref(m.struct()) if m is not None else None,
+           C.byref(v.struct()) if v is not None else None, _ptr(dom),
+           int(dom.numel()), int(sigma), _ptr(xi), _ptr(scratch),
+           _ptr(n_split), _ptr(status), _stream(stream))
+    return scratch
+
+
 def count_pairs(ws, params, settings, counts_dev, stream=None):
     """Adds (examined, in-box, contributing, revisited) pair counts of the
     forward walk to counts_dev (int64[4] device tensor)."""
@@ -440,6 +480,15 @@ class Rasterizer:
         render_fwd(self.ws, params, self.settings, self.rgb, self.T,
                    self.nlast, stream)
         return self.rgb, self.T, self.nlast
+
+    def forward_dominant(self, params, stream=None):
+        """forward() plus each pixel's dominant Gaussian (int32 [V][H][W])."""
+        dom = torch.empty(self.T.shape, dtype=torch.int32, device=self.T.device)
+        project_and_bin(self.ws, params, self.cams_dev, self.settings, stream)
+        sort_tile_keys(self.ws, self.settings, stream)
+        render_dominant(self.ws, params, self.settings, self.rgb, self.T,
+                        self.nlast, dom, stream)
+        return dom
 
     def count_pairs(self, params, stream=None):
         """Work counters of the current sorted lists (run forward first)."""
