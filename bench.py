@@ -34,6 +34,7 @@ BWD_OPS = dict(revisit=14, contributing=45)
 LR = (1.6e-4, 5e-3, 1e-3, 5e-2, 2.5e-3)   # mean, log_scale, quat, opacity, rgb
 LAMBDA_COLOR, LAMBDA_REG, REG_FLOOR = 1.0, 1.0, 0.01
 LAMBDA_PHOTO = 0.2   # weight of the SSIM term inside the colour loss
+DENSIFY_SIGMA = 64   # split threshold: dominated pixels per keyframe
 
 
 TRAFFIC_FILE = os.path.join(ROOT, "profiles",
@@ -126,6 +127,8 @@ def main():
                     help="first run one plain device copy of MIB MiB (a "
                          "known-size reference for HBM traffic counters)")
     ap.add_argument("--no-graph", action="store_true")
+    ap.add_argument("--no-densify", action="store_true",
+                    help="skip the per-keyframe densification timing")
     ap.add_argument("--no-ssim", action="store_true",
                     help="skip the full colour loss (L1 + SSIM) timing")
     ap.add_argument("--no-per-view", action="store_true")
@@ -327,6 +330,43 @@ def main():
                     "batched_speedup": ms_plain / (ms_graph or ms_eager)}
         del singles
 
+    # Clarity-enhancing densification (Eq. 8-9) of one keyframe, a
+    # per-keyframe step: dominant-Gaussian render of view 0, histogram and
+    # split, on a copy of the scene with room to grow.
+    dens = None
+    if not args.no_densify:
+        log("bench: densification of one keyframe")
+        pd = R.ParamBuffer.from_gaussians(w.gaussians, capacity=N + N // 2,
+                                          device=dev)
+        saved = pd.data.clone()
+        n0 = pd.n()
+        r1 = R.Rasterizer([w.cameras[0]], pd.capacity, S, device=dev)
+        r1.fit_key_capacity(pd)
+        gen = torch.Generator(device=dev)
+        gen.manual_seed(0)
+        xi = torch.randn(pd.capacity, 2, 3, device=dev, generator=gen)
+        dscr = R.densify_scratch(pd.capacity, dev)
+        nsplit = torch.zeros(1, dtype=torch.int32, device=dev)
+        times_r, times_d = [], []
+        for rep in range(6):
+            pd.data.copy_(saved)
+            pd.n_dev.fill_(n0)
+            e0, e1, e2 = (torch.cuda.Event(enable_timing=True) for _ in range(3))
+            e0.record()
+            dom = r1.forward_dominant(pd)
+            e1.record()
+            R.densify(pd, None, None, dom, DENSIFY_SIGMA, xi, scratch=dscr,
+                      n_split=nsplit)
+            e2.record()
+            torch.cuda.synchronize()
+            if rep:
+                times_r.append(e0.elapsed_time(e1))
+                times_d.append(e1.elapsed_time(e2))
+        dens = {"view": "1200x680, 300k Gaussians", "sigma": DENSIFY_SIGMA,
+                "split": int(nsplit), "dominant_render_ms": float(np.mean(times_r)),
+                "densify_ms": float(np.mean(times_d))}
+        del r1, pd, saved, dscr
+
     cnt = {k: 0.5 * (counts0[k] + counts1[k]) for k in counts0}
     # Pairs under whole integer boxes (the paper's evaluation rule), for
     # comparison with the pairs the render boxes leave to examine.
@@ -383,6 +423,7 @@ def main():
                      "render_bwd_frac": bwd_ops / (kern["render_bwd"] * 1e-3) / PEAK_LANE_OPS},
         "per_keyframe_plain": per_view,
         "full_colour_loss": full,
+        "densification": dens,
         "autotune_ms": tuned,
         "wall_s": wall,
     }

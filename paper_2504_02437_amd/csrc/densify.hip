@@ -33,11 +33,20 @@ struct DensifyArgs {
   int nb;
 };
 
+// Neighbouring pixels are mostly dominated by the same Gaussian, so each wave
+// adds runs of equal indices (consecutive lanes) with one atomic per run.
 __global__ __launch_bounds__(256) void k_dom_count(DensifyArgs a) {
   const long long i = (long long)blockIdx.x * 256 + threadIdx.x;
-  if (i >= a.n_pix) return;
-  const int g = a.dom[i];
-  if (g >= 0 && g < a.p.capacity) atomicAdd(&a.counts[g], 1);
+  const int lane = threadIdx.x & 63;
+  const int g = i < a.n_pix ? a.dom[i] : -1;
+  const int prev = __shfl_up(g, 1, 64);
+  const bool head = lane == 0 || g != prev;
+  const unsigned long long heads = __ballot(head);
+  const unsigned long long upto =
+      lane == 63 ? ~0ull : ((2ull << lane) - 1ull);   // lanes <= this one
+  const unsigned long long after = heads & ~upto;
+  const int next = after ? __ffsll((long long)after) - 1 : 64;
+  if (head && g >= 0 && g < a.p.capacity) atomicAdd(&a.counts[g], next - lane);
 }
 
 __device__ inline bool eligible(const DensifyArgs& a, int g, int n) {

@@ -6,7 +6,8 @@ For every keyframe: render the current map at the keyframe pose, insert new
 Gaussians at the visual-odometry patch pixels whose accumulated alpha does
 not exceed ``alpha_skip`` (heuristic or learned initial parameters), then run
 window iterations (render, L1 + planar-regulariser gradients, backward, Adam)
-over the last ``window`` keyframes.
+over the last ``window`` keyframes; optionally densify on the keyframe
+(Eq. 8-9).
 """
 from __future__ import annotations
 
@@ -128,6 +129,20 @@ class Mapper:
         if flags:
             r.fit_key_capacity(self.params)
         return float(loss)
+
+    # -- densification -------------------------------------------------------
+    def densify(self, sigma, generator=None):
+        """Clarity-enhancing densification (Eq. 8-9) on the latest keyframe:
+        splits the Gaussians that dominate more than sigma of its pixels.
+        Returns the number split."""
+        cam, _ = self.kfs[-1]
+        r = self._rast([cam])
+        dom = r.forward_dominant(self.params)
+        xi = torch.randn(self.capacity, 2, 3, device=self.device,
+                         generator=generator)
+        n_split = torch.zeros(1, dtype=torch.int32, device=self.device)
+        R.densify(self.params, self.m, self.v, dom, sigma, xi, n_split=n_split)
+        return int(n_split)
 
     def psnr(self, cams=None, images=None):
         """Mean PSNR (dB) of the window views (or the given views)."""

@@ -123,3 +123,20 @@ def test_split_threshold_above_every_count_is_a_no_op():
     w = synth.config0()
     k, over = _split_case(w, 16, 10 ** 9, 100, 9)
     assert k == 0 and not over
+
+
+def test_counts_with_long_runs_and_a_ragged_tail():
+    """Runs of equal indices (as neighbouring pixels give) across wave
+    boundaries, -1 entries and a length that is no multiple of the wave."""
+    rng = np.random.default_rng(3)
+    runs = rng.integers(1, 300, size=400)
+    vals = rng.integers(-1, 50, size=400)
+    dom = np.repeat(vals, runs)[:30001].astype(np.int32)
+    g = synth.tiny_scene(1, n=50).gaussians
+    params = R.ParamBuffer.from_gaussians(g, capacity=60)
+    xi = torch.zeros(60, 2, 3, device="cuda")
+    scratch = R.densify(params, None, None, torch.from_numpy(dom).cuda(),
+                        10 ** 9, xi)
+    np.testing.assert_array_equal(scratch[:60].cpu().numpy(),
+                                  OD.dominated_counts(dom, 60))
+    assert params.n() == 50
