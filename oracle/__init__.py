@@ -70,7 +70,11 @@ def lib():
                               C.c_double, C.c_double, C.c_double, C.c_int]
         L.or_insert.restype = C.c_int
         L.or_insert.argtypes = [_d, _d, _d, _d, C.c_int, C.c_double, C.c_int,
-                                C.c_int, _d, _d, _d, _d, _d, _i32]
+                                C.c_int, _d, _d, _d, _d, _d, _i32, _d,
+                                C.c_double]
+        L.or_nearest.restype = None
+        L.or_nearest.argtypes = [_d, _d, C.c_int, C.c_int, _d, C.c_int, _d,
+                                 C.c_int]
         _LIB = L
     return _LIB
 
@@ -266,25 +270,47 @@ def adam(p, g, m, v, lr, step, b1=0.9, b2=0.999, eps=1e-15):
     return p, m, v
 
 
+def nearest(cam, pts_uvd, means, centre_only=False, nthreads=1):
+    """Squared distance from each insertion candidate's back-projected point
+    to the nearest existing mean (Eq. 7); -1 outside the image or for d <= 0,
+    inf for an empty map.  means: [3][n]."""
+    L = lib()
+    K = pts_uvd.shape[0]
+    per = 1 if centre_only else 9
+    means = _f64(means).reshape(3, -1)
+    out = np.zeros(K * per)
+    L.or_nearest(_p(cam_array(cam), _d), _p(_f64(pts_uvd), _d), K,
+                 1 if centre_only else 0, _p(means, _d), means.shape[1],
+                 _p(out, _d), nthreads)
+    return out
+
+
 def insert(cam, kf_rgb, kf_T, pts_uvd, alpha_skip=0.9, centre_only=False,
-           cap=None):
-    """Back-projected, masked insertion of patch pixels (Eq. 6)."""
+           cap=None, cand_d2=None, tau=None):
+    """Back-projected, masked insertion of patch pixels (Eq. 6), with the
+    accumulated-alpha mask, or with the distance test of Eq. 7 (a candidate
+    is kept when cand_d2 > tau^2) when cand_d2 is given."""
     L = lib()
     K = pts_uvd.shape[0]
     cap = 9 * K if cap is None else cap
     ca = cam_array(cam)
     rgb = _f64(kf_rgb)
-    T = np.ascontiguousarray(kf_T, np.float64)
+    T = np.ascontiguousarray(kf_T if kf_T is not None else np.zeros((1,)),
+                             np.float64)
     pts = _f64(pts_uvd)
     out = dict(mean=np.zeros((3, cap)), log_scale=np.zeros((3, cap)),
                quat=np.zeros((4, cap)), opacity_logit=np.zeros(cap),
                rgb=np.zeros((3, cap)))
     src = np.zeros(cap, np.int32)
+    # The distance threshold is an FP32 setting: square its FP32 value.
+    d2 = None if cand_d2 is None else np.ascontiguousarray(cand_d2, np.float64)
+    tau2 = 0.0 if tau is None else float(np.float32(tau)) ** 2
     cnt = L.or_insert(_p(ca, _d), _p(rgb, _d), _p(T, _d), _p(pts, _d), K,
                       alpha_skip, 1 if centre_only else 0, cap,
                       _p(out["mean"], _d), _p(out["log_scale"], _d),
                       _p(out["quat"], _d), _p(out["opacity_logit"], _d),
-                      _p(out["rgb"], _d), _p(src, _i32))
+                      _p(out["rgb"], _d), _p(src, _i32),
+                      _p(d2, _d), tau2)
     m = min(cnt, cap)
     return dict(count=int(cnt), src=src[:m],
                 **{k: v[..., :m] for k, v in out.items()})

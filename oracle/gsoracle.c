@@ -849,14 +849,67 @@ OR_EXPORT void or_adam(int64_t n, double* p, const double* g, double* m,
  * isotropic log-scale log(z / fx).  Outputs [3][cap] etc. in insertion
  * order; src [cap] is the candidate index (patch * 9 + pixel).  Returns the
  * number kept (which may exceed cap; only cap are written). */
+/* Back-projection of a candidate pixel with inverse depth d (Eq. 6). */
+static void back_project(const ocam* cam, int u, int v, double d, double* X) {
+  const double z = 1.0 / d;
+  const double xc[3] = {((double)u - cam->cx) / cam->fx * z,
+                        ((double)v - cam->cy) / cam->fy * z, z};
+  for (int i = 0; i < 3; ++i) {
+    double s = 0.0;
+    for (int j = 0; j < 3; ++j) s += cam->R[3 * j + i] * (xc[j] - cam->t[j]);
+    X[i] = s;
+  }
+}
+
+/* Distance test of Eq. 7: for every insertion candidate (index patch * per
+ * + pixel, per = 9, or 1 with centre_only), the squared distance from its
+ * back-projected point to the nearest of the n existing means [3][n]
+ * (FP64, (x - m)^2 summed over the axes in order); -1 for candidates outside
+ * the image or with d <= 0; +inf when n == 0. */
+OR_EXPORT void or_nearest(const double* camd, const double* pts, int K,
+                          int centre_only, const double* means, int n,
+                          double* out_d2, int nthreads) {
+  ocam cam;
+  cam_load(camd, &cam);
+  const int per = centre_only ? 1 : 9;
+#ifdef _OPENMP
+  if (nthreads < 1) nthreads = 1;
+#pragma omp parallel for schedule(dynamic, 8) num_threads(nthreads)
+#endif
+  for (int c = 0; c < K * per; ++c) {
+    const int k = c / per, p = centre_only ? 4 : c % per;
+    const double d = pts[3 * k + 2];
+    const int u = (int)pts[3 * k] + (p % 3) - 1, v = (int)pts[3 * k + 1] + (p / 3) - 1;
+    if (u < 0 || u >= cam.W || v < 0 || v >= cam.H || !(d > 0.0)) {
+      out_d2[c] = -1.0;
+      continue;
+    }
+    double X[3];
+    back_project(&cam, u, v, d, X);
+    double best = INFINITY;
+    for (int g = 0; g < n; ++g) {
+      const double a = X[0] - means[g], b = X[1] - means[(size_t)n + g],
+                   e = X[2] - means[2 * (size_t)n + g];
+      const double d2 = (a * a + b * b) + e * e;
+      if (d2 < best) best = d2;
+    }
+    out_d2[c] = best;
+  }
+}
+
+/* Insertion (Eq. 6).  The keep test is the accumulated-alpha mask
+ * (1 - kf_T(u, v) <= alpha_skip) or, when cand_d2 is given, the distance
+ * test of Eq. 7 (cand_d2[c] > tau2, cand_d2 from or_nearest). */
 OR_EXPORT int or_insert(const double* camd, const double* kf_rgb,
                         const double* kf_T, const double* pts, int K,
                         double alpha_skip, int centre_only, int cap,
                         double* out_mean, double* out_lsc, double* out_quat,
-                        double* out_opl, double* out_rgb, int32_t* src) {
+                        double* out_opl, double* out_rgb, int32_t* src,
+                        const double* cand_d2, double tau2) {
   ocam cam;
   cam_load(camd, &cam);
   int cnt = 0;
+  const int per = centre_only ? 1 : 9;
   for (int k = 0; k < K; ++k) {
     const double uc = pts[3 * k], vc = pts[3 * k + 1], d = pts[3 * k + 2];
     for (int p = 0; p < 9; ++p) {
@@ -864,16 +917,18 @@ OR_EXPORT int or_insert(const double* camd, const double* kf_rgb,
       const int u = (int)uc + (p % 3) - 1, v = (int)vc + (p / 3) - 1;
       if (u < 0 || u >= cam.W || v < 0 || v >= cam.H) continue;
       if (!(d > 0.0)) continue;
-      const double acc = 1.0 - kf_T[(size_t)v * cam.W + u];
-      if (acc > alpha_skip) continue;
+      if (cand_d2) {
+        if (!(cand_d2[k * per + (centre_only ? 0 : p)] > tau2)) continue;
+      } else {
+        const double acc = 1.0 - kf_T[(size_t)v * cam.W + u];
+        if (acc > alpha_skip) continue;
+      }
       if (cnt < cap) {
         const double z = 1.0 / d;
-        const double xc[3] = {((double)u - cam.cx) / cam.fx * z,
-                              ((double)v - cam.cy) / cam.fy * z, z};
+        double X[3];
+        back_project(&cam, u, v, d, X);
         for (int i = 0; i < 3; ++i) {
-          double s = 0.0;
-          for (int j = 0; j < 3; ++j) s += cam.R[3 * j + i] * (xc[j] - cam.t[j]);
-          out_mean[(size_t)i * cap + cnt] = s;
+          out_mean[(size_t)i * cap + cnt] = X[i];
           out_lsc[(size_t)i * cap + cnt] = log(z / cam.fx);
           out_rgb[(size_t)i * cap + cnt] =
               kf_rgb[((size_t)i * cam.H + v) * cam.W + u];
