@@ -346,6 +346,25 @@ GS_API int gs_insert_gaussians(gs_params* params, gs_params* adam_m,
                                const float* mlp_out, int32_t* n_inserted_dev,
                                int32_t* status_dev, void* stream);
 
+/* The paper's own insertion test (Eq. 7): same candidates, candidate order,
+ * back-projection, initialisation, capacity handling and outputs as
+ * gs_insert_gaussians, but a candidate inside the image (d > 0) is kept when
+ * the distance from its back-projected point to the nearest live Gaussian
+ * mean exceeds tau (strict; the equation's "<" is read as ">", as its text
+ * states; every candidate is kept when the map is empty).  Distances are
+ * FP64 from the FP32 means, against the map as it was before the call.
+ *   scratch  device uint64 [candidates], caller-owned: receives the FP64
+ *            bit pattern of each candidate's nearest squared distance (all
+ *            ones for an empty map or a candidate that was not tested) */
+GS_API int gs_insert_distance(gs_params* params, gs_params* adam_m,
+                              gs_params* adam_v, const gs_camera* cam,
+                              int32_t width, int32_t height,
+                              const float* kf_rgb, const float* pts_uvd,
+                              int32_t n_pts, float tau, int32_t centre_only,
+                              const float* mlp_out, uint64_t* scratch,
+                              int32_t* n_inserted_dev, int32_t* status_dev,
+                              void* stream);
+
 /* Learned initialisation: the parameter vector of the network
  * (32 -> 64 -> 64 -> 7, GELU) holds GS_MLP_PARAMS FP32 master weights,
  * W1 [32][64], b1 [64], W2 [64][64], b2 [64], W3 [64][7], b3 [7], each layer

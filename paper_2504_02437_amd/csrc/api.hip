@@ -443,6 +443,37 @@ int gs_insert_gaussians(gs_params* params, gs_params* adam_m, gs_params* adam_v,
                               (hipStream_t)stream), "insert_gaussians");
 }
 
+int gs_insert_distance(gs_params* params, gs_params* adam_m,
+                       gs_params* adam_v, const gs_camera* cam, int32_t width,
+                       int32_t height, const float* kf_rgb,
+                       const float* pts_uvd, int32_t n_pts, float tau,
+                       int32_t centre_only, const float* mlp_out,
+                       uint64_t* scratch, int32_t* n_inserted_dev,
+                       int32_t* status_dev, void* stream) {
+  g_err[0] = 0;
+  if (int rc = validate_params(params, "params")) return rc;
+  if (!params->n_dev || !cam || (!kf_rgb && !mlp_out)) {
+    set_error("an argument is NULL");
+    return GS_E_INVALID;
+  }
+  if (n_pts < 0 || (long long)n_pts * 9 > 65536) { set_error("need 0 <= n_pts and 9 n_pts <= 65536"); return GS_E_INVALID; }
+  if (n_pts > 0 && (!pts_uvd || !scratch)) { set_error("pts_uvd or scratch is NULL"); return GS_E_INVALID; }
+  if (width < 1 || height < 1) { set_error("bad image size"); return GS_E_INVALID; }
+  if (!(tau >= 0.f)) { set_error("need tau >= 0"); return GS_E_INVALID; }
+  if ((adam_m && adam_m->capacity != params->capacity) ||
+      (adam_v && adam_v->capacity != params->capacity)) {
+    set_error("moment capacities differ");
+    return GS_E_CAPACITY;
+  }
+  return finish(launch_insert_distance(params, adam_m, adam_v, cam, width,
+                                       height, kf_rgb, pts_uvd, n_pts, tau,
+                                       centre_only, mlp_out,
+                                       (unsigned long long*)scratch,
+                                       n_inserted_dev, status_dev,
+                                       (hipStream_t)stream),
+                "insert_distance");
+}
+
 int gs_knn_features(const gs_params* params, const gs_camera* cam,
                     int32_t width, int32_t height, const float* kf_rgb,
                     const float* pts_uvd, int32_t n_pts, int32_t centre_only,

@@ -91,6 +91,14 @@ hipError_t launch_sort(gs_workspace* ws, const gs_settings* s, hipStream_t st);
 hipError_t launch_render_fwd(gs_workspace* ws, const gs_settings* s,
                              float* rgb, float* T, int32_t* nlast,
                              hipStream_t st);
+hipError_t launch_insert_distance(gs_params* p, gs_params* m, gs_params* v,
+                                  const gs_camera* cam, int W, int H,
+                                  const float* kf_rgb, const float* pts,
+                                  int n_pts, float tau, int centre_only,
+                                  const float* mlp_out,
+                                  unsigned long long* d2bits,
+                                  int32_t* n_inserted, int32_t* status,
+                                  hipStream_t st);
 hipError_t launch_render_dominant(gs_workspace* ws, const gs_settings* s,
                                   float* rgb, float* T, int32_t* nlast,
                                   int32_t* dom, hipStream_t st);

@@ -153,7 +153,27 @@ struct InsertArgs {
   const float* mlp_out;
   int32_t* n_inserted;
   int32_t* status;
+  // Distance test (Eq. 7) instead of the alpha mask when not null: FP64
+  // bits of each candidate's nearest squared distance (all ones: no mean).
+  const unsigned long long* d2bits;
+  double tau2;
 };
+
+// Back-projection of candidate pixel (u, v) with inverse depth d (Eq. 6),
+// FP64 without contraction so the distance test reproduces exactly.
+__device__ inline void back_project(const gs_camera& cam, int u, int v,
+                                    double d, double* X) {
+#pragma clang fp contract(off)
+  const double z = 1.0 / d;
+  const double xc[3] = {((double)u - (double)cam.cx) / (double)cam.fx * z,
+                        ((double)v - (double)cam.cy) / (double)cam.fy * z, z};
+  for (int i = 0; i < 3; ++i) {
+    double sacc = 0.0;
+    for (int j = 0; j < 3; ++j)
+      sacc += (double)cam.R[3 * j + i] * (xc[j] - (double)cam.t[j]);
+    X[i] = sacc;
+  }
+}
 
 constexpr int kInsThreads = 1024;
 
@@ -175,8 +195,13 @@ __global__ __launch_bounds__(kInsThreads) void k_insert(InsertArgs a) {
       v = (int)a.pts[3 * patch + 1] + pix / 3 - 1;
       const float d = a.pts[3 * patch + 2];
       if (u >= 0 && u < a.W && v >= 0 && v < a.H && d > 0.f) {
-        const double accum = 1.0 - (double)a.kf_T[(size_t)v * a.W + u];
-        keep = accum <= (double)a.alpha_skip;
+        if (a.d2bits) {
+          const unsigned long long b = a.d2bits[c];
+          keep = b == ~0ull || __longlong_as_double((long long)b) > a.tau2;
+        } else {
+          const double accum = 1.0 - (double)a.kf_T[(size_t)v * a.W + u];
+          keep = accum <= (double)a.alpha_skip;
+        }
       }
     }
     scan[tid] = keep;
@@ -193,15 +218,9 @@ __global__ __launch_bounds__(kInsThreads) void k_insert(InsertArgs a) {
       const int dst = n0 + running + incl - 1;
       if (dst < a.cap) {
         const double z = 1.0 / (double)a.pts[3 * patch + 2];
-        const double xc[3] = {((double)u - (double)cam.cx) / (double)cam.fx * z,
-                              ((double)v - (double)cam.cy) / (double)cam.fy * z,
-                              z};
-        for (int i = 0; i < 3; ++i) {
-          double sacc = 0.0;
-          for (int j = 0; j < 3; ++j)
-            sacc += (double)cam.R[3 * j + i] * (xc[j] - (double)cam.t[j]);
-          a.rows[i][dst] = (float)sacc;
-        }
+        double X[3];
+        back_project(cam, u, v, (double)a.pts[3 * patch + 2], X);
+        for (int i = 0; i < 3; ++i) a.rows[i][dst] = (float)X[i];
         if (a.mlp_out) {
           const float* o = a.mlp_out + 7 * (size_t)c;
           for (int i = 0; i < 3; ++i) a.rows[3 + i][dst] = o[i];
@@ -234,6 +253,49 @@ __global__ __launch_bounds__(kInsThreads) void k_insert(InsertArgs a) {
     *a.n_dev = (int)min(want, (long long)a.cap);
     if (want > a.cap && a.status) atomicOr(a.status, GS_STATUS_GAUSSIAN_OVERFLOW);
   }
+}
+
+// Distance test of Eq. 7: the squared distance from each candidate's
+// back-projected point to the nearest live mean, as the FP64 bit pattern
+// (non-negative doubles order like their bits) min-combined over blocks that
+// each scan a slice of the means.
+struct NearestArgs {
+  const float* mean;   // [3][cap]
+  const int32_t* n_dev;
+  int cap;
+  const gs_camera* cam;
+  int W, H;
+  const float* pts;
+  int n_pts, centre_only, chunk;
+  unsigned long long* d2bits;
+};
+
+__global__ __launch_bounds__(256) void k_nearest(NearestArgs a) {
+#pragma clang fp contract(off)
+  const int per = a.centre_only ? 1 : 9;
+  const int c = blockIdx.x * 256 + threadIdx.x;
+  if (c >= a.n_pts * per) return;
+  const int patch = c / per;
+  const int pix = a.centre_only ? 4 : c - patch * per;
+  const int u = (int)a.pts[3 * patch] + pix % 3 - 1;
+  const int v = (int)a.pts[3 * patch + 1] + pix / 3 - 1;
+  const float d = a.pts[3 * patch + 2];
+  if (!(u >= 0 && u < a.W && v >= 0 && v < a.H && d > 0.f)) return;
+  const gs_camera cam = *a.cam;
+  double X[3];
+  back_project(cam, u, v, (double)d, X);
+  const int n = min(*a.n_dev, a.cap);
+  const int g0 = blockIdx.y * a.chunk, g1 = min(n, g0 + a.chunk);
+  if (g0 >= g1) return;
+  double best = INFINITY;
+  for (int g = g0; g < g1; ++g) {
+    const double e0 = X[0] - (double)a.mean[g];
+    const double e1 = X[1] - (double)a.mean[a.cap + g];
+    const double e2 = X[2] - (double)a.mean[2 * a.cap + g];
+    const double d2 = (e0 * e0 + e1 * e1) + e2 * e2;
+    best = d2 < best ? d2 : best;
+  }
+  atomicMin(&a.d2bits[c], (unsigned long long)__double_as_longlong(best));
 }
 
 void rows_of(const gs_params* p, float** rows) {
@@ -318,6 +380,46 @@ hipError_t launch_insert(gs_params* p, gs_params* m, gs_params* v,
   a.kf_rgb = kf_rgb; a.kf_T = kf_T; a.pts = pts; a.n_pts = n_pts;
   a.alpha_skip = alpha_skip; a.centre_only = centre_only; a.mlp_out = mlp_out;
   a.n_inserted = n_inserted; a.status = status;
+  a.d2bits = nullptr; a.tau2 = 0.0;
+  hipLaunchKernelGGL(k_insert, dim3(1), dim3(kInsThreads), 0, st, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_insert_distance(gs_params* p, gs_params* m, gs_params* v,
+                                  const gs_camera* cam, int W, int H,
+                                  const float* kf_rgb, const float* pts,
+                                  int n_pts, float tau, int centre_only,
+                                  const float* mlp_out,
+                                  unsigned long long* d2bits,
+                                  int32_t* n_inserted, int32_t* status,
+                                  hipStream_t st) {
+  const int per = centre_only ? 1 : 9;
+  const int C = n_pts * per;
+  if (C > 0) {
+    hipError_t e = launch_fill_u32(d2bits, 0xffffffffu, 2 * (size_t)C, st);
+    if (e != hipSuccess) return e;
+    NearestArgs na;
+    na.mean = p->mean; na.n_dev = p->n_dev; na.cap = p->capacity; na.cam = cam;
+    na.W = W; na.H = H; na.pts = pts; na.n_pts = n_pts;
+    na.centre_only = centre_only; na.d2bits = d2bits;
+    const int bc = (C + 255) / 256;
+    // Slices of the means so that about 1024 blocks run.
+    const int slices = max(1, min((p->capacity + 1023) / 1024, 1024 / bc));
+    na.chunk = max(1, (p->capacity + slices - 1) / slices);
+    hipLaunchKernelGGL(k_nearest, dim3(bc, slices), dim3(256), 0, st, na);
+    e = hipGetLastError();
+    if (e != hipSuccess) return e;
+  }
+  InsertArgs a;
+  rows_of(p, a.rows);
+  if (m) rows_of(m, a.mrows); else for (int i = 0; i < 14; ++i) a.mrows[i] = nullptr;
+  if (v) rows_of(v, a.vrows); else for (int i = 0; i < 14; ++i) a.vrows[i] = nullptr;
+  a.n_dev = p->n_dev; a.cap = p->capacity; a.cam = cam; a.W = W; a.H = H;
+  a.kf_rgb = kf_rgb; a.kf_T = nullptr; a.pts = pts; a.n_pts = n_pts;
+  a.alpha_skip = 0.f; a.centre_only = centre_only; a.mlp_out = mlp_out;
+  a.n_inserted = n_inserted; a.status = status;
+  a.d2bits = d2bits;
+  a.tau2 = (double)tau * (double)tau;
   hipLaunchKernelGGL(k_insert, dim3(1), dim3(kInsThreads), 0, st, a);
   return hipGetLastError();
 }

@@ -381,6 +381,25 @@ def insert_gaussians(params, m, v, cam_dev, width, height, kf_rgb, kf_T, pts,
            _ptr(n_inserted_dev), _ptr(status_dev), _stream(stream))
 
 
+def insert_distance(params, m, v, cam_dev, width, height, kf_rgb, pts, tau,
+                    centre_only=False, mlp_out=None, scratch=None,
+                    n_inserted_dev=None, status_dev=None, stream=None):
+    """Insertion with the distance test of Eq. 7.  Returns the scratch
+    tensor (int64 view of each candidate's nearest squared distance bits)."""
+    n_pts = 0 if pts is None else pts.shape[0]
+    C_ = n_pts * (1 if centre_only else 9)
+    if scratch is None:
+        scratch = torch.empty(max(C_, 1), dtype=torch.int64,
+                              device=params.data.device)
+    L.call("gs_insert_distance", C.byref(params.struct()),
+           C.byref(m.struct()) if m is not None else None,
+           C.byref(v.struct()) if v is not None else None, _ptr(cam_dev),
+           int(width), int(height), _ptr(kf_rgb), _ptr(pts), n_pts,
+           float(tau), 1 if centre_only else 0, _ptr(mlp_out), _ptr(scratch),
+           _ptr(n_inserted_dev), _ptr(status_dev), _stream(stream))
+    return scratch
+
+
 def knn_features(params, cam_dev, width, height, kf_rgb, pts, centre_only,
                  feats, knn_idx=None, knn_dist=None, stream=None):
     n_pts = 0 if pts is None else pts.shape[0]
