@@ -35,6 +35,7 @@ LR = (1.6e-4, 5e-3, 1e-3, 5e-2, 2.5e-3)   # mean, log_scale, quat, opacity, rgb
 LAMBDA_COLOR, LAMBDA_REG, REG_FLOOR = 1.0, 1.0, 0.01
 LAMBDA_PHOTO = 0.2   # weight of the SSIM term inside the colour loss
 DENSIFY_SIGMA = 64   # split threshold: dominated pixels per keyframe
+INSERT_TAU = 0.02    # distance threshold of the paper's insertion test (m)
 
 
 TRAFFIC_FILE = os.path.join(ROOT, "profiles",
@@ -330,9 +331,9 @@ def main():
                     "batched_speedup": ms_plain / (ms_graph or ms_eager)}
         del singles
 
-    # Clarity-enhancing densification (Eq. 8-9) of one keyframe, a
-    # per-keyframe step: dominant-Gaussian render of view 0, histogram and
-    # split, on a copy of the scene with room to grow.
+    # Per-keyframe steps on view 0, on a copy of the scene with room to grow:
+    # clarity-enhancing densification (Eq. 8-9: dominant-Gaussian render,
+    # histogram and split) and keyframe insertion.
     dens = None
     if not args.no_densify:
         log("bench: densification of one keyframe")
@@ -365,6 +366,36 @@ def main():
         dens = {"view": "1200x680, 300k Gaussians", "sigma": DENSIFY_SIGMA,
                 "split": int(nsplit), "dominant_render_ms": float(np.mean(times_r)),
                 "densify_ms": float(np.mean(times_d))}
+        # Keyframe insertion, 96 patches x 9 candidates, against the 300k map:
+        # the accumulated-alpha mask and the paper's distance test (Eq. 7).
+        rng = np.random.default_rng(0)
+        pts = torch.from_numpy(np.stack(
+            [rng.integers(1, W - 1, 96), rng.integers(1, H - 1, 96),
+             1.0 / rng.uniform(1, 5, 96)], 1).astype(np.float32)).to(dev)
+        cam0 = r1.cams_dev
+        kf_rgb = target[0].contiguous()
+        kf_T = r1.T[0].contiguous()
+        ins_scr = torch.empty(96 * 9, dtype=torch.int64, device=dev)
+        t_a, t_d = [], []
+        for rep in range(6):
+            for mode, acc in (("alpha", t_a), ("distance", t_d)):
+                pd.data.copy_(saved)
+                pd.n_dev.fill_(n0)
+                e0, e1 = (torch.cuda.Event(enable_timing=True) for _ in range(2))
+                e0.record()
+                if mode == "alpha":
+                    R.insert_gaussians(pd, None, None, cam0, W, H, kf_rgb, kf_T,
+                                       pts)
+                else:
+                    R.insert_distance(pd, None, None, cam0, W, H, kf_rgb, pts,
+                                      INSERT_TAU, scratch=ins_scr)
+                e1.record()
+                torch.cuda.synchronize()
+                if rep:
+                    acc.append(e0.elapsed_time(e1))
+        dens["insert_alpha_ms"] = float(np.mean(t_a))
+        dens["insert_distance_ms"] = float(np.mean(t_d))
+        dens["insert_tau"] = INSERT_TAU
         del r1, pd, saved, dscr
 
     cnt = {k: 0.5 * (counts0[k] + counts1[k]) for k in counts0}
