@@ -80,6 +80,92 @@ def workload(name):
     raise ValueError(name)
 
 
+def iteration_ms(w, S, steps=10, warmup=3):
+    """Eager mapping iterations (project, sort, render, L1 + planar
+    gradients, backward, Adam) on another workload: ms per iteration."""
+    import torch
+    from paper_2504_02437_amd import raster as R
+    dev = "cuda"
+    params = R.ParamBuffer.from_gaussians(w.gaussians, device=dev)
+    grad, m, v = params.zeros_like(), params.zeros_like(), params.zeros_like()
+    rast = R.Rasterizer(w.cameras, params.capacity, S, device=dev)
+    rast.fit_key_capacity(params)
+    target = torch.from_numpy(w.targets).to(dev)
+    dL = torch.empty_like(rast.rgb)
+    loss = torch.zeros(1, dtype=torch.float64, device=dev)
+    step_dev = torch.ones(1, dtype=torch.int32, device=dev)
+
+    def step():
+        grad.data.zero_()
+        loss.zero_()
+        rast.forward(params)
+        R.loss_l1(rast.rgb, target, LAMBDA_COLOR, dL, loss)
+        R.planar_reg(params, LAMBDA_REG, REG_FLOOR, grad, loss)
+        rast.backward(params, dL, grad)
+        R.adam(params, grad, m, v, LR, 0.9, 0.999, 1e-15, step_dev)
+        step_dev.add_(1)
+
+    for _ in range(warmup):
+        step()
+    torch.cuda.synchronize()
+    if rast.status()[0]:
+        rast.fit_key_capacity(params)
+    a, b = (torch.cuda.Event(enable_timing=True) for _ in range(2))
+    a.record()
+    for _ in range(steps):
+        step()
+    b.record()
+    torch.cuda.synchronize()
+    return a.elapsed_time(b) / steps
+
+
+def insertion_stress(S, n0=50_000, n_kf=200):
+    """The growth run: a 50k-Gaussian initial map as the map initialisation
+    builds it from back-projected VO points (points on the room's surfaces,
+    the heuristic one-pixel isotropic footprint log(z / f) for their distance
+    z from the first keyframe, opacity 0.5), then n_kf keyframes on the random
+    walk, each rendered and given 96 patches x 9 candidates through the
+    accumulated-alpha mask (capacity 50k + n_kf * 864)."""
+    import numpy as np
+    import torch
+    import synth
+    from paper_2504_02437_amd import raster as R
+    dev = "cuda"
+    g = synth.room_gaussians(np.random.default_rng([3, 1]), n0)
+    kf0 = synth.insertion_stream(0, 1)[0].camera
+    cam_pos = -kf0.R.T.astype(np.float64) @ kf0.t.astype(np.float64)
+    z = np.linalg.norm(g.mean.T.astype(np.float64) - cam_pos, axis=1)
+    g.log_scale[:] = np.log(np.maximum(z, 0.1) / kf0.fx).astype(np.float32)
+    g.quat[:] = np.array([[1.0], [0.0], [0.0], [0.0]], np.float32)
+    g.opacity_logit[:] = 0.0
+    cap = n0 + n_kf * 96 * 9
+    params = R.ParamBuffer.from_gaussians(g, capacity=cap, device=dev)
+    m, v = params.zeros_like(), params.zeros_like()
+    kfs = synth.insertion_stream(0, n_kf)
+    rast = R.Rasterizer([kfs[0].camera], cap, S, device=dev,
+                        key_capacity=R.default_key_capacity(cap, 1))
+    t_render, t_insert = [], []
+    for i, kf in enumerate(kfs):
+        rast.set_cameras([kf.camera])
+        img = torch.from_numpy(kf.image).to(dev)
+        pts = torch.from_numpy(kf.pts_uvd).to(dev)
+        a, b, c = (torch.cuda.Event(enable_timing=True) for _ in range(3))
+        a.record()
+        rast.forward(params)
+        b.record()
+        R.insert_gaussians(params, m, v, rast.cams_dev, kf.camera.width,
+                           kf.camera.height, img, rast.T[0].contiguous(), pts)
+        c.record()
+        torch.cuda.synchronize()
+        if rast.status()[0]:
+            raise RuntimeError("key capacity exceeded in the insertion run")
+        t_render.append(a.elapsed_time(b))
+        t_insert.append(b.elapsed_time(c))
+    return {"keyframes": n_kf, "start_n": n0, "final_n": params.n(),
+            "capacity": cap, "ms_per_kf_insert": float(np.mean(t_insert)),
+            "ms_per_kf_render": float(np.mean(t_render))}
+
+
 def cpu_baseline(w, threads):
     """The CPU oracle, as it stands, on the first four views of the workload
     (every stage of the iteration for those views), scaled to window
@@ -128,6 +214,8 @@ def main():
                     help="first run one plain device copy of MIB MiB (a "
                          "known-size reference for HBM traffic counters)")
     ap.add_argument("--no-graph", action="store_true")
+    ap.add_argument("--no-others", action="store_true",
+                    help="skip the other configurations and the insertion run")
     ap.add_argument("--no-densify", action="store_true",
                     help="skip the per-keyframe densification timing")
     ap.add_argument("--no-ssim", action="store_true",
@@ -186,8 +274,8 @@ def main():
     dL = torch.empty_like(rgb)
     loss = torch.zeros(1, dtype=torch.float64, device=dev)
     step_dev = torch.ones(1, dtype=torch.int32, device=dev)
-    names = ("project_and_bin", "sort_tile_keys", "render_fwd", "render_bwd",
-             "project_bwd", "loss_ssim")
+    names = ("project_and_bin", "sort_tile_keys", "render_fwd", "loss_l1",
+             "planar_reg", "render_bwd", "project_bwd", "adam", "loss_ssim")
     scratch = R.ssim_scratch(rgb)
     ev = {k: [] for k in names}
 
@@ -215,13 +303,16 @@ def main():
                   lambda: R.loss_ssim(rgb, target, LAMBDA_COLOR * LAMBDA_PHOTO,
                                       dL, loss, scratch=scratch), on)
         else:
-            R.loss_l1(rgb, target, LAMBDA_COLOR, dL, loss)
-        R.planar_reg(params, LAMBDA_REG, REG_FLOOR, grad, loss)
+            timed("loss_l1",
+                  lambda: R.loss_l1(rgb, target, LAMBDA_COLOR, dL, loss), on)
+        timed("planar_reg",
+              lambda: R.planar_reg(params, LAMBDA_REG, REG_FLOOR, grad, loss), on)
         timed("render_bwd",
               lambda: R.render_bwd_pixels(ws, params, S, dL, T, nlast, grad), on)
         timed("project_bwd",
               lambda: R.project_bwd(ws, params, cams_dev, grad), on)
-        R.adam(params, grad, m, v, LR, 0.9, 0.999, 1e-15, step_dev)
+        timed("adam", lambda: R.adam(params, grad, m, v, LR, 0.9, 0.999, 1e-15,
+                                     step_dev), on)
         step_dev.add_(1)
 
     def run(k, on):
@@ -398,6 +489,28 @@ def main():
         dens["insert_tau"] = INSERT_TAU
         del r1, pd, saved, dscr
 
+    # The other configurations at the same launch shape.
+    others = None
+    if not args.no_others:
+        others = {}
+        for name in ("window640", "single", "small"):
+            wo = workload(name)
+            log("bench: workload", name)
+            po = R.ParamBuffer.from_gaussians(wo.gaussians, device=dev)
+            So, _ = AT.autotune(po, wo.cameras, R.Settings(), reps=2,
+                                use_cache=False, cache_path=None)
+            del po
+            ms_o = iteration_ms(wo, So)
+            Vo = len(wo.cameras)
+            Wo, Ho = wo.cameras[0].width, wo.cameras[0].height
+            others[wo.name] = {"ms_per_iteration": ms_o,
+                               "iterations_per_s": 1000.0 / ms_o,
+                               "mpix_per_s": Vo * Wo * Ho * 1e-3 / ms_o,
+                               "launch": "eager",
+                               "shape": f"{So.tile}/{So.lds_batch}/{So.block_threads}"}
+        log("bench: insertion growth run")
+        others["insertion-200kf-1200x680"] = insertion_stress(S)
+
     cnt = {k: 0.5 * (counts0[k] + counts1[k]) for k in counts0}
     # Pairs under whole integer boxes (the paper's evaluation rule), for
     # comparison with the pairs the render boxes leave to examine.
@@ -455,6 +568,7 @@ def main():
         "per_keyframe_plain": per_view,
         "full_colour_loss": full,
         "densification": dens,
+        "other_workloads": others,
         "autotune_ms": tuned,
         "wall_s": wall,
     }

@@ -197,3 +197,42 @@ def test_loss_reg_adam_match_oracle():
         np.testing.assert_allclose(params.data[r, :500].cpu().numpy(), pr,
                                    rtol=0, atol=1e-6)
     assert torch.equal(params.data[:, 500:], p0[:, 500:])
+
+
+def test_bulk_insertion_fills_a_400k_capacity():
+    """Keyframe insertions grow a 50k map to exactly its 400k capacity: every
+    call before the last inserts all its candidates (fully transparent
+    keyframe), the last one reports the overflow and stops at the capacity,
+    and the grown map renders."""
+    W, H = 1200, 680
+    cam = synth.room_camera()
+    g = synth.room_gaussians(np.random.default_rng([3, 2]), 50_000)
+    cap = 400_000
+    params = R.ParamBuffer.from_gaussians(g, capacity=cap)
+    cam_dev = R.cameras_to_device([cam])
+    kT = torch.ones(H, W, device="cuda")
+    img = torch.rand(3, H, W, device="cuda")
+    rng = np.random.default_rng(4)
+    status = torch.zeros(1, dtype=torch.int32, device="cuda")
+    nins = torch.zeros(1, dtype=torch.int32, device="cuda")
+    n, K = 50_000, 7281
+    print("case bulk insertion", flush=True)
+    while n < cap:
+        pts = np.stack([rng.integers(1, W - 1, K), rng.integers(1, H - 1, K),
+                        1.0 / rng.uniform(1, 5, K)], 1).astype(np.float32)
+        R.insert_gaussians(params, None, None, cam_dev, W, H, img, kT,
+                           torch.from_numpy(pts).cuda(), n_inserted_dev=nins,
+                           status_dev=status)
+        torch.cuda.synchronize()
+        assert int(nins.item()) == 9 * K
+        full = n + 9 * K > cap
+        n = min(n + 9 * K, cap)
+        assert params.n() == n
+        assert bool(int(status.item()) & 2) == full
+    rast = R.Rasterizer([cam], cap, R.Settings(tile=16))
+    rast.fit_key_capacity(params)
+    rast.forward(params)
+    torch.cuda.synchronize()
+    assert rast.status()[0] == 0
+    T = rast.T.cpu().numpy()
+    assert np.isfinite(T).all() and T.min() >= 0.0 and T.max() <= 1.0
