@@ -49,13 +49,15 @@ def lib():
                                   C.c_int64, _u32]
         L.or_forward.restype = C.c_int
         L.or_forward.argtypes = [C.c_int, C.c_int, C.c_int, C.c_int, C.c_int,
-                                 _d, _i32, _d, _u32, _u32, _d, C.c_double,
+                                 _d, _i32, _d, C.c_int, _u32, _u32, _d,
+                                 C.c_double,
                                  C.c_double, C.c_double, _d, _d, _i32, _u8, _d,
                                  _d, _i64, _u8, C.c_int, C.c_int, _i32, _d, _d,
                                  _d, C.c_int]
         L.or_backward.restype = C.c_int
         L.or_backward.argtypes = [C.c_int, C.c_int, C.c_int, C.c_int, C.c_int,
-                                  _d, _i32, _d, _u32, _u32, _d, C.c_double,
+                                  _d, _i32, _d, C.c_int, _u32, _u32, _d,
+                                  C.c_double,
                                   C.c_double, C.c_double, _d, _u8, C.c_int,
                                   C.c_int, _d, _d, _d, C.c_int]
         L.or_project_bwd.restype = C.c_int
@@ -99,9 +101,12 @@ def cam_array(cam) -> np.ndarray:
 
 def params64(g):
     """FP64 copies of a Gaussians set's planar arrays."""
-    return dict(mean=_f64(g.mean), log_scale=_f64(g.log_scale),
-                quat=_f64(g.quat), opacity_logit=_f64(g.opacity_logit),
-                rgb=_f64(g.rgb))
+    out = dict(mean=_f64(g.mean), log_scale=_f64(g.log_scale),
+               quat=_f64(g.quat), opacity_logit=_f64(g.opacity_logit),
+               rgb=_f64(g.rgb))
+    if getattr(g, "sh", None) is not None:
+        out["sh"] = _f64(g.sh)
+    return out
 
 
 def project(p, cams, tile=16, publish=True, nthreads=1):
@@ -152,13 +157,22 @@ def bin_sort(proj, tile, W, H, cap=None, emit=True):
     return out
 
 
+def _colour_layout(rgb, V, n):
+    if rgb.shape == (3, n):
+        return 0
+    if rgb.shape == (V, 3, n):
+        return 1
+    raise ValueError(f"colours must be [3][{n}] or [{V}][3][{n}]")
+
+
 def forward(proj, bins, rgb, W, H, bg=(0.0, 0.0, 0.0), alpha_min=ALPHA_MIN,
             T_min=T_MIN, alpha_max=ALPHA_MAX, dec=None, dec_mode=0,
             nthreads=1):
     """Front-to-back compositing (Eq. 3) over each tile's sorted list; also
     the dominant Gaussian of every pixel (Eq. 8): "dom" (index, -1 if none),
     "w1" its blend weight, "w2" the runner-up weight, "werr" a relative FP32
-    error bound of the weights."""
+    error bound of the weights.  rgb is [3][n], or [V][3][n] per view (the
+    view-dependent colours of ``oracle.sh.colours``)."""
     L = lib()
     V, n = proj["tiles"].shape
     img = np.zeros((V, 3, H, W))
@@ -175,9 +189,11 @@ def forward(proj, bins, rgb, W, H, bg=(0.0, 0.0, 0.0), alpha_min=ALPHA_MIN,
     bgv = np.asarray(bg, np.float64)
     Ld = 0 if dec is None else dec.shape[-1]
     rgb = np.ascontiguousarray(rgb, np.float64)
+    per_view = _colour_layout(rgb, V, n)
     vals = bins["vals"] if bins["n_keys"] else np.zeros(1, np.uint32)
     rc = L.or_forward(V, W, H, bins["tile"], n, _p(proj["rec"], _d),
-                      _p(proj["box"], _i32), _p(rgb, _d), _p(vals, _u32),
+                      _p(proj["box"], _i32), _p(rgb, _d), per_view,
+                      _p(vals, _u32),
                       _p(bins["ranges"], _u32), _p(bgv, _d), alpha_min, T_min,
                       alpha_max, _p(img, _d), _p(T, _d), _p(nlast, _i32),
                       _p(flags, _u8), _p(errb, _d), _p(terr, _d), _p(cnt, _i64),
@@ -201,19 +217,22 @@ def backward(proj, bins, rgb, W, H, dimg, bg=(0.0, 0.0, 0.0),
              alpha_min=ALPHA_MIN, T_min=T_MIN, alpha_max=ALPHA_MAX, dec=None,
              dec_mode=0, nthreads=1):
     """Exact derivative of the compositing with the decision set fixed.
-    Returns g2d [V][n][5] (px, py, A, B, C), gop [n], grgb [3][n]."""
+    Returns g2d [V][n][5] (px, py, A, B, C), gop [n] and grgb: [3][n]
+    summed over the views, or [V][3][n] when the colours are per view."""
     L = lib()
     V, n = proj["tiles"].shape
     g2d = np.zeros((V, n, 5))
     gop = np.zeros(n)
-    grgb = np.zeros((3, n))
     bgv = np.asarray(bg, np.float64)
     dimg = np.ascontiguousarray(dimg, np.float64)
     rgb = np.ascontiguousarray(rgb, np.float64)
+    per_view = _colour_layout(rgb, V, n)
+    grgb = np.zeros(rgb.shape)
     Ld = 0 if dec is None else dec.shape[-1]
     vals = bins["vals"] if bins["n_keys"] else np.zeros(1, np.uint32)
     rc = L.or_backward(V, W, H, bins["tile"], n, _p(proj["rec"], _d),
-                       _p(proj["box"], _i32), _p(rgb, _d), _p(vals, _u32),
+                       _p(proj["box"], _i32), _p(rgb, _d), per_view,
+                       _p(vals, _u32),
                        _p(bins["ranges"], _u32), _p(bgv, _d), alpha_min, T_min,
                        alpha_max, _p(dimg, _d), _p(dec, _u8), Ld, dec_mode,
                        _p(g2d, _d), _p(gop, _d), _p(grgb, _d), nthreads)

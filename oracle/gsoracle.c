@@ -373,7 +373,9 @@ static int eval_pair(const fwdcfg* F, const double* r, const int32_t* b,
   return og > F->alpha_max ? DEC_CLAMP : DEC_ADMIT;
 }
 
-/* Per view: rec [V][n][8], box [V][n][4]; rgb [3][n]; sorted values and
+/* Per view: rec [V][n][8], box [V][n][4]; rgb [3][n], or [V][3][n] when
+ * rgb_per_view is non-zero (the per-view colours c_i of Eq. 3 that
+ * view-dependent colour gives); sorted values and
  * ranges from or_bin_sort.  Outputs image [V][3][H][W], T_final [V][H][W],
  * n_last [V][H][W] (index in the tile list of the last contributing entry,
  * plus one).  flags (optional): non-zero when a threshold decision of the
@@ -393,7 +395,8 @@ static int eval_pair(const fwdcfg* F, const double* r, const int32_t* b,
  * a bound on the relative FP32 error of the weights of the pixel. */
 OR_EXPORT int or_forward(int V, int W, int H, int tile, int n,
                          const double* rec, const int32_t* box,
-                         const double* rgb, const uint32_t* vals,
+                         const double* rgb, int rgb_per_view,
+                         const uint32_t* vals,
                          const uint32_t* ranges, const double* bg,
                          double alpha_min, double T_min, double alpha_max,
                          double* img, double* Tfin, int32_t* nlast,
@@ -416,6 +419,7 @@ OR_EXPORT int or_forward(int V, int W, int H, int tile, int n,
     const int tt = (int)(t % ((int64_t)F.Tx * F.Ty));
     const int ty = tt / F.Tx, tx = tt % F.Tx;
     const uint32_t s = ranges[2 * t], e = ranges[2 * t + 1];
+    const size_t cview = rgb_per_view ? (size_t)k * 3 * n : 0;
     for (int v = ty * tile; v < (ty + 1) * tile && v < H; ++v)
       for (int u = tx * tile; u < (tx + 1) * tile && u < W; ++u) {
         const size_t pix = ((size_t)k * H + v) * W + u;
@@ -468,7 +472,7 @@ OR_EXPORT int or_forward(int V, int W, int H, int tile, int n,
             if (we > wrel) wrel = we;
           }
           for (int ch = 0; ch < 3; ++ch) {
-            const double cc = rgb[(size_t)ch * n + g];
+            const double cc = rgb[cview + (size_t)ch * n + g];
             Cc[ch] += cc * alpha * T;
             err[ch] += fabs(cc) * alpha * T * (ea + rT + 4.0 * EPS32);
           }
@@ -512,12 +516,14 @@ typedef struct {
 } admitted_t;
 
 /* Inputs as or_forward plus dimg [V][3][H][W] = dL/dC.  Outputs (overwritten):
- * g2d [V][n][5] = dL/d(px, py, A, B, C) per view, gop [n] = dL/d opacity,
- * grgb [3][n] = dL/d colour, both summed over views.  The per-pair
+ * g2d [V][n][5] = dL/d(px, py, A, B, C) per view, gop [n] = dL/d opacity
+ * summed over views, grgb = dL/d colour: [3][n] summed over views, or
+ * [V][3][n] per view when rgb_per_view is non-zero.  The per-pair
  * transmittance is recomputed front to back (no division). */
 OR_EXPORT int or_backward(int V, int W, int H, int tile, int n,
                           const double* rec, const int32_t* box,
-                          const double* rgb, const uint32_t* vals,
+                          const double* rgb, int rgb_per_view,
+                          const uint32_t* vals,
                           const uint32_t* ranges, const double* bg,
                           double alpha_min, double T_min, double alpha_max,
                           const double* dimg, const uint8_t* dec, int L,
@@ -538,7 +544,8 @@ OR_EXPORT int or_backward(int V, int W, int H, int tile, int n,
   const size_t per2d = (size_t)V * n * 5;
   double* acc2d = (double*)calloc((size_t)nthreads * per2d, sizeof(double));
   double* accop = (double*)calloc((size_t)nthreads * n, sizeof(double));
-  double* accrgb = (double*)calloc((size_t)nthreads * 3 * n, sizeof(double));
+  const size_t perrgb = (size_t)3 * n * (rgb_per_view ? V : 1);
+  double* accrgb = (double*)calloc((size_t)nthreads * perrgb, sizeof(double));
   int bad = 0;
 #ifdef _OPENMP
 #pragma omp parallel num_threads(nthreads) reduction(+ : bad)
@@ -551,7 +558,7 @@ OR_EXPORT int or_backward(int V, int W, int H, int tile, int n,
     admitted_t* list = (admitted_t*)malloc(sizeof(admitted_t) * maxlen);
     double* my2d = acc2d + (size_t)tid * per2d;
     double* myop = accop + (size_t)tid * n;
-    double* myrgb = accrgb + (size_t)tid * 3 * n;
+    double* myrgb = accrgb + (size_t)tid * perrgb;
 #ifdef _OPENMP
 #pragma omp for schedule(static)
 #endif
@@ -560,6 +567,7 @@ OR_EXPORT int or_backward(int V, int W, int H, int tile, int n,
       const int tt = (int)(t % ((int64_t)F.Tx * F.Ty));
       const int ty = tt / F.Tx, tx = tt % F.Tx;
       const uint32_t s = ranges[2 * t], e = ranges[2 * t + 1];
+      const size_t cview = rgb_per_view ? (size_t)k * 3 * n : 0;
       for (int v = ty * tile; v < (ty + 1) * tile && v < H; ++v)
         for (int u = tx * tile; u < (tx + 1) * tile && u < W; ++u) {
           const size_t pix = ((size_t)k * H + v) * W + u;
@@ -607,8 +615,8 @@ OR_EXPORT int or_backward(int V, int W, int H, int tile, int n,
             const double* r = &rec[((size_t)k * n + g) * REC_STRIDE];
             double dalpha = 0.0;
             for (int ch = 0; ch < 3; ++ch) {
-              const double cc = rgb[(size_t)ch * n + g];
-              myrgb[(size_t)ch * n + g] += P->alpha * P->T * gC[ch];
+              const double cc = rgb[cview + (size_t)ch * n + g];
+              myrgb[cview + (size_t)ch * n + g] += P->alpha * P->T * gC[ch];
               dalpha += P->T * (cc - S[ch]) * gC[ch];
               dalpha -= Tfinal / (1.0 - P->alpha) * F.bg[ch] * gC[ch];
               S[ch] = P->alpha * cc + (1.0 - P->alpha) * S[ch];
@@ -632,12 +640,12 @@ OR_EXPORT int or_backward(int V, int W, int H, int tile, int n,
   }
   memset(g2d, 0, sizeof(double) * per2d);
   memset(gop, 0, sizeof(double) * (size_t)n);
-  memset(grgb, 0, sizeof(double) * 3 * (size_t)n);
+  memset(grgb, 0, sizeof(double) * perrgb);
   for (int th = 0; th < nthreads; ++th) {
     for (size_t i = 0; i < per2d; ++i) g2d[i] += acc2d[(size_t)th * per2d + i];
     for (int i = 0; i < n; ++i) gop[i] += accop[(size_t)th * n + i];
-    for (size_t i = 0; i < 3 * (size_t)n; ++i)
-      grgb[i] += accrgb[(size_t)th * 3 * n + i];
+    for (size_t i = 0; i < perrgb; ++i)
+      grgb[i] += accrgb[(size_t)th * perrgb + i];
   }
   free(acc2d); free(accop); free(accrgb);
   return bad ? -1 : 0;

@@ -38,21 +38,31 @@ class Gaussians:
     quat: np.ndarray
     opacity_logit: np.ndarray
     rgb: np.ndarray
+    # Optional view-dependent colour coefficients [K-1][3][n] of degree
+    # sqrt(K) - 1 (None: view-independent colour).
+    sh: np.ndarray | None = None
 
     @property
     def n(self) -> int:
         return int(self.mean.shape[1])
 
+    @property
+    def sh_degree(self) -> int:
+        return 0 if self.sh is None else int(round(np.sqrt(self.sh.shape[0] + 1))) - 1
+
     def subset(self, idx) -> "Gaussians":
         idx = np.asarray(idx)
         return Gaussians(*(np.ascontiguousarray(a[..., idx]) for a in
                            (self.mean, self.log_scale, self.quat,
-                            self.opacity_logit, self.rgb)))
+                            self.opacity_logit, self.rgb)),
+                         None if self.sh is None else
+                         np.ascontiguousarray(self.sh[..., idx]))
 
     def copy(self) -> "Gaussians":
         return Gaussians(self.mean.copy(), self.log_scale.copy(),
                          self.quat.copy(), self.opacity_logit.copy(),
-                         self.rgb.copy())
+                         self.rgb.copy(),
+                         None if self.sh is None else self.sh.copy())
 
 
 @dataclass
@@ -96,6 +106,24 @@ def _attributes(rng, n):
     opacity_logit = rng.normal(0.0, 1.0, size=n)
     rgb = rng.uniform(0.0, 1.0, size=(3, n))
     return log_scale, q, opacity_logit, rgb
+
+
+def sh_coefficients(seed: int, degree: int, n: int, scale: float = 0.1,
+                    config_id: int = 95) -> np.ndarray:
+    """View-dependent colour coefficients [(degree+1)^2 - 1][3][n], FP32,
+    normal with standard deviation `scale` (the higher-order coefficients
+    of a fitted map are small next to the base colour)."""
+    rng = _rng(config_id, seed)
+    k = (degree + 1) ** 2 - 1
+    return np.ascontiguousarray(rng.normal(0.0, scale, size=(k, 3, n)),
+                                dtype=np.float32)
+
+
+def with_sh(g: Gaussians, seed: int, degree: int, scale: float = 0.1) -> Gaussians:
+    """A copy of g carrying coefficients from sh_coefficients."""
+    out = g.copy()
+    out.sh = sh_coefficients(seed, degree, g.n, scale) if degree > 0 else None
+    return out
 
 
 def _f32(*arrays):
