@@ -57,17 +57,32 @@ extern "C" {
  * them, smaller) but hold the same contributing entries in the same order. */
 #define GS_FLAG_FULL_BOX 2
 
-/* Gaussian parameters (Eq. 1: mean, rotation quaternion, scale, opacity,
- * colour), planar structure of arrays, FP32, all device pointers.  Each row
- * holds `capacity` floats; entries [0, *n_dev) are live.
+/* Gaussian parameters (Eq. 1 and the parameter list after it: mean,
+ * rotation quaternion, scale, opacity, colour coefficients), planar
+ * structure of arrays, FP32, all device pointers.  Each row holds
+ * `capacity` floats; entries [0, *n_dev) are live.
  *   mean          [3][capacity]  x, y, z (world)
  *   log_scale     [3][capacity]  log of the per-axis standard deviation
  *   quat          [4][capacity]  w, x, y, z (any non-zero norm)
  *   opacity_logit [capacity]
- *   rgb           [3][capacity]
+ *   rgb           [3][capacity]  colour; with sh_degree > 0 the base colour
+ *   sh_degree     0..GS_SH_MAX_DEGREE: degree D of the view-dependent colour
+ *   sh            [GS_SH_ROWS(D)][capacity] view-dependent colour
+ *                 coefficients (NULL when D = 0): row 3 (j - 1) + c holds
+ *                 coefficient j = 1 .. (D+1)^2 - 1 of channel c
+ * With D > 0 the colour of a Gaussian in a view is
+ *   max(0, rgb_c + sum_j Y_j(d) sh_{j,c})
+ * where d is the unit direction from the camera centre -R^T t to the mean
+ * and Y_j the real spherical harmonics of degree 1..D in the order
+ * l = 1..D, m = -l..l (Y_lm = sqrt(2) Re Y_l^m for m > 0, sqrt(2) Im
+ * Y_l^|m| for m < 0, Y_l^0 for m = 0, Condon-Shortley phase included).
+ * With D = 0 the colour is rgb in every view, unclamped.
  * n_dev is a device int32 holding the live count, so a captured graph stays
  * valid while insertion grows the map.  The same struct describes gradient
- * and optimiser-moment arrays of the same layout (their n_dev may be NULL). */
+ * and optimiser-moment arrays of the same layout (their n_dev may be NULL;
+ * their sh_degree must equal the parameters'). */
+#define GS_SH_MAX_DEGREE 3
+#define GS_SH_ROWS(d) (3 * (((d) + 1) * ((d) + 1) - 1))
 typedef struct gs_params {
   float* mean;
   float* log_scale;
@@ -76,7 +91,8 @@ typedef struct gs_params {
   float* rgb;
   int32_t* n_dev;
   int32_t capacity;
-  int32_t pad_;
+  int32_t sh_degree;
+  float* sh;
 } gs_params;
 
 /* One view: world-to-camera rotation R (row-major) and translation t,
@@ -180,7 +196,9 @@ GS_API int gs_workspace_get_view(const gs_workspace* ws, gs_workspace_view* out)
  * of ceil(3 sqrt(lambda_max)), the integer pixel box clipped to the image,
  * the render box (see GS_FLAG_FULL_BOX) and the number of screen tiles the
  * render box touches.  This front end runs in FP64 and publishes FP32
- * records (the render box bound in FP32 with slack).  Then counts the keys
+ * records (the render box bound in FP32 with slack).  The record's colour is
+ * the Gaussian's colour in that view (gs_params: view-dependent when
+ * sh_degree > 0, evaluated in FP32 from an FP64 direction).  Then counts the keys
  * per tile, derives
  * the ranges by an exclusive scan (n_keys stays on the device; more keys than
  * key_capacity set GS_STATUS_KEY_OVERFLOW and no key is written past the
@@ -226,7 +244,8 @@ GS_API int gs_render_dominant(gs_workspace* ws, const gs_params* params,
  * Gaussian that dominates more than sigma of them into two children with
  * means mu + R(q) (s * xi[g][c]) (s = exp(log_scale), xi [capacity][2][3]
  * device standard-normal draws supplied by the caller), log-scales reduced
- * by log(1.6), rotation, opacity and colour copied.  Child 0 takes the
+ * by log(1.6), rotation, opacity, colour and view-dependent colour
+ * coefficients copied.  Child 0 takes the
  * parent's slot; child 1 is appended at the live count, in ascending parent
  * order.  Parents whose appended child would not fit in the capacity stay
  * unsplit and GS_STATUS_GAUSSIAN_OVERFLOW is set in *status_dev (may be
@@ -258,8 +277,10 @@ GS_API int gs_count_pairs(gs_workspace* ws, const gs_params* params,
  * decisions): given dL/d(out_rgb) [n_views][3][H][W] and the forward's out_T
  * and out_nlast, walks each tile's list back to front recomputing every
  * entry's transmittance from T_final (no per-entry state is stored), ADDS
- * dL/d(colour) into grad->rgb and accumulates dL/d(mean2D, conic) per view
- * and dL/d(opacity) into the workspace, where gs_project_bwd consumes them.
+ * dL/d(colour) into grad->rgb (with params->sh_degree > 0: accumulates it per
+ * view into the workspace instead) and accumulates dL/d(mean2D, conic) per
+ * view and dL/d(opacity) into the workspace, where gs_project_bwd consumes
+ * them.  grad->sh_degree must equal params->sh_degree.
  * Clamped alphas pass no gradient to opacity or shape.  Call
  * gs_project_bwd afterwards, on the same stream, to finish the backward. */
 GS_API int gs_render_bwd(gs_workspace* ws, const gs_params* params,
@@ -271,9 +292,11 @@ GS_API int gs_render_bwd(gs_workspace* ws, const gs_params* params,
  * gradients that gs_render_bwd left in the workspace, summed over the views,
  * through the conic, the EWA covariance, the Jacobian and the view transform
  * to the mean, log-scale and quaternion, and the opacity gradient through the
- * sigmoid; ADDS them into `grad` (same layout as gs_params; the caller
- * zeroes it) and clears the workspace's screen-space gradients for the next
- * backward.  cams as in gs_project_and_bin. */
+ * sigmoid; with sh_degree > 0 also the per-view colour gradients through
+ * the clamp and the harmonics to rgb, sh and (through the viewing direction)
+ * the mean.  ADDS them into `grad` (same layout as gs_params; the caller
+ * zeroes it) and clears the workspace's screen-space and colour gradients
+ * for the next backward.  cams as in gs_project_and_bin. */
 GS_API int gs_project_bwd(gs_workspace* ws, const gs_params* params,
                           const gs_camera* cams, gs_params* grad,
                           void* stream);
@@ -310,8 +333,10 @@ GS_API int gs_planar_reg(const gs_params* params, float lambda, float floor_,
                   gs_params* grad, double* loss_dev, void* stream);
 
 /* Adam step (the optimiser is not fixed by the paper) over the live entries
- * of the 14 parameter rows.  lr[5] = learning rates of mean, log_scale,
- * quat, opacity_logit, rgb.  m and v are moment arrays of the params layout.
+ * of the 14 parameter rows and the GS_SH_ROWS(sh_degree) coefficient rows.
+ * lr[5] = learning rates of mean, log_scale, quat, opacity_logit, rgb; with
+ * sh_degree > 0, lr[6], lr[5] being the coefficients'.  m and v are moment
+ * arrays of the params layout (same sh_degree).
  * The bias-correction step count is *step_dev (device int32) when step_dev
  * is not NULL - so a captured graph can advance it on the device - and
  * `step` otherwise; it must be >= 1. */
@@ -330,7 +355,8 @@ GS_API int gs_adam(gs_params* params, const gs_params* grad, gs_params* m,
  * [u v 1]^T / d - t), colour = kf_rgb [3][H][W] at the pixel, opacity logit
  * 0, identity rotation and log-scale log(z / fx) on every axis - or, when
  * mlp_out is not NULL, log-scale, opacity logit and colour from row c of
- * mlp_out [candidates][7] (log-scale 3, opacity logit, RGB 3).  Zeroes the
+ * mlp_out [candidates][7] (log-scale 3, opacity logit, RGB 3).  The
+ * view-dependent colour coefficients of new entries are zero.  Zeroes the
  * Adam moments of the new entries (m, v may be NULL), updates
  * *params->n_dev, and sets GS_STATUS_GAUSSIAN_OVERFLOW in *status_dev when
  * capacity would be exceeded (nothing past capacity is written).  At most

@@ -31,7 +31,8 @@ class gs_params(C.Structure):
     _fields_ = [("mean", C.c_void_p), ("log_scale", C.c_void_p),
                 ("quat", C.c_void_p), ("opacity_logit", C.c_void_p),
                 ("rgb", C.c_void_p), ("n_dev", C.c_void_p),
-                ("capacity", C.c_int32), ("pad_", C.c_int32)]
+                ("capacity", C.c_int32), ("sh_degree", C.c_int32),
+                ("sh", C.c_void_p)]
 
 
 class gs_camera(C.Structure):

@@ -1,10 +1,11 @@
 """Builds libgsmap.so (the HIP kernels behind the C ABI) for gfx950.
 
 Every translation unit is compiled by hipcc for gfx950 only.  Packed FP32
-instructions are disabled for device code.  The projection and compositing
-units are compiled without FMA contraction: the projection so its FP64 front
-end rounds exactly in source order, the compositing units so the forward and
-backward kernels take bit-identical decisions (they place FMAs explicitly).
+instructions are disabled for device code.  The projection, view-dependent
+colour and compositing units are compiled without FMA contraction: the
+projection so its FP64 front end rounds exactly in source order, the others
+so their forward and backward kernels take bit-identical decisions (they
+place FMAs explicitly).
 """
 from __future__ import annotations
 
@@ -35,6 +36,7 @@ NO_ATOMIC_OPT = ["-mllvm", "-amdgpu-atomic-optimizer-strategy=None"]
 UNITS = [
     ("api.hip", []),
     ("project.hip", NO_CONTRACT),
+    ("sh.hip", NO_CONTRACT),
     ("bin.hip", []),
     ("sort.hip", []),
     ("render_fwd.hip", NO_CONTRACT),

@@ -59,6 +59,25 @@ int validate_params(const gs_params* p, const char* what) {
     return GS_E_INVALID;
   }
   if (p->capacity < 0) { set_error("%s capacity < 0", what); return GS_E_INVALID; }
+  if (p->sh_degree < 0 || p->sh_degree > GS_SH_MAX_DEGREE) {
+    set_error("%s sh_degree must be 0..%d (got %d)", what, GS_SH_MAX_DEGREE,
+              p->sh_degree);
+    return GS_E_INVALID;
+  }
+  if (p->sh_degree > 0 && !p->sh) {
+    set_error("%s has sh_degree %d and a NULL sh pointer", what, p->sh_degree);
+    return GS_E_INVALID;
+  }
+  return GS_OK;
+}
+
+// Gradient and moment arrays mirror the parameters' layout.
+static int same_layout(const gs_params* p, const gs_params* q, const char* what) {
+  if (q && q->sh_degree != p->sh_degree) {
+    set_error("%s has sh_degree %d, the parameters %d", what, q->sh_degree,
+              p->sh_degree);
+    return GS_E_INVALID;
+  }
   return GS_OK;
 }
 
@@ -98,6 +117,7 @@ static int make_layout(const gs_geometry* g, Layout& L, int& tx, int& ty) {
   L.keys_sorted = take(kc * 8);
   L.grad2d = take(V * 5 * cap * 4);
   L.gop = take(cap * 4);
+  L.gcol = take(V * 3 * cap * 4);
   L.counters = take(sizeof(Counters));
   L.total = off;
   return GS_OK;
@@ -171,12 +191,14 @@ int gs_workspace_create(const gs_geometry* geo, void* device_buffer,
   ws->keys_sorted = (unsigned long long*)(b + L.keys_sorted);
   ws->grad2d = (float*)(b + L.grad2d);
   ws->gop = (float*)(b + L.gop);
+  ws->gcol = (float*)(b + L.gcol);
   ws->counters = (Counters*)(b + L.counters);
   hipStream_t st = (hipStream_t)stream;
   const size_t V = geo->n_views, cap = geo->capacity;
   hipError_t e = launch_fill_u32(ws->diff, 0, V * (size_t)(ty + 1) * (tx + 1), st);
   if (e == hipSuccess) e = launch_fill_u32(ws->grad2d, 0, V * 5 * cap, st);
   if (e == hipSuccess) e = launch_fill_u32(ws->gop, 0, cap, st);
+  if (e == hipSuccess) e = launch_fill_u32(ws->gcol, 0, V * 3 * cap, st);
   if (e == hipSuccess) e = launch_fill_u32(ws->counters, 0, sizeof(Counters) / 4, st);
   if (e == hipSuccess) e = launch_fill_u32(ws->ranges, 0, V * tx * ty * 2, st);
   if (e == hipSuccess) e = launch_fill_u32(ws->tiles_touched, 0, V * cap, st);
@@ -233,6 +255,8 @@ int gs_project_and_bin(gs_workspace* ws, const gs_params* params,
   hipStream_t st = (hipStream_t)stream;
   hipError_t e = launch_project(ws, params, cams, s, st);
   if (e != hipSuccess) return finish(e, "project");
+  e = launch_sh_colour(ws, params, cams, st);
+  if (e != hipSuccess) return finish(e, "view-dependent colour");
   ws->box_alpha_min = (s->flags & GS_FLAG_FULL_BOX) ? 0.f : s->alpha_min;
   return finish(launch_bin(ws, params, st), "bin");
 }
@@ -304,6 +328,8 @@ int gs_densify(gs_params* params, gs_params* adam_m, gs_params* adam_v,
     set_error("Adam moment capacities differ from the parameters'");
     return GS_E_CAPACITY;
   }
+  if (int rc = same_layout(params, adam_m, "adam_m")) return rc;
+  if (int rc = same_layout(params, adam_v, "adam_v")) return rc;
   if (!xi || !scratch || (n_pixels > 0 && !dom)) { set_error("an argument is NULL"); return GS_E_INVALID; }
   if (n_pixels < 0 || sigma < 0) { set_error("need n_pixels >= 0 and sigma >= 0"); return GS_E_INVALID; }
   return finish(launch_densify(params, adam_m, adam_v, dom, n_pixels, sigma, xi,
@@ -344,8 +370,10 @@ int gs_render_bwd(gs_workspace* ws, const gs_params* params,
     set_error("grad / params / workspace capacities differ");
     return GS_E_CAPACITY;
   }
+  if (int rc = same_layout(params, grad, "grad")) return rc;
   return finish(launch_render_bwd(ws, s, dL_drgb, T_final, n_last, grad->rgb,
-                                  (hipStream_t)stream), "render_bwd");
+                                  params->sh_degree > 0, (hipStream_t)stream),
+                "render_bwd");
 }
 
 int gs_project_bwd(gs_workspace* ws, const gs_params* params,
@@ -359,8 +387,12 @@ int gs_project_bwd(gs_workspace* ws, const gs_params* params,
     set_error("grad / params / workspace capacities differ");
     return GS_E_CAPACITY;
   }
-  return finish(launch_project_bwd(ws, params, cams, grad, (hipStream_t)stream),
-                "project_bwd");
+  if (int rc = same_layout(params, grad, "grad")) return rc;
+  hipStream_t st = (hipStream_t)stream;
+  hipError_t e = launch_project_bwd(ws, params, cams, grad, st);
+  if (e != hipSuccess) return finish(e, "project_bwd");
+  return finish(launch_sh_bwd(ws, params, cams, grad, st),
+                "view-dependent colour backward");
 }
 
 int gs_loss_l1(const float* rgb, const float* target, int32_t n_views,
@@ -412,6 +444,9 @@ int gs_adam(gs_params* params, const gs_params* grad, gs_params* m,
     set_error("capacities differ");
     return GS_E_CAPACITY;
   }
+  if (int rc = same_layout(params, grad, "grad")) return rc;
+  if (int rc = same_layout(params, m, "m")) return rc;
+  if (int rc = same_layout(params, v, "v")) return rc;
   return finish(launch_adam(params, grad, m, v, lr, beta1, beta2, eps, step,
                             step_dev, (hipStream_t)stream), "adam");
 }
@@ -436,6 +471,14 @@ int gs_insert_gaussians(gs_params* params, gs_params* adam_m, gs_params* adam_v,
       (adam_v && adam_v->capacity != params->capacity)) {
     set_error("moment capacities differ");
     return GS_E_CAPACITY;
+  }
+  if (adam_m) {
+    if (int rc = validate_params(adam_m, "adam_m")) return rc;
+    if (int rc = same_layout(params, adam_m, "adam_m")) return rc;
+  }
+  if (adam_v) {
+    if (int rc = validate_params(adam_v, "adam_v")) return rc;
+    if (int rc = same_layout(params, adam_v, "adam_v")) return rc;
   }
   return finish(launch_insert(params, adam_m, adam_v, cam, width, height, kf_rgb,
                               kf_T_final, pts_uvd, n_pts, alpha_skip, centre_only,
@@ -464,6 +507,14 @@ int gs_insert_distance(gs_params* params, gs_params* adam_m,
       (adam_v && adam_v->capacity != params->capacity)) {
     set_error("moment capacities differ");
     return GS_E_CAPACITY;
+  }
+  if (adam_m) {
+    if (int rc = validate_params(adam_m, "adam_m")) return rc;
+    if (int rc = same_layout(params, adam_m, "adam_m")) return rc;
+  }
+  if (adam_v) {
+    if (int rc = validate_params(adam_v, "adam_v")) return rc;
+    if (int rc = same_layout(params, adam_v, "adam_v")) return rc;
   }
   return finish(launch_insert_distance(params, adam_m, adam_v, cam, width,
                                        height, kf_rgb, pts_uvd, n_pts, tau,

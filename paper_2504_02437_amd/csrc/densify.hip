@@ -4,8 +4,9 @@
 // k_dom_count counts, per Gaussian, the pixels it dominates.  A Gaussian that
 // dominates more than sigma pixels is split into two children (the split of
 // 3D Gaussian Splatting: means mu + R(q) (s * xi_c) with caller-drawn
-// standard-normal xi, log-scales reduced by log 1.6, rotation, opacity and
-// colour copied; child 0 in the parent's slot, child 1 appended).  The
+// standard-normal xi, log-scales reduced by log 1.6, rotation, opacity,
+// colour and view-dependent colour coefficients copied; child 0 in the
+// parent's slot, child 1 appended).  The
 // appended slots follow ascending parent index through a two-level
 // exclusive scan (per-block counts, one scan block, per-block ranks), so the
 // result is deterministic; parents whose appended child would not fit in
@@ -127,6 +128,8 @@ __device__ inline void zero_slot(const gs_params& q, int cap, int s) {
   }
   for (int j = 0; j < 4; ++j) q.quat[j * cap + s] = 0.f;
   q.opacity_logit[s] = 0.f;
+  const int nsh = q.sh_degree > 0 ? GS_SH_ROWS(q.sh_degree) : 0;
+  for (int r = 0; r < nsh; ++r) q.sh[(size_t)r * cap + s] = 0.f;
 }
 
 __global__ __launch_bounds__(kBlk) void k_split_write(DensifyArgs a) {
@@ -171,6 +174,10 @@ __global__ __launch_bounds__(kBlk) void k_split_write(DensifyArgs a) {
     zero_slot(a.m, cap, t);
     zero_slot(a.v, cap, t);
   }
+  // View-dependent colour coefficients: child 0 keeps the parent's.
+  const int nsh = P.sh_degree > 0 ? GS_SH_ROWS(P.sh_degree) : 0;
+  for (int r = 0; r < nsh; ++r)
+    P.sh[(size_t)r * cap + slots[1]] = P.sh[(size_t)r * cap + g];
 }
 
 }  // namespace

@@ -19,7 +19,7 @@ struct __align__(16) Record {
 // Workspace layout: every region is carved from the caller's device buffer.
 struct Layout {
   size_t records, tiles_touched, rbox, diff, ranges, cursor, view_tot, keys_unsorted,
-      vals_sorted, keys_sorted, grad2d, gop, counters, total;
+      vals_sorted, keys_sorted, grad2d, gop, gcol, counters, total;
 };
 
 // Device-side counters block.
@@ -68,6 +68,8 @@ struct gs_workspace {
   unsigned long long* keys_sorted;
   float* grad2d;         // [V][5][capacity]
   float* gop;            // [capacity] dL/d opacity summed over views
+  float* gcol;           // [V][3][capacity] dL/d colour per view (used with
+                         // view-dependent colour)
   gs::Counters* counters;
 };
 
@@ -111,7 +113,12 @@ hipError_t launch_count_pairs(gs_workspace* ws, const gs_settings* s,
 hipError_t launch_render_bwd(gs_workspace* ws, const gs_settings* s,
                              const float* dL, const float* T,
                              const int32_t* nlast, float* grad_rgb,
-                             hipStream_t st);
+                             int per_view_colour, hipStream_t st);
+hipError_t launch_sh_colour(gs_workspace* ws, const gs_params* p,
+                            const gs_camera* cams, hipStream_t st);
+hipError_t launch_sh_bwd(gs_workspace* ws, const gs_params* p,
+                         const gs_camera* cams, gs_params* grad,
+                         hipStream_t st);
 hipError_t launch_fill_u32(void* ptr, uint32_t value, size_t count,
                            hipStream_t st);
 hipError_t launch_loss_l1(const float* rgb, const float* target, int V, int H,

@@ -108,6 +108,12 @@ struct AdamArgs {
   float* m[14];
   float* v[14];
   float lr[14];
+  // View-dependent colour coefficient rows (row 14 + r at offset r cap).
+  float* psh;
+  const float* gsh;
+  float* msh;
+  float* vsh;
+  float lr_sh;
   const int32_t* n_dev;
   const int32_t* step_dev;
   int cap, step;
@@ -128,12 +134,21 @@ __global__ __launch_bounds__(256) void k_adam(AdamArgs a) {
   __syncthreads();
   if (g >= n) return;
   const float c1 = corr[0], c2 = corr[1];
-  const float gr = a.g[row][g];
-  const float m = a.b1 * a.m[row][g] + (1.f - a.b1) * gr;
-  const float v = a.b2 * a.v[row][g] + (1.f - a.b2) * gr * gr;
-  a.m[row][g] = m;
-  a.v[row][g] = v;
-  a.p[row][g] -= a.lr[row] * (m / c1) / (sqrtf(v / c2) + a.eps);
+  float *P, *M, *Vv;
+  const float* G;
+  float lr;
+  if (row < 14) {
+    P = a.p[row]; G = a.g[row]; M = a.m[row]; Vv = a.v[row]; lr = a.lr[row];
+  } else {
+    const size_t o = (size_t)(row - 14) * a.cap;
+    P = a.psh + o; G = a.gsh + o; M = a.msh + o; Vv = a.vsh + o; lr = a.lr_sh;
+  }
+  const float gr = G[g];
+  const float m = a.b1 * M[g] + (1.f - a.b1) * gr;
+  const float v = a.b2 * Vv[g] + (1.f - a.b2) * gr * gr;
+  M[g] = m;
+  Vv[g] = v;
+  P[g] -= lr * (m / c1) / (sqrtf(v / c2) + a.eps);
 }
 
 struct InsertArgs {
@@ -157,6 +172,12 @@ struct InsertArgs {
   // bits of each candidate's nearest squared distance (all ones: no mean).
   const unsigned long long* d2bits;
   double tau2;
+  // View-dependent colour coefficient rows, zeroed for new entries (the
+  // moments' may be null).
+  float* sh;
+  float* msh;
+  float* vsh;
+  int n_sh_rows;
 };
 
 // Back-projection of candidate pixel (u, v) with inverse depth d (Eq. 6),
@@ -242,6 +263,12 @@ __global__ __launch_bounds__(kInsThreads) void k_insert(InsertArgs a) {
           if (a.mrows[r]) a.mrows[r][dst] = 0.f;
           if (a.vrows[r]) a.vrows[r][dst] = 0.f;
         }
+        for (int r = 0; r < a.n_sh_rows; ++r) {
+          const size_t o = (size_t)r * a.cap + dst;
+          a.sh[o] = 0.f;
+          if (a.msh) a.msh[o] = 0.f;
+          if (a.vsh) a.vsh[o] = 0.f;
+        }
       }
     }
     running += count;
@@ -308,6 +335,17 @@ void rows_of(const gs_params* p, float** rows) {
   for (int i = 0; i < 3; ++i) rows[11 + i] = p->rgb ? p->rgb + (size_t)i * cap : nullptr;
 }
 
+// Row pointers of the parameters and (optional) moments for k_insert.
+void insert_rows(gs_params* p, gs_params* m, gs_params* v, InsertArgs& a) {
+  rows_of(p, a.rows);
+  if (m) rows_of(m, a.mrows); else for (int i = 0; i < 14; ++i) a.mrows[i] = nullptr;
+  if (v) rows_of(v, a.vrows); else for (int i = 0; i < 14; ++i) a.vrows[i] = nullptr;
+  a.n_sh_rows = p->sh_degree > 0 ? GS_SH_ROWS(p->sh_degree) : 0;
+  a.sh = p->sh;
+  a.msh = m ? m->sh : nullptr;
+  a.vsh = v ? v->sh : nullptr;
+}
+
 }  // namespace
 
 hipError_t launch_fill_u32(void* ptr, uint32_t value, size_t count,
@@ -357,12 +395,15 @@ hipError_t launch_adam(gs_params* p, const gs_params* g, gs_params* m,
   rows_of(v, a.v);
   const int grp[14] = {0, 0, 0, 1, 1, 1, 2, 2, 2, 2, 3, 4, 4, 4};
   for (int i = 0; i < 14; ++i) a.lr[i] = lr[grp[i]];
+  const int nsh = p->sh_degree > 0 ? GS_SH_ROWS(p->sh_degree) : 0;
+  a.psh = p->sh; a.gsh = g->sh; a.msh = m->sh; a.vsh = v->sh;
+  a.lr_sh = nsh ? lr[5] : 0.f;
   a.n_dev = p->n_dev; a.cap = p->capacity;
   a.b1 = b1; a.b2 = b2; a.eps = eps;
   a.step = step; a.step_dev = step_dev;
   const int blocks = (p->capacity + 255) / 256;
   if (blocks <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_adam, dim3(blocks, 14), dim3(256), 0, st, a);
+  hipLaunchKernelGGL(k_adam, dim3(blocks, 14 + nsh), dim3(256), 0, st, a);
   return hipGetLastError();
 }
 
@@ -373,9 +414,7 @@ hipError_t launch_insert(gs_params* p, gs_params* m, gs_params* v,
                          int centre_only, const float* mlp_out,
                          int32_t* n_inserted, int32_t* status, hipStream_t st) {
   InsertArgs a;
-  rows_of(p, a.rows);
-  if (m) rows_of(m, a.mrows); else for (int i = 0; i < 14; ++i) a.mrows[i] = nullptr;
-  if (v) rows_of(v, a.vrows); else for (int i = 0; i < 14; ++i) a.vrows[i] = nullptr;
+  insert_rows(p, m, v, a);
   a.n_dev = p->n_dev; a.cap = p->capacity; a.cam = cam; a.W = W; a.H = H;
   a.kf_rgb = kf_rgb; a.kf_T = kf_T; a.pts = pts; a.n_pts = n_pts;
   a.alpha_skip = alpha_skip; a.centre_only = centre_only; a.mlp_out = mlp_out;
@@ -411,9 +450,7 @@ hipError_t launch_insert_distance(gs_params* p, gs_params* m, gs_params* v,
     if (e != hipSuccess) return e;
   }
   InsertArgs a;
-  rows_of(p, a.rows);
-  if (m) rows_of(m, a.mrows); else for (int i = 0; i < 14; ++i) a.mrows[i] = nullptr;
-  if (v) rows_of(v, a.vrows); else for (int i = 0; i < 14; ++i) a.vrows[i] = nullptr;
+  insert_rows(p, m, v, a);
   a.n_dev = p->n_dev; a.cap = p->capacity; a.cam = cam; a.W = W; a.H = H;
   a.kf_rgb = kf_rgb; a.kf_T = nullptr; a.pts = pts; a.n_pts = n_pts;
   a.alpha_skip = 0.f; a.centre_only = centre_only; a.mlp_out = mlp_out;

@@ -31,7 +31,9 @@ struct BwdArgs {
   const int32_t* nlast;
   float* grad2d;   // [V][5][cap]
   float* gop;      // [cap]
-  float* grgb;     // [3][cap] (caller's gradient rows, accumulated)
+  float* grgb;     // [3][cap] (caller's gradient rows, accumulated), or
+                   // [V][3][cap] per view (view-dependent colour)
+  size_t grgb_vstride;   // 0, or 3 cap for per-view colour gradients
 };
 
 // x plus the DPP-permuted y.  Lanes whose source lies outside their row read
@@ -144,6 +146,7 @@ __global__ __launch_bounds__(NT) void k_render_bwd(BwdArgs a) {
   const Record* rv = r.rec + (size_t)k * r.cap;
   const int2* rbv = r.rbox + (size_t)k * r.cap;
   float* gk = a.grad2d + (size_t)k * 5 * r.cap;
+  float* gc = a.grgb + (size_t)k * a.grgb_vstride;
 
   for (int hi = maxlast; hi > 0; hi -= BATCH) {
     const int lo = max(0, hi - BATCH);
@@ -234,7 +237,7 @@ __global__ __launch_bounds__(NT) void k_render_bwd(BwdArgs a) {
       const uint32_t g = gid[jj];
       if (q < 5) atomicAdd(&gk[(size_t)q * r.cap + g], val);
       else if (q == 5) atomicAdd(&a.gop[g], val);
-      else atomicAdd(&a.grgb[(size_t)(q - 6) * r.cap + g], val);
+      else atomicAdd(&gc[(size_t)(q - 6) * r.cap + g], val);
     }
   }
 }
@@ -255,11 +258,13 @@ struct BwdLauncher {
 hipError_t launch_render_bwd(gs_workspace* ws, const gs_settings* s,
                              const float* dL, const float* T,
                              const int32_t* nlast, float* grad_rgb,
-                             hipStream_t st) {
+                             int per_view_colour, hipStream_t st) {
   BwdArgs a;
   a.r = make_raster_args(ws, s);
   a.dL = dL; a.Tfin = T; a.nlast = nlast;
-  a.grad2d = ws->grad2d; a.gop = ws->gop; a.grgb = grad_rgb;
+  a.grad2d = ws->grad2d; a.gop = ws->gop;
+  a.grgb = per_view_colour ? ws->gcol : grad_rgb;
+  a.grgb_vstride = per_view_colour ? (size_t)3 * ws->geo.capacity : 0;
   const int blocks = ws->geo.n_views * ws->tiles_x * ws->tiles_y;
   if (blocks <= 0) return hipSuccess;
   dispatch_shape(ws->geo.tile, s->lds_batch, s->block_threads,

@@ -38,18 +38,29 @@ def _require_cuda(t, name):
         raise ValueError(f"{name} must be contiguous")
 
 
+def sh_rows(degree: int) -> int:
+    """Rows of view-dependent colour coefficients for a degree (0..3)."""
+    return 3 * ((degree + 1) ** 2 - 1)
+
+
 class ParamBuffer:
     """Gaussian parameters (or gradients / optimiser moments of the same
-    layout) as one FP32 device tensor [14][capacity] whose rows are
-    mean 0-2, log_scale 3-5, quat 6-9 (w, x, y, z), opacity_logit 10 and
-    rgb 11-13, plus a device int32 live count."""
+    layout) as one FP32 device tensor [14 + sh_rows(sh_degree)][capacity]
+    whose rows are mean 0-2, log_scale 3-5, quat 6-9 (w, x, y, z),
+    opacity_logit 10, rgb 11-13 and, from row 14, the view-dependent colour
+    coefficients (row 14 + 3 (j - 1) + c: coefficient j of channel c), plus a
+    device int32 live count."""
 
     def __init__(self, capacity: int, device="cuda", n: int = 0, data=None,
-                 n_dev=None):
+                 n_dev=None, sh_degree: int = 0):
+        if not 0 <= sh_degree <= 3:
+            raise ValueError("sh_degree must be 0..3")
         self.capacity = int(capacity)
-        self.data = (torch.zeros(14, self.capacity, dtype=torch.float32,
+        self.sh_degree = int(sh_degree)
+        rows = 14 + sh_rows(self.sh_degree)
+        self.data = (torch.zeros(rows, self.capacity, dtype=torch.float32,
                                  device=device) if data is None else data)
-        assert self.data.shape == (14, self.capacity)
+        assert self.data.shape == (rows, self.capacity)
         self.n_dev = (torch.tensor([n], dtype=torch.int32, device=device)
                       if n_dev is None else n_dev)
 
@@ -59,20 +70,27 @@ class ParamBuffer:
         cap = n if capacity is None else int(capacity)
         if cap < n:
             raise ValueError("capacity below the Gaussian count")
-        host = np.zeros((14, cap), np.float32)
+        D = getattr(g, "sh_degree", 0)
+        host = np.zeros((14 + sh_rows(D), cap), np.float32)
         host[0:3, :n] = g.mean
         host[3:6, :n] = g.log_scale
         host[6:10, :n] = g.quat
         host[10, :n] = g.opacity_logit
         host[11:14, :n] = g.rgb
-        return cls(cap, device, n, torch.from_numpy(host).to(device))
+        if D:
+            host[14:, :n] = np.asarray(g.sh, np.float32).reshape(-1, n)
+        return cls(cap, device, n, torch.from_numpy(host).to(device),
+                   sh_degree=D)
 
     def zeros_like(self, share_count=True):
         return ParamBuffer(self.capacity, self.data.device,
                            data=torch.zeros_like(self.data),
-                           n_dev=self.n_dev if share_count else None)
+                           n_dev=self.n_dev if share_count else None,
+                           sh_degree=self.sh_degree)
 
     def row(self, name):
+        if name == "sh":
+            return self.data[14:]
         a, b = ROWS[name]
         return self.data[a:b]
 
@@ -85,12 +103,17 @@ class ParamBuffer:
         return L.gs_params(base + 0 * stride, base + 3 * stride,
                            base + 6 * stride, base + 10 * stride,
                            base + 11 * stride, self.n_dev.data_ptr(),
-                           self.capacity, 0)
+                           self.capacity, self.sh_degree,
+                           base + 14 * stride if self.sh_degree else 0)
 
     def to_numpy(self):
+        """Live rows as numpy; "sh" is [K-1][3][n] when sh_degree > 0."""
         n = self.n()
         h = self.data[:, :n].cpu().numpy()
-        return {k: (h[a:b] if b - a > 1 else h[a]) for k, (a, b) in ROWS.items()}
+        out = {k: (h[a:b] if b - a > 1 else h[a]) for k, (a, b) in ROWS.items()}
+        if self.sh_degree:
+            out["sh"] = h[14:].reshape(-1, 3, n)
+        return out
 
 
 def camera_struct(cam) -> L.gs_camera:
@@ -356,8 +379,12 @@ def planar_reg(params, lam, floor, grad, loss_dev, stream=None):
 def adam(params, grad, m, v, lr, beta1, beta2, eps, step, stream=None):
     """Adam step; `step` is an int, or an int32 device tensor holding the
     step count (read on the device, so graph replays see its current
-    value)."""
-    lr_arr = (C.c_float * 5)(*[float(x) for x in lr])
+    value).  lr: rates of mean, log_scale, quat, opacity_logit, rgb and,
+    for view-dependent colour, the coefficients (default rgb's / 20)."""
+    lr = [float(x) for x in lr]
+    if len(lr) == 5:
+        lr.append(lr[4] / 20.0)
+    lr_arr = (C.c_float * 6)(*lr)
     if isinstance(step, torch.Tensor):
         if step.dtype != torch.int32 or not step.is_cuda:
             raise ValueError("a device step count must be an int32 device tensor")

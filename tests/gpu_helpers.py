@@ -4,6 +4,7 @@ import numpy as np
 import torch
 
 import oracle
+from oracle import sh as OS
 from paper_2504_02437_amd import raster as R
 
 IMG_TOL = 1e-5       # absolute, per pixel and channel (FP32 vs FP64)
@@ -25,12 +26,20 @@ def gpu_forward(w, tile=16, batch=256, bg=(0.0, 0.0, 0.0), emit_keys=True,
     return params, rast
 
 
+def oracle_colours(w, p64):
+    """The oracle's colours: rgb [3][n], or [V][3][n] per view when the
+    Gaussians carry view-dependent colour coefficients."""
+    D = w.gaussians.sh_degree
+    return p64["rgb"] if D == 0 else OS.colours(p64, w.cameras, D)[0]
+
+
 def oracle_forward(w, tile=16, bg=(0.0, 0.0, 0.0), nthreads=8):
     p64 = oracle.params64(w.gaussians)
     W, H = w.cameras[0].width, w.cameras[0].height
     proj = oracle.project(p64, w.cameras, tile, publish=True, nthreads=nthreads)
     bins = oracle.bin_sort(proj, tile, W, H, emit=False)
-    fwd = oracle.forward(proj, bins, p64["rgb"], W, H, bg, nthreads=nthreads)
+    fwd = oracle.forward(proj, bins, oracle_colours(w, p64), W, H, bg,
+                         nthreads=nthreads)
     return p64, proj, bins, fwd
 
 
@@ -148,9 +157,13 @@ def check_forward(rast, fwd, bins=None, max_flagged=MAX_FLAGGED):
 
 
 def check_grads(got, ref, n, rtol=GRAD_RTOL, names=None):
-    """got: [14][cap] GPU gradients; ref: dict of oracle gradients."""
+    """got: [14 + coefficient rows][cap] GPU gradients; ref: dict of oracle
+    gradients (with "sh" [K-1][3][n] for view-dependent colour)."""
     worst = {}
-    for name, (a, b) in R.ROWS.items():
+    rows = dict(R.ROWS)
+    if "sh" in ref:
+        rows["sh"] = (14, got.shape[0])
+    for name, (a, b) in rows.items():
         if names and name not in names:
             continue
         r = np.asarray(ref[name]).reshape(b - a, -1)
@@ -173,8 +186,11 @@ def gpu_backward(rast, params, dL):
 
 def oracle_backward(w, p64, proj, bins, dL, bg=(0.0, 0.0, 0.0), nthreads=8):
     W, H = w.cameras[0].width, w.cameras[0].height
-    b = oracle.backward(proj, bins, p64["rgb"], W, H, dL.astype(np.float64), bg,
-                        nthreads=nthreads)
+    b = oracle.backward(proj, bins, oracle_colours(w, p64), W, H,
+                        dL.astype(np.float64), bg, nthreads=nthreads)
+    D = w.gaussians.sh_degree
+    if D:
+        return OS.chain(p64, w.cameras, D, b, nthreads=nthreads)
     return oracle.project_bwd(p64, w.cameras, b, nthreads=nthreads)
 
 

@@ -95,3 +95,47 @@ def test_insert_and_adam_reject_bad_arguments():
     assert lib.gs_insert_gaussians(C.byref(p), None, None, None, 10, 10, None,
                                    None, None, 5, 0.9, 0, None, None, None,
                                    None) == L.GS_E_INVALID
+
+
+def _fake_params(D=0, sh=True):
+    p = L.gs_params()
+    p.mean = p.log_scale = p.quat = p.opacity_logit = p.rgb = 256
+    p.n_dev = 256
+    p.capacity = 10
+    p.sh_degree = D
+    p.sh = 256 if (sh and D) else None
+    return p
+
+
+def test_view_dependent_colour_layout_is_checked_on_the_host():
+    """sh_degree outside 0..3, a missing coefficient pointer and gradient or
+    moment arrays whose degree differs from the parameters' are rejected
+    before anything is launched."""
+    lib = L.lib()
+    lr = (C.c_float * 6)(1, 1, 1, 1, 1, 1)
+    for bad in (_fake_params(4), _fake_params(-1), _fake_params(2, sh=False)):
+        assert lib.gs_adam(C.byref(bad), C.byref(bad), C.byref(bad),
+                           C.byref(bad), lr, 0.9, 0.999, 1e-15, 1, None,
+                           None) == L.GS_E_INVALID
+        assert b"sh" in lib.gs_last_error()
+    p, q = _fake_params(3), _fake_params(2)
+    assert lib.gs_adam(C.byref(p), C.byref(q), C.byref(p), C.byref(p), lr,
+                       0.9, 0.999, 1e-15, 1, None, None) == L.GS_E_INVALID
+    assert b"sh_degree" in lib.gs_last_error()
+    assert lib.gs_adam(C.byref(p), C.byref(p), C.byref(p), C.byref(q), lr,
+                       0.9, 0.999, 1e-15, 1, None, None) == L.GS_E_INVALID
+    assert lib.gs_densify(C.byref(p), C.byref(q), None, None, 0, 1,
+                          C.c_void_p(256), C.c_void_p(256), None, None,
+                          None) == L.GS_E_INVALID
+    assert b"sh_degree" in lib.gs_last_error()
+    assert lib.gs_insert_gaussians(C.byref(p), C.byref(q), None,
+                                   C.c_void_p(256), 10, 10, C.c_void_p(256),
+                                   C.c_void_p(256), C.c_void_p(256), 5, 0.9, 0,
+                                   None, None, None, None) == L.GS_E_INVALID
+    assert b"sh_degree" in lib.gs_last_error()
+
+
+def test_params_struct_layout():
+    """gs_params: six pointers, capacity, sh_degree, coefficient pointer."""
+    assert C.sizeof(L.gs_params) == 64
+    assert L.gs_params.sh_degree.offset == 52 and L.gs_params.sh.offset == 56

@@ -1,0 +1,273 @@
+"""GPU view-dependent colour (real spherical harmonics of the viewing
+direction, degrees 1-3) against the oracle: the per-view record colours
+within 2e-6, images within 1e-5, gradients of every row including the
+coefficients within 1e-3 relative, the clamp, and the coefficient rows'
+handling by Adam, insertion, densification and autograd."""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from oracle import densify as OD
+from oracle import sh as OS
+import synth
+from gpu_helpers import (check_forward, check_grads, check_records, check_sort,
+                         gpu_backward, gpu_forward, masked_dL, oracle_backward,
+                         oracle_forward)
+from paper_2504_02437_amd import raster as R
+
+pytestmark = pytest.mark.gpu
+
+COL_TOL = 2e-6     # FP32 harmonics from an FP64 direction vs FP64
+
+
+def _views(c, rng, extra):
+    cams = [c]
+    for _ in range(extra):
+        a = rng.normal(0, 0.15, 3)
+        cs, sn = np.cos(a[0]), np.sin(a[0])
+        Rm = np.array([[cs, 0, sn], [0, 1, 0], [-sn, 0, cs]], np.float32)
+        cams.append(synth.Camera(Rm, rng.normal(0, 0.15, 3).astype(np.float32),
+                                 c.fx, c.fy, c.cx, c.cy, c.width, c.height))
+    return cams
+
+
+def _away_from_clamp(w, margin=1e-4):
+    """Moves base colours whose value in some view lies within `margin` of
+    the clamp, so FP32 and FP64 take the same clamp decision."""
+    p64 = oracle.params64(w.gaussians)
+    _, raw = OS.colours(p64, w.cameras, w.gaussians.sh_degree)
+    near = (np.abs(raw) < margin).any(0)             # [3][n]
+    w.gaussians.rgb[near] += np.float32(4 * margin)
+    return int(near.sum())
+
+
+def _window(seed, D, n=500, W=77, H=53, extra=2, scale=0.12):
+    w = synth.tiny_scene(seed, n=n, width=W, height=H, f=60.0, log_scale_mu=-2.0)
+    w.cameras = _views(w.cameras[0], np.random.default_rng(seed), extra)
+    w.gaussians = synth.with_sh(w.gaussians, seed, D, scale)
+    # Some base colours below zero: clamped in some views, not in others.
+    w.gaussians.rgb[:, :40] -= np.float32(0.6)
+    _away_from_clamp(w)
+    return w
+
+
+def _record_colours(rast):
+    rec = rast.ws.records().cpu().numpy()            # [V][cap][12]
+    return np.moveaxis(rec[..., 6:9], -1, 1)         # [V][3][cap]
+
+
+def _check_colours(rast, w, p64):
+    D = w.gaussians.sh_degree
+    vis = rast.ws.tiles_touched().cpu().numpy() > 0  # [V][cap]
+    got = _record_colours(rast)[..., :w.gaussians.n]
+    ref, raw = OS.colours(p64, w.cameras, D)
+    m = np.broadcast_to(vis[:, None, :w.gaussians.n], ref.shape)
+    err = np.abs(got - ref)[m]
+    assert err.max(initial=0.0) <= COL_TOL, err.max()
+    # The clamp: exactly zero where the oracle clamps.
+    assert np.all(got[m & (raw < 0)] == 0.0)
+    return float((raw[m] < 0).mean())
+
+
+@pytest.mark.parametrize("D", [1, 2, 3])
+def test_window_matches_oracle(D):
+    w = _window(30 + D, D)
+    bg = (0.1, 0.2, 0.3)
+    print("case sh window", D, flush=True)
+    p64, proj, bins, fwd = oracle_forward(w, 16, bg)
+    params, rast = gpu_forward(w, 16, 256, bg)
+    check_records(rast, proj)
+    check_sort(rast, bins)
+    clamped = _check_colours(rast, w, p64)
+    assert 0.0 < clamped < 0.5
+    mask, _ = check_forward(rast, fwd, bins)
+    dL = masked_dL(np.random.default_rng(7), mask, (3, 3, 53, 77))
+    got = gpu_backward(rast, params, dL)
+    ref = oracle_backward(w, p64, proj, bins, dL, bg)
+    worst = check_grads(got, ref, w.gaussians.n)
+    print("sh worst rel err", worst, flush=True)
+
+
+@pytest.mark.parametrize("tile,batch,threads", [(8, 128, 64), (32, 256, 256)])
+def test_other_launch_shapes(tile, batch, threads):
+    w = _window(41, 3, n=800, W=100, H=70)
+    print("case sh shape", tile, batch, threads, flush=True)
+    p64, proj, bins, fwd = oracle_forward(w, tile)
+    params, rast = gpu_forward(w, tile, batch, threads=threads)
+    _check_colours(rast, w, p64)
+    mask, _ = check_forward(rast, fwd, bins)
+    dL = masked_dL(np.random.default_rng(8), mask, (3, 3, 70, 100))
+    got = gpu_backward(rast, params, dL)
+    check_grads(got, oracle_backward(w, p64, proj, bins, dL), w.gaussians.n)
+
+
+def test_zero_coefficients_render_as_view_independent_colour():
+    """Coefficients all zero and base colours >= 0: every degree renders the
+    degree-0 image bit for bit, and the gradients of the shared rows agree
+    to rounding (the colour gradient is summed in another order)."""
+    w = _window(42, 0, n=600)
+    w.gaussians.rgb[:] = np.abs(w.gaussians.rgb)
+    base_params, base = gpu_forward(w, 16, 256)
+    rgb0 = base.rgb.clone()
+    dL = torch.randn(3, 3, 53, 77, device="cuda")
+    g0 = base_params.zeros_like()
+    base.backward(base_params, dL, g0)
+    for D in (1, 3):
+        w3 = synth.Workload(w.name, synth.with_sh(w.gaussians, 1, D), w.cameras,
+                            w.targets)
+        w3.gaussians.sh[:] = 0.0
+        params, rast = gpu_forward(w3, 16, 256)
+        assert torch.equal(rast.rgb, rgb0)
+        g = params.zeros_like()
+        rast.backward(params, dL, g)
+        torch.cuda.synchronize()
+        a, b = g.data[:14].cpu().numpy(), g0.data.cpu().numpy()
+        scale = np.abs(b).max(axis=1, keepdims=True)
+        assert np.all(np.abs(a - b) <= 1e-5 * scale + 1e-12)
+
+
+def test_config1_degree3_full_size():
+    """The 300k-Gaussian room view at 1200x680 with degree-3 colour, in the
+    benchmark's single-view launch configuration: record colours of every
+    binned pair, every unflagged pixel within 1e-5 and the gradients of every
+    Gaussian, coefficients included."""
+    w = synth.config1()
+    w.gaussians = synth.with_sh(w.gaussians, 3, 3, 0.05)
+    _away_from_clamp(w)
+    print("case sh config1 oracle", flush=True)
+    p64, proj, bins, fwd = oracle_forward(w, 16, nthreads=16)
+    print("case sh config1 gpu", flush=True)
+    params, rast = gpu_forward(w, 16, 256)
+    check_records(rast, proj)
+    _check_colours(rast, w, p64)
+    mask, err = check_forward(rast, fwd, bins)
+    dL = masked_dL(np.random.default_rng(12), mask, (1, 3, 680, 1200),
+                   1.0 / (3 * 680 * 1200))
+    got = gpu_backward(rast, params, dL)
+    ref = oracle_backward(w, p64, proj, bins, dL, nthreads=16)
+    worst = check_grads(got, ref, w.gaussians.n)
+    print("sh config1 worst grad rel err", worst, flush=True)
+
+
+def test_window10_degree3_record_colours_full_size():
+    """Ten 1200x680 views of the 300k room with degree-3 colour: the colour
+    of every binned (view, Gaussian) record against the oracle's."""
+    w = synth.config2()
+    w.gaussians = synth.with_sh(w.gaussians, 4, 3, 0.05)
+    print("case sh window10", flush=True)
+    params = R.ParamBuffer.from_gaussians(w.gaussians)
+    rast = R.Rasterizer(w.cameras, params.capacity, R.Settings(tile=32))
+    rast.fit_key_capacity(params)
+    rast.forward(params)
+    torch.cuda.synchronize()
+    p64 = oracle.params64(w.gaussians)
+    frac = _check_colours(rast, w, p64)
+    print("clamped fraction", frac, flush=True)
+
+
+def test_adam_updates_coefficient_rows():
+    w = synth.tiny_scene(53, n=300)
+    g = synth.with_sh(w.gaussians, 53, 2)
+    params = R.ParamBuffer.from_gaussians(g, capacity=400)
+    assert params.data.shape[0] == 14 + 24
+    rng = np.random.default_rng(9)
+    grad = params.zeros_like()
+    grad.data.copy_(torch.from_numpy(rng.normal(size=(38, 400)).astype(np.float32)))
+    m, v = params.zeros_like(), params.zeros_like()
+    p0 = params.data.clone()
+    lr = (1e-2, 2e-2, 3e-2, 4e-2, 5e-2, 7e-3)
+    for step in (1, 2):
+        R.adam(params, grad, m, v, lr, 0.9, 0.999, 1e-15, step)
+    torch.cuda.synchronize()
+    p = p0.cpu().numpy().astype(np.float64)
+    gg = grad.data.cpu().numpy().astype(np.float64)
+    for r in range(14, 38):
+        pr, mr, vr = p[r, :300], np.zeros(300), np.zeros(300)
+        for step in (1, 2):
+            pr, mr, vr = oracle.adam(pr, gg[r, :300], mr, vr, lr[5], step)
+        np.testing.assert_allclose(params.data[r, :300].cpu().numpy(), pr,
+                                   rtol=0, atol=1e-6)
+    assert torch.equal(params.data[:, 300:], p0[:, 300:])
+    # Five rates: the coefficients take the colour's rate / 20.
+    params2 = R.ParamBuffer.from_gaussians(g, capacity=400)
+    m.data.zero_()
+    v.data.zero_()
+    R.adam(params2, grad, m, v, lr[:5], 0.9, 0.999, 1e-15, 1)
+    pr, _, _ = oracle.adam(p[20, :300], gg[20, :300], np.zeros(300),
+                           np.zeros(300), float(np.float32(lr[4] / 20)), 1)
+    np.testing.assert_allclose(params2.data[20, :300].cpu().numpy(), pr,
+                               rtol=0, atol=1e-6)
+
+
+def test_insertion_zeroes_the_coefficients_of_new_entries():
+    W, H = 64, 48
+    cam = synth.identity_camera(50.0, 50.0, W, H)
+    g = synth.with_sh(synth.tiny_scene(54, n=100).gaussians, 54, 3)
+    params = R.ParamBuffer.from_gaussians(g, capacity=1200)
+    params.data[14:, 100:] = 5.0                     # stale values to clear
+    m, v = params.zeros_like(), params.zeros_like()
+    m.data.fill_(3.0)
+    v.data.fill_(3.0)
+    rng = np.random.default_rng(10)
+    pts = np.stack([rng.integers(1, W - 1, 50), rng.integers(1, H - 1, 50),
+                    rng.uniform(0.3, 1.0, 50)], 1).astype(np.float32)
+    kT = torch.ones(H, W, device="cuda")
+    img = torch.rand(3, H, W, device="cuda")
+    nins = torch.zeros(1, dtype=torch.int32, device="cuda")
+    R.insert_gaussians(params, m, v, R.cameras_to_device([cam]), W, H, img, kT,
+                       torch.from_numpy(pts).cuda(), 0.5, n_inserted_dev=nins)
+    torch.cuda.synchronize()
+    k = int(nins)
+    assert k == 450 and params.n() == 550
+    assert torch.all(params.data[14:, 100:550] == 0)
+    assert torch.all(params.data[14:, 550:] == 5.0)
+    assert torch.equal(params.data[14:, :100].cpu(),
+                       torch.from_numpy(g.sh.reshape(45, 100)))
+    assert torch.all(m.data[:, 100:550] == 0) and torch.all(v.data[:, 100:550] == 0)
+    assert torch.all(m.data[:, :100] == 3.0)
+
+
+def test_densify_copies_the_coefficients():
+    w = synth.config0()
+    w.gaussians = synth.with_sh(w.gaussians, 55, 2)
+    n = w.gaussians.n
+    cap = n + 3000
+    params = R.ParamBuffer.from_gaussians(w.gaussians, capacity=cap)
+    rast = R.Rasterizer(w.cameras, cap, R.Settings(tile=16))
+    rast.fit_key_capacity(params)
+    dom = rast.forward_dominant(params)
+    m, v = params.zeros_like(), params.zeros_like()
+    m.data.fill_(1.0)
+    v.data.fill_(2.0)
+    xi = np.random.default_rng(11).normal(size=(cap, 2, 3)).astype(np.float32)
+    n_split = torch.zeros(1, dtype=torch.int32, device="cuda")
+    R.densify(params, m, v, dom, 20, torch.from_numpy(xi).cuda(), n_split=n_split)
+    torch.cuda.synchronize()
+    counts = OD.dominated_counts(dom.cpu().numpy(), cap)
+    parents = [g for g in range(n) if counts[g] > 20]
+    k = int(n_split)
+    assert k == len(parents) > 10 and params.n() == n + k
+    sh = params.data[14:].cpu().numpy()
+    ref = w.gaussians.sh.reshape(24, n)
+    np.testing.assert_array_equal(sh[:, :n], ref)
+    np.testing.assert_array_equal(sh[:, n:n + k], ref[:, parents])
+    mm = m.data.cpu().numpy()
+    slots = parents + list(range(n, n + k))
+    assert np.all(mm[14:, slots] == 0) and np.all(v.data.cpu().numpy()[14:, slots] == 0)
+
+
+def test_autograd_returns_coefficient_gradients():
+    w = _window(43, 3, n=400)
+    p64, proj, bins, fwd = oracle_forward(w, 16)
+    params = R.ParamBuffer.from_gaussians(w.gaussians)
+    rast = R.Rasterizer(w.cameras, params.capacity, R.Settings(tile=16))
+    data = params.data.requires_grad_(True)
+    rgb, T, nl = R.Rasterize.apply(data, rast, params)
+    mask = fwd["flags"] == 0
+    dL = masked_dL(np.random.default_rng(13), mask, tuple(rgb.shape))
+    (rgb * torch.from_numpy(dL).cuda()).sum().backward()
+    got = data.grad.detach().cpu().numpy()
+    assert got.shape == (14 + 45, params.capacity)
+    ref = oracle_backward(w, p64, proj, bins, dL)
+    check_grads(got, ref, w.gaussians.n)
