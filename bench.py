@@ -220,6 +220,9 @@ def main():
                     help="skip the per-keyframe densification timing")
     ap.add_argument("--no-ssim", action="store_true",
                     help="skip the full colour loss (L1 + SSIM) timing")
+    ap.add_argument("--sh-degree", type=int, default=0, choices=[0, 1, 2, 3],
+                    help="give the workload view-dependent colour of this "
+                         "degree (coefficients N(0, 0.05))")
     ap.add_argument("--no-per-view", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-threads", type=int, default=0)
@@ -247,6 +250,9 @@ def main():
         del src, dst
     log("bench: building workload", args.workload)
     w = workload(args.workload)
+    if args.sh_degree:
+        import synth
+        w.gaussians = synth.with_sh(w.gaussians, 0, args.sh_degree, 0.05)
     V = len(w.cameras)
     W, H = w.cameras[0].width, w.cameras[0].height
     N = w.gaussians.n
@@ -508,6 +514,18 @@ def main():
                                "mpix_per_s": Vo * Wo * Ho * 1e-3 / ms_o,
                                "launch": "eager",
                                "shape": f"{So.tile}/{So.lds_batch}/{So.block_threads}"}
+        # View-dependent colour of degree 3 (45 coefficient rows) on the
+        # headline workload and launch shape.
+        log("bench: degree-3 view-dependent colour")
+        import synth
+        wsh = workload(args.workload)
+        wsh.gaussians = synth.with_sh(wsh.gaussians, 0, 3, 0.05)
+        ms_sh = iteration_ms(wsh, S)
+        others[wsh.name + "-sh3"] = {
+            "ms_per_iteration": ms_sh, "iterations_per_s": 1000.0 / ms_sh,
+            "launch": "eager", "shape": f"{S.tile}/{S.lds_batch}/{S.block_threads}",
+            "degree0_eager_ms": ms_eager}
+        del wsh
         log("bench: insertion growth run")
         others["insertion-200kf-1200x680"] = insertion_stress(S)
 
@@ -549,7 +567,8 @@ def main():
                    "gaussians": N, "tile": S.tile, "lds_batch": S.lds_batch,
                    "block_threads": S.block_threads or (256 if S.tile == 32 else 64),
                    "launch": "hip_graph" if ms_graph is not None else "eager",
-                   "adam_in_step": True, "render_box": not S.full_box},
+                   "adam_in_step": True, "render_box": not S.full_box,
+                   "sh_degree": args.sh_degree},
         "mpix_per_s": V * W * H * iters / 1e6,
         "ms_per_step_eager": ms_eager,
         "keys_per_iter": int(n_keys),

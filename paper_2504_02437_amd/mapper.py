@@ -24,14 +24,16 @@ LR = (1.6e-4, 5e-3, 1e-3, 5e-2, 2.5e-3)   # mean, log_scale, quat, opacity, rgb
 class Mapper:
     def __init__(self, capacity, width, height, window=10, settings=None,
                  lr=LR, lam_color=1.0, lam_reg=1.0, reg_floor=0.01,
-                 alpha_skip=0.9, device="cuda"):
+                 alpha_skip=0.9, sh_degree=0, device="cuda"):
         self.capacity, self.W, self.H = capacity, width, height
         self.window = window
         self.settings = settings or R.Settings(tile=16)
         self.lr, self.lam_color, self.lam_reg = lr, lam_color, lam_reg
         self.reg_floor, self.alpha_skip = reg_floor, float(np.float32(alpha_skip))
         self.device = device
-        self.params = R.ParamBuffer(capacity, device, n=0)
+        # sh_degree > 0: view-dependent colour with (sh_degree + 1)^2 - 1
+        # coefficients per channel, zero for new Gaussians.
+        self.params = R.ParamBuffer(capacity, device, n=0, sh_degree=sh_degree)
         self.grad = self.params.zeros_like()
         self.m = self.params.zeros_like()
         self.v = self.params.zeros_like()

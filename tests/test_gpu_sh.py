@@ -271,3 +271,26 @@ def test_autograd_returns_coefficient_gradients():
     assert got.shape == (14 + 45, params.capacity)
     ref = oracle_backward(w, p64, proj, bins, dL)
     check_grads(got, ref, w.gaussians.n)
+
+
+def test_mapper_with_view_dependent_colour():
+    """The keyframe-window mapper with degree-1 colour: insertion starts the
+    coefficients at zero, the window iterations move them, and the window
+    PSNR improves as with view-independent colour."""
+    from paper_2504_02437_amd.mapper import Mapper, render_images
+    st = synth.mapping_stream(7, 3, 160, 120, 130.0, 20_000)
+    gt = synth.with_sh(st.gt, 7, 1, 0.2)
+    imgs = render_images(gt, st.cameras)
+    mp = Mapper(capacity=3 * 9 * 96, width=160, height=120, window=3,
+                sh_degree=1)
+    for i, cam in enumerate(st.cameras):
+        info = mp.add_keyframe(cam, imgs[i], st.pts[i])
+        new = mp.params.data[14:, info["n_before"]:info["n_after"]]
+        assert info["n_after"] > info["n_before"] and torch.all(new == 0)
+        mp.optimise(5)
+    p0 = mp.psnr()
+    mp.optimise(40)
+    p1 = mp.psnr()
+    n = mp.params.n()
+    assert torch.count_nonzero(mp.params.data[14:, :n]) > 0.9 * 9 * n
+    assert np.isfinite(p1) and p1 > p0
