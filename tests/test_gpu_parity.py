@@ -210,6 +210,45 @@ def test_long_tile_lists_use_the_global_sort_path():
     check_forward(rast, fwd, bins, max_flagged=0.05)
 
 
+def _one_tile_scene(n, seed, ties):
+    """n small opaque Gaussians whose boxes all lie inside the first 16x16
+    tile of a 32x32 image, so that tile's list has exactly n keys; with
+    `ties` the depths take only 7 values (many equal-depth keys)."""
+    rng = np.random.default_rng([77, n, seed])
+    cam = synth.identity_camera(30.0, 30.0, 32, 32)
+    z = rng.uniform(1.0, 3.0, n)
+    if ties:
+        z = 1.0 + 0.25 * rng.integers(0, 7, n)
+    u = rng.uniform(4.0, 11.0, n)
+    v = rng.uniform(4.0, 11.0, n)
+    mean = np.stack([(u - cam.cx) * z / cam.fx, (v - cam.cy) * z / cam.fy, z])
+    q = rng.normal(size=(4, n))
+    g = synth.Gaussians(mean.astype(np.float32),
+                        np.full((3, n), -6.0, np.float32),
+                        (q / np.linalg.norm(q, axis=0)).astype(np.float32),
+                        np.zeros(n, np.float32),
+                        rng.uniform(size=(3, n)).astype(np.float32))
+    return synth.Workload(f"onetile-{n}", g, [cam],
+                          np.zeros((1, 3, 32, 32), np.float32))
+
+
+@pytest.mark.parametrize("n", [1, 2, 63, 64, 65, 200, 512, 513, 1024, 1025,
+                               2048, 2049, 3000, 4096])
+def test_sort_every_segment_size_class(n):
+    """Segments of every size class of the in-register sort (one lane per
+    key up to 64, 2-16 keys per lane in one wave up to 1024, two and four
+    waves up to 4096), with distinct and with tied depths: keys, values and
+    ranges bit-exact."""
+    for ties in (False, True):
+        w = _one_tile_scene(n, 0, ties)
+        print("case sort segment", n, ties, flush=True)
+        p64, proj, bins, fwd = oracle_forward(w, 16)
+        r = bins["ranges"]
+        assert r[0, 1] - r[0, 0] == n and (r[1:, 1] == r[1:, 0]).all()
+        params, rast = gpu_forward(w, 16, 256)
+        check_sort(rast, bins)
+
+
 def _same_render(w, tile, batch, threads, n_check_grads=True, rtol=1e-4):
     params = R.ParamBuffer.from_gaussians(w.gaussians)
     _, full = gpu_forward(w, tile, batch, params=params, threads=threads,
