@@ -111,13 +111,15 @@ static int make_layout(const gs_geometry* g, Layout& L, int& tx, int& ty) {
   L.diff = take(V * (size_t)(ty + 1) * (tx + 1) * 4);
   L.ranges = take(tiles * 8);
   L.cursor = take(tiles * 4);
-  L.view_tot = take(V * 8);
+  const int ch = bin_chunk(tx * ty);
+  L.chunk_counts = take(ch ? V * ((cap + ch - 1) / ch) * (size_t)tx * ty * 4 : 0);
   L.keys_unsorted = take(kc * 8);
   L.vals_sorted = take(kc * 4);
   L.keys_sorted = take(kc * 8);
   L.grad2d = take(V * 5 * cap * 4);
   L.gop = take(cap * 4);
   L.gcol = take(V * 3 * cap * 4);
+  L.shape = take(cap * (6 * 8 + 4));
   L.counters = take(sizeof(Counters));
   L.total = off;
   return GS_OK;
@@ -185,13 +187,14 @@ int gs_workspace_create(const gs_geometry* geo, void* device_buffer,
   ws->diff = (int32_t*)(b + L.diff);
   ws->ranges = (uint32_t*)(b + L.ranges);
   ws->cursor = (uint32_t*)(b + L.cursor);
-  ws->view_tot = (long long*)(b + L.view_tot);
+  ws->chunk_counts = (uint32_t*)(b + L.chunk_counts);
   ws->keys_unsorted = (unsigned long long*)(b + L.keys_unsorted);
   ws->vals_sorted = (uint32_t*)(b + L.vals_sorted);
   ws->keys_sorted = (unsigned long long*)(b + L.keys_sorted);
   ws->grad2d = (float*)(b + L.grad2d);
   ws->gop = (float*)(b + L.gop);
   ws->gcol = (float*)(b + L.gcol);
+  ws->shape = (double*)(b + L.shape);
   ws->counters = (Counters*)(b + L.counters);
   hipStream_t st = (hipStream_t)stream;
   const size_t V = geo->n_views, cap = geo->capacity;

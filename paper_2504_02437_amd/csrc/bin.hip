@@ -1,20 +1,21 @@
 // Tile binning: per-tile key counts, ranges, and the scatter of the
-// (depth, index) keys into their tiles' segments.
+// (depth, index) keys into their tiles' segments, without global atomics.
 //
-// Counts come from the tile-coverage difference grid the projection kernel
-// fills (four corner increments per box of tiles): one workgroup per view
-// loads its grid into LDS and takes the 2D prefix sum, which is the number of
-// boxes covering each tile.  A second kernel turns the counts into every
-// tile's [start, end) range with one exclusive scan per view plus the totals
-// of the preceding views, so n_keys never leaves the device.
+// Each workgroup owns a chunk of Gaussians of one view (1024 or 2048) and
+// counts the chunk's keys per tile in LDS, walking the keys with wave-level
+// load balancing (one lane per key); the counts go to a [view][chunk][tile]
+// matrix.  A column scan over the chunks turns every entry into the chunk's
+// offset inside the tile's segment and gives the tile totals; one exclusive
+// scan per view (plus the totals of the preceding views) gives every tile's
+// [start, end) range, so n_keys never leaves the device.  The scatter then
+// walks the same keys again and claims positions with LDS atomics from
+// start + offset.  Each key is written as (depth bits << 32 | index), so the
+// per-tile sort needs no gather.
 //
-// The scatter gives each workgroup a chunk of Gaussians of one view.  It
-// walks the chunk's keys twice with wave-level load balancing (one lane per
-// key): first counting keys per tile in LDS, then - after reserving each
-// touched tile's share with a single global atomic - claiming positions with
-// LDS atomics.  Each key is written as (depth bits << 32 | index), so the
-// per-tile sort needs no gather.  Images whose tile grid does not fit in LDS
-// use a per-key global-atomic scatter.
+// Tile grids too large for LDS counters bin the old way: the projection adds
+// the four corners of each box of tiles into a coverage difference grid,
+// whose 2D prefix sum is the count of every tile, and the scatter takes one
+// global atomic per key.
 
 #include "gs_internal.h"
 
@@ -27,7 +28,6 @@ constexpr int kMaxGridCells = 16384;  // LDS difference grid (64 KB)
 struct CountArgs {
   int32_t* diff;        // [V][Ty + 1][Tx + 1], consumed and cleared
   uint32_t* counts;     // [V][Ty][Tx] key count per tile (the cursor array)
-  long long* view_tot;  // [V]
   int Tx, Ty;
 };
 
@@ -35,7 +35,6 @@ struct CountArgs {
 // grid.  Grids larger than kMaxGridCells are scanned in global memory.
 __global__ __launch_bounds__(kScanThreads) void k_tile_count(CountArgs a) {
   __shared__ int32_t grid[kMaxGridCells];
-  __shared__ long long part[kScanThreads / 64];
   const int k = blockIdx.x, tid = threadIdx.x;
   const int stride = a.Tx + 1, rows = a.Ty + 1;
   const int cells = stride * rows;
@@ -55,46 +54,52 @@ __global__ __launch_bounds__(kScanThreads) void k_tile_count(CountArgs a) {
     for (int y = 0; y < rows; ++y) { acc += G[y * stride + x]; G[y * stride + x] = acc; }
   }
   __syncthreads();
-  long long local = 0;
   const int tiles = a.Tx * a.Ty;
   uint32_t* c = a.counts + (size_t)k * tiles;
   for (int t = tid; t < tiles; t += kScanThreads) {
     const int ty = t / a.Tx, tx = t - ty * a.Tx;
-    const int v = G[ty * stride + tx];
-    c[t] = (uint32_t)v;
-    local += v;
-  }
-  for (int off = 32; off > 0; off >>= 1) local += __shfl_down(local, off, 64);
-  if ((tid & 63) == 0) part[tid >> 6] = local;
-  __syncthreads();
-  if (tid == 0) {
-    long long s = 0;
-    for (int i = 0; i < kScanThreads / 64; ++i) s += part[i];
-    a.view_tot[k] = s;
+    c[t] = (uint32_t)G[ty * stride + tx];
   }
   for (int i = tid; i < cells; i += kScanThreads) d[i] = 0;
 }
 
 struct RangeArgs {
-  uint32_t* counts;   // in: counts; out: cursors (= range starts)
+  uint32_t* counts;   // in: counts; out: range starts
   uint32_t* ranges;
-  const long long* view_tot;
   Counters* ctr;
   int V, Tx, Ty;
   long long key_cap;
 };
 
 // One workgroup per view: exclusive scan of the view's tile counts, offset by
-// the totals of the preceding views.
+// the totals of the preceding views (summed here from their counts).
 __global__ __launch_bounds__(kScanThreads) void k_tile_ranges(RangeArgs a) {
   __shared__ long long part[kScanThreads];
+  __shared__ long long red[2][kScanThreads / 64];
   const int k = blockIdx.x, tid = threadIdx.x;
-  long long base = 0, total = 0;
-  for (int i = 0; i < a.V; ++i) {
-    if (i < k) base += a.view_tot[i];
-    total += a.view_tot[i];
-  }
   const int tiles = a.Tx * a.Ty;
+  long long base = 0, total = 0;
+  for (long long i = tid; i < (long long)a.V * tiles; i += kScanThreads) {
+    const long long v = a.counts[i];
+    total += v;
+    if (i < (long long)k * tiles) base += v;
+  }
+  for (int off = 32; off > 0; off >>= 1) {
+    base += __shfl_down(base, off, 64);
+    total += __shfl_down(total, off, 64);
+  }
+  if ((tid & 63) == 0) {
+    red[0][tid >> 6] = base;
+    red[1][tid >> 6] = total;
+  }
+  __syncthreads();
+  base = 0;
+  total = 0;
+  for (int i = 0; i < kScanThreads / 64; ++i) {
+    base += red[0][i];
+    total += red[1][i];
+  }
+  __syncthreads();
   const int per = (tiles + kScanThreads - 1) / kScanThreads;
   const int t0 = tid * per, t1 = min(tiles, t0 + per);
   uint32_t* c = a.counts + (size_t)k * tiles;
@@ -129,7 +134,8 @@ struct ScatterArgs {
   const int32_t* tiles;
   const int32_t* n_dev;
   int cap, tile, Tx, Ty;
-  uint32_t* cursor;
+  uint32_t* cursor;              // range starts (per-key atomics: cursors)
+  uint32_t* chunk_counts;        // [V][chunks][tiles]
   unsigned long long* keys;
   long long key_cap;
 };
@@ -189,9 +195,10 @@ __device__ inline void wave_enumerate(WaveOwners& O, int lane, int cnt, int x0,
   __syncthreads();
 }
 
-// LDS-privatised scatter: GPT Gaussians per thread, one view per block.
+// Keys of one chunk (GPT Gaussians per thread, one view per block) per tile,
+// counted in LDS, to row [view][chunk] of the chunk-count matrix.
 template <int MAXBINS, int GPT>
-__global__ __launch_bounds__(256) void k_scatter_lds(ScatterArgs a) {
+__global__ __launch_bounds__(256) void k_chunk_count(ScatterArgs a) {
   __shared__ uint32_t bins[MAXBINS];
   __shared__ WaveOwners owners[4];
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
@@ -209,12 +216,58 @@ __global__ __launch_bounds__(256) void k_scatter_lds(ScatterArgs a) {
                    [&](int t, uint32_t, uint32_t) { atomicAdd(&bins[t], 1u); });
   }
   __syncthreads();
-  uint32_t* cur = a.cursor + (size_t)k * nb;
-  for (int i = tid; i < nb; i += 256) {
-    const uint32_t c = bins[i];
-    if (c) bins[i] = atomicAdd(&cur[i], c);
-  }
+  uint32_t* C = a.chunk_counts + ((size_t)k * gridDim.x + blockIdx.x) * nb;
+  for (int i = tid; i < nb; i += 256) C[i] = bins[i];
+}
+
+struct ChunkScanArgs {
+  uint32_t* chunk_counts;   // in: counts; out: offsets inside the tile
+  uint32_t* counts;         // out: [V][tiles] tile totals
+  int tiles, chunks;
+};
+
+// Column scan of the chunk-count matrix: 64 tiles per workgroup, the chunks
+// split in 16 segments (one wave each), one view per grid row.
+__global__ __launch_bounds__(1024) void k_chunk_scan(ChunkScanArgs a) {
+  __shared__ uint32_t part[16][64];
+  const int tl = threadIdx.x & 63, seg = threadIdx.x >> 6;
+  const int k = blockIdx.y;
+  const int t = blockIdx.x * 64 + tl;
+  const int nb = a.tiles, nch = a.chunks;
+  const int sl = (nch + 15) / 16;
+  const int c0 = min(nch, seg * sl), c1 = min(nch, c0 + sl);
+  uint32_t* C = a.chunk_counts + (size_t)k * nch * nb;
+  uint32_t sum = 0;
+  if (t < nb)
+    for (int c = c0; c < c1; ++c) sum += C[(size_t)c * nb + t];
+  part[seg][tl] = sum;
   __syncthreads();
+  uint32_t run = 0;
+  for (int s2 = 0; s2 < seg; ++s2) run += part[s2][tl];
+  if (t >= nb) return;
+  if (seg == 15) a.counts[(size_t)k * nb + t] = run + sum;
+  for (int c = c0; c < c1; ++c) {
+    const size_t i = (size_t)c * nb + t;
+    const uint32_t v = C[i];
+    C[i] = run;
+    run += v;
+  }
+}
+
+// The scatter: the chunk's keys claim positions start + offset + (LDS
+// counter) in their tiles' segments.
+template <int MAXBINS, int GPT>
+__global__ __launch_bounds__(256) void k_scatter_chunks(ScatterArgs a) {
+  __shared__ uint32_t bins[MAXBINS];
+  __shared__ WaveOwners owners[4];
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  const int k = blockIdx.y;
+  const int nb = a.Tx * a.Ty;
+  const uint32_t* C = a.chunk_counts + ((size_t)k * gridDim.x + blockIdx.x) * nb;
+  const uint32_t* start = a.cursor + (size_t)k * nb;
+  for (int i = tid; i < nb; i += 256) bins[i] = start[i] + C[i];
+  __syncthreads();
+  const int g0 = blockIdx.x * 256 * GPT;
   for (int sub = 0; sub < GPT; ++sub) {
     const int g = g0 + sub * 256 + tid;
     int cnt, x0, y0, w;
@@ -248,41 +301,57 @@ __global__ __launch_bounds__(256) void k_scatter_global(ScatterArgs a) {
 }
 
 template <int MAXBINS, int GPT>
-void launch_lds(const ScatterArgs& c, int V, hipStream_t st) {
-  const int bx = (c.cap + 256 * GPT - 1) / (256 * GPT);
-  hipLaunchKernelGGL((k_scatter_lds<MAXBINS, GPT>), dim3(bx, V), dim3(256), 0,
+hipError_t launch_chunked(const ScatterArgs& c, const RangeArgs& ra,
+                          uint32_t* counts, int V, hipStream_t st) {
+  const int nch = (c.cap + 256 * GPT - 1) / (256 * GPT);
+  const int nb = c.Tx * c.Ty;
+  hipLaunchKernelGGL((k_chunk_count<MAXBINS, GPT>), dim3(nch, V), dim3(256), 0,
                      st, c);
+  ChunkScanArgs sa;
+  sa.chunk_counts = c.chunk_counts; sa.counts = counts;
+  sa.tiles = nb; sa.chunks = nch;
+  hipLaunchKernelGGL(k_chunk_scan, dim3((nb + 63) / 64, V), dim3(1024), 0, st,
+                     sa);
+  hipLaunchKernelGGL(k_tile_ranges, dim3(V), dim3(kScanThreads), 0, st, ra);
+  hipLaunchKernelGGL((k_scatter_chunks<MAXBINS, GPT>), dim3(nch, V),
+                     dim3(256), 0, st, c);
+  return hipGetLastError();
 }
 
 }  // namespace
 
 hipError_t launch_bin(gs_workspace* ws, const gs_params* p, hipStream_t st) {
   const int V = ws->geo.n_views;
-  CountArgs ca;
-  ca.diff = ws->diff; ca.counts = ws->cursor; ca.view_tot = ws->view_tot;
-  ca.Tx = ws->tiles_x; ca.Ty = ws->tiles_y;
-  hipLaunchKernelGGL(k_tile_count, dim3(V), dim3(kScanThreads), 0, st, ca);
-  hipError_t e = hipGetLastError();
-  if (e != hipSuccess) return e;
+  const int nb = ws->tiles_x * ws->tiles_y;
   RangeArgs ra;
-  ra.counts = ws->cursor; ra.ranges = ws->ranges; ra.view_tot = ws->view_tot;
+  ra.counts = ws->cursor; ra.ranges = ws->ranges;
   ra.ctr = ws->counters; ra.V = V; ra.Tx = ws->tiles_x; ra.Ty = ws->tiles_y;
   ra.key_cap = ws->geo.key_capacity;
-  hipLaunchKernelGGL(k_tile_ranges, dim3(V), dim3(kScanThreads), 0, st, ra);
-  e = hipGetLastError();
-  if (e != hipSuccess) return e;
-  if (p->capacity <= 0) return hipSuccess;
   ScatterArgs c;
   c.rec = ws->records; c.rbox = ws->rbox; c.tiles = ws->tiles_touched;
   c.n_dev = p->n_dev;
   c.cap = p->capacity; c.tile = ws->geo.tile; c.Tx = ws->tiles_x;
-  c.Ty = ws->tiles_y; c.cursor = ws->cursor; c.keys = ws->keys_unsorted;
+  c.Ty = ws->tiles_y; c.cursor = ws->cursor; c.chunk_counts = ws->chunk_counts;
+  c.keys = ws->keys_unsorted;
   c.key_cap = ws->geo.key_capacity;
-  const int nb = ws->tiles_x * ws->tiles_y;
-  if (nb <= 1024) launch_lds<1024, 4>(c, V, st);
-  else if (nb <= 4096) launch_lds<4096, 8>(c, V, st);
-  else if (nb <= 16384) launch_lds<16384, 8>(c, V, st);
-  else
+  const int ch = bin_chunk(nb);
+  if (ch && p->capacity <= 0) {
+    // No Gaussians: every range is empty.
+    hipError_t e = launch_fill_u32(ws->cursor, 0u, (size_t)V * nb, st);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_tile_ranges, dim3(V), dim3(kScanThreads), 0, st, ra);
+    return hipGetLastError();
+  }
+  if (ch == 1024) return launch_chunked<1024, 4>(c, ra, ws->cursor, V, st);
+  if (ch == 2048 && nb <= 4096)
+    return launch_chunked<4096, 8>(c, ra, ws->cursor, V, st);
+  if (ch == 2048) return launch_chunked<16384, 8>(c, ra, ws->cursor, V, st);
+  CountArgs ca;
+  ca.diff = ws->diff; ca.counts = ws->cursor;
+  ca.Tx = ws->tiles_x; ca.Ty = ws->tiles_y;
+  hipLaunchKernelGGL(k_tile_count, dim3(V), dim3(kScanThreads), 0, st, ca);
+  hipLaunchKernelGGL(k_tile_ranges, dim3(V), dim3(kScanThreads), 0, st, ra);
+  if (p->capacity > 0)
     hipLaunchKernelGGL(k_scatter_global, dim3((c.cap + 255) / 256, V),
                        dim3(256), 0, st, c);
   return hipGetLastError();

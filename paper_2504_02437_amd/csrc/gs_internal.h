@@ -18,9 +18,18 @@ struct __align__(16) Record {
 
 // Workspace layout: every region is carved from the caller's device buffer.
 struct Layout {
-  size_t records, tiles_touched, rbox, diff, ranges, cursor, view_tot, keys_unsorted,
-      vals_sorted, keys_sorted, grad2d, gop, gcol, counters, total;
+  size_t records, tiles_touched, rbox, diff, ranges, cursor, chunk_counts,
+      keys_unsorted, vals_sorted, keys_sorted, grad2d, gop, gcol, shape,
+      counters, total;
 };
+
+// Binning works on chunks of Gaussians of one view (one workgroup each) with
+// the view's tile counters in LDS: 1024 Gaussians per chunk for grids of up
+// to 1024 tiles, 2048 up to 16384 tiles; 0 for larger grids, which bin with
+// a coverage difference grid and per-key global atomics instead.
+inline int bin_chunk(int tiles) {
+  return tiles <= 1024 ? 1024 : tiles <= 16384 ? 2048 : 0;
+}
 
 // Device-side counters block.
 struct Counters {
@@ -60,9 +69,11 @@ struct gs_workspace {
   int2* rbox;            // [V][capacity] render boxes (packed 16-bit pairs)
   float box_alpha_min;   // alpha_min the render boxes were formed for
   int32_t* diff;         // [V][Ty + 1][Tx + 1] tile-coverage difference grid
+                         // (grids too large for the chunked binning)
   uint32_t* ranges;      // [V * Ty * Tx][2]
-  uint32_t* cursor;      // [V * Ty * Tx] tile counts, then scatter cursors
-  long long* view_tot;   // [V] keys per view
+  uint32_t* cursor;      // [V * Ty * Tx] tile counts, then range starts
+  uint32_t* chunk_counts;  // [V][chunks][Ty * Tx] keys of each chunk per
+                           // tile, then each chunk's offset in the tile
   unsigned long long* keys_unsorted;  // [key_capacity] depth bits << 32 | g
   uint32_t* vals_sorted;
   unsigned long long* keys_sorted;
@@ -70,6 +81,8 @@ struct gs_workspace {
   float* gop;            // [capacity] dL/d opacity summed over views
   float* gcol;           // [V][3][capacity] dL/d colour per view (used with
                          // view-dependent colour)
+  double* shape;         // [6][capacity] 3D covariance (upper triangle) of
+                         // the last projection, then float opacity [capacity]
   gs::Counters* counters;
 };
 

@@ -5,9 +5,16 @@
 // published FP32 record and the integer pixel box are reproducible bit for
 // bit by any FP64 implementation that follows the same order.
 //
-// Layout: one thread per Gaussian, looping over the views, so the 56 bytes of
-// parameters are read from HBM once per call (coalesced planar rows) and the
-// view-independent part (scale, rotation, 3D covariance) is formed once.
+// Layout: the view-independent part (scale, rotation, 3D covariance,
+// opacity) is formed once per Gaussian by k_shape and kept in the workspace
+// (52 bytes per Gaussian); k_project then runs one thread per (view,
+// Gaussian), ten times the parallelism of a per-Gaussian loop over the
+// views, which the long FP64 division and square-root chains need to hide
+// their latency.  Its blocks are ordered so that the views of one chunk of
+// Gaussians run on the same XCD (blocks are dealt to the eight XCDs round
+// robin), where the chunk's parameters stay in that XCD's L2.  The backward
+// keeps one thread per Gaussian looping over the views: it accumulates the
+// shape gradient over them.
 
 #include <math.h>
 
@@ -25,6 +32,9 @@ struct ProjArgs {
   const float* rgb;
   const int32_t* n_dev;
   int cap;
+  double* sig;    // [6][cap] Sigma upper triangle; sig[0] = NaN: bad shape
+  float* op;      // [cap] opacity
+  int chunks;     // ceil(cap / 256)
   const gs_camera* cams;
   int V, W, H, tile, Tx, Ty;
   Record* rec;
@@ -33,6 +43,7 @@ struct ProjArgs {
   int2* rbox;
   float amin;     // alpha_min the render boxes are formed for
   int full_box;   // 1: render boxes equal the boxes
+  int diff_atomics;   // 1: fill the coverage difference grid (large grids)
 };
 
 constexpr int kEmptyPair = 0xffff;   // u_lo = 0xffff, u_hi = 0
@@ -232,17 +243,47 @@ __device__ inline void make_view_grad(const gs_camera& cam, double mx,
   P.C = P.a * idet;
 }
 
-__global__ __launch_bounds__(256) void k_project(ProjArgs a) {
+// Upper-triangle entries of the symmetric 3x3 covariance.
+constexpr int kSigIdx[6] = {0, 1, 2, 4, 5, 8};
+
+__global__ __launch_bounds__(256) void k_shape(ProjArgs a) {
   const int g = blockIdx.x * 256 + threadIdx.x;
   const int n = min(*a.n_dev, a.cap);
   if (g >= n) return;
   const int cap = a.cap;
   Shape S;
   make_shape(a.lsc, a.quat, cap, g, S);
+  for (int j = 0; j < 6; ++j) a.sig[(size_t)j * cap + g] = S.Sig[kSigIdx[j]];
+  // A failed shape (zero or non-finite quaternion, non-finite scale) is
+  // culled in every view; a valid one has a finite, non-negative Sigma_00.
+  if (!S.ok) a.sig[g] = NAN;
+  a.op[g] = (float)(1.0 / (1.0 + exp(-(double)a.opl[g])));
+}
+
+__global__ __launch_bounds__(256) void k_project(ProjArgs a) {
+  // Block b runs on XCD b % 8: chunk c of 256 Gaussians and view k with
+  // b = ((c / 8) V + k) 8 + c % 8 keep every view of a chunk on one XCD.
+  const int b = blockIdx.x;
+  const int rest = b >> 3;
+  const int k = rest % a.V;
+  const int c = (rest / a.V) * 8 + (b & 7);
+  if (c >= a.chunks) return;
+  const int g = c * 256 + threadIdx.x;
+  const int n = min(*a.n_dev, a.cap);
+  if (g >= n) return;
+  const int cap = a.cap;
+  Shape S;
+  for (int j = 0; j < 6; ++j) {
+    const double v = a.sig[(size_t)j * cap + g];
+    const int i = kSigIdx[j], r = i / 3, q = i % 3;
+    S.Sig[3 * r + q] = v;
+    S.Sig[3 * q + r] = v;
+  }
+  S.ok = !isnan(S.Sig[0]);
   const double mx = a.mean[g], my = a.mean[cap + g], mz = a.mean[2 * cap + g];
-  const double op = 1.0 / (1.0 + exp(-(double)a.opl[g]));
+  const float op = a.op[g];
   const float r = a.rgb[g], gg = a.rgb[cap + g], bb = a.rgb[2 * cap + g];
-  for (int k = 0; k < a.V; ++k) {
+  {
     const size_t slot = (size_t)k * cap + g;
     View P;
     make_view(a.cams[k], mx, my, mz, S, P);
@@ -263,12 +304,12 @@ __global__ __launch_bounds__(256) void k_project(ProjArgs a) {
     }
     if (!ok) {
       a.tiles[slot] = 0;
-      continue;
+      return;
     }
     const int iu0 = (int)ulo, iu1 = (int)uhi, iv0 = (int)vlo, iv1 = (int)vhi;
     Record R;
     R.q0 = make_float4((float)P.px, (float)P.py, (float)P.A, (float)P.B);
-    R.q1 = make_float4((float)P.C, (float)op, r, gg);
+    R.q1 = make_float4((float)P.C, op, r, gg);
     R.q2 = make_float4(bb, (float)P.t[2],
                        __int_as_float(iu0 | (iu1 << 16)),
                        __int_as_float(iv0 | (iv1 << 16)));
@@ -278,12 +319,13 @@ __global__ __launch_bounds__(256) void k_project(ProjArgs a) {
     a.rbox[slot] = make_int2(ru0 | (ru1 << 16), rv0 | (rv1 << 16));
     if (ru0 > ru1) {   // empty render box: nothing to bin
       a.tiles[slot] = 0;
-      continue;
+      return;
     }
     // The Gaussian is binned into the tiles its render box touches.
     const int tx0 = ru0 / a.tile, tx1 = ru1 / a.tile;
     const int ty0 = rv0 / a.tile, ty1 = rv1 / a.tile;
     a.tiles[slot] = (tx1 - tx0 + 1) * (ty1 - ty0 + 1);
+    if (!a.diff_atomics) return;
     // Tile-coverage difference grid: +1/-1 at the four corners of the box of
     // tiles; a 2D prefix sum then yields the key count of every tile.
     int32_t* d = a.diff + (size_t)k * (a.Ty + 1) * (a.Tx + 1);
@@ -450,8 +492,15 @@ hipError_t launch_project(gs_workspace* ws, const gs_params* p,
   a.rec = ws->records; a.tiles = ws->tiles_touched; a.diff = ws->diff;
   a.rbox = ws->rbox; a.amin = s->alpha_min;
   a.full_box = (s->flags & GS_FLAG_FULL_BOX) ? 1 : 0;
-  const int blocks = (p->capacity + 255) / 256;
-  if (blocks > 0) hipLaunchKernelGGL(k_project, dim3(blocks), dim3(256), 0, st, a);
+  a.diff_atomics = bin_chunk(ws->tiles_x * ws->tiles_y) == 0;
+  a.sig = ws->shape;
+  a.op = (float*)(ws->shape + 6 * (size_t)p->capacity);
+  a.chunks = (p->capacity + 255) / 256;
+  if (a.chunks <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_shape, dim3(a.chunks), dim3(256), 0, st, a);
+  const long long blocks = (long long)((a.chunks + 7) / 8) * 8 * a.V;
+  if (blocks > 0x7fffffff) return hipErrorInvalidConfiguration;
+  hipLaunchKernelGGL(k_project, dim3((unsigned)blocks), dim3(256), 0, st, a);
   return hipGetLastError();
 }
 
