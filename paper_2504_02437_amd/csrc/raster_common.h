@@ -91,6 +91,15 @@ __device__ inline int wave_mask(const Record& R, const int4& rb, int tu0,
   return m;
 }
 
+// A float the compiler keeps in a register: a plain copy it cannot see
+// through, so it does not re-derive the value (an int-to-float conversion
+// per use) inside the compositing loops.
+__device__ __forceinline__ float pinned(float x) {
+  float y;
+  asm("v_mov_b32 %0, %1" : "=v"(y) : "v"(x));
+  return y;
+}
+
 // Column part of the exponent for one (entry, thread): dx and the terms that
 // depend on dx only.
 struct Column {

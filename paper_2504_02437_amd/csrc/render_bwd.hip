@@ -124,7 +124,7 @@ __global__ __launch_bounds__(NT) void k_render_bwd(BwdArgs a) {
   for (int p = 0; p < PPT; ++p) {
     const int v = v0 + p;
     last[p] = 0;
-    vf[p] = (float)v;
+    vf[p] = pinned((float)v);
     T[p] = 1.f; g0[p] = g1[p] = g2[p] = 0.f; Tb[p] = 0.f; Sg[p] = 0.f;
     if (u < r.W && v < r.H) {
       const size_t pix = (size_t)v * r.W + u;

@@ -32,10 +32,13 @@ struct FwdArgs {
 // A pixel's transmittance is kept with its sign as the liveness flag: a
 // pixel that stopped holds -T, so "still compositing" is one compare and the
 // output is |T|.  T >= T_min > 0 holds for every accepted step, so a live
-// pixel's T is never zero.  The per-pixel work is predicated rather than
-// branched: every lane evaluates alpha for each of its pixels and the
-// decisions select what is accumulated.  A wave skips an entry outright when
-// no pixel of its footprint can admit it (wave_mask).
+// pixel's T is never zero, and a stopped pixel needs no test of its own: its
+// candidate T (1 - alpha) is negative, below T_min, so it never contributes,
+// and stopping it again (T = -|T|) leaves it as it is.  The per-pixel work is
+// predicated rather than branched: every lane evaluates alpha for each of
+// its pixels and the decisions select what is accumulated.  A wave skips an
+// entry outright when no pixel of its footprint can admit it (wave_mask).
+// The candidate transmittance is formed as fma(-alpha, T, T), one rounding.
 enum { kRender = 0, kCount = 1, kDominant = 2 };
 
 template <int TILE, int BATCH, int NT, int MODE>
@@ -78,7 +81,7 @@ __global__ __launch_bounds__(NT) void k_render_fwd(FwdArgs a) {
     T[p] = (u < r.W && v0 + p < r.H) ? 1.f : -1.f;
     C0[p] = C1[p] = C2[p] = 0.f;
     last[p] = 0;
-    vf[p] = (float)(v0 + p);
+    vf[p] = pinned((float)(v0 + p));
     ib[p] = ib_last[p] = 0;
   }
   const Record* rv = r.rec + (size_t)k * r.cap;
@@ -136,16 +139,15 @@ __global__ __launch_bounds__(NT) void k_render_fwd(FwdArgs a) {
         const float e2 = exponent2(col, ea.y, eb.x, vf[p], dy);
         const float G = __builtin_amdgcn_exp2f(e2);
         const float al = fminf(amax, eb.y * G);
-        const bool ok = in_u && lo <= p && p <= hi && T[p] > 0.f &&
-                        !(e2 > 0.f) && al >= amin;
-        const float Tn = T[p] * (1.f - al);
+        const bool ok = in_u && lo <= p && p <= hi && !(e2 > 0.f) &&
+                        al >= amin;
+        const float Tn = fmaf(-al, T[p], T[p]);
         const bool con = ok && Tn >= tmin;
-        const bool stop = ok && !(Tn >= tmin);
         const float w = con ? al * T[p] : 0.f;
         C0[p] = fmaf(eb.z, w, C0[p]);
         C1[p] = fmaf(eb.w, w, C1[p]);
         C2[p] = fmaf(ecb, w, C2[p]);
-        T[p] = con ? Tn : (stop ? -T[p] : T[p]);
+        T[p] = con ? Tn : (ok ? -fabsf(T[p]) : T[p]);
         last[p] = con ? idx : last[p];
         if (DOM) {
           const bool better = con && w > wbest[p];
