@@ -111,7 +111,7 @@ static int make_layout(const gs_geometry* g, Layout& L, int& tx, int& ty) {
   L.diff = take(V * (size_t)(ty + 1) * (tx + 1) * 4);
   L.ranges = take(tiles * 8);
   L.cursor = take(tiles * 4);
-  const int ch = bin_chunk(tx * ty);
+  const int ch = bin_chunk(tx, ty);
   L.chunk_counts = take(ch ? V * ((cap + ch - 1) / ch) * (size_t)tx * ty * 4 : 0);
   L.keys_unsorted = take(kc * 8);
   L.vals_sorted = take(kc * 4);

@@ -196,28 +196,50 @@ __device__ inline void wave_enumerate(WaveOwners& O, int lane, int cnt, int x0,
 }
 
 // Keys of one chunk (GPT Gaussians per thread, one view per block) per tile,
-// counted in LDS, to row [view][chunk] of the chunk-count matrix.
+// to row [view][chunk] of the chunk-count matrix: each Gaussian adds the
+// four corners of its box of tiles into an LDS coverage difference grid,
+// whose 2D prefix sum (rows, then columns) is the count of every tile.
 template <int MAXBINS, int GPT>
 __global__ __launch_bounds__(256) void k_chunk_count(ScatterArgs a) {
-  __shared__ uint32_t bins[MAXBINS];
-  __shared__ WaveOwners owners[4];
-  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  constexpr int kCells = MAXBINS + kGridSlack;
+  __shared__ int grid[kCells];
+  const int tid = threadIdx.x;
   const int k = blockIdx.y;
   const int nb = a.Tx * a.Ty;
-  for (int i = tid; i < nb; i += 256) bins[i] = 0;
+  const int stride = a.Tx + 1, cells = stride * (a.Ty + 1);
+  for (int i = tid; i < cells; i += 256) grid[i] = 0;
   __syncthreads();
   const int g0 = blockIdx.x * 256 * GPT;
+  const int n = min(*a.n_dev, a.cap);
   for (int sub = 0; sub < GPT; ++sub) {
     const int g = g0 + sub * 256 + tid;
-    int cnt, x0, y0, w;
-    uint32_t d;
-    load_owner(a, k, g, cnt, x0, y0, w, d);
-    wave_enumerate(owners[wv], lane, cnt, x0, y0, w, (uint32_t)g, d, a.Tx,
-                   [&](int t, uint32_t, uint32_t) { atomicAdd(&bins[t], 1u); });
+    if (g >= n) continue;
+    const size_t slot = (size_t)k * a.cap + g;
+    if (a.tiles[slot] <= 0) continue;
+    const int2 rb = a.rbox[slot];
+    const int tx0 = (rb.x & 0xffff) / a.tile, tx1 = (rb.x >> 16) / a.tile;
+    const int ty0 = (rb.y & 0xffff) / a.tile, ty1 = (rb.y >> 16) / a.tile;
+    atomicAdd(&grid[ty0 * stride + tx0], 1);
+    atomicAdd(&grid[ty0 * stride + tx1 + 1], -1);
+    atomicAdd(&grid[(ty1 + 1) * stride + tx0], -1);
+    atomicAdd(&grid[(ty1 + 1) * stride + tx1 + 1], 1);
+  }
+  __syncthreads();
+  for (int y = tid; y < a.Ty; y += 256) {
+    int acc = 0;
+    for (int x = 0; x < a.Tx; ++x) { acc += grid[y * stride + x]; grid[y * stride + x] = acc; }
+  }
+  __syncthreads();
+  for (int x = tid; x < a.Tx; x += 256) {
+    int acc = 0;
+    for (int y = 0; y < a.Ty; ++y) { acc += grid[y * stride + x]; grid[y * stride + x] = acc; }
   }
   __syncthreads();
   uint32_t* C = a.chunk_counts + ((size_t)k * gridDim.x + blockIdx.x) * nb;
-  for (int i = tid; i < nb; i += 256) C[i] = bins[i];
+  for (int i = tid; i < nb; i += 256) {
+    const int ty = i / a.Tx, tx = i - ty * a.Tx;
+    C[i] = (uint32_t)grid[ty * stride + tx];
+  }
 }
 
 struct ChunkScanArgs {
@@ -334,7 +356,8 @@ hipError_t launch_bin(gs_workspace* ws, const gs_params* p, hipStream_t st) {
   c.Ty = ws->tiles_y; c.cursor = ws->cursor; c.chunk_counts = ws->chunk_counts;
   c.keys = ws->keys_unsorted;
   c.key_cap = ws->geo.key_capacity;
-  const int ch = bin_chunk(nb);
+  const int ch = bin_chunk(ws->tiles_x, ws->tiles_y);
+  const int cells = (ws->tiles_x + 1) * (ws->tiles_y + 1);
   if (ch && p->capacity <= 0) {
     // No Gaussians: every range is empty.
     hipError_t e = launch_fill_u32(ws->cursor, 0u, (size_t)V * nb, st);
@@ -343,7 +366,7 @@ hipError_t launch_bin(gs_workspace* ws, const gs_params* p, hipStream_t st) {
     return hipGetLastError();
   }
   if (ch == 1024) return launch_chunked<1024, 4>(c, ra, ws->cursor, V, st);
-  if (ch == 2048 && nb <= 4096)
+  if (ch == 2048 && nb <= 4096 && cells <= 4096 + kGridSlack)
     return launch_chunked<4096, 8>(c, ra, ws->cursor, V, st);
   if (ch == 2048) return launch_chunked<16384, 8>(c, ra, ws->cursor, V, st);
   CountArgs ca;

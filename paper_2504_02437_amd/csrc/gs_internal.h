@@ -24,11 +24,16 @@ struct Layout {
 };
 
 // Binning works on chunks of Gaussians of one view (one workgroup each) with
-// the view's tile counters in LDS: 1024 Gaussians per chunk for grids of up
-// to 1024 tiles, 2048 up to 16384 tiles; 0 for larger grids, which bin with
-// a coverage difference grid and per-key global atomics instead.
-inline int bin_chunk(int tiles) {
-  return tiles <= 1024 ? 1024 : tiles <= 16384 ? 2048 : 0;
+// the view's tile counters and coverage difference grid in LDS: 1024
+// Gaussians per chunk for grids of up to 1024 tiles, 2048 up to 16384 tiles
+// (difference grids of up to that many cells + 257); 0 for larger grids,
+// which bin with a global difference grid and per-key global atomics.
+constexpr int kGridSlack = 257;
+inline int bin_chunk(int tx, int ty) {
+  const long long nb = (long long)tx * ty, cells = (long long)(tx + 1) * (ty + 1);
+  if (nb <= 1024 && cells <= 1024 + kGridSlack) return 1024;
+  if (nb <= 16384 && cells <= 16384 + kGridSlack) return 2048;
+  return 0;
 }
 
 // Device-side counters block.

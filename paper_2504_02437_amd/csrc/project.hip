@@ -492,7 +492,7 @@ hipError_t launch_project(gs_workspace* ws, const gs_params* p,
   a.rec = ws->records; a.tiles = ws->tiles_touched; a.diff = ws->diff;
   a.rbox = ws->rbox; a.amin = s->alpha_min;
   a.full_box = (s->flags & GS_FLAG_FULL_BOX) ? 1 : 0;
-  a.diff_atomics = bin_chunk(ws->tiles_x * ws->tiles_y) == 0;
+  a.diff_atomics = bin_chunk(ws->tiles_x, ws->tiles_y) == 0;
   a.sig = ws->shape;
   a.op = (float*)(ws->shape + 6 * (size_t)p->capacity);
   a.chunks = (p->capacity + 255) / 256;

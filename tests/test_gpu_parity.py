@@ -249,6 +249,23 @@ def test_sort_every_segment_size_class(n):
         check_sort(rast, bins)
 
 
+@pytest.mark.parametrize("W,H,tile", [(800, 8, 8), (480, 384, 8),
+                                      (640, 480, 8), (1104, 1000, 8)])
+def test_binning_paths(W, H, tile):
+    """Every binning path: chunked with up to 1024 tiles (here a one-row
+    strip of 100 tiles), up to 4096, up to 16384 and the per-key global
+    fallback beyond (138 x 125 tiles): records, keys, ranges and image."""
+    w = synth.tiny_scene(81, n=3000, width=W, height=H, f=0.8 * W,
+                         log_scale_mu=-2.5)
+    print("case binning", W, H, tile, flush=True)
+    p64, proj, bins, fwd = oracle_forward(w, tile)
+    params, rast = gpu_forward(w, tile, 256,
+                               key_capacity=max(1 << 20, 2 * len(bins["vals"])))
+    check_records(rast, proj)
+    check_sort(rast, bins)
+    check_forward(rast, fwd, bins)
+
+
 def _same_render(w, tile, batch, threads, n_check_grads=True, rtol=1e-4):
     params = R.ParamBuffer.from_gaussians(w.gaussians)
     _, full = gpu_forward(w, tile, batch, params=params, threads=threads,
