@@ -108,6 +108,7 @@ static int make_layout(const gs_geometry* g, Layout& L, int& tx, int& ty) {
   L.records = take(V * cap * sizeof(Record));
   L.tiles_touched = take(V * cap * 4);
   L.rbox = take(V * cap * 8);
+  L.depth = take(V * cap * 4);
   L.diff = take(V * (size_t)(ty + 1) * (tx + 1) * 4);
   L.ranges = take(tiles * 8);
   L.cursor = take(tiles * 4);
@@ -183,6 +184,7 @@ int gs_workspace_create(const gs_geometry* geo, void* device_buffer,
   ws->records = (Record*)(b + L.records);
   ws->tiles_touched = (int32_t*)(b + L.tiles_touched);
   ws->rbox = (int2*)(b + L.rbox);
+  ws->depth = (float*)(b + L.depth);
   ws->box_alpha_min = 0.f;
   ws->diff = (int32_t*)(b + L.diff);
   ws->ranges = (uint32_t*)(b + L.ranges);

@@ -129,7 +129,7 @@ __global__ __launch_bounds__(kScanThreads) void k_tile_ranges(RangeArgs a) {
 }
 
 struct ScatterArgs {
-  const Record* rec;
+  const float* depth;
   const int2* rbox;
   const int32_t* tiles;
   const int32_t* n_dev;
@@ -161,7 +161,7 @@ __device__ inline void load_owner(const ScatterArgs& a, int k, int g, int& cnt,
   x0 = (rb.x & 0xffff) / a.tile;
   w = (rb.x >> 16) / a.tile - x0 + 1;
   y0 = (rb.y & 0xffff) / a.tile;
-  dbits = __float_as_uint(a.rec[slot].q2.y);
+  dbits = __float_as_uint(a.depth[slot]);
 }
 
 template <typename F>
@@ -350,7 +350,7 @@ hipError_t launch_bin(gs_workspace* ws, const gs_params* p, hipStream_t st) {
   ra.ctr = ws->counters; ra.V = V; ra.Tx = ws->tiles_x; ra.Ty = ws->tiles_y;
   ra.key_cap = ws->geo.key_capacity;
   ScatterArgs c;
-  c.rec = ws->records; c.rbox = ws->rbox; c.tiles = ws->tiles_touched;
+  c.depth = ws->depth; c.rbox = ws->rbox; c.tiles = ws->tiles_touched;
   c.n_dev = p->n_dev;
   c.cap = p->capacity; c.tile = ws->geo.tile; c.Tx = ws->tiles_x;
   c.Ty = ws->tiles_y; c.cursor = ws->cursor; c.chunk_counts = ws->chunk_counts;

@@ -18,7 +18,7 @@ struct __align__(16) Record {
 
 // Workspace layout: every region is carved from the caller's device buffer.
 struct Layout {
-  size_t records, tiles_touched, rbox, diff, ranges, cursor, chunk_counts,
+  size_t records, tiles_touched, rbox, depth, diff, ranges, cursor, chunk_counts,
       keys_unsorted, vals_sorted, keys_sorted, grad2d, gop, gcol, shape,
       counters, total;
 };
@@ -72,6 +72,8 @@ struct gs_workspace {
   gs::Record* records;
   int32_t* tiles_touched;
   int2* rbox;            // [V][capacity] render boxes (packed 16-bit pairs)
+  float* depth;          // [V][capacity] camera-space depth (the key's upper
+                         // half), beside the records for coalesced reads
   float box_alpha_min;   // alpha_min the render boxes were formed for
   int32_t* diff;         // [V][Ty + 1][Tx + 1] tile-coverage difference grid
                          // (grids too large for the chunked binning)

@@ -41,6 +41,7 @@ struct ProjArgs {
   int32_t* tiles;
   int32_t* diff;
   int2* rbox;
+  float* depth;
   float amin;     // alpha_min the render boxes are formed for
   int full_box;   // 1: render boxes equal the boxes
   int diff_atomics;   // 1: fill the coverage difference grid (large grids)
@@ -314,6 +315,7 @@ __global__ __launch_bounds__(256) void k_project(ProjArgs a) {
                        __int_as_float(iu0 | (iu1 << 16)),
                        __int_as_float(iv0 | (iv1 << 16)));
     a.rec[slot] = R;
+    a.depth[slot] = R.q2.y;
     int ru0 = iu0, ru1 = iu1, rv0 = iv0, rv1 = iv1;
     if (!a.full_box) render_box(R, iu0, iu1, iv0, iv1, a.amin, ru0, ru1, rv0, rv1);
     a.rbox[slot] = make_int2(ru0 | (ru1 << 16), rv0 | (rv1 << 16));
@@ -490,7 +492,7 @@ hipError_t launch_project(gs_workspace* ws, const gs_params* p,
   a.W = ws->geo.width; a.H = ws->geo.height; a.tile = ws->geo.tile;
   a.Tx = ws->tiles_x; a.Ty = ws->tiles_y;
   a.rec = ws->records; a.tiles = ws->tiles_touched; a.diff = ws->diff;
-  a.rbox = ws->rbox; a.amin = s->alpha_min;
+  a.rbox = ws->rbox; a.depth = ws->depth; a.amin = s->alpha_min;
   a.full_box = (s->flags & GS_FLAG_FULL_BOX) ? 1 : 0;
   a.diff_atomics = bin_chunk(ws->tiles_x, ws->tiles_y) == 0;
   a.sig = ws->shape;
