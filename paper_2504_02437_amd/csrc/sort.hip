@@ -14,9 +14,9 @@
 // (64 w + l) E .. + E - 1 (one wave with E = 1 up to 64 keys, else four waves
 // with E = P2 / 256), so a compare-exchange at distance j < E stays inside a
 // lane, one at E <= j < 64 E pairs lane l with lane l ^ (j / E) of the same
-// wave (DPP for 1, 2, 4 and 8, a lane permute for 16 and 32), and only
-// j >= 64 E - at most three stages per segment - goes through LDS with
-// barriers.  Longer segments (rare: a tile covered by more than kCap
+// wave (DPP for 1 and 2, swizzles for 4, 8 and 16, a lane permute for
+// 32), and only j >= 64 E - at most three stages per segment - goes through
+// LDS with barriers.  Longer segments (rare: a tile covered by more than kCap
 // Gaussians) sort in place in the unsorted key buffer, with a global-memory
 // bitonic network whose first comparator of every merge stage pairs mirrored
 // positions, so positions past the end act as +infinity without being
@@ -70,18 +70,18 @@ __device__ void bitonic_sort(P a, int L, int tid, int nthr) {
   }
 }
 
-// 32-bit value of lane (lane ^ M).  DPP within rows for M <= 8 (every lane
-// of the wave is active here), a lane permute otherwise.
+// 32-bit value of lane (lane ^ M): a DPP quad permutation for M = 1, 2 (one
+// VALU instruction), a swizzle in bit-mask mode for 4, 8 and 16 (the LDS
+// unit's crossbar, no LDS memory; a DPP form would take two row shifts and a
+// select), a lane permute for 32.  Every lane of the wave is active here.
 template <int M>
 __device__ __forceinline__ int xor_lane32(int v, int lane) {
   if constexpr (M == 1) {
     return __builtin_amdgcn_update_dpp(0, v, 0xB1, 0xf, 0xf, true);  // quad_perm 1,0,3,2
   } else if constexpr (M == 2) {
     return __builtin_amdgcn_update_dpp(0, v, 0x4E, 0xf, 0xf, true);  // quad_perm 2,3,0,1
-  } else if constexpr (M == 4 || M == 8) {
-    const int up = __builtin_amdgcn_update_dpp(0, v, 0x110 + M, 0xf, 0xf, true);  // row_shr
-    const int dn = __builtin_amdgcn_update_dpp(0, v, 0x100 + M, 0xf, 0xf, true);  // row_shl
-    return (lane & M) ? up : dn;
+  } else if constexpr (M == 4 || M == 8 || M == 16) {
+    return __builtin_amdgcn_ds_swizzle(v, 0x1f | (M << 10));  // and 31, xor M
   } else {
     return __shfl_xor(v, M, 64);
   }
