@@ -112,6 +112,7 @@ static int make_layout(const gs_geometry* g, Layout& L, int& tx, int& ty) {
   L.diff = take(V * (size_t)(ty + 1) * (tx + 1) * 4);
   L.ranges = take(tiles * 8);
   L.cursor = take(tiles * 4);
+  L.tile_order = take(tiles * 4);
   const int ch = bin_chunk(tx, ty);
   L.chunk_counts = take(ch ? V * ((cap + ch - 1) / ch) * (size_t)tx * ty * 4 : 0);
   L.keys_unsorted = take(kc * 8);
@@ -189,6 +190,7 @@ int gs_workspace_create(const gs_geometry* geo, void* device_buffer,
   ws->diff = (int32_t*)(b + L.diff);
   ws->ranges = (uint32_t*)(b + L.ranges);
   ws->cursor = (uint32_t*)(b + L.cursor);
+  ws->tile_order = (uint32_t*)(b + L.tile_order);
   ws->chunk_counts = (uint32_t*)(b + L.chunk_counts);
   ws->keys_unsorted = (unsigned long long*)(b + L.keys_unsorted);
   ws->vals_sorted = (uint32_t*)(b + L.vals_sorted);
@@ -206,6 +208,7 @@ int gs_workspace_create(const gs_geometry* geo, void* device_buffer,
   if (e == hipSuccess) e = launch_fill_u32(ws->gcol, 0, V * 3 * cap, st);
   if (e == hipSuccess) e = launch_fill_u32(ws->counters, 0, sizeof(Counters) / 4, st);
   if (e == hipSuccess) e = launch_fill_u32(ws->ranges, 0, V * tx * ty * 2, st);
+  if (e == hipSuccess) e = launch_iota_u32(ws->tile_order, V * tx * ty, st);
   if (e == hipSuccess) e = launch_fill_u32(ws->tiles_touched, 0, V * cap, st);
   if (e != hipSuccess) {
     free(ws);

@@ -322,6 +322,77 @@ __global__ __launch_bounds__(256) void k_scatter_global(ScatterArgs a) {
                  });
 }
 
+constexpr int kOrderBuckets = 1024;
+constexpr int kOrderMaxTiles = 1 << 18;   // larger grids keep index order
+
+__global__ void k_iota(uint32_t* p, size_t n) {
+  for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n;
+       i += (size_t)gridDim.x * blockDim.x)
+    p[i] = (uint32_t)i;
+}
+
+// Tiles by descending key count (a counting sort over 1024 length buckets)
+// for the per-tile kernels, whose block b takes tile order[b]: the dispatcher
+// hands out the long lists first and the short ones fill the tail.  One
+// workgroup; the order within a bucket is unspecified (the tiles are
+// independent).
+__global__ __launch_bounds__(1024) void k_tile_order(const uint32_t* ranges,
+                                                     uint32_t* order, int n) {
+  __shared__ uint32_t cnt[kOrderBuckets];
+  __shared__ uint32_t wsum[16];
+  __shared__ uint32_t lmin, lmax;
+  const int tid = threadIdx.x;
+  cnt[tid] = 0;
+  if (tid == 0) { lmin = 0xffffffffu; lmax = 0; }
+  __syncthreads();
+  // The buckets span [shortest, longest], so few tiles share a bucket (and
+  // its LDS counter).
+  uint32_t mn = 0xffffffffu, mx = 0;
+  for (int t = tid; t < n; t += 1024) {
+    const uint32_t len = ranges[2 * t + 1] - ranges[2 * t];
+    mn = min(mn, len);
+    mx = max(mx, len);
+  }
+  for (int off = 32; off > 0; off >>= 1) {
+    mn = min(mn, (uint32_t)__shfl_down((int)mn, off, 64));
+    mx = max(mx, (uint32_t)__shfl_down((int)mx, off, 64));
+  }
+  if ((tid & 63) == 0) { atomicMin(&lmin, mn); atomicMax(&lmax, mx); }
+  __syncthreads();
+  const uint32_t base = lmin, width = (lmax - lmin) / kOrderBuckets + 1;
+  for (int t = tid; t < n; t += 1024) {
+    const uint32_t b = (ranges[2 * t + 1] - ranges[2 * t] - base) / width;
+    atomicAdd(&cnt[kOrderBuckets - 1 - b], 1u);
+  }
+  __syncthreads();
+  // Exclusive scan of the bucket counts (longest bucket first).
+  const int lane = tid & 63, w = tid >> 6;
+  const uint32_t c = cnt[tid];
+  uint32_t x = c;
+  for (int off = 1; off < 64; off <<= 1) {
+    const uint32_t y = __shfl_up(x, off, 64);
+    if (lane >= off) x += y;
+  }
+  if (lane == 63) wsum[w] = x;
+  __syncthreads();
+  uint32_t before = 0;
+  for (int i = 0; i < w; ++i) before += wsum[i];
+  cnt[tid] = before + x - c;
+  __syncthreads();
+  for (int t = tid; t < n; t += 1024) {
+    const uint32_t b = (ranges[2 * t + 1] - ranges[2 * t] - base) / width;
+    order[atomicAdd(&cnt[kOrderBuckets - 1 - b], 1u)] = (uint32_t)t;
+  }
+}
+
+hipError_t launch_order(const gs_workspace* ws, hipStream_t st) {
+  const int n = ws->geo.n_views * ws->tiles_x * ws->tiles_y;
+  if (n <= 0 || n > kOrderMaxTiles) return hipSuccess;   // index order kept
+  hipLaunchKernelGGL(k_tile_order, dim3(1), dim3(1024), 0, st, ws->ranges,
+                     ws->tile_order, n);
+  return hipGetLastError();
+}
+
 template <int MAXBINS, int GPT>
 hipError_t launch_chunked(const ScatterArgs& c, const RangeArgs& ra,
                           uint32_t* counts, int V, hipStream_t st) {
@@ -338,6 +409,12 @@ hipError_t launch_chunked(const ScatterArgs& c, const RangeArgs& ra,
   hipLaunchKernelGGL((k_scatter_chunks<MAXBINS, GPT>), dim3(nch, V),
                      dim3(256), 0, st, c);
   return hipGetLastError();
+}
+
+// Ranges are final: order the tiles for the per-tile kernels.
+hipError_t finish_bin(const gs_workspace* ws, hipError_t e, hipStream_t st) {
+  if (e != hipSuccess) return e;
+  return launch_order(ws, st);
 }
 
 }  // namespace
@@ -363,12 +440,14 @@ hipError_t launch_bin(gs_workspace* ws, const gs_params* p, hipStream_t st) {
     hipError_t e = launch_fill_u32(ws->cursor, 0u, (size_t)V * nb, st);
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(k_tile_ranges, dim3(V), dim3(kScanThreads), 0, st, ra);
-    return hipGetLastError();
+    return finish_bin(ws, hipGetLastError(), st);
   }
-  if (ch == 1024) return launch_chunked<1024, 4>(c, ra, ws->cursor, V, st);
+  if (ch == 1024)
+    return finish_bin(ws, launch_chunked<1024, 4>(c, ra, ws->cursor, V, st), st);
   if (ch == 2048 && nb <= 4096 && cells <= 4096 + kGridSlack)
-    return launch_chunked<4096, 8>(c, ra, ws->cursor, V, st);
-  if (ch == 2048) return launch_chunked<16384, 8>(c, ra, ws->cursor, V, st);
+    return finish_bin(ws, launch_chunked<4096, 8>(c, ra, ws->cursor, V, st), st);
+  if (ch == 2048)
+    return finish_bin(ws, launch_chunked<16384, 8>(c, ra, ws->cursor, V, st), st);
   CountArgs ca;
   ca.diff = ws->diff; ca.counts = ws->cursor;
   ca.Tx = ws->tiles_x; ca.Ty = ws->tiles_y;
@@ -377,6 +456,15 @@ hipError_t launch_bin(gs_workspace* ws, const gs_params* p, hipStream_t st) {
   if (p->capacity > 0)
     hipLaunchKernelGGL(k_scatter_global, dim3((c.cap + 255) / 256, V),
                        dim3(256), 0, st, c);
+  return finish_bin(ws, hipGetLastError(), st);
+}
+
+hipError_t launch_iota_u32(uint32_t* ptr, size_t count, hipStream_t st) {
+  if (count == 0) return hipSuccess;
+  size_t blocks = (count + 255) / 256;
+  if (blocks > 4096) blocks = 4096;
+  hipLaunchKernelGGL(k_iota, dim3((unsigned)blocks), dim3(256), 0, st, ptr,
+                     count);
   return hipGetLastError();
 }
 

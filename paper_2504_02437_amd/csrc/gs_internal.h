@@ -18,7 +18,8 @@ struct __align__(16) Record {
 
 // Workspace layout: every region is carved from the caller's device buffer.
 struct Layout {
-  size_t records, tiles_touched, rbox, depth, diff, ranges, cursor, chunk_counts,
+  size_t records, tiles_touched, rbox, depth, diff, ranges, cursor, tile_order,
+      chunk_counts,
       keys_unsorted, vals_sorted, keys_sorted, grad2d, gop, gcol, shape,
       counters, total;
 };
@@ -79,6 +80,8 @@ struct gs_workspace {
                          // (grids too large for the chunked binning)
   uint32_t* ranges;      // [V * Ty * Tx][2]
   uint32_t* cursor;      // [V * Ty * Tx] tile counts, then range starts
+  uint32_t* tile_order;  // [V * Ty * Tx] tiles by descending key count (the
+                         // per-tile kernels take block b -> tile order[b])
   uint32_t* chunk_counts;  // [V][chunks][Ty * Tx] keys of each chunk per
                            // tile, then each chunk's offset in the tile
   unsigned long long* keys_unsorted;  // [key_capacity] depth bits << 32 | g
@@ -139,6 +142,7 @@ hipError_t launch_sh_colour(gs_workspace* ws, const gs_params* p,
 hipError_t launch_sh_bwd(gs_workspace* ws, const gs_params* p,
                          const gs_camera* cams, gs_params* grad,
                          hipStream_t st);
+hipError_t launch_iota_u32(uint32_t* ptr, size_t count, hipStream_t st);
 hipError_t launch_fill_u32(void* ptr, uint32_t value, size_t count,
                            hipStream_t st);
 hipError_t launch_loss_l1(const float* rgb, const float* target, int V, int H,

@@ -129,6 +129,7 @@ struct RasterArgs {
   int ellipse_test;   // 0 with GS_FLAG_FULL_BOX
   const uint32_t* vals;
   const uint32_t* ranges;
+  const uint32_t* order;   // block b renders tile order[b]
   long long key_cap;
   int cap, V, W, H, Tx, Ty;
   float bg0, bg1, bg2;

@@ -96,7 +96,7 @@ __global__ __launch_bounds__(NT) void k_render_bwd(BwdArgs a) {
   __shared__ uint32_t gid[BATCH];
   __shared__ int smax;
   const RasterArgs& r = a.r;
-  const int t = blockIdx.x;
+  const int t = (int)r.order[blockIdx.x];
   const int tpv = r.Tx * r.Ty;
   const int k = t / tpv;
   const int rem = t - k * tpv;

@@ -49,7 +49,7 @@ __global__ __launch_bounds__(NT) void k_render_fwd(FwdArgs a) {
   constexpr int PPT = Lay::PPT;
   __shared__ Entry ent[BATCH];
   const RasterArgs& r = a.r;
-  const int t = blockIdx.x;
+  const int t = (int)r.order[blockIdx.x];
   const int tpv = r.Tx * r.Ty;
   const int k = t / tpv;
   const int rem = t - k * tpv;
@@ -207,7 +207,7 @@ RasterArgs make_raster_args(gs_workspace* ws, const gs_settings* s) {
   RasterArgs r;
   r.rec = ws->records; r.rbox = ws->rbox;
   r.ellipse_test = (s->flags & GS_FLAG_FULL_BOX) ? 0 : 1;
-  r.vals = ws->vals_sorted; r.ranges = ws->ranges;
+  r.vals = ws->vals_sorted; r.ranges = ws->ranges; r.order = ws->tile_order;
   r.key_cap = ws->geo.key_capacity; r.cap = ws->geo.capacity;
   r.V = ws->geo.n_views; r.W = ws->geo.width; r.H = ws->geo.height;
   r.Tx = ws->tiles_x; r.Ty = ws->tiles_y;

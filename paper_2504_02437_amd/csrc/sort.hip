@@ -29,6 +29,7 @@ namespace {
 
 struct SortArgs {
   const uint32_t* ranges;
+  const uint32_t* order;         // block b sorts tile order[b]
   unsigned long long* keys_in;   // sorted in place when a segment is long
   uint32_t* vals_out;
   unsigned long long* keys_out;  // may be null
@@ -198,7 +199,7 @@ template <int kCap>
 __global__ __launch_bounds__(256) void k_sort_tiles(SortArgs a) {
   static_assert(kCap == 4 * 64 * 16, "four waves of 16 keys per lane");
   __shared__ unsigned long long buf[kCap];
-  const int t = blockIdx.x;
+  const int t = (int)a.order[blockIdx.x];
   const int tid = threadIdx.x;
   const long long s = min((long long)a.ranges[2 * t], a.key_cap);
   const long long e = min((long long)a.ranges[2 * t + 1], a.key_cap);
@@ -232,7 +233,7 @@ __global__ __launch_bounds__(256) void k_sort_tiles(SortArgs a) {
 
 hipError_t launch_sort(gs_workspace* ws, const gs_settings* s, hipStream_t st) {
   SortArgs a;
-  a.ranges = ws->ranges; a.keys_in = ws->keys_unsorted;
+  a.ranges = ws->ranges; a.order = ws->tile_order; a.keys_in = ws->keys_unsorted;
   a.vals_out = ws->vals_sorted;
   a.keys_out = (s->flags & GS_FLAG_EMIT_KEYS) ? ws->keys_sorted : nullptr;
   a.key_cap = ws->geo.key_capacity;
