@@ -2,9 +2,10 @@
 """Mapping-iteration benchmark of the differentiable tile rasterizer.
 
 One step is one mapping iteration over a keyframe window: projection and
-binning, per-tile sort, forward render, L1 photometric + planar-regulariser
-gradients, backward pixel pass, projection backward and the Adam update, for
-all views of the window.  Inputs are synthetic (a room-shaped scene standing
+binning, per-tile sort, forward render, planar-regulariser gradient, backward
+pixel pass with the L1 photometric term fused in (loss and its gradient
+formed per pixel), projection backward and the Adam update, for all views of
+the window.  Inputs are synthetic (a room-shaped scene standing
 in for the paper's indoor sequences) and resident in HBM before timing.
 
 Prints one JSON line.  Extra fields: Mpix/s, per-kernel milliseconds, the
@@ -99,9 +100,8 @@ def iteration_ms(w, S, steps=10, warmup=3):
         grad.data.zero_()
         loss.zero_()
         rast.forward(params)
-        R.loss_l1(rast.rgb, target, LAMBDA_COLOR, dL, loss)
         R.planar_reg(params, LAMBDA_REG, REG_FLOOR, grad, loss)
-        rast.backward(params, dL, grad)
+        rast.backward_l1(params, target, LAMBDA_COLOR, grad, loss)
         R.adam(params, grad, m, v, LR, 0.9, 0.999, 1e-15, step_dev)
         step_dev.add_(1)
 
@@ -280,8 +280,8 @@ def main():
     dL = torch.empty_like(rgb)
     loss = torch.zeros(1, dtype=torch.float64, device=dev)
     step_dev = torch.ones(1, dtype=torch.int32, device=dev)
-    names = ("project_and_bin", "sort_tile_keys", "render_fwd", "loss_l1",
-             "planar_reg", "render_bwd", "project_bwd", "adam", "loss_ssim")
+    names = ("project_and_bin", "sort_tile_keys", "render_fwd", "planar_reg",
+             "render_bwd", "project_bwd", "adam", "loss_ssim")
     scratch = R.ssim_scratch(rgb)
     ev = {k: [] for k in names}
 
@@ -308,13 +308,16 @@ def main():
             timed("loss_ssim",
                   lambda: R.loss_ssim(rgb, target, LAMBDA_COLOR * LAMBDA_PHOTO,
                                       dL, loss, scratch=scratch), on)
-        else:
-            timed("loss_l1",
-                  lambda: R.loss_l1(rgb, target, LAMBDA_COLOR, dL, loss), on)
         timed("planar_reg",
               lambda: R.planar_reg(params, LAMBDA_REG, REG_FLOOR, grad, loss), on)
-        timed("render_bwd",
-              lambda: R.render_bwd_pixels(ws, params, S, dL, T, nlast, grad), on)
+        if ssim:
+            R.render_bwd_pixels(ws, params, S, dL, T, nlast, grad)
+        else:
+            # The L1 term is fused into the compositing backward.
+            timed("render_bwd",
+                  lambda: R.render_bwd_l1(ws, params, S, rgb, target,
+                                          LAMBDA_COLOR, T, nlast, grad, loss),
+                  on)
         timed("project_bwd",
               lambda: R.project_bwd(ws, params, cams_dev, grad), on)
         timed("adam", lambda: R.adam(params, grad, m, v, LR, 0.9, 0.999, 1e-15,
@@ -399,15 +402,13 @@ def main():
         for r1 in singles:
             r1.fit_key_capacity(params)
         tgt1 = [target[i:i + 1] for i in range(V)]
-        dL1 = torch.empty(1, 3, H, W, device=dev)
 
         def plain_step():
             grad.data.zero_()
             loss.zero_()
             for i, r1 in enumerate(singles):
                 r1.forward(params)
-                R.loss_l1(r1.rgb, tgt1[i], LAMBDA_COLOR, dL1, loss)
-                r1.backward(params, dL1, grad)
+                r1.backward_l1(params, tgt1[i], LAMBDA_COLOR, grad, loss)
             R.planar_reg(params, LAMBDA_REG, REG_FLOOR, grad, loss)
             R.adam(params, grad, m, v, LR, 0.9, 0.999, 1e-15, step_dev)
             step_dev.add_(1)

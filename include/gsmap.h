@@ -288,6 +288,23 @@ GS_API int gs_render_bwd(gs_workspace* ws, const gs_params* params,
                          const float* T_final, const int32_t* n_last,
                          gs_params* grad, void* stream);
 
+/* gs_render_bwd with the L1 photometric term of the map-optimisation loss
+ * (Eq. 10-11, L1 part) fused in: instead of reading a dL/d(out_rgb) buffer,
+ * every pixel forms dL/dC = lambda * sign(out_rgb - target) / (3HW)
+ * (sign(0) = 0) from the forward's image, exactly as gs_loss_l1 writes it,
+ * and the call ADDS lambda * mean over 3HW of |out_rgb - target|, summed
+ * over views, to *loss_dev (device double) and each view's squared-error sum
+ * to sqerr_dev[n_views] (device double, may be NULL).  The gradient then
+ * flows as in gs_render_bwd.  Equivalent to gs_loss_l1 followed by
+ * gs_render_bwd without the dL buffer's write and read.
+ *   out_rgb, target  device float [n_views][3][H][W] */
+GS_API int gs_render_bwd_l1(gs_workspace* ws, const gs_params* params,
+                            const gs_settings* s, const float* out_rgb,
+                            const float* target, float lambda,
+                            const float* T_final, const int32_t* n_last,
+                            gs_params* grad, double* loss_dev,
+                            double* sqerr_dev, void* stream);
+
 /* Backward of the projection (Eq. 1-2, FP64): chains the screen-space
  * gradients that gs_render_bwd left in the workspace, summed over the views,
  * through the conic, the EWA covariance, the Jacobian and the view transform

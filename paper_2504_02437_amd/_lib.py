@@ -81,6 +81,9 @@ _SIGS = {
                                  _vp]),
     "gs_render_bwd": (C.c_int, [_vp, _P(gs_params), _P(gs_settings), _vp,
                                 _vp, _vp, _P(gs_params), _vp]),
+    "gs_render_bwd_l1": (C.c_int, [_vp, _P(gs_params), _P(gs_settings), _vp,
+                                   _vp, C.c_float, _vp, _vp, _P(gs_params),
+                                   _vp, _vp, _vp]),
     "gs_project_bwd": (C.c_int, [_vp, _P(gs_params), _vp, _P(gs_params),
                                  _vp]),
     "gs_loss_l1": (C.c_int, [_vp, _vp, C.c_int32, C.c_int32, C.c_int32,

@@ -380,8 +380,37 @@ int gs_render_bwd(gs_workspace* ws, const gs_params* params,
   }
   if (int rc = same_layout(params, grad, "grad")) return rc;
   return finish(launch_render_bwd(ws, s, dL_drgb, T_final, n_last, grad->rgb,
-                                  params->sh_degree > 0, (hipStream_t)stream),
+                                  params->sh_degree > 0, nullptr,
+                                  (hipStream_t)stream),
                 "render_bwd");
+}
+
+int gs_render_bwd_l1(gs_workspace* ws, const gs_params* params,
+                     const gs_settings* s, const float* out_rgb,
+                     const float* target, float lambda, const float* T_final,
+                     const int32_t* n_last, gs_params* grad, double* loss_dev,
+                     double* sqerr_dev, void* stream) {
+  g_err[0] = 0;
+  if (int rc = check_ws(ws)) return rc;
+  if (int rc = validate_params(params, "params")) return rc;
+  if (int rc = validate_params(grad, "grad")) return rc;
+  if (int rc = validate_settings(s)) return rc;
+  if (s->tile != ws->geo.tile) { set_error("settings.tile differs from the workspace's"); return GS_E_INVALID; }
+  if (int rc = check_box_alpha(ws, s)) return rc;
+  if (!out_rgb || !target || !T_final || !n_last || !loss_dev) {
+    set_error("an input is NULL");
+    return GS_E_INVALID;
+  }
+  if (grad->capacity != params->capacity || params->capacity != ws->geo.capacity) {
+    set_error("grad / params / workspace capacities differ");
+    return GS_E_CAPACITY;
+  }
+  if (int rc = same_layout(params, grad, "grad")) return rc;
+  const L1Fused l1{out_rgb, target, lambda, loss_dev, sqerr_dev};
+  return finish(launch_render_bwd(ws, s, nullptr, T_final, n_last, grad->rgb,
+                                  params->sh_degree > 0, &l1,
+                                  (hipStream_t)stream),
+                "render_bwd_l1");
 }
 
 int gs_project_bwd(gs_workspace* ws, const gs_params* params,

@@ -133,10 +133,19 @@ hipError_t launch_densify(gs_params* p, gs_params* m, gs_params* v,
                           int32_t* status, hipStream_t st);
 hipError_t launch_count_pairs(gs_workspace* ws, const gs_settings* s,
                               unsigned long long* counts, hipStream_t st);
+// The L1 photometric term fused into the compositing backward.
+struct L1Fused {
+  const float* rgb;
+  const float* target;
+  float lambda;
+  double* loss;
+  double* sqerr;
+};
 hipError_t launch_render_bwd(gs_workspace* ws, const gs_settings* s,
                              const float* dL, const float* T,
                              const int32_t* nlast, float* grad_rgb,
-                             int per_view_colour, hipStream_t st);
+                             int per_view_colour, const L1Fused* l1,
+                             hipStream_t st);
 hipError_t launch_sh_colour(gs_workspace* ws, const gs_params* p,
                             const gs_camera* cams, hipStream_t st);
 hipError_t launch_sh_bwd(gs_workspace* ws, const gs_params* p,

@@ -34,7 +34,20 @@ struct BwdArgs {
   float* grgb;     // [3][cap] (caller's gradient rows, accumulated), or
                    // [V][3][cap] per view (view-dependent colour)
   size_t grgb_vstride;   // 0, or 3 cap for per-view colour gradients
+  // L1 photometric term fused in (target not null): dL/dC is formed per
+  // pixel from the forward's image instead of read from dL.
+  const float* rgb;
+  const float* target;
+  float l1_scale;        // lambda / (3HW), the gradient's magnitude
+  double l1_lam_inv;     // lambda / (3HW) in FP64, for the loss
+  double* loss;
+  double* sqerr;         // [V], may be null
 };
+
+// Sign of r times scale (sign(0) = 0): the L1 term's gradient.
+__device__ __forceinline__ float l1_grad(float r, float scale) {
+  return r > 0.f ? scale : (r < 0.f ? -scale : 0.f);
+}
 
 // x plus the DPP-permuted y.  Lanes whose source lies outside their row read
 // 0; the reductions below only keep lanes whose source is inside the row.
@@ -120,6 +133,8 @@ __global__ __launch_bounds__(NT) void k_render_bwd(BwdArgs a) {
   int last[PPT];
   float T[PPT], g0[PPT], g1[PPT], g2[PPT], Tb[PPT], Sg[PPT], vf[PPT];
   int mylast = 0;
+  float l1_abs = 0.f;
+  double l1_sq = 0.0;
 #pragma unroll
   for (int p = 0; p < PPT; ++p) {
     const int v = v0 + p;
@@ -130,11 +145,38 @@ __global__ __launch_bounds__(NT) void k_render_bwd(BwdArgs a) {
       const size_t pix = (size_t)v * r.W + u;
       T[p] = a.Tfin[(size_t)k * HW + pix];
       last[p] = a.nlast[(size_t)k * HW + pix];
-      g0[p] = a.dL[((size_t)k * 3 + 0) * HW + pix];
-      g1[p] = a.dL[((size_t)k * 3 + 1) * HW + pix];
-      g2[p] = a.dL[((size_t)k * 3 + 2) * HW + pix];
+      if (a.target) {
+        float gg[3];
+#pragma unroll
+        for (int ch = 0; ch < 3; ++ch) {
+          const size_t i = ((size_t)k * 3 + ch) * HW + pix;
+          const float d = a.rgb[i] - a.target[i];
+          l1_abs += fabsf(d);
+          l1_sq += (double)d * (double)d;
+          gg[ch] = l1_grad(d, a.l1_scale);
+        }
+        g0[p] = gg[0]; g1[p] = gg[1]; g2[p] = gg[2];
+      } else {
+        g0[p] = a.dL[((size_t)k * 3 + 0) * HW + pix];
+        g1[p] = a.dL[((size_t)k * 3 + 1) * HW + pix];
+        g2[p] = a.dL[((size_t)k * 3 + 2) * HW + pix];
+      }
       Tb[p] = T[p] * (r.bg0 * g0[p] + r.bg1 * g1[p] + r.bg2 * g2[p]);
       mylast = max(mylast, last[p]);
+    }
+  }
+  // The tile's share of the fused L1 loss: wave sums, then one FP64 atomic
+  // per workgroup.
+  __shared__ double lpart[2][NT / 64];
+  if (a.target) {
+    double la = l1_abs, lq = l1_sq;
+    for (int off = 32; off > 0; off >>= 1) {
+      la += __shfl_down(la, off, 64);
+      lq += __shfl_down(lq, off, 64);
+    }
+    if (lane == 0) {
+      lpart[0][wave] = la;
+      lpart[1][wave] = lq;
     }
   }
   if (tid == 0) smax = 0;
@@ -142,6 +184,15 @@ __global__ __launch_bounds__(NT) void k_render_bwd(BwdArgs a) {
   atomicMax(&smax, mylast);
   const int wlast = wave_max(mylast);
   __syncthreads();
+  if (a.target && tid == 0) {
+    double la = 0.0, lq = 0.0;
+    for (int w = 0; w < NT / 64; ++w) {
+      la += lpart[0][w];
+      lq += lpart[1][w];
+    }
+    atomicAdd(a.loss, la * a.l1_lam_inv);
+    if (a.sqerr) atomicAdd(&a.sqerr[k], lq);
+  }
   const int maxlast = (int)min((long long)smax, e - s);
   const Record* rv = r.rec + (size_t)k * r.cap;
   const int2* rbv = r.rbox + (size_t)k * r.cap;
@@ -258,10 +309,20 @@ struct BwdLauncher {
 hipError_t launch_render_bwd(gs_workspace* ws, const gs_settings* s,
                              const float* dL, const float* T,
                              const int32_t* nlast, float* grad_rgb,
-                             int per_view_colour, hipStream_t st) {
+                             int per_view_colour, const L1Fused* l1,
+                             hipStream_t st) {
   BwdArgs a;
   a.r = make_raster_args(ws, s);
   a.dL = dL; a.Tfin = T; a.nlast = nlast;
+  a.rgb = nullptr; a.target = nullptr; a.l1_scale = 0.f; a.l1_lam_inv = 0.0;
+  a.loss = nullptr; a.sqerr = nullptr;
+  if (l1) {
+    const size_t per = (size_t)3 * ws->geo.height * ws->geo.width;
+    a.rgb = l1->rgb; a.target = l1->target;
+    a.l1_scale = (float)((double)l1->lambda / (double)per);
+    a.l1_lam_inv = (double)l1->lambda / (double)per;
+    a.loss = l1->loss; a.sqerr = l1->sqerr;
+  }
   a.grad2d = ws->grad2d; a.gop = ws->gop;
   a.grgb = per_view_colour ? ws->gcol : grad_rgb;
   a.grgb_vstride = per_view_colour ? (size_t)3 * ws->geo.capacity : 0;

@@ -119,10 +119,9 @@ class Mapper:
             self.grad.data.zero_()
             loss.zero_()
             r.forward(self.params)
-            R.loss_l1(r.rgb, imgs, self.lam_color, dL, loss)
             R.planar_reg(self.params, self.lam_reg, self.reg_floor, self.grad,
                          loss)
-            r.backward(self.params, dL, self.grad)
+            r.backward_l1(self.params, imgs, self.lam_color, self.grad, loss)
             R.adam(self.params, self.grad, self.m, self.v, self.lr, 0.9, 0.999,
                    1e-15, self.step)
             self.step.add_(1)

@@ -328,6 +328,26 @@ def render_bwd_pixels(ws, params, settings, dL_drgb, T_final, n_last, grad,
            _ptr(n_last), C.byref(grad.struct()), _stream(stream))
 
 
+def render_bwd_l1(ws, params, settings, rgb, target, lam, T_final, n_last,
+                  grad, loss_dev, sqerr_dev=None, stream=None):
+    """gs_render_bwd_l1: the compositing backward with the L1 term fused in
+    (dL/dC formed per pixel from the forward's image and the target; the
+    loss is added to loss_dev)."""
+    V, H, W = ws.geo.n_views, ws.geo.height, ws.geo.width
+    for t, nm, cnt in ((rgb, "rgb", V * 3 * H * W), (target, "target", V * 3 * H * W),
+                       (T_final, "T_final", V * H * W),
+                       (n_last, "n_last", V * H * W)):
+        _require_cuda(t, nm)
+        if t.numel() != cnt:
+            raise ValueError(f"{nm} size does not match the workspace geometry")
+    if loss_dev.dtype != torch.float64:
+        raise ValueError("loss_dev must be float64")
+    L.call("gs_render_bwd_l1", ws.handle, C.byref(params.struct()),
+           C.byref(settings.struct()), _ptr(rgb), _ptr(target), float(lam),
+           _ptr(T_final), _ptr(n_last), C.byref(grad.struct()),
+           _ptr(loss_dev), _ptr(sqerr_dev), _stream(stream))
+
+
 def project_bwd(ws, params, cams_dev, grad, stream=None):
     L.call("gs_project_bwd", ws.handle, C.byref(params.struct()),
            _ptr(cams_dev), C.byref(grad.struct()), _stream(stream))
@@ -546,6 +566,16 @@ class Rasterizer:
     def backward(self, params, dL_drgb, grad, stream=None):
         render_bwd(self.ws, params, self.cams_dev, self.settings,
                    dL_drgb.contiguous(), self.T, self.nlast, grad, stream)
+
+    def backward_l1(self, params, target, lam, grad, loss_dev, sqerr_dev=None,
+                    stream=None):
+        """The whole backward of the L1 photometric term of the last forward
+        (fused into the compositing backward) plus the projection backward;
+        adds the loss to loss_dev."""
+        render_bwd_l1(self.ws, params, self.settings, self.rgb,
+                      target.contiguous(), lam, self.T, self.nlast, grad,
+                      loss_dev, sqerr_dev, stream)
+        project_bwd(self.ws, params, self.cams_dev, grad, stream)
 
     def status(self, clear=False):
         return read_status(self.ws, None, clear)

@@ -1,0 +1,130 @@
+"""The compositing backward with the L1 photometric term fused in
+(gs_render_bwd_l1) against gs_loss_l1 followed by gs_render_bwd, and against
+the oracle: the same per-pixel gradient, so parameter gradients agree to the
+order of the atomic sums; the loss and per-view squared errors agree to the
+summation order (|r| summed in FP32 per thread, then FP64, on both sides)."""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import synth
+from gpu_helpers import (check_grads, gpu_forward, oracle_backward,
+                         oracle_forward)
+from paper_2504_02437_amd import raster as R
+
+pytestmark = pytest.mark.gpu
+
+
+def _views(w, n):
+    c = w.cameras[0]
+    rng = np.random.default_rng(3)
+    cams = [c]
+    for _ in range(n - 1):
+        a = rng.normal(0, 0.1)
+        Rm = np.array([[np.cos(a), 0, np.sin(a)], [0, 1, 0],
+                       [-np.sin(a), 0, np.cos(a)]], np.float32)
+        cams.append(synth.Camera(Rm, rng.normal(0, 0.1, 3).astype(np.float32),
+                                 c.fx, c.fy, c.cx, c.cy, c.width, c.height))
+    w.cameras = cams
+    return w
+
+
+def _both(w, tile, batch, lam, bg=(0.0, 0.0, 0.0)):
+    params, rast = gpu_forward(w, tile, batch, bg)
+    V, H, W = len(w.cameras), rast.H, rast.W
+    tgt = torch.from_numpy(np.random.default_rng(9).uniform(
+        size=(V, 3, H, W)).astype(np.float32)).cuda()
+    # Some exact ties (sign 0).
+    tgt[:, :, :2, :5] = rast.rgb[:, :, :2, :5]
+    S = rast.settings
+    out = {}
+    for fused in (False, True):
+        grad = params.zeros_like()
+        loss = torch.zeros(1, dtype=torch.float64, device="cuda")
+        sq = torch.zeros(V, dtype=torch.float64, device="cuda")
+        if fused:
+            R.render_bwd_l1(rast.ws, params, S, rast.rgb, tgt, lam, rast.T,
+                            rast.nlast, grad, loss, sq)
+        else:
+            dL = torch.empty_like(rast.rgb)
+            R.loss_l1(rast.rgb, tgt, lam, dL, loss, sq)
+            R.render_bwd_pixels(rast.ws, params, S, dL, rast.T, rast.nlast, grad)
+        R.project_bwd(rast.ws, params, rast.cams_dev, grad)
+        torch.cuda.synchronize()
+        out[fused] = (grad.data.cpu().numpy(), float(loss), sq.cpu().numpy())
+    return params, rast, tgt, out
+
+
+@pytest.mark.parametrize("tile,batch", [(16, 256), (32, 256), (8, 128)])
+def test_fused_matches_separate_loss_and_backward(tile, batch):
+    w = _views(synth.tiny_scene(61, n=500, width=77, height=53, f=60.0), 3)
+    print("case fused l1", tile, batch, flush=True)
+    _, _, _, out = _both(w, tile, batch, 0.75, bg=(0.1, 0.2, 0.3))
+    (ga, la, sa), (gb, lb, sb) = out[False], out[True]
+    assert lb == pytest.approx(la, rel=1e-6)   # FP32 per-thread partial sums
+    np.testing.assert_allclose(sb, sa, rtol=1e-12)
+    scale = np.abs(ga).max(axis=1, keepdims=True)
+    assert np.all(np.abs(gb - ga) <= 1e-5 * scale + 1e-12)
+
+
+def test_fused_matches_the_oracle():
+    """Loss against the oracle's L1 of the same image; gradients against the
+    oracle's backward fed with the oracle's L1 gradient.  Pixels whose
+    decisions are FP32-ambiguous get target = image there, so both sides
+    see sign(0) = 0 and no gradient from them."""
+    w = synth.tiny_scene(62, n=400, width=70, height=45, f=60.0)
+    print("case fused l1 oracle", flush=True)
+    p64, proj, bins, fwd = oracle_forward(w, 16)
+    params, rast = gpu_forward(w, 16, 256)
+    img = rast.rgb.clone()
+    tgt = torch.from_numpy(np.random.default_rng(4).uniform(
+        size=tuple(img.shape)).astype(np.float32)).cuda()
+    mask = torch.from_numpy(fwd["flags"] == 0).cuda()[:, None]
+    tgt = torch.where(mask, tgt, img)
+    grad = params.zeros_like()
+    loss = torch.zeros(1, dtype=torch.float64, device="cuda")
+    R.render_bwd_l1(rast.ws, params, rast.settings, rast.rgb, tgt, 0.75, rast.T,
+                    rast.nlast, grad, loss)
+    R.project_bwd(rast.ws, params, rast.cams_dev, grad)
+    torch.cuda.synchronize()
+    ref_loss, ref_d = oracle.l1(img.cpu().numpy().astype(np.float64),
+                                tgt.cpu().numpy(), 0.75)
+    assert float(loss) == pytest.approx(ref_loss, rel=1e-6)
+    check_grads(grad.data.cpu().numpy(),
+                oracle_backward(w, p64, proj, bins, ref_d), w.gaussians.n)
+
+
+def test_fused_full_size_window():
+    """The 10-view 1200x680 window at the benchmark's launch shape: loss and
+    per-view squared errors equal, gradients equal to the order of the
+    atomic sums."""
+    w = synth.config2()
+    print("case fused l1 window", flush=True)
+    params = R.ParamBuffer.from_gaussians(w.gaussians)
+    rast = R.Rasterizer(w.cameras, params.capacity,
+                        R.Settings(tile=32, lds_batch=256, block_threads=256))
+    rast.fit_key_capacity(params)
+    rast.forward(params)
+    tgt = torch.from_numpy(w.targets).cuda()
+    res = []
+    for fused in (False, True):
+        grad = params.zeros_like()
+        loss = torch.zeros(1, dtype=torch.float64, device="cuda")
+        sq = torch.zeros(10, dtype=torch.float64, device="cuda")
+        if fused:
+            R.render_bwd_l1(rast.ws, params, rast.settings, rast.rgb, tgt, 1.0,
+                            rast.T, rast.nlast, grad, loss, sq)
+        else:
+            dL = torch.empty_like(rast.rgb)
+            R.loss_l1(rast.rgb, tgt, 1.0, dL, loss, sq)
+            R.render_bwd_pixels(rast.ws, params, rast.settings, dL, rast.T,
+                                rast.nlast, grad)
+        R.project_bwd(rast.ws, params, rast.cams_dev, grad)
+        torch.cuda.synchronize()
+        res.append((grad.data.cpu().numpy(), float(loss), sq.cpu().numpy()))
+    (ga, la, sa), (gb, lb, sb) = res
+    assert lb == pytest.approx(la, rel=1e-6)   # FP32 per-thread partial sums
+    np.testing.assert_allclose(sb, sa, rtol=1e-12)
+    scale = np.abs(ga).max(axis=1, keepdims=True)
+    assert np.all(np.abs(gb - ga) <= 1e-4 * scale + 1e-12)
