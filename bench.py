@@ -304,10 +304,11 @@ def main():
         timed("render_fwd",
               lambda: R.render_fwd(ws, params, S, rgb, T, nlast), on)
         if ssim:
-            R.loss_l1(rgb, target, LAMBDA_COLOR * (1 - LAMBDA_PHOTO), dL, loss)
             timed("loss_ssim",
-                  lambda: R.loss_ssim(rgb, target, LAMBDA_COLOR * LAMBDA_PHOTO,
-                                      dL, loss, scratch=scratch), on)
+                  lambda: R.loss_colour(rgb, target,
+                                        LAMBDA_COLOR * (1 - LAMBDA_PHOTO),
+                                        LAMBDA_COLOR * LAMBDA_PHOTO, dL, loss,
+                                        scratch=scratch), on)
         timed("planar_reg",
               lambda: R.planar_reg(params, LAMBDA_REG, REG_FLOOR, grad, loss), on)
         if ssim:
@@ -391,7 +392,7 @@ def main():
         ms_full = a.elapsed_time(b) / k
         ssim_ms = float(np.mean([x.elapsed_time(y) for x, y in ev["loss_ssim"]]))
         full = {"iterations_per_s": 1000.0 / ms_full, "ms_per_iteration": ms_full,
-                "launch": "eager", "loss_ssim_ms": ssim_ms,
+                "launch": "eager", "loss_colour_ms": ssim_ms,
                 "lambda_photo": LAMBDA_PHOTO}
 
     per_view = None

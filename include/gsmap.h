@@ -342,6 +342,20 @@ GS_API int gs_loss_ssim(const float* rgb, const float* target, int32_t n_views,
                         float* dL_drgb, double* loss_dev, double* ssim_dev,
                         float* scratch, void* stream);
 
+/* The whole colour loss of Eq. 10 in the two passes of gs_loss_ssim:
+ * lambda_l1 * (L1 term of gs_loss_l1) + lambda_ssim * (SSIM term of
+ * gs_loss_ssim), i.e. lambda_color (1 - lambda_photo) and lambda_color
+ * lambda_photo.  WRITES dL_drgb (the sum of both gradients), ADDS both terms
+ * to *loss_dev, the per-view squared-error sums to sqerr_dev[n_views] and the
+ * per-view mean SSIM to ssim_dev[n_views] (both may be NULL).  Equivalent to
+ * gs_loss_l1 then gs_loss_ssim, without the L1 pass over the images.
+ *   rgb, target, dL_drgb, scratch  as in gs_loss_ssim */
+GS_API int gs_loss_colour(const float* rgb, const float* target,
+                          int32_t n_views, int32_t height, int32_t width,
+                          float lambda_l1, float lambda_ssim, float* dL_drgb,
+                          double* loss_dev, double* sqerr_dev,
+                          double* ssim_dev, float* scratch, void* stream);
+
 /* Planar regulariser of Eq. 10-11: lambda * mean over live Gaussians of
  * max(floor, min_j exp(log_scale_j)).  ADDS its gradient into
  * grad->log_scale (smallest axis only, lowest index on ties, only where the

@@ -98,6 +98,9 @@ _SIGS = {
                              C.c_int64, C.c_int32, _vp, _vp, _vp, _vp, _vp]),
     "gs_loss_ssim": (C.c_int, [_vp, _vp, C.c_int32, C.c_int32, C.c_int32,
                                C.c_float, _vp, _vp, _vp, _vp, _vp]),
+    "gs_loss_colour": (C.c_int, [_vp, _vp, C.c_int32, C.c_int32, C.c_int32,
+                                 C.c_float, C.c_float, _vp, _vp, _vp, _vp,
+                                 _vp, _vp]),
     "gs_planar_reg": (C.c_int, [_P(gs_params), C.c_float, C.c_float,
                                 _P(gs_params), _vp, _vp]),
     "gs_adam": (C.c_int, [_P(gs_params), _P(gs_params), _P(gs_params),

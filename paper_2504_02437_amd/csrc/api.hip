@@ -456,6 +456,21 @@ int gs_loss_ssim(const float* rgb, const float* target, int32_t n_views,
                 "loss_ssim");
 }
 
+int gs_loss_colour(const float* rgb, const float* target, int32_t n_views,
+                   int32_t height, int32_t width, float lambda_l1,
+                   float lambda_ssim, float* dL_drgb, double* loss_dev,
+                   double* sqerr_dev, double* ssim_dev, float* scratch,
+                   void* stream) {
+  g_err[0] = 0;
+  if (!rgb || !target || !dL_drgb || !loss_dev || !scratch) { set_error("an argument is NULL"); return GS_E_INVALID; }
+  if (n_views < 1 || height < 1 || width < 1 || n_views > 21845) { set_error("bad image size"); return GS_E_INVALID; }
+  return finish(launch_loss_colour(rgb, target, n_views, height, width,
+                                   lambda_l1, lambda_ssim, 1, dL_drgb,
+                                   loss_dev, sqerr_dev, ssim_dev, scratch,
+                                   (hipStream_t)stream),
+                "loss_colour");
+}
+
 int gs_planar_reg(const gs_params* params, float lambda, float floor_,
                   gs_params* grad, double* loss_dev, void* stream) {
   g_err[0] = 0;

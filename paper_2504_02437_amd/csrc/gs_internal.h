@@ -47,6 +47,11 @@ struct Counters {
 hipError_t launch_loss_ssim(const float* rgb, const float* target, int V,
                             int H, int W, float lam, float* dL, double* loss,
                             double* ssim, float* scratch, hipStream_t st);
+hipError_t launch_loss_colour(const float* rgb, const float* target, int V,
+                              int H, int W, float lam_l1, float lam,
+                              int fuse_l1, float* dL, double* loss,
+                              double* sqerr, double* ssim, float* scratch,
+                              hipStream_t st);
 hipError_t launch_knn_features(const gs_params* p, const gs_camera* cam, int W,
                                int H, const float* kf_rgb, const float* pts,
                                int n_pts, int centre_only, float* feats,

@@ -85,17 +85,19 @@ __global__ __launch_bounds__(256) void k_planar_reg(const float* lsc,
                                                     double floor_, float* dlsc,
                                                     double* loss) {
   __shared__ double sh[4];
-  const int g = blockIdx.x * 256 + threadIdx.x;
   const int n = min(*n_dev, cap);
   double term = 0.0;
-  if (g < n) {
+  // Grid-stride over the Gaussians with a few hundred workgroups: the loss
+  // takes one FP64 atomic per workgroup, and atomics on one address
+  // serialise.
+  for (int g = blockIdx.x * 256 + threadIdx.x; g < n; g += gridDim.x * 256) {
     const float l0 = lsc[g], l1 = lsc[cap + g], l2 = lsc[2 * cap + g];
     int jm = 0;
     float lm = l0;
     if (l1 < lm) { lm = l1; jm = 1; }
     if (l2 < lm) { lm = l2; jm = 2; }
     const double sm = exp((double)lm);
-    term = sm > floor_ ? sm : floor_;
+    term += sm > floor_ ? sm : floor_;
     if (sm > floor_) dlsc[jm * cap + g] += (float)((double)lam * sm / (double)n);
   }
   const double t = block_sum(term, sh);
@@ -374,7 +376,7 @@ hipError_t launch_loss_l1(const float* rgb, const float* target, int V, int H,
 
 hipError_t launch_planar_reg(const gs_params* p, float lambda, float floor_,
                              gs_params* grad, double* loss, hipStream_t st) {
-  const int blocks = (p->capacity + 255) / 256;
+  const int blocks = min(256, (p->capacity + 255) / 256);
   if (blocks <= 0) return hipSuccess;
   hipLaunchKernelGGL(k_planar_reg, dim3(blocks), dim3(256), 0, st,
                      p->log_scale, p->n_dev, p->capacity, lambda,

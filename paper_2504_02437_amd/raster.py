@@ -365,6 +365,23 @@ def loss_l1(rgb, target, lam, dL_drgb, loss_dev, sqerr_dev=None, stream=None):
            _ptr(dL_drgb), _ptr(loss_dev), _ptr(sqerr_dev), _stream(stream))
 
 
+def loss_colour(rgb, target, lam_l1, lam_ssim, dL_drgb, loss_dev,
+                sqerr_dev=None, ssim_dev=None, scratch=None, stream=None):
+    """gs_loss_colour: lam_l1 * L1 + lam_ssim * (1 - SSIM), gradient written
+    to dL_drgb.  Returns the scratch buffer."""
+    V, _, H, W = rgb.shape
+    for t, nm in ((rgb, "rgb"), (target, "target"), (dL_drgb, "dL_drgb")):
+        _require_cuda(t, nm)
+        if t.shape != rgb.shape or t.dtype != torch.float32:
+            raise ValueError(f"{nm} must be float32 of shape {tuple(rgb.shape)}")
+    if scratch is None:
+        scratch = ssim_scratch(rgb)
+    L.call("gs_loss_colour", _ptr(rgb), _ptr(target), V, H, W, float(lam_l1),
+           float(lam_ssim), _ptr(dL_drgb), _ptr(loss_dev), _ptr(sqerr_dev),
+           _ptr(ssim_dev), _ptr(scratch), _stream(stream))
+    return scratch
+
+
 def ssim_scratch(rgb):
     """Scratch buffer gs_loss_ssim needs for images shaped like `rgb`."""
     return torch.empty((3,) + tuple(rgb.shape), dtype=torch.float32,

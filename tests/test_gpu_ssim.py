@@ -81,3 +81,50 @@ def test_full_size_view():
     x, y = _pair(5, (1, 3, 680, 1200))
     print("case ssim full size", flush=True)
     _check(x, y)
+
+
+def _colour(x, y, lam_l1, lam_ssim, fused):
+    xd, yd = torch.from_numpy(x).cuda(), torch.from_numpy(y).cuda()
+    V = x.shape[0]
+    dL = torch.full(x.shape, 7.0, device="cuda")        # overwritten
+    loss = torch.zeros(1, dtype=torch.float64, device="cuda")
+    sq = torch.zeros(V, dtype=torch.float64, device="cuda")
+    ssim = torch.zeros(V, dtype=torch.float64, device="cuda")
+    if fused:
+        R.loss_colour(xd, yd, lam_l1, lam_ssim, dL, loss, sq, ssim)
+    else:
+        R.loss_l1(xd, yd, lam_l1, dL, loss, sq)
+        R.loss_ssim(xd, yd, lam_ssim, dL, loss, ssim)
+    torch.cuda.synchronize()
+    return float(loss), sq.cpu().numpy(), ssim.cpu().numpy(), dL.cpu().numpy()
+
+
+@pytest.mark.parametrize("shape", [(2, 3, 45, 70), (1, 3, 9, 5), (3, 3, 130, 200)])
+def test_colour_loss_fused_equals_l1_then_ssim(shape):
+    """gs_loss_colour = gs_loss_l1 followed by gs_loss_ssim: the gradient bit
+    for bit (same per-pixel arithmetic), squared errors and mean SSIM to
+    FP64 summation order, the loss to the FP32 partial sums of |r|."""
+    x, y = _pair(7, shape)
+    x[:, :, :2, :3] = y[:, :, :2, :3]                  # sign(0) = 0
+    print("case colour loss", shape, flush=True)
+    a = _colour(x, y, 0.8, 0.2, False)
+    b = _colour(x, y, 0.8, 0.2, True)
+    assert b[0] == pytest.approx(a[0], rel=1e-6)
+    np.testing.assert_allclose(b[1], a[1], rtol=1e-12)
+    np.testing.assert_allclose(b[2], a[2], rtol=1e-12)
+    np.testing.assert_array_equal(b[3], a[3])
+
+
+def test_colour_loss_against_the_oracle():
+    import oracle
+    x, y = _pair(8, (2, 3, 45, 70))
+    print("case colour loss oracle", flush=True)
+    loss, sq, ssim, g = _colour(x, y, 0.75, 0.25, True)
+    l1, gl1 = oracle.l1(x.astype(np.float64), y, 0.75)
+    ls, gs = OS.loss_ssim(x.astype(np.float64), y.astype(np.float64), 0.25)
+    assert loss == pytest.approx(l1 + ls, rel=1e-5)
+    ref_g = gl1 + gs
+    tol = 1e-3 * np.maximum(np.abs(ref_g), 1e-2 * np.abs(ref_g).max()) + 1e-30
+    assert np.all(np.abs(g - ref_g) <= tol)
+    np.testing.assert_allclose(
+        sq, ((x.astype(np.float64) - y) ** 2).sum(axis=(1, 2, 3)), rtol=1e-9)
