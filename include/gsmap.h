@@ -296,7 +296,10 @@ GS_API int gs_render_bwd(gs_workspace* ws, const gs_params* params,
  * over views, to *loss_dev (device double) and each view's squared-error sum
  * to sqerr_dev[n_views] (device double, may be NULL).  The gradient then
  * flows as in gs_render_bwd.  Equivalent to gs_loss_l1 followed by
- * gs_render_bwd without the dL buffer's write and read.
+ * gs_render_bwd without the dL buffer's write and read.  The sums are taken
+ * per tile, then over tiles in a fixed order, so repeated calls add the same
+ * bits.  The workspace holds the per-tile partials: calls that share a
+ * workspace must not overlap.
  *   out_rgb, target  device float [n_views][3][H][W] */
 GS_API int gs_render_bwd_l1(gs_workspace* ws, const gs_params* params,
                             const gs_settings* s, const float* out_rgb,

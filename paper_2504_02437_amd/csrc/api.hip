@@ -113,6 +113,7 @@ static int make_layout(const gs_geometry* g, Layout& L, int& tx, int& ty) {
   L.ranges = take(tiles * 8);
   L.cursor = take(tiles * 4);
   L.tile_order = take(tiles * 4);
+  L.tile_loss = take(tiles * 16);
   const int ch = bin_chunk(tx, ty);
   L.chunk_counts = take(ch ? V * ((cap + ch - 1) / ch) * (size_t)tx * ty * 4 : 0);
   L.keys_unsorted = take(kc * 8);
@@ -191,6 +192,7 @@ int gs_workspace_create(const gs_geometry* geo, void* device_buffer,
   ws->ranges = (uint32_t*)(b + L.ranges);
   ws->cursor = (uint32_t*)(b + L.cursor);
   ws->tile_order = (uint32_t*)(b + L.tile_order);
+  ws->tile_loss = (double*)(b + L.tile_loss);
   ws->chunk_counts = (uint32_t*)(b + L.chunk_counts);
   ws->keys_unsorted = (unsigned long long*)(b + L.keys_unsorted);
   ws->vals_sorted = (uint32_t*)(b + L.vals_sorted);

@@ -19,7 +19,7 @@ struct __align__(16) Record {
 // Workspace layout: every region is carved from the caller's device buffer.
 struct Layout {
   size_t records, tiles_touched, rbox, depth, diff, ranges, cursor, tile_order,
-      chunk_counts,
+      tile_loss, chunk_counts,
       keys_unsorted, vals_sorted, keys_sorted, grad2d, gop, gcol, shape,
       counters, total;
 };
@@ -87,6 +87,8 @@ struct gs_workspace {
   uint32_t* cursor;      // [V * Ty * Tx] tile counts, then range starts
   uint32_t* tile_order;  // [V * Ty * Tx] tiles by descending key count (the
                          // per-tile kernels take block b -> tile order[b])
+  double* tile_loss;     // [V * Ty * Tx][2] fused L1 loss and squared error
+                         // of each tile, summed by one small kernel
   uint32_t* chunk_counts;  // [V][chunks][Ty * Tx] keys of each chunk per
                            // tile, then each chunk's offset in the tile
   unsigned long long* keys_unsorted;  // [key_capacity] depth bits << 32 | g

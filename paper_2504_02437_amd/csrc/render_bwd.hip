@@ -40,8 +40,7 @@ struct BwdArgs {
   const float* target;
   float l1_scale;        // lambda / (3HW), the gradient's magnitude
   double l1_lam_inv;     // lambda / (3HW) in FP64, for the loss
-  double* loss;
-  double* sqerr;         // [V], may be null
+  double* tile_loss;     // [tiles][2]: this tile's loss and squared error
 };
 
 // Sign of r times scale (sign(0) = 0): the L1 term's gradient.
@@ -165,8 +164,9 @@ __global__ __launch_bounds__(NT) void k_render_bwd(BwdArgs a) {
       mylast = max(mylast, last[p]);
     }
   }
-  // The tile's share of the fused L1 loss: wave sums, then one FP64 atomic
-  // per workgroup.
+  // The tile's share of the fused L1 loss: wave sums, then one plain store
+  // per workgroup (a second kernel sums the tiles: FP64 atomics on one
+  // address would serialise).
   __shared__ double lpart[2][NT / 64];
   if (a.target) {
     double la = l1_abs, lq = l1_sq;
@@ -190,8 +190,8 @@ __global__ __launch_bounds__(NT) void k_render_bwd(BwdArgs a) {
       la += lpart[0][w];
       lq += lpart[1][w];
     }
-    atomicAdd(a.loss, la * a.l1_lam_inv);
-    if (a.sqerr) atomicAdd(&a.sqerr[k], lq);
+    a.tile_loss[2 * (size_t)t] = la * a.l1_lam_inv;
+    a.tile_loss[2 * (size_t)t + 1] = lq;
   }
   const int maxlast = (int)min((long long)smax, e - s);
   const Record* rv = r.rec + (size_t)k * r.cap;
@@ -293,6 +293,43 @@ __global__ __launch_bounds__(NT) void k_render_bwd(BwdArgs a) {
   }
 }
 
+// Sum of the tiles' fused L1 losses into *loss and of each view's squared
+// errors into sqerr[view], in a fixed order (so the result does not depend on
+// scheduling): wave w of the one workgroup reduces view k0 + w, then thread 0
+// adds the views in order.
+__global__ __launch_bounds__(1024) void k_l1_reduce(const double2* tile_loss,
+                                                    int V, int tpv,
+                                                    double* loss,
+                                                    double* sqerr) {
+  __shared__ double part[16];
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  double total = 0.0;
+  for (int k0 = 0; k0 < V; k0 += 16) {
+    const int k = k0 + w;
+    if (k < V) {
+      double la = 0.0, lq = 0.0;
+      for (int i = lane; i < tpv; i += 64) {
+        const double2 q = tile_loss[(size_t)k * tpv + i];
+        la += q.x;
+        lq += q.y;
+      }
+      for (int off = 32; off > 0; off >>= 1) {
+        la += __shfl_down(la, off, 64);
+        lq += __shfl_down(lq, off, 64);
+      }
+      if (lane == 0) {
+        part[w] = la;
+        if (sqerr) sqerr[k] += lq;
+      }
+    }
+    __syncthreads();
+    if (tid == 0)
+      for (int i = 0; i < 16 && k0 + i < V; ++i) total += part[i];
+    __syncthreads();
+  }
+  if (tid == 0) *loss += total;
+}
+
 struct BwdLauncher {
   const BwdArgs& a;
   int blocks;
@@ -315,13 +352,12 @@ hipError_t launch_render_bwd(gs_workspace* ws, const gs_settings* s,
   a.r = make_raster_args(ws, s);
   a.dL = dL; a.Tfin = T; a.nlast = nlast;
   a.rgb = nullptr; a.target = nullptr; a.l1_scale = 0.f; a.l1_lam_inv = 0.0;
-  a.loss = nullptr; a.sqerr = nullptr;
+  a.tile_loss = ws->tile_loss;
   if (l1) {
     const size_t per = (size_t)3 * ws->geo.height * ws->geo.width;
     a.rgb = l1->rgb; a.target = l1->target;
     a.l1_scale = (float)((double)l1->lambda / (double)per);
     a.l1_lam_inv = (double)l1->lambda / (double)per;
-    a.loss = l1->loss; a.sqerr = l1->sqerr;
   }
   a.grad2d = ws->grad2d; a.gop = ws->gop;
   a.grgb = per_view_colour ? ws->gcol : grad_rgb;
@@ -330,6 +366,14 @@ hipError_t launch_render_bwd(gs_workspace* ws, const gs_settings* s,
   if (blocks <= 0) return hipSuccess;
   dispatch_shape(ws->geo.tile, s->lds_batch, s->block_threads,
                  BwdLauncher{a, blocks, st});
+  if (l1) {
+    const hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_l1_reduce, dim3(1), dim3(1024), 0, st,
+                       (const double2*)ws->tile_loss,
+                       ws->geo.n_views, ws->tiles_x * ws->tiles_y, l1->loss,
+                       l1->sqerr);
+  }
   return hipGetLastError();
 }
 

@@ -8,15 +8,16 @@
 // which is exactly the order of a stable sort of (tile << 32 | depth bits)
 // keys emitted Gaussian by Gaussian.
 //
-// Sorting network: bitonic over the segment padded to a power of two P2
-// with all-ones keys (larger than any real key).  Segments up to kCap keys
-// sort in registers: lane l of wave w holds the E consecutive positions
-// (64 w + l) E .. + E - 1 (one wave with E = 1 up to 64 keys, else four waves
-// with E = P2 / 256), so a compare-exchange at distance j < E stays inside a
-// lane, one at E <= j < 64 E pairs lane l with lane l ^ (j / E) of the same
-// wave (DPP for 1 and 2, swizzles for 4, 8 and 16, a lane permute for
-// 32), and only j >= 64 E - at most three stages per segment - goes through
-// LDS with barriers.  Longer segments (rare: a tile covered by more than kCap
+// Sorting network: bitonic, in its all-ascending form, over the segment
+// padded to a power of two P2 with all-ones keys (larger than any real key).
+// Segments up to kCap keys sort in registers: lane l of wave w holds the E
+// consecutive positions (64 w + l) E .. + E - 1 (one wave with E = 1 up to 64
+// keys, else four waves with E = P2 / 256), so a comparator whose positions
+// differ only below bit log2 E stays inside a lane, one that differs below
+// bit log2 64E pairs two lanes of the same wave (DPP, swizzles or a lane
+// permute), and only the others - at most three merge steps per segment - go
+// through LDS with barriers.  Padding never moves in the all-ascending form,
+// so waves that hold only padding skip the compare-exchanges.  Longer segments (rare: a tile covered by more than kCap
 // Gaussians) sort in place in the unsorted key buffer, with a global-memory
 // bitonic network whose first comparator of every merge stage pairs mirrored
 // positions, so positions past the end act as +infinity without being
@@ -71,101 +72,173 @@ __device__ void bitonic_sort(P a, int L, int tid, int nthr) {
   }
 }
 
-// 32-bit value of lane (lane ^ M): a DPP quad permutation for M = 1, 2 (one
-// VALU instruction), a swizzle in bit-mask mode for 4, 8 and 16 (the LDS
-// unit's crossbar, no LDS memory; a DPP form would take two row shifts and a
-// select), a lane permute for 32.  Every lane of the wave is active here.
+// 32-bit value of lane (lane ^ M), every lane of the wave active:
+//   M = 1, 3      DPP quad permutation (one VALU instruction)
+//   M = 2         DPP quad permutation
+//   M = 7, 15     DPP half-row and row mirror
+//   M = 4, 8, 16, 31  swizzle in bit-mask mode (the LDS unit's crossbar, no
+//                 LDS memory)
+//   M = 32, 63    lane permute.
 template <int M>
-__device__ __forceinline__ int xor_lane32(int v, int lane) {
+__device__ __forceinline__ int xor_lane32(int v) {
   if constexpr (M == 1) {
     return __builtin_amdgcn_update_dpp(0, v, 0xB1, 0xf, 0xf, true);  // quad_perm 1,0,3,2
   } else if constexpr (M == 2) {
     return __builtin_amdgcn_update_dpp(0, v, 0x4E, 0xf, 0xf, true);  // quad_perm 2,3,0,1
-  } else if constexpr (M == 4 || M == 8 || M == 16) {
+  } else if constexpr (M == 3) {
+    return __builtin_amdgcn_update_dpp(0, v, 0x1B, 0xf, 0xf, true);  // quad_perm 3,2,1,0
+  } else if constexpr (M == 7) {
+    return __builtin_amdgcn_update_dpp(0, v, 0x141, 0xf, 0xf, true); // row_half_mirror
+  } else if constexpr (M == 15) {
+    return __builtin_amdgcn_update_dpp(0, v, 0x140, 0xf, 0xf, true); // row_mirror
+  } else if constexpr (M == 4 || M == 8 || M == 16 || M == 31) {
     return __builtin_amdgcn_ds_swizzle(v, 0x1f | (M << 10));  // and 31, xor M
   } else {
+    static_assert(M == 32 || M == 63, "unsupported lane mask");
     return __shfl_xor(v, M, 64);
   }
 }
 
 template <int M>
-__device__ __forceinline__ unsigned long long xor_lane(unsigned long long v,
-                                                       int lane) {
-  const uint32_t lo = (uint32_t)xor_lane32<M>((int)(uint32_t)v, lane);
-  const uint32_t hi = (uint32_t)xor_lane32<M>((int)(uint32_t)(v >> 32), lane);
+__device__ __forceinline__ unsigned long long xor_lane(unsigned long long v) {
+  const uint32_t lo = (uint32_t)xor_lane32<M>((int)(uint32_t)v);
+  const uint32_t hi = (uint32_t)xor_lane32<M>((int)(uint32_t)(v >> 32));
   return ((unsigned long long)hi << 32) | lo;
 }
 
-// Stage (k, J) with J < E: pairs inside the lane.
+__device__ __forceinline__ void keep(unsigned long long& x, unsigned long long y,
+                                     bool keep_min) {
+  x = ((y < x) == keep_min) ? y : x;
+}
+
+// The network is the all-ascending ("mirror") form of bitonic sort: merge
+// step k first compares position p with p ^ (k - 1), the mirror image of p in
+// its block of k, then p with p ^ j for j = k/4 .. 1; every comparator puts
+// the smaller key at the lower position.  Padding keys (all ones) at the
+// positions >= L therefore never move, so a wave whose positions all lie at
+// or past L has nothing to do but its part of the barriers.
+//
+// In-lane stages: mirror step k <= E, or distance j < E.
+template <int E, int K>
+__device__ __forceinline__ void mirror_in_lane(unsigned long long (&x)[E]) {
+#pragma unroll
+  for (int e = 0; e < E; ++e) {
+    if (e & (K >> 1)) continue;
+    const int h = e ^ (K - 1);
+    const unsigned long long a = x[e], b = x[h];
+    x[e] = b < a ? b : a;
+    x[h] = b < a ? a : b;
+  }
+}
+
 template <int E, int J>
-__device__ __forceinline__ void stage_in_lane(unsigned long long (&x)[E],
-                                              int base, int k) {
+__device__ __forceinline__ void stage_in_lane(unsigned long long (&x)[E]) {
 #pragma unroll
   for (int e = 0; e < E; ++e) {
     if (e & J) continue;
-    const bool asc = ((base + e) & k) == 0;
     const unsigned long long a = x[e], b = x[e + J];
-    const bool swap = (b < a) == asc;
-    x[e] = swap ? b : a;
-    x[e + J] = swap ? a : b;
+    x[e] = b < a ? b : a;
+    x[e + J] = b < a ? a : b;
   }
 }
 
-// Stage (k, j) with E <= j < 64 E: lane l pairs with lane l ^ M, M = j / E.
+// Mirror step E < k <= 64 E: position (lane, e) pairs with (lane ^ M,
+// E - 1 - e), M = k / E - 1.
+template <int E, int M>
+__device__ __forceinline__ void mirror_across_lanes(unsigned long long (&x)[E],
+                                                    int lane) {
+  const bool keep_min = (lane & ((M + 1) >> 1)) == 0;
+  if constexpr (E == 1) {
+    keep(x[0], xor_lane<M>(x[0]), keep_min);
+  } else {
+    // Mirrored pairs (e, E - 1 - e) together: two temporaries live at once.
+#pragma unroll
+    for (int e = 0; e < E / 2; ++e) {
+      const unsigned long long ya = xor_lane<M>(x[E - 1 - e]);
+      const unsigned long long yb = xor_lane<M>(x[e]);
+      keep(x[e], ya, keep_min);
+      keep(x[E - 1 - e], yb, keep_min);
+    }
+  }
+}
+
+// Distance E <= j < 64 E: lane l pairs with lane l ^ M, M = j / E.
 template <int E, int M>
 __device__ __forceinline__ void stage_across_lanes(unsigned long long (&x)[E],
-                                                   int base, int k, int lane) {
-  const bool asc = (base & k) == 0;
-  const bool keep_min = ((lane & M) == 0) == asc;
+                                                   int lane) {
+  const bool keep_min = (lane & M) == 0;
 #pragma unroll
-  for (int e = 0; e < E; ++e) {
-    const unsigned long long y = xor_lane<M>(x[e], lane);
-    x[e] = ((y < x[e]) == keep_min) ? y : x[e];
+  for (int e = 0; e < E; ++e) keep(x[e], xor_lane<M>(x[e]), keep_min);
+}
+
+// A stage whose partner lies in another wave (p ^ m with m >= 64 E), through
+// LDS.  half is the bit of p that decides which side keeps the minimum.
+template <int E>
+__device__ __forceinline__ void stage_lds(unsigned long long (&x)[E], int base,
+                                          int m, int half, bool active,
+                                          bool work, unsigned long long* buf) {
+  __syncthreads();
+  if (active) {
+#pragma unroll
+    for (int e = 0; e < E; ++e) buf[base + e] = x[e];
+  }
+  __syncthreads();
+  if (work) {
+    const bool keep_min = (base & half) == 0;
+#pragma unroll
+    for (int e = 0; e < E; ++e) keep(x[e], buf[(base + e) ^ m], keep_min);
   }
 }
 
-// Bitonic sort of P2 <= 64 E * nw keys held E per lane by the first nw waves
-// of the workgroup (all waves reach the barriers of cross-wave stages).
+// Sorts the first L of P2 <= 64 E nw keys held E per lane by the first nw
+// waves of the workgroup (all waves reach the barriers of cross-wave stages);
+// positions >= L hold all-ones keys.
 template <int E>
-__device__ void sort_in_registers(unsigned long long (&x)[E], int P2, int nw,
-                                  unsigned long long* buf) {
+__device__ void sort_in_registers(unsigned long long (&x)[E], int L, int P2,
+                                  int nw, unsigned long long* buf) {
   const int tid = threadIdx.x, lane = tid & 63;
   const bool active = (tid >> 6) < nw;
+  const bool work = active && (tid >> 6) * 64 * E < L;
   const int base = tid * E;
   for (int k = 2; k <= P2; k <<= 1) {
-    for (int j = k >> 1; j > 0; j >>= 1) {
+    if (k > 64 * E) {
+      stage_lds<E>(x, base, k - 1, k >> 1, active, work, buf);
+    } else if (work) {
+      if (k <= E) {
+        if constexpr (E >= 2) { if (k == 2) mirror_in_lane<E, 2>(x); }
+        if constexpr (E >= 4) { if (k == 4) mirror_in_lane<E, 4>(x); }
+        if constexpr (E >= 8) { if (k == 8) mirror_in_lane<E, 8>(x); }
+        if constexpr (E >= 16) { if (k == 16) mirror_in_lane<E, 16>(x); }
+      } else {
+        switch (k / E) {
+          case 2: mirror_across_lanes<E, 1>(x, lane); break;
+          case 4: mirror_across_lanes<E, 3>(x, lane); break;
+          case 8: mirror_across_lanes<E, 7>(x, lane); break;
+          case 16: mirror_across_lanes<E, 15>(x, lane); break;
+          case 32: mirror_across_lanes<E, 31>(x, lane); break;
+          default: mirror_across_lanes<E, 63>(x, lane); break;
+        }
+      }
+    }
+    for (int j = k >> 2; j > 0; j >>= 1) {
       if (j >= 64 * E) {
-        __syncthreads();
-        if (active) {
-#pragma unroll
-          for (int e = 0; e < E; ++e) buf[base + e] = x[e];
-        }
-        __syncthreads();
-        if (active) {
-          const bool asc = (base & k) == 0;
-          const bool keep_min = ((base & j) == 0) == asc;
-#pragma unroll
-          for (int e = 0; e < E; ++e) {
-            const unsigned long long y = buf[(base + e) ^ j];
-            x[e] = ((y < x[e]) == keep_min) ? y : x[e];
-          }
-        }
+        stage_lds<E>(x, base, j, j, active, work, buf);
+      } else if (!work) {
+        continue;
       } else if (j >= E) {
-        if (!active) continue;
         switch (j / E) {
-          case 1: stage_across_lanes<E, 1>(x, base, k, lane); break;
-          case 2: stage_across_lanes<E, 2>(x, base, k, lane); break;
-          case 4: stage_across_lanes<E, 4>(x, base, k, lane); break;
-          case 8: stage_across_lanes<E, 8>(x, base, k, lane); break;
-          case 16: stage_across_lanes<E, 16>(x, base, k, lane); break;
-          default: stage_across_lanes<E, 32>(x, base, k, lane); break;
+          case 1: stage_across_lanes<E, 1>(x, lane); break;
+          case 2: stage_across_lanes<E, 2>(x, lane); break;
+          case 4: stage_across_lanes<E, 4>(x, lane); break;
+          case 8: stage_across_lanes<E, 8>(x, lane); break;
+          case 16: stage_across_lanes<E, 16>(x, lane); break;
+          default: stage_across_lanes<E, 32>(x, lane); break;
         }
       } else {
-        if (!active) continue;
-        if constexpr (E > 8) { if (j == 8) { stage_in_lane<E, 8>(x, base, k); continue; } }
-        if constexpr (E > 4) { if (j == 4) { stage_in_lane<E, 4>(x, base, k); continue; } }
-        if constexpr (E > 2) { if (j == 2) { stage_in_lane<E, 2>(x, base, k); continue; } }
-        if constexpr (E > 1) { if (j == 1) { stage_in_lane<E, 1>(x, base, k); continue; } }
+        if constexpr (E > 8) { if (j == 8) { stage_in_lane<E, 8>(x); continue; } }
+        if constexpr (E > 4) { if (j == 4) { stage_in_lane<E, 4>(x); continue; } }
+        if constexpr (E > 2) { if (j == 2) { stage_in_lane<E, 2>(x); continue; } }
+        if constexpr (E > 1) { if (j == 1) { stage_in_lane<E, 1>(x); continue; } }
       }
     }
   }
@@ -182,7 +255,7 @@ __device__ void sort_tile(const SortArgs& a, int t, long long s, int L, int P2,
 #pragma unroll
   for (int e = 0; e < E; ++e)
     x[e] = (active && base + e < L) ? a.keys_in[s + base + e] : ~0ull;
-  sort_in_registers<E>(x, P2, nw, buf);
+  sort_in_registers<E>(x, L, P2, nw, buf);
   if (!active) return;
 #pragma unroll
   for (int e = 0; e < E; ++e) {
@@ -196,7 +269,8 @@ __device__ void sort_tile(const SortArgs& a, int t, long long s, int L, int P2,
 }
 
 template <int kCap>
-__global__ __launch_bounds__(256) void k_sort_tiles(SortArgs a) {
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(5)))
+void k_sort_tiles(SortArgs a) {
   static_assert(kCap == 4 * 64 * 16, "four waves of 16 keys per lane");
   __shared__ unsigned long long buf[kCap];
   const int t = (int)a.order[blockIdx.x];

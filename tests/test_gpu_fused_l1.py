@@ -2,7 +2,8 @@
 (gs_render_bwd_l1) against gs_loss_l1 followed by gs_render_bwd, and against
 the oracle: the same per-pixel gradient, so parameter gradients agree to the
 order of the atomic sums; the loss and per-view squared errors agree to the
-summation order (|r| summed in FP32 per thread, then FP64, on both sides)."""
+summation order (|r| summed in FP32 per thread, then FP64, on both sides),
+and the fused call's sums, taken in a fixed tile order, repeat bit for bit."""
 import numpy as np
 import pytest
 import torch
@@ -128,3 +129,26 @@ def test_fused_full_size_window():
     np.testing.assert_allclose(sb, sa, rtol=1e-12)
     scale = np.abs(ga).max(axis=1, keepdims=True)
     assert np.all(np.abs(gb - ga) <= 1e-4 * scale + 1e-12)
+
+
+def test_fused_loss_is_reproducible_and_accumulates():
+    """The loss is summed tile by tile in tile order, so repeated calls give
+    the same bits; both outputs add to what the caller's buffers hold."""
+    w = _views(synth.tiny_scene(63, n=800, width=150, height=97, f=90.0), 4)
+    print("case fused l1 reproducible", flush=True)
+    params, rast = gpu_forward(w, 16, 256)
+    tgt = torch.from_numpy(np.random.default_rng(5).uniform(
+        size=tuple(rast.rgb.shape)).astype(np.float32)).cuda()
+    got = []
+    for start in (0.0, 0.0, 2.5):
+        grad = params.zeros_like()
+        loss = torch.full((1,), start, dtype=torch.float64, device="cuda")
+        sq = torch.full((4,), start, dtype=torch.float64, device="cuda")
+        R.render_bwd_l1(rast.ws, params, rast.settings, rast.rgb, tgt, 0.5,
+                        rast.T, rast.nlast, grad, loss, sq)
+        torch.cuda.synchronize()
+        got.append((float(loss), sq.cpu().numpy()))
+    assert got[0][0] == got[1][0]
+    np.testing.assert_array_equal(got[0][1], got[1][1])
+    assert got[2][0] == pytest.approx(2.5 + got[0][0], rel=1e-15)
+    np.testing.assert_allclose(got[2][1], 2.5 + got[0][1], rtol=1e-15)
