@@ -197,8 +197,8 @@ __device__ inline void make_view(const gs_camera& cam, double mx, double my,
 // place of the forward's correctly rounded divisions: the backward only has
 // to be accurate, not reproducible bit for bit.
 __device__ inline void make_view_grad(const gs_camera& cam, double mx,
-                                      double my, double mz, const Shape& S,
-                                      View& P) {
+                                      double my, double mz, const double* Sig,
+                                      bool shape_ok, View& P) {
   for (int i = 0; i < 9; ++i) P.W[i] = (double)cam.R[i];
   P.fx = (double)cam.fx;
   P.fy = (double)cam.fy;
@@ -208,7 +208,7 @@ __device__ inline void make_view_grad(const gs_camera& cam, double mx,
   P.t[2] = ((W[6] * mx + W[7] * my) + W[8] * mz) + (double)cam.t[2];
   const double tx = P.t[0], ty = P.t[1], tz = P.t[2];
   P.ok = isfinite(tx) && isfinite(ty) && isfinite(tz) &&
-         tz > (double)cam.near_z && S.ok;
+         tz > (double)cam.near_z && shape_ok;
   if (!P.ok) return;
   const double itz = 1.0 / tz;
   P.limx = 0.65 * (double)cam.width / P.fx;
@@ -231,7 +231,7 @@ __device__ inline void make_view_grad(const gs_camera& cam, double mx,
   double U[6];
   for (int i = 0; i < 2; ++i)
     for (int j = 0; j < 3; ++j)
-      U[3 * i + j] = T_dot(P.T + 3 * i, S.Sig, j);
+      U[3 * i + j] = T_dot(P.T + 3 * i, Sig, j);
   P.a = U[0] * P.T[0] + U[1] * P.T[1] + U[2] * P.T[2] + 0.3;
   P.b = U[0] * P.T[3] + U[1] * P.T[4] + U[2] * P.T[5];
   P.c = U[3] * P.T[3] + U[4] * P.T[4] + U[5] * P.T[5] + 0.3;
@@ -367,11 +367,21 @@ __global__ __launch_bounds__(256) void k_project_bwd(ProjBwdArgs a) {
   const int n = min(*a.n_dev, a.cap);
   if (g >= n) return;
   const int cap = a.cap;
-  Shape S;
-  make_shape(a.lsc, a.quat, cap, g, S);
+  // Only Sigma stays live through the loop over the views; the rest of the
+  // shape chain is formed again after it.  Fewer registers per thread (about
+  // 150 instead of about 190) let three waves per SIMD instead of two hide
+  // the latency of the per-view FP64 chain.
+  double Sig[9];
+  bool shape_ok;
+  {
+    Shape S;
+    make_shape(a.lsc, a.quat, cap, g, S);
+    for (int i = 0; i < 9; ++i) Sig[i] = S.Sig[i];
+    shape_ok = S.ok;
+  }
   const double mx = a.mean[g], my = a.mean[cap + g], mz = a.mean[2 * cap + g];
   double dmu[3] = {0, 0, 0};
-  double dSig[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
+  double dS[6] = {0, 0, 0, 0, 0, 0};   // dSigma + dSigma^T, upper triangle
   for (int k = 0; k < a.V; ++k) {
     const size_t slot = (size_t)k * cap + g;
     if (a.tiles[slot] == 0) continue;
@@ -383,7 +393,7 @@ __global__ __launch_bounds__(256) void k_project_bwd(ProjBwdArgs a) {
     if (dpx == 0.0 && dpy == 0.0 && dA == 0.0 && dB == 0.0 && dC == 0.0)
       continue;
     View P;
-    make_view_grad(a.cams[k], mx, my, mz, S, P);
+    make_view_grad(a.cams[k], mx, my, mz, Sig, shape_ok, P);
     if (!P.ok) continue;
     // Conic -> dilated screen covariance (symmetric matrix gradient).
     const double Q[4] = {P.A, P.B, P.B, P.C};
@@ -399,17 +409,23 @@ __global__ __launch_bounds__(256) void k_project_bwd(ProjBwdArgs a) {
     G2[2] = -(Q[2] * X[0] + Q[3] * X[2]);
     G2[3] = -(Q[2] * X[1] + Q[3] * X[3]);
     const double* T = P.T;
-    // dSigma += T^T G2 T
-    for (int i = 0; i < 3; ++i)
-      for (int j = 0; j < 3; ++j)
-        dSig[3 * i + j] += T[i] * (G2[0] * T[j] + G2[1] * T[3 + j]) +
-                           T[3 + i] * (G2[2] * T[j] + G2[3] * T[3 + j]);
+    // dSigma += T^T G2 T, kept symmetrised: N + N^T with N = T^T G2 T.
+    double GT[6];   // G2 T
+    for (int j = 0; j < 3; ++j) {
+      GT[j] = G2[0] * T[j] + G2[1] * T[3 + j];
+      GT[3 + j] = G2[2] * T[j] + G2[3] * T[3 + j];
+    }
+    for (int u = 0; u < 6; ++u) {
+      const int i = kSigIdx[u] / 3, j = kSigIdx[u] % 3;
+      dS[u] += (T[i] * GT[j] + T[3 + i] * GT[3 + j]) +
+               (T[j] * GT[i] + T[3 + j] * GT[3 + i]);
+    }
     // dT = (G2 + G2^T) T Sigma
     double TS[6];
     for (int i = 0; i < 2; ++i)
       for (int j = 0; j < 3; ++j)
-        TS[3 * i + j] = T[3 * i] * S.Sig[j] + T[3 * i + 1] * S.Sig[3 + j] +
-                        T[3 * i + 2] * S.Sig[6 + j];
+        TS[3 * i + j] = T[3 * i] * Sig[j] + T[3 * i + 1] * Sig[3 + j] +
+                        T[3 * i + 2] * Sig[6 + j];
     double dT[6];
     for (int j = 0; j < 3; ++j) {
       dT[j] = (2.0 * G2[0]) * TS[j] + (G2[1] + G2[2]) * TS[3 + j];
@@ -440,13 +456,15 @@ __global__ __launch_bounds__(256) void k_project_bwd(ProjBwdArgs a) {
     for (int j = 0; j < 3; ++j)
       dmu[j] += W[j] * dt[0] + W[3 + j] * dt[1] + W[6 + j] * dt[2];
   }
-  // Shared shape chain: dM = 2 dSigma_sym M, with dSigma symmetrised.
+  // Shared shape chain: dM = (dSigma + dSigma^T) M.
+  Shape S;
+  make_shape(a.lsc, a.quat, cap, g, S);
+  constexpr int kSym[9] = {0, 1, 2, 1, 3, 4, 2, 4, 5};   // (i, m) -> dS slot
   double dM[9];
   for (int i = 0; i < 3; ++i)
     for (int j = 0; j < 3; ++j) {
       double acc = 0.0;
-      for (int m = 0; m < 3; ++m)
-        acc += (dSig[3 * i + m] + dSig[3 * m + i]) * S.M[3 * m + j];
+      for (int m = 0; m < 3; ++m) acc += dS[kSym[3 * i + m]] * S.M[3 * m + j];
       dM[3 * i + j] = acc;
     }
   double dR[9], ds[3] = {0, 0, 0};
