@@ -10,7 +10,8 @@ in for the paper's indoor sequences) and resident in HBM before timing.
 
 Prints one JSON line.  Extra fields: Mpix/s, per-kernel milliseconds, the
 roofline of the dominant kernel (credited FP32 VALU lane-operations from exact
-pair counts, against 256 CUs x 64 lanes x 2.4 GHz), and the CPU oracle timed
+pair counts, against the published FP32 vector peak: 157.3 TFLOP/s, i.e.
+78.6 T lane-operations/s with an FMA counted once), and the CPU oracle timed
 on a bounded sample of the same workload.
 """
 from __future__ import annotations
@@ -28,7 +29,10 @@ if ROOT not in sys.path:
 
 METRIC = ("mapping iters/s (fwd+bwd, 10-KF window, 1200×680, 300k "
           "Gaussians) + Mpix/s")
-PEAK_LANE_OPS = 256 * 64 * 2.4e9   # non-packed FP32 VALU lane-ops per second
+# Published FP32 vector peak, 157.3 TFLOP/s, in lane-operations (an FMA counts
+# once): 256 CUs x 128 FP32 lanes x 2.4 GHz.  Half of it is reached only with
+# packed (two-lane) FP32 instructions, which these kernels do not use.
+PEAK_LANE_OPS = 256 * 128 * 2.4e9
 # Credited FP32 VALU lane-operations per pair (what the method must compute):
 FWD_OPS = dict(examined=2, inbox=12, contributing=7)
 BWD_OPS = dict(revisit=14, contributing=45)

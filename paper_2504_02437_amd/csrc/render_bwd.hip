@@ -237,17 +237,21 @@ __global__ __launch_bounds__(NT) void k_render_bwd(BwdArgs a) {
         const bool ok = in_u && rlo <= p && p <= rhi && pos < last[p] &&
                         !(e2 > 0.f) && al >= amin;
         hit |= ok;
-        const float rom = __builtin_amdgcn_rcpf(1.f - al);
+        // A pair that is not admitted takes alpha 0: 1 / (1 - 0) is exactly
+        // 1, so T, the weight and the running colour sum below come out
+        // unchanged without a select each.
+        const float alo = ok ? al : 0.f;
+        const float rom = __builtin_amdgcn_rcpf(1.f - alo);
         const float Ti = T[p] * rom;                 // T_i
-        T[p] = ok ? Ti : T[p];
-        const float w = ok ? al * Ti : 0.f;
+        T[p] = Ti;
+        const float w = alo * Ti;
         d_r = fmaf(w, g0[p], d_r);
         d_g = fmaf(w, g1[p], d_g);
         d_b = fmaf(w, g2[p], d_b);
         const float cg = fmaf(eb.z, g0[p], fmaf(eb.w, g1[p], ec.x * g2[p]));
         const float diff = cg - Sg[p];
         const float dal = fmaf(Ti, diff, -(Tb[p] * rom));
-        Sg[p] = ok ? fmaf(al, diff, Sg[p]) : Sg[p];
+        Sg[p] = fmaf(alo, diff, Sg[p]);
         // Clamped alpha has no shape or opacity gradient.
         const float dalm = (ok && !(oG > amax)) ? dal : 0.f;
         const float dpw = dalm * al;
