@@ -171,22 +171,30 @@ __device__ __forceinline__ void stage_across_lanes(unsigned long long (&x)[E],
   for (int e = 0; e < E; ++e) keep(x[e], xor_lane<M>(x[e]), keep_min);
 }
 
-// A stage whose partner lies in another wave (p ^ m with m >= 64 E), through
-// LDS.  half is the bit of p that decides which side keeps the minimum.
+// A stage whose partner lies in another wave (position p ^ m with m >= 64 E),
+// through LDS.  The buffer is element-major (element e of thread t at
+// buf[e * 256 + t]), so every store and every load of a wave touches 64
+// consecutive slots in some lane order and no two lanes share a bank.
+// m = ml E + ex with ex = 0 (distance j) or E - 1 (mirror step): the partner
+// of element e of thread t is element e ^ ex of thread t ^ ml.  half is the
+// bit of p that decides which side keeps the minimum.
 template <int E>
-__device__ __forceinline__ void stage_lds(unsigned long long (&x)[E], int base,
-                                          int m, int half, bool active,
-                                          bool work, unsigned long long* buf) {
+__device__ __forceinline__ void stage_lds(unsigned long long (&x)[E], int m,
+                                          int half, bool active, bool work,
+                                          unsigned long long* buf) {
+  const int tid = threadIdx.x;
+  const int ml = m / E, ex = m % E;
   __syncthreads();
   if (active) {
 #pragma unroll
-    for (int e = 0; e < E; ++e) buf[base + e] = x[e];
+    for (int e = 0; e < E; ++e) buf[e * 256 + tid] = x[e];
   }
   __syncthreads();
   if (work) {
-    const bool keep_min = (base & half) == 0;
+    const bool keep_min = ((tid * E) & half) == 0;
+    const unsigned long long* src = buf + (tid ^ ml);
 #pragma unroll
-    for (int e = 0; e < E; ++e) keep(x[e], buf[(base + e) ^ m], keep_min);
+    for (int e = 0; e < E; ++e) keep(x[e], src[(e ^ ex) * 256], keep_min);
   }
 }
 
@@ -199,10 +207,9 @@ __device__ void sort_in_registers(unsigned long long (&x)[E], int L, int P2,
   const int tid = threadIdx.x, lane = tid & 63;
   const bool active = (tid >> 6) < nw;
   const bool work = active && (tid >> 6) * 64 * E < L;
-  const int base = tid * E;
   for (int k = 2; k <= P2; k <<= 1) {
     if (k > 64 * E) {
-      stage_lds<E>(x, base, k - 1, k >> 1, active, work, buf);
+      stage_lds<E>(x, k - 1, k >> 1, active, work, buf);
     } else if (work) {
       if (k <= E) {
         if constexpr (E >= 2) { if (k == 2) mirror_in_lane<E, 2>(x); }
@@ -222,7 +229,7 @@ __device__ void sort_in_registers(unsigned long long (&x)[E], int L, int P2,
     }
     for (int j = k >> 2; j > 0; j >>= 1) {
       if (j >= 64 * E) {
-        stage_lds<E>(x, base, j, j, active, work, buf);
+        stage_lds<E>(x, j, j, active, work, buf);
       } else if (!work) {
         continue;
       } else if (j >= E) {
