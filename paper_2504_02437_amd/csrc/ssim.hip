@@ -66,9 +66,11 @@ __device__ inline float block_sum(float v, float* part) {
   return s;
 }
 
-// One plane per grid row; each workgroup takes every gridDim.x-th tile of
-// its plane, so the loss and the per-view SSIM take one FP64 atomic per
-// workgroup rather than per tile (atomics on one address serialise).
+// Both passes: one plane per grid row; each workgroup takes every
+// gridDim.x-th tile of its plane, with the next tile's inputs loaded while
+// the current one is computed.  In the statistics pass the loss and the
+// per-view SSIM then take one FP64 atomic per workgroup rather than per tile
+// (atomics on one address serialise).
 __global__ __launch_bounds__(kNT) void k_ssim_stats(SsimArgs a) {
   __shared__ float sx[kIH][kSW], sy[kIH][kSW];
   __shared__ float hs[5][kIH][kHW];
@@ -88,13 +90,12 @@ __global__ __launch_bounds__(kNT) void k_ssim_stats(SsimArgs a) {
   const float scale = -a.lam * n_inv;
   float ssum = 0.f, l1sum = 0.f;
   double sqsum = 0.0;
-  for (int tile = blockIdx.x; tile < tiles; tile += gridDim.x) {
+  // The halo region of a tile is loaded into registers one tile ahead: the
+  // loads of the next tile are in flight while this one is computed.
+  constexpr int kLoads = (kIH * kIW + kNT - 1) / kNT;
+  float lx[kLoads], ly[kLoads];
+  auto fetch = [&](int tile) {
     const int ou = (tile % tiles_x) * kTW, ov = (tile / tiles_x) * kTH;
-    __syncthreads();   // the previous tile's LDS reads are done
-    // All loads of the halo region are issued before the first LDS write, so
-    // their latencies overlap.
-    constexpr int kLoads = (kIH * kIW + kNT - 1) / kNT;
-    float lx[kLoads], ly[kLoads];
 #pragma unroll
     for (int j = 0; j < kLoads; ++j) {
       const int i = tid + j * kNT;
@@ -104,6 +105,11 @@ __global__ __launch_bounds__(kNT) void k_ssim_stats(SsimArgs a) {
       lx[j] = in ? X[(size_t)v * W + u] : 0.f;
       ly[j] = in ? Y[(size_t)v * W + u] : 0.f;
     }
+  };
+  if ((int)blockIdx.x < tiles) fetch(blockIdx.x);
+  for (int tile = blockIdx.x; tile < tiles; tile += gridDim.x) {
+    const int ou = (tile % tiles_x) * kTW, ov = (tile / tiles_x) * kTH;
+    __syncthreads();   // the previous tile's LDS reads are done
 #pragma unroll
     for (int j = 0; j < kLoads; ++j) {
       const int i = tid + j * kNT;
@@ -114,6 +120,7 @@ __global__ __launch_bounds__(kNT) void k_ssim_stats(SsimArgs a) {
       }
     }
     __syncthreads();
+    if (tile + (int)gridDim.x < tiles) fetch(tile + gridDim.x);
     // Horizontal pass: five sums for every row of the halo region.
     for (int it = tid; it < kIH * (kTW / kRunX); it += kNT) {
       const int r = it / (kTW / kRunX), c0 = (it % (kTW / kRunX)) * kRunX;
@@ -217,93 +224,113 @@ __global__ __launch_bounds__(kNT) void k_ssim_grad(SsimArgs a) {
   __shared__ float sd[3][kIH][kSW];
   __shared__ float hs[3][kIH][kHW];
   const int tid = threadIdx.x;
-  const int plane = blockIdx.z;
+  const int plane = blockIdx.y;
   const int H = a.H, W = a.W;
   const size_t HW = (size_t)H * W;
   const size_t PL = (size_t)a.V * 3 * HW;
   const float* D = a.scratch + (size_t)plane * HW;
-  const int ou = blockIdx.x * kTW, ov = blockIdx.y * kTH;
+  const int tiles_x = (W + kTW - 1) / kTW;
+  const int tiles = tiles_x * ((H + kTH - 1) / kTH);
   float w[2 * kR + 1];
 #pragma unroll
   for (int i = 0; i < 2 * kR + 1; ++i) w[i] = a.w[i];
-  // This thread's output pixels: their x, y and dL are fetched up front.
+  // This thread's output pixels: column c, rows r0 .. r0 + kRunY - 1.
   const int c = tid % kTW, r0 = (tid / kTW) * kRunY;
-  const int u = ou + c;
   const float* X = a.x + (size_t)plane * HW;
   const float* Y = a.y + (size_t)plane * HW;
   float* G = a.dL + (size_t)plane * HW;
-  float xo[kRunY], yo[kRunY], go[kRunY];
-#pragma unroll
-  for (int o = 0; o < kRunY; ++o) {
-    const int v = ov + r0 + o;
-    const bool in = u < W && v < H;
-    const size_t p = (size_t)v * W + u;
-    xo[o] = in ? X[p] : 0.f;
-    yo[o] = in ? Y[p] : 0.f;
-    if (a.l1) {
-      const float d = xo[o] - yo[o];
-      go[o] = d > 0.f ? a.l1_scale : (d < 0.f ? -a.l1_scale : 0.f);
-    } else {
-      go[o] = in ? G[p] : 0.f;
-    }
-  }
+  // A tile's inputs (the derivative maps over the halo region, and x, y and
+  // dL at this thread's pixels) are loaded into registers one tile ahead.
   constexpr int kLoads = (kIH * kIW + kNT - 1) / kNT;
   float ld[3][kLoads];
+  float xo[kRunY], yo[kRunY], go[kRunY];
+  auto fetch = [&](int tile) {
+    const int ou = (tile % tiles_x) * kTW, ov = (tile / tiles_x) * kTH;
+    const int u = ou + c;
 #pragma unroll
-  for (int j = 0; j < kLoads; ++j) {
-    const int i = tid + j * kNT;
-    const int r = i / kIW, c = i - r * kIW;
-    const int u = ou - kR + c, v = ov - kR + r;
-    const bool in = i < kIH * kIW && u >= 0 && u < W && v >= 0 && v < H;
-    const size_t p = (size_t)v * W + u;
-#pragma unroll
-    for (int q = 0; q < 3; ++q) ld[q][j] = in ? D[q * PL + p] : 0.f;
-  }
-#pragma unroll
-  for (int j = 0; j < kLoads; ++j) {
-    const int i = tid + j * kNT;
-    if (i < kIH * kIW) {
-      const int r = i / kIW, c = i - r * kIW;
-#pragma unroll
-      for (int q = 0; q < 3; ++q) sd[q][r][c] = ld[q][j];
+    for (int o = 0; o < kRunY; ++o) {
+      const int v = ov + r0 + o;
+      const bool in = u < W && v < H;
+      const size_t p = (size_t)v * W + u;
+      xo[o] = in ? X[p] : 0.f;
+      yo[o] = in ? Y[p] : 0.f;
+      go[o] = (in && !a.l1) ? G[p] : 0.f;
     }
-  }
-  __syncthreads();
-  for (int it = tid; it < kIH * (kTW / kRunX); it += kNT) {
-    const int r = it / (kTW / kRunX), c0 = (it % (kTW / kRunX)) * kRunX;
 #pragma unroll
-    for (int q = 0; q < 3; ++q) {
-      float pv[kRunX + 2 * kR];
+    for (int j = 0; j < kLoads; ++j) {
+      const int i = tid + j * kNT;
+      const int r = i / kIW, cc = i - r * kIW;
+      const int uu = ou - kR + cc, vv = ov - kR + r;
+      const bool in = i < kIH * kIW && uu >= 0 && uu < W && vv >= 0 && vv < H;
+      const size_t p = (size_t)vv * W + uu;
 #pragma unroll
-      for (int i = 0; i < kRunX + 2 * kR; ++i) pv[i] = sd[q][r][c0 + i];
+      for (int q = 0; q < 3; ++q) ld[q][j] = in ? D[q * PL + p] : 0.f;
+    }
+  };
+  if ((int)blockIdx.x < tiles) fetch(blockIdx.x);
+  for (int tile = blockIdx.x; tile < tiles; tile += gridDim.x) {
+    const int ou = (tile % tiles_x) * kTW, ov = (tile / tiles_x) * kTH;
+    const int u = ou + c;
+    float x0[kRunY], y0[kRunY], g0[kRunY];
 #pragma unroll
-      for (int o = 0; o < kRunX; ++o) {
-        float s = 0.f;
-#pragma unroll
-        for (int b = 0; b < 2 * kR + 1; ++b) s = fmaf(w[b], pv[o + b], s);
-        hs[q][r][c0 + o] = s;
+    for (int o = 0; o < kRunY; ++o) {
+      x0[o] = xo[o];
+      y0[o] = yo[o];
+      if (a.l1) {
+        const float d = xo[o] - yo[o];
+        g0[o] = d > 0.f ? a.l1_scale : (d < 0.f ? -a.l1_scale : 0.f);
+      } else {
+        g0[o] = go[o];
       }
     }
-  }
-  __syncthreads();
-  float col[3][kRunY + 2 * kR];
+    __syncthreads();   // the previous tile's LDS reads are done
 #pragma unroll
-  for (int q = 0; q < 3; ++q)
+    for (int j = 0; j < kLoads; ++j) {
+      const int i = tid + j * kNT;
+      if (i < kIH * kIW) {
+        const int r = i / kIW, cc = i - r * kIW;
 #pragma unroll
-    for (int i = 0; i < kRunY + 2 * kR; ++i) col[q][i] = hs[q][r0 + i][c];
-#pragma unroll
-  for (int o = 0; o < kRunY; ++o) {
-    float m[3];
-#pragma unroll
-    for (int q = 0; q < 3; ++q) {
-      float s = 0.f;
-#pragma unroll
-      for (int b = 0; b < 2 * kR + 1; ++b) s = fmaf(w[b], col[q][o + b], s);
-      m[q] = s;
+        for (int q = 0; q < 3; ++q) sd[q][r][cc] = ld[q][j];
+      }
     }
-    const int v = ov + r0 + o;
-    if (u >= W || v >= H) continue;
-    G[(size_t)v * W + u] = go[o] + (m[0] + 2.f * xo[o] * m[1] + yo[o] * m[2]);
+    __syncthreads();
+    if (tile + (int)gridDim.x < tiles) fetch(tile + gridDim.x);
+    for (int it = tid; it < kIH * (kTW / kRunX); it += kNT) {
+      const int r = it / (kTW / kRunX), c0 = (it % (kTW / kRunX)) * kRunX;
+#pragma unroll
+      for (int q = 0; q < 3; ++q) {
+        float pv[kRunX + 2 * kR];
+#pragma unroll
+        for (int i = 0; i < kRunX + 2 * kR; ++i) pv[i] = sd[q][r][c0 + i];
+#pragma unroll
+        for (int o = 0; o < kRunX; ++o) {
+          float s = 0.f;
+#pragma unroll
+          for (int b = 0; b < 2 * kR + 1; ++b) s = fmaf(w[b], pv[o + b], s);
+          hs[q][r][c0 + o] = s;
+        }
+      }
+    }
+    __syncthreads();
+    float col[3][kRunY + 2 * kR];
+#pragma unroll
+    for (int q = 0; q < 3; ++q)
+#pragma unroll
+      for (int i = 0; i < kRunY + 2 * kR; ++i) col[q][i] = hs[q][r0 + i][c];
+#pragma unroll
+    for (int o = 0; o < kRunY; ++o) {
+      float m[3];
+#pragma unroll
+      for (int q = 0; q < 3; ++q) {
+        float s = 0.f;
+#pragma unroll
+        for (int b = 0; b < 2 * kR + 1; ++b) s = fmaf(w[b], col[q][o + b], s);
+        m[q] = s;
+      }
+      const int v = ov + r0 + o;
+      if (u >= W || v >= H) continue;
+      G[(size_t)v * W + u] = g0[o] + (m[0] + 2.f * x0[o] * m[1] + y0[o] * m[2]);
+    }
   }
 }
 
@@ -350,7 +377,8 @@ hipError_t launch_loss_colour(const float* rgb, const float* target, int V,
                      st, a);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(k_ssim_grad, grid, dim3(kNT), 0, st, a);
+  hipLaunchKernelGGL(k_ssim_grad, dim3(min(tiles, 64), V * 3), dim3(kNT), 0,
+                     st, a);
   return hipGetLastError();
 }
 
