@@ -26,8 +26,8 @@ namespace {
 constexpr int kR = 5;                     // window radius (11 taps)
 constexpr int kTW = 64, kTH = 16;         // output tile
 constexpr int kIW = kTW + 2 * kR, kIH = kTH + 2 * kR;
-// LDS row strides padded so the lanes of a wave (8 rows x 8 runs) spread
-// over the banks in the horizontal pass.
+// LDS row strides padded so that the lanes of a half-wave in the horizontal
+// pass spread over the banks (hitem below).
 constexpr int kSW = kIW + 7;    // 81
 constexpr int kHW = kTW + 1;    // 65
 constexpr int kNT = 256;
@@ -55,6 +55,19 @@ struct SsimArgs {
   double l1_lam_inv;   // lam_l1 / (3HW) in FP64
   double* sqerr;       // [V], may be null
 };
+
+// Work item it of a horizontal pass -> (halo row r, first output column
+// c0).  The 32 lanes of a half-wave take 8 rows x 4 runs: with row strides
+// of 17 and 1 modulo 32 (kSW, kHW) their LDS reads and writes fall in 32
+// distinct banks.  Items with r >= kIH have no row.
+constexpr int kHItems = 64 * ((kIH + 7) / 8);
+static_assert(kTW / kRunX == 8 && kSW % 32 == 17 && kHW % 32 == 1,
+              "horizontal-pass lane layout");
+__device__ inline void hitem(int it, int& r, int& c0) {
+  const int g = it >> 6, l = it & 63;
+  r = ((l & 31) >> 2) + 8 * g;
+  c0 = ((l & 3) + 4 * (l >> 5)) * kRunX;
+}
 
 __device__ inline float block_sum(float v, float* part) {
   for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
@@ -122,8 +135,10 @@ __global__ __launch_bounds__(kNT) void k_ssim_stats(SsimArgs a) {
     __syncthreads();
     if (tile + (int)gridDim.x < tiles) fetch(tile + gridDim.x);
     // Horizontal pass: five sums for every row of the halo region.
-    for (int it = tid; it < kIH * (kTW / kRunX); it += kNT) {
-      const int r = it / (kTW / kRunX), c0 = (it % (kTW / kRunX)) * kRunX;
+    for (int it = tid; it < kHItems; it += kNT) {
+      int r, c0;
+      hitem(it, r, c0);
+      if (r >= kIH) continue;
       float px[kRunX + 2 * kR], py[kRunX + 2 * kR];
       float pxx[kRunX + 2 * kR], pyy[kRunX + 2 * kR], pxy[kRunX + 2 * kR];
 #pragma unroll
@@ -295,8 +310,10 @@ __global__ __launch_bounds__(kNT) void k_ssim_grad(SsimArgs a) {
     }
     __syncthreads();
     if (tile + (int)gridDim.x < tiles) fetch(tile + gridDim.x);
-    for (int it = tid; it < kIH * (kTW / kRunX); it += kNT) {
-      const int r = it / (kTW / kRunX), c0 = (it % (kTW / kRunX)) * kRunX;
+    for (int it = tid; it < kHItems; it += kNT) {
+      int r, c0;
+      hitem(it, r, c0);
+      if (r >= kIH) continue;
 #pragma unroll
       for (int q = 0; q < 3; ++q) {
         float pv[kRunX + 2 * kR];
