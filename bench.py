@@ -8,7 +8,8 @@ formed per pixel), projection backward and the Adam update, for all views of
 the window.  Inputs are synthetic (a room-shaped scene standing
 in for the paper's indoor sequences) and resident in HBM before timing.
 
-Prints one JSON line.  Extra fields: Mpix/s, per-kernel milliseconds, the
+Prints one JSON line.  Extra fields: Mpix/s, the p10/p50/p90 of 50 single
+graph replays (after the timed region), per-kernel milliseconds, the
 roofline of the dominant kernel (credited FP32 VALU lane-operations from exact
 pair counts, against the published FP32 vector peak: 157.3 TFLOP/s, i.e.
 78.6 T lane-operations/s with an FMA counted once), and the CPU oracle timed
@@ -355,6 +356,7 @@ def main():
             for k in names if ev[k]}
 
     ms_graph = None
+    dist = None
     if not args.no_graph:
         log("bench: capturing one iteration in a HIP graph")
         g = torch.cuda.CUDAGraph()
@@ -376,6 +378,17 @@ def main():
         torch.cuda.synchronize()
         ms_graph = a.elapsed_time(b) / args.steps
         log(f"bench: graph {ms_graph:.3f} ms/iteration, eager {ms_eager:.3f}")
+        # Spread of single replays, each between two events (after the timed
+        # region; not part of `value`).
+        evs = [torch.cuda.Event(enable_timing=True) for _ in range(51)]
+        evs[0].record()
+        for i in range(50):
+            g.replay()
+            evs[i + 1].record()
+        torch.cuda.synchronize()
+        per = np.array([evs[i].elapsed_time(evs[i + 1]) for i in range(50)])
+        dist = {"replays": 50,
+                **{f"p{q}": float(np.percentile(per, q)) for q in (10, 50, 90)}}
 
     # The paper's full colour loss (Eq. 10): 0.8 L1 + 0.2 (1 - SSIM), reported
     # beside the headline iteration (which uses the L1 term only).
@@ -577,6 +590,7 @@ def main():
                    "sh_degree": args.sh_degree},
         "mpix_per_s": V * W * H * iters / 1e6,
         "ms_per_step_eager": ms_eager,
+        "ms_per_replay": dist,
         "keys_per_iter": int(n_keys),
         "kernels_ms": kern,
         "pairs": cnt,
