@@ -164,6 +164,15 @@ __device__ inline void load_owner(const ScatterArgs& a, int k, int g, int& cnt,
   dbits = __float_as_uint(a.depth[slot]);
 }
 
+// Orders one wave's LDS accesses before and after this point.  The owner
+// table below is private to a wave: its lanes only need to see each other's
+// writes, not the other waves' (a block barrier would make the waves of a
+// workgroup wait for the slowest one).
+__device__ __forceinline__ void wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+}
+
 template <typename F>
 __device__ inline void wave_enumerate(WaveOwners& O, int lane, int cnt, int x0,
                                       int y0, int w, uint32_t g, uint32_t dbits,
@@ -175,7 +184,7 @@ __device__ inline void wave_enumerate(WaveOwners& O, int lane, int cnt, int x0,
   }
   O.incl[lane] = s; O.x0[lane] = x0; O.y0[lane] = y0; O.w[lane] = w;
   O.g[lane] = g; O.d[lane] = dbits;
-  __syncthreads();
+  wave_sync();
   const int total = __shfl(s, 63, 64);
   for (int b = 0; b < total; b += 64) {
     const int j = b + lane;
@@ -192,7 +201,7 @@ __device__ inline void wave_enumerate(WaveOwners& O, int lane, int cnt, int x0,
       f(ty * Tx + tx, O.g[lo], O.d[lo]);
     }
   }
-  __syncthreads();
+  wave_sync();   // the table is rewritten by the wave's next call
 }
 
 // Keys of one chunk (GPT Gaussians per thread, one view per block) per tile,
@@ -290,12 +299,19 @@ __global__ __launch_bounds__(256) void k_scatter_chunks(ScatterArgs a) {
   for (int i = tid; i < nb; i += 256) bins[i] = start[i] + C[i];
   __syncthreads();
   const int g0 = blockIdx.x * 256 * GPT;
+  // The owners of all GPT sub-chunks are loaded up front, so their latencies
+  // overlap.
+  int cnt[GPT], x0[GPT], y0[GPT], w[GPT];
+  uint32_t d[GPT];
+#pragma unroll
+  for (int sub = 0; sub < GPT; ++sub)
+    load_owner(a, k, g0 + sub * 256 + tid, cnt[sub], x0[sub], y0[sub], w[sub],
+               d[sub]);
+#pragma unroll
   for (int sub = 0; sub < GPT; ++sub) {
     const int g = g0 + sub * 256 + tid;
-    int cnt, x0, y0, w;
-    uint32_t d;
-    load_owner(a, k, g, cnt, x0, y0, w, d);
-    wave_enumerate(owners[wv], lane, cnt, x0, y0, w, (uint32_t)g, d, a.Tx,
+    wave_enumerate(owners[wv], lane, cnt[sub], x0[sub], y0[sub], w[sub],
+                   (uint32_t)g, d[sub], a.Tx,
                    [&](int t, uint32_t gg, uint32_t dd) {
                      const uint32_t pos = atomicAdd(&bins[t], 1u);
                      if ((long long)pos < a.key_cap)
