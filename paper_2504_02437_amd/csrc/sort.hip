@@ -17,11 +17,11 @@
 // bit log2 64E pairs two lanes of the same wave (DPP, swizzles or a lane
 // permute), and only the others - at most three merge steps per segment - go
 // through LDS with barriers.  Padding never moves in the all-ascending form,
-// so waves that hold only padding skip the compare-exchanges.  Longer segments (rare: a tile covered by more than kCap
-// Gaussians) sort in place in the unsorted key buffer, with a global-memory
-// bitonic network whose first comparator of every merge stage pairs mirrored
-// positions, so positions past the end act as +infinity without being
-// stored.
+// so waves that hold only padding skip the compare-exchanges.  Longer
+// segments (rare: a tile covered by more than kCap Gaussians) sort in place
+// in the unsorted key buffer, with a global-memory bitonic network in the
+// same all-ascending form, so positions past the end act as +infinity
+// without being stored.
 
 #include "gs_internal.h"
 
@@ -275,6 +275,8 @@ __device__ void sort_tile(const SortArgs& a, int t, long long s, int L, int P2,
   }
 }
 
+// At most 96 VGPRs (five waves per SIMD): the 32 KB LDS buffer also allows
+// five workgroups per CU.
 template <int kCap>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(5)))
 void k_sort_tiles(SortArgs a) {
