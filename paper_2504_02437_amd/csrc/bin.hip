@@ -268,20 +268,36 @@ __global__ __launch_bounds__(1024) void k_chunk_scan(ChunkScanArgs a) {
   const int sl = (nch + 15) / 16;
   const int c0 = min(nch, seg * sl), c1 = min(nch, c0 + sl);
   uint32_t* C = a.chunk_counts + (size_t)k * nch * nb;
+  // The first kReg counts of the segment stay in registers between the two
+  // passes, so the offsets are stored without a load before each store.
+  constexpr int kReg = 32;
+  uint32_t v[kReg];
   uint32_t sum = 0;
+#pragma unroll
+  for (int j = 0; j < kReg; ++j) {
+    const int c = c0 + j;
+    v[j] = (t < nb && c < c1) ? C[(size_t)c * nb + t] : 0u;
+    sum += v[j];
+  }
   if (t < nb)
-    for (int c = c0; c < c1; ++c) sum += C[(size_t)c * nb + t];
+    for (int c = c0 + kReg; c < c1; ++c) sum += C[(size_t)c * nb + t];
   part[seg][tl] = sum;
   __syncthreads();
   uint32_t run = 0;
   for (int s2 = 0; s2 < seg; ++s2) run += part[s2][tl];
   if (t >= nb) return;
   if (seg == 15) a.counts[(size_t)k * nb + t] = run + sum;
-  for (int c = c0; c < c1; ++c) {
+#pragma unroll
+  for (int j = 0; j < kReg; ++j) {
+    const int c = c0 + j;
+    if (c < c1) C[(size_t)c * nb + t] = run;
+    run += v[j];
+  }
+  for (int c = c0 + kReg; c < c1; ++c) {
     const size_t i = (size_t)c * nb + t;
-    const uint32_t v = C[i];
+    const uint32_t x = C[i];
     C[i] = run;
-    run += v;
+    run += x;
   }
 }
 
