@@ -80,7 +80,10 @@ extern "C" {
  * n_dev is a device int32 holding the live count, so a captured graph stays
  * valid while insertion grows the map.  The same struct describes gradient
  * and optimiser-moment arrays of the same layout (their n_dev may be NULL;
- * their sh_degree must equal the parameters'). */
+ * their sh_degree must equal the parameters').  Parameter, gradient and
+ * moment arrays passed to one call must not share memory: every call that
+ * takes two of them returns GS_E_INVALID, before any launch, when their rows
+ * overlap. */
 #define GS_SH_MAX_DEGREE 3
 #define GS_SH_ROWS(d) (3 * (((d) + 1) * ((d) + 1) - 1))
 typedef struct gs_params {

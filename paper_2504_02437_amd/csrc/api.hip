@@ -81,6 +81,39 @@ static int same_layout(const gs_params* p, const gs_params* q, const char* what)
   return GS_OK;
 }
 
+// Byte ranges of a parameter set's rows (empty for a NULL row).
+static void row_ranges(const gs_params* p, uintptr_t (&r)[6][2]) {
+  const size_t c = (size_t)(p->capacity > 0 ? p->capacity : 0) * sizeof(float);
+  const void* ptr[6] = {p->mean, p->log_scale, p->quat, p->opacity_logit,
+                        p->rgb, p->sh_degree > 0 ? p->sh : nullptr};
+  const size_t rows[6] = {3, 3, 4, 1, 3,
+                          (size_t)(p->sh_degree > 0 ? GS_SH_ROWS(p->sh_degree)
+                                                    : 0)};
+  for (int i = 0; i < 6; ++i) {
+    r[i][0] = (uintptr_t)ptr[i];
+    r[i][1] = ptr[i] ? r[i][0] + rows[i] * c : r[i][0];
+  }
+}
+
+// Parameters, gradients and moments are read and written in the same
+// kernels, one thread per Gaussian and row: two of them must not share
+// memory.
+static int disjoint(const gs_params* p, const char* pw, const gs_params* q,
+                    const char* qw) {
+  if (!p || !q) return GS_OK;
+  uintptr_t a[6][2], b[6][2];
+  row_ranges(p, a);
+  row_ranges(q, b);
+  for (int i = 0; i < 6; ++i)
+    for (int j = 0; j < 6; ++j)
+      if (a[i][0] < a[i][1] && b[j][0] < b[j][1] && a[i][0] < b[j][1] &&
+          b[j][0] < a[i][1]) {
+        set_error("%s and %s share memory", pw, qw);
+        return GS_E_INVALID;
+      }
+  return GS_OK;
+}
+
 static size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 
 static int make_layout(const gs_geometry* g, Layout& L, int& tx, int& ty) {
@@ -340,6 +373,9 @@ int gs_densify(gs_params* params, gs_params* adam_m, gs_params* adam_v,
   }
   if (int rc = same_layout(params, adam_m, "adam_m")) return rc;
   if (int rc = same_layout(params, adam_v, "adam_v")) return rc;
+  if (int rc = disjoint(params, "params", adam_m, "adam_m")) return rc;
+  if (int rc = disjoint(params, "params", adam_v, "adam_v")) return rc;
+  if (int rc = disjoint(adam_m, "adam_m", adam_v, "adam_v")) return rc;
   if (!xi || !scratch || (n_pixels > 0 && !dom)) { set_error("an argument is NULL"); return GS_E_INVALID; }
   if (n_pixels < 0 || sigma < 0) { set_error("need n_pixels >= 0 and sigma >= 0"); return GS_E_INVALID; }
   return finish(launch_densify(params, adam_m, adam_v, dom, n_pixels, sigma, xi,
@@ -381,6 +417,7 @@ int gs_render_bwd(gs_workspace* ws, const gs_params* params,
     return GS_E_CAPACITY;
   }
   if (int rc = same_layout(params, grad, "grad")) return rc;
+  if (int rc = disjoint(params, "params", grad, "grad")) return rc;
   return finish(launch_render_bwd(ws, s, dL_drgb, T_final, n_last, grad->rgb,
                                   params->sh_degree > 0, nullptr,
                                   (hipStream_t)stream),
@@ -408,6 +445,7 @@ int gs_render_bwd_l1(gs_workspace* ws, const gs_params* params,
     return GS_E_CAPACITY;
   }
   if (int rc = same_layout(params, grad, "grad")) return rc;
+  if (int rc = disjoint(params, "params", grad, "grad")) return rc;
   const L1Fused l1{out_rgb, target, lambda, loss_dev, sqerr_dev};
   return finish(launch_render_bwd(ws, s, nullptr, T_final, n_last, grad->rgb,
                                   params->sh_degree > 0, &l1,
@@ -427,6 +465,7 @@ int gs_project_bwd(gs_workspace* ws, const gs_params* params,
     return GS_E_CAPACITY;
   }
   if (int rc = same_layout(params, grad, "grad")) return rc;
+  if (int rc = disjoint(params, "params", grad, "grad")) return rc;
   hipStream_t st = (hipStream_t)stream;
   hipError_t e = launch_project_bwd(ws, params, cams, grad, st);
   if (e != hipSuccess) return finish(e, "project_bwd");
@@ -479,6 +518,7 @@ int gs_planar_reg(const gs_params* params, float lambda, float floor_,
   if (int rc = validate_params(params, "params")) return rc;
   if (!grad || !grad->log_scale || !loss_dev || !params->n_dev) { set_error("an argument is NULL"); return GS_E_INVALID; }
   if (grad->capacity != params->capacity) { set_error("capacities differ"); return GS_E_CAPACITY; }
+  if (int rc = disjoint(params, "params", grad, "grad")) return rc;
   return finish(launch_planar_reg(params, lambda, floor_, grad, loss_dev,
                                   (hipStream_t)stream), "planar_reg");
 }
@@ -499,8 +539,14 @@ int gs_adam(gs_params* params, const gs_params* grad, gs_params* m,
     return GS_E_CAPACITY;
   }
   if (int rc = same_layout(params, grad, "grad")) return rc;
+  if (int rc = disjoint(params, "params", grad, "grad")) return rc;
   if (int rc = same_layout(params, m, "m")) return rc;
   if (int rc = same_layout(params, v, "v")) return rc;
+  const gs_params* all[4] = {params, grad, m, v};
+  const char* names[4] = {"params", "grad", "m", "v"};
+  for (int i = 0; i < 4; ++i)
+    for (int j = i + 1; j < 4; ++j)
+      if (int rc = disjoint(all[i], names[i], all[j], names[j])) return rc;
   return finish(launch_adam(params, grad, m, v, lr, beta1, beta2, eps, step,
                             step_dev, (hipStream_t)stream), "adam");
 }
@@ -534,6 +580,9 @@ int gs_insert_gaussians(gs_params* params, gs_params* adam_m, gs_params* adam_v,
     if (int rc = validate_params(adam_v, "adam_v")) return rc;
     if (int rc = same_layout(params, adam_v, "adam_v")) return rc;
   }
+  if (int rc = disjoint(params, "params", adam_m, "adam_m")) return rc;
+  if (int rc = disjoint(params, "params", adam_v, "adam_v")) return rc;
+  if (int rc = disjoint(adam_m, "adam_m", adam_v, "adam_v")) return rc;
   return finish(launch_insert(params, adam_m, adam_v, cam, width, height, kf_rgb,
                               kf_T_final, pts_uvd, n_pts, alpha_skip, centre_only,
                               mlp_out, n_inserted_dev, status_dev,
@@ -570,6 +619,9 @@ int gs_insert_distance(gs_params* params, gs_params* adam_m,
     if (int rc = validate_params(adam_v, "adam_v")) return rc;
     if (int rc = same_layout(params, adam_v, "adam_v")) return rc;
   }
+  if (int rc = disjoint(params, "params", adam_m, "adam_m")) return rc;
+  if (int rc = disjoint(params, "params", adam_v, "adam_v")) return rc;
+  if (int rc = disjoint(adam_m, "adam_m", adam_v, "adam_v")) return rc;
   return finish(launch_insert_distance(params, adam_m, adam_v, cam, width,
                                        height, kf_rgb, pts_uvd, n_pts, tau,
                                        centre_only, mlp_out,

@@ -139,3 +139,41 @@ def test_params_struct_layout():
     """gs_params: six pointers, capacity, sh_degree, coefficient pointer."""
     assert C.sizeof(L.gs_params) == 64
     assert L.gs_params.sh_degree.offset == 52 and L.gs_params.sh.offset == 56
+
+
+def test_parameters_gradients_and_moments_must_not_share_memory():
+    """A gradient or moment set that overlaps the parameters (or another such
+    set) is rejected on the host: the kernels read one and write the other
+    Gaussian by Gaussian."""
+    lib = L.lib()
+    lr = (C.c_float * 6)(1, 1, 1, 1, 1, 1)
+
+    def rows(base, cap=10):
+        q = L.gs_params()
+        row = cap * 4
+        q.mean, q.log_scale, q.quat = base, base + 3 * row, base + 6 * row
+        q.opacity_logit, q.rgb = base + 10 * row, base + 11 * row
+        q.n_dev, q.capacity = 1 << 20, cap
+        return q
+
+    p, g, m, v = rows(4096), rows(8192), rows(12288), rows(16384)
+    overlap = rows(4096 + 40 * 5)      # starts inside p's log_scale rows
+    cases = [(overlap, m, v), (g, overlap, v), (g, m, overlap), (g, m, m)]
+    for gg, mm, vv in cases:
+        assert lib.gs_adam(C.byref(p), C.byref(gg), C.byref(mm), C.byref(vv),
+                           lr, 0.9, 0.999, 1e-15, 1, None,
+                           None) == L.GS_E_INVALID
+        assert b"share memory" in lib.gs_last_error()
+    loss = C.c_void_p(1 << 20)
+    assert lib.gs_planar_reg(C.byref(p), 1.0, 0.01, C.byref(p), loss,
+                             None) == L.GS_E_INVALID
+    assert b"share memory" in lib.gs_last_error()
+    assert lib.gs_densify(C.byref(p), C.byref(overlap), None, None, 0, 1,
+                          C.c_void_p(256), C.c_void_p(256), None, None,
+                          None) == L.GS_E_INVALID
+    assert b"share memory" in lib.gs_last_error()
+    assert lib.gs_insert_gaussians(C.byref(p), C.byref(m), C.byref(m),
+                                   C.c_void_p(256), 10, 10, C.c_void_p(256),
+                                   C.c_void_p(256), C.c_void_p(256), 5, 0.9, 0,
+                                   None, None, None, None) == L.GS_E_INVALID
+    assert b"share memory" in lib.gs_last_error()
