@@ -8,7 +8,11 @@
  * caller owns; the library allocates no device memory.  Every call that takes
  * a stream only enqueues work on it (no host synchronisation) unless stated,
  * so a sequence of calls can be captured into a HIP graph.  Streams are
- * passed as void* (a hipStream_t; NULL is the null stream).
+ * passed as void* (a hipStream_t; NULL is the null stream).  A workspace
+ * holds the state that flows from one call to the next (records, sorted
+ * lists, screen-space gradients, loss partials): the calls on one workspace
+ * go on one stream, in the order of the method, and do not overlap; distinct
+ * workspaces are independent.
  *
  * Return codes: GS_OK, or
  *   GS_E_INVALID   a host-side argument check failed; nothing was launched;
