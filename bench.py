@@ -171,35 +171,62 @@ def insertion_stress(S, n0=50_000, n_kf=200):
             "ms_per_kf_render": float(np.mean(t_render))}
 
 
-def cpu_baseline(w, threads):
-    """The CPU oracle, as it stands, on the first four views of the workload
-    (every stage of the iteration for those views), scaled to window
-    iterations/s."""
+def cpu_model():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return None
+
+
+def cpu_baseline(w, threads, views=None):
+    """The CPU oracle, as it stands, timed stage by stage over the first
+    `views` views of the workload (all of them by default: one whole mapping
+    iteration), scaled to window iterations/s."""
     import numpy as np
     import oracle
-    views = 4
+    V = len(w.cameras)
+    views = views or V
     cam = list(w.cameras[:views])
     W, H = cam[0].width, cam[0].height
-    t0 = time.perf_counter()
+    st = {}
+    t = time.perf_counter()
+
+    def lap(name):
+        nonlocal t
+        now = time.perf_counter()
+        st[name] = round(now - t, 3)
+        t = now
+
+    t0 = t
     p64 = oracle.params64(w.gaussians)
     proj = oracle.project(p64, cam, 16, publish=True, nthreads=threads)
+    lap("project")
     bins = oracle.bin_sort(proj, 16, W, H, emit=False)
+    lap("bin_sort")
     fwd = oracle.forward(proj, bins, p64["rgb"], W, H, nthreads=threads)
+    lap("render_fwd")
     _, dimg = oracle.l1(fwd["img"], w.targets[:views], LAMBDA_COLOR)
+    lap("l1")
     b = oracle.backward(proj, bins, p64["rgb"], W, H, dimg, nthreads=threads)
+    lap("render_bwd")
     g = oracle.project_bwd(p64, cam, b, nthreads=threads)
+    lap("project_bwd")
     _, greg = oracle.planar_reg(p64["log_scale"], LAMBDA_REG, REG_FLOOR)
     g["log_scale"] = g["log_scale"] + greg
     for k, lr in zip(("mean", "log_scale", "quat", "opacity_logit", "rgb"), LR):
         z = np.zeros_like(p64[k])
         oracle.adam(p64[k], g[k], z, z, lr, 1)
+    lap("planar_reg_adam")
     dt = time.perf_counter() - t0
-    V = len(w.cameras)
     return {"value": views / (dt * V), "unit": "iterations/s",
             "cores": threads, "kind": "oracle",
-            "sample": f"{views} of {V} views, every stage of the iteration, "
-                      f"FP64, {threads} threads, {dt:.2f} s; scaled "
-                      f"x{V / views:g}"}
+            "sample": (f"{views} of {V} views, every stage of the iteration, "
+                       f"FP64, {threads} threads, {dt:.2f} s"
+                       + (f"; scaled x{V / views:g}" if views != V else "")),
+            "cpu_model": cpu_model(), "stages_s": st}
 
 
 def main():
