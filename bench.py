@@ -232,8 +232,8 @@ def cpu_baseline(w, threads, views=None):
 def main():
     ap = argparse.ArgumentParser(description=__doc__)
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=20)
-    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--steps", type=int, default=50)
+    ap.add_argument("--warmup", type=int, default=10)
     ap.add_argument("--workload", default="window",
                     choices=["window", "window640", "single", "small"])
     ap.add_argument("--tile", type=int, default=0,
