@@ -370,6 +370,17 @@ def main():
 
     log("bench: warmup", args.warmup)
     run(args.warmup, False)
+    # Every iteration is a real optimiser step, so the map drifts as the
+    # bench runs (and with it the pair counts).  Each measured phase below
+    # starts from this post-warm-up state, restored in place (graph-safe).
+    torch.cuda.synchronize()
+    snap = [t.clone() for t in (params.data, m.data, v.data, step_dev)]
+
+    def restore():
+        for dst, src in zip((params.data, m.data, v.data, step_dev), snap):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+
     flags, n_keys = rast.status()
     if flags:
         raise SystemExit(f"device status {flags}: key capacity exceeded")
@@ -396,7 +407,7 @@ def main():
             step()
         for _ in range(args.warmup):
             g.replay()
-        torch.cuda.synchronize()
+        restore()
         a, b = (torch.cuda.Event(enable_timing=True) for _ in range(2))
         a.record()
         for i in range(args.steps):
@@ -407,6 +418,7 @@ def main():
         log(f"bench: graph {ms_graph:.3f} ms/iteration, eager {ms_eager:.3f}")
         # Spread of single replays, each between two events (after the timed
         # region; not part of `value`).
+        restore()
         evs = [torch.cuda.Event(enable_timing=True) for _ in range(51)]
         evs[0].record()
         for i in range(50):
@@ -425,7 +437,7 @@ def main():
         for _ in range(2):
             step(True, ssim=True)
         ev["loss_ssim"].clear()
-        torch.cuda.synchronize()
+        restore()
         a, b = (torch.cuda.Event(enable_timing=True) for _ in range(2))
         k = max(3, args.steps // 2)
         a.record()
@@ -460,7 +472,7 @@ def main():
 
         for _ in range(2):
             plain_step()
-        torch.cuda.synchronize()
+        restore()
         a, b = (torch.cuda.Event(enable_timing=True) for _ in range(2))
         k = max(3, args.steps // 2)
         a.record()
