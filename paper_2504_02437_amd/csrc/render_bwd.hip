@@ -298,7 +298,7 @@ __global__ __launch_bounds__(NT) void k_render_bwd(BwdArgs a) {
 }
 
 // Sum of the tiles' fused L1 losses into *loss and of each view's squared
-// errors into sqerr[view], in a fixed order (so the result does not depend on
+// errors into sqerr[view], in a fixed order (so the sums do not depend on
 // scheduling): wave w of the one workgroup reduces view k0 + w, then thread 0
 // adds the views in order.
 __global__ __launch_bounds__(1024) void k_l1_reduce(const double2* tile_loss,
@@ -323,7 +323,7 @@ __global__ __launch_bounds__(1024) void k_l1_reduce(const double2* tile_loss,
       }
       if (lane == 0) {
         part[w] = la;
-        if (sqerr) sqerr[k] += lq;
+        if (sqerr) atomicAdd(&sqerr[k], lq);
       }
     }
     __syncthreads();
@@ -331,7 +331,9 @@ __global__ __launch_bounds__(1024) void k_l1_reduce(const double2* tile_loss,
       for (int i = 0; i < 16 && k0 + i < V; ++i) total += part[i];
     __syncthreads();
   }
-  if (tid == 0) *loss += total;
+  // One atomic add each: other calls (other workspaces, other streams) may
+  // accumulate into the same buffers.
+  if (tid == 0) atomicAdd(loss, total);
 }
 
 struct BwdLauncher {

@@ -152,3 +152,38 @@ def test_fused_loss_is_reproducible_and_accumulates():
     np.testing.assert_array_equal(got[0][1], got[1][1])
     assert got[2][0] == pytest.approx(2.5 + got[0][0], rel=1e-15)
     np.testing.assert_allclose(got[2][1], 2.5 + got[0][1], rtol=1e-15)
+
+
+def test_fused_loss_from_two_streams_into_one_buffer():
+    """Two workspaces, each on its own stream, add their fused L1 losses into
+    the same device scalar: the result is the sum of the two (each call adds
+    its total with one atomic)."""
+    w = _views(synth.tiny_scene(64, n=600, width=120, height=80, f=80.0), 4)
+    print("case fused l1 two streams", flush=True)
+    params = R.ParamBuffer.from_gaussians(w.gaussians)
+    S = R.Settings(tile=16)
+    halves = [w.cameras[:2], w.cameras[2:]]
+    rasts = [R.Rasterizer(c, params.capacity, S) for c in halves]
+    tgt = torch.from_numpy(np.random.default_rng(6).uniform(
+        size=(4, 3, 80, 120)).astype(np.float32)).cuda()
+    for r in rasts:
+        r.fit_key_capacity(params)
+        r.forward(params)
+    grads = [params.zeros_like() for _ in rasts]
+    # Each half alone, one after the other.
+    alone = []
+    for i, r in enumerate(rasts):
+        loss = torch.zeros(1, dtype=torch.float64, device="cuda")
+        R.render_bwd_l1(r.ws, params, S, r.rgb, tgt[2 * i:2 * i + 2], 0.5,
+                        r.T, r.nlast, grads[i], loss)
+        torch.cuda.synchronize()
+        alone.append(float(loss))
+    shared = torch.zeros(1, dtype=torch.float64, device="cuda")
+    streams = [torch.cuda.Stream() for _ in rasts]
+    torch.cuda.synchronize()
+    for i, (r, st) in enumerate(zip(rasts, streams)):
+        with torch.cuda.stream(st):
+            R.render_bwd_l1(r.ws, params, S, r.rgb, tgt[2 * i:2 * i + 2], 0.5,
+                            r.T, r.nlast, grads[i], shared, stream=st)
+    torch.cuda.synchronize()
+    assert float(shared) == pytest.approx(alone[0] + alone[1], rel=1e-14)
