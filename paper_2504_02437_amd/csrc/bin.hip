@@ -138,6 +138,10 @@ struct ScatterArgs {
   uint32_t* chunk_counts;        // [V][chunks][tiles]
   unsigned long long* keys;
   long long key_cap;
+  int nch;                       // chunks per view (chunked scatter)
+  const uint32_t* ranges;        // final ranges, for the tile order
+  uint32_t* order;
+  int order_n;                   // tiles to order in the scatter (0: none)
 };
 
 // Per-wave key enumeration: lane l owns one Gaussian with cnt keys (the tiles
@@ -301,20 +305,34 @@ __global__ __launch_bounds__(1024) void k_chunk_scan(ChunkScanArgs a) {
   }
 }
 
+template <int NT>
+__device__ void order_tiles(const uint32_t* ranges, uint32_t* order, int n,
+                            uint32_t* cnt, uint32_t* wsum, uint32_t* mm);
+
 // The scatter: the chunk's keys claim positions start + offset + (LDS
-// counter) in their tiles' segments.
+// counter) in their tiles' segments.  Grid (1 + chunks, views): workgroup
+// (0, 0) orders the tiles by list length meanwhile (the ranges are final),
+// the other workgroups of column 0 have nothing to do.
 template <int MAXBINS, int GPT>
 __global__ __launch_bounds__(256) void k_scatter_chunks(ScatterArgs a) {
+  static_assert(MAXBINS >= 1024, "the tile order counts in the bins");
   __shared__ uint32_t bins[MAXBINS];
   __shared__ WaveOwners owners[4];
+  if (blockIdx.x == 0) {
+    if (blockIdx.y == 0 && a.order_n > 0)
+      order_tiles<256>(a.ranges, a.order, a.order_n, bins,
+                       (uint32_t*)owners[0].incl, (uint32_t*)owners[0].x0);
+    return;
+  }
+  const int chunk = blockIdx.x - 1;
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
   const int k = blockIdx.y;
   const int nb = a.Tx * a.Ty;
-  const uint32_t* C = a.chunk_counts + ((size_t)k * gridDim.x + blockIdx.x) * nb;
+  const uint32_t* C = a.chunk_counts + ((size_t)k * a.nch + chunk) * nb;
   const uint32_t* start = a.cursor + (size_t)k * nb;
   for (int i = tid; i < nb; i += 256) bins[i] = start[i] + C[i];
   __syncthreads();
-  const int g0 = blockIdx.x * 256 * GPT;
+  const int g0 = chunk * 256 * GPT;
   // The owners of all GPT sub-chunks are loaded up front, so their latencies
   // overlap.
   int cnt[GPT], x0[GPT], y0[GPT], w[GPT];
@@ -363,24 +381,19 @@ __global__ void k_iota(uint32_t* p, size_t n) {
     p[i] = (uint32_t)i;
 }
 
-// Tiles by descending key count (a counting sort over 1024 length buckets)
-// for the per-tile kernels, whose block b takes tile order[b]: the dispatcher
-// hands out the long lists first and the short ones fill the tail.  One
-// workgroup; the order within a bucket is unspecified (the tiles are
-// independent).
-__global__ __launch_bounds__(1024) void k_tile_order(const uint32_t* ranges,
-                                                     uint32_t* order, int n) {
-  __shared__ uint32_t cnt[kOrderBuckets];
-  __shared__ uint32_t wsum[16];
-  __shared__ uint32_t lmin, lmax;
+template <int NT>
+__device__ void order_tiles(const uint32_t* ranges, uint32_t* order, int n,
+                            uint32_t* cnt, uint32_t* wsum, uint32_t* mm) {
+  constexpr int PER = kOrderBuckets / NT;   // buckets per thread in the scan
+  static_assert(PER * NT == kOrderBuckets && NT % 64 == 0, "order layout");
   const int tid = threadIdx.x;
-  cnt[tid] = 0;
-  if (tid == 0) { lmin = 0xffffffffu; lmax = 0; }
+  for (int b = tid; b < kOrderBuckets; b += NT) cnt[b] = 0;
+  if (tid == 0) { mm[0] = 0xffffffffu; mm[1] = 0; }
   __syncthreads();
   // The buckets span [shortest, longest], so few tiles share a bucket (and
   // its LDS counter).
   uint32_t mn = 0xffffffffu, mx = 0;
-  for (int t = tid; t < n; t += 1024) {
+  for (int t = tid; t < n; t += NT) {
     const uint32_t len = ranges[2 * t + 1] - ranges[2 * t];
     mn = min(mn, len);
     mx = max(mx, len);
@@ -389,32 +402,56 @@ __global__ __launch_bounds__(1024) void k_tile_order(const uint32_t* ranges,
     mn = min(mn, (uint32_t)__shfl_down((int)mn, off, 64));
     mx = max(mx, (uint32_t)__shfl_down((int)mx, off, 64));
   }
-  if ((tid & 63) == 0) { atomicMin(&lmin, mn); atomicMax(&lmax, mx); }
+  if ((tid & 63) == 0) { atomicMin(&mm[0], mn); atomicMax(&mm[1], mx); }
   __syncthreads();
-  const uint32_t base = lmin, width = (lmax - lmin) / kOrderBuckets + 1;
-  for (int t = tid; t < n; t += 1024) {
+  const uint32_t base = mm[0], width = (mm[1] - mm[0]) / kOrderBuckets + 1;
+  for (int t = tid; t < n; t += NT) {
     const uint32_t b = (ranges[2 * t + 1] - ranges[2 * t] - base) / width;
     atomicAdd(&cnt[kOrderBuckets - 1 - b], 1u);
   }
   __syncthreads();
-  // Exclusive scan of the bucket counts (longest bucket first).
+  // Exclusive scan of the bucket counts (longest bucket first): each thread
+  // owns PER consecutive buckets.
   const int lane = tid & 63, w = tid >> 6;
-  const uint32_t c = cnt[tid];
-  uint32_t x = c;
+  uint32_t c[PER], own = 0;
+#pragma unroll
+  for (int q = 0; q < PER; ++q) {
+    c[q] = cnt[tid * PER + q];
+    own += c[q];
+  }
+  uint32_t x = own;
   for (int off = 1; off < 64; off <<= 1) {
     const uint32_t y = __shfl_up(x, off, 64);
     if (lane >= off) x += y;
   }
   if (lane == 63) wsum[w] = x;
   __syncthreads();
-  uint32_t before = 0;
-  for (int i = 0; i < w; ++i) before += wsum[i];
-  cnt[tid] = before + x - c;
+  uint32_t run = x - own;
+  for (int i = 0; i < w; ++i) run += wsum[i];
+#pragma unroll
+  for (int q = 0; q < PER; ++q) {
+    cnt[tid * PER + q] = run;
+    run += c[q];
+  }
   __syncthreads();
-  for (int t = tid; t < n; t += 1024) {
+  for (int t = tid; t < n; t += NT) {
     const uint32_t b = (ranges[2 * t + 1] - ranges[2 * t] - base) / width;
     order[atomicAdd(&cnt[kOrderBuckets - 1 - b], 1u)] = (uint32_t)t;
   }
+}
+
+// Tiles by descending key count (a counting sort over 1024 length buckets)
+// for the per-tile kernels, whose block b takes tile order[b]: the dispatcher
+// hands out the long lists first and the short ones fill the tail.  One
+// workgroup; the order within a bucket is unspecified (the tiles are
+// independent).  The chunked scatter forms the same order in its first
+// workgroup instead.
+__global__ __launch_bounds__(1024) void k_tile_order(const uint32_t* ranges,
+                                                     uint32_t* order, int n) {
+  __shared__ uint32_t cnt[kOrderBuckets];
+  __shared__ uint32_t wsum[16];
+  __shared__ uint32_t mm[2];
+  order_tiles<1024>(ranges, order, n, cnt, wsum, mm);
 }
 
 hipError_t launch_order(const gs_workspace* ws, hipStream_t st) {
@@ -438,8 +475,12 @@ hipError_t launch_chunked(const ScatterArgs& c, const RangeArgs& ra,
   hipLaunchKernelGGL(k_chunk_scan, dim3((nb + 63) / 64, V), dim3(1024), 0, st,
                      sa);
   hipLaunchKernelGGL(k_tile_ranges, dim3(V), dim3(kScanThreads), 0, st, ra);
-  hipLaunchKernelGGL((k_scatter_chunks<MAXBINS, GPT>), dim3(nch, V),
-                     dim3(256), 0, st, c);
+  ScatterArgs cs = c;
+  cs.nch = nch;
+  const int n = V * nb;
+  cs.order_n = n <= kOrderMaxTiles ? n : 0;   // larger grids keep index order
+  hipLaunchKernelGGL((k_scatter_chunks<MAXBINS, GPT>), dim3(1 + nch, V),
+                     dim3(256), 0, st, cs);
   return hipGetLastError();
 }
 
@@ -465,6 +506,7 @@ hipError_t launch_bin(gs_workspace* ws, const gs_params* p, hipStream_t st) {
   c.Ty = ws->tiles_y; c.cursor = ws->cursor; c.chunk_counts = ws->chunk_counts;
   c.keys = ws->keys_unsorted;
   c.key_cap = ws->geo.key_capacity;
+  c.nch = 0; c.ranges = nullptr; c.order = nullptr; c.order_n = 0;
   const int ch = bin_chunk(ws->tiles_x, ws->tiles_y);
   const int cells = (ws->tiles_x + 1) * (ws->tiles_y + 1);
   if (ch && p->capacity <= 0) {
@@ -474,12 +516,14 @@ hipError_t launch_bin(gs_workspace* ws, const gs_params* p, hipStream_t st) {
     hipLaunchKernelGGL(k_tile_ranges, dim3(V), dim3(kScanThreads), 0, st, ra);
     return finish_bin(ws, hipGetLastError(), st);
   }
+  // The chunked scatter also orders the tiles.
+  c.ranges = ws->ranges; c.order = ws->tile_order;
   if (ch == 1024)
-    return finish_bin(ws, launch_chunked<1024, 4>(c, ra, ws->cursor, V, st), st);
+    return launch_chunked<1024, 4>(c, ra, ws->cursor, V, st);
   if (ch == 2048 && nb <= 4096 && cells <= 4096 + kGridSlack)
-    return finish_bin(ws, launch_chunked<4096, 8>(c, ra, ws->cursor, V, st), st);
+    return launch_chunked<4096, 8>(c, ra, ws->cursor, V, st);
   if (ch == 2048)
-    return finish_bin(ws, launch_chunked<16384, 8>(c, ra, ws->cursor, V, st), st);
+    return launch_chunked<16384, 8>(c, ra, ws->cursor, V, st);
   CountArgs ca;
   ca.diff = ws->diff; ca.counts = ws->cursor;
   ca.Tx = ws->tiles_x; ca.Ty = ws->tiles_y;
