@@ -4,7 +4,8 @@ For every pixel it gathers every Gaussian whose integer pixel box contains the
 pixel, orders them by (FP32 depth, index) with ``numpy.lexsort`` and blends
 front to back with the rule of Eq. 3 plus the cut-offs.  It uses no tiles, no
 keys and no ranges, so it checks the oracle's binning, sort and tile walk
-independently.  Only for tiny scenes: pure Python loops over pixels.
+independently.  Pure Python loops over pixels: composite() only for tiny
+scenes, composite_pixels() for a sample of pixels of a large image.
 """
 from __future__ import annotations
 
@@ -13,15 +14,54 @@ import math
 import numpy as np
 
 
+def _blend_pixel(rec_k, box_k, depth_bits, rgb, u, v, alpha_min, T_min,
+                 alpha_max):
+    """Eq. 3 at pixel (u, v) of one view: every Gaussian whose integer box
+    holds the pixel, in (FP32 depth, index) order, blended front to back with
+    the cut-offs.  Returns (colour without background, T_final, count,
+    dominant Gaussian, its weight)."""
+    inb = ((box_k[:, 0] <= u) & (u <= box_k[:, 1]) &
+           (box_k[:, 2] <= v) & (v <= box_k[:, 3]))
+    cand = np.nonzero(inb)[0]
+    order = cand[np.lexsort((cand, depth_bits[cand]))]
+    T = 1.0
+    C = [0.0, 0.0, 0.0]
+    cnt = 0
+    wbest, gbest = 0.0, -1
+    for g in order:
+        px, py, A, B, Cc, o = rec_k[g, :6]
+        dx, dy = px - u, py - v
+        pw = -0.5 * (A * dx * dx + Cc * dy * dy) - B * dx * dy
+        if pw > 0:
+            continue
+        a = min(alpha_max, o * math.exp(pw))
+        if a < alpha_min:
+            continue
+        Tn = T * (1.0 - a)
+        if Tn < T_min:
+            break
+        for ch in range(3):
+            C[ch] += rgb[ch, g] * a * T
+        if a * T > wbest:
+            wbest, gbest = a * T, int(g)
+        T = Tn
+        cnt += 1
+    return C, T, cnt, gbest
+
+
+def _cutoffs(alpha_min, T_min, alpha_max):
+    from . import ALPHA_MAX, ALPHA_MIN, T_MIN
+    return (ALPHA_MIN if alpha_min is None else alpha_min,
+            T_MIN if T_min is None else T_min,
+            ALPHA_MAX if alpha_max is None else alpha_max)
+
+
 def composite(rec, box, rgb, W, H, bg=(0.0, 0.0, 0.0), alpha_min=None,
               T_min=None, alpha_max=None, with_dominant=False):
     """Returns (image, T_final, contributor count) and, with_dominant, also
     the Gaussian of largest blend weight alpha * T per pixel (Eq. 8; first
     on ties, -1 when none)."""
-    from . import ALPHA_MAX, ALPHA_MIN, T_MIN
-    alpha_min = ALPHA_MIN if alpha_min is None else alpha_min
-    T_min = T_MIN if T_min is None else T_min
-    alpha_max = ALPHA_MAX if alpha_max is None else alpha_max
+    alpha_min, T_min, alpha_max = _cutoffs(alpha_min, T_min, alpha_max)
     V, n, _ = rec.shape
     img = np.zeros((V, 3, H, W))
     Tf = np.ones((V, H, W))
@@ -31,32 +71,9 @@ def composite(rec, box, rgb, W, H, bg=(0.0, 0.0, 0.0), alpha_min=None,
         depth_bits = rec[k, :, 6].astype(np.float32).view(np.uint32)
         for v in range(H):
             for u in range(W):
-                inb = ((box[k, :, 0] <= u) & (u <= box[k, :, 1]) &
-                       (box[k, :, 2] <= v) & (v <= box[k, :, 3]))
-                cand = np.nonzero(inb)[0]
-                order = cand[np.lexsort((cand, depth_bits[cand]))]
-                T = 1.0
-                C = [0.0, 0.0, 0.0]
-                cnt = 0
-                wbest, gbest = 0.0, -1
-                for g in order:
-                    px, py, A, B, Cc, o = rec[k, g, :6]
-                    dx, dy = px - u, py - v
-                    pw = -0.5 * (A * dx * dx + Cc * dy * dy) - B * dx * dy
-                    if pw > 0:
-                        continue
-                    a = min(alpha_max, o * math.exp(pw))
-                    if a < alpha_min:
-                        continue
-                    Tn = T * (1.0 - a)
-                    if Tn < T_min:
-                        break
-                    for ch in range(3):
-                        C[ch] += rgb[ch, g] * a * T
-                    if a * T > wbest:
-                        wbest, gbest = a * T, int(g)
-                    T = Tn
-                    cnt += 1
+                C, T, cnt, gbest = _blend_pixel(rec[k], box[k], depth_bits,
+                                                rgb, u, v, alpha_min, T_min,
+                                                alpha_max)
                 for ch in range(3):
                     img[k, ch, v, u] = C[ch] + T * bg[ch]
                 Tf[k, v, u] = T
@@ -65,3 +82,21 @@ def composite(rec, box, rgb, W, H, bg=(0.0, 0.0, 0.0), alpha_min=None,
     if with_dominant:
         return img, Tf, ncontrib, dominant
     return img, Tf, ncontrib
+
+
+def composite_pixels(rec, box, rgb, view, us, vs, bg=(0.0, 0.0, 0.0),
+                     alpha_min=None, T_min=None, alpha_max=None):
+    """composite() at the listed pixels (us[i], vs[i]) of one view only, for
+    images too large to composite whole: colours [m][3] and T_final [m]."""
+    alpha_min, T_min, alpha_max = _cutoffs(alpha_min, T_min, alpha_max)
+    depth_bits = rec[view, :, 6].astype(np.float32).view(np.uint32)
+    m = len(us)
+    img = np.zeros((m, 3))
+    Tf = np.ones(m)
+    for i in range(m):
+        C, T, _, _ = _blend_pixel(rec[view], box[view], depth_bits, rgb,
+                                  int(us[i]), int(vs[i]), alpha_min, T_min,
+                                  alpha_max)
+        img[i] = [C[ch] + T * bg[ch] for ch in range(3)]
+        Tf[i] = T
+    return img, Tf

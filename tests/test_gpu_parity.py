@@ -6,6 +6,7 @@ import pytest
 import torch
 
 import oracle
+from oracle import brute
 import synth
 from gpu_helpers import (_unpack, check_forward, check_grads, check_records,
                          check_sort, gpu_backward, gpu_forward,
@@ -356,3 +357,44 @@ def test_render_needs_the_projection_alpha_min():
     R.sort_tile_keys(rast.ws, base)
     R.render_fwd(rast.ws, params, lower, rast.rgb, rast.T, rast.nlast)
     torch.cuda.synchronize()
+
+
+@pytest.mark.parametrize("tile", [32, 8])
+def test_maximum_image_size(tile):
+    """The largest image a workspace accepts, 16384 x 16384, one view:
+    records, ranges and keys bit-exact against the oracle (tile 32: 262,144
+    tiles, the largest grid that is ordered by list length; tile 8: 4.2M
+    tiles, kept in index order; both on the global binning path), and the
+    image and transmittance at sampled pixels against the per-pixel brute
+    force (a pixel whose FP32 decision is ambiguous may differ: at most 1% of
+    the samples)."""
+    W = H = 16384
+    rng = np.random.default_rng([91, tile])
+    cam = synth.identity_camera(0.8 * W, 0.8 * W, W, H)
+    g = synth.frustum_gaussians(rng, 4000, cam, 1.0, 3.0)
+    g.log_scale[:] = rng.normal(-6.5, 0.4, size=(3, g.n)).astype(np.float32)
+    w = synth.Workload("max16384", g, [cam], np.zeros((1, 3, 1, 1), np.float32))
+    print("case maximum image size, tile", tile, flush=True)
+    p64 = oracle.params64(g)
+    proj = oracle.project(p64, [cam], tile, publish=True, nthreads=8)
+    bins = oracle.bin_sort(proj, tile, W, H, emit=False)
+    params, rast = gpu_forward(w, tile, 256,
+                               key_capacity=max(1 << 20, 2 * len(bins["vals"])))
+    check_records(rast, proj)
+    check_sort(rast, bins)
+    # Sampled pixels: the projected centres of visible Gaussians and uniform
+    # ones.
+    rec = proj["rec"][0]
+    vis = proj["tiles"][0] > 0
+    cu = np.clip(np.rint(rec[vis, 0]), 0, W - 1).astype(np.int64)[:1000]
+    cv = np.clip(np.rint(rec[vis, 1]), 0, H - 1).astype(np.int64)[:1000]
+    us = np.concatenate([cu, rng.integers(0, W, 500)])
+    vs = np.concatenate([cv, rng.integers(0, H, 500)])
+    ref_img, ref_T = brute.composite_pixels(proj["rec"], proj["box"],
+                                            p64["rgb"], 0, us, vs)
+    ui, vi = torch.from_numpy(us).cuda(), torch.from_numpy(vs).cuda()
+    img = rast.rgb[0][:, vi, ui].T.cpu().numpy()
+    T = rast.T[0][vi, ui].cpu().numpy()
+    bad = (np.abs(img - ref_img).max(axis=1) > 1e-5) | (np.abs(T - ref_T) > 1e-5)
+    assert bad.sum() <= 0.01 * len(us), (int(bad.sum()), len(us))
+    assert np.mean(ref_T < 1.0) > 0.5     # the samples do see Gaussians

@@ -139,6 +139,28 @@ def test_tile_path_equals_brute_force(seed):
     np.testing.assert_array_equal(fwd["nlast"] == 0, cnt == 0)
 
 
+def test_sampled_pixels_equal_the_whole_brute_force_image():
+    """composite_pixels, the per-pixel form used on images too large to
+    composite whole, returns the same values as composite at those pixels,
+    and agrees with the tile path there."""
+    w = _scene(2)
+    c = w.cameras[0]
+    p = oracle.params64(w.gaussians)
+    bg = (0.1, 0.2, 0.3)
+    proj, bins, fwd = oracle.render(p, [c], tile=16, bg=bg)
+    img, T, _ = brute.composite(proj["rec"], proj["box"], p["rgb"], c.width,
+                                c.height, bg)
+    rng = np.random.default_rng(7)
+    us = rng.integers(0, c.width, 60)
+    vs = rng.integers(0, c.height, 60)
+    pimg, pT = brute.composite_pixels(proj["rec"], proj["box"], p["rgb"], 0,
+                                      us, vs, bg)
+    np.testing.assert_array_equal(pimg, img[0][:, vs, us].T)
+    np.testing.assert_array_equal(pT, T[0][vs, us])
+    np.testing.assert_allclose(pimg, fwd["img"][0][:, vs, us].T, rtol=0,
+                               atol=1e-13)
+
+
 @pytest.mark.parametrize("seed", [0, 4])
 def test_tile_size_invariance(seed):
     w = _scene(seed, n=80)
