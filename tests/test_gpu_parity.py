@@ -143,10 +143,10 @@ def test_repeat_runs_are_deterministic_in_forward():
 
 
 def test_config1_full_size():
-    """The room scene at 1200x680 with 300k Gaussians, in the launch
-    configuration the benchmark times (tile 16, LDS batch 256): every record,
-    key and range bit-exact, every unflagged pixel within 1e-5, and the
-    gradients of every Gaussian within tolerance."""
+    """The room scene at 1200x680 with 300k Gaussians, one view, tile 16 and
+    LDS batch 256: every record, key and range bit-exact, every unflagged
+    pixel within 1e-5, and the gradients of every Gaussian within
+    tolerance."""
     w = synth.config1()
     print("case config1 oracle", flush=True)
     p64, proj, bins, fwd = oracle_forward(w, 16, nthreads=16)
@@ -162,6 +162,31 @@ def test_config1_full_size():
     ref = oracle_backward(w, p64, proj, bins, dL, nthreads=16)
     worst = check_grads(got, ref, w.gaussians.n)
     print("config1 worst grad rel err", worst, flush=True)
+
+
+def test_window_full_size_in_the_benchmark_shape():
+    """The benchmark's workload and launch shape: the 10-view 1200x680 window
+    over 300k Gaussians at tile 32, LDS batch 256, 256 threads.  Every record,
+    key and range bit-exact, every unflagged pixel of every view within 1e-5,
+    and the gradients of every Gaussian, summed over the views, within
+    tolerance."""
+    w = synth.config2()
+    print("case window oracle", flush=True)
+    p64, proj, bins, fwd = oracle_forward(w, 32, nthreads=16)
+    print("case window gpu", flush=True)
+    params, rast = gpu_forward(w, 32, 256, threads=256,
+                               key_capacity=int(1.25 * len(bins["vals"])))
+    check_records(rast, proj)
+    check_sort(rast, bins)
+    mask, err = check_forward(rast, fwd, bins)
+    print("window max image error", err, "flagged", 1 - mask.mean(), flush=True)
+    V, H, W = rast.T.shape
+    dL = masked_dL(np.random.default_rng(12), mask, (V, 3, H, W),
+                   1.0 / (3 * H * W))
+    got = gpu_backward(rast, params, dL)
+    ref = oracle_backward(w, p64, proj, bins, dL, nthreads=16)
+    worst = check_grads(got, ref, w.gaussians.n)
+    print("window worst grad rel err", worst, flush=True)
 
 
 @pytest.mark.parametrize("tile", [8, 16, 32])
