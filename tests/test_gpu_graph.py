@@ -1,7 +1,8 @@
 """One whole mapping iteration (project, bin, sort, render, L1 + planar
 gradients, backward, projection backward, Adam with a device step count)
-captured as a HIP graph and replayed: every replay matches the same
-iteration run eagerly from the same state."""
+captured as a HIP graph and replayed, with the L1 term as a separate pass
+and fused into the backward: every replay matches the same iteration run
+eagerly from the same state."""
 import numpy as np
 import pytest
 import torch
@@ -33,21 +34,25 @@ def _setup():
     return w, st
 
 
-def _iteration(st):
+def _iteration(st, fused=False):
     p, r = st["params"], st["rast"]
     st["grad"].data.zero_()
     st["loss"].zero_()
     r.forward(p)
-    R.loss_l1(r.rgb, st["target"], 1.0, st["dL"], st["loss"])
     R.planar_reg(p, 1.0, 0.01, st["grad"], st["loss"])
-    r.backward(p, st["dL"], st["grad"])
+    if fused:
+        # The benchmark's iteration: the L1 term fused into the backward.
+        r.backward_l1(p, st["target"], 1.0, st["grad"], st["loss"])
+    else:
+        R.loss_l1(r.rgb, st["target"], 1.0, st["dL"], st["loss"])
+        r.backward(p, st["dL"], st["grad"])
     R.adam(p, st["grad"], st["m"], st["v"], LR, 0.9, 0.999, 1e-15, st["step"])
     st["step"].add_(1)
 
 
 def _snapshot(st):
     return [st[k].data.clone() for k in ("params", "m", "v")] + \
-        [st["step"].clone(), st["rast"].rgb.clone()]
+        [st["step"].clone(), st["rast"].rgb.clone(), st["loss"].clone()]
 
 
 def _restore(st, snap):
@@ -56,25 +61,26 @@ def _restore(st, snap):
     st["step"].copy_(snap[3])
 
 
-def test_graph_replays_match_eager_iterations():
+@pytest.mark.parametrize("fused", [False, True])
+def test_graph_replays_match_eager_iterations(fused):
     w, st = _setup()
     start = _snapshot(st)
     eager = []
     for _ in range(3):
-        _iteration(st)
+        _iteration(st, fused)
         eager.append(_snapshot(st))
     torch.cuda.synchronize()
     g = torch.cuda.CUDAGraph()
     side = torch.cuda.Stream()
     side.wait_stream(torch.cuda.current_stream())
     with torch.cuda.stream(side):
-        _iteration(st)                         # warm-up outside the capture
+        _iteration(st, fused)                  # warm-up outside the capture
     torch.cuda.current_stream().wait_stream(side)
     torch.cuda.synchronize()
     _restore(st, start)
     torch.cuda.synchronize()
     with torch.cuda.graph(g):
-        _iteration(st)
+        _iteration(st, fused)
     torch.cuda.synchronize()
     _restore(st, start)
     torch.cuda.synchronize()
@@ -90,6 +96,9 @@ def test_graph_replays_match_eager_iterations():
         # The forward is deterministic: the replayed image is bit-identical.
         assert torch.equal(got[4], eager[i][4]), i
         assert torch.equal(got[3], eager[i][3]), i
+        # The loss: the fused L1 sum is formed in a fixed order, the planar
+        # term with FP64 atomics (last bits).
+        torch.testing.assert_close(got[5], eager[i][5], rtol=1e-12, atol=0)
         # Gradients are summed with float atomics: the parameters agree to
         # rounding.
         for a, b in zip(got[:3], eager[i][:3]):
