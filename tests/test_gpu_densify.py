@@ -140,3 +140,23 @@ def test_counts_with_long_runs_and_a_ragged_tail():
     np.testing.assert_array_equal(scratch[:60].cpu().numpy(),
                                   OD.dominated_counts(dom, 60))
     assert params.n() == 50
+
+
+def test_dominant_and_split_full_size_view():
+    """The benchmark's densification workload: the 1200x680 room view with
+    300k Gaussians at tile 32, LDS batch 256, 256 threads, sigma 64: the
+    dominant Gaussian against the oracle (off near ties), the dominated-pixel
+    counts exact and the split against the oracle's."""
+    w = synth.config1()
+    print("case dominant full size", flush=True)
+    _, _, _, fwd = oracle_forward(w, 32, nthreads=16)
+    _, _, dom = _dominant(w, 32, 256, 256)
+    ties = _check_dominant(dom, fwd)
+    print("near-tie pixels", ties, flush=True)
+    # The dense full-size view has more pixels whose two largest weights
+    # are within their FP32 error (0.13% here) than the small scenes.
+    assert ties < 5e-3
+    print("case split full size", flush=True)
+    k, over = _split_case(w, 32, 64, 150_000, 10)
+    print("split", k, flush=True)
+    assert k > 0 and not over

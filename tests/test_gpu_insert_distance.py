@@ -13,21 +13,28 @@ from paper_2504_02437_amd import raster as R
 pytestmark = pytest.mark.gpu
 
 
-def _case(seed, n0, cap, K=96, centre_only=False, tau_q=0.5):
+def _case(seed, n0, cap, K=96, centre_only=False, tau_q=0.5, scene=None):
+    """scene: None for a 96x64 camera over a tiny scene, else a workload
+    whose first camera and Gaussians are used (n0 = all of them)."""
     rng = np.random.default_rng(seed)
-    W, H = 96, 64
-    R_ = np.array([[0.8, 0.0, 0.6], [0.0, 1.0, 0.0], [-0.6, 0.0, 0.8]],
-                  np.float32)
-    cam = synth.Camera(R_, np.array([0.3, -0.1, 0.5], np.float32), 80.0, 82.0,
-                       (W - 1) / 2, (H - 1) / 2, W, H)
+    if scene is None:
+        W, H = 96, 64
+        R_ = np.array([[0.8, 0.0, 0.6], [0.0, 1.0, 0.0], [-0.6, 0.0, 0.8]],
+                      np.float32)
+        cam = synth.Camera(R_, np.array([0.3, -0.1, 0.5], np.float32), 80.0,
+                           82.0, (W - 1) / 2, (H - 1) / 2, W, H)
+        gauss = synth.tiny_scene(seed, n=max(n0, 1)).gaussians
+    else:
+        cam = scene.cameras[0]
+        W, H = cam.width, cam.height
+        gauss = scene.gaussians
     img = rng.uniform(size=(3, H, W)).astype(np.float32)
     pts = np.stack([rng.integers(-1, W + 1, K), rng.integers(-1, H + 1, K),
                     1.0 / rng.uniform(1, 5, K)], 1).astype(np.float32)
-    base = synth.tiny_scene(seed, n=max(n0, 1))
-    params = R.ParamBuffer.from_gaussians(base.gaussians, capacity=cap)
+    params = R.ParamBuffer.from_gaussians(gauss, capacity=cap)
     params.n_dev.fill_(n0)
     means = params.data[0:3, :n0].cpu().numpy()
-    d2 = oracle.nearest(cam, pts, means, centre_only=centre_only)
+    d2 = oracle.nearest(cam, pts, means, centre_only=centre_only, nthreads=16)
     inside = d2 >= 0
     finite = inside & np.isfinite(d2)
     tau = float(np.float32(np.sqrt(np.quantile(d2[finite], tau_q)))) if finite.any() else 1.0
@@ -83,3 +90,13 @@ def test_distance_insertion_into_an_empty_map():
 def test_distance_insertion_overflow():
     print("case insert distance overflow", flush=True)
     _case(53, 3000, 3010, tau_q=0.1)
+
+
+def test_distance_insertion_full_size():
+    """The benchmark's insertion workload: 96 patches x 9 candidates on the
+    1200x680 room view, tested against all 300k Gaussians of the map."""
+    w = synth.config1()
+    n = w.gaussians.n
+    print("case insert distance full size", flush=True)
+    cnt = _case(52, n, n + 96 * 9, scene=w)
+    assert cnt > 0
