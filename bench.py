@@ -13,7 +13,7 @@ graph replays (after the timed region), per-kernel milliseconds, the
 roofline of the dominant kernel (credited FP32 VALU lane-operations from exact
 pair counts, against the published FP32 vector peak: 157.3 TFLOP/s, i.e.
 78.6 T lane-operations/s with an FMA counted once), and the CPU oracle timed
-on a bounded sample of the same workload.
+stage by stage over one whole iteration of the same workload.
 """
 from __future__ import annotations
 
