@@ -122,19 +122,22 @@ struct AdamArgs {
   float b1, b2, eps;
 };
 
+// Elements per thread: the bias corrections (two FP64 powers by one thread
+// of the workgroup) are formed once per kAdamPer * 256 elements.
+constexpr int kAdamPer = 4;
+
 __global__ __launch_bounds__(256) void k_adam(AdamArgs a) {
   __shared__ float corr[2];
-  const int g = blockIdx.x * 256 + threadIdx.x;
+  const int g0 = blockIdx.x * 256 * kAdamPer + threadIdx.x;
   const int row = blockIdx.y;
   const int n = min(*a.n_dev, a.cap);
-  if (blockIdx.x * 256 >= n) return;
+  if (blockIdx.x * 256 * kAdamPer >= n) return;
   if (threadIdx.x == 0) {
     const int step = a.step_dev ? max(1, *a.step_dev) : a.step;
     corr[0] = (float)(1.0 - pow((double)a.b1, (double)step));
     corr[1] = (float)(1.0 - pow((double)a.b2, (double)step));
   }
   __syncthreads();
-  if (g >= n) return;
   const float c1 = corr[0], c2 = corr[1];
   float *P, *M, *Vv;
   const float* G;
@@ -145,12 +148,27 @@ __global__ __launch_bounds__(256) void k_adam(AdamArgs a) {
     const size_t o = (size_t)(row - 14) * a.cap;
     P = a.psh + o; G = a.gsh + o; M = a.msh + o; Vv = a.vsh + o; lr = a.lr_sh;
   }
-  const float gr = G[g];
-  const float m = a.b1 * M[g] + (1.f - a.b1) * gr;
-  const float v = a.b2 * Vv[g] + (1.f - a.b2) * gr * gr;
-  M[g] = m;
-  Vv[g] = v;
-  P[g] -= lr * (m / c1) / (sqrtf(v / c2) + a.eps);
+  // All loads first, so their latencies overlap.
+  float gr[kAdamPer], mo[kAdamPer], vo[kAdamPer], po[kAdamPer];
+#pragma unroll
+  for (int i = 0; i < kAdamPer; ++i) {
+    const int g = g0 + i * 256;
+    const bool in = g < n;
+    gr[i] = in ? G[g] : 0.f;
+    mo[i] = in ? M[g] : 0.f;
+    vo[i] = in ? Vv[g] : 0.f;
+    po[i] = in ? P[g] : 0.f;
+  }
+#pragma unroll
+  for (int i = 0; i < kAdamPer; ++i) {
+    const int g = g0 + i * 256;
+    if (g >= n) break;
+    const float m = a.b1 * mo[i] + (1.f - a.b1) * gr[i];
+    const float v = a.b2 * vo[i] + (1.f - a.b2) * gr[i] * gr[i];
+    M[g] = m;
+    Vv[g] = v;
+    P[g] = po[i] - lr * (m / c1) / (sqrtf(v / c2) + a.eps);
+  }
 }
 
 struct InsertArgs {
@@ -403,7 +421,7 @@ hipError_t launch_adam(gs_params* p, const gs_params* g, gs_params* m,
   a.n_dev = p->n_dev; a.cap = p->capacity;
   a.b1 = b1; a.b2 = b2; a.eps = eps;
   a.step = step; a.step_dev = step_dev;
-  const int blocks = (p->capacity + 255) / 256;
+  const int blocks = (p->capacity + 256 * kAdamPer - 1) / (256 * kAdamPer);
   if (blocks <= 0) return hipSuccess;
   hipLaunchKernelGGL(k_adam, dim3(blocks, 14 + nsh), dim3(256), 0, st, a);
   return hipGetLastError();
