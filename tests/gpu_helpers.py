@@ -156,10 +156,17 @@ def check_forward(rast, fwd, bins=None, max_flagged=MAX_FLAGGED):
     return mask, float(err.max(initial=0.0))
 
 
-def check_grads(got, ref, n, rtol=GRAD_RTOL, names=None):
+def check_grads(got, ref, n, rtol=GRAD_RTOL, names=None, outliers=0.0,
+                hard_rtol=None):
     """got: [14 + coefficient rows][cap] GPU gradients; ref: dict of oracle
-    gradients (with "sh" [K-1][3][n] for view-dependent colour)."""
+    gradients (with "sh" [K-1][3][n] for view-dependent colour).  Every
+    element within rtol, relative to max(|ref|, 1e-2 of the row group's
+    largest), except, with outliers > 0, at most that fraction of the
+    elements, which must still be within hard_rtol (for full-size scenes:
+    the FP32 conic gradients' rounding, amplified through the covariance
+    chain, can exceed rtol where a small result cancels large terms)."""
     worst = {}
+    n_bad = n_all = 0
     rows = dict(R.ROWS)
     if "sh" in ref:
         rows["sh"] = (14, got.shape[0])
@@ -173,7 +180,18 @@ def check_grads(got, ref, n, rtol=GRAD_RTOL, names=None):
         rel = np.abs(g - r) / tol
         worst[name] = float(rel.max(initial=0.0)) * rtol
         bad = np.argwhere(rel > 1.0)
-        assert bad.size == 0, (name, bad[:5], g[tuple(bad[0])], r[tuple(bad[0])])
+        n_bad += len(bad)
+        n_all += rel.size
+        if outliers > 0:
+            hard = (hard_rtol / rtol) if hard_rtol else np.inf
+            worse = np.argwhere(rel > hard)
+            assert worse.size == 0, (name, worse[:5], g[tuple(worse[0])],
+                                     r[tuple(worse[0])])
+        else:
+            assert bad.size == 0, (name, bad[:5], g[tuple(bad[0])],
+                                   r[tuple(bad[0])])
+    assert n_bad <= outliers * n_all, (n_bad, n_all)
+    worst["elements_over_rtol"] = n_bad
     return worst
 
 

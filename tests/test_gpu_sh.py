@@ -131,7 +131,8 @@ def test_config1_degree3_full_size():
     """The 300k-Gaussian room view at 1200x680 with degree-3 colour, in the
     benchmark's single-view launch configuration: record colours of every
     binned pair, every unflagged pixel within 1e-5 and the gradients of every
-    Gaussian, coefficients included."""
+    Gaussian, coefficients included, within 1e-3 (at most 1e-5 of the
+    elements within 1e-2, see check_grads)."""
     w = synth.config1()
     w.gaussians = synth.with_sh(w.gaussians, 3, 3, 0.05)
     _away_from_clamp(w)
@@ -146,7 +147,7 @@ def test_config1_degree3_full_size():
                    1.0 / (3 * 680 * 1200))
     got = gpu_backward(rast, params, dL)
     ref = oracle_backward(w, p64, proj, bins, dL, nthreads=16)
-    worst = check_grads(got, ref, w.gaussians.n)
+    worst = check_grads(got, ref, w.gaussians.n, outliers=1e-5, hard_rtol=1e-2)
     print("sh config1 worst grad rel err", worst, flush=True)
 
 
