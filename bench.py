@@ -260,9 +260,9 @@ def main():
     ap.add_argument("--cpu-threads", type=int, default=0)
     args = ap.parse_args()
     if args.gpus != 1:
-        print("bench.py measures one GPU only: this build has no multi-GPU "
+        print("bench.py measures one GPU only: the library has no multi-GPU "
               "path (the window would shard by views with one gradient "
-              "all-reduce; not built). Run with --gpus 1.", file=sys.stderr)
+              "all-reduce). Run with --gpus 1.", file=sys.stderr)
         sys.exit(2)
 
     import numpy as np
