@@ -34,9 +34,26 @@ METRIC = ("mapping iters/s (fwd+bwd, 10-KF window, 1200×680, 300k "
 # once): 256 CUs x 128 FP32 lanes x 2.4 GHz.  Half of it is reached only with
 # packed (two-lane) FP32 instructions, which these kernels do not use.
 PEAK_LANE_OPS = 256 * 128 * 2.4e9
-# Credited FP32 VALU lane-operations per pair (what the method must compute):
+# Credited FP32 VALU lane-operations per pair (what the method must compute).
+# Forward: 2 per examined pair (box test), +12 per in-box pair (offset,
+# exponent, exponential, opacity, clamp, threshold), +7 per contributing pair
+# (transmittance, stop test, weight, three colour FMAs).  Backward: 45 per
+# contributing pair (alpha recomputed, transmittance recovered, colour, alpha,
+# opacity, mean and conic gradients) and 14 per in-box pair before the
+# pixel's last contributor that does not contribute (alpha recomputed and
+# rejected).  "revisit" counts all in-box pairs before n_last, contributing
+# ones included, so the backward credits revisit - contributing at 14.
 FWD_OPS = dict(examined=2, inbox=12, contributing=7)
-BWD_OPS = dict(revisit=14, contributing=45)
+BWD_OPS = dict(revisit_only=14, contributing=45)
+
+
+def credited_ops(cnt):
+    """(forward, backward) credited lane-operations for the pair counts of
+    one launch."""
+    fwd = sum(FWD_OPS[k] * cnt[k] for k in FWD_OPS)
+    c = dict(cnt, revisit_only=cnt["revisit"] - cnt["contributing"])
+    bwd = sum(BWD_OPS[k] * c[k] for k in BWD_OPS)
+    return fwd, bwd
 LR = (1.6e-4, 5e-3, 1e-3, 5e-2, 2.5e-3)   # mean, log_scale, quat, opacity, rgb
 LAMBDA_COLOR, LAMBDA_REG, REG_FLOOR = 1.0, 1.0, 0.01
 LAMBDA_PHOTO = 0.2   # weight of the SSIM term inside the colour loss
@@ -171,14 +188,48 @@ def insertion_stress(S, n0=50_000, n_kf=200):
             "ms_per_kf_render": float(np.mean(t_render))}
 
 
-def cpu_model():
+def host_cpus():
+    """The host CPUs as the process sees them: nproc (every logical CPU of
+    the machine), the CPUs this process may run on (its affinity mask), the
+    OpenMP thread budget the environment sets, and lscpu's description."""
+    info = {"nproc": os.cpu_count()}
     try:
-        for line in open("/proc/cpuinfo"):
-            if line.startswith("model name"):
-                return line.split(":", 1)[1].strip()
-    except OSError:
+        info["affinity"] = len(os.sched_getaffinity(0))
+    except (AttributeError, OSError):
+        info["affinity"] = os.cpu_count()
+    env = os.environ.get("OMP_NUM_THREADS", "")
+    info["omp_num_threads"] = int(env) if env.isdigit() else None
+    keys = {"Model name": "model", "Socket(s)": "sockets",
+            "Core(s) per socket": "cores_per_socket",
+            "Thread(s) per core": "threads_per_core", "CPU max MHz": "max_mhz"}
+    try:
+        import subprocess
+        out = subprocess.run(["lscpu"], capture_output=True, text=True,
+                             timeout=10).stdout
+        for line in out.splitlines():
+            k, _, v = line.partition(":")
+            if k.strip() in keys:
+                info[keys[k.strip()]] = v.strip()
+    except (OSError, subprocess.SubprocessError):
         pass
-    return None
+    if "model" not in info:
+        try:
+            for line in open("/proc/cpuinfo"):
+                if line.startswith("model name"):
+                    info["model"] = line.split(":", 1)[1].strip()
+                    break
+        except OSError:
+            pass
+    return info
+
+
+def cpu_threads(info):
+    """Threads for the CPU baseline: every CPU the process may use, within
+    the thread budget the environment grants (OMP_NUM_THREADS)."""
+    n = info.get("affinity") or info.get("nproc") or 1
+    if info.get("omp_num_threads"):
+        n = min(n, info["omp_num_threads"])
+    return max(1, n)
 
 
 def cpu_baseline(w, threads, views=None):
@@ -204,7 +255,7 @@ def cpu_baseline(w, threads, views=None):
     p64 = oracle.params64(w.gaussians)
     proj = oracle.project(p64, cam, 16, publish=True, nthreads=threads)
     lap("project")
-    bins = oracle.bin_sort(proj, 16, W, H, emit=False)
+    bins = oracle.bin_sort(proj, 16, W, H, emit=False, nthreads=threads)
     lap("bin_sort")
     fwd = oracle.forward(proj, bins, p64["rgb"], W, H, nthreads=threads)
     lap("render_fwd")
@@ -226,7 +277,7 @@ def cpu_baseline(w, threads, views=None):
             "sample": (f"{views} of {V} views, every stage of the iteration, "
                        f"FP64, {threads} threads, {dt:.2f} s"
                        + (f"; scaled x{V / views:g}" if views != V else "")),
-            "cpu_model": cpu_model(), "stages_s": st}
+            "host": host_cpus(), "stages_s": st}
 
 
 def main():
@@ -598,8 +649,7 @@ def main():
         rf.forward(params)
         cnt_full = rf.count_pairs(params)
         del rf
-    fwd_ops = sum(FWD_OPS[k] * cnt[k] for k in FWD_OPS)
-    bwd_ops = sum(BWD_OPS[k] * cnt[k] for k in BWD_OPS)
+    fwd_ops, bwd_ops = credited_ops(cnt)
     if kern["render_bwd"] >= kern["render_fwd"]:
         dom, ops, t = "render_bwd", bwd_ops, kern["render_bwd"]
     else:
@@ -651,7 +701,7 @@ def main():
         "wall_s": wall,
     }
     if not args.no_cpu_baseline:
-        threads = args.cpu_threads or min(16, os.cpu_count() or 1)
+        threads = args.cpu_threads or cpu_threads(host_cpus())
         log("bench: CPU oracle baseline on", threads, "threads")
         out["cpu_baseline"] = cpu_baseline(w, threads)
     print(json.dumps(out), flush=True)

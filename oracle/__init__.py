@@ -46,7 +46,7 @@ def lib():
         L.or_bin_sort.restype = C.c_int64
         L.or_bin_sort.argtypes = [C.c_int, C.c_int, _i32, _i32, _d, C.c_int,
                                   C.c_int, C.c_int, _u64, _u32, _u64, _u32,
-                                  C.c_int64, _u32]
+                                  C.c_int64, _u32, C.c_int]
         L.or_forward.restype = C.c_int
         L.or_forward.argtypes = [C.c_int, C.c_int, C.c_int, C.c_int, C.c_int,
                                  _d, _i32, _d, C.c_int, _u32, _u32, _d,
@@ -131,8 +131,10 @@ def project(p, cams, tile=16, publish=True, nthreads=1):
     return dict(rec=rec, cov=cov, box=box, tiles=tiles)
 
 
-def bin_sort(proj, tile, W, H, cap=None, emit=True):
-    """Duplicated (tile, depth) keys, stable sort and tile ranges."""
+def bin_sort(proj, tile, W, H, cap=None, emit=True, nthreads=1):
+    """Duplicated (tile, depth) keys, stable sort and tile ranges (views
+    emitted and sorted on nthreads threads; the result does not depend on
+    it)."""
     L = lib()
     V, n = proj["tiles"].shape
     total = int(proj["tiles"].astype(np.int64).sum())
@@ -146,7 +148,7 @@ def bin_sort(proj, tile, W, H, cap=None, emit=True):
     nk = L.or_bin_sort(V, n, _p(proj["box"], _i32), _p(proj["tiles"], _i32),
                        _p(proj["rec"], _d), tile, W, H, _p(keys_emit, _u64),
                        _p(vals_emit, _u32), _p(keys, _u64), _p(vals, _u32),
-                       cap, _p(ranges, _u32))
+                       cap, _p(ranges, _u32), nthreads)
     if nk < 0:
         raise OverflowError("key capacity exceeded")
     out = dict(keys=keys[:nk], vals=vals[:nk], ranges=ranges, n_keys=int(nk),

@@ -270,20 +270,34 @@ static void merge_sort_pairs(uint64_t* k, uint32_t* v, uint64_t* tk,
  * with value g, sorts the pairs stably by key and derives each tile's
  * [start, end) range in the sorted list (start = number of keys in lower
  * tiles, so empty tiles have start == end).  keys_emit / vals_emit may be
- * NULL.  Returns the key count, or -1 when it exceeds cap. */
+ * NULL.  Returns the key count, or -1 when it exceeds cap.
+ *
+ * The keys of view k all lie in [k Ty Tx << 32, (k + 1) Ty Tx << 32) and are
+ * emitted as one contiguous run after those of views < k, so the stable sort
+ * of the whole array is the concatenation of the stable sorts of the views'
+ * runs: each view is emitted and sorted on its own (over nthreads threads),
+ * which yields exactly the array a single stable sort of all keys gives. */
 OR_EXPORT int64_t or_bin_sort(int V, int n, const int32_t* box,
                               const int32_t* tiles, const double* rec,
                               int tile, int W, int H, uint64_t* keys_emit,
                               uint32_t* vals_emit, uint64_t* keys_sorted,
                               uint32_t* vals_sorted, int64_t cap,
-                              uint32_t* ranges) {
+                              uint32_t* ranges, int nthreads) {
   const int Tx = (W + tile - 1) / tile, Ty = (H + tile - 1) / tile;
-  int64_t total = 0;
-  for (int k = 0; k < V; ++k)
-    for (int g = 0; g < n; ++g) total += tiles[(size_t)k * n + g];
-  if (total > cap) return -1;
-  int64_t o = 0;
-  for (int k = 0; k < V; ++k)
+  int64_t* voff = (int64_t*)calloc((size_t)V + 1, sizeof(int64_t));
+  for (int k = 0; k < V; ++k) {
+    int64_t t = 0;
+    for (int g = 0; g < n; ++g) t += tiles[(size_t)k * n + g];
+    voff[k + 1] = voff[k] + t;
+  }
+  const int64_t total = voff[V];
+  if (total > cap) { free(voff); return -1; }
+  if (nthreads < 1) nthreads = 1;
+#ifdef _OPENMP
+#pragma omp parallel for schedule(dynamic, 1) num_threads(nthreads)
+#endif
+  for (int k = 0; k < V; ++k) {
+    int64_t o = voff[k];
     for (int g = 0; g < n; ++g) {
       const int32_t* b = &box[((size_t)k * n + g) * 4];
       if (tiles[(size_t)k * n + g] == 0) continue;
@@ -296,16 +310,21 @@ OR_EXPORT int64_t or_bin_sort(int V, int n, const int32_t* box,
           ++o;
         }
     }
-  if (keys_emit) memcpy(keys_emit, keys_sorted, sizeof(uint64_t) * (size_t)o);
-  if (vals_emit) memcpy(vals_emit, vals_sorted, sizeof(uint32_t) * (size_t)o);
-  uint64_t* tk = (uint64_t*)malloc(sizeof(uint64_t) * (size_t)(o > 0 ? o : 1));
-  uint32_t* tv = (uint32_t*)malloc(sizeof(uint32_t) * (size_t)(o > 0 ? o : 1));
-  merge_sort_pairs(keys_sorted, vals_sorted, tk, tv, o);
-  free(tk);
-  free(tv);
+    const int64_t m = voff[k + 1] - voff[k];
+    if (keys_emit)
+      memcpy(keys_emit + voff[k], keys_sorted + voff[k], sizeof(uint64_t) * (size_t)m);
+    if (vals_emit)
+      memcpy(vals_emit + voff[k], vals_sorted + voff[k], sizeof(uint32_t) * (size_t)m);
+    uint64_t* tk = (uint64_t*)malloc(sizeof(uint64_t) * (size_t)(m > 0 ? m : 1));
+    uint32_t* tv = (uint32_t*)malloc(sizeof(uint32_t) * (size_t)(m > 0 ? m : 1));
+    merge_sort_pairs(keys_sorted + voff[k], vals_sorted + voff[k], tk, tv, m);
+    free(tk);
+    free(tv);
+  }
+  free(voff);
   const int64_t nt = (int64_t)V * Tx * Ty;
   int64_t* cnt = (int64_t*)calloc((size_t)nt, sizeof(int64_t));
-  for (int64_t i = 0; i < o; ++i) cnt[keys_sorted[i] >> 32] += 1;
+  for (int64_t i = 0; i < total; ++i) cnt[keys_sorted[i] >> 32] += 1;
   int64_t acc = 0;
   for (int64_t t = 0; t < nt; ++t) {
     ranges[2 * t] = (uint32_t)acc;
@@ -313,7 +332,7 @@ OR_EXPORT int64_t or_bin_sort(int V, int n, const int32_t* box,
     ranges[2 * t + 1] = (uint32_t)acc;
   }
   free(cnt);
-  return o;
+  return total;
 }
 
 /* ---- Forward compositing (Eq. 3). ---- */

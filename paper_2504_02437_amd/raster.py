@@ -534,6 +534,9 @@ class Rasterizer:
         self.T = torch.empty(self.V, self.H, self.W, device=device)
         self.nlast = torch.empty(self.V, self.H, self.W, dtype=torch.int32,
                                  device=device)
+        # Bumped by every forward, camera change and workspace rebuild: a
+        # backward checks it against the forward it belongs to.
+        self.generation = 0
 
     def fit_key_capacity(self, params, margin=1.25, stream=None):
         """Projects and bins once; if the keys overflowed the workspace,
@@ -549,6 +552,7 @@ class Rasterizer:
             torch.cuda.empty_cache()
             self.ws = Workspace(self.V, self.W, self.H, self.settings.tile,
                                 self.capacity, cap, self.rgb.device)
+        self.generation += 1
         return nk
 
     def set_cameras(self, cams):
@@ -556,8 +560,10 @@ class Rasterizer:
             raise ValueError("view count is fixed per rasterizer")
         self.cams = list(cams)
         self.cams_dev.copy_(cameras_to_device(cams, self.cams_dev.device))
+        self.generation += 1
 
     def forward(self, params, stream=None):
+        self.generation += 1
         project_and_bin(self.ws, params, self.cams_dev, self.settings, stream)
         sort_tile_keys(self.ws, self.settings, stream)
         render_fwd(self.ws, params, self.settings, self.rgb, self.T,
@@ -567,6 +573,7 @@ class Rasterizer:
     def forward_dominant(self, params, stream=None):
         """forward() plus each pixel's dominant Gaussian (int32 [V][H][W])."""
         dom = torch.empty(self.T.shape, dtype=torch.int32, device=self.T.device)
+        self.generation += 1
         project_and_bin(self.ws, params, self.cams_dev, self.settings, stream)
         sort_tile_keys(self.ws, self.settings, stream)
         render_dominant(self.ws, params, self.settings, self.rgb, self.T,
@@ -608,16 +615,30 @@ class Rasterize(torch.autograd.Function):
         if data.data_ptr() != params.data.data_ptr():
             raise ValueError("data must be params.data")
         rgb, T, nlast = rast.forward(params)
+        # Truncated tile lists would give a wrong image and wrong gradients:
+        # on a key overflow, refit the workspace to the exact count and
+        # render again (this reads the status word: one stream sync).
+        flags, _ = rast.status()
+        if flags & L.GS_STATUS_KEY_OVERFLOW:
+            rast.fit_key_capacity(params)
+            rgb, T, nlast = rast.forward(params)
+            flags, _ = rast.status()
+            if flags & L.GS_STATUS_KEY_OVERFLOW:
+                raise RuntimeError("key capacity exceeded after refitting")
+        if flags:
+            raise RuntimeError(f"device status {flags} after the forward")
         ctx.rast = rast
         ctx.params = params
-        ctx.generation = rast.ws.generation
+        ctx.generation = rast.generation
+        ctx.ws, ctx.ws_generation = rast.ws, rast.ws.generation
         ctx.mark_non_differentiable(T, nlast)
         return rgb.clone(), T.clone(), nlast.clone()
 
     @staticmethod
     def backward(ctx, g_rgb, g_T, g_nlast):
         rast, params = ctx.rast, ctx.params
-        if rast.ws.generation != ctx.generation:
+        if rast.generation != ctx.generation or rast.ws is not ctx.ws or \
+                rast.ws.generation != ctx.ws_generation:
             raise RuntimeError("another forward ran on this rasterizer before "
                                "the backward of this one")
         grad = params.zeros_like()

@@ -37,7 +37,7 @@ def oracle_forward(w, tile=16, bg=(0.0, 0.0, 0.0), nthreads=8):
     p64 = oracle.params64(w.gaussians)
     W, H = w.cameras[0].width, w.cameras[0].height
     proj = oracle.project(p64, w.cameras, tile, publish=True, nthreads=nthreads)
-    bins = oracle.bin_sort(proj, tile, W, H, emit=False)
+    bins = oracle.bin_sort(proj, tile, W, H, emit=False, nthreads=nthreads)
     fwd = oracle.forward(proj, bins, oracle_colours(w, p64), W, H, bg,
                          nthreads=nthreads)
     return p64, proj, bins, fwd

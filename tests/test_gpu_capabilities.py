@@ -31,6 +31,52 @@ def test_autograd_function_matches_oracle_gradient():
     check_grads(got, ref, w.gaussians.n)
 
 
+def test_autograd_refits_an_overflowing_key_capacity():
+    """A workspace too small for the keys would truncate the tile lists: the
+    autograd forward reads the status word, refits the workspace to the key
+    count and renders again, so image and gradient match the oracle."""
+    w = synth.tiny_scene(33, n=250, width=64, height=48, f=55.0,
+                         log_scale_mu=-2.0)
+    print("case autograd overflow refit", flush=True)
+    p64, proj, bins, fwd = oracle_forward(w, 16)
+    mask = fwd["flags"][0] == 0
+    params = R.ParamBuffer.from_gaussians(w.gaussians)
+    rast = R.Rasterizer(w.cameras, params.capacity, R.Settings(tile=16),
+                        key_capacity=16)
+    data = params.data.requires_grad_(True)
+    rgb, T, nlast = R.Rasterize.apply(data, rast, params)
+    assert rast.status()[0] == 0
+    img = rgb.detach().cpu().numpy()[0]
+    assert np.abs(img - fwd["img"][0])[:, mask].max() <= 1e-5
+    wimg = masked_dL(np.random.default_rng(1), mask[None], (1, 3, 48, 64))
+    (rgb * torch.from_numpy(wimg).cuda()).sum().backward()
+    check_grads(data.grad.detach().cpu().numpy(),
+                oracle_backward(w, p64, proj, bins, wimg), w.gaussians.n)
+
+
+@pytest.mark.parametrize("change", ["forward", "cameras", "workspace"])
+def test_autograd_backward_refuses_stale_state(change):
+    """The backward recomputes from the rasterizer's current lists: after
+    another forward, a camera change or a workspace rebuild it raises instead
+    of returning gradients of another render."""
+    w = synth.tiny_scene(34, n=120, width=48, height=40, f=45.0)
+    print("case autograd stale", change, flush=True)
+    params = R.ParamBuffer.from_gaussians(w.gaussians)
+    rast = R.Rasterizer(w.cameras, params.capacity, R.Settings(tile=16))
+    data = params.data.requires_grad_(True)
+    rgb, _, _ = R.Rasterize.apply(data, rast, params)
+    if change == "forward":
+        rast.forward(params)
+    elif change == "cameras":
+        rast.set_cameras(w.cameras)
+    else:
+        rast.ws = R.Workspace(rast.V, rast.W, rast.H, 16, params.capacity,
+                              1 << 16)
+        rast.fit_key_capacity(params)
+    with pytest.raises(RuntimeError, match="before the backward"):
+        rgb.sum().backward()
+
+
 def test_autograd_function_against_fp32_finite_differences():
     """Central differences of the GPU forward itself (FP32, step 1e-3
     relative).  The alpha and transmittance cut-offs are discontinuities that

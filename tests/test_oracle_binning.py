@@ -19,13 +19,16 @@ def _multi_view(seed=0, V=3, n=400):
     return w, cams
 
 
-@pytest.mark.parametrize("tile", [8, 16, 32])
-def test_sort_matches_stable_argsort_and_lexsort(tile):
-    w, cams = _multi_view()
+@pytest.mark.parametrize("tile,threads", [(8, 1), (16, 1), (32, 1), (8, 3),
+                                          (16, 8)])
+def test_sort_matches_stable_argsort_and_lexsort(tile, threads):
+    """Views are emitted and sorted in parallel: the result is the single
+    stable sort of all keys whatever the thread count."""
+    w, cams = _multi_view(V=5 if threads > 1 else 3)
     p = oracle.params64(w.gaussians)
     W, H = cams[0].width, cams[0].height
     proj = oracle.project(p, cams, tile)
-    b = oracle.bin_sort(proj, tile, W, H)
+    b = oracle.bin_sort(proj, tile, W, H, nthreads=threads)
     assert b["n_keys"] == int(proj["tiles"].sum())
     order = np.argsort(b["keys_emit"], kind="stable")
     np.testing.assert_array_equal(b["keys"], b["keys_emit"][order])
