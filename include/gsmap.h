@@ -169,7 +169,12 @@ typedef struct gs_workspace gs_workspace;
  *                  only with GS_FLAG_EMIT_KEYS
  *   grad2d         [n_views][5][capacity] dL/d(px, py, A, B, C)
  *   n_keys         device int64 key count of the last project_and_bin
- *   status         device int32 GS_STATUS_* bits (sticky until cleared) */
+ *   status         device int32 GS_STATUS_* bits (sticky until cleared)
+ *   grad_opacity   [capacity] dL/d opacity, summed over the views
+ *   grad_colour    [n_views][3][capacity] dL/d colour per view (only with
+ *                  view-dependent colour)
+ * The three gradient buffers hold what the last compositing backward added
+ * until gs_project_bwd consumes and clears them. */
 typedef struct gs_workspace_view {
   void* records;
   int32_t* tiles_touched;
@@ -182,6 +187,8 @@ typedef struct gs_workspace_view {
   int32_t* status;
   int32_t tiles_x;
   int32_t tiles_y;
+  float* grad_opacity;
+  float* grad_colour;
 } gs_workspace_view;
 
 /* Host only.  Bytes of device memory a workspace for `geo` needs. */

@@ -23,6 +23,8 @@ _LIB = None
 ALPHA_MIN = float(np.float32(1.0) / np.float32(255.0))
 T_MIN = float(np.float32(1e-4))
 ALPHA_MAX = float(np.float32(0.99))
+# Decision codes of a (pixel, entry) pair in the forward walk.
+DEC_SKIP, DEC_ADMIT, DEC_CLAMP, DEC_STOP = 0, 1, 2, 3
 REC_FIELDS = ("px", "py", "A", "B", "C", "opacity", "depth", "radius")
 
 _d = C.POINTER(C.c_double)
@@ -63,6 +65,18 @@ def lib():
         L.or_project_bwd.restype = C.c_int
         L.or_project_bwd.argtypes = [C.c_int, C.c_int, _d, _d, _d, _d, _d, _d,
                                      _d, _d, _d, _d, _d, _d, _d, C.c_int]
+        L.or_project_bwd_abs.restype = C.c_int
+        L.or_project_bwd_abs.argtypes = [C.c_int, C.c_int, _d, _d, _d, _d,
+                                         _d, _d, _d, _d, _d, _d, _d, _d, _d,
+                                         C.c_int]
+        L.or_pixel_walk.restype = C.c_int
+        L.or_pixel_walk.argtypes = [C.c_int, C.c_int, C.c_int, C.c_int, C.c_int,
+                                    _d, _i32, _u32, _u32, C.c_double,
+                                    C.c_double, C.c_double, C.c_int, _i64,
+                                    C.c_int, _i32, _d, _u8, _i32]
+        L.or_admit_extent.restype = None
+        L.or_admit_extent.argtypes = [C.c_int, C.c_int, _d, _i32, C.c_double,
+                                      _i32, C.c_int]
         L.or_l1.restype = C.c_double
         L.or_l1.argtypes = [C.c_int, C.c_int, C.c_int, _d, _d, C.c_double, _d]
         L.or_planar_reg.restype = C.c_double
@@ -209,6 +223,46 @@ def forward(proj, bins, rgb, W, H, bg=(0.0, 0.0, 0.0), alpha_min=ALPHA_MIN,
                               contributing=int(cnt[2]), revisit=int(cnt[3])))
 
 
+def pixel_walk(proj, bins, W, H, pix, alpha_min=ALPHA_MIN, T_min=T_MIN,
+               alpha_max=ALPHA_MAX):
+    """The forward walk at the listed pixels (flat indices (k H + v) W + u):
+    for each, the in-box entries of its tile list up to the stop, as arrays
+    (gaussian [m][L], weight alpha T [m][L] (0 if not contributing),
+    decision code [m][L], count [m])."""
+    L = lib()
+    V, n = proj["tiles"].shape
+    pix = np.ascontiguousarray(pix, np.int64)
+    r = bins["ranges"].astype(np.int64)
+    maxw = max(1, int((r[:, 1] - r[:, 0]).max()))
+    m = len(pix)
+    g = np.zeros((m, maxw), np.int32)
+    wt = np.zeros((m, maxw))
+    code = np.zeros((m, maxw), np.uint8)
+    cnt = np.zeros(m, np.int32)
+    vals = bins["vals"] if bins["n_keys"] else np.zeros(1, np.uint32)
+    rc = L.or_pixel_walk(V, W, H, bins["tile"], n, _p(proj["rec"], _d),
+                         _p(proj["box"], _i32), _p(vals, _u32),
+                         _p(bins["ranges"], _u32), alpha_min, T_min, alpha_max,
+                         m, _p(pix, _i64), maxw, _p(g, _i32), _p(wt, _d),
+                         _p(code, _u8), _p(cnt, _i32))
+    if rc != 0:
+        raise ValueError("pixel outside the views, or a walk longer than the "
+                         "longest tile list")
+    return g, wt, code, cnt
+
+
+def admit_extent(proj, alpha_min=ALPHA_MIN, nthreads=1):
+    """Per (view, Gaussian), the pixel rectangle (u_lo, u_hi, v_lo, v_hi)
+    of its box outside which no FP32 evaluation of alpha can reach
+    alpha_min; (0, -1, 0, -1) when none can."""
+    L = lib()
+    V, n = proj["tiles"].shape
+    rect = np.zeros((V, n, 4), np.int32)
+    L.or_admit_extent(V, n, _p(proj["rec"], _d), _p(proj["box"], _i32),
+                      alpha_min, _p(rect, _i32), nthreads)
+    return rect
+
+
 def decision_buffer(bins, V, W, H):
     r = bins["ranges"].astype(np.int64)
     L = max(1, int((r[:, 1] - r[:, 0]).max()))
@@ -257,6 +311,34 @@ def project_bwd(p, cams, bwd, nthreads=1):
                      _p(bwd["grgb"], _d), _p(out["mean"], _d),
                      _p(out["log_scale"], _d), _p(out["quat"], _d),
                      _p(out["opacity_logit"], _d), _p(out["rgb"], _d), nthreads)
+    return out
+
+
+def project_bwd_abs(p, cams, bwd, nthreads=1):
+    """Magnitude of the chain-rule terms behind each parameter gradient: the
+    projection backward with every partial derivative and every screen-space
+    gradient taken by absolute value (sum over views and screen quantities
+    of |d out / d g2d| |g2d|; |gop| o (1 - o); |grgb|).  It bounds the
+    gradient's absolute value, and an error of relative size e in the
+    screen-space gradients moves the gradient by at most e times it."""
+    L = lib()
+    n = p["mean"].shape[1]
+    camd = np.stack([cam_array(c) for c in cams])
+    out = dict(mean=np.zeros((3, n)), log_scale=np.zeros((3, n)),
+               quat=np.zeros((4, n)), opacity_logit=np.zeros(n),
+               rgb=np.zeros((3, n)))
+    x2d = np.ascontiguousarray(np.abs(bwd["g2d"]), np.float64)
+    xop = np.ascontiguousarray(np.abs(bwd["gop"]), np.float64)
+    xrgb = np.ascontiguousarray(np.abs(bwd["grgb"]), np.float64)
+    if xrgb.shape != (3, n):
+        raise ValueError("per-view colour magnitudes go through oracle.sh")
+    L.or_project_bwd_abs(len(cams), n, _p(p["mean"], _d),
+                         _p(p["log_scale"], _d), _p(p["quat"], _d),
+                         _p(p["opacity_logit"], _d), _p(camd, _d),
+                         _p(x2d, _d), _p(xop, _d), _p(xrgb, _d),
+                         _p(out["mean"], _d), _p(out["log_scale"], _d),
+                         _p(out["quat"], _d), _p(out["opacity_logit"], _d),
+                         _p(out["rgb"], _d), nthreads)
     return out
 
 

@@ -6,6 +6,9 @@ front to back with the rule of Eq. 3 plus the cut-offs.  It uses no tiles, no
 keys and no ranges, so it checks the oracle's binning, sort and tile walk
 independently.  Pure Python loops over pixels: composite() only for tiny
 scenes, composite_pixels() for a sample of pixels of a large image.
+count_pairs() counts the work of a tile walk from the definition of a tile's
+list (every Gaussian whose box meets the tile, in (depth, index) order), built
+here without keys or a sort of the oracle's.
 """
 from __future__ import annotations
 
@@ -100,3 +103,59 @@ def composite_pixels(rec, box, rgb, view, us, vs, bg=(0.0, 0.0, 0.0),
         img[i] = [C[ch] + T * bg[ch] for ch in range(3)]
         Tf[i] = T
     return img, Tf
+
+
+def count_pairs(rec, box, W, H, tile, alpha_min=None, T_min=None,
+                alpha_max=None):
+    """Work of walking every pixel's tile list front to back, summed over
+    all pixels of all views: examined entries (from the list's start up to
+    and including the entry that stops the pixel, or to the list's end),
+    in-box entries among them, contributing entries, and in-box entries
+    before the pixel's last contributing one (the pairs a backward pass
+    walking back from the last contributor revisits).  A tile's list is every
+    Gaussian whose integer box meets the tile's pixel rectangle, ordered by
+    (FP32 depth bits, index)."""
+    alpha_min, T_min, alpha_max = _cutoffs(alpha_min, T_min, alpha_max)
+    V, n, _ = rec.shape
+    Tx, Ty = -(-W // tile), -(-H // tile)
+    tot = dict(examined=0, inbox=0, contributing=0, revisit=0)
+    for k in range(V):
+        depth_bits = rec[k, :, 6].astype(np.float32).view(np.uint32)
+        b = box[k]
+        for ty in range(Ty):
+            for tx in range(Tx):
+                u0, v0 = tx * tile, ty * tile
+                u1, v1 = min(W, u0 + tile) - 1, min(H, v0 + tile) - 1
+                meets = ((b[:, 0] <= u1) & (b[:, 1] >= u0) & (b[:, 2] <= v1) &
+                         (b[:, 3] >= v0) & (b[:, 0] <= b[:, 1]) &
+                         (b[:, 2] <= b[:, 3]))
+                cand = np.nonzero(meets)[0]
+                lst = cand[np.lexsort((cand, depth_bits[cand]))]
+                for v in range(v0, v1 + 1):
+                    for u in range(u0, u1 + 1):
+                        T = 1.0
+                        inb_pos = []
+                        last = 0
+                        for i, g in enumerate(lst):
+                            tot["examined"] += 1
+                            if not (b[g, 0] <= u <= b[g, 1] and
+                                    b[g, 2] <= v <= b[g, 3]):
+                                continue
+                            tot["inbox"] += 1
+                            inb_pos.append(i)
+                            px, py, A, B, Cc, o = rec[k, g, :6]
+                            dx, dy = px - u, py - v
+                            pw = -0.5 * (A * dx * dx + Cc * dy * dy) - B * dx * dy
+                            if pw > 0:
+                                continue
+                            a = min(alpha_max, o * math.exp(pw))
+                            if a < alpha_min:
+                                continue
+                            Tn = T * (1.0 - a)
+                            if Tn < T_min:
+                                break
+                            T = Tn
+                            tot["contributing"] += 1
+                            last = i + 1
+                        tot["revisit"] += sum(1 for i in inb_pos if i < last)
+    return tot

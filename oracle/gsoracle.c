@@ -31,6 +31,7 @@
  * mode the projected record is rounded to FP32 (round-to-nearest-even) and
  * widened again, which is what the GPU path composites with.
  */
+#include <limits.h>
 #include <math.h>
 #include <stdint.h>
 #include <stdlib.h>
@@ -525,6 +526,96 @@ OR_EXPORT int or_forward(int V, int W, int H, int tile, int n,
   return bad ? -1 : 0;
 }
 
+/* The front-to-back walk of or_forward at selected pixels only, listing the
+ * walk: for each pixel pix[i] (flat index (k H + v) W + u), every entry of
+ * its tile's list whose integer box holds the pixel, in list order, up to
+ * and including the entry that stops the pixel: out_g [npix][maxw] the
+ * Gaussian, out_w the blend weight alpha T it receives (0 when it does not
+ * contribute), out_code the decision (DEC_SKIP, DEC_ADMIT, DEC_CLAMP,
+ * DEC_STOP); out_cnt [npix] the number listed.  Returns -1 when a pixel
+ * lists more than maxw entries. */
+OR_EXPORT int or_pixel_walk(int V, int W, int H, int tile, int n,
+                            const double* rec, const int32_t* box,
+                            const uint32_t* vals, const uint32_t* ranges,
+                            double alpha_min, double T_min, double alpha_max,
+                            int npix, const int64_t* pix, int maxw,
+                            int32_t* out_g, double* out_w, uint8_t* out_code,
+                            int32_t* out_cnt) {
+  fwdcfg F = {W, H, tile, (W + tile - 1) / tile, (H + tile - 1) / tile, n,
+              alpha_min, T_min, alpha_max, {0.0, 0.0, 0.0}};
+  int bad = 0;
+  for (int q = 0; q < npix; ++q) {
+    const int64_t p = pix[q];
+    const int k = (int)(p / ((int64_t)W * H));
+    const int rem = (int)(p % ((int64_t)W * H));
+    const int v = rem / W, u = rem % W;
+    if (p < 0 || k >= V) { bad = 1; out_cnt[q] = 0; continue; }
+    const int64_t t = ((int64_t)k * F.Ty + v / tile) * F.Tx + u / tile;
+    double T = 1.0;
+    int m = 0;
+    for (uint32_t i = ranges[2 * t]; i < ranges[2 * t + 1]; ++i) {
+      const uint32_t g = vals[i];
+      const double* r = &rec[((size_t)k * n + g) * REC_STRIDE];
+      const int32_t* b = &box[((size_t)k * n + g) * 4];
+      if (u < b[0] || u > b[1] || v < b[2] || v > b[3]) continue;
+      double alpha = 0, G = 0, dx = 0, dy = 0;
+      const int code = eval_pair(&F, r, b, u, v, T, &alpha, &G, &dx, &dy,
+                                 NULL, NULL, 0.0);
+      if (m >= maxw) { bad = 1; break; }
+      const size_t o = (size_t)q * maxw + m;
+      out_g[o] = (int32_t)g;
+      out_code[o] = (uint8_t)code;
+      out_w[o] = (code == DEC_ADMIT || code == DEC_CLAMP) ? alpha * T : 0.0;
+      ++m;
+      if (code == DEC_STOP) break;
+      if (code == DEC_ADMIT || code == DEC_CLAMP) T = T * (1.0 - alpha);
+    }
+    out_cnt[q] = m;
+  }
+  return bad ? -1 : 0;
+}
+
+/* Where a Gaussian can be admitted at all: for every view k and Gaussian g
+ * with a non-empty integer box, the smallest pixel rectangle holding every
+ * pixel of the box at which an FP32 evaluation of alpha could reach
+ * alpha_min, i.e. where o exp(pi) >= alpha_min (1 - max(1e-5, ea)) with the
+ * FP32 error bound ea of the pair's alpha and pi <= 8 eps S (the exponent's
+ * sign within its rounding).  rect [V][n][4] = (u_lo, u_hi, v_lo, v_hi), or
+ * (0, -1, 0, -1) when no pixel qualifies.  Transmittance is ignored, so the
+ * rectangle holds every pixel where the Gaussian might contribute. */
+OR_EXPORT void or_admit_extent(int V, int n, const double* rec,
+                               const int32_t* box, double alpha_min,
+                               int32_t* rect, int nthreads) {
+#ifdef _OPENMP
+  if (nthreads < 1) nthreads = 1;
+#pragma omp parallel for schedule(dynamic, 64) num_threads(nthreads)
+#endif
+  for (int64_t kg = 0; kg < (int64_t)V * n; ++kg) {
+    const double* r = &rec[(size_t)kg * REC_STRIDE];
+    const int32_t* b = &box[(size_t)kg * 4];
+    int32_t* o = &rect[(size_t)kg * 4];
+    o[0] = 0; o[1] = -1; o[2] = 0; o[3] = -1;
+    if (b[1] < b[0] || b[3] < b[2]) continue;
+    const double px = r[0], py = r[1], A = r[2], B = r[3], C = r[4], op = r[5];
+    int ulo = INT32_MAX, uhi = -1, vlo = INT32_MAX, vhi = -1;
+    for (int v = b[2]; v <= b[3]; ++v)
+      for (int u = b[0]; u <= b[1]; ++u) {
+        const double dx = px - (double)u, dy = py - (double)v;
+        const double pw = -0.5 * (A * dx * dx + C * dy * dy) - B * dx * dy;
+        const double S = fabs(A) * dx * dx + 2.0 * fabs(B) * fabs(dx * dy) +
+                         fabs(C) * dy * dy;
+        if (pw > 8.0 * EPS32 * S) continue;
+        const double ea = EPS32 * (4.0 * S + 4.0);
+        if (op * exp(pw) < alpha_min * (1.0 - fmax(1e-5, ea))) continue;
+        if (u < ulo) ulo = u;
+        if (u > uhi) uhi = u;
+        if (v < vlo) vlo = v;
+        if (v > vhi) vhi = v;
+      }
+    if (uhi >= 0) { o[0] = ulo; o[1] = uhi; o[2] = vlo; o[3] = vhi; }
+  }
+}
+
 /* ---- Backward of the compositing (exact derivative of Eq. 3 with the
  * decision set fixed). ---- */
 
@@ -672,6 +763,114 @@ OR_EXPORT int or_backward(int V, int W, int H, int tile, int n,
 
 /* ---- Backward of the projection (chain rule through Eq. 2 and Eq. 1). ---- */
 
+/* Chain rule of one view: adds to dmu [3], dl [3], dq [4] the gradients that
+ * the screen-space gradient d = dL/d(px, py, A, B, C) of view cam sends back
+ * through Eq. 2 (conic -> screen covariance -> Jacobian, world-to-camera
+ * rotation and camera-space mean) and Eq. 1 (covariance -> rotation and
+ * scale -> quaternion and log-scale).  Linear in d. */
+static void chain_view(const ocam* cam, const proj_t* P, const double* d,
+                       double* dmu, double* dl, double* dq) {
+  const double dpx = d[0], dpy = d[1], dA = d[2], dB = d[3], dC = d[4];
+  if (dpx == 0.0 && dpy == 0.0 && dA == 0.0 && dB == 0.0 && dC == 0.0)
+    return;
+  const double a = P->a, b = P->b, c = P->c, det = P->det;
+  const double det2 = det * det;
+  /* conic (A, B, C) = (c, -b, a) / det  ->  (a, b, c) */
+  const double da = dA * (-c * c / det2) + dB * (b * c / det2) +
+                    dC * (1.0 / det - a * c / det2);
+  const double db = dA * (2.0 * b * c / det2) +
+                    dB * (-1.0 / det - 2.0 * b * b / det2) +
+                    dC * (2.0 * a * b / det2);
+  const double dc = dA * (1.0 / det - c * a / det2) + dB * (b * a / det2) +
+                    dC * (-a * a / det2);
+  /* a = T0 Sig T0^T + 0.3, b = T0 Sig T1^T, c = T1 Sig T1^T + 0.3 */
+  const double* T0 = &P->Tm[0];
+  const double* T1 = &P->Tm[3];
+  double ST0[3], ST1[3];
+  for (int i = 0; i < 3; ++i) {
+    ST0[i] = P->Sig[3 * i] * T0[0] + P->Sig[3 * i + 1] * T0[1] +
+             P->Sig[3 * i + 2] * T0[2];
+    ST1[i] = P->Sig[3 * i] * T1[0] + P->Sig[3 * i + 1] * T1[1] +
+             P->Sig[3 * i + 2] * T1[2];
+  }
+  double GS[9];  /* dL/dSig_mn treating all nine entries as free */
+  for (int m = 0; m < 3; ++m)
+    for (int nn = 0; nn < 3; ++nn)
+      GS[3 * m + nn] = da * T0[m] * T0[nn] + db * T0[m] * T1[nn] +
+                       dc * T1[m] * T1[nn];
+  double dT0[3], dT1[3];
+  for (int m = 0; m < 3; ++m) {
+    dT0[m] = 2.0 * da * ST0[m] + db * ST1[m];
+    dT1[m] = db * ST0[m] + 2.0 * dc * ST1[m];
+  }
+  /* T = J W */
+  const double* Wm = cam->R;
+  double dJ00 = 0, dJ02 = 0, dJ11 = 0, dJ12 = 0;
+  for (int j = 0; j < 3; ++j) {
+    dJ00 += dT0[j] * Wm[j];
+    dJ02 += dT0[j] * Wm[6 + j];
+    dJ11 += dT1[j] * Wm[3 + j];
+    dJ12 += dT1[j] * Wm[6 + j];
+  }
+  const double tx = P->t[0], ty = P->t[1], tz = P->t[2];
+  const double tz2 = tz * tz, tz3 = tz2 * tz;
+  double dt[3] = {0, 0, 0};
+  /* J00 = fx/tz, J11 = fy/tz */
+  dt[2] += dJ00 * (-cam->fx / tz2) + dJ11 * (-cam->fy / tz2);
+  /* J02 = -fx xc / tz^2, xc = tx (unclamped) or +-limx tz (clamped) */
+  const double dxc_dtx = P->clampx ? 0.0 : 1.0;
+  const double dxc_dtz = P->clampx ? (double)P->clampx * P->limx : 0.0;
+  const double dyc_dty = P->clampy ? 0.0 : 1.0;
+  const double dyc_dtz = P->clampy ? (double)P->clampy * P->limy : 0.0;
+  dt[0] += dJ02 * (-cam->fx / tz2) * dxc_dtx;
+  dt[2] += dJ02 * (-cam->fx / tz2 * dxc_dtz + 2.0 * cam->fx * P->xc / tz3);
+  dt[1] += dJ12 * (-cam->fy / tz2) * dyc_dty;
+  dt[2] += dJ12 * (-cam->fy / tz2 * dyc_dtz + 2.0 * cam->fy * P->yc / tz3);
+  /* px = fx tx / tz + cx, py = fy ty / tz + cy */
+  dt[0] += dpx * cam->fx / tz;
+  dt[2] += dpx * (-cam->fx * tx / tz2);
+  dt[1] += dpy * cam->fy / tz;
+  dt[2] += dpy * (-cam->fy * ty / tz2);
+  /* t = W mu + t_k */
+  for (int j = 0; j < 3; ++j)
+    dmu[j] += Wm[j] * dt[0] + Wm[3 + j] * dt[1] + Wm[6 + j] * dt[2];
+  /* Sig = M M^T: dM = (GS + GS^T) M */
+  double dM[9];
+  for (int i = 0; i < 3; ++i)
+    for (int j = 0; j < 3; ++j) {
+      double acc = 0.0;
+      for (int m = 0; m < 3; ++m)
+        acc += (GS[3 * i + m] + GS[3 * m + i]) * P->M[3 * m + j];
+      dM[3 * i + j] = acc;
+    }
+  /* M = R diag(s) */
+  double dR[9], ds[3] = {0, 0, 0};
+  for (int i = 0; i < 3; ++i)
+    for (int j = 0; j < 3; ++j) {
+      dR[3 * i + j] = dM[3 * i + j] * P->s[j];
+      ds[j] += dM[3 * i + j] * P->Rq[3 * i + j];
+    }
+  for (int j = 0; j < 3; ++j) dl[j] += ds[j] * P->s[j];
+  /* R(w, x, y, z) of the normalised quaternion */
+  const double w = P->qn[0], x = P->qn[1], y = P->qn[2], z = P->qn[3];
+  double dqn[4];
+  dqn[0] = 2.0 * (-z * dR[1] + y * dR[2] + z * dR[3] - x * dR[5] -
+                  y * dR[6] + x * dR[7]);
+  dqn[1] = 2.0 * (y * dR[1] + z * dR[2] + y * dR[3] - w * dR[5] +
+                  z * dR[6] + w * dR[7]) -
+           4.0 * x * (dR[4] + dR[8]);
+  dqn[2] = 2.0 * (x * dR[1] + w * dR[2] + x * dR[3] + z * dR[5] -
+                  w * dR[6] + z * dR[7]) -
+           4.0 * y * (dR[0] + dR[8]);
+  dqn[3] = 2.0 * (-w * dR[1] + x * dR[2] + w * dR[3] + y * dR[5] +
+                  x * dR[6] + y * dR[7]) -
+           4.0 * z * (dR[0] + dR[4]);
+  /* qn = q / |q| */
+  const double dot = dqn[0] * w + dqn[1] * x + dqn[2] * y + dqn[3] * z;
+  for (int j = 0; j < 4; ++j)
+    dq[j] += (dqn[j] - P->qn[j] * dot) / P->qnorm;
+}
+
 /* cams [V][19]; g2d [V][n][5]; gop [n]; grgb_in [3][n].  Outputs
  * (overwritten) in planar layout: gmean [3][n], glsc [3][n], gquat [4][n],
  * gopl [n], grgb [3][n]. */
@@ -698,106 +897,7 @@ OR_EXPORT int or_project_bwd(int V, int n, const double* mean,
       project_one(&cam, mean[g], mean[n + g], mean[2 * n + g], l, q, opl[g],
                   &P);
       if (!P.valid) continue;
-      const double* d = &g2d[((size_t)k * n + g) * 5];
-      const double dpx = d[0], dpy = d[1], dA = d[2], dB = d[3], dC = d[4];
-      if (dpx == 0.0 && dpy == 0.0 && dA == 0.0 && dB == 0.0 && dC == 0.0)
-        continue;
-      const double a = P.a, b = P.b, c = P.c, det = P.det;
-      const double det2 = det * det;
-      /* conic (A, B, C) = (c, -b, a) / det  ->  (a, b, c) */
-      const double da = dA * (-c * c / det2) + dB * (b * c / det2) +
-                        dC * (1.0 / det - a * c / det2);
-      const double db = dA * (2.0 * b * c / det2) +
-                        dB * (-1.0 / det - 2.0 * b * b / det2) +
-                        dC * (2.0 * a * b / det2);
-      const double dc = dA * (1.0 / det - c * a / det2) + dB * (b * a / det2) +
-                        dC * (-a * a / det2);
-      /* a = T0 Sig T0^T + 0.3, b = T0 Sig T1^T, c = T1 Sig T1^T + 0.3 */
-      const double* T0 = &P.Tm[0];
-      const double* T1 = &P.Tm[3];
-      double ST0[3], ST1[3];
-      for (int i = 0; i < 3; ++i) {
-        ST0[i] = P.Sig[3 * i] * T0[0] + P.Sig[3 * i + 1] * T0[1] +
-                 P.Sig[3 * i + 2] * T0[2];
-        ST1[i] = P.Sig[3 * i] * T1[0] + P.Sig[3 * i + 1] * T1[1] +
-                 P.Sig[3 * i + 2] * T1[2];
-      }
-      double GS[9];  /* dL/dSig_mn treating all nine entries as free */
-      for (int m = 0; m < 3; ++m)
-        for (int nn = 0; nn < 3; ++nn)
-          GS[3 * m + nn] = da * T0[m] * T0[nn] + db * T0[m] * T1[nn] +
-                           dc * T1[m] * T1[nn];
-      double dT0[3], dT1[3];
-      for (int m = 0; m < 3; ++m) {
-        dT0[m] = 2.0 * da * ST0[m] + db * ST1[m];
-        dT1[m] = db * ST0[m] + 2.0 * dc * ST1[m];
-      }
-      /* T = J W */
-      const double* Wm = cam.R;
-      double dJ00 = 0, dJ02 = 0, dJ11 = 0, dJ12 = 0;
-      for (int j = 0; j < 3; ++j) {
-        dJ00 += dT0[j] * Wm[j];
-        dJ02 += dT0[j] * Wm[6 + j];
-        dJ11 += dT1[j] * Wm[3 + j];
-        dJ12 += dT1[j] * Wm[6 + j];
-      }
-      const double tx = P.t[0], ty = P.t[1], tz = P.t[2];
-      const double tz2 = tz * tz, tz3 = tz2 * tz;
-      double dt[3] = {0, 0, 0};
-      /* J00 = fx/tz, J11 = fy/tz */
-      dt[2] += dJ00 * (-cam.fx / tz2) + dJ11 * (-cam.fy / tz2);
-      /* J02 = -fx xc / tz^2, xc = tx (unclamped) or +-limx tz (clamped) */
-      const double dxc_dtx = P.clampx ? 0.0 : 1.0;
-      const double dxc_dtz = P.clampx ? (double)P.clampx * P.limx : 0.0;
-      const double dyc_dty = P.clampy ? 0.0 : 1.0;
-      const double dyc_dtz = P.clampy ? (double)P.clampy * P.limy : 0.0;
-      dt[0] += dJ02 * (-cam.fx / tz2) * dxc_dtx;
-      dt[2] += dJ02 * (-cam.fx / tz2 * dxc_dtz + 2.0 * cam.fx * P.xc / tz3);
-      dt[1] += dJ12 * (-cam.fy / tz2) * dyc_dty;
-      dt[2] += dJ12 * (-cam.fy / tz2 * dyc_dtz + 2.0 * cam.fy * P.yc / tz3);
-      /* px = fx tx / tz + cx, py = fy ty / tz + cy */
-      dt[0] += dpx * cam.fx / tz;
-      dt[2] += dpx * (-cam.fx * tx / tz2);
-      dt[1] += dpy * cam.fy / tz;
-      dt[2] += dpy * (-cam.fy * ty / tz2);
-      /* t = W mu + t_k */
-      for (int j = 0; j < 3; ++j)
-        dmu[j] += Wm[j] * dt[0] + Wm[3 + j] * dt[1] + Wm[6 + j] * dt[2];
-      /* Sig = M M^T: dM = (GS + GS^T) M */
-      double dM[9];
-      for (int i = 0; i < 3; ++i)
-        for (int j = 0; j < 3; ++j) {
-          double acc = 0.0;
-          for (int m = 0; m < 3; ++m)
-            acc += (GS[3 * i + m] + GS[3 * m + i]) * P.M[3 * m + j];
-          dM[3 * i + j] = acc;
-        }
-      /* M = R diag(s) */
-      double dR[9], ds[3] = {0, 0, 0};
-      for (int i = 0; i < 3; ++i)
-        for (int j = 0; j < 3; ++j) {
-          dR[3 * i + j] = dM[3 * i + j] * P.s[j];
-          ds[j] += dM[3 * i + j] * P.Rq[3 * i + j];
-        }
-      for (int j = 0; j < 3; ++j) dl[j] += ds[j] * P.s[j];
-      /* R(w, x, y, z) of the normalised quaternion */
-      const double w = P.qn[0], x = P.qn[1], y = P.qn[2], z = P.qn[3];
-      double dqn[4];
-      dqn[0] = 2.0 * (-z * dR[1] + y * dR[2] + z * dR[3] - x * dR[5] -
-                      y * dR[6] + x * dR[7]);
-      dqn[1] = 2.0 * (y * dR[1] + z * dR[2] + y * dR[3] - w * dR[5] +
-                      z * dR[6] + w * dR[7]) -
-               4.0 * x * (dR[4] + dR[8]);
-      dqn[2] = 2.0 * (x * dR[1] + w * dR[2] + x * dR[3] + z * dR[5] -
-                      w * dR[6] + z * dR[7]) -
-               4.0 * y * (dR[0] + dR[8]);
-      dqn[3] = 2.0 * (-w * dR[1] + x * dR[2] + w * dR[3] + y * dR[5] +
-                      x * dR[6] + y * dR[7]) -
-               4.0 * z * (dR[0] + dR[4]);
-      /* qn = q / |q| */
-      const double dot = dqn[0] * w + dqn[1] * x + dqn[2] * y + dqn[3] * z;
-      for (int j = 0; j < 4; ++j)
-        dq[j] += (dqn[j] - P.qn[j] * dot) / P.qnorm;
+      chain_view(&cam, &P, &g2d[((size_t)k * n + g) * 5], dmu, dl, dq);
     }
     for (int j = 0; j < 3; ++j) {
       gmean[(size_t)j * n + g] = dmu[j];
@@ -807,6 +907,67 @@ OR_EXPORT int or_project_bwd(int V, int n, const double* mean,
     for (int j = 0; j < 4; ++j) gquat[(size_t)j * n + g] = dq[j];
     const double o = 1.0 / (1.0 + exp(-opl[g]));
     gopl[g] = gop[g] * o * (1.0 - o);
+  }
+  return 0;
+}
+
+/* Magnitudes through the projection backward: for non-negative per-view
+ * screen-space magnitudes x2d [V][n][5] (for instance |dL/d(px, py, A, B,
+ * C)|), every output receives the sum over views k and screen quantities c
+ * of |d output / d g2d[k][g][c]| x2d[k][g][c] -- the sum of the absolute
+ * values of the chain-rule terms that the projection backward adds up (the
+ * chain is linear in g2d, so each column is the chain of one unit input).
+ * The opacity magnitude xop [n] is scaled by o (1 - o) and the colour
+ * magnitude xrgb [3][n] passed through.  Outputs in the layout of
+ * or_project_bwd. */
+OR_EXPORT int or_project_bwd_abs(int V, int n, const double* mean,
+                                 const double* lsc, const double* quat,
+                                 const double* opl, const double* cams,
+                                 const double* x2d, const double* xop,
+                                 const double* xrgb_in, double* amean,
+                                 double* alsc, double* aquat, double* aopl,
+                                 double* argb, int nthreads) {
+#ifdef _OPENMP
+  if (nthreads < 1) nthreads = 1;
+#pragma omp parallel for schedule(static) num_threads(nthreads)
+#endif
+  for (int g = 0; g < n; ++g) {
+    double amu[3] = {0, 0, 0}, al[3] = {0, 0, 0}, aq[4] = {0, 0, 0, 0};
+    const double l[3] = {lsc[g], lsc[n + g], lsc[2 * n + g]};
+    const double q[4] = {quat[g], quat[n + g], quat[2 * n + g],
+                         quat[3 * n + g]};
+    for (int k = 0; k < V; ++k) {
+      const double* e = &x2d[((size_t)k * n + g) * 5];
+      if (e[0] == 0.0 && e[1] == 0.0 && e[2] == 0.0 && e[3] == 0.0 &&
+          e[4] == 0.0)
+        continue;
+      ocam cam;
+      cam_load(&cams[(size_t)k * 19], &cam);
+      proj_t P;
+      project_one(&cam, mean[g], mean[n + g], mean[2 * n + g], l, q, opl[g],
+                  &P);
+      if (!P.valid) continue;
+      for (int c = 0; c < 5; ++c) {
+        if (e[c] == 0.0) continue;
+        double d[5] = {0, 0, 0, 0, 0};
+        d[c] = e[c];
+        double dmu[3] = {0, 0, 0}, dl[3] = {0, 0, 0}, dq[4] = {0, 0, 0, 0};
+        chain_view(&cam, &P, d, dmu, dl, dq);
+        for (int j = 0; j < 3; ++j) {
+          amu[j] += fabs(dmu[j]);
+          al[j] += fabs(dl[j]);
+        }
+        for (int j = 0; j < 4; ++j) aq[j] += fabs(dq[j]);
+      }
+    }
+    for (int j = 0; j < 3; ++j) {
+      amean[(size_t)j * n + g] = amu[j];
+      alsc[(size_t)j * n + g] = al[j];
+      argb[(size_t)j * n + g] = xrgb_in[(size_t)j * n + g];
+    }
+    for (int j = 0; j < 4; ++j) aquat[(size_t)j * n + g] = aq[j];
+    const double o = 1.0 / (1.0 + exp(-opl[g]));
+    aopl[g] = xop[g] * o * (1.0 - o);
   }
   return 0;
 }

@@ -175,3 +175,43 @@ def chain(p: dict, cams, D: int, bwd: dict, nthreads: int = 1) -> dict:
     out["mean"] = out["mean"] + d_mean
     out["sh"] = d_sh
     return out
+
+
+def colours_bwd_abs(p: dict, cams, D: int, gcol: np.ndarray):
+    """Magnitudes of the terms colours_bwd adds up, for the same per-view
+    colour gradients gcol [V][3][n]: every partial derivative and gradient
+    by absolute value (the direction chain as |(I - d d^T) / |v|| applied to
+    sum_j |dY_j| |f_j| |g|).  Returns d_rgb, d_sh, d_mean magnitudes."""
+    rgb = np.asarray(p["rgb"], np.float64)
+    n = rgb.shape[1]
+    gabs = np.abs(np.asarray(gcol, np.float64))
+    if D == 0:
+        return gabs.sum(0), np.zeros((0, 3, n)), np.zeros((3, n))
+    sh = np.asarray(p["sh"], np.float64)
+    _, raw = colours(p, cams, D)
+    d_rgb = np.zeros((3, n))
+    d_sh = np.zeros_like(sh)
+    d_mean = np.zeros((3, n))
+    for k, cam in enumerate(cams):
+        d, inv_r = _directions(p["mean"], cam)
+        g = np.where(raw[k] >= 0.0, gabs[k], 0.0)     # [3][n]
+        d_rgb += g
+        Y = np.abs(basis(D, d)[:, 1:])                # [n][K-1]
+        d_sh += np.einsum("nj,cn->jcn", Y, g)
+        dY = np.abs(basis_grad(D, d)[:, 1:, :])       # [n][K-1][3]
+        gd = np.einsum("njx,jcn,cn->nx", dY, np.abs(sh), g)
+        P = np.abs(np.eye(3)[None] - d[:, :, None] * d[:, None, :])
+        d_mean += (np.einsum("nxy,ny->nx", P, gd) * inv_r[:, None]).T
+    return d_rgb, d_sh, d_mean
+
+
+def chain_abs(p: dict, cams, D: int, bwd: dict, nthreads: int = 1) -> dict:
+    """Magnitudes of the chain-rule terms of chain() (see
+    oracle.project_bwd_abs): the screen-space part through the projection
+    backward, the colour part through colours_bwd_abs."""
+    from . import project_bwd_abs
+    d_rgb, d_sh, d_mean = colours_bwd_abs(p, cams, D, bwd["grgb"])
+    out = project_bwd_abs(p, cams, dict(bwd, grgb=d_rgb), nthreads)
+    out["mean"] = out["mean"] + d_mean
+    out["sh"] = d_sh
+    return out

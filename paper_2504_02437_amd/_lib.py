@@ -61,7 +61,8 @@ class gs_workspace_view(C.Structure):
                 ("render_box", C.c_void_p), ("ranges", C.c_void_p), ("vals_sorted", C.c_void_p),
                 ("keys_sorted", C.c_void_p), ("grad2d", C.c_void_p),
                 ("n_keys", C.c_void_p), ("status", C.c_void_p),
-                ("tiles_x", C.c_int32), ("tiles_y", C.c_int32)]
+                ("tiles_x", C.c_int32), ("tiles_y", C.c_int32),
+                ("grad_opacity", C.c_void_p), ("grad_colour", C.c_void_p)]
 
 
 _P = C.POINTER

@@ -273,6 +273,8 @@ int gs_workspace_get_view(const gs_workspace* ws, gs_workspace_view* out) {
   out->status = &ws->counters->status;
   out->tiles_x = ws->tiles_x;
   out->tiles_y = ws->tiles_y;
+  out->grad_opacity = ws->gop;
+  out->grad_colour = ws->gcol;
   return GS_OK;
 }
 

@@ -228,6 +228,15 @@ class Workspace:
         return self._slice(self.view.grad2d, torch.float32, V * 5 * cap).view(
             V, 5, cap)
 
+    def grad_opacity(self):
+        return self._slice(self.view.grad_opacity, torch.float32,
+                           self.geo.capacity)
+
+    def grad_colour(self):
+        V, cap = self.geo.n_views, self.geo.capacity
+        return self._slice(self.view.grad_colour, torch.float32,
+                           V * 3 * cap).view(V, 3, cap)
+
 
 # ---- The C ABI under its own names ---------------------------------------
 

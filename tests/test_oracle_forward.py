@@ -197,3 +197,97 @@ def test_work_counters():
     _, _, nb = brute.composite(proj["rec"], proj["box"], p["rgb"], c.width,
                                c.height)
     assert cnt["contributing"] == int(nb.sum())
+
+
+@pytest.mark.parametrize("tile,views", [(8, 1), (16, 2), (32, 1)])
+def test_work_counters_equal_an_independent_count(tile, views):
+    """All four work counters (examined, in-box, contributing, revisited)
+    equal brute.count_pairs, which builds every tile's list from the boxes
+    that meet the tile and walks it per pixel, without the oracle's keys,
+    sort or ranges.  Dense enough that many pixels stop at T_min, so the
+    stop entry's place in the counts is pinned."""
+    w = _scene(7, n=200, mu=-1.5)
+    cams = [w.cameras[0]]
+    c = cams[0]
+    for i in range(views - 1):
+        t = (c.t + np.array([0.05 * (i + 1), -0.03, 0.02])).astype(np.float32)
+        cams.append(synth.Camera(c.R, t, c.fx, c.fy, c.cx, c.cy, c.width,
+                                 c.height))
+    p = oracle.params64(w.gaussians)
+    proj, bins, fwd = oracle.render(p, cams, tile=tile)
+    ref = brute.count_pairs(proj["rec"], proj["box"], c.width, c.height, tile)
+    assert (fwd["T"] < 1e-3).sum() > 500
+    assert fwd["counters"] == ref
+    assert ref["examined"] > ref["inbox"] > ref["revisit"] > ref["contributing"] > 0
+
+
+def test_pixel_walk_against_brute_force():
+    """oracle.pixel_walk at every pixel: the contributing entries' weights
+    and the transmittance left add to one, their count and the Gaussian of
+    largest weight equal the brute-force compositor's, and the walk's
+    in-box entries are those whose box holds the pixel, in list order."""
+    w = _scene(8, n=150, mu=-1.6)
+    c = w.cameras[0]
+    p = oracle.params64(w.gaussians)
+    proj, bins, fwd = oracle.render(p, [c], tile=16)
+    W, H = c.width, c.height
+    g, wt, code, cnt = oracle.pixel_walk(proj, bins, W, H, np.arange(W * H))
+    _, Tb, nb, domb = brute.composite(proj["rec"], proj["box"], p["rgb"], W, H,
+                                      with_dominant=True)
+    contrib = (code == oracle.DEC_ADMIT) | (code == oracle.DEC_CLAMP)
+    valid = np.arange(g.shape[1])[None, :] < cnt[:, None]
+    contrib &= valid
+    np.testing.assert_array_equal(contrib.sum(1), nb.reshape(-1))
+    np.testing.assert_allclose(wt.sum(1) + Tb.reshape(-1), 1.0, atol=1e-12)
+    best = np.where(contrib.any(1), g[np.arange(W * H), np.argmax(wt, 1)], -1)
+    np.testing.assert_array_equal(best, domb.reshape(-1))
+    np.testing.assert_array_equal(best, fwd["dom"].reshape(-1))
+    np.testing.assert_allclose(wt.max(1), fwd["w1"].reshape(-1), rtol=1e-15)
+    assert (code[valid] == oracle.DEC_STOP).sum() > 0
+    assert np.all(wt[~contrib] == 0)
+
+
+def test_admit_extent_closed_form_and_containment():
+    """An isotropic Gaussian centred on a pixel: the admissible rectangle's
+    half-width is the largest integer d with o exp(-d^2 / (2 s^2)) >=
+    alpha_min (1 - max(1e-5, ea)).  On a random scene every contributing
+    (pixel, Gaussian) pair lies in the Gaussian's rectangle, which lies in its
+    integer box."""
+    W = H = 101
+    cam = one_cam(W, H, 100.0)
+    for sigma_world, logit in ((0.02, 1.0), (0.05, -0.5)):
+        p = dict(mean=np.array([[0.0], [0.0], [2.0]]),
+                 log_scale=np.full((3, 1), math.log(sigma_world)),
+                 quat=np.array([[1.0], [0.0], [0.0], [0.0]]),
+                 opacity_logit=np.array([logit]), rgb=np.full((3, 1), 0.5))
+        proj = oracle.project(p, [cam], 16, publish=False)
+        rect = oracle.admit_extent(proj)[0, 0]
+        A = proj["rec"][0, 0, 2]
+        o = 1.0 / (1.0 + math.exp(-logit))
+        s2 = 1.0 / A
+        d = 0
+        while True:
+            nd = d + 1
+            ea = 2.0 ** -24 * (4.0 * nd * nd / s2 + 4.0)
+            if o * math.exp(-0.5 * nd * nd / s2) < oracle.ALPHA_MIN * (1 - max(1e-5, ea)):
+                break
+            d = nd
+        np.testing.assert_array_equal(rect, [50 - d, 50 + d, 50 - d, 50 + d])
+    w = _scene(9, n=150, mu=-1.6)
+    c = w.cameras[0]
+    p = oracle.params64(w.gaussians)
+    proj, bins, fwd = oracle.render(p, [c], tile=16)
+    rect = oracle.admit_extent(proj)[0]
+    box = proj["box"][0]
+    has = rect[:, 1] >= rect[:, 0]
+    assert np.all(rect[has, 0] >= box[has, 0]) and np.all(rect[has, 1] <= box[has, 1])
+    assert np.all(rect[has, 2] >= box[has, 2]) and np.all(rect[has, 3] <= box[has, 3])
+    g, wt, code, cnt = oracle.pixel_walk(proj, bins, c.width, c.height,
+                                         np.arange(c.width * c.height))
+    pix = np.repeat(np.arange(c.width * c.height), g.shape[1]).reshape(g.shape)
+    sel = (code == oracle.DEC_ADMIT) | (code == oracle.DEC_CLAMP)
+    sel &= np.arange(g.shape[1])[None, :] < cnt[:, None]
+    gg, pp = g[sel], pix[sel]
+    u, v = pp % c.width, pp // c.width
+    r = rect[gg]
+    assert np.all((u >= r[:, 0]) & (u <= r[:, 1]) & (v >= r[:, 2]) & (v <= r[:, 3]))
