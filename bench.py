@@ -447,23 +447,25 @@ def main():
     ms_graph = None
     dist = None
     if not args.no_graph:
-        log("bench: capturing one iteration in a HIP graph")
-        g = torch.cuda.CUDAGraph()
-        side = torch.cuda.Stream()
-        side.wait_stream(torch.cuda.current_stream())
-        with torch.cuda.stream(side):
-            step()
-        torch.cuda.current_stream().wait_stream(side)
-        with torch.cuda.graph(g):
-            step()
+        # The library captures the iteration (gs_window_build) and replays
+        # it (gs_window_run) on a stream of its own.
+        log("bench: capturing one iteration in a HIP graph (gs_window_build)")
+        gstream = torch.cuda.Stream()
+        gstream.wait_stream(torch.cuda.current_stream())
+        win = R.WindowGraph(rast, params, grad, target, loss,
+                            lam_l1=LAMBDA_COLOR, lam_reg=LAMBDA_REG,
+                            reg_floor=REG_FLOOR, m=m, v=v, lr=LR, beta1=0.9,
+                            beta2=0.999, eps=1e-15, step=step_dev,
+                            stream=gstream)
         for _ in range(args.warmup):
-            g.replay()
+            win.run(gstream)
         restore()
         a, b = (torch.cuda.Event(enable_timing=True) for _ in range(2))
-        a.record()
+        gstream.synchronize()
+        a.record(gstream)
         for i in range(args.steps):
-            g.replay()
-        b.record()
+            win.run(gstream)
+        b.record(gstream)
         torch.cuda.synchronize()
         ms_graph = a.elapsed_time(b) / args.steps
         log(f"bench: graph {ms_graph:.3f} ms/iteration, eager {ms_eager:.3f}")
@@ -471,14 +473,15 @@ def main():
         # region; not part of `value`).
         restore()
         evs = [torch.cuda.Event(enable_timing=True) for _ in range(51)]
-        evs[0].record()
+        evs[0].record(gstream)
         for i in range(50):
-            g.replay()
-            evs[i + 1].record()
+            win.run(gstream)
+            evs[i + 1].record(gstream)
         torch.cuda.synchronize()
         per = np.array([evs[i].elapsed_time(evs[i + 1]) for i in range(50)])
         dist = {"replays": 50,
                 **{f"p{q}": float(np.percentile(per, q)) for q in (10, 50, 90)}}
+        win.close()
 
     # The paper's full colour loss (Eq. 10): 0.8 L1 + 0.2 (1 - SSIM), reported
     # beside the headline iteration (which uses the L1 term only).

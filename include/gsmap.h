@@ -484,6 +484,71 @@ GS_API int gs_mlp_adam(float* weights, const float* dweights, float* adam_m,
                        float* adam_v, float lr, float beta1, float beta2,
                        float eps, int32_t step, void* stream);
 
+/* ---- One mapping iteration of a keyframe window as a HIP graph ----
+ *
+ * The map optimisation (Methodology: Map Optimization with Planar
+ * Regularization, Eq. 10-11) runs the same iteration over the keyframe
+ * window many times.  gs_window_build captures one iteration, on the
+ * caller's stream, into a HIP graph the handle owns (the executable graph
+ * only: the handle holds no device memory; every buffer below is borrowed
+ * and must outlive it), gs_window_run replays it, gs_window_destroy frees
+ * it.  The iteration, in order:
+ *   clear grad (every row, the live and the spare capacity), *loss_dev and
+ *   sqerr_dev[n_views] to zero;
+ *   gs_project_and_bin, gs_sort_tile_keys, gs_render_fwd into out_rgb,
+ *   out_T, out_nlast;
+ *   with GS_WINDOW_PLANAR_REG, gs_planar_reg(lambda_reg, reg_floor);
+ *   gs_render_bwd_l1 against target with lambda_l1;
+ *   gs_project_bwd;
+ *   with GS_WINDOW_ADAM, gs_adam(lr, beta1, beta2, eps, step_dev) and then
+ *   *step_dev += 1, so the next run uses the next bias correction.
+ * Each call is checked on the host at build time as the call itself checks
+ * its arguments (GS_E_INVALID / GS_E_CAPACITY, nothing captured); the graph
+ * keeps the pointers, sizes and settings of the build: rebuild after the
+ * workspace, a buffer or a setting changes.  The live Gaussian count is read
+ * on the device (params.n_dev), so insertion between runs needs no rebuild.
+ * The stream must not be the null stream and must not be capturing.  Runs,
+ * like the calls they replay, do not overlap other work on the same
+ * workspace or buffers.  Device-side overflows are reported by
+ * gs_read_status as usual.
+ *   out_rgb [V][3][H][W], out_T [V][H][W], out_nlast [V][H][W], target
+ *   [V][3][H][W] device; loss_dev device double; sqerr_dev device double
+ *   [V] or NULL; grad, adam_m, adam_v of the params layout; lr as in
+ *   gs_adam. */
+#define GS_WINDOW_PLANAR_REG 1
+#define GS_WINDOW_ADAM 2
+typedef struct gs_window gs_window;
+typedef struct gs_window_desc {
+  gs_workspace* ws;
+  gs_params params;
+  const gs_camera* cams;
+  gs_settings settings;
+  float* out_rgb;
+  float* out_T;
+  int32_t* out_nlast;
+  const float* target;
+  float lambda_l1;
+  float lambda_reg;
+  float reg_floor;
+  int32_t flags;
+  double* loss_dev;
+  double* sqerr_dev;
+  gs_params grad;
+  gs_params adam_m;
+  gs_params adam_v;
+  float lr[6];
+  float beta1;
+  float beta2;
+  float eps;
+  int32_t pad_;
+  int32_t* step_dev;
+} gs_window_desc;
+
+GS_API int gs_window_build(const gs_window_desc* desc, void* stream,
+                           gs_window** out);
+GS_API int gs_window_run(gs_window* window, void* stream);
+GS_API int gs_window_destroy(gs_window* window);
+
 /* Synchronises `stream`, then reads the workspace's status bits and key
  * count (either output may be NULL).  Returns GS_E_OVERFLOW when any status
  * bit is set, GS_OK otherwise.  clear != 0 resets the status word. */

@@ -19,6 +19,8 @@ GS_STATUS_KEY_OVERFLOW = 1
 GS_STATUS_GAUSSIAN_OVERFLOW = 2
 GS_FLAG_EMIT_KEYS = 1
 GS_FLAG_FULL_BOX = 2
+GS_WINDOW_PLANAR_REG = 1
+GS_WINDOW_ADAM = 2
 
 
 class GsError(RuntimeError):
@@ -47,6 +49,20 @@ class gs_settings(C.Structure):
                 ("bg", C.c_float * 3), ("alpha_min", C.c_float),
                 ("T_min", C.c_float), ("alpha_max", C.c_float),
                 ("flags", C.c_int32), ("block_threads", C.c_int32)]
+
+
+class gs_window_desc(C.Structure):
+    _fields_ = [("ws", C.c_void_p), ("params", gs_params), ("cams", C.c_void_p),
+                ("settings", gs_settings), ("out_rgb", C.c_void_p),
+                ("out_T", C.c_void_p), ("out_nlast", C.c_void_p),
+                ("target", C.c_void_p), ("lambda_l1", C.c_float),
+                ("lambda_reg", C.c_float), ("reg_floor", C.c_float),
+                ("flags", C.c_int32), ("loss_dev", C.c_void_p),
+                ("sqerr_dev", C.c_void_p), ("grad", gs_params),
+                ("adam_m", gs_params), ("adam_v", gs_params),
+                ("lr", C.c_float * 6), ("beta1", C.c_float),
+                ("beta2", C.c_float), ("eps", C.c_float), ("pad_", C.c_int32),
+                ("step_dev", C.c_void_p)]
 
 
 class gs_geometry(C.Structure):
@@ -121,6 +137,9 @@ _SIGS = {
                               C.c_float, C.c_float, C.c_int32, _vp]),
     "gs_read_status": (C.c_int, [_vp, _vp, _P(C.c_int32), _P(C.c_int64),
                                  C.c_int32]),
+    "gs_window_build": (C.c_int, [_P(gs_window_desc), _vp, _P(_vp)]),
+    "gs_window_run": (C.c_int, [_vp, _vp]),
+    "gs_window_destroy": (C.c_int, [_vp]),
     "gs_last_error": (C.c_char_p, []),
     "gs_version": (C.c_char_p, []),
 }

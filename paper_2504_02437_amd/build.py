@@ -45,6 +45,7 @@ UNITS = [
     ("ssim.hip", []),
     ("densify.hip", []),
     ("mlp.hip", NO_CONTRACT),
+    ("window.hip", []),
 ]
 
 

@@ -442,6 +442,77 @@ def adam(params, grad, m, v, lr, beta1, beta2, eps, step, stream=None):
            float(beta2), float(eps), s_host, s_dev, _stream(stream))
 
 
+class WindowGraph:
+    """One mapping iteration over a rasterizer's window captured as a HIP
+    graph by the library (gs_window_build): clear grad / loss / sqerr,
+    project and bin, sort, render, planar regulariser (lam_reg > 0 or
+    floor given), backward with the fused L1 term, projection backward and,
+    with m, v and step (an int32 device tensor), the Adam step that also
+    advances step.  The graph keeps the buffers' addresses: keep them alive
+    and rebuild after replacing any (for instance after fit_key_capacity
+    rebuilt the workspace)."""
+
+    def __init__(self, rast, params, grad, target, loss, lam_l1=1.0,
+                 lam_reg=0.0, reg_floor=0.01, m=None, v=None, lr=None,
+                 beta1=0.9, beta2=0.999, eps=1e-15, step=None, sqerr=None,
+                 planar_reg=True, stream=None):
+        _require_cuda(target, "target")
+        _require_cuda(loss, "loss")
+        if target.shape != rast.rgb.shape or target.dtype != torch.float32:
+            raise ValueError("target must be float32 of the rendered shape")
+        if loss.dtype != torch.float64 or loss.numel() < 1:
+            raise ValueError("loss must be a float64 device tensor")
+        if sqerr is not None and (sqerr.dtype != torch.float64 or
+                                  sqerr.numel() < rast.V):
+            raise ValueError("sqerr must hold n_views float64")
+        d = L.gs_window_desc()
+        d.ws = rast.ws.handle
+        d.params = params.struct()
+        d.cams = _ptr(rast.cams_dev)
+        d.settings = rast.settings.struct()
+        d.out_rgb, d.out_T, d.out_nlast = (_ptr(rast.rgb), _ptr(rast.T),
+                                           _ptr(rast.nlast))
+        d.target = _ptr(target)
+        d.lambda_l1, d.lambda_reg, d.reg_floor = lam_l1, lam_reg, reg_floor
+        d.loss_dev = _ptr(loss)
+        d.sqerr_dev = _ptr(sqerr) if sqerr is not None else None
+        d.grad = grad.struct()
+        flags = L.GS_WINDOW_PLANAR_REG if planar_reg else 0
+        if m is not None:
+            if step is None or step.dtype != torch.int32 or not step.is_cuda:
+                raise ValueError("the Adam step needs an int32 device step")
+            lr = [float(x) for x in lr]
+            if len(lr) == 5:
+                lr.append(lr[4] / 20.0)
+            d.adam_m, d.adam_v = m.struct(), v.struct()
+            d.lr = (C.c_float * 6)(*lr)
+            d.beta1, d.beta2, d.eps = beta1, beta2, eps
+            d.step_dev = _ptr(step)
+            flags |= L.GS_WINDOW_ADAM
+        d.flags = flags
+        self._keep = (rast, params, grad, target, loss, m, v, step, sqerr)
+        self.handle = C.c_void_p()
+        st = torch.cuda.current_stream() if stream is None else stream
+        L.call("gs_window_build", C.byref(d), C.c_void_p(st.cuda_stream),
+               C.byref(self.handle))
+
+    def run(self, stream=None):
+        st = torch.cuda.current_stream() if stream is None else stream
+        L.call("gs_window_run", self.handle, C.c_void_p(st.cuda_stream))
+
+    def close(self):
+        h = getattr(self, "handle", None)
+        if h is not None and h.value:
+            L.lib().gs_window_destroy(h)
+        self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
 def insert_gaussians(params, m, v, cam_dev, width, height, kf_rgb, kf_T, pts,
                      alpha_skip=0.9, centre_only=False, mlp_out=None,
                      n_inserted_dev=None, status_dev=None, stream=None):

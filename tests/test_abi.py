@@ -177,3 +177,21 @@ def test_parameters_gradients_and_moments_must_not_share_memory():
                                    C.c_void_p(256), C.c_void_p(256), 5, 0.9, 0,
                                    None, None, None, None) == L.GS_E_INVALID
     assert b"share memory" in lib.gs_last_error()
+
+
+def test_window_build_rejects_bad_arguments_on_the_host():
+    """gs_window_build checks its arguments before it touches the stream:
+    NULL out / desc, the null stream and missing buffers are GS_E_INVALID,
+    and out is cleared.  run and destroy of a NULL handle are safe."""
+    lib = L.lib()
+    d = L.gs_window_desc()
+    h = C.c_void_p(1234)
+    assert lib.gs_window_build(C.byref(d), C.c_void_p(8), None) == L.GS_E_INVALID
+    assert lib.gs_window_build(None, C.c_void_p(8), C.byref(h)) == L.GS_E_INVALID
+    assert h.value is None
+    assert lib.gs_window_build(C.byref(d), None, C.byref(h)) == L.GS_E_INVALID
+    assert b"null stream" in lib.gs_last_error()
+    assert lib.gs_window_build(C.byref(d), C.c_void_p(8), C.byref(h)) == L.GS_E_INVALID
+    assert b"required" in lib.gs_last_error()
+    assert lib.gs_window_run(None, None) == L.GS_E_INVALID
+    assert lib.gs_window_destroy(None) == L.GS_OK
