@@ -18,6 +18,9 @@ pytestmark = pytest.mark.gpu
 
 LR = (1.6e-4, 5e-3, 1e-3, 5e-2, 2.5e-3)
 B1, B2, EPS = 0.9, 0.999, 1e-15
+# The Adam kernel takes the betas as FP32 settings: 1 - 0.999f is 1.3e-5 off
+# 1 - 0.999, so the check below uses the FP32 values.
+B1F, B2F = float(np.float32(B1)), float(np.float32(B2))
 
 
 def _state(params, rast, target):
@@ -199,14 +202,14 @@ def test_window_graph_on_the_benchmark_window_against_the_oracle():
         # Adam from the graph's own gradient (FP64 here, FP32 on the GPU).
         s = int(start["step"])
         g64 = gg[:, :n].astype(np.float64)
-        m1 = B1 * start["m"][:, :n].cpu().numpy() + (1 - B1) * g64
-        v1 = B2 * start["v"][:, :n].cpu().numpy() + (1 - B2) * g64 * g64
+        m1 = B1F * start["m"][:, :n].cpu().numpy() + (1 - B1F) * g64
+        v1 = B2F * start["v"][:, :n].cpu().numpy() + (1 - B2F) * g64 * g64
         np.testing.assert_allclose(got["m"][:, :n].cpu().numpy(), m1,
                                    rtol=1e-5, atol=1e-12)
         np.testing.assert_allclose(got["v"][:, :n].cpu().numpy(), v1,
                                    rtol=1e-5, atol=1e-20)
         lr = np.repeat(np.asarray(LR), [3, 3, 4, 1, 3])[:, None]
-        step = lr * (m1 / (1 - B1 ** s)) / (np.sqrt(v1 / (1 - B2 ** s)) + EPS)
+        step = lr * (m1 / (1 - B1F ** s)) / (np.sqrt(v1 / (1 - B2F ** s)) + EPS)
         p1 = start["params"][:, :n].cpu().numpy().astype(np.float64) - step
         np.testing.assert_allclose(got["params"][:, :n].cpu().numpy(), p1,
                                    rtol=1e-6, atol=1e-6 * lr.max())
