@@ -439,6 +439,24 @@ GS_API int gs_insert_distance(gs_params* params, gs_params* adam_m,
                               int32_t* n_inserted_dev, int32_t* status_dev,
                               void* stream);
 
+/* gs_insert_distance for callers that cannot allocate device memory (code
+ * under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc): the same arguments, kernels and results without `scratch`.
+ * The per-candidate scratch is a file-scope device array of the library,
+ * 65536 candidates (512 KiB) per GPU, held until the process ends; more
+ * candidates (9 n_pts, or n_pts with centre_only) return GS_E_CAPACITY
+ * before any launch.  The call allocates nothing.  All calls on one GPU
+ * share that GPU's array: calls that overlap on one GPU race. */
+GS_API int gs_insert_distance_noalloc(gs_params* params, gs_params* adam_m,
+                                      gs_params* adam_v, const gs_camera* cam,
+                                      int32_t width, int32_t height,
+                                      const float* kf_rgb,
+                                      const float* pts_uvd, int32_t n_pts,
+                                      float tau, int32_t centre_only,
+                                      const float* mlp_out,
+                                      int32_t* n_inserted_dev,
+                                      int32_t* status_dev, void* stream);
+
 /* Learned initialisation: the parameter vector of the network
  * (32 -> 64 -> 64 -> 7, GELU) holds GS_MLP_PARAMS FP32 master weights,
  * W1 [32][64], b1 [64], W2 [64][64], b2 [64], W3 [64][7], b3 [7], each layer

@@ -109,6 +109,11 @@ _SIGS = {
                                      _P(gs_params), _vp, C.c_int32, C.c_int32,
                                      _vp, _vp, C.c_int32, C.c_float, C.c_int32,
                                      _vp, _vp, _vp, _vp, _vp]),
+    "gs_insert_distance_noalloc": (C.c_int, [_P(gs_params), _P(gs_params),
+                                             _P(gs_params), _vp, C.c_int32,
+                                             C.c_int32, _vp, _vp, C.c_int32,
+                                             C.c_float, C.c_int32, _vp, _vp,
+                                             _vp, _vp]),
     "gs_render_dominant": (C.c_int, [_vp, _P(gs_params), _P(gs_settings), _vp,
                                      _vp, _vp, _vp, _vp]),
     "gs_densify": (C.c_int, [_P(gs_params), _P(gs_params), _P(gs_params), _vp,

@@ -46,6 +46,7 @@ UNITS = [
     ("densify.hip", []),
     ("mlp.hip", NO_CONTRACT),
     ("window.hip", []),
+    ("noalloc.hip", []),
 ]
 
 
