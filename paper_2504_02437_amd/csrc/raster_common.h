@@ -115,12 +115,45 @@ __device__ __forceinline__ Column column(const float4& ea, float uf) {
 }
 
 // Base-2 exponent of the Gaussian at the pixel in row vf of the thread's
-// column: e2 = A2 dx^2 + B2 dx dy + C2 dy^2.  e2 > 0 happens only by
-// rounding; the callers skip such pairs.
+// column, e2 = A2 dx^2 + B2 dx dy + C2 dy^2 = a0 + dy (b0 + C2 dy) in Horner
+// form (two FMAs; its rounding error stays below 3 u S, S the sum of the
+// three terms' magnitudes).
 __device__ __forceinline__ float exponent2(const Column& c, float py, float C2,
                                            float vf, float& dy) {
   dy = py - vf;
-  return fmaf(C2 * dy, dy, fmaf(c.b0, dy, c.a0));
+  return fmaf(fmaf(C2, dy, c.b0), dy, c.a0);
+}
+
+// The Gaussian's value exp2(e2) with e2 taken as -|e2|: the exponent is a
+// negative semi-definite form, so e2 > 0 arises only by rounding next to the
+// centre, where the pair is then evaluated as at the centre (G <= 1 always).
+__device__ __forceinline__ float gauss2(float e2) {
+  return __builtin_amdgcn_exp2f(-fabsf(e2));
+}
+
+// Per staged entry and wave, two bits: bit 2w set when wave w evaluates the
+// entry at all (wave_mask), bit 2w + 1 when it may take the fast path: the
+// render box holds every pixel of the wave's footprint that lies in the
+// image, and opacity <= alpha_max (so alpha = o G needs no clamp).
+template <int TILE, int NT>
+__device__ inline int wave_bits(const Record& R, const int4& rb, int tu0,
+                                int tv0, int W, int H, float amin, float amax,
+                                bool ellipse) {
+  using Lay = PixLayout<TILE, NT>;
+  const int m = wave_mask<TILE, NT>(R, rb, tu0, tv0, amin, ellipse);
+  const bool no_clamp = R.q1.y <= amax;
+  int bits = 0;
+#pragma unroll
+  for (int w = 0; w < NT / 64; ++w) {
+    if (!((m >> w) & 1)) continue;
+    int wu, wv;
+    Lay::wave_origin(w, wu, wv);
+    const int u0 = tu0 + wu, u1 = min(W - 1, tu0 + wu + Lay::WC - 1);
+    const int v0 = tv0 + wv, v1 = min(H - 1, tv0 + wv + Lay::FH - 1);
+    const bool full = rb.x <= u0 && rb.y >= u1 && rb.z <= v0 && rb.w >= v1;
+    bits |= (no_clamp && full ? 3 : 1) << (2 * w);
+  }
+  return bits;
 }
 
 struct RasterArgs {

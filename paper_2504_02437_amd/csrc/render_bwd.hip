@@ -10,7 +10,7 @@
 //   dL/dc_i     = a_i T_i g
 //   dL/da_i     = T_i (c_i . g - S_i) - T_final (bg . g) / (1 - a_i)
 //   dL/dpi_i    = a_i dL/da_i                 (a = o exp(pi), unclamped)
-//   dL/do_i     = G_i dL/da_i
+//   dL/do_i     = G_i dL/da_i = (dL/dpi_i) / o   (summed per entry, then / o)
 // with pi = -(A dx^2 + C dy^2) / 2 - B dx dy.  A thread's pixels share dx, so
 // it accumulates only sum(dL/dpi), sum(dL/dpi dy) and sum(dL/dpi dy^2) over
 // its strip and forms the mean and conic gradients once per entry.  The nine
@@ -95,11 +95,81 @@ __device__ __forceinline__ int wave_max(int x) {
   return x;
 }
 
+__device__ __forceinline__ int wave_min(int x) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) x = min(x, __shfl_xor(x, off, 64));
+  return x;
+}
+
+template <int PPT>
+struct BwdPix {
+  float T[PPT], g0[PPT], g1[PPT], g2[PPT], Tb[PPT], Sg[PPT], vf[PPT];
+  int last[PPT];
+};
+
+// Per-lane sums of one entry over the thread's strip.
+struct EntrySums {
+  float S0, S1, S2, d_r, d_g, d_b;
+  bool hit;
+};
+
+// The backward of one entry over the thread's strip, back to front: T is
+// recovered as T_{i+1} / (1 - alpha_i) (a pair that is not admitted takes
+// alpha 0: 1 / (1 - 0) is exactly 1, so T, the weight and the running colour
+// sum come out unchanged without a select each).  FAST: the entry's render
+// box holds the whole strip, no alpha is clamped and every pixel's n_last
+// lies beyond the entry, so only the alpha threshold decides.  BG: a
+// non-zero background, whose term enters dL/dalpha.  The opacity gradient
+// is formed once per entry from S0 = sum of dL/dpi: with alpha = o G
+// unclamped, dL/dpi = alpha dL/dalpha and dL/do = G dL/dalpha = S0 / o
+// (clamped pairs add 0 to both).
+template <bool FAST, bool BG, int PPT>
+__device__ __forceinline__ EntrySums entry_bwd(BwdPix<PPT>& px,
+                                               const Column& col, float py,
+                                               float C2, float o, float cr,
+                                               float cgc, float cbc, float amin,
+                                               float amax, bool in_u, int rlo,
+                                               int rhi, int pos) {
+  EntrySums r = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, false};
+#pragma unroll
+  for (int p = 0; p < PPT; ++p) {
+    float dy;
+    const float e2 = exponent2(col, py, C2, px.vf[p], dy);
+    const float G = gauss2(e2);
+    const float oG = o * G;
+    const float al = FAST ? oG : fminf(amax, oG);
+    const bool ok = (FAST || (in_u && rlo <= p && p <= rhi &&
+                              pos < px.last[p])) && al >= amin;
+    r.hit |= ok;
+    const float alo = ok ? al : 0.f;
+    const float rom = __builtin_amdgcn_rcpf(1.f - alo);
+    const float Ti = px.T[p] * rom;                 // T_i
+    px.T[p] = Ti;
+    const float w = alo * Ti;
+    r.d_r = fmaf(w, px.g0[p], r.d_r);
+    r.d_g = fmaf(w, px.g1[p], r.d_g);
+    r.d_b = fmaf(w, px.g2[p], r.d_b);
+    const float cgp = fmaf(cr, px.g0[p], fmaf(cgc, px.g1[p], cbc * px.g2[p]));
+    const float diff = cgp - px.Sg[p];
+    const float dal = BG ? fmaf(Ti, diff, -(px.Tb[p] * rom)) : Ti * diff;
+    px.Sg[p] = fmaf(alo, diff, px.Sg[p]);
+    // Clamped alpha has no shape or opacity gradient.
+    const float dpw = FAST ? dal * alo : ((ok && !(oG > amax)) ? dal * al : 0.f);
+    const float tdy = dpw * dy;
+    r.S0 += dpw;
+    r.S1 += tdy;
+    r.S2 = fmaf(tdy, dy, r.S2);
+  }
+  return r;
+}
+
 // The per-pixel work is predicated like the forward's: every lane evaluates
 // its pixels for each entry and the admit decision selects what is
 // accumulated.  A wave starts its backward walk at the largest n_last of its
-// own pixels and skips entries no pixel of its footprint can admit.
-template <int TILE, int BATCH, int NT>
+// own pixels, skips entries no pixel of its footprint can admit and takes
+// the fast path (wave_bits, and the entry before every pixel's n_last) when
+// it can; the choice is uniform over the wave.
+template <int TILE, int BATCH, int NT, bool BG>
 __global__ __launch_bounds__(NT) void k_render_bwd(BwdArgs a) {
   using Lay = PixLayout<TILE, NT>;
   constexpr int PPT = Lay::PPT;
@@ -125,25 +195,27 @@ __global__ __launch_bounds__(NT) void k_render_bwd(BwdArgs a) {
   Lay::of(tid, cu, cv0);
   const int u = tx * TILE + cu;
   const int v0 = ty * TILE + cv0;
-  const int wave = tid >> 6;
-  __shared__ int wmask[BATCH];   // per staged entry: waves that evaluate it
-  const float uf = (float)u;
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+  __shared__ int wbits[BATCH];   // per staged entry: wave_bits
+  const float uf = pinned((float)u);
   const float amax = r.alpha_max, amin = r.alpha_min;
-  int last[PPT];
-  float T[PPT], g0[PPT], g1[PPT], g2[PPT], Tb[PPT], Sg[PPT], vf[PPT];
-  int mylast = 0;
+  BwdPix<PPT> px;
+  int mylast = 0, myfirst = 0x7fffffff;
   float l1_abs = 0.f;
   double l1_sq = 0.0;
 #pragma unroll
   for (int p = 0; p < PPT; ++p) {
     const int v = v0 + p;
-    last[p] = 0;
-    vf[p] = pinned((float)v);
-    T[p] = 1.f; g0[p] = g1[p] = g2[p] = 0.f; Tb[p] = 0.f; Sg[p] = 0.f;
+    px.last[p] = 0;
+    px.vf[p] = pinned((float)v);
+    // Pixels outside the image keep T = 0 and a zero gradient: every term
+    // they could add is zero.
+    px.T[p] = 0.f; px.g0[p] = px.g1[p] = px.g2[p] = 0.f; px.Tb[p] = 0.f;
+    px.Sg[p] = 0.f;
     if (u < r.W && v < r.H) {
       const size_t pix = (size_t)v * r.W + u;
-      T[p] = a.Tfin[(size_t)k * HW + pix];
-      last[p] = a.nlast[(size_t)k * HW + pix];
+      px.T[p] = a.Tfin[(size_t)k * HW + pix];
+      px.last[p] = a.nlast[(size_t)k * HW + pix];
       if (a.target) {
         float gg[3];
 #pragma unroll
@@ -154,14 +226,15 @@ __global__ __launch_bounds__(NT) void k_render_bwd(BwdArgs a) {
           l1_sq += (double)d * (double)d;
           gg[ch] = l1_grad(d, a.l1_scale);
         }
-        g0[p] = gg[0]; g1[p] = gg[1]; g2[p] = gg[2];
+        px.g0[p] = gg[0]; px.g1[p] = gg[1]; px.g2[p] = gg[2];
       } else {
-        g0[p] = a.dL[((size_t)k * 3 + 0) * HW + pix];
-        g1[p] = a.dL[((size_t)k * 3 + 1) * HW + pix];
-        g2[p] = a.dL[((size_t)k * 3 + 2) * HW + pix];
+        px.g0[p] = a.dL[((size_t)k * 3 + 0) * HW + pix];
+        px.g1[p] = a.dL[((size_t)k * 3 + 1) * HW + pix];
+        px.g2[p] = a.dL[((size_t)k * 3 + 2) * HW + pix];
       }
-      Tb[p] = T[p] * (r.bg0 * g0[p] + r.bg1 * g1[p] + r.bg2 * g2[p]);
-      mylast = max(mylast, last[p]);
+      px.Tb[p] = px.T[p] * (r.bg0 * px.g0[p] + r.bg1 * px.g1[p] + r.bg2 * px.g2[p]);
+      mylast = max(mylast, px.last[p]);
+      myfirst = min(myfirst, px.last[p]);
     }
   }
   // The tile's share of the fused L1 loss: wave sums, then one plain store
@@ -182,7 +255,9 @@ __global__ __launch_bounds__(NT) void k_render_bwd(BwdArgs a) {
   if (tid == 0) smax = 0;
   __syncthreads();
   atomicMax(&smax, mylast);
-  const int wlast = wave_max(mylast);
+  const int wlast = __builtin_amdgcn_readfirstlane(wave_max(mylast));
+  // Entries before every pixel's n_last: no per-pixel position test.
+  const int wfirst = __builtin_amdgcn_readfirstlane(wave_min(myfirst));
   __syncthreads();
   if (a.target && tid == 0) {
     double la = 0.0, lq = 0.0;
@@ -209,72 +284,45 @@ __global__ __launch_bounds__(NT) void k_render_bwd(BwdArgs a) {
       const Record R = rv[g];
       const int4 box = unpack_box(rbv[g]);
       stage(ent[i], R, box);
-      wmask[i] = wave_mask<TILE, NT>(R, box, tx * TILE, ty * TILE, amin,
-                                     r.ellipse_test);
+      wbits[i] = wave_bits<TILE, NT>(R, box, tx * TILE, ty * TILE, r.W, r.H,
+                                     amin, amax, r.ellipse_test);
     }
     for (int i = tid; i < cnt * 9; i += NT) (&acc[0][0])[i] = 0.f;
     __syncthreads();
     for (int j = min(cnt, wlast - lo) - 1; j >= 0; --j) {
       const int pos = lo + j;
-      if (!((wmask[j] >> wave) & 1)) continue;
-      const int4 box = ent[j].box;
+      const int wb = __builtin_amdgcn_readfirstlane(wbits[j]) >> (2 * wave);
+      if (!(wb & 1)) continue;
       const float4 ea = ent[j].a;
       const float4 eb = ent[j].b;
       const float4 ec = ent[j].c;
-      const bool in_u = u >= box.x && u <= box.y;
-      const int rlo = box.z - v0, rhi = box.w - v0;
       const Column col = column(ea, uf);
-      float d_o = 0.f, d_r = 0.f, d_g = 0.f, d_b = 0.f;
-      float S0 = 0.f, S1 = 0.f, S2 = 0.f;
-      bool hit = false;
-#pragma unroll
-      for (int p = 0; p < PPT; ++p) {
-        float dy;
-        const float e2 = exponent2(col, ea.y, eb.x, vf[p], dy);
-        const float G = __builtin_amdgcn_exp2f(e2);
-        const float oG = eb.y * G;
-        const float al = fminf(amax, oG);
-        const bool ok = in_u && rlo <= p && p <= rhi && pos < last[p] &&
-                        !(e2 > 0.f) && al >= amin;
-        hit |= ok;
-        // A pair that is not admitted takes alpha 0: 1 / (1 - 0) is exactly
-        // 1, so T, the weight and the running colour sum below come out
-        // unchanged without a select each.
-        const float alo = ok ? al : 0.f;
-        const float rom = __builtin_amdgcn_rcpf(1.f - alo);
-        const float Ti = T[p] * rom;                 // T_i
-        T[p] = Ti;
-        const float w = alo * Ti;
-        d_r = fmaf(w, g0[p], d_r);
-        d_g = fmaf(w, g1[p], d_g);
-        d_b = fmaf(w, g2[p], d_b);
-        const float cg = fmaf(eb.z, g0[p], fmaf(eb.w, g1[p], ec.x * g2[p]));
-        const float diff = cg - Sg[p];
-        const float dal = fmaf(Ti, diff, -(Tb[p] * rom));
-        Sg[p] = fmaf(alo, diff, Sg[p]);
-        // Clamped alpha has no shape or opacity gradient.
-        const float dalm = (ok && !(oG > amax)) ? dal : 0.f;
-        const float dpw = dalm * al;
-        d_o = fmaf(dalm, G, d_o);
-        const float tdy = dpw * dy;
-        S0 += dpw;
-        S1 += tdy;
-        S2 = fmaf(tdy, dy, S2);
+      EntrySums es;
+      if ((wb & 2) && pos < wfirst) {
+        es = entry_bwd<true, BG>(px, col, ea.y, eb.x, eb.y, eb.z, eb.w, ec.x,
+                                 amin, amax, true, 0, 0, pos);
+      } else {
+        const int4 box = ent[j].box;
+        const bool in_u = u >= box.x && u <= box.y;
+        es = entry_bwd<false, BG>(px, col, ea.y, eb.x, eb.y, eb.z, eb.w, ec.x,
+                                  amin, amax, in_u, box.z - v0, box.w - v0,
+                                  pos);
       }
-      if (__any(hit)) {
+      if (__any(es.hit)) {
         const float A = ec.y, B = ec.z, C = ec.w;
-        const float dx = col.dx, dxS0 = dx * S0;
-        const float d_px = -fmaf(A, dxS0, B * S1);
-        const float d_py = -fmaf(C, S1, B * dxS0);
+        const float dx = col.dx, dxS0 = dx * es.S0;
+        const float d_px = -fmaf(A, dxS0, B * es.S1);
+        const float d_py = -fmaf(C, es.S1, B * dxS0);
         const float d_A = -0.5f * dx * dxS0;
-        const float d_B = -dx * S1;
-        const float d_C = -0.5f * S2;
+        const float d_B = -dx * es.S1;
+        const float d_C = -0.5f * es.S2;
+        const float d_o = es.S0 * __builtin_amdgcn_rcpf(eb.y);
         // Row sums of the nine quantities, added into the entry's LDS slot
         // by lanes 0, 4, 8, 12 of each row (the four rows of the wave and
         // the other waves of the tile meet in the LDS adds).
         const float x = row_sum4(d_px, d_py, d_A, d_B, bank02, bank01);
-        const float y = row_sum4(d_C, d_o, d_r, d_g, bank02, bank01);
-        const float z = row_sum(d_b);
+        const float y = row_sum4(d_C, d_o, es.d_r, es.d_g, bank02, bank01);
+        const float z = row_sum(es.d_b);
         float* ac = acc[j];
         if ((lane & 3) == 0) {
           const int q = (lane >> 2) & 3;
@@ -339,11 +387,16 @@ __global__ __launch_bounds__(1024) void k_l1_reduce(const double2* tile_loss,
 struct BwdLauncher {
   const BwdArgs& a;
   int blocks;
+  bool bg;
   hipStream_t st;
   template <int T, int B, int N>
   void go() const {
-    hipLaunchKernelGGL((k_render_bwd<T, B, N>), dim3(blocks), dim3(N), 0, st,
-                       a);
+    if (bg)
+      hipLaunchKernelGGL((k_render_bwd<T, B, N, true>), dim3(blocks), dim3(N),
+                         0, st, a);
+    else
+      hipLaunchKernelGGL((k_render_bwd<T, B, N, false>), dim3(blocks),
+                         dim3(N), 0, st, a);
   }
 };
 
@@ -370,8 +423,9 @@ hipError_t launch_render_bwd(gs_workspace* ws, const gs_settings* s,
   a.grgb_vstride = per_view_colour ? (size_t)3 * ws->geo.capacity : 0;
   const int blocks = ws->geo.n_views * ws->tiles_x * ws->tiles_y;
   if (blocks <= 0) return hipSuccess;
+  const bool bg = s->bg[0] != 0.f || s->bg[1] != 0.f || s->bg[2] != 0.f;
   dispatch_shape(ws->geo.tile, s->lds_batch, s->block_threads,
-                 BwdLauncher{a, blocks, st});
+                 BwdLauncher{a, blocks, bg, st});
   if (l1) {
     const hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;

@@ -34,12 +34,65 @@ struct FwdArgs {
 // output is |T|.  T >= T_min > 0 holds for every accepted step, so a live
 // pixel's T is never zero, and a stopped pixel needs no test of its own: its
 // candidate T (1 - alpha) is negative, below T_min, so it never contributes,
-// and stopping it again (T = -|T|) leaves it as it is.  The per-pixel work is
-// predicated rather than branched: every lane evaluates alpha for each of
-// its pixels and the decisions select what is accumulated.  A wave skips an
-// entry outright when no pixel of its footprint can admit it (wave_mask).
-// The candidate transmittance is formed as fma(-alpha, T, T), one rounding.
+// and stopping it again (T = -|T|) leaves it as it is.  Pixels outside the
+// image start stopped.  The per-pixel work is predicated rather than
+// branched: every lane evaluates
+// alpha for each of its pixels and the decisions select what is
+// accumulated.  A wave skips an entry outright when no pixel of its
+// footprint can admit it (wave_bits, bit 0), and takes a fast path without
+// the per-pixel box tests and the alpha clamp when the entry's render box
+// holds the whole footprint and its opacity is at most alpha_max (bit 1);
+// the choice is uniform over the wave, read into a scalar register.  The
+// candidate transmittance is formed as fma(-alpha, T, T), one rounding.
 enum { kRender = 0, kCount = 1, kDominant = 2 };
+
+template <int PPT, int MODE>
+struct PixState {
+  float T[PPT], C0[PPT], C1[PPT], C2[PPT], vf[PPT];
+  int last[PPT];
+  float wbest[MODE == kDominant ? PPT : 1];
+  int32_t best[MODE == kDominant ? PPT : 1];
+  unsigned ib[MODE == kCount ? PPT : 1], ib_last[MODE == kCount ? PPT : 1];
+  unsigned n_contrib;
+};
+
+// Blends one staged entry into the thread's strip.  FAST: the entry's render
+// box holds the whole strip and alpha needs no clamp.
+template <bool FAST, int PPT, int MODE>
+__device__ __forceinline__ void blend_entry(PixState<PPT, MODE>& st,
+                                            const Column& col, float py,
+                                            float C2, float o, float cr,
+                                            float cg, float cb, float amin,
+                                            float amax, float tmin, bool in_u,
+                                            int lo, int hi, int idx,
+                                            int32_t gj) {
+#pragma unroll
+  for (int p = 0; p < PPT; ++p) {
+    float dy;
+    const float e2 = exponent2(col, py, C2, st.vf[p], dy);
+    const float G = gauss2(e2);
+    const float al = FAST ? o * G : fminf(amax, o * G);
+    const bool inbox = FAST || (in_u && lo <= p && p <= hi);
+    const bool ok = inbox && al >= amin;
+    const float Tn = fmaf(-al, st.T[p], st.T[p]);
+    const bool con = ok && Tn >= tmin;
+    const float w = con ? al * st.T[p] : 0.f;
+    st.C0[p] = fmaf(cr, w, st.C0[p]);
+    st.C1[p] = fmaf(cg, w, st.C1[p]);
+    st.C2[p] = fmaf(cb, w, st.C2[p]);
+    st.T[p] = con ? Tn : (ok ? -fabsf(st.T[p]) : st.T[p]);
+    st.last[p] = con ? idx : st.last[p];
+    if (MODE == kDominant) {
+      const bool better = con && w > st.wbest[p];
+      st.wbest[p] = better ? w : st.wbest[p];
+      st.best[p] = better ? gj : st.best[p];
+    }
+    if (MODE == kCount) {
+      st.n_contrib += con;
+      st.ib_last[p] = con ? st.ib[p] : st.ib_last[p];
+    }
+  }
+}
 
 template <int TILE, int BATCH, int NT, int MODE>
 __global__ __launch_bounds__(NT) void k_render_fwd(FwdArgs a) {
@@ -62,34 +115,34 @@ __global__ __launch_bounds__(NT) void k_render_fwd(FwdArgs a) {
   Lay::of(tid, cu, cv0);
   const int u = tx * TILE + cu;
   const int v0 = ty * TILE + cv0;
-  const int wave = tid >> 6;
-  __shared__ int wmask[BATCH];   // per staged entry: waves that evaluate it
+  // The wave index, uniform over the wave, in a scalar register.
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+  __shared__ int wbits[BATCH];   // per staged entry: wave_bits
   __shared__ uint32_t egid[DOM ? BATCH : 1];   // Gaussian index per entry
-  const float uf = (float)u;
-  const float amax = __builtin_canonicalizef(r.alpha_max);
+  const float uf = pinned((float)u);
+  const float amax = r.alpha_max;
   const float amin = r.alpha_min, tmin = r.T_min;
-  int last[PPT];
-  float T[PPT], C0[PPT], C1[PPT], C2[PPT], vf[PPT];
-  unsigned n_exam = 0, n_inbox = 0, n_contrib = 0;
-  unsigned ib[PPT], ib_last[PPT];
-  float wbest[PPT];
-  int32_t best[PPT];
+  PixState<PPT, MODE> st;
+  unsigned n_exam = 0, n_inbox = 0;
+  st.n_contrib = 0;
 #pragma unroll
   for (int p = 0; p < PPT; ++p) {
-    wbest[p] = 0.f;
-    best[p] = -1;
-    T[p] = (u < r.W && v0 + p < r.H) ? 1.f : -1.f;
-    C0[p] = C1[p] = C2[p] = 0.f;
-    last[p] = 0;
-    vf[p] = pinned((float)(v0 + p));
-    ib[p] = ib_last[p] = 0;
+    if (DOM) {
+      st.wbest[p] = 0.f;
+      st.best[p] = -1;
+    }
+    st.T[p] = (u < r.W && v0 + p < r.H) ? 1.f : -1.f;
+    st.C0[p] = st.C1[p] = st.C2[p] = 0.f;
+    st.last[p] = 0;
+    st.vf[p] = pinned((float)(v0 + p));
+    if (COUNT) st.ib[p] = st.ib_last[p] = 0;
   }
   const Record* rv = r.rec + (size_t)k * r.cap;
   const int2* rbv = r.rbox + (size_t)k * r.cap;
   for (long long b0 = s; b0 < e; b0 += BATCH) {
     int alive = 0;
 #pragma unroll
-    for (int p = 0; p < PPT; ++p) alive |= T[p] > 0.f;
+    for (int p = 0; p < PPT; ++p) alive |= st.T[p] > 0.f;
     if (__syncthreads_or(alive) == 0) break;
     const int cnt = (int)min((long long)BATCH, e - b0);
     for (int i = tid; i < cnt; i += NT) {
@@ -97,8 +150,8 @@ __global__ __launch_bounds__(NT) void k_render_fwd(FwdArgs a) {
       const Record R = rv[g];
       const int4 box = unpack_box(rbv[g]);
       stage(ent[i], R, box);
-      wmask[i] = wave_mask<TILE, NT>(R, box, tx * TILE, ty * TILE, amin,
-                                     r.ellipse_test);
+      wbits[i] = wave_bits<TILE, NT>(R, box, tx * TILE, ty * TILE, r.W, r.H,
+                                     amin, amax, r.ellipse_test);
       if (DOM) egid[i] = g;
     }
     __syncthreads();
@@ -107,64 +160,45 @@ __global__ __launch_bounds__(NT) void k_render_fwd(FwdArgs a) {
       if ((j & 7) == 0) {
         bool any = false;
 #pragma unroll
-        for (int p = 0; p < PPT; ++p) any |= T[p] > 0.f;
+        for (int p = 0; p < PPT; ++p) any |= st.T[p] > 0.f;
         if (!__any(any)) break;
       }
+      const int wb = __builtin_amdgcn_readfirstlane(wbits[j]) >> (2 * wave);
       const int4 box = ent[j].box;
-      const bool evaluate = (wmask[j] >> wave) & 1;
       if (COUNT) {
+        const bool evaluate = wb & 1;
 #pragma unroll
         for (int p = 0; p < PPT; ++p) {
-          if (!(T[p] > 0.f)) continue;
+          if (!(st.T[p] > 0.f)) continue;
           ++n_exam;
           if (evaluate && u >= box.x && u <= box.y && v0 + p >= box.z &&
               v0 + p <= box.w) {
             ++n_inbox;
-            ++ib[p];
+            ++st.ib[p];
           }
         }
       }
-      if (!evaluate) continue;
+      if (!(wb & 1)) continue;
       const float4 ea = ent[j].a;
       const float4 eb = ent[j].b;
       const float ecb = ent[j].c.x;
-      const bool in_u = u >= box.x && u <= box.y;
-      const int lo = box.z - v0, hi = box.w - v0;
       const Column col = column(ea, uf);
       const int idx = base + j;
       const int32_t gj = DOM ? (int32_t)egid[j] : 0;
-#pragma unroll
-      for (int p = 0; p < PPT; ++p) {
-        float dy;
-        const float e2 = exponent2(col, ea.y, eb.x, vf[p], dy);
-        const float G = __builtin_amdgcn_exp2f(e2);
-        const float al = fminf(amax, eb.y * G);
-        const bool ok = in_u && lo <= p && p <= hi && !(e2 > 0.f) &&
-                        al >= amin;
-        const float Tn = fmaf(-al, T[p], T[p]);
-        const bool con = ok && Tn >= tmin;
-        const float w = con ? al * T[p] : 0.f;
-        C0[p] = fmaf(eb.z, w, C0[p]);
-        C1[p] = fmaf(eb.w, w, C1[p]);
-        C2[p] = fmaf(ecb, w, C2[p]);
-        T[p] = con ? Tn : (ok ? -fabsf(T[p]) : T[p]);
-        last[p] = con ? idx : last[p];
-        if (DOM) {
-          const bool better = con && w > wbest[p];
-          wbest[p] = better ? w : wbest[p];
-          best[p] = better ? gj : best[p];
-        }
-        if (COUNT) {
-          n_contrib += con;
-          ib_last[p] = con ? ib[p] : ib_last[p];
-        }
+      if (wb & 2) {
+        blend_entry<true>(st, col, ea.y, eb.x, eb.y, eb.z, eb.w, ecb, amin,
+                          amax, tmin, true, 0, 0, idx, gj);
+      } else {
+        const bool in_u = u >= box.x && u <= box.y;
+        blend_entry<false>(st, col, ea.y, eb.x, eb.y, eb.z, eb.w, ecb, amin,
+                           amax, tmin, in_u, box.z - v0, box.w - v0, idx, gj);
       }
     }
   }
   if (COUNT) {
-    unsigned long long c[4] = {n_exam, n_inbox, n_contrib, 0};
+    unsigned long long c[4] = {n_exam, n_inbox, st.n_contrib, 0};
 #pragma unroll
-    for (int p = 0; p < PPT; ++p) c[3] += ib_last[p];
+    for (int p = 0; p < PPT; ++p) c[3] += st.ib_last[p];
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
       unsigned long long x = c[q];
@@ -178,14 +212,14 @@ __global__ __launch_bounds__(NT) void k_render_fwd(FwdArgs a) {
   for (int p = 0; p < PPT; ++p) {
     const int v = v0 + p;
     if (!(u < r.W && v < r.H)) continue;
-    const float Tf = fabsf(T[p]);
+    const float Tf = fabsf(st.T[p]);
     const size_t pix = (size_t)v * r.W + u;
-    a.rgb[((size_t)k * 3 + 0) * HW + pix] = fmaf(Tf, r.bg0, C0[p]);
-    a.rgb[((size_t)k * 3 + 1) * HW + pix] = fmaf(Tf, r.bg1, C1[p]);
-    a.rgb[((size_t)k * 3 + 2) * HW + pix] = fmaf(Tf, r.bg2, C2[p]);
+    a.rgb[((size_t)k * 3 + 0) * HW + pix] = fmaf(Tf, r.bg0, st.C0[p]);
+    a.rgb[((size_t)k * 3 + 1) * HW + pix] = fmaf(Tf, r.bg1, st.C1[p]);
+    a.rgb[((size_t)k * 3 + 2) * HW + pix] = fmaf(Tf, r.bg2, st.C2[p]);
     a.T[(size_t)k * HW + pix] = Tf;
-    a.nlast[(size_t)k * HW + pix] = last[p];
-    if (DOM) a.dom[(size_t)k * HW + pix] = best[p];
+    a.nlast[(size_t)k * HW + pix] = st.last[p];
+    if (DOM) a.dom[(size_t)k * HW + pix] = st.best[p];
   }
 }
 
