@@ -56,24 +56,24 @@ struct PixState {
   unsigned n_contrib;
 };
 
-// Blends one staged entry into the thread's strip.  FAST: the entry's render
-// box holds the whole strip and alpha needs no clamp.
-template <bool FAST, int PPT, int MODE>
+// Blends one staged entry into the thread's strip.  inb[p]: the pixel lies
+// in the entry's render box (all true on the fast path); amx: the alpha
+// clamp (+inf on the fast path, where opacity <= alpha_max).
+template <int PPT, int MODE>
 __device__ __forceinline__ void blend_entry(PixState<PPT, MODE>& st,
                                             const Column& col, float py,
                                             float C2, float o, float cr,
                                             float cg, float cb, float amin,
-                                            float amax, float tmin, bool in_u,
-                                            int lo, int hi, int idx,
+                                            float amx, float tmin,
+                                            const bool* inb, int idx,
                                             int32_t gj) {
 #pragma unroll
   for (int p = 0; p < PPT; ++p) {
     float dy;
     const float e2 = exponent2(col, py, C2, st.vf[p], dy);
     const float G = gauss2(e2);
-    const float al = FAST ? o * G : fminf(amax, o * G);
-    const bool inbox = FAST || (in_u && lo <= p && p <= hi);
-    const bool ok = inbox && al >= amin;
+    const float al = fminf(amx, o * G);
+    const bool ok = inb[p] && al >= amin;
     const float Tn = fmaf(-al, st.T[p], st.T[p]);
     const bool con = ok && Tn >= tmin;
     const float w = con ? al * st.T[p] : 0.f;
@@ -185,14 +185,23 @@ __global__ __launch_bounds__(NT) void k_render_fwd(FwdArgs a) {
       const Column col = column(ea, uf);
       const int idx = base + j;
       const int32_t gj = DOM ? (int32_t)egid[j] : 0;
+      // Only the box masks and the clamp differ between the paths, so the
+      // pixels' running state is updated by one common body.
+      bool inb[PPT];
+      float amx;
       if (wb & 2) {
-        blend_entry<true>(st, col, ea.y, eb.x, eb.y, eb.z, eb.w, ecb, amin,
-                          amax, tmin, true, 0, 0, idx, gj);
+#pragma unroll
+        for (int p = 0; p < PPT; ++p) inb[p] = true;
+        amx = INFINITY;
       } else {
         const bool in_u = u >= box.x && u <= box.y;
-        blend_entry<false>(st, col, ea.y, eb.x, eb.y, eb.z, eb.w, ecb, amin,
-                           amax, tmin, in_u, box.z - v0, box.w - v0, idx, gj);
+        const int lo = box.z - v0, hi = box.w - v0;
+#pragma unroll
+        for (int p = 0; p < PPT; ++p) inb[p] = in_u && lo <= p && p <= hi;
+        amx = amax;
       }
+      blend_entry(st, col, ea.y, eb.x, eb.y, eb.z, eb.w, ecb, amin, amx, tmin,
+                  inb, idx, gj);
     }
   }
   if (COUNT) {
