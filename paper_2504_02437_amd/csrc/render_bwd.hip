@@ -116,20 +116,21 @@ struct EntrySums {
 // The backward of one entry over the thread's strip, back to front: T is
 // recovered as T_{i+1} / (1 - alpha_i) (a pair that is not admitted takes
 // alpha 0: 1 / (1 - 0) is exactly 1, so T, the weight and the running colour
-// sum come out unchanged without a select each).  FAST: the entry's render
-// box holds the whole strip, no alpha is clamped and every pixel's n_last
-// lies beyond the entry, so only the alpha threshold decides.  BG: a
-// non-zero background, whose term enters dL/dalpha.  The opacity gradient
-// is formed once per entry from S0 = sum of dL/dpi: with alpha = o G
-// unclamped, dL/dpi = alpha dL/dalpha and dL/do = G dL/dalpha = S0 / o
-// (clamped pairs add 0 to both).
-template <bool FAST, bool BG, int PPT>
+// sum come out unchanged without a select each).  inb[p]: the pixel lies in
+// the entry's render box and before its n_last (all true on the fast path).
+// CLAMP: some entry of the batch has opacity above alpha_max, so alpha is
+// clamped and a clamped pair passes no shape or opacity gradient; batches
+// without such an entry (nearly all) run the version without the clamp.
+// BG: a non-zero background, whose term enters dL/dalpha.  The opacity
+// gradient is formed once per entry from S0 = sum of dL/dpi: with
+// alpha = o G unclamped, dL/dpi = alpha dL/dalpha and dL/do = G dL/dalpha =
+// S0 / o (clamped pairs add 0 to both).
+template <bool CLAMP, bool BG, int PPT>
 __device__ __forceinline__ EntrySums entry_bwd(BwdPix<PPT>& px,
                                                const Column& col, float py,
                                                float C2, float o, float cr,
                                                float cgc, float cbc, float amin,
-                                               float amax, bool in_u, int rlo,
-                                               int rhi, int pos) {
+                                               float amax, const bool* inb) {
   EntrySums r = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, false};
 #pragma unroll
   for (int p = 0; p < PPT; ++p) {
@@ -137,9 +138,8 @@ __device__ __forceinline__ EntrySums entry_bwd(BwdPix<PPT>& px,
     const float e2 = exponent2(col, py, C2, px.vf[p], dy);
     const float G = gauss2(e2);
     const float oG = o * G;
-    const float al = FAST ? oG : fminf(amax, oG);
-    const bool ok = (FAST || (in_u && rlo <= p && p <= rhi &&
-                              pos < px.last[p])) && al >= amin;
+    const float al = CLAMP ? fminf(amax, oG) : oG;
+    const bool ok = inb[p] && al >= amin;
     r.hit |= ok;
     const float alo = ok ? al : 0.f;
     const float rom = __builtin_amdgcn_rcpf(1.f - alo);
@@ -153,14 +153,71 @@ __device__ __forceinline__ EntrySums entry_bwd(BwdPix<PPT>& px,
     const float diff = cgp - px.Sg[p];
     const float dal = BG ? fmaf(Ti, diff, -(px.Tb[p] * rom)) : Ti * diff;
     px.Sg[p] = fmaf(alo, diff, px.Sg[p]);
-    // Clamped alpha has no shape or opacity gradient.
-    const float dpw = FAST ? dal * alo : ((ok && !(oG > amax)) ? dal * al : 0.f);
+    const float dpw = (CLAMP && oG > amax) ? 0.f : dal * alo;
     const float tdy = dpw * dy;
     r.S0 += dpw;
     r.S1 += tdy;
     r.S2 = fmaf(tdy, dy, r.S2);
   }
   return r;
+}
+
+// The entries [0, jn) of the staged batch, back to front, for one wave.
+template <bool CLAMP, bool BG, int TILE, int BATCH, int NT>
+__device__ __forceinline__ void walk_batch(
+    BwdPix<PixLayout<TILE, NT>::PPT>& px, const Entry* ent, const int* wbits,
+    float (*acc)[9], int jn, int lo, int wave, int wfirst, int u, int v0,
+    float uf, float amin, float amax, int lane, bool bank02, bool bank01) {
+  constexpr int PPT = PixLayout<TILE, NT>::PPT;
+  for (int j = jn - 1; j >= 0; --j) {
+    const int pos = lo + j;
+    const int wb = __builtin_amdgcn_readfirstlane(wbits[j]) >> (2 * wave);
+    if (!(wb & 1)) continue;
+    const float4 ea = ent[j].a;
+    const float4 eb = ent[j].b;
+    const float4 ec = ent[j].c;
+    const Column col = column(ea, uf);
+    // Only the box / position masks differ between the fast and the general
+    // path, chosen in scalar registers, so the pixels' running state is
+    // updated by one common body.
+    bool inb[PPT];
+    if ((wb & 2) && pos < wfirst) {
+#pragma unroll
+      for (int p = 0; p < PPT; ++p) inb[p] = true;
+    } else {
+      const int4 box = ent[j].box;
+      const bool in_u = u >= box.x && u <= box.y;
+      const int rlo = box.z - v0, rhi = box.w - v0;
+#pragma unroll
+      for (int p = 0; p < PPT; ++p)
+        inb[p] = in_u && rlo <= p && p <= rhi && pos < px.last[p];
+    }
+    const EntrySums es = entry_bwd<CLAMP, BG>(px, col, ea.y, eb.x, eb.y, eb.z,
+                                              eb.w, ec.x, amin, amax, inb);
+    if (__any(es.hit)) {
+      const float A = ec.y, B = ec.z, C = ec.w;
+      const float dx = col.dx, dxS0 = dx * es.S0;
+      const float d_px = -fmaf(A, dxS0, B * es.S1);
+      const float d_py = -fmaf(C, es.S1, B * dxS0);
+      const float d_A = -0.5f * dx * dxS0;
+      const float d_B = -dx * es.S1;
+      const float d_C = -0.5f * es.S2;
+      const float d_o = es.S0 * __builtin_amdgcn_rcpf(eb.y);
+      // Row sums of the nine quantities, added into the entry's LDS slot by
+      // lanes 0, 4, 8, 12 of each row (the four rows of the wave and the
+      // other waves of the tile meet in the LDS adds).
+      const float x = row_sum4(d_px, d_py, d_A, d_B, bank02, bank01);
+      const float y = row_sum4(d_C, d_o, es.d_r, es.d_g, bank02, bank01);
+      const float z = row_sum(es.d_b);
+      float* ac = acc[j];
+      if ((lane & 3) == 0) {
+        const int q = (lane >> 2) & 3;
+        atomicAdd(&ac[q], x);
+        atomicAdd(&ac[4 + q], y);
+        if (q == 0) atomicAdd(&ac[8], z);
+      }
+    }
+  }
 }
 
 // The per-pixel work is predicated like the forward's: every lane evaluates
@@ -278,6 +335,7 @@ __global__ __launch_bounds__(NT) void k_render_bwd(BwdArgs a) {
     const int lo = max(0, hi - BATCH);
     const int cnt = hi - lo;
     __syncthreads();   // the previous batch is flushed
+    int clampable = 0;
     for (int i = tid; i < cnt; i += NT) {
       const uint32_t g = r.vals[s + lo + i];
       gid[i] = g;
@@ -286,51 +344,18 @@ __global__ __launch_bounds__(NT) void k_render_bwd(BwdArgs a) {
       stage(ent[i], R, box);
       wbits[i] = wave_bits<TILE, NT>(R, box, tx * TILE, ty * TILE, r.W, r.H,
                                      amin, amax, r.ellipse_test);
+      clampable |= R.q1.y > amax;
     }
     for (int i = tid; i < cnt * 9; i += NT) (&acc[0][0])[i] = 0.f;
-    __syncthreads();
-    for (int j = min(cnt, wlast - lo) - 1; j >= 0; --j) {
-      const int pos = lo + j;
-      const int wb = __builtin_amdgcn_readfirstlane(wbits[j]) >> (2 * wave);
-      if (!(wb & 1)) continue;
-      const float4 ea = ent[j].a;
-      const float4 eb = ent[j].b;
-      const float4 ec = ent[j].c;
-      const Column col = column(ea, uf);
-      EntrySums es;
-      if ((wb & 2) && pos < wfirst) {
-        es = entry_bwd<true, BG>(px, col, ea.y, eb.x, eb.y, eb.z, eb.w, ec.x,
-                                 amin, amax, true, 0, 0, pos);
-      } else {
-        const int4 box = ent[j].box;
-        const bool in_u = u >= box.x && u <= box.y;
-        es = entry_bwd<false, BG>(px, col, ea.y, eb.x, eb.y, eb.z, eb.w, ec.x,
-                                  amin, amax, in_u, box.z - v0, box.w - v0,
-                                  pos);
-      }
-      if (__any(es.hit)) {
-        const float A = ec.y, B = ec.z, C = ec.w;
-        const float dx = col.dx, dxS0 = dx * es.S0;
-        const float d_px = -fmaf(A, dxS0, B * es.S1);
-        const float d_py = -fmaf(C, es.S1, B * dxS0);
-        const float d_A = -0.5f * dx * dxS0;
-        const float d_B = -dx * es.S1;
-        const float d_C = -0.5f * es.S2;
-        const float d_o = es.S0 * __builtin_amdgcn_rcpf(eb.y);
-        // Row sums of the nine quantities, added into the entry's LDS slot
-        // by lanes 0, 4, 8, 12 of each row (the four rows of the wave and
-        // the other waves of the tile meet in the LDS adds).
-        const float x = row_sum4(d_px, d_py, d_A, d_B, bank02, bank01);
-        const float y = row_sum4(d_C, d_o, es.d_r, es.d_g, bank02, bank01);
-        const float z = row_sum(es.d_b);
-        float* ac = acc[j];
-        if ((lane & 3) == 0) {
-          const int q = (lane >> 2) & 3;
-          atomicAdd(&ac[q], x);
-          atomicAdd(&ac[4 + q], y);
-          if (q == 0) atomicAdd(&ac[8], z);
-        }
-      }
+    const int jn = min(cnt, wlast - lo);
+    if (__syncthreads_or(clampable)) {
+      walk_batch<true, BG, TILE, BATCH, NT>(px, ent, wbits, acc, jn, lo, wave,
+                                            wfirst, u, v0, uf, amin, amax,
+                                            lane, bank02, bank01);
+    } else {
+      walk_batch<false, BG, TILE, BATCH, NT>(px, ent, wbits, acc, jn, lo, wave,
+                                             wfirst, u, v0, uf, amin, amax,
+                                             lane, bank02, bank01);
     }
     __syncthreads();
     for (int i = tid; i < cnt * 9; i += NT) {

@@ -57,14 +57,15 @@ struct PixState {
 };
 
 // Blends one staged entry into the thread's strip.  inb[p]: the pixel lies
-// in the entry's render box (all true on the fast path); amx: the alpha
-// clamp (+inf on the fast path, where opacity <= alpha_max).
-template <int PPT, int MODE>
+// in the entry's render box (all true on the fast path).  CLAMP: some entry
+// of the batch has opacity above alpha_max, so alpha is clamped; batches
+// without such an entry (nearly all) run the version without the clamp.
+template <bool CLAMP, int PPT, int MODE>
 __device__ __forceinline__ void blend_entry(PixState<PPT, MODE>& st,
                                             const Column& col, float py,
                                             float C2, float o, float cr,
                                             float cg, float cb, float amin,
-                                            float amx, float tmin,
+                                            float amax, float tmin,
                                             const bool* inb, int idx,
                                             int32_t gj) {
 #pragma unroll
@@ -72,7 +73,7 @@ __device__ __forceinline__ void blend_entry(PixState<PPT, MODE>& st,
     float dy;
     const float e2 = exponent2(col, py, C2, st.vf[p], dy);
     const float G = gauss2(e2);
-    const float al = fminf(amx, o * G);
+    const float al = CLAMP ? fminf(amax, o * G) : o * G;
     const bool ok = inb[p] && al >= amin;
     const float Tn = fmaf(-al, st.T[p], st.T[p]);
     const bool con = ok && Tn >= tmin;
@@ -91,6 +92,63 @@ __device__ __forceinline__ void blend_entry(PixState<PPT, MODE>& st,
       st.n_contrib += con;
       st.ib_last[p] = con ? st.ib[p] : st.ib_last[p];
     }
+  }
+}
+
+// The staged batch front to back for one thread's strip.
+template <bool CLAMP, int TILE, int NT, int MODE>
+__device__ __forceinline__ void walk_batch(
+    PixState<PixLayout<TILE, NT>::PPT, MODE>& st, const Entry* ent,
+    const int* wbits, const uint32_t* egid, int cnt, int base, int wave,
+    int u, int v0, float uf, float amin, float amax, float tmin,
+    unsigned& n_exam, unsigned& n_inbox) {
+  constexpr bool COUNT = MODE == kCount;
+  constexpr bool DOM = MODE == kDominant;
+  constexpr int PPT = PixLayout<TILE, NT>::PPT;
+  for (int j = 0; j < cnt; ++j) {
+    if ((j & 7) == 0) {
+      bool any = false;
+#pragma unroll
+      for (int p = 0; p < PPT; ++p) any |= st.T[p] > 0.f;
+      if (!__any(any)) break;
+    }
+    const int wb = __builtin_amdgcn_readfirstlane(wbits[j]) >> (2 * wave);
+    const int4 box = ent[j].box;
+    if (COUNT) {
+      const bool evaluate = wb & 1;
+#pragma unroll
+      for (int p = 0; p < PPT; ++p) {
+        if (!(st.T[p] > 0.f)) continue;
+        ++n_exam;
+        if (evaluate && u >= box.x && u <= box.y && v0 + p >= box.z &&
+            v0 + p <= box.w) {
+          ++n_inbox;
+          ++st.ib[p];
+        }
+      }
+    }
+    if (!(wb & 1)) continue;
+    const float4 ea = ent[j].a;
+    const float4 eb = ent[j].b;
+    const float ecb = ent[j].c.x;
+    const Column col = column(ea, uf);
+    const int idx = base + j;
+    const int32_t gj = DOM ? (int32_t)egid[j] : 0;
+    // Only the box masks differ between the fast and the general path,
+    // chosen in scalar registers, so the pixels' running state is updated
+    // by one common body.
+    bool inb[PPT];
+    if (wb & 2) {
+#pragma unroll
+      for (int p = 0; p < PPT; ++p) inb[p] = true;
+    } else {
+      const bool in_u = u >= box.x && u <= box.y;
+      const int lo = box.z - v0, hi = box.w - v0;
+#pragma unroll
+      for (int p = 0; p < PPT; ++p) inb[p] = in_u && lo <= p && p <= hi;
+    }
+    blend_entry<CLAMP>(st, col, ea.y, eb.x, eb.y, eb.z, eb.w, ecb, amin,
+                       amax, tmin, inb, idx, gj);
   }
 }
 
@@ -145,6 +203,7 @@ __global__ __launch_bounds__(NT) void k_render_fwd(FwdArgs a) {
     for (int p = 0; p < PPT; ++p) alive |= st.T[p] > 0.f;
     if (__syncthreads_or(alive) == 0) break;
     const int cnt = (int)min((long long)BATCH, e - b0);
+    int clampable = 0;
     for (int i = tid; i < cnt; i += NT) {
       const uint32_t g = r.vals[b0 + i];
       const Record R = rv[g];
@@ -152,57 +211,18 @@ __global__ __launch_bounds__(NT) void k_render_fwd(FwdArgs a) {
       stage(ent[i], R, box);
       wbits[i] = wave_bits<TILE, NT>(R, box, tx * TILE, ty * TILE, r.W, r.H,
                                      amin, amax, r.ellipse_test);
+      clampable |= R.q1.y > amax;
       if (DOM) egid[i] = g;
     }
-    __syncthreads();
     const int base = (int)(b0 - s) + 1;
-    for (int j = 0; j < cnt; ++j) {
-      if ((j & 7) == 0) {
-        bool any = false;
-#pragma unroll
-        for (int p = 0; p < PPT; ++p) any |= st.T[p] > 0.f;
-        if (!__any(any)) break;
-      }
-      const int wb = __builtin_amdgcn_readfirstlane(wbits[j]) >> (2 * wave);
-      const int4 box = ent[j].box;
-      if (COUNT) {
-        const bool evaluate = wb & 1;
-#pragma unroll
-        for (int p = 0; p < PPT; ++p) {
-          if (!(st.T[p] > 0.f)) continue;
-          ++n_exam;
-          if (evaluate && u >= box.x && u <= box.y && v0 + p >= box.z &&
-              v0 + p <= box.w) {
-            ++n_inbox;
-            ++st.ib[p];
-          }
-        }
-      }
-      if (!(wb & 1)) continue;
-      const float4 ea = ent[j].a;
-      const float4 eb = ent[j].b;
-      const float ecb = ent[j].c.x;
-      const Column col = column(ea, uf);
-      const int idx = base + j;
-      const int32_t gj = DOM ? (int32_t)egid[j] : 0;
-      // Only the box masks and the clamp differ between the paths, so the
-      // pixels' running state is updated by one common body.
-      bool inb[PPT];
-      float amx;
-      if (wb & 2) {
-#pragma unroll
-        for (int p = 0; p < PPT; ++p) inb[p] = true;
-        amx = INFINITY;
-      } else {
-        const bool in_u = u >= box.x && u <= box.y;
-        const int lo = box.z - v0, hi = box.w - v0;
-#pragma unroll
-        for (int p = 0; p < PPT; ++p) inb[p] = in_u && lo <= p && p <= hi;
-        amx = amax;
-      }
-      blend_entry(st, col, ea.y, eb.x, eb.y, eb.z, eb.w, ecb, amin, amx, tmin,
-                  inb, idx, gj);
-    }
+    if (__syncthreads_or(clampable))
+      walk_batch<true, TILE, NT, MODE>(st, ent, wbits, egid, cnt, base, wave, u,
+                                       v0, uf, amin, amax, tmin, n_exam,
+                                       n_inbox);
+    else
+      walk_batch<false, TILE, NT, MODE>(st, ent, wbits, egid, cnt, base, wave,
+                                        u, v0, uf, amin, amax, tmin, n_exam,
+                                        n_inbox);
   }
   if (COUNT) {
     unsigned long long c[4] = {n_exam, n_inbox, st.n_contrib, 0};

@@ -461,3 +461,36 @@ def test_maximum_image_size(tile):
     bad = (np.abs(img - ref_img).max(axis=1) > 1e-5) | (np.abs(T - ref_T) > 1e-5)
     assert bad.sum() <= 0.01 * len(us), (int(bad.sum()), len(us))
     assert np.mean(ref_T < 1.0) > 0.5     # the samples do see Gaussians
+
+
+@pytest.mark.parametrize("tile,batch,threads", [(16, 256, 64), (32, 256, 256),
+                                                (8, 128, 64)])
+def test_clamped_alpha_against_oracle(tile, batch, threads):
+    """Opacities above alpha_max (logit 6: o = 0.9975) next to ordinary ones:
+    alpha is clamped to 0.99 at the centres of the opaque Gaussians, which
+    pass no shape or opacity gradient there.  Two views with a background;
+    image, transmittance and n_last against the oracle, gradients of every
+    parameter at the plain per-element bar."""
+    w = _scene(91, n=400, W=70, H=45)
+    rng = np.random.default_rng(5)
+    opaque = rng.uniform(size=w.gaussians.n) < 0.5
+    w.gaussians.opacity_logit[opaque] = 6.0
+    c = w.cameras[0]
+    w.cameras = [c, synth.Camera(c.R, (c.t + np.array([0.03, -0.02, 0.01])
+                                       ).astype(np.float32),
+                                 c.fx, c.fy, c.cx, c.cy, c.width, c.height)]
+    bg = (0.2, 0.1, 0.3)
+    print("case clamped alpha", tile, batch, threads, flush=True)
+    p64, proj, bins, fwd = oracle_forward(w, tile, bg=bg)
+    params, rast = gpu_forward(w, tile, batch, bg=bg, threads=threads)
+    check_records(rast, proj)
+    mask, _ = check_forward(rast, fwd, bins, max_flagged=5e-3)
+    # The oracle's walk holds clamped contributions.
+    g, wt, code, cnt = oracle.pixel_walk(proj, bins, 70, 45,
+                                         np.arange(2 * 70 * 45))
+    valid = np.arange(g.shape[1])[None, :] < cnt[:, None]
+    assert ((code == oracle.DEC_CLAMP) & valid).sum() > 50
+    dL = masked_dL(np.random.default_rng(7), mask, (2, 3, 45, 70))
+    got = gpu_backward(rast, params, dL)
+    ref = oracle_backward(w, p64, proj, bins, dL, bg=bg)
+    check_grads(got, ref, w.gaussians.n)
