@@ -99,6 +99,42 @@ def backward(w, cache, dy, rounding=True):
                            db3])
 
 
+def forward_magnitude(w, cache):
+    """Per output, the magnitude through which a one-ulp change of a BF16
+    hidden activation reaches it: sum_j |W3_jk| (|h2_j| + |gelu'(z2_j)|
+    sum_i |W2_ij| |h1_i|).  A BF16 rounding of an activation that lands on
+    the other side of a rounding boundary (FP32 vs FP64 arithmetic) moves it
+    by at most 2^-7 of its magnitude, so the output moves by at most 2^-7
+    times this."""
+    (W1, _), (W2, _), (W3, _) = unpack(w)
+    a2 = np.abs(bf16(W2))
+    a3 = np.abs(bf16(W3))
+    e2 = np.abs(cache["h2"]) + np.abs(gelu_grad(cache["z2"])) * \
+        (np.abs(cache["h1"]) @ a2)
+    return e2 @ a3
+
+
+def backward_magnitude(w, cache, dy):
+    """backward() with every factor by absolute value (the BF16 roundings
+    kept): for non-negative dy it bounds how far an input change of size dy
+    moves each gradient element, and it is the sum of the magnitudes of the
+    terms each element adds up."""
+    (W1, _), (W2, _), (W3, _) = unpack(w)
+    dyh = np.abs(bf16(np.asarray(dy, np.float64)))
+    dW3 = np.abs(cache["h2"]).T @ dyh
+    db3 = dyh.sum(0)
+    dz2 = (dyh @ np.abs(bf16(W3)).T) * np.abs(gelu_grad(cache["z2"]))
+    dz2h = np.abs(bf16(dz2))
+    dW2 = np.abs(cache["h1"]).T @ dz2h
+    db2 = dz2.sum(0)
+    dz1 = (dz2h @ np.abs(bf16(W2)).T) * np.abs(gelu_grad(cache["z1"]))
+    dz1h = np.abs(bf16(dz1))
+    dW1 = np.abs(cache["x"]).T @ dz1h
+    db1 = dz1.sum(0)
+    return np.concatenate([dW1.ravel(), db1, dW2.ravel(), db2, dW3.ravel(),
+                           db3])
+
+
 def mse(y, t):
     """Mean over all entries of (y - t)^2 and its gradient."""
     d = np.asarray(y, np.float64) - np.asarray(t, np.float64)

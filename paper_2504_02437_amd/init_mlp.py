@@ -171,9 +171,11 @@ def collect_pairs(seed, n_kf=40, width=320, height=240, f=260.0,
 
 def run_window(seed, mlp=None, n_kf=10, width=320, height=240, f=260.0,
                n_gt=100_000, iters_per_kf=5, extra_iters=100, eval_every=5,
-               device="cuda"):
+               plateau=None, device="cuda"):
     """Maps a keyframe window with heuristic (mlp=None) or learned
-    initialisation; returns the window PSNR curve over iterations."""
+    initialisation; returns the window PSNR curve over iterations.  With
+    plateau = (span, gain) the run stops early once the PSNR rose by less
+    than `gain` dB over the last `span` iterations."""
     from .mapper import Mapper, render_images
     st = _stream(seed, n_kf, width, height, f, n_gt)
     imgs = render_images(st.gt, st.cameras, device)
@@ -189,6 +191,11 @@ def run_window(seed, mlp=None, n_kf=10, width=320, height=240, f=260.0,
     for _ in range(0, extra_iters, eval_every):
         mp.optimise(eval_every)
         curve.append((mp.iterations, mp.psnr(cams, full)))
+        if plateau:
+            span, gain = plateau
+            back = [p for it, p in curve if it <= curve[-1][0] - span]
+            if back and curve[-1][1] - back[-1] < gain:
+                break
     return dict(curve=curve, gaussians=mp.params.n())
 
 
@@ -199,9 +206,45 @@ def iterations_to_reach(curve, target):
     return None
 
 
+def compare_at_levels(heuristic, learned, levels):
+    """For each PSNR level: the first iteration at which each curve reaches
+    it (None when it never does within its run)."""
+    return [dict(psnr=float(lv), heuristic=iterations_to_reach(heuristic, lv),
+                 learned=iterations_to_reach(learned, lv)) for lv in levels]
+
+
+def evaluate(net, eval_seeds=(1000, 1001, 1002), eval_kf=10, width=320,
+             height=240, f=260.0, n_gt=100_000, max_iters=4000, eval_every=20,
+             plateau=(400, 0.05), levels=(8, 10, 12, 14, 16, 18, 20, 22, 24),
+             device="cuda", log=None):
+    """Heuristic against learned initialisation on held-out scenes, each run
+    until its PSNR plateaus (or max_iters): the curves and the iterations
+    each needs to reach every PSNR level."""
+    out = []
+    for s in eval_seeds:
+        runs = {}
+        for name, m in (("heuristic", None), ("learned", net)):
+            runs[name] = run_window(s, m, n_kf=eval_kf, width=width,
+                                    height=height, f=f, n_gt=n_gt,
+                                    extra_iters=max_iters,
+                                    eval_every=eval_every, plateau=plateau,
+                                    device=device)["curve"]
+        ev = dict(seed=s, heuristic=runs["heuristic"], learned=runs["learned"],
+                  levels=compare_at_levels(runs["heuristic"], runs["learned"],
+                                           levels))
+        out.append(ev)
+        if log:
+            ch, cm = runs["heuristic"], runs["learned"]
+            log(f"eval seed {s}: heuristic {ch[0][1]:.2f} -> {ch[-1][1]:.2f} dB "
+                f"in {ch[-1][0]} it., learned {cm[0][1]:.2f} -> {cm[-1][1]:.2f}"
+                f" dB in {cm[-1][0]} it.; levels {ev['levels']}")
+    return out
+
+
 def experiment(train_seeds=range(16), eval_seeds=(1000, 1001, 1002),
                n_kf=40, epochs=30, iters_per_kf=10, width=320, height=240,
-               f=260.0, n_gt=100_000, eval_kf=10, device="cuda", log=None):
+               f=260.0, n_gt=100_000, eval_kf=10, eval_iters=4000,
+               device="cuda", log=None):
     """Collects pairs from the plain mapper on the training seeds, trains the
     network, and compares heuristic vs learned initialisation on the held-out
     seeds over an ``eval_kf``-keyframe window.  Returns (results, network)."""
@@ -223,21 +266,11 @@ def experiment(train_seeds=range(16), eval_seeds=(1000, 1001, 1002),
                setup=dict(width=width, height=height, f=f, n_gt=n_gt,
                           train_seeds=list(train_seeds), n_kf=n_kf,
                           iters_per_kf=iters_per_kf, epochs=epochs,
-                          eval_seeds=list(eval_seeds), eval_kf=eval_kf))
-    for s in eval_seeds:
-        h = run_window(s, None, n_kf=eval_kf, width=width, height=height,
-                       f=f, n_gt=n_gt, device=device)
-        m = run_window(s, net, n_kf=eval_kf, width=width, height=height,
-                       f=f, n_gt=n_gt, device=device)
-        ch, cm = h["curve"], m["curve"]
-        ev = dict(seed=s, heuristic=ch, learned=cm)
-        # Iterations the heuristic needs to reach the learned PSNR at each
-        # point of the learned curve.
-        ev["equal_psnr"] = [(it, p, iterations_to_reach(ch, p)) for it, p in cm]
-        res["evals"].append(ev)
-        if log:
-            log(f"eval seed {s}: heuristic {ch[0][1]:.2f} -> {ch[-1][1]:.2f} dB, "
-                f"learned {cm[0][1]:.2f} -> {cm[-1][1]:.2f} dB")
+                          eval_seeds=list(eval_seeds), eval_kf=eval_kf,
+                          eval_iters=eval_iters))
+    res["evals"] = evaluate(net, eval_seeds, eval_kf=eval_kf, width=width,
+                            height=height, f=f, n_gt=n_gt,
+                            max_iters=eval_iters, device=device, log=log)
     return res, net
 
 
@@ -253,12 +286,24 @@ def main(argv=None):
     ap.add_argument("--height", type=int, default=240)
     ap.add_argument("--f", type=float, default=260.0)
     ap.add_argument("--n-gt", type=int, default=100_000)
+    ap.add_argument("--eval-iters", type=int, default=4000)
     ap.add_argument("--save", default="")
+    ap.add_argument("--evaluate", default="",
+                    help="skip training: evaluate the weights in this .npz")
     a = ap.parse_args(argv)
     lg = lambda *x: print(*x, file=sys.stderr, flush=True)
+    if a.evaluate:
+        net = InitMLP.load(a.evaluate)
+        res = dict(weights=a.evaluate,
+                   setup=dict(width=a.width, height=a.height, f=a.f,
+                              n_gt=a.n_gt, eval_iters=a.eval_iters),
+                   evals=evaluate(net, width=a.width, height=a.height, f=a.f,
+                                  n_gt=a.n_gt, max_iters=a.eval_iters, log=lg))
+        print(json.dumps(res))
+        return
     res, net = experiment(train_seeds=range(a.train_seeds), n_kf=a.n_kf,
                           epochs=a.epochs, width=a.width, height=a.height,
-                          f=a.f, n_gt=a.n_gt, log=lg)
+                          f=a.f, n_gt=a.n_gt, eval_iters=a.eval_iters, log=lg)
     if a.save:
         np.savez(a.save, **net.state())
     print(json.dumps(res))

@@ -1,8 +1,10 @@
 """What the learned initialisation gains over the plain heuristic (an
 empirical claim, parity unpinned): trained by the project's kernels on
 converged parameters the plain mapper produced on three training scenes, it
-reaches on held-out scenes the PSNR the heuristic needs many more window
-iterations for, and ends a fixed iteration budget ahead."""
+reaches on held-out scenes, run until their PSNR plateaus, each of at least
+three PSNR levels in fewer window iterations than the heuristic needs for
+the same level (or ever reaches)."""
+import numpy as np
 import pytest
 
 from paper_2504_02437_amd import init_mlp as IM
@@ -13,14 +15,20 @@ pytestmark = pytest.mark.gpu
 def test_learned_initialisation_beats_heuristic_on_held_out_scenes():
     print("case learned init", flush=True)
     res, net = IM.experiment(train_seeds=range(3), eval_seeds=(2000, 2001),
-                             n_kf=20, epochs=10, log=print)
+                             n_kf=20, epochs=10, eval_iters=1500, log=print)
     assert res["pairs"] > 20000
     assert res["train_loss"][-1] < 0.5 * res["train_loss"][0]
     for ev in res["evals"]:
         h, m = ev["heuristic"], ev["learned"]
-        it0, p0 = m[0]
-        # The heuristic needs more iterations to reach the learned start.
-        need = IM.iterations_to_reach(h, p0)
-        assert need is None or need > it0, (ev["seed"], need, it0)
-        # And ends the same budget at least 1 dB lower.
-        assert m[-1][1] > h[-1][1] + 1.0, (ev["seed"], m[-1], h[-1])
+        levels = np.arange(np.floor(m[0][1]), np.ceil(max(p for _, p in m)))
+        cmp = IM.compare_at_levels(h, m, levels)
+        faster = [c for c in cmp if c["learned"] is not None and
+                  (c["heuristic"] is None or c["learned"] < c["heuristic"])]
+        print("seed", ev["seed"], "levels where learned is faster:",
+              [(c["psnr"], c["learned"], c["heuristic"]) for c in faster],
+              flush=True)
+        assert len(faster) >= 3, (ev["seed"], cmp)
+        # The learned start is already a level the heuristic needs many
+        # iterations for.
+        need = IM.iterations_to_reach(h, m[0][1])
+        assert need is None or need > m[0][0], (ev["seed"], need, m[0])

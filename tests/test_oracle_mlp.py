@@ -152,3 +152,59 @@ def test_mse_gradient():
     v, g = M.mse(y, t)
     assert v == pytest.approx(((y - t) ** 2).mean())
     np.testing.assert_allclose(g, 2 * (y - t) / 70)
+
+
+def _next_bf16(x):
+    """The BF16 neighbour of each BF16 value x away from zero (one ulp)."""
+    f = np.asarray(x, np.float32)
+    u = f.view(np.uint32).astype(np.uint64) + (1 << 16)
+    return u.astype(np.uint32).view(np.float32).astype(np.float64)
+
+
+def test_forward_magnitude_bounds_one_ulp_flips():
+    """Moving any one BF16 hidden activation (layer 1 or 2) by one ulp, as a
+    rounding on the other side of a boundary would, changes every output by
+    at most 2^-7 of forward_magnitude; and the magnitude bounds |y - b3|."""
+    rng = np.random.default_rng(11)
+    w = M.init_weights(3)
+    w[-7:] = rng.normal(size=7)
+    x = rng.normal(size=(20, 32)).astype(np.float32)
+    y, c = M.forward(w, x)
+    mag = M.forward_magnitude(w, c)
+    (_, _), (W2, b2), (W3, b3) = M.unpack(w)
+    r = M.bf16
+    assert np.all(np.abs(y - b3) <= mag * (1 + 1e-12) + 1e-12)
+    worst = 0.0
+    for trial in range(300):
+        m = rng.integers(20)
+        h1, h2 = c["h1"][m].copy(), c["h2"][m].copy()
+        if trial % 2:
+            i = rng.integers(64)
+            h1[i] = _next_bf16(h1[i])
+            h2 = r(M.gelu(h1 @ r(W2) + b2))
+        else:
+            j = rng.integers(64)
+            h2[j] = _next_bf16(h2[j])
+        d = np.abs(h2 @ r(W3) + b3 - y[m])
+        assert np.all(d <= 2 ** -7 * mag[m] * (1 + 1e-9) + 1e-15), (trial, d, mag[m])
+        worst = max(worst, float((d / (2 ** -7 * mag[m] + 1e-300)).max()))
+    assert worst > 0.05     # the bound is not vacuous
+
+
+def test_backward_magnitude_bounds_the_gradient():
+    """backward_magnitude(|dy|) bounds |backward(dy)| element by element, and
+    the bound of a difference of two dy is the magnitude of the difference."""
+    rng = np.random.default_rng(12)
+    w = M.init_weights(4)
+    x = rng.normal(size=(30, 32)).astype(np.float32)
+    _, c = M.forward(w, x)
+    dy = rng.normal(size=(30, 7)) * 1e-2
+    g = M.backward(w, c, dy)
+    mg = M.backward_magnitude(w, c, np.abs(dy))
+    assert np.all(np.abs(g) <= mg * (1 + 1e-9) + 1e-18)
+    dy2 = dy + rng.normal(size=dy.shape) * 1e-4
+    d = np.abs(M.backward(w, c, dy2) - g)
+    # BF16 rounding of dy and of the hidden gradients: each a relative 2^-8.
+    bound = M.backward_magnitude(w, c, np.abs(dy2 - dy)) * (1 + 2 ** -6) + \
+        2 ** -6 * (mg + M.backward_magnitude(w, c, np.abs(dy2)))
+    assert np.all(d <= bound + 1e-18)
