@@ -11,12 +11,16 @@
 //   dL/da_i     = T_i (c_i . g - S_i) - T_final (bg . g) / (1 - a_i)
 //   dL/dpi_i    = a_i dL/da_i                 (a = o exp(pi), unclamped)
 //   dL/do_i     = G_i dL/da_i = (dL/dpi_i) / o   (summed per entry, then / o)
-// with pi = -(A dx^2 + C dy^2) / 2 - B dx dy.  A thread's pixels share dx, so
-// it accumulates only sum(dL/dpi), sum(dL/dpi dy) and sum(dL/dpi dy^2) over
-// its strip and forms the mean and conic gradients once per entry.  The nine
-// per-entry sums are reduced over each 16-lane row with DPP (a transposed
-// reduction that packs four quantities into one register), merged across
-// rows and waves by LDS adds, and added to global memory with one atomic per
+// with pi = -(A dx^2 + C dy^2) / 2 - B dx dy.  A thread's pixels share dx,
+// so per entry it needs only the moments sum(dL/dpi), sum(dL/dpi dy) and
+// sum(dL/dpi dy^2) over its strip; the rows of a strip are consecutive
+// (dy_p = dy_0 - p), so these follow from sums weighted by the constants p
+// and p^2.  Nine per-lane sums per entry (the three moments, the first one
+// times dx and dx^2, the second times dx, and the colour gradient) are
+// reduced over each 16-lane row with DPP (a transposed reduction that packs
+// four quantities into one register), merged across rows and waves by LDS
+// adds, and turned into the mean, conic and opacity gradients once per
+// entry and workgroup, which adds them to global memory with one atomic per
 // (entry, quantity).
 
 #include "raster_common.h"
@@ -57,26 +61,53 @@ __device__ __forceinline__ float add_dpp(float x, float y) {
   return x + __int_as_float(t);
 }
 
-// Transposed row reduction of four per-lane values: returns, in each lane,
-// the sum over the lane's 16-lane row of value number (lane >> 2) & 3.
-// Two bank-masked exchange levels halve the number of registers each time
-// (shift 4: banks 0, 2 keep a / c and banks 1, 3 keep b / d; shift 8: banks
-// 0, 1 keep the first pair), then a quad reduction finishes each bank.
-__device__ __forceinline__ float row_sum4(float a, float b, float c, float d,
-                                          bool bank02, bool bank01) {
-  // The DPP reads of neighbouring lanes run in converged control flow; only
-  // the selects depend on the lane.
-  const float a1 = add_dpp<0x104>(a, a);   // row_shl:4
-  const float b1 = add_dpp<0x114>(b, b);   // row_shr:4
-  const float c1 = add_dpp<0x104>(c, c);
-  const float d1 = add_dpp<0x114>(d, d);
-  const float ab = bank02 ? a1 : b1;
-  const float cd = bank02 ? c1 : d1;
-  const float ab1 = add_dpp<0x108>(ab, ab);  // row_shl:8
-  const float cd1 = add_dpp<0x118>(cd, cd);  // row_shr:8
-  float x = bank01 ? ab1 : cd1;
-  x = add_dpp<0xb1>(x, x);   // quad_perm [1,0,3,2]
-  x = add_dpp<0x4e>(x, x);   // quad_perm [2,3,0,1]
+// a + b over the two halves of the wave: returns, in lanes 0-31, a's lanes
+// l + (l + 32) and, in lanes 32-63, b's (v_permlane32_swap exchanges the
+// upper half of its first operand with the lower half of its second).
+__device__ __forceinline__ float fold32(float a, float b) {
+  const auto t = __builtin_amdgcn_permlane32_swap(__float_as_uint(a),
+                                                  __float_as_uint(b), false,
+                                                  false);
+  return __uint_as_float(t[0]) + __uint_as_float(t[1]);
+}
+
+// The same over adjacent rows: rows 0 and 2 receive a's rows r + (r + 1)
+// and rows 1 and 3 b's (v_permlane16_swap exchanges the odd rows of its
+// first operand with the even rows of its second).
+__device__ __forceinline__ float fold16(float a, float b) {
+  const auto t = __builtin_amdgcn_permlane16_swap(__float_as_uint(a),
+                                                  __float_as_uint(b), false,
+                                                  false);
+  return __uint_as_float(t[0]) + __uint_as_float(t[1]);
+}
+
+// Sum over the wave of eight per-lane values: lane 8k receives the total of
+// q[k].  A transposed reduction: the two half-wave folds and the two row
+// folds leave two registers whose row r holds one value's 16 row partials
+// (value r of the first four, in the order 0, 2, 4, 6 / 1, 3, 5, 7 below),
+// a shift-8 exchange writing only banks 0-1 from the first register and
+// banks 2-3 from the second (bank_mask: no select) merges them, and three
+// shifts within each half-row finish the sums.  The DPP adds read
+// registers written just before them, which needs two wait states after a
+// VALU write (the s_nop 1 before each); lanes whose DPP source lies outside
+// their row are not written and are not used.  Runs in converged control
+// flow with every lane active.
+__device__ __forceinline__ float wave_sum8(const float (&q)[8]) {
+  const float r1 = fold16(fold32(q[0], q[4]), fold32(q[2], q[6]));
+  const float r2 = fold16(fold32(q[1], q[5]), fold32(q[3], q[7]));
+  float x;
+  asm volatile(
+      "s_nop 1\n\t"
+      "v_add_f32_dpp %[x], %[r1], %[r1] row_shl:8 row_mask:0xf bank_mask:0x3\n\t"
+      "v_add_f32_dpp %[x], %[r2], %[r2] row_shr:8 row_mask:0xf bank_mask:0xc\n\t"
+      "s_nop 1\n\t"
+      "v_add_f32_dpp %[x], %[x], %[x] row_shl:4 row_mask:0xf bank_mask:0xf\n\t"
+      "s_nop 1\n\t"
+      "v_add_f32_dpp %[x], %[x], %[x] row_shl:2 row_mask:0xf bank_mask:0xf\n\t"
+      "s_nop 1\n\t"
+      "v_add_f32_dpp %[x], %[x], %[x] row_shl:1 row_mask:0xf bank_mask:0xf"
+      : [x] "=&v"(x)
+      : [r1] "v"(r1), [r2] "v"(r2));
   return x;
 }
 
@@ -107,7 +138,8 @@ struct BwdPix {
   int last[PPT];
 };
 
-// Per-lane sums of one entry over the thread's strip.
+// Per-lane sums of one entry over the thread's strip: S0, S1, S2 are the
+// moments sum(dL/dpi dy^k), k = 0, 1, 2.
 struct EntrySums {
   float S0, S1, S2, d_r, d_g, d_b;
   bool hit;
@@ -121,21 +153,27 @@ struct EntrySums {
 // CLAMP: some entry of the batch has opacity above alpha_max, so alpha is
 // clamped and a clamped pair passes no shape or opacity gradient; batches
 // without such an entry (nearly all) run the version without the clamp.
-// BG: a non-zero background, whose term enters dL/dalpha.  The opacity
-// gradient is formed once per entry from S0 = sum of dL/dpi: with
-// alpha = o G unclamped, dL/dpi = alpha dL/dalpha and dL/do = G dL/dalpha =
-// S0 / o (clamped pairs add 0 to both).
+// BG: a non-zero background, whose term enters dL/dalpha.  With the weight
+// w = alpha T_i, dL/dpi = alpha dL/dalpha is w (c.g - S) without a
+// background.  The moments are formed from P0 = sum(dL/dpi),
+// P1 = sum(p dL/dpi) and P2 = sum(p^2 dL/dpi) over the strip's rows p:
+// with dy_p = dy_0 - p, S1 = dy_0 P0 - P1 and
+// S2 = dy_0^2 P0 - 2 dy_0 P1 + P2 = dy_0 (S1 - P1) + P2.
 template <bool CLAMP, bool BG, int PPT>
 __device__ __forceinline__ EntrySums entry_bwd(BwdPix<PPT>& px,
                                                const Column& col, float py,
                                                float C2, float o, float cr,
                                                float cgc, float cbc, float amin,
                                                float amax, const bool* inb) {
-  EntrySums r = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, false};
+  EntrySums r;
+  r.hit = false;
+  r.d_r = r.d_g = r.d_b = 0.f;
+  float P0 = 0.f, P1 = 0.f, P2 = 0.f, dy0 = 0.f;
 #pragma unroll
   for (int p = 0; p < PPT; ++p) {
     float dy;
     const float e2 = exponent2(col, py, C2, px.vf[p], dy);
+    if (p == 0) dy0 = dy;
     const float G = gauss2(e2);
     const float oG = o * G;
     const float al = CLAMP ? fminf(amax, oG) : oG;
@@ -151,14 +189,20 @@ __device__ __forceinline__ EntrySums entry_bwd(BwdPix<PPT>& px,
     r.d_b = fmaf(w, px.g2[p], r.d_b);
     const float cgp = fmaf(cr, px.g0[p], fmaf(cgc, px.g1[p], cbc * px.g2[p]));
     const float diff = cgp - px.Sg[p];
-    const float dal = BG ? fmaf(Ti, diff, -(px.Tb[p] * rom)) : Ti * diff;
     px.Sg[p] = fmaf(alo, diff, px.Sg[p]);
-    const float dpw = (CLAMP && oG > amax) ? 0.f : dal * alo;
-    const float tdy = dpw * dy;
-    r.S0 += dpw;
-    r.S1 += tdy;
-    r.S2 = fmaf(tdy, dy, r.S2);
+    float dpw = BG ? alo * fmaf(Ti, diff, -(px.Tb[p] * rom)) : w * diff;
+    if (CLAMP) dpw = oG > amax ? 0.f : dpw;
+    if (p == 0) {
+      P0 = dpw;
+    } else {
+      P0 += dpw;
+      P1 = p == 1 ? dpw : fmaf((float)p, dpw, P1);
+      P2 = p == 1 ? dpw : fmaf((float)(p * p), dpw, P2);
+    }
   }
+  r.S0 = P0;
+  r.S1 = fmaf(dy0, P0, -P1);
+  r.S2 = fmaf(dy0, r.S1 - P1, P2);
   return r;
 }
 
@@ -167,7 +211,7 @@ template <bool CLAMP, bool BG, int TILE, int BATCH, int NT>
 __device__ __forceinline__ void walk_batch(
     BwdPix<PixLayout<TILE, NT>::PPT>& px, const Entry* ent, const int* wbits,
     float (*acc)[9], int jn, int lo, int wave, int wfirst, int u, int v0,
-    float uf, float amin, float amax, int lane, bool bank02, bool bank01) {
+    float uf, float amin, float amax, int lane) {
   constexpr int PPT = PixLayout<TILE, NT>::PPT;
   for (int j = jn - 1; j >= 0; --j) {
     const int pos = lo + j;
@@ -194,28 +238,19 @@ __device__ __forceinline__ void walk_batch(
     }
     const EntrySums es = entry_bwd<CLAMP, BG>(px, col, ea.y, eb.x, eb.y, eb.z,
                                               eb.w, ec.x, amin, amax, inb);
-    if (__any(es.hit)) {
-      const float A = ec.y, B = ec.z, C = ec.w;
+    if (__builtin_amdgcn_ballot_w64(es.hit) != 0) {
+      // Wave totals of eight of the nine per-lane sums, added into the
+      // entry's LDS slot by lanes 0, 8, ..., 56 (distinct addresses), and
+      // row totals of the ninth by lane 0 of each row; the other waves of
+      // the tile meet in the LDS adds.
       const float dx = col.dx, dxS0 = dx * es.S0;
-      const float d_px = -fmaf(A, dxS0, B * es.S1);
-      const float d_py = -fmaf(C, es.S1, B * dxS0);
-      const float d_A = -0.5f * dx * dxS0;
-      const float d_B = -dx * es.S1;
-      const float d_C = -0.5f * es.S2;
-      const float d_o = es.S0 * __builtin_amdgcn_rcpf(eb.y);
-      // Row sums of the nine quantities, added into the entry's LDS slot by
-      // lanes 0, 4, 8, 12 of each row (the four rows of the wave and the
-      // other waves of the tile meet in the LDS adds).
-      const float x = row_sum4(d_px, d_py, d_A, d_B, bank02, bank01);
-      const float y = row_sum4(d_C, d_o, es.d_r, es.d_g, bank02, bank01);
+      const float q[8] = {es.S0, dxS0, dx * dxS0, es.S1,
+                          dx * es.S1, es.S2, es.d_r, es.d_g};
+      const float x = wave_sum8(q);
       const float z = row_sum(es.d_b);
       float* ac = acc[j];
-      if ((lane & 3) == 0) {
-        const int q = (lane >> 2) & 3;
-        atomicAdd(&ac[q], x);
-        atomicAdd(&ac[4 + q], y);
-        if (q == 0) atomicAdd(&ac[8], z);
-      }
+      if ((lane & 7) == 0) atomicAdd(&ac[lane >> 3], x);
+      if ((lane & 15) == 0) atomicAdd(&ac[8], z);
     }
   }
 }
@@ -227,7 +262,7 @@ __device__ __forceinline__ void walk_batch(
 // the fast path (wave_bits, and the entry before every pixel's n_last) when
 // it can; the choice is uniform over the wave.
 template <int TILE, int BATCH, int NT, bool BG>
-__global__ __launch_bounds__(NT) void k_render_bwd(BwdArgs a) {
+__global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(BG ? 1 : 5))) void k_render_bwd(BwdArgs a) {
   using Lay = PixLayout<TILE, NT>;
   constexpr int PPT = Lay::PPT;
   __shared__ Entry ent[BATCH];
@@ -242,8 +277,6 @@ __global__ __launch_bounds__(NT) void k_render_bwd(BwdArgs a) {
   const int ty = rem / r.Tx, tx = rem - ty * r.Tx;
   const int tid = threadIdx.x;
   const int lane = tid & 63;
-  const bool bank02 = ((lane >> 2) & 1) == 0;   // lane in bank 0 or 2 of its row
-  const bool bank01 = ((lane >> 3) & 1) == 0;   // lane in bank 0 or 1
   long long s, e;
   tile_range(r, t, s, e);
   const size_t HW = (size_t)r.H * r.W;
@@ -351,21 +384,39 @@ __global__ __launch_bounds__(NT) void k_render_bwd(BwdArgs a) {
     if (__syncthreads_or(clampable)) {
       walk_batch<true, BG, TILE, BATCH, NT>(px, ent, wbits, acc, jn, lo, wave,
                                             wfirst, u, v0, uf, amin, amax,
-                                            lane, bank02, bank01);
+                                            lane);
     } else {
       walk_batch<false, BG, TILE, BATCH, NT>(px, ent, wbits, acc, jn, lo, wave,
                                              wfirst, u, v0, uf, amin, amax,
-                                             lane, bank02, bank01);
+                                             lane);
     }
     __syncthreads();
-    for (int i = tid; i < cnt * 9; i += NT) {
-      const float val = (&acc[0][0])[i];
-      if (val == 0.f) continue;
-      const int jj = i / 9, q = i - jj * 9;
+    // Per entry: the mean, conic and opacity gradients from the nine sums
+    // (A, B, C the unscaled conic, o the opacity), then one atomic each.
+    for (int jj = tid; jj < cnt; jj += NT) {
+      const float* ac = acc[jj];
+      const float s0 = ac[0], xs0 = ac[1], x2s0 = ac[2], s1 = ac[3];
+      const float xs1 = ac[4], s2 = ac[5];
+      const float4 ec = ent[jj].c;
+      const float A = ec.y, B = ec.z, C = ec.w;
+      float val[9];
+      val[0] = -fmaf(A, xs0, B * s1);   // dL/dpx
+      val[1] = -fmaf(C, s1, B * xs0);   // dL/dpy
+      val[2] = -0.5f * x2s0;            // dL/dA
+      val[3] = -xs1;                    // dL/dB
+      val[4] = -0.5f * s2;              // dL/dC
+      val[5] = s0 / ent[jj].b.y;        // dL/do
+      val[6] = ac[6];
+      val[7] = ac[7];
+      val[8] = ac[8];
       const uint32_t g = gid[jj];
-      if (q < 5) atomicAdd(&gk[(size_t)q * r.cap + g], val);
-      else if (q == 5) atomicAdd(&a.gop[g], val);
-      else atomicAdd(&gc[(size_t)(q - 6) * r.cap + g], val);
+#pragma unroll
+      for (int q = 0; q < 9; ++q) {
+        if (val[q] == 0.f) continue;
+        if (q < 5) atomicAdd(&gk[(size_t)q * r.cap + g], val[q]);
+        else if (q == 5) atomicAdd(&a.gop[g], val[q]);
+        else atomicAdd(&gc[(size_t)(q - 6) * r.cap + g], val[q]);
+      }
     }
   }
 }
