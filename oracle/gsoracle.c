@@ -363,11 +363,13 @@ static int eval_pair(const fwdcfg* F, const double* r, const int32_t* b,
   const double pw = -0.5 * (A * dx * dx + C * dy * dy) - B * dx * dy;
   const double S = fabs(A) * dx * dx + 2.0 * fabs(B) * fabs(dx * dy) +
                    fabs(C) * dy * dy;
-  /* First-order bound on the relative error of alpha evaluated in FP32:
-   * the exponent is a sum of three products (about 2 eps S), its scaling and
-   * exponential add about eps (|pi| + 2) <= eps (S / 2 + 2), and the product
-   * with the opacity one more eps; 4 S + 4 keeps a margin over 2.5 S + 3. */
-  const double ea = EPS32 * (4.0 * S + 4.0);
+  /* First-order bound on the relative error of alpha evaluated in FP32 as
+   * the exponential of log2(o) plus the scaled exponent: the exponent is a
+   * sum of three products (about 2 eps S), its scaling and exponential add
+   * about eps (|pi| + 2) <= eps (S / 2 + 2), and log2(o), rounded once and
+   * added inside the sum, about 2 eps |ln o|; 4 S + 4 + 3 |ln o| keeps a
+   * margin over 2.5 S + 2 + 2 |ln o|. */
+  const double ea = EPS32 * (4.0 * S + 4.0 + 3.0 * fabs(log(o)));
   if (ea_out) *ea_out = ea;
   *dxo = dx; *dyo = dy;
   if (amb && pw != 0.0 && fabs(pw) <= 8.0 * EPS32 * S) *amb |= 8;
@@ -605,7 +607,7 @@ OR_EXPORT void or_admit_extent(int V, int n, const double* rec,
         const double S = fabs(A) * dx * dx + 2.0 * fabs(B) * fabs(dx * dy) +
                          fabs(C) * dy * dy;
         if (pw > 8.0 * EPS32 * S) continue;
-        const double ea = EPS32 * (4.0 * S + 4.0);
+        const double ea = EPS32 * (4.0 * S + 4.0 + 3.0 * fabs(log(op)));
         if (op * exp(pw) < alpha_min * (1.0 - fmax(1e-5, ea))) continue;
         if (u < ulo) ulo = u;
         if (u > uhi) uhi = u;

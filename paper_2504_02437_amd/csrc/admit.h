@@ -1,13 +1,14 @@
 // Conservative bounds on where the compositing kernels can admit a Gaussian.
 //
 // The kernels admit a (pixel, entry) pair only when their FP32 alpha =
-// min(alpha_max, o * exp2(e2)) reaches alpha_min, with e2 the FP32 evaluation
-// of -log2(e)/2 * q(d), q(d) = A dx^2 + 2 B dx dy + C dy^2 over the published
-// record (d = mean2D - pixel).  The rounding error of e2 is below 8 u S
-// (u = 2^-24, S the sum of the magnitudes of the three terms), and exp2 and
-// the product with o add less than 2^-20 relative.  So an admitted pixel of
-// the integer box satisfies
-//   q(d) <= 2 ln(o / alpha_min) + 2 ln(2) (16 u S_max + 2^-19) =: L,
+// min(alpha_max, exp2(e2)) reaches alpha_min, with e2 the FP32 evaluation of
+// log2(o) - log2(e)/2 * q(d), q(d) = A dx^2 + 2 B dx dy + C dy^2 over the
+// published record (d = mean2D - pixel).  The rounding error of e2 is below
+// u (8 S + 4 |log2 o|) (u = 2^-24, S the sum of the magnitudes of the three
+// quadratic terms, log2(o) rounded once), and exp2 adds less than 2^-20
+// relative.  So an admitted pixel of the integer box satisfies
+//   q(d) <= 2 ln(o / alpha_min) + 2 ln(2) (u (16 S_max + 4 |log2 o|) + 2^-19)
+//        =: L,
 // with S_max bounding S over the box.  L is formed in FP32 with relative and
 // absolute slack well above its own rounding.
 #pragma once
@@ -32,7 +33,8 @@ __device__ inline float admit_level(const Record& R, int iu0, int iu1, int iv0,
   const float dym = fmaxf(fabsf(py - (float)iv0), fabsf((float)iv1 - py)) + 1.f;
   const float smax = 0.7213475f * ((A * dxm * dxm + 2.f * fabsf(B) * dxm * dym) +
                                    C * dym * dym) * 1.0001f;
-  const float marg = 16.f * 0x1p-24f * smax + 0x1p-19f;
+  const float marg = 0x1p-24f * (16.f * smax + 4.f * fabsf(log2f(o))) +
+                     0x1p-19f;
   return 2.f * logf(o / amin) + 1.3862944f * marg + 1e-5f;
 }
 

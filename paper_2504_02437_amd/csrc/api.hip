@@ -155,7 +155,7 @@ static int make_layout(const gs_geometry* g, Layout& L, int& tx, int& ty) {
   L.grad2d = take(V * 5 * cap * 4);
   L.gop = take(cap * 4);
   L.gcol = take(V * 3 * cap * 4);
-  L.shape = take(cap * (6 * 8 + 4));
+  L.shape = take(cap * (6 * 8 + 4 + 4));
   L.counters = take(sizeof(Counters));
   L.total = off;
   return GS_OK;

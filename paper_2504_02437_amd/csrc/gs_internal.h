@@ -99,7 +99,8 @@ struct gs_workspace {
   float* gcol;           // [V][3][capacity] dL/d colour per view (used with
                          // view-dependent colour)
   double* shape;         // [6][capacity] 3D covariance (upper triangle) of
-                         // the last projection, then float opacity [capacity]
+                         // the last projection, then float opacity
+                         // [capacity] and float log2(opacity) [capacity]
   gs::Counters* counters;
 };
 

@@ -6,8 +6,8 @@
 // bit by any FP64 implementation that follows the same order.
 //
 // Layout: the view-independent part (scale, rotation, 3D covariance,
-// opacity) is formed once per Gaussian by k_shape and kept in the workspace
-// (52 bytes per Gaussian); k_project then runs one thread per (view,
+// opacity and its base-2 logarithm) is formed once per Gaussian by k_shape
+// and kept in the workspace (56 bytes per Gaussian); k_project then runs one thread per (view,
 // Gaussian), ten times the parallelism of a per-Gaussian loop over the
 // views, which the long FP64 division and square-root chains need to hide
 // their latency.  Its blocks are ordered so that the views of one chunk of
@@ -34,6 +34,7 @@ struct ProjArgs {
   int cap;
   double* sig;    // [6][cap] Sigma upper triangle; sig[0] = NaN: bad shape
   float* op;      // [cap] opacity
+  float* lop;     // [cap] log2(opacity) of the FP32 opacity, rounded once
   int chunks;     // ceil(cap / 256)
   const gs_camera* cams;
   int V, W, H, tile, Tx, Ty;
@@ -258,7 +259,9 @@ __global__ __launch_bounds__(256) void k_shape(ProjArgs a) {
   // A failed shape (zero or non-finite quaternion, non-finite scale) is
   // culled in every view; a valid one has a finite, non-negative Sigma_00.
   if (!S.ok) a.sig[g] = NAN;
-  a.op[g] = (float)(1.0 / (1.0 + exp(-(double)a.opl[g])));
+  const float op = (float)(1.0 / (1.0 + exp(-(double)a.opl[g])));
+  a.op[g] = op;
+  a.lop[g] = (float)log2((double)op);
 }
 
 __global__ __launch_bounds__(256) void k_project(ProjArgs a) {
@@ -515,6 +518,7 @@ hipError_t launch_project(gs_workspace* ws, const gs_params* p,
   a.diff_atomics = bin_chunk(ws->tiles_x, ws->tiles_y) == 0;
   a.sig = ws->shape;
   a.op = (float*)(ws->shape + 6 * (size_t)p->capacity);
+  a.lop = a.op + p->capacity;
   a.chunks = (p->capacity + 255) / 256;
   if (a.chunks <= 0) return hipSuccess;
   hipLaunchKernelGGL(k_shape, dim3(a.chunks), dim3(256), 0, st, a);

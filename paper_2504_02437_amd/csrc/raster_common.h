@@ -19,10 +19,11 @@
 namespace gs {
 
 // One staged Gaussian in LDS (64 bytes).  The exponent coefficients are
-// pre-scaled so that exp(-1/2 d^T Q d) = exp2(A2 dx^2 + C2 dy^2 + B2 dx dy).
+// pre-scaled so that o exp(-1/2 d^T Q d) = exp2(log2(o) + A2 dx^2 + C2 dy^2
+// + B2 dx dy).
 struct __align__(16) Entry {
   float4 a;   // px, py, A2, B2
-  float4 b;   // C2, opacity, r, g
+  float4 b;   // C2, log2(opacity), r, g
   float4 c;   // b, A, B, C (unscaled conic, for the backward)
   int4 box;   // u_lo, u_hi, v_lo, v_hi
 };
@@ -57,11 +58,13 @@ __device__ __forceinline__ int4 unpack_box(int2 b) {
   return make_int4(b.x & 0xffff, b.x >> 16, b.y & 0xffff, b.y >> 16);
 }
 
+// lo: log2 of the opacity, formed in FP64 by the projection and rounded
+// once (relative error below u = 2^-24).
 __device__ __forceinline__ void stage(Entry& E, const Record& R,
-                                      const int4& box) {
+                                      const int4& box, float lo) {
   const float A = R.q0.z, B = R.q0.w, C = R.q1.x;
   E.a = make_float4(R.q0.x, R.q0.y, A * kHalfLog2e, B * kLog2e);
-  E.b = make_float4(C * kHalfLog2e, R.q1.y, R.q1.z, R.q1.w);
+  E.b = make_float4(C * kHalfLog2e, lo, R.q1.z, R.q1.w);
   E.c = make_float4(R.q2.x, A, B, C);
   E.box = box;
 }
@@ -101,34 +104,37 @@ __device__ __forceinline__ float pinned(float x) {
 }
 
 // Column part of the exponent for one (entry, thread): dx and the terms that
-// depend on dx only.
+// depend on dx only, with log2(o) added to the dx^2 term.
 struct Column {
   float dx, a0, b0;
 };
 
-__device__ __forceinline__ Column column(const float4& ea, float uf) {
+__device__ __forceinline__ Column column(const float4& ea, float lo,
+                                         float uf) {
   Column c;
   c.dx = ea.x - uf;
-  c.a0 = (ea.z * c.dx) * c.dx;   // A2 dx^2
-  c.b0 = ea.w * c.dx;            // B2 dx
+  c.a0 = fmaf(ea.z * c.dx, c.dx, lo);   // log2(o) + A2 dx^2
+  c.b0 = ea.w * c.dx;                   // B2 dx
   return c;
 }
 
-// Base-2 exponent of the Gaussian at the pixel in row vf of the thread's
-// column, e2 = A2 dx^2 + B2 dx dy + C2 dy^2 = a0 + dy (b0 + C2 dy) in Horner
-// form (two FMAs; its rounding error stays below 3 u S, S the sum of the
-// three terms' magnitudes).
+// Base-2 exponent of alpha at the pixel in row vf of the thread's column,
+// e2 = log2(o) + A2 dx^2 + B2 dx dy + C2 dy^2 = a0 + dy (b0 + C2 dy) in
+// Horner form (two FMAs; with the column terms its rounding error stays
+// below u (3 S + 3 |log2 o|), S the sum of the three quadratic terms'
+// magnitudes).
 __device__ __forceinline__ float exponent2(const Column& c, float py, float C2,
                                            float vf, float& dy) {
   dy = py - vf;
   return fmaf(fmaf(C2, dy, c.b0), dy, c.a0);
 }
 
-// The Gaussian's value exp2(e2) with e2 taken as -|e2|: the exponent is a
-// negative semi-definite form, so e2 > 0 arises only by rounding next to the
-// centre, where the pair is then evaluated as at the centre (G <= 1 always).
-__device__ __forceinline__ float gauss2(float e2) {
-  return __builtin_amdgcn_exp2f(-fabsf(e2));
+// The unclamped alpha o G = exp2(e2), clamped to [0, 1] (the exponential's
+// output clamp, no extra instruction): the quadratic form is negative
+// semi-definite, so only rounding next to the centre of a very elongated
+// footprint could take e2 above log2(o); alpha stays at most 1 there.
+__device__ __forceinline__ float alpha2(float e2) {
+  return __builtin_amdgcn_fmed3f(__builtin_amdgcn_exp2f(e2), 0.f, 1.f);
 }
 
 // Per staged entry and wave, two bits: bit 2w set when wave w evaluates the
@@ -156,9 +162,41 @@ __device__ inline int wave_bits(const Record& R, const int4& rb, int tu0,
   return bits;
 }
 
+// Per staged batch and wave w: bit j of eval[w] is set when wave w has to
+// evaluate staged entry j (wave_bits, bit 2w), bit j of fast[w] when it may
+// take the fast path (bit 2w + 1).  A wave walks the set bits of its own
+// words in scalar registers, so skipped entries cost nothing.
+template <int BATCH, int NT>
+struct alignas(8) WaveMasks {
+  uint32_t eval[NT / 64][BATCH / 32];
+  uint32_t fast[NT / 64][BATCH / 32];
+};
+
+// Called by every thread of the workgroup in converged control flow, after
+// it staged entry i0 + tid (bits: its wave_bits, 0 past the batch's end):
+// each wave turns its 64 entries' bits into two 64-bit ballots per target
+// wave, stored by its first lane.  Every word that holds an entry below the
+// batch's count is written by the round that stages it.
+template <int BATCH, int NT>
+__device__ inline void publish_masks(WaveMasks<BATCH, NT>& m, int i0,
+                                     int bits, int wave, int lane) {
+  if (i0 + 64 * wave >= BATCH) return;   // uniform over the wave
+  const int dw = (i0 >> 5) + 2 * wave;   // even: 8-byte aligned
+#pragma unroll
+  for (int w = 0; w < NT / 64; ++w) {
+    const uint64_t e = __builtin_amdgcn_ballot_w64((bits >> (2 * w)) & 1);
+    const uint64_t f = __builtin_amdgcn_ballot_w64((bits >> (2 * w + 1)) & 1);
+    if (lane == 0) {
+      *reinterpret_cast<uint64_t*>(&m.eval[w][dw]) = e;
+      *reinterpret_cast<uint64_t*>(&m.fast[w][dw]) = f;
+    }
+  }
+}
+
 struct RasterArgs {
   const Record* rec;
   const int2* rbox;
+  const float* lop;   // [capacity] log2(opacity)
   int ellipse_test;   // 0 with GS_FLAG_FULL_BOX
   const uint32_t* vals;
   const uint32_t* ranges;

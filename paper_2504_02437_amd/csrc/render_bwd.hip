@@ -162,8 +162,8 @@ struct EntrySums {
 template <bool CLAMP, bool BG, int PPT>
 __device__ __forceinline__ EntrySums entry_bwd(BwdPix<PPT>& px,
                                                const Column& col, float py,
-                                               float C2, float o, float cr,
-                                               float cgc, float cbc, float amin,
+                                               float C2, float cr, float cgc,
+                                               float cbc, float amin,
                                                float amax, const bool* inb) {
   EntrySums r;
   r.hit = false;
@@ -174,8 +174,7 @@ __device__ __forceinline__ EntrySums entry_bwd(BwdPix<PPT>& px,
     float dy;
     const float e2 = exponent2(col, py, C2, px.vf[p], dy);
     if (p == 0) dy0 = dy;
-    const float G = gauss2(e2);
-    const float oG = o * G;
+    const float oG = alpha2(e2);
     const float al = CLAMP ? fminf(amax, oG) : oG;
     const bool ok = inb[p] && al >= amin;
     r.hit |= ok;
@@ -220,7 +219,7 @@ __device__ __forceinline__ void walk_batch(
     const float4 ea = ent[j].a;
     const float4 eb = ent[j].b;
     const float4 ec = ent[j].c;
-    const Column col = column(ea, uf);
+    const Column col = column(ea, eb.y, uf);
     // Only the box / position masks differ between the fast and the general
     // path, chosen in scalar registers, so the pixels' running state is
     // updated by one common body.
@@ -236,8 +235,8 @@ __device__ __forceinline__ void walk_batch(
       for (int p = 0; p < PPT; ++p)
         inb[p] = in_u && rlo <= p && p <= rhi && pos < px.last[p];
     }
-    const EntrySums es = entry_bwd<CLAMP, BG>(px, col, ea.y, eb.x, eb.y, eb.z,
-                                              eb.w, ec.x, amin, amax, inb);
+    const EntrySums es = entry_bwd<CLAMP, BG>(px, col, ea.y, eb.x, eb.z, eb.w,
+                                              ec.x, amin, amax, inb);
     if (__builtin_amdgcn_ballot_w64(es.hit) != 0) {
       // Wave totals of eight of the nine per-lane sums, added into the
       // entry's LDS slot by lanes 0, 8, ..., 56 (distinct addresses), and
@@ -268,6 +267,7 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(BG ? 1 : 5))
   __shared__ Entry ent[BATCH];
   __shared__ float acc[BATCH][9];
   __shared__ uint32_t gid[BATCH];
+  __shared__ float eop[BATCH];   // opacity per staged entry
   __shared__ int smax;
   const RasterArgs& r = a.r;
   const int t = (int)r.order[blockIdx.x];
@@ -373,8 +373,9 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(BG ? 1 : 5))
       const uint32_t g = r.vals[s + lo + i];
       gid[i] = g;
       const Record R = rv[g];
+      eop[i] = R.q1.y;
       const int4 box = unpack_box(rbv[g]);
-      stage(ent[i], R, box);
+      stage(ent[i], R, box, r.lop[g]);
       wbits[i] = wave_bits<TILE, NT>(R, box, tx * TILE, ty * TILE, r.W, r.H,
                                      amin, amax, r.ellipse_test);
       clampable |= R.q1.y > amax;
@@ -405,7 +406,7 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(BG ? 1 : 5))
       val[2] = -0.5f * x2s0;            // dL/dA
       val[3] = -xs1;                    // dL/dB
       val[4] = -0.5f * s2;              // dL/dC
-      val[5] = s0 / ent[jj].b.y;        // dL/do
+      val[5] = s0 / eop[jj];            // dL/do
       val[6] = ac[6];
       val[7] = ac[7];
       val[8] = ac[8];

@@ -36,14 +36,14 @@ struct FwdArgs {
 // candidate T (1 - alpha) is negative, below T_min, so it never contributes,
 // and stopping it again (T = -|T|) leaves it as it is.  Pixels outside the
 // image start stopped.  The per-pixel work is predicated rather than
-// branched: every lane evaluates
-// alpha for each of its pixels and the decisions select what is
-// accumulated.  A wave skips an entry outright when no pixel of its
-// footprint can admit it (wave_bits, bit 0), and takes a fast path without
-// the per-pixel box tests and the alpha clamp when the entry's render box
-// holds the whole footprint and its opacity is at most alpha_max (bit 1);
-// the choice is uniform over the wave, read into a scalar register.  The
-// candidate transmittance is formed as fma(-alpha, T, T), one rounding.
+// branched: every lane evaluates alpha for each of its pixels and the
+// decisions select what is accumulated.  A wave skips an entry outright
+// when no pixel of its footprint can admit it (its eval mask bit), and
+// takes a fast path without the per-pixel box tests and the alpha clamp
+// when the entry's render box holds the whole footprint and its opacity is
+// at most alpha_max (its fast mask bit); the choice is uniform over the
+// wave, made in scalar registers.  The candidate transmittance is formed as
+// fma(-alpha, T, T), one rounding.
 enum { kRender = 0, kCount = 1, kDominant = 2 };
 
 template <int PPT, int MODE>
@@ -63,17 +63,16 @@ struct PixState {
 template <bool CLAMP, int PPT, int MODE>
 __device__ __forceinline__ void blend_entry(PixState<PPT, MODE>& st,
                                             const Column& col, float py,
-                                            float C2, float o, float cr,
-                                            float cg, float cb, float amin,
-                                            float amax, float tmin,
-                                            const bool* inb, int idx,
-                                            int32_t gj) {
+                                            float C2, float cr, float cg,
+                                            float cb, float amin, float amax,
+                                            float tmin, const bool* inb,
+                                            int idx, int32_t gj) {
 #pragma unroll
   for (int p = 0; p < PPT; ++p) {
     float dy;
     const float e2 = exponent2(col, py, C2, st.vf[p], dy);
-    const float G = gauss2(e2);
-    const float al = CLAMP ? fminf(amax, o * G) : o * G;
+    const float oG = alpha2(e2);
+    const float al = CLAMP ? fminf(amax, oG) : oG;
     const bool ok = inb[p] && al >= amin;
     const float Tn = fmaf(-al, st.T[p], st.T[p]);
     const bool con = ok && Tn >= tmin;
@@ -95,60 +94,98 @@ __device__ __forceinline__ void blend_entry(PixState<PPT, MODE>& st,
   }
 }
 
-// The staged batch front to back for one thread's strip.
+// Staged entry j for one thread's strip; fast: the wave's fast-path bit.
 template <bool CLAMP, int TILE, int NT, int MODE>
+__device__ __forceinline__ void walk_entry(
+    PixState<PixLayout<TILE, NT>::PPT, MODE>& st, const Entry* ent,
+    const uint32_t* egid, int j, bool fast, int base, int u, int v0,
+    float uf, float amin, float amax, float tmin) {
+  constexpr int PPT = PixLayout<TILE, NT>::PPT;
+  const float4 ea = ent[j].a;
+  const float4 eb = ent[j].b;
+  const float ecb = ent[j].c.x;
+  const Column col = column(ea, eb.y, uf);
+  const int32_t gj = MODE == kDominant ? (int32_t)egid[j] : 0;
+  // Only the box masks differ between the fast and the general path, chosen
+  // in scalar registers, so the pixels' running state is updated by one
+  // common body.
+  bool inb[PPT];
+  if (fast) {
+#pragma unroll
+    for (int p = 0; p < PPT; ++p) inb[p] = true;
+  } else {
+    const int4 box = ent[j].box;
+    const bool in_u = u >= box.x && u <= box.y;
+    const int lo = box.z - v0, hi = box.w - v0;
+#pragma unroll
+    for (int p = 0; p < PPT; ++p) inb[p] = in_u && lo <= p && p <= hi;
+  }
+  blend_entry<CLAMP>(st, col, ea.y, eb.x, eb.z, eb.w, ecb, amin, amax, tmin,
+                     inb, base + j, gj);
+}
+
+template <int PPT, int MODE>
+__device__ __forceinline__ bool any_alive(const PixState<PPT, MODE>& st) {
+  bool any = false;
+#pragma unroll
+  for (int p = 0; p < PPT; ++p) any |= st.T[p] > 0.f;
+  return __builtin_amdgcn_ballot_w64(any) != 0;
+}
+
+// The staged batch front to back for one thread's strip: the set bits of
+// the wave's eval mask, in order; the wave leaves the batch once all its
+// pixels stopped (checked every eight evaluated entries).
+template <bool CLAMP, int TILE, int BATCH, int NT, int MODE>
 __device__ __forceinline__ void walk_batch(
     PixState<PixLayout<TILE, NT>::PPT, MODE>& st, const Entry* ent,
-    const int* wbits, const uint32_t* egid, int cnt, int base, int wave,
-    int u, int v0, float uf, float amin, float amax, float tmin,
-    unsigned& n_exam, unsigned& n_inbox) {
-  constexpr bool COUNT = MODE == kCount;
-  constexpr bool DOM = MODE == kDominant;
+    const WaveMasks<BATCH, NT>& masks, const uint32_t* egid, int cnt,
+    int base, int wave, int u, int v0, float uf, float amin, float amax,
+    float tmin) {
+  const int nw = (cnt + 31) >> 5;
+  int seen = 0;
+  for (int k = 0; k < nw; ++k) {
+    uint32_t e = __builtin_amdgcn_readfirstlane(masks.eval[wave][k]);
+    const uint32_t f = __builtin_amdgcn_readfirstlane(masks.fast[wave][k]);
+    while (e) {
+      const int b = __builtin_ctz(e);
+      e &= e - 1;
+      if ((seen++ & 7) == 0 && !any_alive(st)) return;
+      walk_entry<CLAMP, TILE, NT, MODE>(st, ent, egid, 32 * k + b,
+                                        (f >> b) & 1, base, u, v0, uf, amin,
+                                        amax, tmin);
+    }
+  }
+}
+
+// The counting variant walks every staged entry, adding the examined and
+// in-box pairs of the pixels still compositing, and blends the evaluated
+// ones as walk_batch does.
+template <bool CLAMP, int TILE, int BATCH, int NT, int MODE>
+__device__ __forceinline__ void count_batch(
+    PixState<PixLayout<TILE, NT>::PPT, MODE>& st, const Entry* ent,
+    const WaveMasks<BATCH, NT>& masks, const uint32_t* egid, int cnt,
+    int base, int wave, int u, int v0, float uf, float amin, float amax,
+    float tmin, unsigned& n_exam, unsigned& n_inbox) {
   constexpr int PPT = PixLayout<TILE, NT>::PPT;
   for (int j = 0; j < cnt; ++j) {
-    if ((j & 7) == 0) {
-      bool any = false;
-#pragma unroll
-      for (int p = 0; p < PPT; ++p) any |= st.T[p] > 0.f;
-      if (!__any(any)) break;
-    }
-    const int wb = __builtin_amdgcn_readfirstlane(wbits[j]) >> (2 * wave);
+    if ((j & 7) == 0 && !any_alive(st)) break;
+    const uint32_t e = __builtin_amdgcn_readfirstlane(masks.eval[wave][j >> 5]);
+    const uint32_t f = __builtin_amdgcn_readfirstlane(masks.fast[wave][j >> 5]);
+    const bool evaluate = (e >> (j & 31)) & 1;
     const int4 box = ent[j].box;
-    if (COUNT) {
-      const bool evaluate = wb & 1;
 #pragma unroll
-      for (int p = 0; p < PPT; ++p) {
-        if (!(st.T[p] > 0.f)) continue;
-        ++n_exam;
-        if (evaluate && u >= box.x && u <= box.y && v0 + p >= box.z &&
-            v0 + p <= box.w) {
-          ++n_inbox;
-          ++st.ib[p];
-        }
+    for (int p = 0; p < PPT; ++p) {
+      if (!(st.T[p] > 0.f)) continue;
+      ++n_exam;
+      if (evaluate && u >= box.x && u <= box.y && v0 + p >= box.z &&
+          v0 + p <= box.w) {
+        ++n_inbox;
+        ++st.ib[p];
       }
     }
-    if (!(wb & 1)) continue;
-    const float4 ea = ent[j].a;
-    const float4 eb = ent[j].b;
-    const float ecb = ent[j].c.x;
-    const Column col = column(ea, uf);
-    const int idx = base + j;
-    const int32_t gj = DOM ? (int32_t)egid[j] : 0;
-    // Only the box masks differ between the fast and the general path,
-    // chosen in scalar registers, so the pixels' running state is updated
-    // by one common body.
-    bool inb[PPT];
-    if (wb & 2) {
-#pragma unroll
-      for (int p = 0; p < PPT; ++p) inb[p] = true;
-    } else {
-      const bool in_u = u >= box.x && u <= box.y;
-      const int lo = box.z - v0, hi = box.w - v0;
-#pragma unroll
-      for (int p = 0; p < PPT; ++p) inb[p] = in_u && lo <= p && p <= hi;
-    }
-    blend_entry<CLAMP>(st, col, ea.y, eb.x, eb.y, eb.z, eb.w, ecb, amin,
-                       amax, tmin, inb, idx, gj);
+    if (!evaluate) continue;
+    walk_entry<CLAMP, TILE, NT, MODE>(st, ent, egid, j, (f >> (j & 31)) & 1,
+                                      base, u, v0, uf, amin, amax, tmin);
   }
 }
 
@@ -175,7 +212,8 @@ __global__ __launch_bounds__(NT) void k_render_fwd(FwdArgs a) {
   const int v0 = ty * TILE + cv0;
   // The wave index, uniform over the wave, in a scalar register.
   const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
-  __shared__ int wbits[BATCH];   // per staged entry: wave_bits
+  const int lane = tid & 63;
+  __shared__ WaveMasks<BATCH, NT> masks;
   __shared__ uint32_t egid[DOM ? BATCH : 1];   // Gaussian index per entry
   const float uf = pinned((float)u);
   const float amax = r.alpha_max;
@@ -204,25 +242,37 @@ __global__ __launch_bounds__(NT) void k_render_fwd(FwdArgs a) {
     if (__syncthreads_or(alive) == 0) break;
     const int cnt = (int)min((long long)BATCH, e - b0);
     int clampable = 0;
-    for (int i = tid; i < cnt; i += NT) {
-      const uint32_t g = r.vals[b0 + i];
-      const Record R = rv[g];
-      const int4 box = unpack_box(rbv[g]);
-      stage(ent[i], R, box);
-      wbits[i] = wave_bits<TILE, NT>(R, box, tx * TILE, ty * TILE, r.W, r.H,
-                                     amin, amax, r.ellipse_test);
-      clampable |= R.q1.y > amax;
-      if (DOM) egid[i] = g;
+#pragma unroll
+    for (int i0 = 0; i0 < BATCH; i0 += NT) {
+      const int i = i0 + tid;
+      int bits = 0;
+      if (i < cnt) {
+        const uint32_t g = r.vals[b0 + i];
+        const Record R = rv[g];
+        const int4 box = unpack_box(rbv[g]);
+        stage(ent[i], R, box, r.lop[g]);
+        bits = wave_bits<TILE, NT>(R, box, tx * TILE, ty * TILE, r.W, r.H,
+                                   amin, amax, r.ellipse_test);
+        clampable |= R.q1.y > amax;
+        if (DOM) egid[i] = g;
+      }
+      publish_masks(masks, i0, bits, wave, lane);
     }
     const int base = (int)(b0 - s) + 1;
-    if (__syncthreads_or(clampable))
-      walk_batch<true, TILE, NT, MODE>(st, ent, wbits, egid, cnt, base, wave, u,
-                                       v0, uf, amin, amax, tmin, n_exam,
-                                       n_inbox);
-    else
-      walk_batch<false, TILE, NT, MODE>(st, ent, wbits, egid, cnt, base, wave,
-                                        u, v0, uf, amin, amax, tmin, n_exam,
-                                        n_inbox);
+    if (COUNT) {
+      if (__syncthreads_or(clampable))
+        count_batch<true, TILE>(st, ent, masks, egid, cnt, base, wave, u, v0,
+                                uf, amin, amax, tmin, n_exam, n_inbox);
+      else
+        count_batch<false, TILE>(st, ent, masks, egid, cnt, base, wave, u, v0,
+                                 uf, amin, amax, tmin, n_exam, n_inbox);
+    } else if (__syncthreads_or(clampable)) {
+      walk_batch<true, TILE>(st, ent, masks, egid, cnt, base, wave, u, v0, uf,
+                             amin, amax, tmin);
+    } else {
+      walk_batch<false, TILE>(st, ent, masks, egid, cnt, base, wave, u, v0,
+                              uf, amin, amax, tmin);
+    }
   }
   if (COUNT) {
     unsigned long long c[4] = {n_exam, n_inbox, st.n_contrib, 0};
@@ -269,6 +319,8 @@ struct FwdLauncher {
 RasterArgs make_raster_args(gs_workspace* ws, const gs_settings* s) {
   RasterArgs r;
   r.rec = ws->records; r.rbox = ws->rbox;
+  r.lop = (const float*)(ws->shape + 6 * (size_t)ws->geo.capacity) +
+          ws->geo.capacity;
   r.ellipse_test = (s->flags & GS_FLAG_FULL_BOX) ? 0 : 1;
   r.vals = ws->vals_sorted; r.ranges = ws->ranges; r.order = ws->tile_order;
   r.key_cap = ws->geo.key_capacity; r.cap = ws->geo.capacity;

@@ -268,7 +268,7 @@ def test_admit_extent_closed_form_and_containment():
         d = 0
         while True:
             nd = d + 1
-            ea = 2.0 ** -24 * (4.0 * nd * nd / s2 + 4.0)
+            ea = 2.0 ** -24 * (4.0 * nd * nd / s2 + 4.0 + 3.0 * abs(math.log(o)))
             if o * math.exp(-0.5 * nd * nd / s2) < oracle.ALPHA_MIN * (1 - max(1e-5, ea)):
                 break
             d = nd
