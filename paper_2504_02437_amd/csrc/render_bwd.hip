@@ -205,51 +205,72 @@ __device__ __forceinline__ EntrySums entry_bwd(BwdPix<PPT>& px,
   return r;
 }
 
-// The entries [0, jn) of the staged batch, back to front, for one wave.
+// Staged entry j for one wave; fast: the wave's fast-path bit and the entry
+// lies before every pixel's n_last.
+template <bool CLAMP, bool BG, int TILE, int NT>
+__device__ __forceinline__ void walk_entry(
+    BwdPix<PixLayout<TILE, NT>::PPT>& px, const Entry* ent, float (*acc)[9],
+    int j, int pos, bool fast, int u, int v0, float uf, float amin,
+    float amax, int lane) {
+  constexpr int PPT = PixLayout<TILE, NT>::PPT;
+  const float4 ea = ent[j].a;
+  const float4 eb = ent[j].b;
+  const float ecb = ent[j].c.x;
+  const Column col = column(ea, eb.y, uf);
+  // Only the box / position masks differ between the fast and the general
+  // path, chosen in scalar registers, so the pixels' running state is
+  // updated by one common body.
+  bool inb[PPT];
+  if (fast) {
+#pragma unroll
+    for (int p = 0; p < PPT; ++p) inb[p] = true;
+  } else {
+    const int4 box = ent[j].box;
+    const bool in_u = u >= box.x && u <= box.y;
+    const int rlo = box.z - v0, rhi = box.w - v0;
+#pragma unroll
+    for (int p = 0; p < PPT; ++p)
+      inb[p] = in_u && rlo <= p && p <= rhi && pos < px.last[p];
+  }
+  const EntrySums es = entry_bwd<CLAMP, BG>(px, col, ea.y, eb.x, eb.z, eb.w,
+                                            ecb, amin, amax, inb);
+  if (__builtin_amdgcn_ballot_w64(es.hit) != 0) {
+    // Wave totals of eight of the nine per-lane sums, added into the
+    // entry's LDS slot by lanes 0, 8, ..., 56 (distinct addresses), and row
+    // totals of the ninth by lane 0 of each row; the other waves of the
+    // tile meet in the LDS adds.
+    const float dx = col.dx, dxS0 = dx * es.S0;
+    const float q[8] = {es.S0, dxS0, dx * dxS0, es.S1,
+                        dx * es.S1, es.S2, es.d_r, es.d_g};
+    const float x = wave_sum8(q);
+    const float z = row_sum(es.d_b);
+    float* ac = acc[j];
+    if ((lane & 7) == 0) atomicAdd(&ac[lane >> 3], x);
+    if ((lane & 15) == 0) atomicAdd(&ac[8], z);
+  }
+}
+
+// The entries [0, jn) of the staged batch, back to front, for one wave: the
+// set bits of its eval mask below jn, highest first.
 template <bool CLAMP, bool BG, int TILE, int BATCH, int NT>
 __device__ __forceinline__ void walk_batch(
-    BwdPix<PixLayout<TILE, NT>::PPT>& px, const Entry* ent, const int* wbits,
-    float (*acc)[9], int jn, int lo, int wave, int wfirst, int u, int v0,
-    float uf, float amin, float amax, int lane) {
-  constexpr int PPT = PixLayout<TILE, NT>::PPT;
-  for (int j = jn - 1; j >= 0; --j) {
-    const int pos = lo + j;
-    const int wb = __builtin_amdgcn_readfirstlane(wbits[j]) >> (2 * wave);
-    if (!(wb & 1)) continue;
-    const float4 ea = ent[j].a;
-    const float4 eb = ent[j].b;
-    const float4 ec = ent[j].c;
-    const Column col = column(ea, eb.y, uf);
-    // Only the box / position masks differ between the fast and the general
-    // path, chosen in scalar registers, so the pixels' running state is
-    // updated by one common body.
-    bool inb[PPT];
-    if ((wb & 2) && pos < wfirst) {
-#pragma unroll
-      for (int p = 0; p < PPT; ++p) inb[p] = true;
-    } else {
-      const int4 box = ent[j].box;
-      const bool in_u = u >= box.x && u <= box.y;
-      const int rlo = box.z - v0, rhi = box.w - v0;
-#pragma unroll
-      for (int p = 0; p < PPT; ++p)
-        inb[p] = in_u && rlo <= p && p <= rhi && pos < px.last[p];
-    }
-    const EntrySums es = entry_bwd<CLAMP, BG>(px, col, ea.y, eb.x, eb.z, eb.w,
-                                              ec.x, amin, amax, inb);
-    if (__builtin_amdgcn_ballot_w64(es.hit) != 0) {
-      // Wave totals of eight of the nine per-lane sums, added into the
-      // entry's LDS slot by lanes 0, 8, ..., 56 (distinct addresses), and
-      // row totals of the ninth by lane 0 of each row; the other waves of
-      // the tile meet in the LDS adds.
-      const float dx = col.dx, dxS0 = dx * es.S0;
-      const float q[8] = {es.S0, dxS0, dx * dxS0, es.S1,
-                          dx * es.S1, es.S2, es.d_r, es.d_g};
-      const float x = wave_sum8(q);
-      const float z = row_sum(es.d_b);
-      float* ac = acc[j];
-      if ((lane & 7) == 0) atomicAdd(&ac[lane >> 3], x);
-      if ((lane & 15) == 0) atomicAdd(&ac[8], z);
+    BwdPix<PixLayout<TILE, NT>::PPT>& px, const Entry* ent,
+    const WaveMasks<BATCH, NT>& masks, float (*acc)[9], int jn, int lo,
+    int wave, int wfirst, int u, int v0, float uf, float amin, float amax,
+    int lane) {
+  for (int k = (jn - 1) >> 5; k >= 0; --k) {
+    uint32_t e = __builtin_amdgcn_readfirstlane(masks.eval[wave][k]);
+    const uint32_t f = __builtin_amdgcn_readfirstlane(masks.fast[wave][k]);
+    const int top = jn - 32 * k;   // entries of this word below jn
+    if (top < 32) e &= (1u << top) - 1u;
+    while (e) {
+      const int b = 31 - __builtin_clz(e);
+      e &= ~(1u << b);
+      const int j = 32 * k + b;
+      const int pos = lo + j;
+      walk_entry<CLAMP, BG, TILE, NT>(px, ent, acc, j, pos,
+                                      ((f >> b) & 1) && pos < wfirst, u, v0,
+                                      uf, amin, amax, lane);
     }
   }
 }
@@ -258,8 +279,9 @@ __device__ __forceinline__ void walk_batch(
 // its pixels for each entry and the admit decision selects what is
 // accumulated.  A wave starts its backward walk at the largest n_last of its
 // own pixels, skips entries no pixel of its footprint can admit and takes
-// the fast path (wave_bits, and the entry before every pixel's n_last) when
-// it can; the choice is uniform over the wave.
+// the fast path (its fast mask bit, and the entry before every pixel's
+// n_last) when it can; the choice is uniform over the wave, made in scalar
+// registers.
 template <int TILE, int BATCH, int NT, bool BG>
 __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(BG ? 1 : 5))) void k_render_bwd(BwdArgs a) {
   using Lay = PixLayout<TILE, NT>;
@@ -286,7 +308,7 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(BG ? 1 : 5))
   const int u = tx * TILE + cu;
   const int v0 = ty * TILE + cv0;
   const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
-  __shared__ int wbits[BATCH];   // per staged entry: wave_bits
+  __shared__ WaveMasks<BATCH, NT> masks;
   const float uf = pinned((float)u);
   const float amax = r.alpha_max, amin = r.alpha_min;
   BwdPix<PPT> px;
@@ -369,25 +391,31 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(BG ? 1 : 5))
     const int cnt = hi - lo;
     __syncthreads();   // the previous batch is flushed
     int clampable = 0;
-    for (int i = tid; i < cnt; i += NT) {
-      const uint32_t g = r.vals[s + lo + i];
-      gid[i] = g;
-      const Record R = rv[g];
-      eop[i] = R.q1.y;
-      const int4 box = unpack_box(rbv[g]);
-      stage(ent[i], R, box, r.lop[g]);
-      wbits[i] = wave_bits<TILE, NT>(R, box, tx * TILE, ty * TILE, r.W, r.H,
-                                     amin, amax, r.ellipse_test);
-      clampable |= R.q1.y > amax;
+#pragma unroll
+    for (int i0 = 0; i0 < BATCH; i0 += NT) {
+      const int i = i0 + tid;
+      int bits = 0;
+      if (i < cnt) {
+        const uint32_t g = r.vals[s + lo + i];
+        gid[i] = g;
+        const Record R = rv[g];
+        eop[i] = R.q1.y;
+        const int4 box = unpack_box(rbv[g]);
+        stage(ent[i], R, box, r.lop[g]);
+        bits = wave_bits<TILE, NT>(R, box, tx * TILE, ty * TILE, r.W, r.H,
+                                   amin, amax, r.ellipse_test);
+        clampable |= R.q1.y > amax;
+      }
+      publish_masks(masks, i0, bits, wave, lane);
     }
     for (int i = tid; i < cnt * 9; i += NT) (&acc[0][0])[i] = 0.f;
     const int jn = min(cnt, wlast - lo);
     if (__syncthreads_or(clampable)) {
-      walk_batch<true, BG, TILE, BATCH, NT>(px, ent, wbits, acc, jn, lo, wave,
+      walk_batch<true, BG, TILE, BATCH, NT>(px, ent, masks, acc, jn, lo, wave,
                                             wfirst, u, v0, uf, amin, amax,
                                             lane);
     } else {
-      walk_batch<false, BG, TILE, BATCH, NT>(px, ent, wbits, acc, jn, lo, wave,
+      walk_batch<false, BG, TILE, BATCH, NT>(px, ent, masks, acc, jn, lo, wave,
                                              wfirst, u, v0, uf, amin, amax,
                                              lane);
     }
