@@ -74,7 +74,8 @@ def measured_traffic(kernel):
     try:
         kv = dict(l.split(": ", 1) for l in open(TRAFFIC_FILE).read().splitlines()
                   if l and not l.startswith("#") and ": " in l)
-        if not kv["traffic_kernel"].startswith(kernel + ">"):
+        name = kv["traffic_kernel"]
+        if not (name.startswith(kernel + ">") or name.startswith(kernel + ",")):
             return None
         h = hashlib.sha256()
         for src in kv["traffic_sources"].split():
