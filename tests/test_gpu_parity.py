@@ -276,13 +276,17 @@ def test_long_tile_lists_use_the_global_sort_path():
 
 def _one_tile_scene(n, seed, ties):
     """n small opaque Gaussians whose boxes all lie inside the first 16x16
-    tile of a 32x32 image, so that tile's list has exactly n keys; with
-    `ties` the depths take only 7 values (many equal-depth keys)."""
+    tile of a 32x32 image, so that tile's list has exactly n keys.  ties:
+    "none" (distinct depths), "few" (depths take only 7 values: runs of
+    equal depth far longer than 32 keys) or "pairs" (n / 2 values: runs of a
+    few keys)."""
     rng = np.random.default_rng([77, n, seed])
     cam = synth.identity_camera(30.0, 30.0, 32, 32)
     z = rng.uniform(1.0, 3.0, n)
-    if ties:
+    if ties == "few":
         z = 1.0 + 0.25 * rng.integers(0, 7, n)
+    elif ties == "pairs":
+        z = 1.0 + 1e-3 * rng.integers(0, max(1, n // 2), n)
     u = rng.uniform(4.0, 11.0, n)
     v = rng.uniform(4.0, 11.0, n)
     mean = np.stack([(u - cam.cx) * z / cam.fx, (v - cam.cy) * z / cam.fy, z])
@@ -301,14 +305,18 @@ def _one_tile_scene(n, seed, ties):
 def test_sort_every_segment_size_class(n):
     """Segments of every size class of the in-register sort (one lane per
     key up to 64, 2-16 keys per lane in one wave up to 1024, two and four
-    waves up to 4096), with distinct and with tied depths: keys, values and
-    ranges bit-exact."""
-    for ties in (False, True):
+    waves up to 4096), with distinct depths, with runs of a few equal depths
+    and with only seven depths (long runs): keys, values and ranges
+    bit-exact (equal depths in index order)."""
+    for ties in ("none", "pairs", "few"):
         w = _one_tile_scene(n, 0, ties)
         print("case sort segment", n, ties, flush=True)
         p64, proj, bins, fwd = oracle_forward(w, 16)
         r = bins["ranges"]
         assert r[0, 1] - r[0, 0] == n and (r[1:, 1] == r[1:, 0]).all()
+        if ties == "pairs" and n >= 64:
+            d = bins["keys"][:n] & np.uint64(0xffffffff)
+            assert (d[1:] == d[:-1]).sum() > n // 8   # many short runs
         params, rast = gpu_forward(w, 16, 256)
         check_sort(rast, bins)
 
