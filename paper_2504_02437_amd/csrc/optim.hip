@@ -305,7 +305,14 @@ __global__ __launch_bounds__(kInsThreads) void k_insert(InsertArgs a) {
 // Distance test of Eq. 7: the squared distance from each candidate's
 // back-projected point to the nearest live mean, as the FP64 bit pattern
 // (non-negative doubles order like their bits) min-combined over blocks that
-// each scan a slice of the means.
+// each scan a slice of the means.  A block stages its slice in LDS (FP64)
+// and each thread holds kNearPer candidates (threads tid, tid + 256, ...),
+// so one LDS broadcast read of a mean serves kNearPer distances.  The
+// distance is formed exactly as before in the same order, so the minimum
+// does not depend on the partition.
+constexpr int kNearPer = 4;      // candidates per thread
+constexpr int kNearSlice = 256;  // means per block
+
 struct NearestArgs {
   const float* mean;   // [3][cap]
   const int32_t* n_dev;
@@ -313,36 +320,64 @@ struct NearestArgs {
   const gs_camera* cam;
   int W, H;
   const float* pts;
-  int n_pts, centre_only, chunk;
+  int n_pts, centre_only;
   unsigned long long* d2bits;
 };
 
 __global__ __launch_bounds__(256) void k_nearest(NearestArgs a) {
 #pragma clang fp contract(off)
+  __shared__ double sm[3][kNearSlice];
   const int per = a.centre_only ? 1 : 9;
-  const int c = blockIdx.x * 256 + threadIdx.x;
-  if (c >= a.n_pts * per) return;
-  const int patch = c / per;
-  const int pix = a.centre_only ? 4 : c - patch * per;
-  const int u = (int)a.pts[3 * patch] + pix % 3 - 1;
-  const int v = (int)a.pts[3 * patch + 1] + pix / 3 - 1;
-  const float d = a.pts[3 * patch + 2];
-  if (!(u >= 0 && u < a.W && v >= 0 && v < a.H && d > 0.f)) return;
-  const gs_camera cam = *a.cam;
-  double X[3];
-  back_project(cam, u, v, (double)d, X);
+  const int C = a.n_pts * per;
   const int n = min(*a.n_dev, a.cap);
-  const int g0 = blockIdx.y * a.chunk, g1 = min(n, g0 + a.chunk);
-  if (g0 >= g1) return;
-  double best = INFINITY;
-  for (int g = g0; g < g1; ++g) {
-    const double e0 = X[0] - (double)a.mean[g];
-    const double e1 = X[1] - (double)a.mean[a.cap + g];
-    const double e2 = X[2] - (double)a.mean[2 * a.cap + g];
-    const double d2 = (e0 * e0 + e1 * e1) + e2 * e2;
-    best = d2 < best ? d2 : best;
+  const int g0 = blockIdx.y * kNearSlice;
+  if (g0 >= n) return;   // uniform over the block
+  const int cnt = min(kNearSlice, n - g0);
+  const int tid = threadIdx.x;
+  for (int i = tid; i < cnt; i += 256) {
+    sm[0][i] = (double)a.mean[g0 + i];
+    sm[1][i] = (double)a.mean[a.cap + g0 + i];
+    sm[2][i] = (double)a.mean[2 * a.cap + g0 + i];
   }
-  atomicMin(&a.d2bits[c], (unsigned long long)__double_as_longlong(best));
+  const gs_camera cam = *a.cam;
+  double X[kNearPer][3];
+  bool live[kNearPer];
+  int cid[kNearPer];
+#pragma unroll
+  for (int q = 0; q < kNearPer; ++q) {
+    const int c = (blockIdx.x * kNearPer + q) * 256 + tid;
+    cid[q] = c;
+    live[q] = false;
+    X[q][0] = X[q][1] = X[q][2] = 0.0;
+    if (c >= C) continue;
+    const int patch = c / per;
+    const int pix = a.centre_only ? 4 : c - patch * per;
+    const int u = (int)a.pts[3 * patch] + pix % 3 - 1;
+    const int v = (int)a.pts[3 * patch + 1] + pix / 3 - 1;
+    const float d = a.pts[3 * patch + 2];
+    if (!(u >= 0 && u < a.W && v >= 0 && v < a.H && d > 0.f)) continue;
+    back_project(cam, u, v, (double)d, X[q]);
+    live[q] = true;
+  }
+  __syncthreads();
+  double best[kNearPer];
+#pragma unroll
+  for (int q = 0; q < kNearPer; ++q) best[q] = INFINITY;
+  for (int i = 0; i < cnt; ++i) {
+    const double mx = sm[0][i], my = sm[1][i], mz = sm[2][i];
+#pragma unroll
+    for (int q = 0; q < kNearPer; ++q) {
+      const double e0 = X[q][0] - mx;
+      const double e1 = X[q][1] - my;
+      const double e2 = X[q][2] - mz;
+      const double d2 = (e0 * e0 + e1 * e1) + e2 * e2;
+      best[q] = fmin(best[q], d2);
+    }
+  }
+#pragma unroll
+  for (int q = 0; q < kNearPer; ++q)
+    if (live[q])
+      atomicMin(&a.d2bits[cid[q]], (unsigned long long)__double_as_longlong(best[q]));
 }
 
 void rows_of(const gs_params* p, float** rows) {
@@ -461,11 +496,10 @@ hipError_t launch_insert_distance(gs_params* p, gs_params* m, gs_params* v,
     na.mean = p->mean; na.n_dev = p->n_dev; na.cap = p->capacity; na.cam = cam;
     na.W = W; na.H = H; na.pts = pts; na.n_pts = n_pts;
     na.centre_only = centre_only; na.d2bits = d2bits;
-    const int bc = (C + 255) / 256;
-    // Slices of the means so that about 1024 blocks run.
-    const int slices = max(1, min((p->capacity + 1023) / 1024, 1024 / bc));
-    na.chunk = max(1, (p->capacity + slices - 1) / slices);
-    hipLaunchKernelGGL(k_nearest, dim3(bc, slices), dim3(256), 0, st, na);
+    const int bc = (C + 256 * kNearPer - 1) / (256 * kNearPer);
+    const int slices = (p->capacity + kNearSlice - 1) / kNearSlice;
+    if (slices > 0)
+      hipLaunchKernelGGL(k_nearest, dim3(bc, slices), dim3(256), 0, st, na);
     e = hipGetLastError();
     if (e != hipSuccess) return e;
   }
