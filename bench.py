@@ -65,26 +65,30 @@ TRAFFIC_FILE = os.path.join(ROOT, "profiles",
                             "render_window10-1200x680-300k_tile32_counters.txt")
 
 
-def measured_traffic(kernel):
-    """HBM bytes per dispatch of `kernel` from the committed rocprofv3
-    counter summary (FETCH_SIZE and WRITE_SIZE scaled by a known-size copy),
-    or None when the summary is for another kernel or the kernel's sources
-    changed since the counters were taken."""
+def measured_counters(kernel):
+    """From the committed rocprofv3 counter summary of the dominant kernel:
+    HBM bytes per dispatch (FETCH_SIZE and WRITE_SIZE scaled by a known-size
+    copy), VALU issue (instructions x 4 cycles over the SIMD cycles) and the
+    FP32 arithmetic rate (TFLOP/s); None each when the summary is for
+    another kernel or the kernel's sources changed since it was taken."""
     import hashlib
+    none = {"traffic": None, "valu_issue": None, "fp32_tflops": None}
     try:
         kv = dict(l.split(": ", 1) for l in open(TRAFFIC_FILE).read().splitlines()
                   if l and not l.startswith("#") and ": " in l)
         name = kv["traffic_kernel"]
         if not (name.startswith(kernel + ">") or name.startswith(kernel + ",")):
-            return None
+            return none
         h = hashlib.sha256()
         for src in kv["traffic_sources"].split():
             h.update(open(os.path.join(ROOT, src), "rb").read())
         if h.hexdigest() != kv["traffic_sources_sha256"].strip():
-            return None
-        return int(kv["traffic_bytes"])
+            return none
+        return {"traffic": int(kv["traffic_bytes"]),
+                "valu_issue": float(kv["valu_issue"]),
+                "fp32_tflops": float(kv["fp32_tflops"])}
     except (OSError, KeyError, ValueError):
-        return None
+        return none
 
 
 def log(*a):
@@ -660,6 +664,9 @@ def main():
         dom, ops, t = "render_fwd", fwd_ops, kern["render_fwd"]
     achieved = ops / (t * 1e-3) / 1e12
     peak = PEAK_LANE_OPS / 1e12
+    meas = measured_counters(
+        f"k_render_{dom[7:]}<{S.tile}, {S.lds_batch}, "
+        f"{S.block_threads or (256 if S.tile == 32 else 64)}")
     ms = ms_graph if ms_graph is not None else ms_eager
     iters = 1000.0 / ms
     out = {
@@ -691,9 +698,9 @@ def main():
         "roofline": {"bound": "alu", "kernel": dom, "achieved": achieved,
                      "peak": peak, "unit": "Tlane-op/s",
                      "frac": achieved / peak,
-                     "traffic": measured_traffic(
-                         f"k_render_{dom[7:]}<{S.tile}, {S.lds_batch}, "
-                         f"{S.block_threads or (256 if S.tile == 32 else 64)}"),
+                     "traffic": meas["traffic"],
+                     "valu_issue": meas["valu_issue"],
+                     "fp32_tflops": meas["fp32_tflops"],
                      "ops_per_launch": ops,
                      "render_fwd_frac": fwd_ops / (kern["render_fwd"] * 1e-3) / PEAK_LANE_OPS,
                      "render_bwd_frac": bwd_ops / (kern["render_bwd"] * 1e-3) / PEAK_LANE_OPS},
