@@ -620,6 +620,33 @@ def main():
         dens["insert_alpha_ms"] = float(np.mean(t_a))
         dens["insert_distance_ms"] = float(np.mean(t_d))
         dens["insert_tau"] = INSERT_TAU
+        # Learned initialisation of the same candidates: kNN features, the
+        # network's forward pass (random weights: the cost does not depend on
+        # them) and the accumulated-alpha insertion taking its outputs.
+        C = 96 * 9
+        feats = torch.empty(C, 32, dtype=torch.float32, device=dev)
+        mlp_y = torch.empty(C, 7, dtype=torch.float32, device=dev)
+        from paper_2504_02437_amd.init_mlp import N_PARAMS
+        wts = (torch.randn(N_PARAMS, generator=torch.Generator().manual_seed(5))
+               * 0.1).to(dev)
+        t_k, t_l = [], []
+        for rep in range(6):
+            pd.data.copy_(saved)
+            pd.n_dev.fill_(n0)
+            e0, e1, e2 = (torch.cuda.Event(enable_timing=True) for _ in range(3))
+            e0.record()
+            R.knn_features(pd, cam0, W, H, kf_rgb, pts, False, feats)
+            e1.record()
+            R.mlp_fwd(wts, feats, mlp_y)
+            R.insert_gaussians(pd, None, None, cam0, W, H, kf_rgb, kf_T, pts,
+                               mlp_out=mlp_y)
+            e2.record()
+            torch.cuda.synchronize()
+            if rep:
+                t_k.append(e0.elapsed_time(e1))
+                t_l.append(e0.elapsed_time(e2))
+        dens["knn_features_ms"] = float(np.mean(t_k))
+        dens["insert_learned_ms"] = float(np.mean(t_l))
         del r1, pd, saved, dscr
 
     # The other configurations at the same launch shape.

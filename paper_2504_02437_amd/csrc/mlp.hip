@@ -334,14 +334,128 @@ __device__ __forceinline__ bool nb_less(const Nb& a, const Nb& b) {
   return a.d2 < b.d2 || (a.d2 == b.d2 && (unsigned)a.idx < (unsigned)b.idx);
 }
 
-// One workgroup per candidate: every thread keeps the 8 nearest of its
-// stride of Gaussians (FP64 squared distances), then the lists are merged
-// pairwise in LDS.
-__global__ __launch_bounds__(256) void k_knn_features(KnnArgs a) {
-  __shared__ Nb lists[256][8];
-  const int c = blockIdx.x, tid = threadIdx.x;
-  const int patch = c / a.per;
-  const int pix = a.per == 1 ? 4 : c - patch * a.per;
+// kNN features.  A workgroup serves kKnnCpb candidates with kKnnWpc waves
+// each.  The means pass through LDS a chunk at a time (read once per
+// workgroup), the next chunk's loads in flight while the current one is
+// scanned; every lane keeps the 8 nearest of its share in registers (FP64
+// squared distances in (distance, index) order).  The lists of a wave are
+// then merged with a bitonic network over lane shuffles, and the waves of a
+// candidate through LDS.  Each distance is formed from the same FP32 means
+// in the same order, so the result does not depend on the partition.
+constexpr int kKnnWpc = 4;      // waves per candidate
+constexpr int kKnnCpb = 4;      // candidates per workgroup
+constexpr int kKnnThreads = 64 * kKnnWpc * kKnnCpb;
+constexpr int kKnnChunk = 4096;  // means staged per round
+constexpr int kKnnPer = kKnnChunk / kKnnThreads;   // staged per thread
+constexpr int kKnnIt = kKnnChunk / (64 * kKnnWpc);   // scanned per lane
+static_assert(kKnnChunk % kKnnThreads == 0, "whole staging rounds");
+
+// Sorted insertion as a chain of compare-swaps (no dynamic index, so the
+// list stays in registers).
+__device__ __forceinline__ void nb_insert(Nb (&best)[8], Nb x) {
+#pragma unroll
+  for (int j = 0; j < 8; ++j) {
+    const bool lt = nb_less(x, best[j]);
+    const double td = best[j].d2;
+    const int ti = best[j].idx;
+    best[j].d2 = lt ? x.d2 : td;
+    best[j].idx = lt ? x.idx : ti;
+    x.d2 = lt ? td : x.d2;
+    x.idx = lt ? ti : x.idx;
+  }
+}
+
+__device__ __forceinline__ void nb_cswap(Nb& lo, Nb& hi) {
+  const bool sw = nb_less(hi, lo);
+  const double d = lo.d2;
+  const int i = lo.idx;
+  lo.d2 = sw ? hi.d2 : d;
+  lo.idx = sw ? hi.idx : i;
+  hi.d2 = sw ? d : hi.d2;
+  hi.idx = sw ? i : hi.idx;
+}
+
+// 64-bit value of lane (lane ^ m).
+__device__ __forceinline__ unsigned long long xor_lane64(unsigned long long v, int m) {
+  const int src = ((int)__lane_id() ^ m) << 2;
+  const unsigned lo = __builtin_amdgcn_ds_bpermute(src, (int)v);
+  const unsigned hi = __builtin_amdgcn_ds_bpermute(src, (int)(v >> 32));
+  return ((unsigned long long)hi << 32) | lo;
+}
+
+// The 8 smallest of the union of this lane's sorted list and that of lane
+// (lane ^ m), for m = 1, 2, .. < span: every lane of an aligned group of
+// span lanes ends with the group's 8 smallest, sorted.  (Elementwise minima
+// of one ascending and one descending list are the lower half of their
+// union and form a bitonic sequence; three half-cleaner stages sort it.)
+__device__ __forceinline__ void nb_wave_merge(Nb (&best)[8], int span) {
+  for (int m = 1; m < span; m <<= 1) {
+    Nb o[8];
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
+      o[j].d2 = __longlong_as_double(
+          (long long)xor_lane64((unsigned long long)__double_as_longlong(best[j].d2), m));
+      o[j].idx = __builtin_amdgcn_ds_bpermute(((int)__lane_id() ^ m) << 2, best[j].idx);
+    }
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
+      const bool tb = nb_less(o[7 - j], best[j]);
+      best[j].d2 = tb ? o[7 - j].d2 : best[j].d2;
+      best[j].idx = tb ? o[7 - j].idx : best[j].idx;
+    }
+#pragma unroll
+    for (int s = 4; s >= 1; s >>= 1)
+#pragma unroll
+      for (int j = 0; j < 8; ++j)
+        if ((j & s) == 0) nb_cswap(best[j], best[j + s]);
+  }
+}
+
+// Squared distances compare as their bit patterns (they are >= 0 or NaN,
+// and NaN orders last); a full key for "no entry".
+__device__ __forceinline__ unsigned long long d2_key(double d2) {
+  return (unsigned long long)__double_as_longlong(d2);
+}
+
+// The 8th smallest key over the wave's 64 lanes (bitonic sort across lanes),
+// in every lane.
+__device__ __forceinline__ unsigned long long wave_eighth(unsigned long long v) {
+  const int lane = (int)__lane_id();
+#pragma unroll
+  for (int k = 2; k <= 64; k <<= 1)
+#pragma unroll
+    for (int j = k >> 1; j > 0; j >>= 1) {
+      const unsigned long long o = xor_lane64(v, j);
+      const bool take_min = ((lane & j) == 0) == ((lane & k) == 0);
+      const bool ol = o < v;
+      v = take_min == ol ? o : v;
+    }
+  const unsigned lo = __builtin_amdgcn_readlane((int)v, 7);
+  const unsigned hi = __builtin_amdgcn_readlane((int)(v >> 32), 7);
+  return ((unsigned long long)hi << 32) | lo;
+}
+
+// Chunks after which the waves refresh the shared rejection threshold: 1, 2,
+// 3, 4, 6, 8, 12, 16, .. (it falls roughly as the inverse of the count
+// scanned, so a geometric schedule keeps it close).
+__device__ __forceinline__ bool knn_refresh(int m) {
+  const int q = m % 3 == 0 ? m / 3 : 0;
+  return (m & (m - 1)) == 0 || (q && (q & (q - 1)) == 0);
+}
+
+__global__ __launch_bounds__(kKnnThreads) void k_knn_features(KnnArgs a) {
+  __shared__ float sm[2][3][kKnnChunk];   // double-buffered chunks
+  __shared__ double ld[kKnnCpb][kKnnWpc][8];
+  __shared__ int li[kKnnCpb][kKnnWpc][8];
+  __shared__ unsigned long long tau_sh[2][kKnnCpb][kKnnWpc];
+  const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+  const int cw = wave / kKnnWpc, ww = wave % kKnnWpc;
+  const int C = a.n_pts * a.per;
+  const int c = blockIdx.x * kKnnCpb + cw;
+  const bool live = c < C;   // uniform over the wave
+  const int cc = live ? c : 0;
+  const int patch = cc / a.per;
+  const int pix = a.per == 1 ? 4 : cc - patch * a.per;
   const int u = (int)a.pts[3 * patch] + pix % 3 - 1;
   const int v = (int)a.pts[3 * patch + 1] + pix / 3 - 1;
   const float d = a.pts[3 * patch + 2];
@@ -350,8 +464,10 @@ __global__ __launch_bounds__(256) void k_knn_features(KnnArgs a) {
   const double xc[3] = {((double)u - (double)cam.cx) / (double)cam.fx * z,
                         ((double)v - (double)cam.cy) / (double)cam.fy * z, z};
   double X[3];
+#pragma unroll
   for (int i = 0; i < 3; ++i) {
     double s = 0.0;
+#pragma unroll
     for (int j = 0; j < 3; ++j) s += (double)cam.R[3 * j + i] * (xc[j] - (double)cam.t[j]);
     X[i] = s;
   }
@@ -359,67 +475,139 @@ __global__ __launch_bounds__(256) void k_knn_features(KnnArgs a) {
 #pragma unroll
   for (int j = 0; j < 8; ++j) best[j] = Nb{INFINITY, -1};
   const int n = min(*a.n_dev, a.cap);
-  for (int g = tid; g < n; g += 256) {
-    const double dx = (double)a.mean[g] - X[0];
-    const double dy = (double)a.mean[a.cap + g] - X[1];
-    const double dz = (double)a.mean[2 * a.cap + g] - X[2];
-    Nb cand{dx * dx + dy * dy + dz * dz, g};
-    if (!nb_less(cand, best[7])) continue;
+  float pf[3][kKnnPer];
+  auto fetch = [&](int g0) {
+    if (g0 + kKnnChunk <= n) {
 #pragma unroll
-    for (int j = 7; j >= 0; --j) {
-      if (j > 0 && nb_less(cand, best[j - 1])) {
-        best[j] = best[j - 1];
-      } else {
-        best[j] = cand;
-        break;
+      for (int p = 0; p < kKnnPer; ++p)
+#pragma unroll
+        for (int k = 0; k < 3; ++k)
+          pf[k][p] = a.mean[(size_t)k * a.cap + g0 + tid + p * kKnnThreads];
+    } else {
+#pragma unroll
+      for (int p = 0; p < kKnnPer; ++p) {
+        const int g = g0 + tid + p * kKnnThreads;
+#pragma unroll
+        for (int k = 0; k < 3; ++k) pf[k][p] = g < n ? a.mean[(size_t)k * a.cap + g] : 0.f;
       }
     }
-  }
+  };
+  auto put = [&](int b) {
 #pragma unroll
-  for (int j = 0; j < 8; ++j) lists[tid][j] = best[j];
+    for (int p = 0; p < kKnnPer; ++p)
+#pragma unroll
+      for (int k = 0; k < 3; ++k) sm[b][k][tid + p * kKnnThreads] = pf[k][p];
+  };
+  // Workgroups start at chunks spread over the map and wrap around, so that
+  // they do not all read the same lines at once.  The lists are ordered by
+  // (distance, index), so the scan order does not change them.
+  //
+  // Rejection threshold: when 8 lanes of the candidate each hold an entry at
+  // squared distance <= tau, a Gaussian farther than tau cannot be among the
+  // 8 nearest, so tau = the 8th smallest of the lanes' nearest entries lets
+  // a lane skip it even while its own list is not full.  Equal distances
+  // still reach the insertion, which settles them by index.
+  const int nch = (n + kKnnChunk - 1) / kKnnChunk;
+  int ch = (int)(((long long)blockIdx.x * nch) / gridDim.x);
+  if (nch) {
+    fetch(ch * kKnnChunk);
+    put(0);
+  }
   __syncthreads();
-  for (int step = 1; step < 256; step <<= 1) {
-    if ((tid & (2 * step - 1)) == 0) {
-      Nb m[8];
-      int ia = 0, ib = 0;
-      for (int j = 0; j < 8; ++j) {
-        const Nb& A = lists[tid][ia];
-        const Nb& B = lists[tid + step][ib];
-        if (nb_less(B, A)) { m[j] = B; ++ib; } else { m[j] = A; ++ia; }
-      }
-      for (int j = 0; j < 8; ++j) lists[tid][j] = m[j];
+  const int sub = ww * 64 + lane;
+  unsigned long long tau = ~0ull, thr = d2_key(INFINITY);
+  auto scan = [&](const float* mx, const float* my, const float* mz, int i, int g) {
+    const double dx = (double)mx[i] - X[0];
+    const double dy = (double)my[i] - X[1];
+    const double dz = (double)mz[i] - X[2];
+    const double d2 = dx * dx + dy * dy + dz * dz;
+    if (d2_key(d2) <= thr) {
+      nb_insert(best, Nb{d2, g});
+      thr = min(d2_key(best[7].d2), tau);
     }
+  };
+  for (int t = 0, b = 0; t < nch; ++t, b ^= 1) {
+    // Chunk t is in buffer b; the loads of chunk t + 1 fly meanwhile.
+    const int g0 = ch * kKnnChunk;
+    const int cnt = min(kKnnChunk, n - g0);
+    ch = ch + 1 == nch ? 0 : ch + 1;
+    if (t + 1 < nch) fetch(ch * kKnnChunk);
+    const bool refresh = knn_refresh(t + 1);
+    if (live) {
+      const float* mx = sm[b][0];
+      const float* my = sm[b][1];
+      const float* mz = sm[b][2];
+      if (cnt == kKnnChunk) {
+#pragma unroll
+        for (int u = 0; u < kKnnIt; ++u) scan(mx, my, mz, sub + u * 64 * kKnnWpc, g0 + sub + u * 64 * kKnnWpc);
+      } else {
+        for (int i = sub; i < cnt; i += 64 * kKnnWpc) scan(mx, my, mz, i, g0 + i);
+      }
+      if (refresh) {
+        const unsigned long long tw = wave_eighth(d2_key(best[0].d2));
+        if (lane == 0) tau_sh[b][cw][ww] = tw;
+      }
+    }
+    // Buffer b ^ 1 was released by the barrier that ended chunk t - 1.
+    if (t + 1 < nch) put(b ^ 1);
     __syncthreads();
+    if (live && refresh) {
+#pragma unroll
+      for (int w = 0; w < kKnnWpc; ++w) tau = min(tau, tau_sh[b][cw][w]);
+      thr = min(d2_key(best[7].d2), tau);
+    }
   }
+  nb_wave_merge(best, 64);
+  if (lane == 0) {
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
+      ld[cw][ww][j] = best[j].d2;
+      li[cw][ww][j] = best[j].idx;
+    }
+  }
+  __syncthreads();
+  if (!live || ww != 0) return;
+#pragma unroll
+  for (int j = 0; j < 8; ++j) {
+    best[j].d2 = lane < kKnnWpc ? ld[cw][lane % kKnnWpc][j] : INFINITY;
+    best[j].idx = lane < kKnnWpc ? li[cw][lane % kKnnWpc][j] : -1;
+  }
+  nb_wave_merge(best, 64);
   float* f = a.feats + (size_t)c * 32;
-  if (tid < 27) {
-    const int q = tid / 3, ch = tid % 3;
+  if (lane < 27) {
+    const int q = lane / 3, ch = lane % 3;
     const int uu = u + q % 3 - 1, vv = v + q / 3 - 1;
-    f[tid] = (uu >= 0 && uu < a.W && vv >= 0 && vv < a.H)
-                 ? a.kf_rgb[((size_t)ch * a.H + vv) * a.W + uu] : 0.f;
-  } else if (tid == 27) {
+    f[lane] = (uu >= 0 && uu < a.W && vv >= 0 && vv < a.H)
+                  ? a.kf_rgb[((size_t)ch * a.H + vv) * a.W + uu] : 0.f;
+  } else if (lane == 27) {
     f[27] = d;
-  } else if (tid == 28) {
+  } else if (lane == 28) {
     double sl = 0.0, sw = 0.0, sc[3] = {0, 0, 0};
     int cnt = 0;
+#pragma unroll
     for (int j = 0; j < 8; ++j) {
-      const Nb& b = lists[0][j];
-      if (b.idx < 0) break;
+      const Nb& b = best[j];
+      if (b.idx < 0) continue;
       const double dist = fmax(sqrt(b.d2), 1e-6);
       sl += log(dist);
       const double wgt = 1.0 / dist;
       sw += wgt;
+#pragma unroll
       for (int ch = 0; ch < 3; ++ch) sc[ch] += wgt * (double)a.rgb[(size_t)ch * a.cap + b.idx];
-      if (a.knn_idx) a.knn_idx[(size_t)c * 8 + j] = b.idx;
-      if (a.knn_dist) a.knn_dist[(size_t)c * 8 + j] = (float)sqrt(b.d2);
       ++cnt;
     }
-    for (int j = cnt; j < 8; ++j) {
-      if (a.knn_idx) a.knn_idx[(size_t)c * 8 + j] = -1;
-      if (a.knn_dist) a.knn_dist[(size_t)c * 8 + j] = 0.f;
-    }
     f[28] = cnt ? (float)(sl / cnt) : 0.f;
+#pragma unroll
     for (int ch = 0; ch < 3; ++ch) f[29 + ch] = cnt ? (float)(sc[ch] / sw) : 0.f;
+  }
+  if (lane < 8) {
+    // Lane j writes neighbour j (the lists are identical on every lane).
+    Nb b = best[0];
+#pragma unroll
+    for (int j = 1; j < 8; ++j)
+      if (lane == j) b = best[j];
+    if (a.knn_idx) a.knn_idx[(size_t)c * 8 + lane] = b.idx;
+    if (a.knn_dist) a.knn_dist[(size_t)c * 8 + lane] = b.idx < 0 ? 0.f : (float)sqrt(b.d2);
   }
 }
 
@@ -436,7 +624,9 @@ hipError_t launch_knn_features(const gs_params* p, const gs_camera* cam, int W,
   a.n_pts = n_pts; a.per = centre_only ? 1 : 9; a.feats = feats;
   a.knn_idx = knn_idx; a.knn_dist = knn_dist;
   const int C = n_pts * a.per;
-  if (C > 0) hipLaunchKernelGGL(k_knn_features, dim3(C), dim3(256), 0, st, a);
+  if (C > 0)
+    hipLaunchKernelGGL(k_knn_features, dim3((C + kKnnCpb - 1) / kKnnCpb),
+                       dim3(kKnnThreads), 0, st, a);
   return hipGetLastError();
 }
 

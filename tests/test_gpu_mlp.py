@@ -48,6 +48,60 @@ def test_knn_features_match_oracle(centre_only):
     np.testing.assert_allclose(feats.cpu().numpy(), F, rtol=1e-6, atol=1e-7)
 
 
+def test_knn_features_equal_distances_take_the_lower_index():
+    """The second half of the map repeats the first, so every neighbour
+    comes as a pair at the same distance (indices i and i + 10000, staged in
+    different chunks and read by different lanes): the lower index first."""
+    g, cam, img, pts = _kf(3, K=23)
+    g.mean[:, 10000:] = g.mean[:, :10000]
+    print("case knn ties", flush=True)
+    params = R.ParamBuffer.from_gaussians(g)
+    C = pts.shape[0] * 9
+    feats = torch.empty(C, 32, device="cuda")
+    kidx = torch.empty(C, 8, dtype=torch.int32, device="cuda")
+    kd = torch.empty(C, 8, device="cuda")
+    R.knn_features(params, R.cameras_to_device([cam]), cam.width, cam.height,
+                   _dev(img), _dev(pts), False, feats, kidx, kd)
+    torch.cuda.synchronize()
+    F, P = OM.features(cam, img, pts, g.mean.astype(np.float64),
+                       g.rgb.astype(np.float64), False)
+    idx, _ = OM.knn(g.mean.astype(np.float64), P)
+    assert np.all(idx[:, 1::2] == idx[:, 0::2] + 10000)
+    np.testing.assert_array_equal(kidx.cpu().numpy(), idx)
+    np.testing.assert_allclose(feats.cpu().numpy(), F, rtol=1e-6, atol=1e-7)
+
+
+def test_knn_features_full_map_sampled():
+    """The densification workload's shape: 96 patches x 9 candidates against
+    a 300k-Gaussian map (spare capacity as in mapping), one launch; sampled
+    patches (corners included) against the brute-force oracle."""
+    rng = np.random.default_rng(7)
+    W, H = 1200, 680
+    g = synth.room_gaussians(rng, 300000)
+    cam = synth.room_camera(W, H, 600.0)
+    img = rng.uniform(size=(3, H, W)).astype(np.float32)
+    pts = np.stack([rng.integers(0, W, 96), rng.integers(0, H, 96),
+                    1.0 / rng.uniform(1, 5, 96)], 1).astype(np.float32)
+    pts[0, :2] = (0, 0)
+    pts[95, :2] = (W - 1, H - 1)
+    print("case knn full", flush=True)
+    params = R.ParamBuffer.from_gaussians(g, capacity=450000)
+    feats = torch.empty(96 * 9, 32, device="cuda")
+    kidx = torch.empty(96 * 9, 8, dtype=torch.int32, device="cuda")
+    kd = torch.empty(96 * 9, 8, device="cuda")
+    R.knn_features(params, R.cameras_to_device([cam]), W, H, _dev(img),
+                   _dev(pts), False, feats, kidx, kd)
+    torch.cuda.synchronize()
+    sel = np.array([0, 13, 41, 77, 95])
+    F, P = OM.features(cam, img, pts[sel], g.mean.astype(np.float64),
+                       g.rgb.astype(np.float64), False)
+    idx, dist = OM.knn(g.mean.astype(np.float64), P)
+    rows = (sel[:, None] * 9 + np.arange(9)).ravel()
+    np.testing.assert_array_equal(kidx.cpu().numpy()[rows], idx)
+    np.testing.assert_allclose(kd.cpu().numpy()[rows], dist, rtol=1e-6)
+    np.testing.assert_allclose(feats.cpu().numpy()[rows], F, rtol=1e-6, atol=1e-7)
+
+
 def test_knn_features_small_and_empty_map():
     g, cam, img, pts = _kf(2, K=5)
     params = R.ParamBuffer.from_gaussians(g.subset(np.arange(5)), capacity=64)
