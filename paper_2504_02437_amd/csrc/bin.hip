@@ -309,24 +309,36 @@ template <int NT>
 __device__ void order_tiles(const uint32_t* ranges, uint32_t* order, int n,
                             uint32_t* cnt, uint32_t* wsum, uint32_t* mm);
 
+// Workgroup i of a launch goes to XCD i mod 8.  This renumbering of n
+// workgroups gives every XCD a contiguous run of logical ids (a bijection on
+// [0, n)), so neighbouring logical workgroups share an L2.
+__device__ __forceinline__ int xcd_contiguous(int i, int n) {
+  const int q = n >> 3, r = n & 7, x = i & 7, j = i >> 3;
+  return x < r ? x * (q + 1) + j : r * (q + 1) + (x - r) * q + j;
+}
+
 // The scatter: the chunk's keys claim positions start + offset + (LDS
-// counter) in their tiles' segments.  Grid (1 + chunks, views): workgroup
-// (0, 0) orders the tiles by list length meanwhile (the ranges are final),
+// counter) in their tiles' segments.  Logical grid (1 + chunks) x views,
+// numbered so that consecutive chunks run on one XCD: their keys fill
+// neighbouring slots of every tile's segment (a few keys per chunk and
+// tile), so the partial-line writes combine in that XCD's L2.  Workgroup
+// (0, 0) orders the tiles by list length meanwhile (the ranges are final);
 // the other workgroups of column 0 have nothing to do.
 template <int MAXBINS, int GPT>
 __global__ __launch_bounds__(256) void k_scatter_chunks(ScatterArgs a) {
   static_assert(MAXBINS >= 1024, "the tile order counts in the bins");
   __shared__ uint32_t bins[MAXBINS];
   __shared__ WaveOwners owners[4];
-  if (blockIdx.x == 0) {
-    if (blockIdx.y == 0 && a.order_n > 0)
+  const int lid = xcd_contiguous((int)blockIdx.x, (int)gridDim.x);
+  const int bx = lid % (1 + a.nch), k = lid / (1 + a.nch);
+  if (bx == 0) {
+    if (k == 0 && a.order_n > 0)
       order_tiles<256>(a.ranges, a.order, a.order_n, bins,
                        (uint32_t*)owners[0].incl, (uint32_t*)owners[0].x0);
     return;
   }
-  const int chunk = blockIdx.x - 1;
+  const int chunk = bx - 1;
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
-  const int k = blockIdx.y;
   const int nb = a.Tx * a.Ty;
   const uint32_t* C = a.chunk_counts + ((size_t)k * a.nch + chunk) * nb;
   const uint32_t* start = a.cursor + (size_t)k * nb;
@@ -479,7 +491,7 @@ hipError_t launch_chunked(const ScatterArgs& c, const RangeArgs& ra,
   cs.nch = nch;
   const int n = V * nb;
   cs.order_n = n <= kOrderMaxTiles ? n : 0;   // larger grids keep index order
-  hipLaunchKernelGGL((k_scatter_chunks<MAXBINS, GPT>), dim3(1 + nch, V),
+  hipLaunchKernelGGL((k_scatter_chunks<MAXBINS, GPT>), dim3((1 + nch) * V),
                      dim3(256), 0, st, cs);
   return hipGetLastError();
 }
