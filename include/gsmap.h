@@ -519,7 +519,9 @@ GS_API int gs_mlp_adam(float* weights, const float* dweights, float* adam_m,
  *   gs_render_bwd_l1 against target with lambda_l1;
  *   gs_project_bwd;
  *   with GS_WINDOW_ADAM, gs_adam(lr, beta1, beta2, eps, step_dev) and then
- *   *step_dev += 1, so the next run uses the next bias correction.
+ *   *step_dev += 1, so the next run uses the next bias correction (the
+ *   graph advances the count in its clearing kernel and has the Adam step
+ *   read the count minus one: the same values, one launch fewer).
  * Each call is checked on the host at build time as the call itself checks
  * its arguments (GS_E_INVALID / GS_E_CAPACITY, nothing captured); the graph
  * keeps the pointers, sizes and settings of the build: rebuild after the

@@ -168,6 +168,35 @@ static int check_ws(const gs_workspace* ws) {
 
 static int finish(hipError_t e, const char* what) { return check_hip(e, what); }
 
+int adam_checked(gs_params* params, const gs_params* grad, gs_params* m,
+                 gs_params* v, const float* lr, float beta1, float beta2,
+                 float eps, int32_t step, const int32_t* step_dev,
+                 int step_bias, void* stream) {
+  g_err[0] = 0;
+  if (int rc = validate_params(params, "params")) return rc;
+  if (int rc = validate_params(grad, "grad")) return rc;
+  if (int rc = validate_params(m, "m")) return rc;
+  if (int rc = validate_params(v, "v")) return rc;
+  if (!lr || !params->n_dev) { set_error("lr or n_dev is NULL"); return GS_E_INVALID; }
+  if (!step_dev && step < 1) { set_error("step must be >= 1"); return GS_E_INVALID; }
+  if (grad->capacity != params->capacity || m->capacity != params->capacity ||
+      v->capacity != params->capacity) {
+    set_error("capacities differ");
+    return GS_E_CAPACITY;
+  }
+  if (int rc = same_layout(params, grad, "grad")) return rc;
+  if (int rc = disjoint(params, "params", grad, "grad")) return rc;
+  if (int rc = same_layout(params, m, "m")) return rc;
+  if (int rc = same_layout(params, v, "v")) return rc;
+  const gs_params* all[4] = {params, grad, m, v};
+  const char* names[4] = {"params", "grad", "m", "v"};
+  for (int i = 0; i < 4; ++i)
+    for (int j = i + 1; j < 4; ++j)
+      if (int rc = disjoint(all[i], names[i], all[j], names[j])) return rc;
+  return finish(launch_adam(params, grad, m, v, lr, beta1, beta2, eps, step,
+                            step_dev, (hipStream_t)stream, step_bias), "adam");
+}
+
 }  // namespace gs
 
 using namespace gs;
@@ -528,29 +557,8 @@ int gs_planar_reg(const gs_params* params, float lambda, float floor_,
 int gs_adam(gs_params* params, const gs_params* grad, gs_params* m,
             gs_params* v, const float* lr, float beta1, float beta2,
             float eps, int32_t step, const int32_t* step_dev, void* stream) {
-  g_err[0] = 0;
-  if (int rc = validate_params(params, "params")) return rc;
-  if (int rc = validate_params(grad, "grad")) return rc;
-  if (int rc = validate_params(m, "m")) return rc;
-  if (int rc = validate_params(v, "v")) return rc;
-  if (!lr || !params->n_dev) { set_error("lr or n_dev is NULL"); return GS_E_INVALID; }
-  if (!step_dev && step < 1) { set_error("step must be >= 1"); return GS_E_INVALID; }
-  if (grad->capacity != params->capacity || m->capacity != params->capacity ||
-      v->capacity != params->capacity) {
-    set_error("capacities differ");
-    return GS_E_CAPACITY;
-  }
-  if (int rc = same_layout(params, grad, "grad")) return rc;
-  if (int rc = disjoint(params, "params", grad, "grad")) return rc;
-  if (int rc = same_layout(params, m, "m")) return rc;
-  if (int rc = same_layout(params, v, "v")) return rc;
-  const gs_params* all[4] = {params, grad, m, v};
-  const char* names[4] = {"params", "grad", "m", "v"};
-  for (int i = 0; i < 4; ++i)
-    for (int j = i + 1; j < 4; ++j)
-      if (int rc = disjoint(all[i], names[i], all[j], names[j])) return rc;
-  return finish(launch_adam(params, grad, m, v, lr, beta1, beta2, eps, step,
-                            step_dev, (hipStream_t)stream), "adam");
+  return adam_checked(params, grad, m, v, lr, beta1, beta2, eps, step,
+                      step_dev, 0, stream);
 }
 
 int gs_insert_gaussians(gs_params* params, gs_params* adam_m, gs_params* adam_v,

@@ -167,10 +167,17 @@ hipError_t launch_loss_l1(const float* rgb, const float* target, int V, int H,
                           double* sqerr, hipStream_t st);
 hipError_t launch_planar_reg(const gs_params* p, float lambda, float floor_,
                              gs_params* grad, double* loss, hipStream_t st);
+// step_bias is added to *step_dev (the window graph advances the count
+// before its Adam step).
 hipError_t launch_adam(gs_params* p, const gs_params* g, gs_params* m,
                        gs_params* v, const float* lr, float b1, float b2,
                        float eps, int step, const int32_t* step_dev,
-                       hipStream_t st);
+                       hipStream_t st, int step_bias = 0);
+// gs_adam with its argument checks, the bias passed to launch_adam.
+int adam_checked(gs_params* params, const gs_params* grad, gs_params* m,
+                 gs_params* v, const float* lr, float beta1, float beta2,
+                 float eps, int32_t step, const int32_t* step_dev,
+                 int step_bias, void* stream);
 hipError_t launch_insert(gs_params* p, gs_params* m, gs_params* v,
                          const gs_camera* cam, int W, int H,
                          const float* kf_rgb, const float* kf_T,

@@ -119,6 +119,7 @@ struct AdamArgs {
   const int32_t* n_dev;
   const int32_t* step_dev;
   int cap, step;
+  int step_bias;   // added to *step_dev
   float b1, b2, eps;
 };
 
@@ -133,7 +134,7 @@ __global__ __launch_bounds__(256) void k_adam(AdamArgs a) {
   const int n = min(*a.n_dev, a.cap);
   if (blockIdx.x * 256 * kAdamPer >= n) return;
   if (threadIdx.x == 0) {
-    const int step = a.step_dev ? max(1, *a.step_dev) : a.step;
+    const int step = a.step_dev ? max(1, *a.step_dev + a.step_bias) : a.step;
     corr[0] = (float)(1.0 - pow((double)a.b1, (double)step));
     corr[1] = (float)(1.0 - pow((double)a.b2, (double)step));
   }
@@ -440,7 +441,7 @@ hipError_t launch_planar_reg(const gs_params* p, float lambda, float floor_,
 hipError_t launch_adam(gs_params* p, const gs_params* g, gs_params* m,
                        gs_params* v, const float* lr, float b1, float b2,
                        float eps, int step, const int32_t* step_dev,
-                       hipStream_t st) {
+                       hipStream_t st, int step_bias) {
   AdamArgs a;
   float* tmp[14];
   rows_of(p, a.p);
@@ -455,7 +456,7 @@ hipError_t launch_adam(gs_params* p, const gs_params* g, gs_params* m,
   a.lr_sh = nsh ? lr[5] : 0.f;
   a.n_dev = p->n_dev; a.cap = p->capacity;
   a.b1 = b1; a.b2 = b2; a.eps = eps;
-  a.step = step; a.step_dev = step_dev;
+  a.step = step; a.step_dev = step_dev; a.step_bias = step_bias;
   const int blocks = (p->capacity + 256 * kAdamPer - 1) / (256 * kAdamPer);
   if (blocks <= 0) return hipSuccess;
   hipLaunchKernelGGL(k_adam, dim3(blocks, 14 + nsh), dim3(256), 0, st, a);

@@ -6,9 +6,10 @@
 // projection and binning, the per-tile sort, the forward render, the planar
 // regulariser's gradient, the compositing backward with the L1 term fused
 // in, the projection backward and the Adam step with its device step count
-// advanced.  Clearing uses the library's fill kernels (no memset nodes), so
-// every node of the graph is a kernel.  The graph holds the caller's device
-// pointers; it owns no device memory of its own.
+// advanced.  The clearing is one kernel of its own (no memset nodes), which
+// also advances the step count, so every node of the graph is a kernel.  The
+// graph holds the caller's device pointers; it owns no device memory of its
+// own.
 
 #include <new>
 
@@ -22,40 +23,80 @@ struct gs_window {
 namespace gs {
 namespace {
 
-__global__ void k_add_i32(int32_t* x, int32_t d) {
-  if (threadIdx.x == 0 && blockIdx.x == 0) *x += d;
-}
-
 size_t rows_of(const gs_params* p) {
   return p->sh_degree > 0 ? (size_t)GS_SH_ROWS(p->sh_degree) : 0;
 }
 
-hipError_t zero_rows(const gs_params* g, hipStream_t st) {
+// The iteration's clearing in one launch: up to kClearJobs 32-bit rows set
+// to zero (the gradient rows, the loss and squared-error slots), workgroups
+// dealt to the rows in turn, and the Adam step count advanced by one (its
+// Adam launch reads the count minus one, so a run still uses the count it
+// started with and leaves it advanced).
+constexpr int kClearJobs = 8;
+constexpr int kClearPer = 4;   // elements per thread
+struct ClearArgs {
+  uint32_t* p[kClearJobs];
+  size_t n[kClearJobs];
+  int first[kClearJobs + 1];   // first workgroup of each row
+  int jobs;
+  int32_t* step;               // advanced by one when not NULL
+};
+
+__global__ __launch_bounds__(256) void k_clear_iteration(ClearArgs a) {
+  if (a.step && blockIdx.x == 0 && threadIdx.x == 0) *a.step += 1;
+  int j = 0;
+  while (j + 1 < a.jobs && (int)blockIdx.x >= a.first[j + 1]) ++j;
+  uint32_t* p = a.p[j];
+  const size_t n = a.n[j];
+  const size_t base =
+      (size_t)(blockIdx.x - a.first[j]) * 256 * kClearPer + threadIdx.x;
+#pragma unroll
+  for (int e = 0; e < kClearPer; ++e) {
+    const size_t i = base + (size_t)e * 256;
+    if (i < n) p[i] = 0u;
+  }
+}
+
+hipError_t clear_iteration(const gs_window_desc* d, hipStream_t st) {
+  const gs_params* g = &d->grad;
   const size_t c = (size_t)(g->capacity > 0 ? g->capacity : 0);
+  ClearArgs a;
+  a.jobs = 0;
+  auto add = [&](void* ptr, size_t n) {
+    if (!ptr || n == 0) return;
+    a.p[a.jobs] = (uint32_t*)ptr;
+    a.n[a.jobs] = n;
+    ++a.jobs;
+  };
   float* rows[6] = {g->mean, g->log_scale, g->quat, g->opacity_logit, g->rgb,
                     g->sh};
-  const size_t n[6] = {3, 3, 4, 1, 3, rows_of(g)};
-  for (int i = 0; i < 6; ++i) {
-    if (!rows[i] || n[i] == 0 || c == 0) continue;
-    const hipError_t e = launch_fill_u32(rows[i], 0u, n[i] * c, st);
-    if (e != hipSuccess) return e;
+  const size_t nr[6] = {3, 3, 4, 1, 3, rows_of(g)};
+  for (int i = 0; i < 6; ++i) add(rows[i], nr[i] * c);
+  add(d->loss_dev, 2);
+  if (d->sqerr_dev) add(d->sqerr_dev, 2 * (size_t)d->ws->geo.n_views);
+  a.step = (d->flags & GS_WINDOW_ADAM) ? d->step_dev : nullptr;
+  long long blocks = 0;
+  for (int j = 0; j < a.jobs; ++j) {
+    a.first[j] = (int)blocks;
+    blocks += (long long)((a.n[j] + 256 * kClearPer - 1) / (256 * kClearPer));
+    if (blocks > 0x7fffffff) return hipErrorInvalidConfiguration;
   }
-  return hipSuccess;
+  a.first[a.jobs] = (int)blocks;
+  if (blocks == 0) {   // nothing to clear; the step count still advances
+    if (!a.step) return hipSuccess;
+    a.jobs = 1; a.p[0] = nullptr; a.n[0] = 0; a.first[0] = 0; a.first[1] = 1;
+    blocks = 1;
+  }
+  hipLaunchKernelGGL(k_clear_iteration, dim3((unsigned)blocks), dim3(256), 0,
+                     st, a);
+  return hipGetLastError();
 }
 
 // The iteration, enqueued on st (called while st captures).
 int enqueue_iteration(const gs_window_desc* d, hipStream_t st) {
   gs_params params = d->params, grad = d->grad, m = d->adam_m, v = d->adam_v;
-  int rc = check_hip(zero_rows(&grad, st), "clearing the gradient");
+  int rc = check_hip(clear_iteration(d, st), "clearing the iteration's rows");
   if (rc) return rc;
-  rc = check_hip(launch_fill_u32(d->loss_dev, 0u, 2, st), "clearing the loss");
-  if (rc) return rc;
-  if (d->sqerr_dev) {
-    rc = check_hip(launch_fill_u32(d->sqerr_dev, 0u,
-                                   2 * (size_t)d->ws->geo.n_views, st),
-                   "clearing the squared errors");
-    if (rc) return rc;
-  }
   if ((rc = gs_project_and_bin(d->ws, &params, d->cams, &d->settings, st)))
     return rc;
   if ((rc = gs_sort_tile_keys(d->ws, &d->settings, st))) return rc;
@@ -73,11 +114,9 @@ int enqueue_iteration(const gs_window_desc* d, hipStream_t st) {
     return rc;
   if ((rc = gs_project_bwd(d->ws, &params, d->cams, &grad, st))) return rc;
   if (d->flags & GS_WINDOW_ADAM) {
-    if ((rc = gs_adam(&params, &grad, &m, &v, d->lr, d->beta1, d->beta2,
-                      d->eps, 1, d->step_dev, st)))
-      return rc;
-    hipLaunchKernelGGL(k_add_i32, dim3(1), dim3(64), 0, st, d->step_dev, 1);
-    if ((rc = check_hip(hipGetLastError(), "advancing the step count")))
+    // The clearing launch advanced *step_dev already.
+    if ((rc = adam_checked(&params, &grad, &m, &v, d->lr, d->beta1, d->beta2,
+                           d->eps, 1, d->step_dev, -1, st)))
       return rc;
   }
   return GS_OK;
