@@ -8,14 +8,20 @@
 // which is exactly the order of a stable sort of (tile << 32 | depth bits)
 // keys emitted Gaussian by Gaussian.
 //
+// Segments up to kCap keys sort in registers on 32-bit keys standing for
+// the 64-bit ones (the segment's depth bits quantised to 20 bits, tagged
+// with the key's position; equal quanta are put in order afterwards, see
+// sort_tile), so that a compare-exchange is a min and a max rather than a
+// 64-bit compare and four selects.
+//
 // Sorting network: bitonic, in its all-ascending form, over the segment
 // padded to a power of two P2 with all-ones keys (larger than any real key).
-// Segments up to kCap keys sort in registers: lane l of wave w holds the E
+// In registers, lane l of wave w holds the E
 // consecutive positions (64 w + l) E .. + E - 1 (one wave with E = 1 up to 64
 // keys, else four waves with E = P2 / 256), so a comparator whose positions
 // differ only below bit log2 E stays inside a lane, one that differs below
-// bit log2 64E pairs two lanes of the same wave (DPP, swizzles or a lane
-// permute), and only the others - at most three merge steps per segment - go
+// bit log2 64E pairs two lanes of the same wave (DPP, swizzles, lane
+// permutes or swaps), and only the others - at most three merge steps per segment - go
 // through LDS with barriers.  Padding never moves in the all-ascending form,
 // so waves that hold only padding skip the compare-exchanges.  Longer
 // segments (rare: a tile covered by more than kCap Gaussians) sort in place
@@ -76,9 +82,12 @@ __device__ void bitonic_sort(P a, int L, int tid, int nthr) {
 //   M = 1, 3      DPP quad permutation (one VALU instruction)
 //   M = 2         DPP quad permutation
 //   M = 7, 15     DPP half-row and row mirror
-//   M = 4, 8, 16, 31  swizzle in bit-mask mode (the LDS unit's crossbar, no
+//   M = 8         DPP row rotation by 8 (lane l of a 16-lane row reads l ^ 8)
+//   M = 4, 16, 31 swizzle in bit-mask mode (the LDS unit's crossbar, no
 //                 LDS memory)
 //   M = 32, 63    lane permute.
+// (The compare-exchanges at distance 16 and 32 use swap_halves below
+// instead.)
 template <int M>
 __device__ __forceinline__ int xor_lane32(int v) {
   if constexpr (M == 1) {
@@ -91,7 +100,9 @@ __device__ __forceinline__ int xor_lane32(int v) {
     return __builtin_amdgcn_update_dpp(0, v, 0x141, 0xf, 0xf, true); // row_half_mirror
   } else if constexpr (M == 15) {
     return __builtin_amdgcn_update_dpp(0, v, 0x140, 0xf, 0xf, true); // row_mirror
-  } else if constexpr (M == 4 || M == 8 || M == 16 || M == 31) {
+  } else if constexpr (M == 8) {
+    return __builtin_amdgcn_update_dpp(0, v, 0x128, 0xf, 0xf, true); // row_ror:8
+  } else if constexpr (M == 4 || M == 16 || M == 31) {
     return __builtin_amdgcn_ds_swizzle(v, 0x1f | (M << 10));  // and 31, xor M
   } else {
     static_assert(M == 32 || M == 63, "unsupported lane mask");
@@ -100,14 +111,11 @@ __device__ __forceinline__ int xor_lane32(int v) {
 }
 
 template <int M>
-__device__ __forceinline__ unsigned long long xor_lane(unsigned long long v) {
-  const uint32_t lo = (uint32_t)xor_lane32<M>((int)(uint32_t)v);
-  const uint32_t hi = (uint32_t)xor_lane32<M>((int)(uint32_t)(v >> 32));
-  return ((unsigned long long)hi << 32) | lo;
+__device__ __forceinline__ uint32_t xor_lane(uint32_t v) {
+  return (uint32_t)xor_lane32<M>((int)v);
 }
 
-__device__ __forceinline__ void keep(unsigned long long& x, unsigned long long y,
-                                     bool keep_min) {
+__device__ __forceinline__ void keep(uint32_t& x, uint32_t y, bool keep_min) {
   x = ((y < x) == keep_min) ? y : x;
 }
 
@@ -116,37 +124,38 @@ __device__ __forceinline__ void keep(unsigned long long& x, unsigned long long y
 // its block of k, then p with p ^ j for j = k/4 .. 1; every comparator puts
 // the smaller key at the lower position.  Padding keys (all ones) at the
 // positions >= L therefore never move, so a wave whose positions all lie at
-// or past L has nothing to do but its part of the barriers.
+// or past L has nothing to do but its part of the barriers.  It runs on the
+// 32-bit keys of sort_tile: a compare-exchange within a lane is one min and
+// one max.
 //
 // In-lane stages: mirror step k <= E, or distance j < E.
 template <int E, int K>
-__device__ __forceinline__ void mirror_in_lane(unsigned long long (&x)[E]) {
+__device__ __forceinline__ void mirror_in_lane(uint32_t (&x)[E]) {
 #pragma unroll
   for (int e = 0; e < E; ++e) {
     if (e & (K >> 1)) continue;
     const int h = e ^ (K - 1);
-    const unsigned long long a = x[e], b = x[h];
-    x[e] = b < a ? b : a;
-    x[h] = b < a ? a : b;
+    const uint32_t a = x[e], b = x[h];
+    x[e] = min(a, b);
+    x[h] = max(a, b);
   }
 }
 
 template <int E, int J>
-__device__ __forceinline__ void stage_in_lane(unsigned long long (&x)[E]) {
+__device__ __forceinline__ void stage_in_lane(uint32_t (&x)[E]) {
 #pragma unroll
   for (int e = 0; e < E; ++e) {
     if (e & J) continue;
-    const unsigned long long a = x[e], b = x[e + J];
-    x[e] = b < a ? b : a;
-    x[e + J] = b < a ? a : b;
+    const uint32_t a = x[e], b = x[e + J];
+    x[e] = min(a, b);
+    x[e + J] = max(a, b);
   }
 }
 
 // Mirror step E < k <= 64 E: position (lane, e) pairs with (lane ^ M,
 // E - 1 - e), M = k / E - 1.
 template <int E, int M>
-__device__ __forceinline__ void mirror_across_lanes(unsigned long long (&x)[E],
-                                                    int lane) {
+__device__ __forceinline__ void mirror_across_lanes(uint32_t (&x)[E], int lane) {
   const bool keep_min = (lane & ((M + 1) >> 1)) == 0;
   if constexpr (E == 1) {
     keep(x[0], xor_lane<M>(x[0]), keep_min);
@@ -154,21 +163,51 @@ __device__ __forceinline__ void mirror_across_lanes(unsigned long long (&x)[E],
     // Mirrored pairs (e, E - 1 - e) together: two temporaries live at once.
 #pragma unroll
     for (int e = 0; e < E / 2; ++e) {
-      const unsigned long long ya = xor_lane<M>(x[E - 1 - e]);
-      const unsigned long long yb = xor_lane<M>(x[e]);
+      const uint32_t ya = xor_lane<M>(x[E - 1 - e]);
+      const uint32_t yb = xor_lane<M>(x[e]);
       keep(x[e], ya, keep_min);
       keep(x[E - 1 - e], yb, keep_min);
     }
   }
 }
 
+// Both halves of the pair (l, l ^ M) for M = 16 or 32 without an LDS-unit
+// round trip: v_permlane16_swap / v_permlane32_swap of a value with itself
+// leave, in every lane, its own key in t0 and its partner's in t1 when
+// (l & M) == 0, and the other way round otherwise.
+template <int M>
+__device__ __forceinline__ void swap_halves(uint32_t v, uint32_t& t0,
+                                            uint32_t& t1) {
+  if constexpr (M == 32) {
+    const auto p = __builtin_amdgcn_permlane32_swap(v, v, false, false);
+    t0 = p[0];
+    t1 = p[1];
+  } else {
+    static_assert(M == 16, "row or half-wave exchange only");
+    const auto p = __builtin_amdgcn_permlane16_swap(v, v, false, false);
+    t0 = p[0];
+    t1 = p[1];
+  }
+}
+
 // Distance E <= j < 64 E: lane l pairs with lane l ^ M, M = j / E.
 template <int E, int M>
-__device__ __forceinline__ void stage_across_lanes(unsigned long long (&x)[E],
-                                                   int lane) {
+__device__ __forceinline__ void stage_across_lanes(uint32_t (&x)[E], int lane) {
   const bool keep_min = (lane & M) == 0;
+  if constexpr (M == 16 || M == 32) {
+    // The lower lane of a pair keeps min(t0, t1), the upper max(t0, t1):
+    // with t0 its own key in the lower lane and its partner's in the upper,
+    // both take t1 exactly when (t1 < t0) equals being the lower.
 #pragma unroll
-  for (int e = 0; e < E; ++e) keep(x[e], xor_lane<M>(x[e]), keep_min);
+    for (int e = 0; e < E; ++e) {
+      uint32_t t0, t1;
+      swap_halves<M>(x[e], t0, t1);
+      x[e] = ((t1 < t0) == keep_min) ? t1 : t0;
+    }
+  } else {
+#pragma unroll
+    for (int e = 0; e < E; ++e) keep(x[e], xor_lane<M>(x[e]), keep_min);
+  }
 }
 
 // A stage whose partner lies in another wave (position p ^ m with m >= 64 E),
@@ -179,9 +218,9 @@ __device__ __forceinline__ void stage_across_lanes(unsigned long long (&x)[E],
 // of element e of thread t is element e ^ ex of thread t ^ ml.  half is the
 // bit of p that decides which side keeps the minimum.
 template <int E>
-__device__ __forceinline__ void stage_lds(unsigned long long (&x)[E], int m,
-                                          int half, bool active, bool work,
-                                          unsigned long long* buf) {
+__device__ __forceinline__ void stage_lds(uint32_t (&x)[E], int m, int half,
+                                          bool active, bool work,
+                                          uint32_t* buf) {
   const int tid = threadIdx.x;
   const int ml = m / E, ex = m % E;
   __syncthreads();
@@ -192,7 +231,7 @@ __device__ __forceinline__ void stage_lds(unsigned long long (&x)[E], int m,
   __syncthreads();
   if (work) {
     const bool keep_min = ((tid * E) & half) == 0;
-    const unsigned long long* src = buf + (tid ^ ml);
+    const uint32_t* src = buf + (tid ^ ml);
 #pragma unroll
     for (int e = 0; e < E; ++e) keep(x[e], src[(e ^ ex) * 256], keep_min);
   }
@@ -202,8 +241,8 @@ __device__ __forceinline__ void stage_lds(unsigned long long (&x)[E], int m,
 // waves of the workgroup (all waves reach the barriers of cross-wave stages);
 // positions >= L hold all-ones keys.
 template <int E>
-__device__ void sort_in_registers(unsigned long long (&x)[E], int L, int P2,
-                                  int nw, unsigned long long* buf) {
+__device__ void sort_in_registers(uint32_t (&x)[E], int L, int P2, int nw,
+                                  uint32_t* buf) {
   const int tid = threadIdx.x, lane = tid & 63;
   const bool active = (tid >> 6) < nw;
   const bool work = active && (tid >> 6) * 64 * E < L;
@@ -251,37 +290,114 @@ __device__ void sort_in_registers(unsigned long long (&x)[E], int L, int P2,
   }
 }
 
+// Orders one wave's LDS accesses before and after this point (the one-wave
+// segments have no other wave to wait for).
+__device__ __forceinline__ void wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+}
+
+constexpr int kIdxBits = 12;   // position in a segment of at most 4096 keys
+constexpr int kQBits = 32 - kIdxBits;
+
+// One segment of L <= 4096 keys.  The network sorts 32-bit keys
+//   q << 12 | i,   q = (depth bits - the segment's smallest) >> shift,
+// i the key's position in the unsorted segment, shift the least that fits
+// the segment's depth-bit range in 20 bits.  Integer differences and shifts
+// keep the order of the depth bits (a smaller q means a smaller depth), and
+// i makes every key unique and names its 64-bit key; the all-ones padding
+// stays above every real key (i = 4095 only when L = 4096, with no padding).
+// After the network each run of equal q - in practice almost always a
+// single key - is put in (depth, index) order by ranking its members'
+// 64-bit keys, so the result is exactly the sorted 64-bit segment.
 template <int E>
 __device__ void sort_tile(const SortArgs& a, int t, long long s, int L, int P2,
-                          int nw, unsigned long long* buf) {
-  const int tid = threadIdx.x;
-  const bool active = (tid >> 6) < nw;
+                          int nw, uint32_t* buf, uint32_t* red) {
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const bool active = wave < nw;
   if (nw == 1 && !active) return;   // no cross-wave stage: no barrier
-  unsigned long long x[E];
   const int base = tid * E;
+  uint32_t dhi[E];
+  uint32_t dmin = 0xffffffffu, dmax = 0u;
 #pragma unroll
-  for (int e = 0; e < E; ++e)
-    x[e] = (active && base + e < L) ? a.keys_in[s + base + e] : ~0ull;
+  for (int e = 0; e < E; ++e) {
+    const int p = base + e;
+    dhi[e] = (active && p < L) ? (uint32_t)(a.keys_in[s + p] >> 32) : 0u;
+    if (active && p < L) {
+      dmin = min(dmin, dhi[e]);
+      dmax = max(dmax, dhi[e]);
+    }
+  }
+  for (int off = 32; off > 0; off >>= 1) {
+    dmin = min(dmin, (uint32_t)__shfl_xor((int)dmin, off, 64));
+    dmax = max(dmax, (uint32_t)__shfl_xor((int)dmax, off, 64));
+  }
+  if (nw > 1) {
+    if (lane == 0) {
+      red[2 * wave] = dmin;
+      red[2 * wave + 1] = dmax;
+    }
+    __syncthreads();
+    for (int w = 0; w < nw; ++w) {
+      dmin = min(dmin, red[2 * w]);
+      dmax = max(dmax, red[2 * w + 1]);
+    }
+  }
+  const uint32_t range = dmax - dmin;   // dmax >= dmin for L >= 1
+  const int bits = range ? 32 - __clz((int)range) : 0;
+  const int shift = bits > kQBits ? bits - kQBits : 0;
+  uint32_t x[E];
+#pragma unroll
+  for (int e = 0; e < E; ++e) {
+    const int p = base + e;
+    x[e] = (active && p < L)
+               ? (((dhi[e] - dmin) >> shift) << kIdxBits) | (uint32_t)p
+               : 0xffffffffu;
+  }
   sort_in_registers<E>(x, L, P2, nw, buf);
+  // Publish the sorted 32-bit keys position-major for the run tests.
+  if (nw > 1) __syncthreads(); else wave_sync();
+  if (active) {
+#pragma unroll
+    for (int e = 0; e < E; ++e)
+      if (base + e < L) buf[base + e] = x[e];
+  }
+  if (nw > 1) __syncthreads(); else wave_sync();
   if (!active) return;
 #pragma unroll
   for (int e = 0; e < E; ++e) {
     const int p = base + e;
-    if (p < L) {
-      a.vals_out[s + p] = (uint32_t)x[e];
-      if (a.keys_out)
-        a.keys_out[s + p] = ((unsigned long long)(uint32_t)t << 32) | (x[e] >> 32);
+    if (p >= L) continue;
+    const uint32_t q = x[e] >> kIdxBits;
+    const unsigned long long full =
+        a.keys_in[s + (x[e] & ((1u << kIdxBits) - 1))];
+    int pos = p;
+    const bool left = p > 0 && (buf[p - 1] >> kIdxBits) == q;
+    const bool right = p + 1 < L && (buf[p + 1] >> kIdxBits) == q;
+    if (left || right) {
+      int a0 = p, b0 = p + 1;
+      while (a0 > 0 && (buf[a0 - 1] >> kIdxBits) == q) --a0;
+      while (b0 < L && (buf[b0] >> kIdxBits) == q) ++b0;
+      int r = 0;
+      for (int i = a0; i < b0; ++i)
+        r += a.keys_in[s + (buf[i] & ((1u << kIdxBits) - 1))] < full;
+      pos = a0 + r;
     }
+    a.vals_out[s + pos] = (uint32_t)full;
+    if (a.keys_out)
+      a.keys_out[s + pos] = ((unsigned long long)(uint32_t)t << 32) | (full >> 32);
   }
 }
 
-// At most 96 VGPRs (five waves per SIMD): the 32 KB LDS buffer also allows
-// five workgroups per CU.
+// At most 96 VGPRs (five waves per SIMD); the 16 KB LDS buffer allows more
+// workgroups per CU than the registers do.
 template <int kCap>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(5)))
 void k_sort_tiles(SortArgs a) {
   static_assert(kCap == 4 * 64 * 16, "four waves of 16 keys per lane");
-  __shared__ unsigned long long buf[kCap];
+  static_assert(kCap <= (1 << kIdxBits), "positions fit the key's index bits");
+  __shared__ uint32_t buf[kCap];
+  __shared__ uint32_t red[8];
   const int t = (int)a.order[blockIdx.x];
   const int tid = threadIdx.x;
   const long long s = min((long long)a.ranges[2 * t], a.key_cap);
@@ -294,12 +410,12 @@ void k_sort_tiles(SortArgs a) {
     // One wave for up to 64 keys, else all four waves (E = P2 / 256 keys
     // per lane, at least one), so enough waves per CU hide the latency of
     // the dependent compare-exchange stages.
-    if (P2 <= 64) sort_tile<1>(a, t, s, L, P2, 1, buf);
-    else if (P2 <= 256) sort_tile<1>(a, t, s, L, P2, 4, buf);
-    else if (P2 <= 512) sort_tile<2>(a, t, s, L, P2, 4, buf);
-    else if (P2 <= 1024) sort_tile<4>(a, t, s, L, P2, 4, buf);
-    else if (P2 <= 2048) sort_tile<8>(a, t, s, L, P2, 4, buf);
-    else sort_tile<16>(a, t, s, L, P2, 4, buf);
+    if (P2 <= 64) sort_tile<1>(a, t, s, L, P2, 1, buf, red);
+    else if (P2 <= 256) sort_tile<1>(a, t, s, L, P2, 4, buf, red);
+    else if (P2 <= 512) sort_tile<2>(a, t, s, L, P2, 4, buf, red);
+    else if (P2 <= 1024) sort_tile<4>(a, t, s, L, P2, 4, buf, red);
+    else if (P2 <= 2048) sort_tile<8>(a, t, s, L, P2, 4, buf, red);
+    else sort_tile<16>(a, t, s, L, P2, 4, buf, red);
   } else {
     unsigned long long* g = a.keys_in + s;
     bitonic_sort(g, L, tid, 256);
