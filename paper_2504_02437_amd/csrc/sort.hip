@@ -300,16 +300,21 @@ __device__ __forceinline__ void wave_sync() {
 constexpr int kIdxBits = 12;   // position in a segment of at most 4096 keys
 constexpr int kQBits = 32 - kIdxBits;
 
-// One segment of L <= 4096 keys.  The network sorts 32-bit keys
-//   q << 12 | i,   q = (depth bits - the segment's smallest) >> shift,
-// i the key's position in the unsorted segment, shift the least that fits
-// the segment's depth-bit range in 20 bits.  Integer differences and shifts
-// keep the order of the depth bits (a smaller q means a smaller depth), and
-// i makes every key unique and names its 64-bit key; the all-ones padding
-// stays above every real key (i = 4095 only when L = 4096, with no padding).
-// After the network each run of equal q - in practice almost always a
-// single key - is put in (depth, index) order by ranking its members'
-// 64-bit keys, so the result is exactly the sorted 64-bit segment.
+// One segment of L <= 4096 keys, sorted by the network on 32-bit keys that
+// stand for the 64-bit ones.  With d the depth bits and g the index less
+// the segment's smallest of each:
+//  - exact, when the ranges of d and g fit 31 bits together (a segment of
+//    one depth, or nearly): d << gbits | g, the 64-bit order itself;
+//  - quantised otherwise: q << 12 | i, q = d >> shift with the least shift
+//    that fits d's range in 20 bits, i the key's position in the unsorted
+//    segment.  Integer shifts keep the order of the depth bits (a smaller q
+//    means a smaller depth); i makes every key unique and names its 64-bit
+//    key.  After the network each run of equal q - in practice a single key,
+//    or the few Gaussians of an inserted patch - is put in (depth, index)
+//    order by ranking its members' 64-bit keys, so the result is exactly
+//    the sorted 64-bit segment.
+// The all-ones padding stays above every real key (exact keys are below
+// 2^31; i = 4095 only when L = 4096, with no padding).
 template <int E>
 __device__ void sort_tile(const SortArgs& a, int t, long long s, int L, int P2,
                           int nw, uint32_t* buf, uint32_t* red) {
@@ -317,44 +322,73 @@ __device__ void sort_tile(const SortArgs& a, int t, long long s, int L, int P2,
   const bool active = wave < nw;
   if (nw == 1 && !active) return;   // no cross-wave stage: no barrier
   const int base = tid * E;
-  uint32_t dhi[E];
-  uint32_t dmin = 0xffffffffu, dmax = 0u;
+  uint32_t dhi[E], glo[E];
+  uint32_t dmin = 0xffffffffu, dmax = 0u, gmin = 0xffffffffu, gmax = 0u;
 #pragma unroll
   for (int e = 0; e < E; ++e) {
     const int p = base + e;
-    dhi[e] = (active && p < L) ? (uint32_t)(a.keys_in[s + p] >> 32) : 0u;
-    if (active && p < L) {
+    const bool real = active && p < L;
+    const unsigned long long k = real ? a.keys_in[s + p] : 0ull;
+    dhi[e] = (uint32_t)(k >> 32);
+    glo[e] = (uint32_t)k;
+    if (real) {
       dmin = min(dmin, dhi[e]);
       dmax = max(dmax, dhi[e]);
+      gmin = min(gmin, glo[e]);
+      gmax = max(gmax, glo[e]);
     }
   }
   for (int off = 32; off > 0; off >>= 1) {
     dmin = min(dmin, (uint32_t)__shfl_xor((int)dmin, off, 64));
     dmax = max(dmax, (uint32_t)__shfl_xor((int)dmax, off, 64));
+    gmin = min(gmin, (uint32_t)__shfl_xor((int)gmin, off, 64));
+    gmax = max(gmax, (uint32_t)__shfl_xor((int)gmax, off, 64));
   }
   if (nw > 1) {
     if (lane == 0) {
-      red[2 * wave] = dmin;
-      red[2 * wave + 1] = dmax;
+      red[4 * wave] = dmin;
+      red[4 * wave + 1] = dmax;
+      red[4 * wave + 2] = gmin;
+      red[4 * wave + 3] = gmax;
     }
     __syncthreads();
     for (int w = 0; w < nw; ++w) {
-      dmin = min(dmin, red[2 * w]);
-      dmax = max(dmax, red[2 * w + 1]);
+      dmin = min(dmin, red[4 * w]);
+      dmax = max(dmax, red[4 * w + 1]);
+      gmin = min(gmin, red[4 * w + 2]);
+      gmax = max(gmax, red[4 * w + 3]);
     }
   }
-  const uint32_t range = dmax - dmin;   // dmax >= dmin for L >= 1
-  const int bits = range ? 32 - __clz((int)range) : 0;
-  const int shift = bits > kQBits ? bits - kQBits : 0;
+  // dmax >= dmin and gmax >= gmin for L >= 1.
+  const uint32_t drange = dmax - dmin, grange = gmax - gmin;
+  const int dbits = drange ? 32 - __clz((int)drange) : 0;
+  const int gbits = grange ? 32 - __clz((int)grange) : 0;
+  const bool exact = dbits + gbits <= 31;
+  const int shift = dbits > kQBits ? dbits - kQBits : 0;
   uint32_t x[E];
 #pragma unroll
   for (int e = 0; e < E; ++e) {
     const int p = base + e;
-    x[e] = (active && p < L)
-               ? (((dhi[e] - dmin) >> shift) << kIdxBits) | (uint32_t)p
-               : 0xffffffffu;
+    const uint32_t d = dhi[e] - dmin;
+    x[e] = !(active && p < L) ? 0xffffffffu
+           : exact ? (d << gbits) | (glo[e] - gmin)
+                   : ((d >> shift) << kIdxBits) | (uint32_t)p;
   }
   sort_in_registers<E>(x, L, P2, nw, buf);
+  if (exact) {   // the keys are the 64-bit order: write them out
+    if (!active) return;
+    const uint32_t gmask = gbits ? 0xffffffffu >> (32 - gbits) : 0u;
+#pragma unroll
+    for (int e = 0; e < E; ++e) {
+      const int p = base + e;
+      if (p >= L) continue;
+      a.vals_out[s + p] = (x[e] & gmask) + gmin;
+      if (a.keys_out)
+        a.keys_out[s + p] = ((unsigned long long)(uint32_t)t << 32) |
+                            ((x[e] >> gbits) + dmin);
+    }
+    return;
+  }
   // Publish the sorted 32-bit keys position-major for the run tests.
   if (nw > 1) __syncthreads(); else wave_sync();
   if (active) {
@@ -363,29 +397,54 @@ __device__ void sort_tile(const SortArgs& a, int t, long long s, int L, int P2,
       if (base + e < L) buf[base + e] = x[e];
   }
   if (nw > 1) __syncthreads(); else wave_sync();
-  if (!active) return;
+  if (!active || base >= L) return;
+  // The lane's E positions are consecutive, so the runs they fall in cover
+  // one range [A, B): one scan to the left of the first position and one to
+  // the right of the last.  Inside it a smaller quantum means a smaller
+  // 64-bit key, so each key's final position is A plus the number of keys
+  // of the range below it; the range's keys are loaded once for all E.
+  // (Quadratic in the length of a run: fine for the runs of real scenes, a
+  // few keys; a segment of many Gaussians at a few exact depths is correct
+  // but slow.)
+  constexpr uint32_t kIdxMask = (1u << kIdxBits) - 1;
+  const int ne = min(E, L - base);
+  unsigned long long full[E];
+  bool multi = false;
 #pragma unroll
   for (int e = 0; e < E; ++e) {
-    const int p = base + e;
-    if (p >= L) continue;
-    const uint32_t q = x[e] >> kIdxBits;
-    const unsigned long long full =
-        a.keys_in[s + (x[e] & ((1u << kIdxBits) - 1))];
-    int pos = p;
-    const bool left = p > 0 && (buf[p - 1] >> kIdxBits) == q;
-    const bool right = p + 1 < L && (buf[p + 1] >> kIdxBits) == q;
-    if (left || right) {
-      int a0 = p, b0 = p + 1;
-      while (a0 > 0 && (buf[a0 - 1] >> kIdxBits) == q) --a0;
-      while (b0 < L && (buf[b0] >> kIdxBits) == q) ++b0;
-      int r = 0;
-      for (int i = a0; i < b0; ++i)
-        r += a.keys_in[s + (buf[i] & ((1u << kIdxBits) - 1))] < full;
-      pos = a0 + r;
+    full[e] = e < ne ? a.keys_in[s + (x[e] & kIdxMask)] : 0ull;
+    if (e + 1 < ne) multi |= (x[e] >> kIdxBits) == (x[e + 1] >> kIdxBits);
+  }
+  const uint32_t q0 = x[0] >> kIdxBits;
+  uint32_t ql = q0;
+#pragma unroll
+  for (int e = 1; e < E; ++e)
+    if (e < ne) ql = x[e] >> kIdxBits;
+  int A = base;
+  while (A > 0 && (buf[A - 1] >> kIdxBits) == q0) --A;
+  int B = base + ne;
+  while (B < L && (buf[B] >> kIdxBits) == ql) ++B;
+  multi |= A < base || B > base + ne;
+  int r[E];
+#pragma unroll
+  for (int e = 0; e < E; ++e) r[e] = e;
+  if (multi) {
+#pragma unroll
+    for (int e = 0; e < E; ++e) r[e] = A - base;
+    for (int i = A; i < B; ++i) {
+      const unsigned long long fi = a.keys_in[s + (buf[i] & kIdxMask)];
+#pragma unroll
+      for (int e = 0; e < E; ++e) r[e] += fi < full[e] ? 1 : 0;
     }
-    a.vals_out[s + pos] = (uint32_t)full;
+  }
+#pragma unroll
+  for (int e = 0; e < E; ++e) {
+    if (e >= ne) continue;
+    const int pos = base + r[e];
+    a.vals_out[s + pos] = (uint32_t)full[e];
     if (a.keys_out)
-      a.keys_out[s + pos] = ((unsigned long long)(uint32_t)t << 32) | (full >> 32);
+      a.keys_out[s + pos] =
+          ((unsigned long long)(uint32_t)t << 32) | (full[e] >> 32);
   }
 }
 
@@ -397,7 +456,7 @@ void k_sort_tiles(SortArgs a) {
   static_assert(kCap == 4 * 64 * 16, "four waves of 16 keys per lane");
   static_assert(kCap <= (1 << kIdxBits), "positions fit the key's index bits");
   __shared__ uint32_t buf[kCap];
-  __shared__ uint32_t red[8];
+  __shared__ uint32_t red[16];
   const int t = (int)a.order[blockIdx.x];
   const int tid = threadIdx.x;
   const long long s = min((long long)a.ranges[2 * t], a.key_cap);

@@ -278,8 +278,8 @@ def _one_tile_scene(n, seed, ties):
     """n small opaque Gaussians whose boxes all lie inside the first 16x16
     tile of a 32x32 image, so that tile's list has exactly n keys.  ties:
     "none" (distinct depths), "few" (depths take only 7 values: runs of
-    equal depth far longer than 32 keys) or "pairs" (n / 2 values: runs of a
-    few keys)."""
+    equal depth far longer than 32 keys), "pairs" (n / 2 values: runs of a
+    few keys) or "same" (one depth for all)."""
     rng = np.random.default_rng([77, n, seed])
     cam = synth.identity_camera(30.0, 30.0, 32, 32)
     z = rng.uniform(1.0, 3.0, n)
@@ -287,6 +287,8 @@ def _one_tile_scene(n, seed, ties):
         z = 1.0 + 0.25 * rng.integers(0, 7, n)
     elif ties == "pairs":
         z = 1.0 + 1e-3 * rng.integers(0, max(1, n // 2), n)
+    elif ties == "same":
+        z = np.full(n, 2.0)
     u = rng.uniform(4.0, 11.0, n)
     v = rng.uniform(4.0, 11.0, n)
     mean = np.stack([(u - cam.cx) * z / cam.fx, (v - cam.cy) * z / cam.fy, z])
@@ -305,10 +307,10 @@ def _one_tile_scene(n, seed, ties):
 def test_sort_every_segment_size_class(n):
     """Segments of every size class of the in-register sort (one lane per
     key up to 64, 2-16 keys per lane in one wave up to 1024, two and four
-    waves up to 4096), with distinct depths, with runs of a few equal depths
-    and with only seven depths (long runs): keys, values and ranges
-    bit-exact (equal depths in index order)."""
-    for ties in ("none", "pairs", "few"):
+    waves up to 4096), with distinct depths, with runs of a few equal depths,
+    with only seven depths (long runs) and with a single depth: keys, values
+    and ranges bit-exact (equal depths in index order)."""
+    for ties in ("none", "pairs", "few", "same"):
         w = _one_tile_scene(n, 0, ties)
         print("case sort segment", n, ties, flush=True)
         p64, proj, bins, fwd = oracle_forward(w, 16)
