@@ -237,57 +237,46 @@ __device__ __forceinline__ void stage_lds(uint32_t (&x)[E], int m, int half,
   }
 }
 
-// Sorts the first L of P2 <= 64 E nw keys held E per lane by the first nw
-// waves of the workgroup (all waves reach the barriers of cross-wave stages);
-// positions >= L hold all-ones keys.
-template <int E>
-__device__ void sort_in_registers(uint32_t (&x)[E], int L, int P2, int nw,
-                                  uint32_t* buf) {
+// The network for a padded size P2 known at compile time, as a recursion
+// over the merge steps k = 2 .. P2 and their distances j = k/4 .. 1, so that
+// every stage's kind, partner mask and LDS offsets are constants (no loop or
+// switch left to the scalar unit).  Sorts the first L of P2 <= 64 E nw keys
+// held E per lane by the first nw waves of the workgroup (all waves reach
+// the barriers of cross-wave stages); positions >= L hold all-ones keys.
+template <int E, int J>
+__device__ __forceinline__ void distance_stages(uint32_t (&x)[E], bool active,
+                                                bool work, int lane,
+                                                uint32_t* buf) {
+  if constexpr (J >= 64 * E) {
+    stage_lds<E>(x, J, J, active, work, buf);
+  } else if (work) {
+    if constexpr (J >= E) stage_across_lanes<E, J / E>(x, lane);
+    else stage_in_lane<E, J>(x);
+  }
+  if constexpr (J > 1) distance_stages<E, J / 2>(x, active, work, lane, buf);
+}
+
+template <int E, int P2, int K>
+__device__ __forceinline__ void merge_steps(uint32_t (&x)[E], bool active,
+                                            bool work, int lane,
+                                            uint32_t* buf) {
+  if constexpr (K > 64 * E) {
+    stage_lds<E>(x, K - 1, K >> 1, active, work, buf);
+  } else if (work) {
+    if constexpr (K <= E) mirror_in_lane<E, K>(x);
+    else mirror_across_lanes<E, K / E - 1>(x, lane);
+  }
+  if constexpr (K >= 4) distance_stages<E, K / 4>(x, active, work, lane, buf);
+  if constexpr (K < P2) merge_steps<E, P2, 2 * K>(x, active, work, lane, buf);
+}
+
+template <int E, int P2>
+__device__ __forceinline__ void sort_in_registers(uint32_t (&x)[E], int L,
+                                                  int nw, uint32_t* buf) {
   const int tid = threadIdx.x, lane = tid & 63;
   const bool active = (tid >> 6) < nw;
   const bool work = active && (tid >> 6) * 64 * E < L;
-  for (int k = 2; k <= P2; k <<= 1) {
-    if (k > 64 * E) {
-      stage_lds<E>(x, k - 1, k >> 1, active, work, buf);
-    } else if (work) {
-      if (k <= E) {
-        if constexpr (E >= 2) { if (k == 2) mirror_in_lane<E, 2>(x); }
-        if constexpr (E >= 4) { if (k == 4) mirror_in_lane<E, 4>(x); }
-        if constexpr (E >= 8) { if (k == 8) mirror_in_lane<E, 8>(x); }
-        if constexpr (E >= 16) { if (k == 16) mirror_in_lane<E, 16>(x); }
-      } else {
-        switch (k / E) {
-          case 2: mirror_across_lanes<E, 1>(x, lane); break;
-          case 4: mirror_across_lanes<E, 3>(x, lane); break;
-          case 8: mirror_across_lanes<E, 7>(x, lane); break;
-          case 16: mirror_across_lanes<E, 15>(x, lane); break;
-          case 32: mirror_across_lanes<E, 31>(x, lane); break;
-          default: mirror_across_lanes<E, 63>(x, lane); break;
-        }
-      }
-    }
-    for (int j = k >> 2; j > 0; j >>= 1) {
-      if (j >= 64 * E) {
-        stage_lds<E>(x, j, j, active, work, buf);
-      } else if (!work) {
-        continue;
-      } else if (j >= E) {
-        switch (j / E) {
-          case 1: stage_across_lanes<E, 1>(x, lane); break;
-          case 2: stage_across_lanes<E, 2>(x, lane); break;
-          case 4: stage_across_lanes<E, 4>(x, lane); break;
-          case 8: stage_across_lanes<E, 8>(x, lane); break;
-          case 16: stage_across_lanes<E, 16>(x, lane); break;
-          default: stage_across_lanes<E, 32>(x, lane); break;
-        }
-      } else {
-        if constexpr (E > 8) { if (j == 8) { stage_in_lane<E, 8>(x); continue; } }
-        if constexpr (E > 4) { if (j == 4) { stage_in_lane<E, 4>(x); continue; } }
-        if constexpr (E > 2) { if (j == 2) { stage_in_lane<E, 2>(x); continue; } }
-        if constexpr (E > 1) { if (j == 1) { stage_in_lane<E, 1>(x); continue; } }
-      }
-    }
-  }
+  if constexpr (P2 >= 2) merge_steps<E, P2, 2>(x, active, work, lane, buf);
 }
 
 // Orders one wave's LDS accesses before and after this point (the one-wave
@@ -315,9 +304,9 @@ constexpr int kQBits = 32 - kIdxBits;
 //    the sorted 64-bit segment.
 // The all-ones padding stays above every real key (exact keys are below
 // 2^31; i = 4095 only when L = 4096, with no padding).
-template <int E>
-__device__ void sort_tile(const SortArgs& a, int t, long long s, int L, int P2,
-                          int nw, uint32_t* buf, uint32_t* red) {
+template <int E, int P2>
+__device__ void sort_tile(const SortArgs& a, int t, long long s, int L, int nw,
+                          uint32_t* buf, uint32_t* red) {
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const bool active = wave < nw;
   if (nw == 1 && !active) return;   // no cross-wave stage: no barrier
@@ -374,7 +363,7 @@ __device__ void sort_tile(const SortArgs& a, int t, long long s, int L, int P2,
            : exact ? (d << gbits) | (glo[e] - gmin)
                    : ((d >> shift) << kIdxBits) | (uint32_t)p;
   }
-  sort_in_registers<E>(x, L, P2, nw, buf);
+  sort_in_registers<E, P2>(x, L, nw, buf);
   if (exact) {   // the keys are the 64-bit order: write them out
     if (!active) return;
     const uint32_t gmask = gbits ? 0xffffffffu >> (32 - gbits) : 0u;
@@ -469,12 +458,21 @@ void k_sort_tiles(SortArgs a) {
     // One wave for up to 64 keys, else all four waves (E = P2 / 256 keys
     // per lane, at least one), so enough waves per CU hide the latency of
     // the dependent compare-exchange stages.
-    if (P2 <= 64) sort_tile<1>(a, t, s, L, P2, 1, buf, red);
-    else if (P2 <= 256) sort_tile<1>(a, t, s, L, P2, 4, buf, red);
-    else if (P2 <= 512) sort_tile<2>(a, t, s, L, P2, 4, buf, red);
-    else if (P2 <= 1024) sort_tile<4>(a, t, s, L, P2, 4, buf, red);
-    else if (P2 <= 2048) sort_tile<8>(a, t, s, L, P2, 4, buf, red);
-    else sort_tile<16>(a, t, s, L, P2, 4, buf, red);
+    switch (P2) {   // padded sizes: 1 .. 64 in one wave, then 256 E
+      case 1: sort_tile<1, 1>(a, t, s, L, 1, buf, red); break;
+      case 2: sort_tile<1, 2>(a, t, s, L, 1, buf, red); break;
+      case 4: sort_tile<1, 4>(a, t, s, L, 1, buf, red); break;
+      case 8: sort_tile<1, 8>(a, t, s, L, 1, buf, red); break;
+      case 16: sort_tile<1, 16>(a, t, s, L, 1, buf, red); break;
+      case 32: sort_tile<1, 32>(a, t, s, L, 1, buf, red); break;
+      case 64: sort_tile<1, 64>(a, t, s, L, 1, buf, red); break;
+      case 128: sort_tile<1, 128>(a, t, s, L, 4, buf, red); break;
+      case 256: sort_tile<1, 256>(a, t, s, L, 4, buf, red); break;
+      case 512: sort_tile<2, 512>(a, t, s, L, 4, buf, red); break;
+      case 1024: sort_tile<4, 1024>(a, t, s, L, 4, buf, red); break;
+      case 2048: sort_tile<8, 2048>(a, t, s, L, 4, buf, red); break;
+      default: sort_tile<16, 4096>(a, t, s, L, 4, buf, red); break;
+    }
   } else {
     unsigned long long* g = a.keys_in + s;
     bitonic_sort(g, L, tid, 256);
