@@ -133,13 +133,6 @@ __global__ __launch_bounds__(256) void k_adam(AdamArgs a) {
   const int row = blockIdx.y;
   const int n = min(*a.n_dev, a.cap);
   if (blockIdx.x * 256 * kAdamPer >= n) return;
-  if (threadIdx.x == 0) {
-    const int step = a.step_dev ? max(1, *a.step_dev + a.step_bias) : a.step;
-    corr[0] = (float)(1.0 - pow((double)a.b1, (double)step));
-    corr[1] = (float)(1.0 - pow((double)a.b2, (double)step));
-  }
-  __syncthreads();
-  const float c1 = corr[0], c2 = corr[1];
   float *P, *M, *Vv;
   const float* G;
   float lr;
@@ -149,7 +142,8 @@ __global__ __launch_bounds__(256) void k_adam(AdamArgs a) {
     const size_t o = (size_t)(row - 14) * a.cap;
     P = a.psh + o; G = a.gsh + o; M = a.msh + o; Vv = a.vsh + o; lr = a.lr_sh;
   }
-  // All loads first, so their latencies overlap.
+  // All loads first, so their latencies overlap each other and the bias
+  // corrections' powers below.
   float gr[kAdamPer], mo[kAdamPer], vo[kAdamPer], po[kAdamPer];
 #pragma unroll
   for (int i = 0; i < kAdamPer; ++i) {
@@ -160,6 +154,13 @@ __global__ __launch_bounds__(256) void k_adam(AdamArgs a) {
     vo[i] = in ? Vv[g] : 0.f;
     po[i] = in ? P[g] : 0.f;
   }
+  if (threadIdx.x == 0) {
+    const int step = a.step_dev ? max(1, *a.step_dev + a.step_bias) : a.step;
+    corr[0] = (float)(1.0 - pow((double)a.b1, (double)step));
+    corr[1] = (float)(1.0 - pow((double)a.b2, (double)step));
+  }
+  __syncthreads();
+  const float c1 = corr[0], c2 = corr[1];
 #pragma unroll
   for (int i = 0; i < kAdamPer; ++i) {
     const int g = g0 + i * 256;
