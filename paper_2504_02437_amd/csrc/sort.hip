@@ -9,25 +9,27 @@
 // keys emitted Gaussian by Gaussian.
 //
 // Segments up to kCap keys sort in registers on 32-bit keys standing for
-// the 64-bit ones (the segment's depth bits quantised to 20 bits, tagged
-// with the key's position; equal quanta are put in order afterwards, see
-// sort_tile), so that a compare-exchange is a min and a max rather than a
-// 64-bit compare and four selects.
+// the 64-bit ones (see sort_tile: exact offsets when the segment's depth
+// and index ranges allow, else its depth bits quantised to 20 bits and
+// tagged with the key's position, equal quanta put in order afterwards), so
+// that a compare-exchange is a min and a max rather than a 64-bit compare
+// and four selects.
 //
 // Sorting network: bitonic, in its all-ascending form, over the segment
-// padded to a power of two P2 with all-ones keys (larger than any real key).
-// In registers, lane l of wave w holds the E
-// consecutive positions (64 w + l) E .. + E - 1 (one wave with E = 1 up to 64
-// keys, else four waves with E = P2 / 256), so a comparator whose positions
-// differ only below bit log2 E stays inside a lane, one that differs below
-// bit log2 64E pairs two lanes of the same wave (DPP, swizzles, lane
-// permutes or swaps), and only the others - at most three merge steps per segment - go
-// through LDS with barriers.  Padding never moves in the all-ascending form,
-// so waves that hold only padding skip the compare-exchanges.  Longer
-// segments (rare: a tile covered by more than kCap Gaussians) sort in place
-// in the unsorted key buffer, with a global-memory bitonic network in the
-// same all-ascending form, so positions past the end act as +infinity
-// without being stored.
+// padded to a power of two P2 with all-ones keys (larger than any real key),
+// unrolled at compile time for each P2.  In registers, lane l of wave w
+// holds the E consecutive positions (64 w + l) E .. + E - 1 (one wave with
+// E = 1 up to 64 keys, else four waves with E = P2 / 256), so a comparator
+// whose positions differ only below bit log2 E stays inside a lane, one that
+// differs below bit log2 64E pairs two lanes of the same wave (DPP,
+// swizzles, lane permutes or swaps), and only the others - at most three
+// merge steps per segment - go through LDS with barriers.  Padding never
+// moves in the all-ascending form, so waves that hold only padding skip the
+// compare-exchanges.  Longer segments (rare: a tile covered by more than
+// kCap Gaussians) sort in place in the unsorted key buffer, with a
+// global-memory bitonic network on the 64-bit keys in the same
+// all-ascending form, so positions past the end act as +infinity without
+// being stored.
 
 #include "gs_internal.h"
 
