@@ -7,6 +7,7 @@
 #include <string.h>
 
 #include "gs_internal.h"
+#include "tails.h"
 
 namespace gs {
 
@@ -167,6 +168,83 @@ static int check_ws(const gs_workspace* ws) {
 }
 
 static int finish(hipError_t e, const char* what) { return check_hip(e, what); }
+
+// The render boxes of the last projection hold every pixel whose alpha can
+// reach the alpha_min they were formed for; a smaller alpha_min needs larger
+// boxes.
+static int check_box_alpha(const gs_workspace* ws, const gs_settings* s) {
+  if (s->alpha_min < ws->box_alpha_min) {
+    set_error("settings.alpha_min %g is below the %g the render boxes were "
+              "formed for; project again with these settings",
+              (double)s->alpha_min, (double)ws->box_alpha_min);
+    return GS_E_INVALID;
+  }
+  return GS_OK;
+}
+
+int render_bwd_l1_checked(gs_workspace* ws, const gs_params* params,
+                         const gs_settings* s, const float* out_rgb,
+                         const float* target, float lambda,
+                         const float* T_final, const int32_t* n_last,
+                         gs_params* grad, double* loss_dev, double* sqerr_dev,
+                         void* stream, const PlanarJob* planar,
+                         bool defer_reduce) {
+  g_err[0] = 0;
+  if (int rc = check_ws(ws)) return rc;
+  if (int rc = validate_params(params, "params")) return rc;
+  if (int rc = validate_params(grad, "grad")) return rc;
+  if (int rc = validate_settings(s)) return rc;
+  if (s->tile != ws->geo.tile) { set_error("settings.tile differs from the workspace's"); return GS_E_INVALID; }
+  if (int rc = check_box_alpha(ws, s)) return rc;
+  if (!out_rgb || !target || !T_final || !n_last || !loss_dev) {
+    set_error("an input is NULL");
+    return GS_E_INVALID;
+  }
+  if (grad->capacity != params->capacity || params->capacity != ws->geo.capacity) {
+    set_error("grad / params / workspace capacities differ");
+    return GS_E_CAPACITY;
+  }
+  if (int rc = same_layout(params, grad, "grad")) return rc;
+  if (int rc = disjoint(params, "params", grad, "grad")) return rc;
+  L1Fused l1{out_rgb, target, lambda, loss_dev, sqerr_dev};
+  l1.defer_reduce = defer_reduce;
+  return finish(launch_render_bwd(ws, s, nullptr, T_final, n_last, grad->rgb,
+                                  params->sh_degree > 0, &l1,
+                                  (hipStream_t)stream, planar),
+                "render_bwd_l1");
+}
+
+int project_bwd_checked(gs_workspace* ws, const gs_params* params,
+                        const gs_camera* cams, gs_params* grad, void* stream,
+                        const L1ReduceJob* l1) {
+  g_err[0] = 0;
+  if (int rc = check_ws(ws)) return rc;
+  if (int rc = validate_params(params, "params")) return rc;
+  if (int rc = validate_params(grad, "grad")) return rc;
+  if (!cams || !params->n_dev) { set_error("an input is NULL"); return GS_E_INVALID; }
+  if (grad->capacity != params->capacity || params->capacity != ws->geo.capacity) {
+    set_error("grad / params / workspace capacities differ");
+    return GS_E_CAPACITY;
+  }
+  if (int rc = same_layout(params, grad, "grad")) return rc;
+  if (int rc = disjoint(params, "params", grad, "grad")) return rc;
+  hipStream_t st = (hipStream_t)stream;
+  hipError_t e = launch_project_bwd(ws, params, cams, grad, st, l1);
+  if (e != hipSuccess) return finish(e, "project_bwd");
+  return finish(launch_sh_bwd(ws, params, cams, grad, st),
+                "view-dependent colour backward");
+}
+
+int planar_checked(const gs_params* params, float lambda, float floor_,
+                   gs_params* grad, double* loss_dev, PlanarJob* job) {
+  g_err[0] = 0;
+  if (int rc = validate_params(params, "params")) return rc;
+  if (!grad || !grad->log_scale || !loss_dev || !params->n_dev) { set_error("an argument is NULL"); return GS_E_INVALID; }
+  if (grad->capacity != params->capacity) { set_error("capacities differ"); return GS_E_CAPACITY; }
+  if (int rc = disjoint(params, "params", grad, "grad")) return rc;
+  *job = planar_job(params, lambda, floor_, grad, loss_dev);
+  return GS_OK;
+}
 
 int adam_checked(gs_params* params, const gs_params* grad, gs_params* m,
                  gs_params* v, const float* lr, float beta1, float beta2,
@@ -342,19 +420,6 @@ int gs_sort_tile_keys(gs_workspace* ws, const gs_settings* s, void* stream) {
   return finish(launch_sort(ws, s, (hipStream_t)stream), "sort_tile_keys");
 }
 
-// The render boxes of the last projection hold every pixel whose alpha can
-// reach the alpha_min they were formed for; a smaller alpha_min needs larger
-// boxes.
-static int check_box_alpha(const gs_workspace* ws, const gs_settings* s) {
-  if (s->alpha_min < ws->box_alpha_min) {
-    set_error("settings.alpha_min %g is below the %g the render boxes were "
-              "formed for; project again with these settings",
-              (double)s->alpha_min, (double)ws->box_alpha_min);
-    return GS_E_INVALID;
-  }
-  return GS_OK;
-}
-
 int gs_render_fwd(gs_workspace* ws, const gs_params* params,
                   const gs_settings* s, float* out_rgb, float* out_T,
                   int32_t* out_nlast, void* stream) {
@@ -460,48 +525,14 @@ int gs_render_bwd_l1(gs_workspace* ws, const gs_params* params,
                      const float* target, float lambda, const float* T_final,
                      const int32_t* n_last, gs_params* grad, double* loss_dev,
                      double* sqerr_dev, void* stream) {
-  g_err[0] = 0;
-  if (int rc = check_ws(ws)) return rc;
-  if (int rc = validate_params(params, "params")) return rc;
-  if (int rc = validate_params(grad, "grad")) return rc;
-  if (int rc = validate_settings(s)) return rc;
-  if (s->tile != ws->geo.tile) { set_error("settings.tile differs from the workspace's"); return GS_E_INVALID; }
-  if (int rc = check_box_alpha(ws, s)) return rc;
-  if (!out_rgb || !target || !T_final || !n_last || !loss_dev) {
-    set_error("an input is NULL");
-    return GS_E_INVALID;
-  }
-  if (grad->capacity != params->capacity || params->capacity != ws->geo.capacity) {
-    set_error("grad / params / workspace capacities differ");
-    return GS_E_CAPACITY;
-  }
-  if (int rc = same_layout(params, grad, "grad")) return rc;
-  if (int rc = disjoint(params, "params", grad, "grad")) return rc;
-  const L1Fused l1{out_rgb, target, lambda, loss_dev, sqerr_dev};
-  return finish(launch_render_bwd(ws, s, nullptr, T_final, n_last, grad->rgb,
-                                  params->sh_degree > 0, &l1,
-                                  (hipStream_t)stream),
-                "render_bwd_l1");
+  return render_bwd_l1_checked(ws, params, s, out_rgb, target, lambda, T_final,
+                               n_last, grad, loss_dev, sqerr_dev, stream,
+                               nullptr, false);
 }
 
 int gs_project_bwd(gs_workspace* ws, const gs_params* params,
                    const gs_camera* cams, gs_params* grad, void* stream) {
-  g_err[0] = 0;
-  if (int rc = check_ws(ws)) return rc;
-  if (int rc = validate_params(params, "params")) return rc;
-  if (int rc = validate_params(grad, "grad")) return rc;
-  if (!cams || !params->n_dev) { set_error("an input is NULL"); return GS_E_INVALID; }
-  if (grad->capacity != params->capacity || params->capacity != ws->geo.capacity) {
-    set_error("grad / params / workspace capacities differ");
-    return GS_E_CAPACITY;
-  }
-  if (int rc = same_layout(params, grad, "grad")) return rc;
-  if (int rc = disjoint(params, "params", grad, "grad")) return rc;
-  hipStream_t st = (hipStream_t)stream;
-  hipError_t e = launch_project_bwd(ws, params, cams, grad, st);
-  if (e != hipSuccess) return finish(e, "project_bwd");
-  return finish(launch_sh_bwd(ws, params, cams, grad, st),
-                "view-dependent colour backward");
+  return project_bwd_checked(ws, params, cams, grad, stream, nullptr);
 }
 
 int gs_loss_l1(const float* rgb, const float* target, int32_t n_views,
@@ -545,13 +576,10 @@ int gs_loss_colour(const float* rgb, const float* target, int32_t n_views,
 
 int gs_planar_reg(const gs_params* params, float lambda, float floor_,
                   gs_params* grad, double* loss_dev, void* stream) {
-  g_err[0] = 0;
-  if (int rc = validate_params(params, "params")) return rc;
-  if (!grad || !grad->log_scale || !loss_dev || !params->n_dev) { set_error("an argument is NULL"); return GS_E_INVALID; }
-  if (grad->capacity != params->capacity) { set_error("capacities differ"); return GS_E_CAPACITY; }
-  if (int rc = disjoint(params, "params", grad, "grad")) return rc;
-  return finish(launch_planar_reg(params, lambda, floor_, grad, loss_dev,
-                                  (hipStream_t)stream), "planar_reg");
+  PlanarJob j;
+  if (int rc = planar_checked(params, lambda, floor_, grad, loss_dev, &j))
+    return rc;
+  return finish(launch_planar_job(j, (hipStream_t)stream), "planar_reg");
 }
 
 int gs_adam(gs_params* params, const gs_params* grad, gs_params* m,

@@ -116,9 +116,13 @@ int validate_params(const gs_params* p, const char* what);
 hipError_t launch_project(gs_workspace* ws, const gs_params* p,
                           const gs_camera* cams, const gs_settings* s,
                           hipStream_t st);
+struct PlanarJob;      // tails.h
+struct L1ReduceJob;    // tails.h
+// l1: the fused L1 term's tile-loss reduction as one workgroup appended to
+// the launch (the window graph), or null.
 hipError_t launch_project_bwd(gs_workspace* ws, const gs_params* p,
                               const gs_camera* cams, gs_params* grad,
-                              hipStream_t st);
+                              hipStream_t st, const L1ReduceJob* l1 = nullptr);
 hipError_t launch_bin(gs_workspace* ws, const gs_params* p, hipStream_t st);
 hipError_t launch_sort(gs_workspace* ws, const gs_settings* s, hipStream_t st);
 hipError_t launch_render_fwd(gs_workspace* ws, const gs_settings* s,
@@ -148,12 +152,17 @@ struct L1Fused {
   float lambda;
   double* loss;
   double* sqerr;
+  bool defer_reduce = false;   // the caller reduces the tile losses later
 };
+// planar: the planar regulariser's workgroups appended to the launch (the
+// window graph), or null.
 hipError_t launch_render_bwd(gs_workspace* ws, const gs_settings* s,
                              const float* dL, const float* T,
                              const int32_t* nlast, float* grad_rgb,
                              int per_view_colour, const L1Fused* l1,
-                             hipStream_t st);
+                             hipStream_t st, const PlanarJob* planar = nullptr);
+hipError_t launch_l1_reduce(const gs_workspace* ws, double* loss,
+                            double* sqerr, hipStream_t st);
 hipError_t launch_sh_colour(gs_workspace* ws, const gs_params* p,
                             const gs_camera* cams, hipStream_t st);
 hipError_t launch_sh_bwd(gs_workspace* ws, const gs_params* p,
@@ -173,6 +182,24 @@ hipError_t launch_adam(gs_params* p, const gs_params* g, gs_params* m,
                        gs_params* v, const float* lr, float b1, float b2,
                        float eps, int step, const int32_t* step_dev,
                        hipStream_t st, int step_bias = 0);
+// gs_render_bwd_l1 with its argument checks, the planar regulariser's
+// workgroups appended (or null) and the tile-loss reduction optionally left
+// to the caller.
+int render_bwd_l1_checked(gs_workspace* ws, const gs_params* params,
+                         const gs_settings* s, const float* out_rgb,
+                         const float* target, float lambda,
+                         const float* T_final, const int32_t* n_last,
+                         gs_params* grad, double* loss_dev, double* sqerr_dev,
+                         void* stream, const PlanarJob* planar,
+                         bool defer_reduce);
+// gs_project_bwd with its argument checks and an optional tile-loss
+// reduction workgroup.
+int project_bwd_checked(gs_workspace* ws, const gs_params* params,
+                        const gs_camera* cams, gs_params* grad, void* stream,
+                        const L1ReduceJob* l1);
+// gs_planar_reg's argument checks; on success *job holds its launch.
+int planar_checked(const gs_params* params, float lambda, float floor_,
+                   gs_params* grad, double* loss_dev, PlanarJob* job);
 // gs_adam with its argument checks, the bias passed to launch_adam.
 int adam_checked(gs_params* params, const gs_params* grad, gs_params* m,
                  gs_params* v, const float* lr, float beta1, float beta2,

@@ -5,6 +5,7 @@
 #include <math.h>
 
 #include "gs_internal.h"
+#include "tails.h"
 
 namespace gs {
 namespace {
@@ -78,30 +79,12 @@ __global__ __launch_bounds__(256) void k_loss_l1(const float* rgb,
   }
 }
 
-// Planar regulariser: lambda * mean_g max(floor, min_j exp(l_gj)).
-__global__ __launch_bounds__(256) void k_planar_reg(const float* lsc,
-                                                    const int32_t* n_dev,
-                                                    int cap, float lam,
-                                                    double floor_, float* dlsc,
-                                                    double* loss) {
+// Planar regulariser: lambda * mean_g max(floor, min_j exp(l_gj)).  A grid
+// stride over the Gaussians with a few hundred workgroups: the loss takes
+// one FP64 atomic per workgroup, and atomics on one address serialise.
+__global__ __launch_bounds__(256) void k_planar_reg(PlanarJob j) {
   __shared__ double sh[4];
-  const int n = min(*n_dev, cap);
-  double term = 0.0;
-  // Grid-stride over the Gaussians with a few hundred workgroups: the loss
-  // takes one FP64 atomic per workgroup, and atomics on one address
-  // serialise.
-  for (int g = blockIdx.x * 256 + threadIdx.x; g < n; g += gridDim.x * 256) {
-    const float l0 = lsc[g], l1 = lsc[cap + g], l2 = lsc[2 * cap + g];
-    int jm = 0;
-    float lm = l0;
-    if (l1 < lm) { lm = l1; jm = 1; }
-    if (l2 < lm) { lm = l2; jm = 2; }
-    const double sm = exp((double)lm);
-    term += sm > floor_ ? sm : floor_;
-    if (sm > floor_) dlsc[jm * cap + g] += (float)((double)lam * sm / (double)n);
-  }
-  const double t = block_sum(term, sh);
-  if (threadIdx.x == 0 && n > 0) atomicAdd(loss, (double)lam * t / (double)n);
+  planar_part(j, blockIdx.x, gridDim.x, sh);
 }
 
 struct AdamArgs {
@@ -429,14 +412,22 @@ hipError_t launch_loss_l1(const float* rgb, const float* target, int V, int H,
   return hipGetLastError();
 }
 
+PlanarJob planar_job(const gs_params* p, float lambda, float floor_,
+                     gs_params* grad, double* loss) {
+  return PlanarJob{p->log_scale, p->n_dev, p->capacity, lambda,
+                   (double)floor_, grad->log_scale, loss};
+}
+
+hipError_t launch_planar_job(const PlanarJob& j, hipStream_t st) {
+  const int blocks = min(256, (j.cap + 255) / 256);
+  if (blocks <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_planar_reg, dim3(blocks), dim3(256), 0, st, j);
+  return hipGetLastError();
+}
+
 hipError_t launch_planar_reg(const gs_params* p, float lambda, float floor_,
                              gs_params* grad, double* loss, hipStream_t st) {
-  const int blocks = min(256, (p->capacity + 255) / 256);
-  if (blocks <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_planar_reg, dim3(blocks), dim3(256), 0, st,
-                     p->log_scale, p->n_dev, p->capacity, lambda,
-                     (double)floor_, grad->log_scale, loss);
-  return hipGetLastError();
+  return launch_planar_job(planar_job(p, lambda, floor_, grad, loss), st);
 }
 
 hipError_t launch_adam(gs_params* p, const gs_params* g, gs_params* m,

@@ -20,6 +20,7 @@
 
 #include "admit.h"
 #include "gs_internal.h"
+#include "tails.h"
 
 namespace gs {
 namespace {
@@ -358,6 +359,9 @@ struct ProjBwdArgs {
   float* d_lsc;
   float* d_quat;
   float* d_opl;
+  // Workgroups past main_blocks reduce the fused L1 term's tile losses.
+  int main_blocks;
+  L1ReduceJob l1;
 };
 
 // Chain rule from dL/d(px, py, A, B, C) of every view back to the mean,
@@ -366,6 +370,11 @@ struct ProjBwdArgs {
 // G2 = -Q dQ Q; for Sigma2D = T Sigma T^T, dSigma = T^T G2 T and
 // dT = 2 G2 T Sigma; Sigma = M M^T gives dM = 2 dSigma M (summed over views).
 __global__ __launch_bounds__(256) void k_project_bwd(ProjBwdArgs a) {
+  __shared__ double part[4];
+  if ((int)blockIdx.x >= a.main_blocks) {   // dispatched last: the tail
+    l1_reduce_part(a.l1, part);
+    return;
+  }
   const int g = blockIdx.x * 256 + threadIdx.x;
   const int n = min(*a.n_dev, a.cap);
   if (g >= n) return;
@@ -530,7 +539,7 @@ hipError_t launch_project(gs_workspace* ws, const gs_params* p,
 
 hipError_t launch_project_bwd(gs_workspace* ws, const gs_params* p,
                               const gs_camera* cams, gs_params* grad,
-                              hipStream_t st) {
+                              hipStream_t st, const L1ReduceJob* l1) {
   ProjBwdArgs a;
   a.mean = p->mean; a.lsc = p->log_scale; a.quat = p->quat;
   a.opl = p->opacity_logit; a.n_dev = p->n_dev; a.cap = p->capacity;
@@ -539,8 +548,11 @@ hipError_t launch_project_bwd(gs_workspace* ws, const gs_params* p,
   a.d_mean = grad->mean; a.d_lsc = grad->log_scale; a.d_quat = grad->quat;
   a.d_opl = grad->opacity_logit;
   const int blocks = (p->capacity + 255) / 256;
-  if (blocks > 0)
-    hipLaunchKernelGGL(k_project_bwd, dim3(blocks), dim3(256), 0, st, a);
+  a.main_blocks = blocks;
+  a.l1 = l1 ? *l1 : L1ReduceJob{};
+  if (blocks + (l1 ? 1 : 0) > 0)
+    hipLaunchKernelGGL(k_project_bwd, dim3(blocks + (l1 ? 1 : 0)), dim3(256),
+                       0, st, a);
   return hipGetLastError();
 }
 

@@ -24,6 +24,7 @@
 // (entry, quantity).
 
 #include "raster_common.h"
+#include "tails.h"
 
 namespace gs {
 namespace {
@@ -45,6 +46,9 @@ struct BwdArgs {
   float l1_scale;        // lambda / (3HW), the gradient's magnitude
   double l1_lam_inv;     // lambda / (3HW) in FP64, for the loss
   double* tile_loss;     // [tiles][2]: this tile's loss and squared error
+  // Workgroups past the tiles' (tile_blocks) run the planar regulariser.
+  int tile_blocks;
+  PlanarJob planar;
 };
 
 // Sign of r times scale (sign(0) = 0): the L1 term's gradient.
@@ -291,6 +295,12 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(BG ? 1 : 5))
   __shared__ uint32_t gid[BATCH];
   __shared__ float eop[BATCH];   // opacity per staged entry
   __shared__ int smax;
+  __shared__ double psh[NT / 64];
+  if ((int)blockIdx.x >= a.tile_blocks) {   // dispatched last: the tail
+    planar_part(a.planar, (int)blockIdx.x - a.tile_blocks,
+                (int)gridDim.x - a.tile_blocks, psh);
+    return;
+  }
   const RasterArgs& r = a.r;
   const int t = (int)r.order[blockIdx.x];
   const int tpv = r.Tx * r.Ty;
@@ -451,42 +461,10 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(BG ? 1 : 5))
 }
 
 // Sum of the tiles' fused L1 losses into *loss and of each view's squared
-// errors into sqerr[view], in a fixed order (so the sums do not depend on
-// scheduling): wave w of the one workgroup reduces view k0 + w, then thread 0
-// adds the views in order.
-__global__ __launch_bounds__(1024) void k_l1_reduce(const double2* tile_loss,
-                                                    int V, int tpv,
-                                                    double* loss,
-                                                    double* sqerr) {
+// errors into sqerr[view], in a fixed order (l1_reduce_part).
+__global__ __launch_bounds__(1024) void k_l1_reduce(L1ReduceJob j) {
   __shared__ double part[16];
-  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
-  double total = 0.0;
-  for (int k0 = 0; k0 < V; k0 += 16) {
-    const int k = k0 + w;
-    if (k < V) {
-      double la = 0.0, lq = 0.0;
-      for (int i = lane; i < tpv; i += 64) {
-        const double2 q = tile_loss[(size_t)k * tpv + i];
-        la += q.x;
-        lq += q.y;
-      }
-      for (int off = 32; off > 0; off >>= 1) {
-        la += __shfl_down(la, off, 64);
-        lq += __shfl_down(lq, off, 64);
-      }
-      if (lane == 0) {
-        part[w] = la;
-        if (sqerr) atomicAdd(&sqerr[k], lq);
-      }
-    }
-    __syncthreads();
-    if (tid == 0)
-      for (int i = 0; i < 16 && k0 + i < V; ++i) total += part[i];
-    __syncthreads();
-  }
-  // One atomic add each: other calls (other workspaces, other streams) may
-  // accumulate into the same buffers.
-  if (tid == 0) atomicAdd(loss, total);
+  l1_reduce_part(j, part);
 }
 
 struct BwdLauncher {
@@ -511,7 +489,7 @@ hipError_t launch_render_bwd(gs_workspace* ws, const gs_settings* s,
                              const float* dL, const float* T,
                              const int32_t* nlast, float* grad_rgb,
                              int per_view_colour, const L1Fused* l1,
-                             hipStream_t st) {
+                             hipStream_t st, const PlanarJob* planar) {
   BwdArgs a;
   a.r = make_raster_args(ws, s);
   a.dL = dL; a.Tfin = T; a.nlast = nlast;
@@ -526,19 +504,41 @@ hipError_t launch_render_bwd(gs_workspace* ws, const gs_settings* s,
   a.grad2d = ws->grad2d; a.gop = ws->gop;
   a.grgb = per_view_colour ? ws->gcol : grad_rgb;
   a.grgb_vstride = per_view_colour ? (size_t)3 * ws->geo.capacity : 0;
-  const int blocks = ws->geo.n_views * ws->tiles_x * ws->tiles_y;
-  if (blocks <= 0) return hipSuccess;
-  const bool bg = s->bg[0] != 0.f || s->bg[1] != 0.f || s->bg[2] != 0.f;
-  dispatch_shape(ws->geo.tile, s->lds_batch, s->block_threads,
-                 BwdLauncher{a, blocks, bg, st});
-  if (l1) {
+  const int tiles = ws->geo.n_views * ws->tiles_x * ws->tiles_y;
+  a.tile_blocks = tiles;
+  a.planar = planar ? *planar : PlanarJob{};
+  if (tiles <= 0) {
+    if (planar) {
+      const hipError_t e = launch_planar_job(*planar, st);
+      if (e != hipSuccess) return e;
+    }
+  } else {
+    // The regulariser's workgroups (a grid stride over the Gaussians, as
+    // many as its own launch would have) follow the tiles'.
+    const int nt = s->block_threads ? s->block_threads
+                                    : default_threads(ws->geo.tile);
+    const int pb = planar ? min(256, (planar->cap + nt - 1) / nt) : 0;
+    const bool bg = s->bg[0] != 0.f || s->bg[1] != 0.f || s->bg[2] != 0.f;
+    dispatch_shape(ws->geo.tile, s->lds_batch, s->block_threads,
+                   BwdLauncher{a, tiles + pb, bg, st});
+  }
+  if (l1 && !l1->defer_reduce) {
     const hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_l1_reduce, dim3(1), dim3(1024), 0, st,
-                       (const double2*)ws->tile_loss,
-                       ws->geo.n_views, ws->tiles_x * ws->tiles_y, l1->loss,
-                       l1->sqerr);
+    return launch_l1_reduce(ws, l1->loss, l1->sqerr, st);
   }
+  return hipGetLastError();
+}
+
+L1ReduceJob l1_reduce_job(const gs_workspace* ws, double* loss, double* sqerr) {
+  return L1ReduceJob{(const double2*)ws->tile_loss, ws->geo.n_views,
+                     ws->tiles_x * ws->tiles_y, loss, sqerr};
+}
+
+hipError_t launch_l1_reduce(const gs_workspace* ws, double* loss,
+                            double* sqerr, hipStream_t st) {
+  hipLaunchKernelGGL(k_l1_reduce, dim3(1), dim3(1024), 0, st,
+                     l1_reduce_job(ws, loss, sqerr));
   return hipGetLastError();
 }
 

@@ -3,10 +3,11 @@
 //
 // The build captures, on the caller's stream, the same calls an eager
 // iteration makes: clear the gradient, loss and squared-error buffers, then
-// projection and binning, the per-tile sort, the forward render, the planar
-// regulariser's gradient, the compositing backward with the L1 term fused
-// in, the projection backward and the Adam step with its device step count
-// advanced.  The clearing is one kernel of its own (no memset nodes), which
+// projection and binning, the per-tile sort, the forward render, the
+// compositing backward with the L1 term fused in (the planar regulariser's
+// gradient in extra workgroups of the same launch), the projection backward
+// (the L1 tile-loss sum in one extra workgroup) and the Adam step with its
+// device step count advanced.  The clearing is one kernel of its own (no memset nodes), which
 // also advances the step count, so every node of the graph is a kernel.  The
 // graph holds the caller's device pointers; it owns no device memory of its
 // own.
@@ -14,6 +15,7 @@
 #include <new>
 
 #include "gs_internal.h"
+#include "tails.h"
 
 struct gs_window {
   hipGraphExec_t exec;
@@ -103,16 +105,23 @@ int enqueue_iteration(const gs_window_desc* d, hipStream_t st) {
   if ((rc = gs_render_fwd(d->ws, &params, &d->settings, d->out_rgb, d->out_T,
                           d->out_nlast, st)))
     return rc;
-  if (d->flags & GS_WINDOW_PLANAR_REG) {
-    if ((rc = gs_planar_reg(&params, d->lambda_reg, d->reg_floor, &grad,
-                            d->loss_dev, st)))
-      return rc;
-  }
-  if ((rc = gs_render_bwd_l1(d->ws, &params, &d->settings, d->out_rgb,
-                             d->target, d->lambda_l1, d->out_T, d->out_nlast,
-                             &grad, d->loss_dev, d->sqerr_dev, st)))
+  // The planar regulariser runs as extra workgroups of the compositing
+  // backward, and the L1 tile losses are summed by one extra workgroup of the
+  // projection backward: two launches fewer than calling the entry points.
+  PlanarJob planar;
+  const bool reg = (d->flags & GS_WINDOW_PLANAR_REG) != 0;
+  if (reg && (rc = planar_checked(&params, d->lambda_reg, d->reg_floor, &grad,
+                                  d->loss_dev, &planar)))
     return rc;
-  if ((rc = gs_project_bwd(d->ws, &params, d->cams, &grad, st))) return rc;
+  if ((rc = render_bwd_l1_checked(d->ws, &params, &d->settings, d->out_rgb,
+                                  d->target, d->lambda_l1, d->out_T,
+                                  d->out_nlast, &grad, d->loss_dev,
+                                  d->sqerr_dev, st, reg ? &planar : nullptr,
+                                  true)))
+    return rc;
+  const L1ReduceJob l1 = l1_reduce_job(d->ws, d->loss_dev, d->sqerr_dev);
+  if ((rc = project_bwd_checked(d->ws, &params, d->cams, &grad, st, &l1)))
+    return rc;
   if (d->flags & GS_WINDOW_ADAM) {
     // The clearing launch advanced *step_dev already.
     if ((rc = adam_checked(&params, &grad, &m, &v, d->lr, d->beta1, d->beta2,
