@@ -70,14 +70,18 @@ def _restore(st, s):
     torch.cuda.synchronize()
 
 
-def test_window_graph_replays_match_eager_calls():
+@pytest.mark.parametrize("degree", [0, 1])
+def test_window_graph_replays_match_eager_calls(degree):
     """Two views of a small scene, tile 16: three replays, each from the
     state an eager iteration started from, with the program's own eager work
     between them.  Image, transmittance, n_last and step count are
     identical; the losses agree to FP64 atomic order, parameters and moments
-    to FP32 atomic order."""
+    to FP32 atomic order.  Degree 1 adds the view-dependent colour's
+    backward after the projection backward, and its coefficient rows to the
+    Adam step."""
     w = synth.tiny_scene(71, n=800, width=96, height=72, f=80.0,
                          log_scale_mu=-2.0)
+    w.gaussians = synth.with_sh(w.gaussians, 3, degree, 0.05)
     c = w.cameras[0]
     w.cameras = [c, synth.Camera(c.R, (c.t + np.array([0.05, 0.0, 0.02])
                                        ).astype(np.float32),
@@ -101,7 +105,7 @@ def test_window_graph_replays_match_eager_calls():
     # The capture enqueued nothing: the state is untouched.
     assert torch.equal(st["params"].data, starts[0]["params"])
     for i in range(3):
-        print("case window replay", i, flush=True)
+        print("case window replay", degree, i, flush=True)
         _restore(st, starts[i])
         g.run(stream)
         torch.cuda.synchronize()
