@@ -138,6 +138,19 @@ struct View {
   bool ok;
 };
 
+// A camera record in the constant address space (read-only for the whole
+// launch), copied field by field.
+using ConstCamera = const __attribute__((address_space(4))) gs_camera;
+__device__ inline gs_camera load_camera(ConstCamera* c) {
+  gs_camera r;
+  for (int i = 0; i < 9; ++i) r.R[i] = c->R[i];
+  for (int i = 0; i < 3; ++i) r.t[i] = c->t[i];
+  r.fx = c->fx; r.fy = c->fy; r.cx = c->cx; r.cy = c->cy;
+  r.near_z = c->near_z;
+  r.width = c->width; r.height = c->height; r.pad_ = 0;
+  return r;
+}
+
 __device__ inline double T_dot(const double* Trow, const double* Sig, int j) {
   return Trow[0] * Sig[j] + Trow[1] * Sig[3 + j] + Trow[2] * Sig[6 + j];
 }
@@ -394,18 +407,29 @@ __global__ __launch_bounds__(256) void k_project_bwd(ProjBwdArgs a) {
   const double mx = a.mean[g], my = a.mean[cap + g], mz = a.mean[2 * cap + g];
   double dmu[3] = {0, 0, 0};
   double dS[6] = {0, 0, 0, 0, 0, 0};   // dSigma + dSigma^T, upper triangle
+  // The camera records are read through the constant address space: the
+  // view index is uniform, so they arrive by scalar loads (a generic pointer
+  // would take vector loads, the loop's stores keeping the compiler from
+  // proving them read-only).
+  ConstCamera* cams = (ConstCamera*)a.cams;
   for (int k = 0; k < a.V; ++k) {
     const size_t slot = (size_t)k * cap + g;
-    if (a.tiles[slot] == 0) continue;
+    // Every load of the view first, then one test: a slot with no tiles or
+    // an all-zero gradient has nothing to add (and nothing to clear).
+    const int binned = a.tiles[slot];
     float* gk = a.grad2d + (size_t)k * 5 * cap + g;
-    const double dpx = gk[0], dpy = gk[cap], dA = gk[2 * (size_t)cap],
-                 dB = gk[3 * (size_t)cap], dC = gk[4 * (size_t)cap];
+    const float f0 = gk[0], f1 = gk[cap], f2 = gk[2 * (size_t)cap],
+                f3 = gk[3 * (size_t)cap], f4 = gk[4 * (size_t)cap];
+    const gs_camera cam = load_camera(cams + k);
+    // (Bitwise, not short-circuit: the loads must not wait on one another.)
+    if ((binned == 0) | ((f0 == 0.f) & (f1 == 0.f) & (f2 == 0.f) &
+                         (f3 == 0.f) & (f4 == 0.f)))
+      continue;
     gk[0] = 0.f; gk[cap] = 0.f; gk[2 * (size_t)cap] = 0.f;
     gk[3 * (size_t)cap] = 0.f; gk[4 * (size_t)cap] = 0.f;
-    if (dpx == 0.0 && dpy == 0.0 && dA == 0.0 && dB == 0.0 && dC == 0.0)
-      continue;
+    const double dpx = f0, dpy = f1, dA = f2, dB = f3, dC = f4;
     View P;
-    make_view_grad(a.cams[k], mx, my, mz, Sig, shape_ok, P);
+    make_view_grad(cam, mx, my, mz, Sig, shape_ok, P);
     if (!P.ok) continue;
     // Conic -> dilated screen covariance (symmetric matrix gradient).
     const double Q[4] = {P.A, P.B, P.B, P.C};
