@@ -412,16 +412,27 @@ __global__ __launch_bounds__(256) void k_project_bwd(ProjBwdArgs a) {
   // would take vector loads, the loop's stores keeping the compiler from
   // proving them read-only).
   ConstCamera* cams = (ConstCamera*)a.cams;
+  // Each view's tile count and five gradients are loaded one view ahead,
+  // so their latency overlaps the previous view's chain.
+  int nx_binned = 0;
+  float nx[5] = {0.f, 0.f, 0.f, 0.f, 0.f};
+  if (a.V > 0) {
+    nx_binned = a.tiles[g];
+    for (int i = 0; i < 5; ++i) nx[i] = a.grad2d[(size_t)i * cap + g];
+  }
   for (int k = 0; k < a.V; ++k) {
-    const size_t slot = (size_t)k * cap + g;
-    // Every load of the view first, then one test: a slot with no tiles or
-    // an all-zero gradient has nothing to add (and nothing to clear).
-    const int binned = a.tiles[slot];
+    const int binned = nx_binned;
+    const float f0 = nx[0], f1 = nx[1], f2 = nx[2], f3 = nx[3], f4 = nx[4];
+    if (k + 1 < a.V) {
+      nx_binned = a.tiles[(size_t)(k + 1) * cap + g];
+      const float* gn = a.grad2d + (size_t)(k + 1) * 5 * cap + g;
+      for (int i = 0; i < 5; ++i) nx[i] = gn[(size_t)i * cap];
+    }
     float* gk = a.grad2d + (size_t)k * 5 * cap + g;
-    const float f0 = gk[0], f1 = gk[cap], f2 = gk[2 * (size_t)cap],
-                f3 = gk[3 * (size_t)cap], f4 = gk[4 * (size_t)cap];
     const gs_camera cam = load_camera(cams + k);
-    // (Bitwise, not short-circuit: the loads must not wait on one another.)
+    // One test: a slot with no tiles or an all-zero gradient has nothing to
+    // add (and nothing to clear).  (Bitwise, not short-circuit: the loads
+    // must not wait on one another.)
     if ((binned == 0) | ((f0 == 0.f) & (f1 == 0.f) & (f2 == 0.f) &
                          (f3 == 0.f) & (f4 == 0.f)))
       continue;
