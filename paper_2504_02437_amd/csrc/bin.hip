@@ -153,19 +153,41 @@ struct WaveOwners {
   uint32_t g[64], d[64];
 };
 
-__device__ inline void load_owner(const ScatterArgs& a, int k, int g, int& cnt,
-                                  int& x0, int& y0, int& w, uint32_t& dbits) {
-  cnt = 0; x0 = 0; y0 = 0; w = 1; dbits = 0;
-  const int n = min(*a.n_dev, a.cap);
-  if (g >= n) return;
-  const size_t slot = (size_t)k * a.cap + g;
-  cnt = a.tiles[slot];
-  if (cnt <= 0) { cnt = 0; return; }
+// The binned tile box of (view k, Gaussian g) among the n live ones: its
+// tile count (0 when g is not live or not binned), tile columns [tx0, tx1],
+// rows [ty0, ty1] and depth bits.  The three loads are issued together from
+// an index clamped into the arrays and the result selected afterwards, so a
+// thread's owners cost one memory round trip, not a chain of two (tile count,
+// then box and depth); tile is 8, 16 or 32, a shift.
+struct OwnerBox {
+  int cnt, tx0, tx1, ty0, ty1;
+  uint32_t dbits;
+};
+
+__device__ inline OwnerBox load_box(const ScatterArgs& a, int n, int k, int g,
+                                    int tsh) {
+  const bool live = g < n;
+  const size_t slot = (size_t)k * a.cap + (live ? g : 0);
+  const int c = a.tiles[slot];
   const int2 rb = a.rbox[slot];
-  x0 = (rb.x & 0xffff) / a.tile;
-  w = (rb.x >> 16) / a.tile - x0 + 1;
-  y0 = (rb.y & 0xffff) / a.tile;
-  dbits = __float_as_uint(a.depth[slot]);
+  const uint32_t d = __float_as_uint(a.depth[slot]);
+  const bool any = live && c > 0;
+  OwnerBox o;
+  o.cnt = any ? c : 0;
+  o.tx0 = any ? (rb.x & 0xffff) >> tsh : 0;
+  o.tx1 = any ? (rb.x >> 16) >> tsh : 0;
+  o.ty0 = any ? (rb.y & 0xffff) >> tsh : 0;
+  o.ty1 = any ? (rb.y >> 16) >> tsh : 0;
+  o.dbits = any ? d : 0u;
+  return o;
+}
+
+__device__ inline void load_owner(const ScatterArgs& a, int n, int k, int g,
+                                  int tsh, int& cnt, int& x0, int& y0, int& w,
+                                  uint32_t& dbits) {
+  const OwnerBox o = load_box(a, n, k, g, tsh);
+  cnt = o.cnt; x0 = o.tx0; y0 = o.ty0; w = o.tx1 - o.tx0 + 1;
+  dbits = o.dbits;
 }
 
 // Orders one wave's LDS accesses before and after this point.  The owner
@@ -224,14 +246,17 @@ __global__ __launch_bounds__(256) void k_chunk_count(ScatterArgs a) {
   __syncthreads();
   const int g0 = blockIdx.x * 256 * GPT;
   const int n = min(*a.n_dev, a.cap);
+  const int tsh = __builtin_ctz(a.tile);
+  // Every sub-chunk's loads first (their latencies overlap), then the adds.
+  OwnerBox o[GPT];
+#pragma unroll
+  for (int sub = 0; sub < GPT; ++sub)
+    o[sub] = load_box(a, n, k, g0 + sub * 256 + tid, tsh);
+#pragma unroll
   for (int sub = 0; sub < GPT; ++sub) {
-    const int g = g0 + sub * 256 + tid;
-    if (g >= n) continue;
-    const size_t slot = (size_t)k * a.cap + g;
-    if (a.tiles[slot] <= 0) continue;
-    const int2 rb = a.rbox[slot];
-    const int tx0 = (rb.x & 0xffff) / a.tile, tx1 = (rb.x >> 16) / a.tile;
-    const int ty0 = (rb.y & 0xffff) / a.tile, ty1 = (rb.y >> 16) / a.tile;
+    if (o[sub].cnt <= 0) continue;
+    const int tx0 = o[sub].tx0, tx1 = o[sub].tx1;
+    const int ty0 = o[sub].ty0, ty1 = o[sub].ty1;
     atomicAdd(&grid[ty0 * stride + tx0], 1);
     atomicAdd(&grid[ty0 * stride + tx1 + 1], -1);
     atomicAdd(&grid[(ty1 + 1) * stride + tx0], -1);
@@ -342,17 +367,32 @@ __global__ __launch_bounds__(256) void k_scatter_chunks(ScatterArgs a) {
   const int nb = a.Tx * a.Ty;
   const uint32_t* C = a.chunk_counts + ((size_t)k * a.nch + chunk) * nb;
   const uint32_t* start = a.cursor + (size_t)k * nb;
-  for (int i = tid; i < nb; i += 256) bins[i] = start[i] + C[i];
-  __syncthreads();
   const int g0 = chunk * 256 * GPT;
+  const int n = min(*a.n_dev, a.cap);
+  const int tsh = __builtin_ctz(a.tile);
   // The owners of all GPT sub-chunks are loaded up front, so their latencies
-  // overlap.
+  // overlap each other and the bins' set-up.
   int cnt[GPT], x0[GPT], y0[GPT], w[GPT];
   uint32_t d[GPT];
 #pragma unroll
   for (int sub = 0; sub < GPT; ++sub)
-    load_owner(a, k, g0 + sub * 256 + tid, cnt[sub], x0[sub], y0[sub], w[sub],
-               d[sub]);
+    load_owner(a, n, k, g0 + sub * 256 + tid, tsh, cnt[sub], x0[sub], y0[sub],
+               w[sub], d[sub]);
+  // The bins in groups of four per thread, each group's loads issued before
+  // the first is used (clamped indices keep them in bounds).
+  for (int i0 = tid; i0 < nb; i0 += 4 * 256) {
+    uint32_t sv[4], cv[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int i = min(i0 + u * 256, nb - 1);
+      sv[u] = start[i];
+      cv[u] = C[i];
+    }
+#pragma unroll
+    for (int u = 0; u < 4; ++u)
+      if (i0 + u * 256 < nb) bins[i0 + u * 256] = sv[u] + cv[u];
+  }
+  __syncthreads();
 #pragma unroll
   for (int sub = 0; sub < GPT; ++sub) {
     const int g = g0 + sub * 256 + tid;
@@ -374,7 +414,8 @@ __global__ __launch_bounds__(256) void k_scatter_global(ScatterArgs a) {
   const int g = blockIdx.x * 256 + tid;
   int cnt, x0, y0, w;
   uint32_t d;
-  load_owner(a, k, g, cnt, x0, y0, w, d);
+  load_owner(a, min(*a.n_dev, a.cap), k, g, __builtin_ctz(a.tile), cnt, x0, y0,
+             w, d);
   uint32_t* cur = a.cursor + (size_t)k * a.Tx * a.Ty;
   wave_enumerate(owners[wv], lane, cnt, x0, y0, w, (uint32_t)g, d, a.Tx,
                  [&](int t, uint32_t gg, uint32_t dd) {
