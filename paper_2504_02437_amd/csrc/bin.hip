@@ -64,7 +64,7 @@ __global__ __launch_bounds__(kScanThreads) void k_tile_count(CountArgs a) {
 }
 
 struct RangeArgs {
-  uint32_t* counts;   // in: counts; out: range starts
+  uint32_t* counts;   // tile counts (read only)
   uint32_t* ranges;
   Counters* ctr;
   int V, Tx, Ty;
@@ -72,54 +72,66 @@ struct RangeArgs {
 };
 
 // One workgroup per view: exclusive scan of the view's tile counts, offset by
-// the totals of the preceding views (summed here from their counts).
+// the totals of the preceding views (summed here from their counts), into
+// the ranges.  The counts are left as they are: the other views' workgroups
+// read them too.  The totals take four loads in flight per thread; the scan
+// is a shuffle scan per wave plus the preceding waves' totals, so the
+// workgroup meets at one barrier.
 __global__ __launch_bounds__(kScanThreads) void k_tile_ranges(RangeArgs a) {
-  __shared__ long long part[kScanThreads];
-  __shared__ long long red[2][kScanThreads / 64];
-  const int k = blockIdx.x, tid = threadIdx.x;
+  constexpr int kWaves = kScanThreads / 64;
+  __shared__ long long red[2][kWaves];
+  __shared__ long long wsum[kWaves];
+  const int k = blockIdx.x, tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
   const int tiles = a.Tx * a.Ty;
+  const long long all = (long long)a.V * tiles, before = (long long)k * tiles;
   long long base = 0, total = 0;
-  for (long long i = tid; i < (long long)a.V * tiles; i += kScanThreads) {
-    const long long v = a.counts[i];
-    total += v;
-    if (i < (long long)k * tiles) base += v;
+  for (long long i0 = tid; i0 < all; i0 += 4LL * kScanThreads) {
+    uint32_t v[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const long long i = i0 + (long long)u * kScanThreads;
+      v[u] = i < all ? a.counts[i] : 0u;
+    }
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      total += v[u];
+      if (i0 + (long long)u * kScanThreads < before) base += v[u];
+    }
   }
   for (int off = 32; off > 0; off >>= 1) {
     base += __shfl_down(base, off, 64);
     total += __shfl_down(total, off, 64);
   }
-  if ((tid & 63) == 0) {
-    red[0][tid >> 6] = base;
-    red[1][tid >> 6] = total;
-  }
-  __syncthreads();
-  base = 0;
-  total = 0;
-  for (int i = 0; i < kScanThreads / 64; ++i) {
-    base += red[0][i];
-    total += red[1][i];
-  }
-  __syncthreads();
+  // This thread's run of the view's tiles, scanned within the wave.
   const int per = (tiles + kScanThreads - 1) / kScanThreads;
   const int t0 = tid * per, t1 = min(tiles, t0 + per);
   uint32_t* c = a.counts + (size_t)k * tiles;
   long long local = 0;
   for (int t = t0; t < t1; ++t) local += c[t];
-  part[tid] = local;
-  __syncthreads();
-  for (int off = 1; off < kScanThreads; off <<= 1) {
-    const long long v = tid >= off ? part[tid - off] : 0;
-    __syncthreads();
-    part[tid] += v;
-    __syncthreads();
+  long long incl = local;
+  for (int off = 1; off < 64; off <<= 1) {
+    const long long y = __shfl_up(incl, off, 64);
+    if (lane >= off) incl += y;
   }
-  long long run = base + part[tid] - local;
+  if (lane == 0) {
+    red[0][w] = base;
+    red[1][w] = total;
+  }
+  if (lane == 63) wsum[w] = incl;
+  __syncthreads();
+  base = 0;
+  total = 0;
+  long long before_w = 0;
+  for (int i = 0; i < kWaves; ++i) {
+    base += red[0][i];
+    total += red[1][i];
+    if (i < w) before_w += wsum[i];
+  }
+  long long run = base + before_w + incl - local;
   uint32_t* r = a.ranges + 2 * (size_t)k * tiles;
   for (int t = t0; t < t1; ++t) {
-    const uint32_t cnt = c[t];
     r[2 * t] = (uint32_t)run;
-    c[t] = (uint32_t)run;
-    run += cnt;
+    run += c[t];
     r[2 * t + 1] = (uint32_t)run;
   }
   if (k == 0 && tid == 0) {
@@ -134,12 +146,14 @@ struct ScatterArgs {
   const int32_t* tiles;
   const int32_t* n_dev;
   int cap, tile, Tx, Ty;
-  uint32_t* cursor;              // range starts (per-key atomics: cursors)
+  uint32_t* cursor;              // tile counts (the per-key-atomic scatter
+                                 // counts them down)
   uint32_t* chunk_counts;        // [V][chunks][tiles]
   unsigned long long* keys;
   long long key_cap;
   int nch;                       // chunks per view (chunked scatter)
-  const uint32_t* ranges;        // final ranges, for the tile order
+  const uint32_t* ranges;        // final ranges: the tiles' starts, and the
+                                 // tile order
   uint32_t* order;
   int order_n;                   // tiles to order in the scatter (0: none)
 };
@@ -366,7 +380,7 @@ __global__ __launch_bounds__(256) void k_scatter_chunks(ScatterArgs a) {
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
   const int nb = a.Tx * a.Ty;
   const uint32_t* C = a.chunk_counts + ((size_t)k * a.nch + chunk) * nb;
-  const uint32_t* start = a.cursor + (size_t)k * nb;
+  const uint32_t* range = a.ranges + 2 * (size_t)k * nb;   // [start, end)
   const int g0 = chunk * 256 * GPT;
   const int n = min(*a.n_dev, a.cap);
   const int tsh = __builtin_ctz(a.tile);
@@ -385,7 +399,7 @@ __global__ __launch_bounds__(256) void k_scatter_chunks(ScatterArgs a) {
 #pragma unroll
     for (int u = 0; u < 4; ++u) {
       const int i = min(i0 + u * 256, nb - 1);
-      sv[u] = start[i];
+      sv[u] = range[2 * i];
       cv[u] = C[i];
     }
 #pragma unroll
@@ -416,10 +430,14 @@ __global__ __launch_bounds__(256) void k_scatter_global(ScatterArgs a) {
   uint32_t d;
   load_owner(a, min(*a.n_dev, a.cap), k, g, __builtin_ctz(a.tile), cnt, x0, y0,
              w, d);
+  // Each tile's count, taken down by one per key, numbers its keys within
+  // the tile's range.
   uint32_t* cur = a.cursor + (size_t)k * a.Tx * a.Ty;
+  const uint32_t* range = a.ranges + 2 * (size_t)k * a.Tx * a.Ty;
   wave_enumerate(owners[wv], lane, cnt, x0, y0, w, (uint32_t)g, d, a.Tx,
                  [&](int t, uint32_t gg, uint32_t dd) {
-                   const uint32_t pos = atomicAdd(&cur[t], 1u);
+                   const uint32_t pos =
+                       range[2 * t] + atomicSub(&cur[t], 1u) - 1u;
                    if ((long long)pos < a.key_cap)
                      a.keys[pos] = ((unsigned long long)dd << 32) | gg;
                  });

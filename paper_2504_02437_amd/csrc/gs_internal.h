@@ -84,7 +84,7 @@ struct gs_workspace {
   int32_t* diff;         // [V][Ty + 1][Tx + 1] tile-coverage difference grid
                          // (grids too large for the chunked binning)
   uint32_t* ranges;      // [V * Ty * Tx][2]
-  uint32_t* cursor;      // [V * Ty * Tx] tile counts, then range starts
+  uint32_t* cursor;      // [V * Ty * Tx] tile counts
   uint32_t* tile_order;  // [V * Ty * Tx] tiles by descending key count (the
                          // per-tile kernels take block b -> tile order[b])
   double* tile_loss;     // [V * Ty * Tx][2] fused L1 loss and squared error
