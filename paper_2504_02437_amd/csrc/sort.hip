@@ -315,11 +315,17 @@ __device__ void sort_tile(const SortArgs& a, int t, long long s, int L, int nw,
   const int base = tid * E;
   uint32_t dhi[E], glo[E];
   uint32_t dmin = 0xffffffffu, dmax = 0u, gmin = 0xffffffffu, gmax = 0u;
+  // Positions clamped into the segment (L >= 1), so every load is valid
+  // and a lane's E loads are issued together instead of one guarded load
+  // and wait after another; padding then takes 0.
+  unsigned long long kin[E];
+#pragma unroll
+  for (int e = 0; e < E; ++e) kin[e] = a.keys_in[s + min(base + e, L - 1)];
 #pragma unroll
   for (int e = 0; e < E; ++e) {
     const int p = base + e;
     const bool real = active && p < L;
-    const unsigned long long k = real ? a.keys_in[s + p] : 0ull;
+    const unsigned long long k = real ? kin[e] : 0ull;
     dhi[e] = (uint32_t)(k >> 32);
     glo[e] = (uint32_t)k;
     if (real) {
