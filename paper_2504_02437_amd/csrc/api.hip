@@ -246,6 +246,34 @@ int planar_checked(const gs_params* params, float lambda, float floor_,
   return GS_OK;
 }
 
+int project_and_bin_checked(gs_workspace* ws, const gs_params* params,
+                            const gs_camera* cams, const gs_settings* s,
+                            void* stream, bool shape_done) {
+  g_err[0] = 0;
+  if (int rc = check_ws(ws)) return rc;
+  if (int rc = validate_params(params, "params")) return rc;
+  if (int rc = validate_settings(s)) return rc;
+  if (!params->n_dev) { set_error("params.n_dev is NULL"); return GS_E_INVALID; }
+  if (!cams) { set_error("cams is NULL"); return GS_E_INVALID; }
+  if (s->tile != ws->geo.tile) {
+    set_error("settings.tile %d differs from the workspace's %d", s->tile,
+              ws->geo.tile);
+    return GS_E_INVALID;
+  }
+  if (params->capacity != ws->geo.capacity) {
+    set_error("params.capacity %d differs from the workspace's %d",
+              params->capacity, ws->geo.capacity);
+    return GS_E_CAPACITY;
+  }
+  hipStream_t st = (hipStream_t)stream;
+  hipError_t e = launch_project(ws, params, cams, s, st, shape_done);
+  if (e != hipSuccess) return finish(e, "project");
+  e = launch_sh_colour(ws, params, cams, st);
+  if (e != hipSuccess) return finish(e, "view-dependent colour");
+  ws->box_alpha_min = (s->flags & GS_FLAG_FULL_BOX) ? 0.f : s->alpha_min;
+  return finish(launch_bin(ws, params, st), "bin");
+}
+
 int adam_checked(gs_params* params, const gs_params* grad, gs_params* m,
                  gs_params* v, const float* lr, float beta1, float beta2,
                  float eps, int32_t step, const int32_t* step_dev,
@@ -388,29 +416,7 @@ int gs_workspace_get_view(const gs_workspace* ws, gs_workspace_view* out) {
 int gs_project_and_bin(gs_workspace* ws, const gs_params* params,
                        const gs_camera* cams, const gs_settings* s,
                        void* stream) {
-  g_err[0] = 0;
-  if (int rc = check_ws(ws)) return rc;
-  if (int rc = validate_params(params, "params")) return rc;
-  if (int rc = validate_settings(s)) return rc;
-  if (!params->n_dev) { set_error("params.n_dev is NULL"); return GS_E_INVALID; }
-  if (!cams) { set_error("cams is NULL"); return GS_E_INVALID; }
-  if (s->tile != ws->geo.tile) {
-    set_error("settings.tile %d differs from the workspace's %d", s->tile,
-              ws->geo.tile);
-    return GS_E_INVALID;
-  }
-  if (params->capacity != ws->geo.capacity) {
-    set_error("params.capacity %d differs from the workspace's %d",
-              params->capacity, ws->geo.capacity);
-    return GS_E_CAPACITY;
-  }
-  hipStream_t st = (hipStream_t)stream;
-  hipError_t e = launch_project(ws, params, cams, s, st);
-  if (e != hipSuccess) return finish(e, "project");
-  e = launch_sh_colour(ws, params, cams, st);
-  if (e != hipSuccess) return finish(e, "view-dependent colour");
-  ws->box_alpha_min = (s->flags & GS_FLAG_FULL_BOX) ? 0.f : s->alpha_min;
-  return finish(launch_bin(ws, params, st), "bin");
+  return project_and_bin_checked(ws, params, cams, s, stream, false);
 }
 
 int gs_sort_tile_keys(gs_workspace* ws, const gs_settings* s, void* stream) {

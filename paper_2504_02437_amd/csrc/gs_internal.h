@@ -113,9 +113,10 @@ int validate_params(const gs_params* p, const char* what);
 
 // Launchers implemented by the kernel translation units.  They return a
 // hipError_t from the launch (hipGetLastError).
+// shape_done: the per-Gaussian shapes of p are formed already (shape.h).
 hipError_t launch_project(gs_workspace* ws, const gs_params* p,
                           const gs_camera* cams, const gs_settings* s,
-                          hipStream_t st);
+                          hipStream_t st, bool shape_done = false);
 struct PlanarJob;      // tails.h
 struct L1ReduceJob;    // tails.h
 // l1: the fused L1 term's tile-loss reduction as one workgroup appended to
@@ -200,6 +201,11 @@ int project_bwd_checked(gs_workspace* ws, const gs_params* params,
 // gs_planar_reg's argument checks; on success *job holds its launch.
 int planar_checked(const gs_params* params, float lambda, float floor_,
                    gs_params* grad, double* loss_dev, PlanarJob* job);
+// gs_project_and_bin with its argument checks; shape_done: the per-Gaussian
+// shapes are formed already (the window graph's clearing kernel does it).
+int project_and_bin_checked(gs_workspace* ws, const gs_params* params,
+                            const gs_camera* cams, const gs_settings* s,
+                            void* stream, bool shape_done);
 // gs_adam with its argument checks, the bias passed to launch_adam.
 int adam_checked(gs_params* params, const gs_params* grad, gs_params* m,
                  gs_params* v, const float* lr, float beta1, float beta2,

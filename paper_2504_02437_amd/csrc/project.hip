@@ -20,6 +20,7 @@
 
 #include "admit.h"
 #include "gs_internal.h"
+#include "shape.h"
 #include "tails.h"
 
 namespace gs {
@@ -81,47 +82,6 @@ __device__ inline void render_box(const Record& R, int iu0, int iu1, int iv0,
     ru0 = rv0 = kEmptyPair;
     ru1 = rv1 = 0;
   }
-}
-
-// View-independent part of Eq. 1: s = exp(l), R(q / |q|), M = R diag(s),
-// Sigma = M M^T.
-struct Shape {
-  double s[3];
-  double qn[4];
-  double qnorm;
-  double R[9];
-  double M[9];
-  double Sig[9];
-  bool ok;
-};
-
-__device__ inline void make_shape(const float* lsc, const float* quat, int cap,
-                                  int g, Shape& S) {
-  for (int j = 0; j < 3; ++j) S.s[j] = exp((double)lsc[j * cap + g]);
-  double q[4];
-  for (int j = 0; j < 4; ++j) q[j] = (double)quat[j * cap + g];
-  const double qq = ((q[0] * q[0] + q[1] * q[1]) + q[2] * q[2]) + q[3] * q[3];
-  S.qnorm = sqrt(qq);
-  S.ok = S.qnorm > 0.0 && isfinite(S.qnorm) && isfinite(S.s[0]) &&
-         isfinite(S.s[1]) && isfinite(S.s[2]);
-  for (int j = 0; j < 4; ++j) S.qn[j] = q[j] / S.qnorm;
-  const double w = S.qn[0], x = S.qn[1], y = S.qn[2], z = S.qn[3];
-  double* R = S.R;
-  R[0] = 1.0 - 2.0 * (y * y + z * z);
-  R[1] = 2.0 * (x * y - w * z);
-  R[2] = 2.0 * (x * z + w * y);
-  R[3] = 2.0 * (x * y + w * z);
-  R[4] = 1.0 - 2.0 * (x * x + z * z);
-  R[5] = 2.0 * (y * z - w * x);
-  R[6] = 2.0 * (x * z - w * y);
-  R[7] = 2.0 * (y * z + w * x);
-  R[8] = 1.0 - 2.0 * (x * x + y * y);
-  for (int i = 0; i < 3; ++i)
-    for (int j = 0; j < 3; ++j) S.M[3 * i + j] = R[3 * i + j] * S.s[j];
-  for (int i = 0; i < 3; ++i)
-    for (int j = 0; j < 3; ++j)
-      S.Sig[3 * i + j] = (S.M[3 * i] * S.M[3 * j] + S.M[3 * i + 1] * S.M[3 * j + 1]) +
-                         S.M[3 * i + 2] * S.M[3 * j + 2];
 }
 
 // View-dependent part of Eq. 2 for one camera.
@@ -259,23 +219,8 @@ __device__ inline void make_view_grad(const gs_camera& cam, double mx,
   P.C = P.a * idet;
 }
 
-// Upper-triangle entries of the symmetric 3x3 covariance.
-constexpr int kSigIdx[6] = {0, 1, 2, 4, 5, 8};
-
-__global__ __launch_bounds__(256) void k_shape(ProjArgs a) {
-  const int g = blockIdx.x * 256 + threadIdx.x;
-  const int n = min(*a.n_dev, a.cap);
-  if (g >= n) return;
-  const int cap = a.cap;
-  Shape S;
-  make_shape(a.lsc, a.quat, cap, g, S);
-  for (int j = 0; j < 6; ++j) a.sig[(size_t)j * cap + g] = S.Sig[kSigIdx[j]];
-  // A failed shape (zero or non-finite quaternion, non-finite scale) is
-  // culled in every view; a valid one has a finite, non-negative Sigma_00.
-  if (!S.ok) a.sig[g] = NAN;
-  const float op = (float)(1.0 / (1.0 + exp(-(double)a.opl[g])));
-  a.op[g] = op;
-  a.lop[g] = (float)log2((double)op);
+__global__ __launch_bounds__(256) void k_shape(ShapeJob j) {
+  shape_one(j, blockIdx.x * 256 + threadIdx.x);
 }
 
 __global__ __launch_bounds__(256) void k_project(ProjArgs a) {
@@ -547,9 +492,19 @@ __global__ __launch_bounds__(256) void k_project_bwd(ProjBwdArgs a) {
 
 }  // namespace
 
+ShapeJob shape_job(const gs_workspace* ws, const gs_params* p) {
+  ShapeJob j;
+  j.lsc = p->log_scale; j.quat = p->quat; j.opl = p->opacity_logit;
+  j.n_dev = p->n_dev; j.cap = p->capacity;
+  j.sig = ws->shape;
+  j.op = (float*)(ws->shape + 6 * (size_t)p->capacity);
+  j.lop = j.op + p->capacity;
+  return j;
+}
+
 hipError_t launch_project(gs_workspace* ws, const gs_params* p,
                           const gs_camera* cams, const gs_settings* s,
-                          hipStream_t st) {
+                          hipStream_t st, bool shape_done) {
   ProjArgs a;
   a.mean = p->mean; a.lsc = p->log_scale; a.quat = p->quat;
   a.opl = p->opacity_logit; a.rgb = p->rgb; a.n_dev = p->n_dev;
@@ -565,7 +520,9 @@ hipError_t launch_project(gs_workspace* ws, const gs_params* p,
   a.lop = a.op + p->capacity;
   a.chunks = (p->capacity + 255) / 256;
   if (a.chunks <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_shape, dim3(a.chunks), dim3(256), 0, st, a);
+  if (!shape_done)
+    hipLaunchKernelGGL(k_shape, dim3(a.chunks), dim3(256), 0, st,
+                       shape_job(ws, p));
   const long long blocks = (long long)((a.chunks + 7) / 8) * 8 * a.V;
   if (blocks > 0x7fffffff) return hipErrorInvalidConfiguration;
   hipLaunchKernelGGL(k_project, dim3((unsigned)blocks), dim3(256), 0, st, a);

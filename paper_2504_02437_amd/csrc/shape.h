@@ -1,0 +1,89 @@
+// The view-independent part of the projection (Eq. 1), per Gaussian: the
+// 3D covariance from the log-scales and the normalised quaternion, and the
+// opacity with its base-2 logarithm.  Formed once per Gaussian before the
+// per-view projection reads it: by k_shape, or, in the window graph, by the
+// first workgroups of the kernel that clears the iteration.
+#pragma once
+
+#include <math.h>
+
+#include "gs_internal.h"
+
+namespace gs {
+
+// View-independent part of Eq. 1: s = exp(l), R(q / |q|), M = R diag(s),
+// Sigma = M M^T.
+struct Shape {
+  double s[3];
+  double qn[4];
+  double qnorm;
+  double R[9];
+  double M[9];
+  double Sig[9];
+  bool ok;
+};
+
+__device__ inline void make_shape(const float* lsc, const float* quat, int cap,
+                                  int g, Shape& S) {
+  for (int j = 0; j < 3; ++j) S.s[j] = exp((double)lsc[j * cap + g]);
+  double q[4];
+  for (int j = 0; j < 4; ++j) q[j] = (double)quat[j * cap + g];
+  const double qq = ((q[0] * q[0] + q[1] * q[1]) + q[2] * q[2]) + q[3] * q[3];
+  S.qnorm = sqrt(qq);
+  S.ok = S.qnorm > 0.0 && isfinite(S.qnorm) && isfinite(S.s[0]) &&
+         isfinite(S.s[1]) && isfinite(S.s[2]);
+  for (int j = 0; j < 4; ++j) S.qn[j] = q[j] / S.qnorm;
+  const double w = S.qn[0], x = S.qn[1], y = S.qn[2], z = S.qn[3];
+  double* R = S.R;
+  R[0] = 1.0 - 2.0 * (y * y + z * z);
+  R[1] = 2.0 * (x * y - w * z);
+  R[2] = 2.0 * (x * z + w * y);
+  R[3] = 2.0 * (x * y + w * z);
+  R[4] = 1.0 - 2.0 * (x * x + z * z);
+  R[5] = 2.0 * (y * z - w * x);
+  R[6] = 2.0 * (x * z - w * y);
+  R[7] = 2.0 * (y * z + w * x);
+  R[8] = 1.0 - 2.0 * (x * x + y * y);
+  for (int i = 0; i < 3; ++i)
+    for (int j = 0; j < 3; ++j) S.M[3 * i + j] = R[3 * i + j] * S.s[j];
+  for (int i = 0; i < 3; ++i)
+    for (int j = 0; j < 3; ++j)
+      S.Sig[3 * i + j] = (S.M[3 * i] * S.M[3 * j] + S.M[3 * i + 1] * S.M[3 * j + 1]) +
+                         S.M[3 * i + 2] * S.M[3 * j + 2];
+}
+
+// Upper-triangle entries of the symmetric 3x3 covariance.
+constexpr int kSigIdx[6] = {0, 1, 2, 4, 5, 8};
+
+// Where the per-Gaussian shape goes: Sigma's upper triangle [6][cap] (FP64),
+// the opacity and its base-2 logarithm [cap] each.
+struct ShapeJob {
+  const float* lsc;
+  const float* quat;
+  const float* opl;
+  const int32_t* n_dev;
+  int cap;
+  double* sig;   // sig[0][g] = NaN: a failed shape
+  float* op;
+  float* lop;
+};
+
+ShapeJob shape_job(const gs_workspace* ws, const gs_params* p);
+
+// Gaussian g (any g: those past the live count do nothing).
+__device__ inline void shape_one(const ShapeJob& j, int g) {
+  const int n = min(*j.n_dev, j.cap);
+  if (g >= n) return;
+  const int cap = j.cap;
+  Shape S;
+  make_shape(j.lsc, j.quat, cap, g, S);
+  for (int i = 0; i < 6; ++i) j.sig[(size_t)i * cap + g] = S.Sig[kSigIdx[i]];
+  // A failed shape (zero or non-finite quaternion, non-finite scale) is
+  // culled in every view; a valid one has a finite, non-negative Sigma_00.
+  if (!S.ok) j.sig[g] = NAN;
+  const float op = (float)(1.0 / (1.0 + exp(-(double)j.opl[g])));
+  j.op[g] = op;
+  j.lop[g] = (float)log2((double)op);
+}
+
+}  // namespace gs

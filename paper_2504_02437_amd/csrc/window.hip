@@ -2,7 +2,8 @@
 // the C ABI (gs_window_build / gs_window_run / gs_window_destroy).
 //
 // The build captures, on the caller's stream, the same calls an eager
-// iteration makes: clear the gradient, loss and squared-error buffers, then
+// iteration makes: clear the gradient, loss and squared-error buffers (the
+// same launch forms the per-Gaussian shapes of the projection), then
 // projection and binning, the per-tile sort, the forward render, the
 // compositing backward with the L1 term fused in (the planar regulariser's
 // gradient in extra workgroups of the same launch), the projection backward
@@ -15,6 +16,7 @@
 #include <new>
 
 #include "gs_internal.h"
+#include "shape.h"
 #include "tails.h"
 
 struct gs_window {
@@ -39,19 +41,27 @@ constexpr int kClearPer = 4;   // elements per thread
 struct ClearArgs {
   uint32_t* p[kClearJobs];
   size_t n[kClearJobs];
-  int first[kClearJobs + 1];   // first workgroup of each row
+  int first[kClearJobs + 1];   // first clearing workgroup of each row
   int jobs;
   int32_t* step;               // advanced by one when not NULL
+  // The first shape_blocks workgroups form the per-Gaussian shapes of the
+  // projection (256 Gaussians each) instead of clearing.
+  int shape_blocks;
+  ShapeJob shape;
 };
 
 __global__ __launch_bounds__(256) void k_clear_iteration(ClearArgs a) {
   if (a.step && blockIdx.x == 0 && threadIdx.x == 0) *a.step += 1;
+  if ((int)blockIdx.x < a.shape_blocks) {
+    shape_one(a.shape, (int)blockIdx.x * 256 + (int)threadIdx.x);
+    return;
+  }
+  const int b = (int)blockIdx.x - a.shape_blocks;
   int j = 0;
-  while (j + 1 < a.jobs && (int)blockIdx.x >= a.first[j + 1]) ++j;
+  while (j + 1 < a.jobs && b >= a.first[j + 1]) ++j;
   uint32_t* p = a.p[j];
   const size_t n = a.n[j];
-  const size_t base =
-      (size_t)(blockIdx.x - a.first[j]) * 256 * kClearPer + threadIdx.x;
+  const size_t base = (size_t)(b - a.first[j]) * 256 * kClearPer + threadIdx.x;
 #pragma unroll
   for (int e = 0; e < kClearPer; ++e) {
     const size_t i = base + (size_t)e * 256;
@@ -85,10 +95,13 @@ hipError_t clear_iteration(const gs_window_desc* d, hipStream_t st) {
   }
   a.first[a.jobs] = (int)blocks;
   if (blocks == 0) {   // nothing to clear; the step count still advances
-    if (!a.step) return hipSuccess;
     a.jobs = 1; a.p[0] = nullptr; a.n[0] = 0; a.first[0] = 0; a.first[1] = 1;
     blocks = 1;
   }
+  a.shape = shape_job(d->ws, &d->params);
+  a.shape_blocks = (d->params.capacity + 255) / 256;
+  blocks += a.shape_blocks;
+  if (blocks > 0x7fffffff) return hipErrorInvalidConfiguration;
   hipLaunchKernelGGL(k_clear_iteration, dim3((unsigned)blocks), dim3(256), 0,
                      st, a);
   return hipGetLastError();
@@ -99,7 +112,9 @@ int enqueue_iteration(const gs_window_desc* d, hipStream_t st) {
   gs_params params = d->params, grad = d->grad, m = d->adam_m, v = d->adam_v;
   int rc = check_hip(clear_iteration(d, st), "clearing the iteration's rows");
   if (rc) return rc;
-  if ((rc = gs_project_and_bin(d->ws, &params, d->cams, &d->settings, st)))
+  // The clearing launch formed the per-Gaussian shapes already.
+  if ((rc = project_and_bin_checked(d->ws, &params, d->cams, &d->settings, st,
+                                    true)))
     return rc;
   if ((rc = gs_sort_tile_keys(d->ws, &d->settings, st))) return rc;
   if ((rc = gs_render_fwd(d->ws, &params, &d->settings, d->out_rgb, d->out_T,
@@ -157,6 +172,12 @@ GS_API int gs_window_build(const gs_window_desc* d, void* stream,
   if (!rc) rc = validate_params(&d->grad, "grad");
   if (!rc) rc = validate_settings(&d->settings);
   if (rc) return rc;
+  // The clearing launch forms the shapes in the workspace's buffer.
+  if (d->params.capacity != d->ws->geo.capacity) {
+    set_error("window: params.capacity %d differs from the workspace's %d",
+              d->params.capacity, d->ws->geo.capacity);
+    return GS_E_CAPACITY;
+  }
   if (d->flags & ~(GS_WINDOW_PLANAR_REG | GS_WINDOW_ADAM)) {
     set_error("window: unknown flags 0x%x", d->flags);
     return GS_E_INVALID;
