@@ -138,6 +138,14 @@ def test_window_graph_build_errors_leave_the_stream_usable():
         with pytest.raises(R.L.GsError, match="lds_batch"):
             _graph(st)
         rast.settings.lds_batch = 256
+        # Parameters of another capacity than the workspace's are refused
+        # before anything is captured.
+        other = R.ParamBuffer.from_gaussians(w.gaussians,
+                                             capacity=params.capacity + 64)
+        st_other = dict(st, params=other, grad=other.zeros_like(),
+                        m=other.zeros_like(), v=other.zeros_like())
+        with pytest.raises(R.L.GsError, match="capacity"):
+            _graph(st_other)
         rast.forward(params)
     torch.cuda.synchronize()
     assert float(rast.T.min()) > 0
