@@ -157,6 +157,7 @@ static int make_layout(const gs_geometry* g, Layout& L, int& tx, int& ty) {
   L.gop = take(cap * 4);
   L.gcol = take(V * 3 * cap * 4);
   L.shape = take(cap * (6 * 8 + 4 + 4));
+  L.camd = take(V * 17 * 8);
   L.counters = take(sizeof(Counters));
   L.total = off;
   return GS_OK;
@@ -216,7 +217,7 @@ int render_bwd_l1_checked(gs_workspace* ws, const gs_params* params,
 
 int project_bwd_checked(gs_workspace* ws, const gs_params* params,
                         const gs_camera* cams, gs_params* grad, void* stream,
-                        const L1ReduceJob* l1) {
+                        const L1ReduceJob* l1, bool cam_table) {
   g_err[0] = 0;
   if (int rc = check_ws(ws)) return rc;
   if (int rc = validate_params(params, "params")) return rc;
@@ -229,7 +230,7 @@ int project_bwd_checked(gs_workspace* ws, const gs_params* params,
   if (int rc = same_layout(params, grad, "grad")) return rc;
   if (int rc = disjoint(params, "params", grad, "grad")) return rc;
   hipStream_t st = (hipStream_t)stream;
-  hipError_t e = launch_project_bwd(ws, params, cams, grad, st, l1);
+  hipError_t e = launch_project_bwd(ws, params, cams, grad, st, l1, cam_table);
   if (e != hipSuccess) return finish(e, "project_bwd");
   return finish(launch_sh_bwd(ws, params, cams, grad, st),
                 "view-dependent colour backward");
@@ -369,6 +370,7 @@ int gs_workspace_create(const gs_geometry* geo, void* device_buffer,
   ws->gop = (float*)(b + L.gop);
   ws->gcol = (float*)(b + L.gcol);
   ws->shape = (double*)(b + L.shape);
+  ws->camd = (double*)(b + L.camd);
   ws->counters = (Counters*)(b + L.counters);
   hipStream_t st = (hipStream_t)stream;
   const size_t V = geo->n_views, cap = geo->capacity;

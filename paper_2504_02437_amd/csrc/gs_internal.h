@@ -21,7 +21,7 @@ struct Layout {
   size_t records, tiles_touched, rbox, depth, diff, ranges, cursor, tile_order,
       tile_loss, chunk_counts,
       keys_unsorted, vals_sorted, keys_sorted, grad2d, gop, gcol, shape,
-      counters, total;
+      camd, counters, total;
 };
 
 // Binning works on chunks of Gaussians of one view (one workgroup each) with
@@ -96,6 +96,8 @@ struct gs_workspace {
   unsigned long long* keys_sorted;
   float* grad2d;         // [V][5][capacity]
   float* gop;            // [capacity] dL/d opacity summed over views
+  double* camd;          // [V][17] FP64 camera constants (shape.h), formed
+                         // by the window graph's clearing launch
   float* gcol;           // [V][3][capacity] dL/d colour per view (used with
                          // view-dependent colour)
   double* shape;         // [6][capacity] 3D covariance (upper triangle) of
@@ -123,7 +125,8 @@ struct L1ReduceJob;    // tails.h
 // the launch (the window graph), or null.
 hipError_t launch_project_bwd(gs_workspace* ws, const gs_params* p,
                               const gs_camera* cams, gs_params* grad,
-                              hipStream_t st, const L1ReduceJob* l1 = nullptr);
+                              hipStream_t st, const L1ReduceJob* l1 = nullptr,
+                              bool cam_table = false);
 hipError_t launch_bin(gs_workspace* ws, const gs_params* p, hipStream_t st);
 hipError_t launch_sort(gs_workspace* ws, const gs_settings* s, hipStream_t st);
 hipError_t launch_render_fwd(gs_workspace* ws, const gs_settings* s,
@@ -194,10 +197,11 @@ int render_bwd_l1_checked(gs_workspace* ws, const gs_params* params,
                          void* stream, const PlanarJob* planar,
                          bool defer_reduce);
 // gs_project_bwd with its argument checks and an optional tile-loss
-// reduction workgroup.
+// reduction workgroup; cam_table: the camera constants come from ws->camd
+// (formed from cams earlier in the same launch sequence).
 int project_bwd_checked(gs_workspace* ws, const gs_params* params,
                         const gs_camera* cams, gs_params* grad, void* stream,
-                        const L1ReduceJob* l1);
+                        const L1ReduceJob* l1, bool cam_table = false);
 // gs_planar_reg's argument checks; on success *job holds its launch.
 int planar_checked(const gs_params* params, float lambda, float floor_,
                    gs_params* grad, double* loss_dev, PlanarJob* job);

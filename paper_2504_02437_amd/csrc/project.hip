@@ -171,23 +171,23 @@ __device__ inline void make_view(const gs_camera& cam, double mx, double my,
 // The view quantities the backward needs, formed with two reciprocals in
 // place of the forward's correctly rounded divisions: the backward only has
 // to be accurate, not reproducible bit for bit.
-__device__ inline void make_view_grad(const gs_camera& cam, double mx,
-                                      double my, double mz, const double* Sig,
+__device__ inline void make_view_grad(const CamD& cam, double mx, double my,
+                                      double mz, const double* Sig,
                                       bool shape_ok, View& P) {
-  for (int i = 0; i < 9; ++i) P.W[i] = (double)cam.R[i];
-  P.fx = (double)cam.fx;
-  P.fy = (double)cam.fy;
+  for (int i = 0; i < 9; ++i) P.W[i] = cam.W[i];
+  P.fx = cam.fx;
+  P.fy = cam.fy;
   const double* W = P.W;
-  P.t[0] = ((W[0] * mx + W[1] * my) + W[2] * mz) + (double)cam.t[0];
-  P.t[1] = ((W[3] * mx + W[4] * my) + W[5] * mz) + (double)cam.t[1];
-  P.t[2] = ((W[6] * mx + W[7] * my) + W[8] * mz) + (double)cam.t[2];
+  P.t[0] = ((W[0] * mx + W[1] * my) + W[2] * mz) + cam.t[0];
+  P.t[1] = ((W[3] * mx + W[4] * my) + W[5] * mz) + cam.t[1];
+  P.t[2] = ((W[6] * mx + W[7] * my) + W[8] * mz) + cam.t[2];
   const double tx = P.t[0], ty = P.t[1], tz = P.t[2];
-  P.ok = isfinite(tx) && isfinite(ty) && isfinite(tz) &&
-         tz > (double)cam.near_z && shape_ok;
+  P.ok = isfinite(tx) && isfinite(ty) && isfinite(tz) && tz > cam.near_z &&
+         shape_ok;
   if (!P.ok) return;
   const double itz = 1.0 / tz;
-  P.limx = 0.65 * (double)cam.width / P.fx;
-  P.limy = 0.65 * (double)cam.height / P.fy;
+  P.limx = cam.limx;
+  P.limy = cam.limy;
   double rx = tx * itz, ry = ty * itz;
   P.clampx = rx > P.limx ? 1 : rx < -P.limx ? -1 : 0;
   P.clampy = ry > P.limy ? 1 : ry < -P.limy ? -1 : 0;
@@ -317,6 +317,7 @@ struct ProjBwdArgs {
   float* d_lsc;
   float* d_quat;
   float* d_opl;
+  const double* camd;   // [V][kCamDoubles] (k_project_bwd<true>)
   // Workgroups past main_blocks reduce the fused L1 term's tile losses.
   int main_blocks;
   L1ReduceJob l1;
@@ -327,6 +328,9 @@ struct ProjBwdArgs {
 // matrix form: for the conic Q = Sigma2D^-1 the symmetric gradient is
 // G2 = -Q dQ Q; for Sigma2D = T Sigma T^T, dSigma = T^T G2 T and
 // dT = 2 G2 T Sigma; Sigma = M M^T gives dM = 2 dSigma M (summed over views).
+// TABLE: the views' FP64 camera constants come from a table formed earlier
+// in the launch sequence (scalar registers, no per-lane conversions).
+template <bool TABLE>
 __global__ __launch_bounds__(256) void k_project_bwd(ProjBwdArgs a) {
   __shared__ double part[4];
   if ((int)blockIdx.x >= a.main_blocks) {   // dispatched last: the tail
@@ -374,7 +378,8 @@ __global__ __launch_bounds__(256) void k_project_bwd(ProjBwdArgs a) {
       for (int i = 0; i < 5; ++i) nx[i] = gn[(size_t)i * cap];
     }
     float* gk = a.grad2d + (size_t)k * 5 * cap + g;
-    const gs_camera cam = load_camera(cams + k);
+    const CamD cam = TABLE ? cam_d_table((ConstDouble*)a.camd + kCamDoubles * k)
+                           : cam_d(load_camera(cams + k));
     // One test: a slot with no tiles or an all-zero gradient has nothing to
     // add (and nothing to clear).  (Bitwise, not short-circuit: the loads
     // must not wait on one another.)
@@ -531,7 +536,8 @@ hipError_t launch_project(gs_workspace* ws, const gs_params* p,
 
 hipError_t launch_project_bwd(gs_workspace* ws, const gs_params* p,
                               const gs_camera* cams, gs_params* grad,
-                              hipStream_t st, const L1ReduceJob* l1) {
+                              hipStream_t st, const L1ReduceJob* l1,
+                              bool cam_table) {
   ProjBwdArgs a;
   a.mean = p->mean; a.lsc = p->log_scale; a.quat = p->quat;
   a.opl = p->opacity_logit; a.n_dev = p->n_dev; a.cap = p->capacity;
@@ -542,9 +548,14 @@ hipError_t launch_project_bwd(gs_workspace* ws, const gs_params* p,
   const int blocks = (p->capacity + 255) / 256;
   a.main_blocks = blocks;
   a.l1 = l1 ? *l1 : L1ReduceJob{};
-  if (blocks + (l1 ? 1 : 0) > 0)
-    hipLaunchKernelGGL(k_project_bwd, dim3(blocks + (l1 ? 1 : 0)), dim3(256),
-                       0, st, a);
+  a.camd = ws->camd;
+  const int nb = blocks + (l1 ? 1 : 0);
+  if (nb > 0) {
+    if (cam_table)
+      hipLaunchKernelGGL(k_project_bwd<true>, dim3(nb), dim3(256), 0, st, a);
+    else
+      hipLaunchKernelGGL(k_project_bwd<false>, dim3(nb), dim3(256), 0, st, a);
+  }
   return hipGetLastError();
 }
 

@@ -1,6 +1,7 @@
 // The view-independent part of the projection (Eq. 1), per Gaussian: the
 // 3D covariance from the log-scales and the normalised quaternion, and the
-// opacity with its base-2 logarithm.  Formed once per Gaussian before the
+// opacity with its base-2 logarithm; and per view the FP64 camera constants
+// of the projection backward.  Formed once per Gaussian before the
 // per-view projection reads it: by k_shape, or, in the window graph, by the
 // first workgroups of the kernel that clears the iteration.
 #pragma once
@@ -84,6 +85,57 @@ __device__ inline void shape_one(const ShapeJob& j, int g) {
   const float op = (float)(1.0 / (1.0 + exp(-(double)j.opl[g])));
   j.op[g] = op;
   j.lop[g] = (float)log2((double)op);
+}
+
+// FP64 camera constants of the projection backward, kCamDoubles per view:
+// the rotation (row-major), the translation, fx, fy, the clamp limits of the
+// projected position and the near-plane depth, each formed exactly as the
+// per-lane code forms it from the camera record.  The window graph's
+// clearing launch writes them (so they follow camera updates between
+// replays); the projection backward then reads them by scalar loads and
+// holds them in scalar registers instead of converting them in every lane.
+constexpr int kCamDoubles = 17;
+
+struct CamD {
+  double W[9], t[3], fx, fy, limx, limy, near_z;
+};
+
+__device__ inline CamD cam_d(const gs_camera& c) {
+  CamD d;
+  for (int i = 0; i < 9; ++i) d.W[i] = (double)c.R[i];
+  for (int i = 0; i < 3; ++i) d.t[i] = (double)c.t[i];
+  d.fx = (double)c.fx;
+  d.fy = (double)c.fy;
+  d.limx = 0.65 * (double)c.width / d.fx;
+  d.limy = 0.65 * (double)c.height / d.fy;
+  d.near_z = (double)c.near_z;
+  return d;
+}
+
+// Entry i of a view's constants, in CamD's field order.
+__device__ inline double cam_d_entry(const gs_camera& c, int i) {
+  const CamD d = cam_d(c);
+  if (i < 9) return d.W[i];
+  if (i < 12) return d.t[i - 9];
+  switch (i) {
+    case 12: return d.fx;
+    case 13: return d.fy;
+    case 14: return d.limx;
+    case 15: return d.limy;
+    default: return d.near_z;
+  }
+}
+
+using ConstDouble = const __attribute__((address_space(4))) double;
+
+// A view's constants from the table (uniform: scalar loads).
+__device__ inline CamD cam_d_table(ConstDouble* t) {
+  CamD d;
+  for (int i = 0; i < 9; ++i) d.W[i] = t[i];
+  for (int i = 0; i < 3; ++i) d.t[i] = t[9 + i];
+  d.fx = t[12]; d.fy = t[13]; d.limx = t[14]; d.limy = t[15];
+  d.near_z = t[16];
+  return d;
 }
 
 }  // namespace gs

@@ -48,10 +48,17 @@ struct ClearArgs {
   // projection (256 Gaussians each) instead of clearing.
   int shape_blocks;
   ShapeJob shape;
+  // Workgroup 0 also forms the views' FP64 camera constants.
+  const gs_camera* cams;
+  int V;
+  double* camd;
 };
 
 __global__ __launch_bounds__(256) void k_clear_iteration(ClearArgs a) {
   if (a.step && blockIdx.x == 0 && threadIdx.x == 0) *a.step += 1;
+  if (blockIdx.x == 0)
+    for (int i = threadIdx.x; i < kCamDoubles * a.V; i += 256)
+      a.camd[i] = cam_d_entry(a.cams[i / kCamDoubles], i % kCamDoubles);
   if ((int)blockIdx.x < a.shape_blocks) {
     shape_one(a.shape, (int)blockIdx.x * 256 + (int)threadIdx.x);
     return;
@@ -99,6 +106,9 @@ hipError_t clear_iteration(const gs_window_desc* d, hipStream_t st) {
     blocks = 1;
   }
   a.shape = shape_job(d->ws, &d->params);
+  a.cams = d->cams;
+  a.V = d->ws->geo.n_views;
+  a.camd = d->ws->camd;
   a.shape_blocks = (d->params.capacity + 255) / 256;
   blocks += a.shape_blocks;
   if (blocks > 0x7fffffff) return hipErrorInvalidConfiguration;
@@ -135,7 +145,9 @@ int enqueue_iteration(const gs_window_desc* d, hipStream_t st) {
                                   true)))
     return rc;
   const L1ReduceJob l1 = l1_reduce_job(d->ws, d->loss_dev, d->sqerr_dev);
-  if ((rc = project_bwd_checked(d->ws, &params, d->cams, &grad, st, &l1)))
+  // The camera constants were formed by the clearing launch.
+  if ((rc = project_bwd_checked(d->ws, &params, d->cams, &grad, st, &l1,
+                                true)))
     return rc;
   if (d->flags & GS_WINDOW_ADAM) {
     // The clearing launch advanced *step_dev already.
