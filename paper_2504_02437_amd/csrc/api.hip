@@ -7,6 +7,7 @@
 #include <string.h>
 
 #include "gs_internal.h"
+#include "shape.h"
 #include "tails.h"
 
 namespace gs {
@@ -157,7 +158,7 @@ static int make_layout(const gs_geometry* g, Layout& L, int& tx, int& ty) {
   L.gop = take(cap * 4);
   L.gcol = take(V * 3 * cap * 4);
   L.shape = take(cap * (6 * 8 + 4 + 4));
-  L.camd = take(V * 17 * 8);
+  L.camd = take(V * kCamDoubles * sizeof(double));
   L.counters = take(sizeof(Counters));
   L.total = off;
   return GS_OK;

@@ -96,8 +96,8 @@ struct gs_workspace {
   unsigned long long* keys_sorted;
   float* grad2d;         // [V][5][capacity]
   float* gop;            // [capacity] dL/d opacity summed over views
-  double* camd;          // [V][17] FP64 camera constants (shape.h), formed
-                         // by the window graph's clearing launch
+  double* camd;          // [V][21] FP64 camera constants (shape.h), formed
+                         // by the launch before the projection
   float* gcol;           // [V][3][capacity] dL/d colour per view (used with
                          // view-dependent colour)
   double* shape;         // [6][capacity] 3D covariance (upper triangle) of

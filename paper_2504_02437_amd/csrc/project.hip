@@ -39,6 +39,7 @@ struct ProjArgs {
   float* lop;     // [cap] log2(opacity) of the FP32 opacity, rounded once
   int chunks;     // ceil(cap / 256)
   const gs_camera* cams;
+  const double* camd;   // [V][kCamDoubles], written by k_shape (workgroup 0)
   int V, W, H, tile, Tx, Ty;
   Record* rec;
   int32_t* tiles;
@@ -115,23 +116,23 @@ __device__ inline double T_dot(const double* Trow, const double* Sig, int j) {
   return Trow[0] * Sig[j] + Trow[1] * Sig[3 + j] + Trow[2] * Sig[6 + j];
 }
 
-__device__ inline void make_view(const gs_camera& cam, double mx, double my,
+__device__ inline void make_view(const CamD& cam, double mx, double my,
                                  double mz, const Shape& S, View& P) {
-  for (int i = 0; i < 9; ++i) P.W[i] = (double)cam.R[i];
-  P.fx = (double)cam.fx;
-  P.fy = (double)cam.fy;
-  P.cx = (double)cam.cx;
-  P.cy = (double)cam.cy;
+  for (int i = 0; i < 9; ++i) P.W[i] = cam.W[i];
+  P.fx = cam.fx;
+  P.fy = cam.fy;
+  P.cx = cam.cx;
+  P.cy = cam.cy;
   const double* W = P.W;
-  P.t[0] = ((W[0] * mx + W[1] * my) + W[2] * mz) + (double)cam.t[0];
-  P.t[1] = ((W[3] * mx + W[4] * my) + W[5] * mz) + (double)cam.t[1];
-  P.t[2] = ((W[6] * mx + W[7] * my) + W[8] * mz) + (double)cam.t[2];
+  P.t[0] = ((W[0] * mx + W[1] * my) + W[2] * mz) + cam.t[0];
+  P.t[1] = ((W[3] * mx + W[4] * my) + W[5] * mz) + cam.t[1];
+  P.t[2] = ((W[6] * mx + W[7] * my) + W[8] * mz) + cam.t[2];
   const double tx = P.t[0], ty = P.t[1], tz = P.t[2];
-  P.ok = isfinite(tx) && isfinite(ty) && isfinite(tz) &&
-         tz > (double)cam.near_z && S.ok;
+  P.ok = isfinite(tx) && isfinite(ty) && isfinite(tz) && tz > cam.near_z &&
+         S.ok;
   if (!P.ok) return;
-  P.limx = 1.3 * ((double)cam.width / (2.0 * P.fx));
-  P.limy = 1.3 * ((double)cam.height / (2.0 * P.fy));
+  P.limx = cam.flimx;
+  P.limy = cam.flimy;
   double rx = tx / tz, ry = ty / tz;
   P.clampx = 0;
   P.clampy = 0;
@@ -219,7 +220,10 @@ __device__ inline void make_view_grad(const CamD& cam, double mx, double my,
   P.C = P.a * idet;
 }
 
-__global__ __launch_bounds__(256) void k_shape(ShapeJob j) {
+__global__ __launch_bounds__(256) void k_shape(ShapeJob j,
+                                               const gs_camera* cams, int V,
+                                               double* camd) {
+  cam_d_fill(cams, V, camd);
   shape_one(j, blockIdx.x * 256 + threadIdx.x);
 }
 
@@ -249,7 +253,8 @@ __global__ __launch_bounds__(256) void k_project(ProjArgs a) {
   {
     const size_t slot = (size_t)k * cap + g;
     View P;
-    make_view(a.cams[k], mx, my, mz, S, P);
+    make_view(cam_d_table((ConstDouble*)a.camd + kCamDoubles * k), mx, my, mz,
+              S, P);
     bool ok = P.ok;
     double ulo = 0, uhi = -1, vlo = 0, vhi = -1;
     if (ok) {
@@ -525,9 +530,10 @@ hipError_t launch_project(gs_workspace* ws, const gs_params* p,
   a.lop = a.op + p->capacity;
   a.chunks = (p->capacity + 255) / 256;
   if (a.chunks <= 0) return hipSuccess;
-  if (!shape_done)
+  a.camd = ws->camd;
+  if (!shape_done)   // else the window graph's clearing launch did both
     hipLaunchKernelGGL(k_shape, dim3(a.chunks), dim3(256), 0, st,
-                       shape_job(ws, p));
+                       shape_job(ws, p), cams, a.V, ws->camd);
   const long long blocks = (long long)((a.chunks + 7) / 8) * 8 * a.V;
   if (blocks > 0x7fffffff) return hipErrorInvalidConfiguration;
   hipLaunchKernelGGL(k_project, dim3((unsigned)blocks), dim3(256), 0, st, a);

@@ -87,17 +87,19 @@ __device__ inline void shape_one(const ShapeJob& j, int g) {
   j.lop[g] = (float)log2((double)op);
 }
 
-// FP64 camera constants of the projection backward, kCamDoubles per view:
-// the rotation (row-major), the translation, fx, fy, the clamp limits of the
-// projected position and the near-plane depth, each formed exactly as the
-// per-lane code forms it from the camera record.  The window graph's
-// clearing launch writes them (so they follow camera updates between
-// replays); the projection backward then reads them by scalar loads and
-// holds them in scalar registers instead of converting them in every lane.
-constexpr int kCamDoubles = 17;
+// FP64 camera constants of the projection and its backward, kCamDoubles
+// per view: the rotation (row-major), the translation, fx, fy, the
+// backward's clamp limits of the projected position, the near-plane depth,
+// cx, cy and the projection's clamp limits, each formed exactly as the
+// per-lane code formed it from the camera record.  Written, from the
+// cameras of the call, by the launch before the projection (k_shape, or the
+// window graph's clearing launch, so they follow camera updates between
+// replays); the kernels read them by scalar loads and hold them in scalar
+// registers instead of converting them in every lane.
+constexpr int kCamDoubles = 21;
 
 struct CamD {
-  double W[9], t[3], fx, fy, limx, limy, near_z;
+  double W[9], t[3], fx, fy, limx, limy, near_z, cx, cy, flimx, flimy;
 };
 
 __device__ inline CamD cam_d(const gs_camera& c) {
@@ -109,6 +111,10 @@ __device__ inline CamD cam_d(const gs_camera& c) {
   d.limx = 0.65 * (double)c.width / d.fx;
   d.limy = 0.65 * (double)c.height / d.fy;
   d.near_z = (double)c.near_z;
+  d.cx = (double)c.cx;
+  d.cy = (double)c.cy;
+  d.flimx = 1.3 * ((double)c.width / (2.0 * d.fx));
+  d.flimy = 1.3 * ((double)c.height / (2.0 * d.fy));
   return d;
 }
 
@@ -122,7 +128,11 @@ __device__ inline double cam_d_entry(const gs_camera& c, int i) {
     case 13: return d.fy;
     case 14: return d.limx;
     case 15: return d.limy;
-    default: return d.near_z;
+    case 16: return d.near_z;
+    case 17: return d.cx;
+    case 18: return d.cy;
+    case 19: return d.flimx;
+    default: return d.flimy;
   }
 }
 
@@ -135,7 +145,15 @@ __device__ inline CamD cam_d_table(ConstDouble* t) {
   for (int i = 0; i < 3; ++i) d.t[i] = t[9 + i];
   d.fx = t[12]; d.fy = t[13]; d.limx = t[14]; d.limy = t[15];
   d.near_z = t[16];
+  d.cx = t[17]; d.cy = t[18]; d.flimx = t[19]; d.flimy = t[20];
   return d;
+}
+
+// Workgroup 0 of a launch writes the V views' constants.
+__device__ inline void cam_d_fill(const gs_camera* cams, int V, double* out) {
+  if (blockIdx.x != 0) return;
+  for (int i = threadIdx.x; i < kCamDoubles * V; i += blockDim.x)
+    out[i] = cam_d_entry(cams[i / kCamDoubles], i % kCamDoubles);
 }
 
 }  // namespace gs

@@ -56,9 +56,7 @@ struct ClearArgs {
 
 __global__ __launch_bounds__(256) void k_clear_iteration(ClearArgs a) {
   if (a.step && blockIdx.x == 0 && threadIdx.x == 0) *a.step += 1;
-  if (blockIdx.x == 0)
-    for (int i = threadIdx.x; i < kCamDoubles * a.V; i += 256)
-      a.camd[i] = cam_d_entry(a.cams[i / kCamDoubles], i % kCamDoubles);
+  cam_d_fill(a.cams, a.V, a.camd);
   if ((int)blockIdx.x < a.shape_blocks) {
     shape_one(a.shape, (int)blockIdx.x * 256 + (int)threadIdx.x);
     return;
